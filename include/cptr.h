@@ -1,0 +1,204 @@
+/*
+ * cptr.h -- C ABI of the MI355X (gfx950) CPTR-FGMRES library (libcptr.so).
+ *
+ * The library solves the linearised fully implicit thermal multiphase system
+ * A dx = b of one Newton iterate (Section 3, eq:AXR), where A is stored cell by
+ * cell as nv x nv blocks (nv = 3: p, S_w, T; nv = 4: p, S_w, S_g, T), with
+ * right-preconditioned flexible GMRES and the two-stage constrained
+ * pressure-temperature residual (CPTR) preconditioner of Section 3.2:
+ *   first stage  M1^{-1} = [A00~^{-1} 0; 0 0], A00 the pressure-temperature
+ *                submatrix (eq:A00), A00~^{-1} the block preconditioner of
+ *                eq:Aschur with its Schur-complement approximation S~_T (eq:Se),
+ *                each inverse one algebraic-multigrid V-cycle;
+ *   second stage block ILU(0) of the full matrix;
+ *   combination  x1 = M1^{-1} v, b1 = v - A x1, z = M2^{-1} b1 + x1
+ *                ("Two-stage preconditioners", Section 3).
+ * CPR (Section 3.1: pressure-only first stage) is available for comparison.
+ *
+ * Conventions shared by every entry point
+ *   - All matrix and vector pointers are DEVICE pointers (HIP memory on the
+ *     current device) unless stated otherwise.  Host arrays are named *_host.
+ *   - BSR: int32 row_ptr[n+1], int32 col_idx[nnzb] (ascending within a row,
+ *     diagonal block present), double vals[nnzb*nv*nv] with each block
+ *     row-major: vals[k*nv*nv + r*nv + c] = d(equation r of the row cell) /
+ *     d(unknown c of the column cell).  The pattern must be structurally
+ *     symmetric (cell graph).  Vectors are interleaved: x[i*nv + u].
+ *   - Row/column slot ip (default 0) is the weighted, scaled pressure equation
+ *     and pressure unknown (eq:weighted, eq:scaling); slot iT (default nv-1)
+ *     is the energy equation and temperature unknown.
+ *   - S~_T is a scalar CSR matrix on the cell graph (int32/int32/double),
+ *     assembled by the caller from eq:Se; it cannot be recovered from A alone.
+ *   - `stream` is a hipStream_t passed as void*; NULL is the null stream.
+ *   - Return values: 0 = CPTR_OK, > 0 informational, < 0 error.  No C++
+ *     exception crosses this interface.  cptr_last_error() gives the message
+ *     of the last failure on the calling thread.
+ *   - A handle is not thread safe; distinct handles may be used concurrently
+ *     on distinct streams.
+ */
+#ifndef CPTR_H
+#define CPTR_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CPTR_OK 0
+#define CPTR_NOT_CONVERGED 1
+#define CPTR_ERR_INVALID_ARG (-1)
+#define CPTR_ERR_UNSUPPORTED (-2)
+#define CPTR_ERR_NONFINITE (-3)
+#define CPTR_ERR_SINGULAR_BLOCK (-4)
+#define CPTR_ERR_OOM (-5)
+#define CPTR_ERR_HIP (-6)
+#define CPTR_ERR_SETUP (-7)
+
+/* first stage */
+#define CPTR_FIRST_NONE 0        /* x1 = 0 */
+#define CPTR_FIRST_BLOCK 1       /* CPTR-Block: the five steps of eq:Aschur */
+#define CPTR_FIRST_BLOCK_LOWER 2 /* right factor of eq:Aschur dropped (block lower triangular) */
+#define CPTR_FIRST_CPR 3         /* CPR: x1 = R_p^T V(A_pp) R_p v */
+
+/* second stage */
+#define CPTR_SECOND_NONE 0       /* z = x1 */
+#define CPTR_SECOND_BILU0 1      /* block ILU(0), natural order, level-scheduled solves */
+#define CPTR_SECOND_BILU0_MC 2   /* block ILU(0) in greedy multicolour order */
+#define CPTR_SECOND_IDENTITY 3   /* z = b1 + x1 */
+
+/* precision of the preconditioner (FGMRES itself is always FP64) */
+#define CPTR_FP64 0
+#define CPTR_FP32 1
+
+typedef struct {
+  int n;                 /* block rows = cells */
+  int nv;                /* unknowns per cell: 3 or 4 */
+  int nnzb;              /* stored blocks */
+  const int *row_ptr;    /* device, n+1 */
+  const int *col_idx;    /* device, nnzb */
+  const double *vals;    /* device, nnzb*nv*nv, borrowed (see cptr_setup) */
+} cptr_bsr;
+
+typedef struct {
+  int n;
+  int nnz;
+  const int *row_ptr;    /* device, n+1 */
+  const int *col_idx;    /* device, nnz */
+  const double *vals;    /* device, nnz */
+} cptr_csr;
+
+typedef struct {
+  int first_stage;       /* CPTR_FIRST_* (default CPTR_FIRST_BLOCK) */
+  int second_stage;      /* CPTR_SECOND_* (default CPTR_SECOND_BILU0_MC) */
+  int precision;         /* CPTR_FP64 / CPTR_FP32 (default CPTR_FP32) */
+  int ip, iT;            /* slots of p and T (defaults 0 and nv-1; iT < 0 means nv-1) */
+  double amg_theta;      /* strength threshold of the finest AMG level (0.08), halved per level */
+  int amg_max_levels;    /* <= 16 (10) */
+  int amg_coarse_size;   /* coarsest level solved directly once n <= this (512) */
+  unsigned amg_seed;     /* aggregation priority seed (0) */
+  int amg_sweeps;        /* l1-Jacobi sweeps before and after the coarse correction (1) */
+  int amg_smooth_p;      /* 1 smoothed aggregation, 0 plain aggregation (1) */
+  int use_graph;         /* 1: replay the preconditioner and the Arnoldi step as HIP graphs (1) */
+} cptr_options;
+
+typedef struct {
+  int restart;           /* m of FGMRES(m) (30) */
+  double rtol;           /* stop when ||b - A x|| <= rtol ||b|| (1e-6) */
+  int maxit;             /* total inner iterations (1000) */
+  int nonzero_guess;     /* 0: x0 = 0, 1: x holds the initial guess */
+} cptr_solve_opts;
+
+typedef struct {
+  int iters;             /* preconditioner applications */
+  int restarts;
+  int converged;
+  double relres_est;     /* |g_{j+1}| / ||b|| at exit */
+  double relres_true;    /* ||b - A x|| / ||b||, FP64, at exit */
+  double solve_ms;       /* wall time inside fgmres_solve */
+} cptr_solve_info;
+
+typedef struct {
+  int nlevels[2];        /* AMG levels of A_pp [0] and S~_T [1] */
+  int level_rows[2][16];
+  int level_nnz[2][16];
+  int ilu_levels_lower;  /* dependent steps of the forward sweep */
+  int ilu_levels_upper;  /* dependent steps of the backward sweep */
+  int ilu_colors;        /* colours of the multicolour order (0 for natural) */
+  double setup_ms;
+  double apply_bytes;    /* algorithmic HBM bytes of one preconditioner application */
+  double spmv_bytes;     /* algorithmic bytes of one FP64 BSR product */
+  long long applies;     /* preconditioner applications so far */
+} cptr_stats;
+
+typedef struct cptr_handle cptr_handle;
+
+/* Fill *opt with the defaults listed above. */
+void cptr_default_options(cptr_options *opt);
+
+/* Build the preconditioner for A (first stage: sub-block extraction eq:A00,
+ * two AMG hierarchies for A_pp and S~_T; second stage: BILU(0) factors).
+ *   out   receives the handle (NULL on failure).
+ *   A     must stay alive and unchanged until cptr_destroy: A->vals (FP64) is
+ *         BORROWED for the FP64 Arnoldi products; everything derived is owned.
+ *   S_T   the assembled S~_T of eq:Se; required for CPTR_FIRST_BLOCK(_LOWER),
+ *         ignored (may be NULL) otherwise.
+ *   opt   NULL for defaults.
+ * Blocks until setup is complete.  Errors: CPTR_ERR_INVALID_ARG (sizes,
+ * unsorted or out-of-range columns, missing diagonal, nv not 3/4, ip == iT,
+ * structurally unsymmetric pattern), CPTR_ERR_NONFINITE, CPTR_ERR_SINGULAR_BLOCK
+ * (zero pivot in a diagonal block of the ILU factorisation),
+ * CPTR_ERR_SETUP (AMG coarsening stalled above 4096 rows), CPTR_ERR_OOM,
+ * CPTR_ERR_HIP. */
+int cptr_setup(cptr_handle **out, const cptr_bsr *A, const cptr_csr *S_T,
+               const cptr_options *opt, void *stream);
+
+/* z = M^{-1} v (one two-stage application).  v, z: device FP64 [n*nv], must
+ * not alias.  Asynchronous on `stream`. */
+int cptr_apply(cptr_handle *h, const double *v, double *z, void *stream);
+
+/* Only the first stage: x1 = M1^{-1} v prolonged to the full vector (zeros in
+ * the saturation slots).  Device FP64 [n*nv].  Asynchronous. */
+int cptr_first_stage(cptr_handle *h, const double *v, double *x1, void *stream);
+
+/* One AMG V-cycle from a zero initial guess on A_pp (which = 0) or S~_T
+ * (which = 1), in the handle's precision: x = V(b).  Device FP64 [n].
+ * Asynchronous. */
+int cptr_vcycle(cptr_handle *h, int which, const double *b, double *x, void *stream);
+
+/* Right-preconditioned flexible GMRES(m) (Saad 1993) with the handle's
+ * preconditioner; Arnoldi by classical Gram-Schmidt with one
+ * re-orthogonalisation in FP64; stops when the Givens estimate reaches
+ * rtol ||b|| and the FP64 true residual confirms it, otherwise restarts.
+ * b, x: device FP64 [n*nv]; x is the initial guess if so->nonzero_guess, and
+ * is overwritten with the solution.  `so` NULL for defaults; `info` may be
+ * NULL.  Blocking (reads one FP64 scalar per iteration).  Returns CPTR_OK or
+ * CPTR_NOT_CONVERGED (info filled in both cases). */
+int fgmres_solve(cptr_handle *h, const double *b, double *x, const cptr_solve_opts *so,
+                 cptr_solve_info *info, void *stream);
+
+/* Numeric re-setup with an unchanged pattern.  Not available yet: returns
+ * CPTR_ERR_UNSUPPORTED. */
+int cptr_update_values(cptr_handle *h, const double *A_vals, const double *S_vals,
+                       void *stream);
+
+/* Introspection.  Integer setup results, copied to host arrays (NULL to skip):
+ * the aggregate of every row of AMG level `level` (size = rows of that level),
+ * and the level / colour of every cell in the BILU(0) solves (size n). */
+int cptr_get_stats(const cptr_handle *h, cptr_stats *st);
+int cptr_get_aggregates(const cptr_handle *h, int which, int level, int *agg_host);
+int cptr_get_ilu_schedule(const cptr_handle *h, int *lev_lower_host, int *lev_upper_host,
+                          int *color_host);
+
+/* y = A x for an FP64 BSR matrix (nv = 3 or 4); device pointers.  The kernel
+ * used for the Arnoldi products, exposed for testing.  Asynchronous. */
+int cptr_bsr_spmv(int n, int nv, const int *row_ptr, const int *col_idx, const double *vals,
+                  const double *x, double *y, void *stream);
+
+const char *cptr_status_string(int status);
+const char *cptr_last_error(void);
+void cptr_destroy(cptr_handle *h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

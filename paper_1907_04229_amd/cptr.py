@@ -1,0 +1,269 @@
+"""Python binding of libcptr (include/cptr.h): argument marshalling only.
+
+Device memory comes from torch tensors on a ROCm device (their data_ptr()),
+streams from torch.cuda streams.  Every computation runs in libcptr's HIP
+kernels; there is no fallback.  If the library has not been built, loading it
+raises.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcptr.so")
+
+CPTR_OK = 0
+CPTR_NOT_CONVERGED = 1
+FIRST = {"none": 0, "cptr": 1, "cptr_lower": 2, "cpr": 3}
+SECOND = {"none": 0, "bilu0": 1, "bilu0_mc": 2, "identity": 3}
+PRECISION = {"fp64": 0, "fp32": 1}
+
+
+class Options(C.Structure):
+    _fields_ = [("first_stage", C.c_int), ("second_stage", C.c_int), ("precision", C.c_int),
+                ("ip", C.c_int), ("iT", C.c_int), ("amg_theta", C.c_double),
+                ("amg_max_levels", C.c_int), ("amg_coarse_size", C.c_int),
+                ("amg_seed", C.c_uint), ("amg_sweeps", C.c_int), ("amg_smooth_p", C.c_int),
+                ("use_graph", C.c_int)]
+
+
+class Bsr(C.Structure):
+    _fields_ = [("n", C.c_int), ("nv", C.c_int), ("nnzb", C.c_int), ("row_ptr", C.c_void_p),
+                ("col_idx", C.c_void_p), ("vals", C.c_void_p)]
+
+
+class Csr(C.Structure):
+    _fields_ = [("n", C.c_int), ("nnz", C.c_int), ("row_ptr", C.c_void_p),
+                ("col_idx", C.c_void_p), ("vals", C.c_void_p)]
+
+
+class SolveOpts(C.Structure):
+    _fields_ = [("restart", C.c_int), ("rtol", C.c_double), ("maxit", C.c_int),
+                ("nonzero_guess", C.c_int)]
+
+
+class SolveInfo(C.Structure):
+    _fields_ = [("iters", C.c_int), ("restarts", C.c_int), ("converged", C.c_int),
+                ("relres_est", C.c_double), ("relres_true", C.c_double),
+                ("solve_ms", C.c_double)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("nlevels", C.c_int * 2), ("level_rows", (C.c_int * 16) * 2),
+                ("level_nnz", (C.c_int * 16) * 2), ("ilu_levels_lower", C.c_int),
+                ("ilu_levels_upper", C.c_int), ("ilu_colors", C.c_int),
+                ("setup_ms", C.c_double), ("apply_bytes", C.c_double),
+                ("spmv_bytes", C.c_double), ("applies", C.c_longlong)]
+
+
+class CptrError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{msg} (status {code})")
+        self.code = code
+
+
+_lib = None
+
+
+def load():
+    """Load libcptr.so; raises if it is missing (build it first)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built: run `python -m paper_1907_04229_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        vp, ip = C.c_void_p, C.c_int
+        L.cptr_default_options.argtypes = [C.POINTER(Options)]
+        L.cptr_setup.argtypes = [C.POINTER(vp), C.POINTER(Bsr), C.POINTER(Csr), C.POINTER(Options), vp]
+        L.cptr_apply.argtypes = [vp, vp, vp, vp]
+        L.cptr_first_stage.argtypes = [vp, vp, vp, vp]
+        L.cptr_vcycle.argtypes = [vp, ip, vp, vp, vp]
+        L.fgmres_solve.argtypes = [vp, vp, vp, C.POINTER(SolveOpts), C.POINTER(SolveInfo), vp]
+        L.cptr_update_values.argtypes = [vp, vp, vp, vp]
+        L.cptr_get_stats.argtypes = [vp, C.POINTER(Stats)]
+        L.cptr_get_aggregates.argtypes = [vp, ip, ip, C.POINTER(C.c_int)]
+        L.cptr_get_ilu_schedule.argtypes = [vp, C.POINTER(C.c_int), C.POINTER(C.c_int),
+                                            C.POINTER(C.c_int)]
+        L.cptr_bsr_spmv.argtypes = [ip, ip, vp, vp, vp, vp, vp, vp]
+        L.cptr_status_string.restype = C.c_char_p
+        L.cptr_status_string.argtypes = [ip]
+        L.cptr_last_error.restype = C.c_char_p
+        L.cptr_destroy.argtypes = [vp]
+        _lib = L
+    return _lib
+
+
+def _check(rc, allow=(CPTR_OK,)):
+    if rc in allow:
+        return rc
+    L = load()
+    raise CptrError(rc, f"{L.cptr_status_string(rc).decode()}: {L.cptr_last_error().decode()}")
+
+
+def _ptr(t, dtype=None):
+    if t is None:
+        return None
+    import torch
+    assert t.is_cuda and t.is_contiguous(), "device tensors must be contiguous ROCm tensors"
+    if dtype is not None:
+        assert t.dtype == dtype, f"expected {dtype}, got {t.dtype}"
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def cptr_default_options(**kw):
+    o = Options()
+    load().cptr_default_options(C.byref(o))
+    for k, v in kw.items():
+        if k == "first_stage" and isinstance(v, str):
+            v = FIRST[v]
+        if k == "second_stage" and isinstance(v, str):
+            v = SECOND[v]
+        if k == "precision" and isinstance(v, str):
+            v = PRECISION[v]
+        setattr(o, k, v)
+    return o
+
+
+def cptr_setup(n, nv, row_ptr, col_idx, vals, st_row_ptr=None, st_col_idx=None, st_vals=None,
+               options=None, stream=None):
+    """Returns an opaque handle.  The tensors must outlive the handle (vals is borrowed)."""
+    import torch
+    A = Bsr(n, nv, col_idx.numel(), _ptr(row_ptr, torch.int32), _ptr(col_idx, torch.int32),
+            _ptr(vals, torch.float64))
+    S = None
+    if st_row_ptr is not None:
+        S = Csr(n, st_col_idx.numel(), _ptr(st_row_ptr, torch.int32), _ptr(st_col_idx, torch.int32),
+                _ptr(st_vals, torch.float64))
+    h = C.c_void_p()
+    _check(load().cptr_setup(C.byref(h), C.byref(A), C.byref(S) if S is not None else None,
+                             C.byref(options) if options is not None else None, _stream(stream)))
+    return h
+
+
+def cptr_apply(h, v, z, stream=None):
+    import torch
+    _check(load().cptr_apply(h, _ptr(v, torch.float64), _ptr(z, torch.float64), _stream(stream)))
+
+
+def cptr_first_stage(h, v, x1, stream=None):
+    import torch
+    _check(load().cptr_first_stage(h, _ptr(v, torch.float64), _ptr(x1, torch.float64),
+                                   _stream(stream)))
+
+
+def cptr_vcycle(h, which, b, x, stream=None):
+    import torch
+    _check(load().cptr_vcycle(h, which, _ptr(b, torch.float64), _ptr(x, torch.float64),
+                              _stream(stream)))
+
+
+def fgmres_solve(h, b, x, restart=30, rtol=1e-6, maxit=1000, nonzero_guess=False, stream=None):
+    import torch
+    so = SolveOpts(restart, rtol, maxit, int(bool(nonzero_guess)))
+    info = SolveInfo()
+    rc = load().fgmres_solve(h, _ptr(b, torch.float64), _ptr(x, torch.float64), C.byref(so),
+                             C.byref(info), _stream(stream))
+    _check(rc, allow=(CPTR_OK, CPTR_NOT_CONVERGED))
+    return dict(iters=info.iters, restarts=info.restarts, converged=bool(info.converged),
+                relres_est=info.relres_est, relres_true=info.relres_true, solve_ms=info.solve_ms)
+
+
+def cptr_update_values(h, A_vals, S_vals=None, stream=None):
+    import torch
+    _check(load().cptr_update_values(h, _ptr(A_vals, torch.float64), _ptr(S_vals, torch.float64),
+                                     _stream(stream)))
+
+
+def cptr_get_stats(h):
+    st = Stats()
+    _check(load().cptr_get_stats(h, C.byref(st)))
+    d = dict(nlevels=list(st.nlevels), ilu_levels_lower=st.ilu_levels_lower,
+             ilu_levels_upper=st.ilu_levels_upper, ilu_colors=st.ilu_colors,
+             setup_ms=st.setup_ms, apply_bytes=st.apply_bytes, spmv_bytes=st.spmv_bytes,
+             applies=st.applies)
+    d["level_rows"] = [list(st.level_rows[w])[:st.nlevels[w]] for w in range(2)]
+    d["level_nnz"] = [list(st.level_nnz[w])[:st.nlevels[w]] for w in range(2)]
+    return d
+
+
+def cptr_get_aggregates(h, which, level, nrows):
+    out = np.empty(max(nrows, 1), np.int32)
+    rc = load().cptr_get_aggregates(h, which, level, out.ctypes.data_as(C.POINTER(C.c_int)))
+    if rc < 0:
+        _check(rc)
+    return out[:rc]
+
+
+def cptr_get_ilu_schedule(h, n):
+    a, b, c = (np.empty(n, np.int32) for _ in range(3))
+    p = lambda x: x.ctypes.data_as(C.POINTER(C.c_int))  # noqa: E731
+    _check(load().cptr_get_ilu_schedule(h, p(a), p(b), p(c)))
+    return a, b, c
+
+
+def cptr_bsr_spmv(n, nv, row_ptr, col_idx, vals, x, y, stream=None):
+    import torch
+    _check(load().cptr_bsr_spmv(n, nv, _ptr(row_ptr, torch.int32), _ptr(col_idx, torch.int32),
+                                _ptr(vals, torch.float64), _ptr(x, torch.float64),
+                                _ptr(y, torch.float64), _stream(stream)))
+
+
+def cptr_destroy(h):
+    if h:
+        load().cptr_destroy(h)
+
+
+class Solver:
+    """Keeps the device copies of one system alive together with its handle."""
+
+    def __init__(self, problem, device="cuda", **opts):
+        import torch
+        self.problem = problem
+        dev = torch.device(device)
+        t = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=dev)  # noqa: E731
+        self.rp = t(problem.row_ptr, torch.int32)
+        self.ci = t(problem.col_idx, torch.int32)
+        self.vals = t(problem.vals, torch.float64)
+        self.srp = t(problem.st_row_ptr, torch.int32)
+        self.sci = t(problem.st_col_idx, torch.int32)
+        self.svals = t(problem.st_vals, torch.float64)
+        self.n, self.nv = problem.n, problem.nv
+        self.options = cptr_default_options(**opts)
+        self.h = cptr_setup(self.n, self.nv, self.rp, self.ci, self.vals, self.srp, self.sci,
+                            self.svals, self.options)
+
+    def solve(self, b, x=None, **kw):
+        import torch
+        if not torch.is_tensor(b):
+            b = torch.as_tensor(np.ascontiguousarray(b), dtype=torch.float64, device=self.vals.device)
+        if x is None:
+            x = torch.zeros_like(b)
+        info = fgmres_solve(self.h, b, x, **kw)
+        return x, info
+
+    def apply(self, v):
+        import torch
+        z = torch.empty_like(v)
+        cptr_apply(self.h, v, z)
+        return z
+
+    def stats(self):
+        return cptr_get_stats(self.h)
+
+    def close(self):
+        if self.h:
+            cptr_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,1041 @@
+// libcptr: C ABI (include/cptr.h) of the MI355X CPTR-FGMRES path.
+//
+// One application of the preconditioner (Section 3.2, "two-stage"), in the
+// handle's precision T (float or double):
+//   a3  b_p, b_T  <- restriction of v to the p and T slots
+//   a4  x_p  = V(A_pp) b_p                   (block preconditioner step 1)
+//   a5  b~_T = b_T - A_Tp x_p                (step 2)
+//   a6  d_T  = V(S~_T) b~_T                  (step 3)
+//   a7  b~_p = b_p - A_pT d_T                (step 4)
+//   a8  d_p  = V(A_pp) b~_p                  (step 5)
+//   a9  b1   = v - A R^T (d_p, d_T)          (two-stage residual)
+//   a10 z    = BILU0^{-1} b1 + R^T (d_p, d_T)
+// V(.) is one smoothed-aggregation V-cycle; its coarsest level is applied in
+// FP64.  FGMRES (a12, a13) is FP64 throughout; in FP32 mode the preconditioned
+// vectors Z are stored in FP32 (they are produced in FP32, so nothing is lost).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "common.h"
+#include "device_kernels.hip"
+
+namespace cptr {
+
+static thread_local std::string g_last_error;
+void set_last_error(const std::string &msg) { g_last_error = msg; }
+
+// ---------------------------------------------------------------- device memory
+struct DevMem {
+  void *p = nullptr;
+  size_t bytes = 0;
+  DevMem() = default;
+  DevMem(const DevMem &) = delete;
+  DevMem &operator=(const DevMem &) = delete;
+  ~DevMem() {
+    if (p) (void)hipFree(p);
+  }
+  void alloc(size_t b) {
+    if (p) {
+      (void)hipFree(p);
+      p = nullptr;
+    }
+    bytes = b;
+    if (b == 0) return;
+    hipError_t e = hipMalloc(&p, b);
+    if (e != hipSuccess) {
+      p = nullptr;
+      (void)hipGetLastError();
+      throw Error{CPTR_ERR_OOM, "hipMalloc of " + std::to_string(b) + " bytes failed"};
+    }
+  }
+};
+
+template <typename X>
+static inline X *devp(const DevMem &m) { return reinterpret_cast<X *>(m.p); }
+
+template <typename X>
+static void upload(DevMem &m, const std::vector<X> &h) {
+  m.alloc(h.size() * sizeof(X));
+  if (!h.empty()) CPTR_HIP_TRY(hipMemcpy(m.p, h.data(), h.size() * sizeof(X), hipMemcpyHostToDevice));
+}
+
+static inline int nblk(size_t n, int b = kBlock) { return int((n + b - 1) / b); }
+static inline int sgrid(size_t n) { return std::max(1, std::min(kDotBlocks, nblk(n))); }
+
+#define LAUNCH_CHECK() CPTR_HIP_TRY(hipGetLastError())
+
+// ---------------------------------------------------------------- SELL-64 on device
+template <typename T>
+struct SellDev {
+  DevMem sptr, col, val;
+  Sell<T> view;
+  size_t stored = 0;  // stored elements (padding included)
+  size_t nnz = 0;
+
+  void build(const HostCSR &a) {
+    int ns = (a.nr + kSlice - 1) / kSlice;
+    std::vector<int> sp(ns + 1, 0);
+    for (int s = 0; s < ns; s++) {
+      int w = 0;
+      for (int r = s * kSlice; r < std::min(a.nr, (s + 1) * kSlice); r++)
+        w = std::max(w, a.rp[r + 1] - a.rp[r]);
+      sp[s + 1] = sp[s] + w * kSlice;
+    }
+    std::vector<int> c(std::max(sp[ns], 1), 0);
+    std::vector<T> v(std::max(sp[ns], 1), T(0));
+    for (int s = 0; s < ns; s++)
+      for (int lane = 0; lane < kSlice; lane++) {
+        int r = s * kSlice + lane;
+        if (r >= a.nr) break;
+        int k = 0;
+        for (int q = a.rp[r]; q < a.rp[r + 1]; q++, k++) {
+          c[sp[s] + k * kSlice + lane] = a.ci[q];
+          v[sp[s] + k * kSlice + lane] = T(a.v[q]);
+        }
+      }
+    upload(sptr, sp);
+    upload(col, c);
+    upload(val, v);
+    view.nrows = a.nr;
+    view.nslices = ns;
+    view.sptr = devp<int>(sptr);
+    view.col = devp<int>(col);
+    view.val = devp<T>(val);
+    stored = sp[ns];
+    nnz = a.nnz();
+  }
+  // algorithmic bytes of one product: stored values + indices + slice offsets
+  double bytes() const { return double(nnz) * (sizeof(T) + 4) + 4.0 * (view.nslices + 1); }
+};
+
+// ---------------------------------------------------------------- AMG on device
+template <typename T>
+struct AmgDev {
+  struct Level {
+    SellDev<T> A, P, R;
+    DevMem dinv, b, x, y, r;
+    int n = 0;
+  };
+  std::vector<std::unique_ptr<Level>> lev;
+  DevMem coarse_inv;
+  int nc = 0;
+  int sweeps = 1;
+  std::vector<std::vector<int>> agg;  // host copy of the aggregates (introspection)
+  double bytes_per_cycle = 0.0;
+
+  void build(const AmgHost &h, int nsweeps) {
+    sweeps = std::max(1, nsweeps);
+    lev.clear();
+    agg.clear();
+    bytes_per_cycle = 0.0;
+    const size_t s = sizeof(T);
+    for (size_t l = 0; l < h.lev.size(); l++) {
+      auto L = std::make_unique<Level>();
+      const AmgLevelHost &H = h.lev[l];
+      L->n = H.A.nr;
+      agg.push_back(H.agg);
+      L->b.alloc(L->n * s);
+      L->x.alloc(L->n * s);
+      L->y.alloc(L->n * s);
+      L->r.alloc(L->n * s);
+      if (l + 1 < h.lev.size()) {
+        L->A.build(H.A);
+        L->P.build(H.P);
+        L->R.build(H.R);
+        std::vector<T> d(L->n);
+        for (int i = 0; i < L->n; i++) {
+          double sum = 0.0;
+          for (int k = H.A.rp[i]; k < H.A.rp[i + 1]; k++) sum += std::fabs(H.A.v[k]);
+          d[i] = T(1.0 / sum);
+        }
+        upload(L->dinv, d);
+        // pre: sweeps products with A (first fused with the residual), post: sweeps;
+        // restriction and prolongation once each
+        double n = L->n;
+        bytes_per_cycle += (2.0 * sweeps) * (L->A.bytes() + 3 * n * s)  // A x, b, dinv, x
+                           + L->R.bytes() + n * s + H.R.nr * s          // R r
+                           + L->P.bytes() + 2 * n * s + H.P.nc * s;     // x += P x_c
+      }
+      lev.push_back(std::move(L));
+    }
+    nc = h.lev.back().A.nr;
+    upload(coarse_inv, h.coarse_inv);
+    bytes_per_cycle += double(nc) * nc * 8 + 2.0 * nc * s;
+  }
+
+  // x = V(b) from a zero guess; b and x are level-0 sized device vectors (T)
+  void cycle(hipStream_t st, const T *b, T *x) const { cycle_level(st, 0, b, x); }
+
+  void cycle_level(hipStream_t st, size_t l, const T *b, T *out) const {
+    const Level &L = *lev[l];
+    const int n = L.n;
+    if (l + 1 == lev.size()) {
+      const int waves_per_block = kBlock / 64;
+      hipLaunchKernelGGL((k_coarse_gemv<T>), dim3(nblk(nc, waves_per_block)), dim3(kBlock), 0, st,
+                         devp<double>(coarse_inv), nc, b, out);
+      LAUNCH_CHECK();
+      return;
+    }
+    T *x = devp<T>(L.x), *y = devp<T>(L.y), *r = devp<T>(L.r);
+    const T *dinv = devp<T>(L.dinv);
+    const Level &C = *lev[l + 1];
+    // pre-smoothing from zero + residual
+    if (sweeps == 1) {
+      hipLaunchKernelGGL((k_smooth0_resid<T>), dim3(nblk(n)), dim3(kBlock), 0, st, L.A.view, dinv, b, x, r);
+      LAUNCH_CHECK();
+    } else {
+      hipLaunchKernelGGL((k_smooth0_resid<T>), dim3(nblk(n)), dim3(kBlock), 0, st, L.A.view, dinv, b, x, r);
+      T *cur = x, *nxt = y;
+      for (int s = 1; s < sweeps; s++) {
+        hipLaunchKernelGGL((k_jacobi<T>), dim3(nblk(n)), dim3(kBlock), 0, st, L.A.view, dinv, b, cur, nxt);
+        std::swap(cur, nxt);
+      }
+      if (cur != x) std::swap(x, y);  // keep the iterate in x
+      hipLaunchKernelGGL((k_sell_spmv<T, 2>), dim3(nblk(n)), dim3(kBlock), 0, st, L.A.view, x, b, r);
+      LAUNCH_CHECK();
+    }
+    // restriction, coarse correction, prolongation
+    hipLaunchKernelGGL((k_sell_spmv<T, 0>), dim3(nblk(C.n)), dim3(kBlock), 0, st, L.R.view, r,
+                       (const T *)nullptr, devp<T>(C.b));
+    LAUNCH_CHECK();
+    cycle_level(st, l + 1, devp<T>(C.b), devp<T>(C.r));  // coarse result in C.r
+    hipLaunchKernelGGL((k_sell_spmv<T, 1>), dim3(nblk(n)), dim3(kBlock), 0, st, L.P.view,
+                       devp<T>(C.r), (const T *)nullptr, x);
+    LAUNCH_CHECK();
+    // post-smoothing; the last sweep writes to out
+    T *cur = x;
+    for (int s = 0; s < sweeps; s++) {
+      T *dst = (s == sweeps - 1) ? out : (cur == x ? y : x);
+      hipLaunchKernelGGL((k_jacobi<T>), dim3(nblk(n)), dim3(kBlock), 0, st, L.A.view, dinv, b, cur, dst);
+      LAUNCH_CHECK();
+      cur = dst;
+    }
+  }
+};
+
+// ---------------------------------------------------------------- BILU(0) on device
+template <typename T>
+struct IluDev {
+  DevMem f_rows, f_ptr, f_col, f_val, b_rows, b_ptr, b_col, b_val, dinv;
+  std::vector<int> f_lev_ptr, b_lev_ptr;
+  std::vector<char> f_nonempty;  // forward levels holding at least one L block
+  std::vector<int> lev_lower, lev_upper, color;
+  int ncolor = 0;
+  double bytes = 0.0;
+
+  void build(const IluHost &h) {
+    upload(f_rows, h.f_rows);
+    upload(f_ptr, h.f_ptr);
+    upload(f_col, h.f_col);
+    upload(b_rows, h.b_rows);
+    upload(b_ptr, h.b_ptr);
+    upload(b_col, h.b_col);
+    std::vector<T> fv(h.f_val.begin(), h.f_val.end()), bv(h.b_val.begin(), h.b_val.end()),
+        dv(h.dinv.begin(), h.dinv.end());
+    upload(f_val, fv);
+    upload(b_val, bv);
+    upload(dinv, dv);
+    f_lev_ptr = h.f_lev_ptr;
+    b_lev_ptr = h.b_lev_ptr;
+    f_nonempty.assign(f_lev_ptr.size() - 1, 0);
+    for (size_t l = 0; l + 1 < f_lev_ptr.size(); l++)
+      f_nonempty[l] = h.f_ptr[f_lev_ptr[l + 1]] > h.f_ptr[f_lev_ptr[l]];
+    lev_lower = h.lev_lower;
+    lev_upper = h.lev_upper;
+    color = h.color;
+    ncolor = h.ncolor;
+    const double s = sizeof(T), b2 = double(h.nv) * h.nv;
+    const double n = h.n;
+    bytes = (h.f_col.size() + h.b_col.size()) * (b2 * s + 4) + 2 * 4 * (n + 1) + 2 * 4 * n  // factors
+            + n * b2 * s                                                                      // D^-1
+            + 4 * n * h.nv * s;                                                               // b1, y, w
+  }
+};
+
+// ---------------------------------------------------------------- preconditioner
+struct PrecondBase {
+  virtual ~PrecondBase() = default;
+  virtual void apply(hipStream_t st, const ApplySlots *slots, bool z_double) = 0;
+  virtual void first_stage(hipStream_t st, const ApplySlots *slots) = 0;
+  virtual void vcycle(hipStream_t st, int which, const double *b, double *x) = 0;
+  virtual const AmgDev<float> *amgf(int) const { return nullptr; }
+  virtual const AmgDev<double> *amgd(int) const { return nullptr; }
+};
+
+struct Options {
+  cptr_options o;
+  int n, nv, nnzb;
+};
+
+template <typename T>
+struct Precond : PrecondBase {
+  Options op;
+  const int *rp = nullptr, *ci = nullptr;  // device pattern (caller's)
+  DevMem acol;                             // p/T columns of A as nv x 2 blocks
+  SellDev<T> ApT, ATp;
+  AmgDev<T> amg_p, amg_s;
+  IluDev<T> ilu;
+  DevMem bp, bt, xp, dT, dp, tmp, b1;
+  DevMem vtmp, ztmp;  // FP64 staging of cptr_vcycle
+  bool have_s = false, have_ilu = false;
+  double bytes = 0.0;
+
+  void apply_first(hipStream_t st, const ApplySlots *slots) {
+    const int n = op.n, fs = op.o.first_stage;
+    const int ip = op.o.ip, iT = op.o.iT;
+    if (fs == CPTR_FIRST_NONE) return;
+    T *bpp = devp<T>(bp), *btt = devp<T>(bt), *xpp = devp<T>(xp), *dTT = devp<T>(dT),
+      *dpp = devp<T>(dp), *t = devp<T>(tmp);
+    hipLaunchKernelGGL((k_restrict_pT<T>), dim3(nblk(n)), dim3(kBlock), 0, st, n, op.nv, ip, iT, slots,
+                       bpp, fs == CPTR_FIRST_CPR ? (T *)nullptr : btt);
+    LAUNCH_CHECK();
+    if (fs == CPTR_FIRST_CPR) {
+      amg_p.cycle(st, bpp, dpp);
+      return;
+    }
+    amg_p.cycle(st, bpp, xpp);
+    hipLaunchKernelGGL((k_sell_spmv<T, 2>), dim3(nblk(n)), dim3(kBlock), 0, st, ATp.view, xpp, btt, t);
+    LAUNCH_CHECK();
+    amg_s.cycle(st, t, dTT);
+    if (fs == CPTR_FIRST_BLOCK_LOWER) {
+      hipLaunchKernelGGL((k_convert<T, T>), dim3(sgrid(n)), dim3(kBlock), 0, st, xpp, dpp, (size_t)n);
+      LAUNCH_CHECK();
+      return;
+    }
+    hipLaunchKernelGGL((k_sell_spmv<T, 2>), dim3(nblk(n)), dim3(kBlock), 0, st, ApT.view, dTT, bpp, t);
+    LAUNCH_CHECK();
+    amg_p.cycle(st, t, dpp);
+  }
+
+  const T *x1p() const { return op.o.first_stage == CPTR_FIRST_NONE ? nullptr : devp<T>(dp); }
+  const T *x1T() const {
+    int fs = op.o.first_stage;
+    return (fs == CPTR_FIRST_NONE || fs == CPTR_FIRST_CPR) ? nullptr : devp<T>(dT);
+  }
+
+  template <int NV, typename ZT>
+  void apply_nv(hipStream_t st, const ApplySlots *slots) {
+    const int n = op.n, ss = op.o.second_stage;
+    apply_first(st, slots);
+    T *b1p = devp<T>(b1);
+    // two-stage residual b1 = v - A x1 (x1 = 0 without a first stage)
+    if (ss == CPTR_SECOND_NONE) {
+      hipLaunchKernelGGL((k_finish<T, ZT>), dim3(nblk((size_t)n * NV)), dim3(kBlock), 0, st, n, NV,
+                         op.o.ip, op.o.iT, (const T *)nullptr, x1p(), x1T(), slots);
+      LAUNCH_CHECK();
+      return;
+    }
+    hipLaunchKernelGGL((k_resid_pT<NV, T>), dim3(nblk((size_t)n * NV)), dim3(kBlock), 0, st, n, rp, ci,
+                       devp<T>(acol), slots, x1p() ? x1p() : (const T *)zero_vec(), x1T(), b1p);
+    LAUNCH_CHECK();
+    if (ss == CPTR_SECOND_IDENTITY) {
+      hipLaunchKernelGGL((k_finish<T, ZT>), dim3(nblk((size_t)n * NV)), dim3(kBlock), 0, st, n, NV,
+                         op.o.ip, op.o.iT, (const T *)b1p, x1p(), x1T(), slots);
+      LAUNCH_CHECK();
+      return;
+    }
+    // BILU(0): forward sweep level by level (levels without L blocks are no-ops)
+    for (size_t l = 0; l + 1 < ilu.f_lev_ptr.size(); l++) {
+      if (!ilu.f_nonempty[l]) continue;
+      int p0 = ilu.f_lev_ptr[l], cnt = ilu.f_lev_ptr[l + 1] - p0;
+      hipLaunchKernelGGL((k_ilu_fwd<NV, T>), dim3(nblk((size_t)cnt * NV)), dim3(kBlock), 0, st, p0, cnt,
+                         devp<int>(ilu.f_rows), devp<int>(ilu.f_ptr), devp<int>(ilu.f_col),
+                         devp<T>(ilu.f_val), b1p);
+      LAUNCH_CHECK();
+    }
+    constexpr int rows_per_block = kBlock / NV;
+    for (size_t l = 0; l + 1 < ilu.b_lev_ptr.size(); l++) {
+      int p0 = ilu.b_lev_ptr[l], cnt = ilu.b_lev_ptr[l + 1] - p0;
+      hipLaunchKernelGGL((k_ilu_bwd<NV, T, ZT>), dim3(nblk(cnt, rows_per_block)), dim3(kBlock), 0, st,
+                         p0, cnt, devp<int>(ilu.b_rows), devp<int>(ilu.b_ptr), devp<int>(ilu.b_col),
+                         devp<T>(ilu.b_val), devp<T>(ilu.dinv), b1p, op.o.ip, op.o.iT, x1p(), x1T(),
+                         slots);
+      LAUNCH_CHECK();
+    }
+  }
+
+  DevMem zeros;
+  const T *zero_vec() {
+    return devp<T>(zeros);
+  }
+
+  void apply(hipStream_t st, const ApplySlots *slots, bool z_double) override {
+    if (op.nv == 3) {
+      if (z_double) apply_nv<3, double>(st, slots);
+      else apply_nv<3, T>(st, slots);
+    } else {
+      if (z_double) apply_nv<4, double>(st, slots);
+      else apply_nv<4, T>(st, slots);
+    }
+  }
+
+  void first_stage(hipStream_t st, const ApplySlots *slots) override {
+    apply_first(st, slots);
+    const int n = op.n;
+    hipLaunchKernelGGL((k_finish<T, double>), dim3(nblk((size_t)n * op.nv)), dim3(kBlock), 0, st, n,
+                       op.nv, op.o.ip, op.o.iT, (const T *)nullptr, x1p(), x1T(), slots);
+    LAUNCH_CHECK();
+  }
+
+  void vcycle(hipStream_t st, int which, const double *b, double *x) override {
+    const AmgDev<T> &a = which == 0 ? amg_p : amg_s;
+    if (which == 1 && !have_s) throw Error{CPTR_ERR_INVALID_ARG, "no S~_T hierarchy in this handle"};
+    const int n = op.n;
+    T *bb = devp<T>(tmp), *xx = devp<T>(xp);
+    hipLaunchKernelGGL((k_convert<double, T>), dim3(sgrid(n)), dim3(kBlock), 0, st, b, bb, (size_t)n);
+    a.cycle(st, bb, xx);
+    hipLaunchKernelGGL((k_convert<T, double>), dim3(sgrid(n)), dim3(kBlock), 0, st, (const T *)xx, x,
+                       (size_t)n);
+    LAUNCH_CHECK();
+  }
+};
+
+// ---------------------------------------------------------------- handle
+}  // namespace cptr
+
+struct cptr_handle {
+  cptr::Options op;
+  const int *rp = nullptr, *ci = nullptr;
+  const double *vals = nullptr;
+  std::unique_ptr<cptr::PrecondBase> pc;
+  cptr::DevMem slots;                 // ApplySlots
+  hipStream_t stream = nullptr;       // internal stream (default priority)
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  cptr_stats stats{};
+  // FGMRES workspace
+  int m_alloc = 0;
+  cptr::DevMem V, Z, w, r, part, h1, h2, R, cs, sn, g, y, kstate, scal;
+  double *pinned = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  hipGraph_t graph = nullptr;
+  int graph_m = -1;
+};
+
+namespace cptr {
+
+template <typename T>
+static void build_precond(cptr_handle *h, const std::vector<int> &rp, const std::vector<int> &ci,
+                          const std::vector<double> &vals, const HostCSR *S) {
+  auto pc = std::make_unique<Precond<T>>();
+  Precond<T> &P = *pc;
+  const cptr_options &o = h->op.o;
+  const int n = h->op.n, nv = h->op.nv, nnzb = h->op.nnzb;
+  P.op = h->op;
+  P.rp = h->rp;
+  P.ci = h->ci;
+  const size_t s = sizeof(T);
+  // a0: p/T columns of A and the scalar sub-blocks on the cell graph
+  std::vector<T> acol((size_t)nnzb * nv * 2);
+  for (int k = 0; k < nnzb; k++)
+    for (int r = 0; r < nv; r++) {
+      acol[((size_t)k * nv + r) * 2 + 0] = T(vals[((size_t)k * nv + r) * nv + o.ip]);
+      acol[((size_t)k * nv + r) * 2 + 1] = T(vals[((size_t)k * nv + r) * nv + o.iT]);
+    }
+  upload(P.acol, acol);
+  auto sub = [&](int r, int c) {
+    HostCSR a;
+    a.nr = a.nc = n;
+    a.rp = rp;
+    a.ci = ci;
+    a.v.resize(nnzb);
+    for (int k = 0; k < nnzb; k++) a.v[k] = vals[((size_t)k * nv + r) * nv + c];
+    return a;
+  };
+  for (DevMem *m : {&P.bp, &P.bt, &P.xp, &P.dT, &P.dp, &P.tmp, &P.zeros}) m->alloc(n * s);
+  P.b1.alloc((size_t)n * nv * s);
+  hipLaunchKernelGGL((k_fill<T>), dim3(sgrid(n)), dim3(kBlock), 0, 0, devp<T>(P.zeros), (size_t)n, T(0));
+  LAUNCH_CHECK();
+  AmgParams prm;
+  prm.theta = o.amg_theta;
+  prm.max_levels = o.amg_max_levels;
+  prm.coarse_size = o.amg_coarse_size;
+  prm.seed = o.amg_seed;
+  prm.smooth_p = o.amg_smooth_p;
+  double bytes = 0.0;
+  if (o.first_stage != CPTR_FIRST_NONE) {
+    AmgHost hp;
+    amg_build(sub(o.ip, o.ip), prm, hp);
+    P.amg_p.build(hp, o.amg_sweeps);
+    if (o.first_stage != CPTR_FIRST_CPR) {
+      AmgHost hs;
+      amg_build(*S, prm, hs);
+      P.amg_s.build(hs, o.amg_sweeps);
+      P.have_s = true;
+      P.ApT.build(sub(o.ip, o.iT));
+      P.ATp.build(sub(o.iT, o.ip));
+    }
+    int ncyc = o.first_stage == CPTR_FIRST_BLOCK ? 2 : 1;
+    bytes += 8.0 * n * 2 + 2.0 * n * s;                         // restriction
+    bytes += ncyc * P.amg_p.bytes_per_cycle;
+    if (P.have_s) {
+      bytes += P.amg_s.bytes_per_cycle;
+      bytes += P.ATp.bytes() + 3.0 * n * s;                     // b~_T
+      if (o.first_stage == CPTR_FIRST_BLOCK) bytes += P.ApT.bytes() + 3.0 * n * s;
+    }
+  }
+  if (o.second_stage == CPTR_SECOND_BILU0 || o.second_stage == CPTR_SECOND_BILU0_MC) {
+    IluHost ih;
+    ilu_build(n, nv, rp.data(), ci.data(), vals.data(), o.second_stage == CPTR_SECOND_BILU0_MC, ih);
+    P.ilu.build(ih);
+    P.have_ilu = true;
+    bytes += P.ilu.bytes;
+    h->stats.ilu_levels_lower = int(ih.f_lev_ptr.size()) - 1;
+    h->stats.ilu_levels_upper = int(ih.b_lev_ptr.size()) - 1;
+    h->stats.ilu_colors = ih.ncolor;
+  }
+  if (o.second_stage != CPTR_SECOND_NONE)  // two-stage residual
+    bytes += (double)nnzb * (nv * 2 * s + 4) + 4.0 * (n + 1) + 8.0 * n * nv + 2.0 * n * s + n * nv * s;
+  bytes += 8.0 * n * nv;  // z
+  P.bytes = bytes;
+  h->stats.apply_bytes = bytes;
+  for (int w = 0; w < 2; w++) {
+    const AmgDev<T> &a = w == 0 ? P.amg_p : P.amg_s;
+    h->stats.nlevels[w] = int(a.lev.size());
+    for (size_t l = 0; l < a.lev.size() && l < 16; l++) {
+      h->stats.level_rows[w][l] = a.lev[l]->n;
+      h->stats.level_nnz[w][l] = l + 1 < a.lev.size() ? int(a.lev[l]->A.nnz) : a.nc * a.nc;
+    }
+  }
+  h->pc = std::move(pc);
+}
+
+template <typename T>
+static const AmgDev<T> *amg_of(const cptr_handle *h, int which);
+template <>
+const AmgDev<float> *amg_of<float>(const cptr_handle *h, int which) {
+  auto *p = dynamic_cast<Precond<float> *>(h->pc.get());
+  if (!p) return nullptr;
+  return which == 0 ? &p->amg_p : &p->amg_s;
+}
+template <>
+const AmgDev<double> *amg_of<double>(const cptr_handle *h, int which) {
+  auto *p = dynamic_cast<Precond<double> *>(h->pc.get());
+  if (!p) return nullptr;
+  return which == 0 ? &p->amg_p : &p->amg_s;
+}
+
+template <typename T>
+static const IluDev<T> *ilu_of(const cptr_handle *h) {
+  auto *p = dynamic_cast<Precond<T> *>(h->pc.get());
+  return (p && p->have_ilu) ? &p->ilu : nullptr;
+}
+
+static void validate_and_fetch(const cptr_bsr *A, const cptr_csr *S, const cptr_options &o,
+                               std::vector<int> &rp, std::vector<int> &ci, std::vector<double> &vals,
+                               HostCSR &sh) {
+  const int n = A->n, nv = A->nv, nnzb = A->nnzb;
+  if (n <= 0 || nnzb <= 0 || !A->row_ptr || !A->col_idx || !A->vals)
+    throw Error{CPTR_ERR_INVALID_ARG, "empty or null BSR matrix"};
+  if (nv != 3 && nv != 4) throw Error{CPTR_ERR_UNSUPPORTED, "nv must be 3 or 4"};
+  if (o.ip < 0 || o.ip >= nv || o.iT < 0 || o.iT >= nv || o.ip == o.iT)
+    throw Error{CPTR_ERR_INVALID_ARG, "invalid p/T slots"};
+  if (o.amg_max_levels < 1 || o.amg_coarse_size < 1 || o.amg_sweeps < 1 || !(o.amg_theta >= 0.0))
+    throw Error{CPTR_ERR_INVALID_ARG, "invalid AMG options"};
+  if (o.first_stage < 0 || o.first_stage > 3) throw Error{CPTR_ERR_INVALID_ARG, "invalid first stage"};
+  if (o.second_stage < 0 || o.second_stage > 3)
+    throw Error{CPTR_ERR_UNSUPPORTED, "unsupported second stage"};
+  if (o.precision != CPTR_FP32 && o.precision != CPTR_FP64)
+    throw Error{CPTR_ERR_INVALID_ARG, "invalid precision"};
+  rp.resize(n + 1);
+  ci.resize(nnzb);
+  vals.resize((size_t)nnzb * nv * nv);
+  CPTR_HIP_TRY(hipMemcpy(rp.data(), A->row_ptr, sizeof(int) * (n + 1), hipMemcpyDeviceToHost));
+  CPTR_HIP_TRY(hipMemcpy(ci.data(), A->col_idx, sizeof(int) * nnzb, hipMemcpyDeviceToHost));
+  CPTR_HIP_TRY(hipMemcpy(vals.data(), A->vals, sizeof(double) * vals.size(), hipMemcpyDeviceToHost));
+  if (rp[0] != 0 || rp[n] != nnzb) throw Error{CPTR_ERR_INVALID_ARG, "row_ptr does not span nnzb"};
+  std::vector<std::pair<int, int>> edges;
+  for (int i = 0; i < n; i++) {
+    if (rp[i + 1] < rp[i]) throw Error{CPTR_ERR_INVALID_ARG, "row_ptr not monotone"};
+    bool diag = false;
+    for (int k = rp[i]; k < rp[i + 1]; k++) {
+      if (ci[k] < 0 || ci[k] >= n) throw Error{CPTR_ERR_INVALID_ARG, "column index out of range"};
+      if (k > rp[i] && ci[k] <= ci[k - 1])
+        throw Error{CPTR_ERR_INVALID_ARG, "columns not strictly ascending"};
+      diag |= ci[k] == i;
+    }
+    if (!diag) throw Error{CPTR_ERR_INVALID_ARG, "missing diagonal block in row " + std::to_string(i)};
+  }
+  // structural symmetry
+  for (int i = 0; i < n; i++)
+    for (int k = rp[i]; k < rp[i + 1]; k++) {
+      int j = ci[k];
+      if (!std::binary_search(ci.begin() + rp[j], ci.begin() + rp[j + 1], i))
+        throw Error{CPTR_ERR_INVALID_ARG, "pattern is not structurally symmetric"};
+    }
+  for (double v : vals)
+    if (!std::isfinite(v)) throw Error{CPTR_ERR_NONFINITE, "non-finite value in A"};
+  const bool need_s = o.first_stage == CPTR_FIRST_BLOCK || o.first_stage == CPTR_FIRST_BLOCK_LOWER;
+  if (need_s) {
+    if (!S || S->n != n || S->nnz <= 0 || !S->row_ptr || !S->col_idx || !S->vals)
+      throw Error{CPTR_ERR_INVALID_ARG, "the block first stage needs S~_T on the cell graph"};
+    sh.nr = sh.nc = n;
+    sh.rp.resize(n + 1);
+    sh.ci.resize(S->nnz);
+    sh.v.resize(S->nnz);
+    CPTR_HIP_TRY(hipMemcpy(sh.rp.data(), S->row_ptr, sizeof(int) * (n + 1), hipMemcpyDeviceToHost));
+    CPTR_HIP_TRY(hipMemcpy(sh.ci.data(), S->col_idx, sizeof(int) * S->nnz, hipMemcpyDeviceToHost));
+    CPTR_HIP_TRY(hipMemcpy(sh.v.data(), S->vals, sizeof(double) * S->nnz, hipMemcpyDeviceToHost));
+    if (sh.rp[0] != 0 || sh.rp[n] != S->nnz) throw Error{CPTR_ERR_INVALID_ARG, "S~_T row_ptr"};
+    for (int i = 0; i < n; i++) {
+      if (sh.rp[i + 1] < sh.rp[i]) throw Error{CPTR_ERR_INVALID_ARG, "S~_T row_ptr not monotone"};
+      for (int k = sh.rp[i]; k < sh.rp[i + 1]; k++) {
+        if (sh.ci[k] < 0 || sh.ci[k] >= n) throw Error{CPTR_ERR_INVALID_ARG, "S~_T column out of range"};
+        if (k > sh.rp[i] && sh.ci[k] <= sh.ci[k - 1])
+          throw Error{CPTR_ERR_INVALID_ARG, "S~_T columns not strictly ascending"};
+      }
+    }
+    for (double v : sh.v)
+      if (!std::isfinite(v)) throw Error{CPTR_ERR_NONFINITE, "non-finite value in S~_T"};
+  }
+}
+
+static int fail(const Error &e) {
+  set_last_error(e.msg);
+  return e.code;
+}
+
+// ---------------------------------------------------------------- FGMRES
+template <int NV, typename ZT>
+static void launch_spmv(cptr_handle *h, hipStream_t st, const ZT *x, const ApplySlots *sl,
+                        const double *b, double *y) {
+  const int n = h->op.n;
+  if (b)
+    hipLaunchKernelGGL((k_bsr_spmv<NV, ZT, true>), dim3(nblk(n, 64)), dim3(64 * NV), 0, st, n, h->rp, h->ci,
+                       h->vals, x, sl, b, y);
+  else
+    hipLaunchKernelGGL((k_bsr_spmv<NV, ZT, false>), dim3(nblk(n, 64)), dim3(64 * NV), 0, st, n, h->rp,
+                       h->ci, h->vals, x, sl, (const double *)nullptr, y);
+  LAUNCH_CHECK();
+}
+
+// y = A x, or y = b - A x when b is given
+template <typename ZT>
+static void spmv(cptr_handle *h, hipStream_t st, const ZT *x, const double *b, double *y) {
+  if (h->op.nv == 3) launch_spmv<3, ZT>(h, st, x, nullptr, b, y);
+  else launch_spmv<4, ZT>(h, st, x, nullptr, b, y);
+}
+
+// y = A z with z read from the slots
+template <typename ZT>
+static void spmv_slot(cptr_handle *h, hipStream_t st, const ApplySlots *sl, double *y) {
+  if (h->op.nv == 3) launch_spmv<3, ZT>(h, st, nullptr, sl, nullptr, y);
+  else launch_spmv<4, ZT>(h, st, nullptr, sl, nullptr, y);
+}
+
+static void ensure_krylov(cptr_handle *h, int m) {
+  if (h->m_alloc >= m) return;
+  const size_t N = (size_t)h->op.n * h->op.nv;
+  const size_t zb = h->op.o.precision == CPTR_FP32 ? 4 : 8;
+  h->V.alloc((m + 1) * N * 8);
+  h->Z.alloc(m * N * zb);
+  h->w.alloc(N * 8);
+  h->r.alloc(N * 8);
+  h->part.alloc((size_t)kDotBlocks * 64 * 8);
+  h->h1.alloc(72 * 8);
+  h->h2.alloc(72 * 8);
+  h->R.alloc((size_t)(m + 1) * m * 8);
+  h->cs.alloc(m * 8);
+  h->sn.alloc(m * 8);
+  h->g.alloc((m + 1) * 8);
+  h->y.alloc(m * 8);
+  h->kstate.alloc(sizeof(KState));
+  h->scal.alloc(8 * 8);
+  if (!h->pinned) CPTR_HIP_TRY(hipHostMalloc((void **)&h->pinned, 8 * sizeof(double), hipHostMallocDefault));
+  h->m_alloc = m;
+  if (h->graph_exec) {
+    (void)hipGraphExecDestroy(h->graph_exec);
+    (void)hipGraphDestroy(h->graph);
+    h->graph_exec = nullptr;
+    h->graph = nullptr;
+    h->graph_m = -1;
+  }
+}
+
+// ||x||_2 into scal[slot] (device)
+static void norm2(cptr_handle *h, hipStream_t st, const double *x, size_t N, int slot) {
+  const int g = sgrid(N);
+  hipLaunchKernelGGL(k_norm2_partial, dim3(g), dim3(kBlock), 0, st, x, N, devp<double>(h->part));
+  hipLaunchKernelGGL((k_reduce<1>), dim3(1), dim3(kBlock), 0, st, (const double *)devp<double>(h->part), g,
+                     (const int *)nullptr, 1, devp<double>(h->scal) + slot, 1);
+  LAUNCH_CHECK();
+}
+
+static double fetch(cptr_handle *h, hipStream_t st, const double *dev) {
+  CPTR_HIP_TRY(hipMemcpyAsync(h->pinned, dev, sizeof(double), hipMemcpyDeviceToHost, st));
+  CPTR_HIP_TRY(hipStreamSynchronize(st));
+  return h->pinned[0];
+}
+
+// one Arnoldi step for column j (read from the device state)
+template <typename ZT, int MAXK>
+static void arnoldi_step(cptr_handle *h, hipStream_t st) {
+  const size_t N = (size_t)h->op.n * h->op.nv;
+  KState *ks = devp<KState>(h->kstate);
+  ApplySlots *sl = devp<ApplySlots>(h->slots);
+  const int g = sgrid(N);
+  double *part = devp<double>(h->part);
+  hipLaunchKernelGGL(k_set_slots_krylov, dim3(1), dim3(64), 0, st, sl, (const double *)devp<double>(h->V),
+                     h->Z.p, N, (int)sizeof(ZT), (const KState *)ks);
+  LAUNCH_CHECK();
+  h->pc->apply(st, sl, sizeof(ZT) == 8);
+  // w = A z_j (the column address is read from the slots)
+  spmv_slot<ZT>(h, st, sl, devp<double>(h->w));
+  const int *jd = &ks->j;
+  hipLaunchKernelGGL((k_mdot<MAXK>), dim3(g), dim3(kBlock), 0, st, (const double *)devp<double>(h->V), N, jd,
+                     (const double *)devp<double>(h->w), part);
+  hipLaunchKernelGGL((k_reduce<MAXK>), dim3(1), dim3(kBlock), 0, st, (const double *)part, g, jd, 0,
+                     devp<double>(h->h1), 0);
+  hipLaunchKernelGGL((k_cgs_update_mdot<MAXK>), dim3(g), dim3(kBlock), 0, st, (const double *)devp<double>(h->V),
+                     N, jd, (const double *)devp<double>(h->h1), devp<double>(h->w), part);
+  hipLaunchKernelGGL((k_reduce<MAXK>), dim3(1), dim3(kBlock), 0, st, (const double *)part, g, jd, 0,
+                     devp<double>(h->h2), 0);
+  hipLaunchKernelGGL((k_cgs_update_norm<MAXK>), dim3(g), dim3(kBlock), 0, st, (const double *)devp<double>(h->V),
+                     N, jd, (const double *)devp<double>(h->h2), devp<double>(h->w), part);
+  hipLaunchKernelGGL((k_reduce<1>), dim3(1), dim3(kBlock), 0, st, (const double *)part, g, (const int *)nullptr,
+                     1, &ks->hn, 1);
+  hipLaunchKernelGGL(k_scale_next, dim3(g), dim3(kBlock), 0, st, devp<double>(h->V), N, (const KState *)ks,
+                     (const double *)devp<double>(h->w));
+  hipLaunchKernelGGL(k_givens, dim3(1), dim3(64), 0, st, ks, (const double *)devp<double>(h->h1),
+                     (const double *)devp<double>(h->h2), devp<double>(h->R), devp<double>(h->cs),
+                     devp<double>(h->sn), devp<double>(h->g));
+  LAUNCH_CHECK();
+}
+
+
+template <typename ZT>
+static int fgmres_impl(cptr_handle *h, const double *b, double *x, const cptr_solve_opts &so,
+                       cptr_solve_info &info, hipStream_t user) {
+  auto t0 = std::chrono::steady_clock::now();
+  const size_t N = (size_t)h->op.n * h->op.nv;
+  const int m = so.restart;
+  hipStream_t st = h->stream;
+  // order the internal stream after the caller's
+  CPTR_HIP_TRY(hipEventRecord(h->ev_in, user));
+  CPTR_HIP_TRY(hipStreamWaitEvent(st, h->ev_in, 0));
+  ensure_krylov(h, m);
+  KState *ks = devp<KState>(h->kstate);
+  double *scal = devp<double>(h->scal);
+  norm2(h, st, b, N, 0);
+  const double bnorm = fetch(h, st, scal);
+  info = cptr_solve_info{};
+  if (!std::isfinite(bnorm)) throw Error{CPTR_ERR_NONFINITE, "non-finite right-hand side"};
+  if (!so.nonzero_guess || bnorm == 0.0) {
+    hipLaunchKernelGGL((k_fill<double>), dim3(sgrid(N)), dim3(kBlock), 0, st, x, N, 0.0);
+    LAUNCH_CHECK();
+  }
+  if (bnorm == 0.0) {
+    info.converged = 1;
+    CPTR_HIP_TRY(hipStreamSynchronize(st));
+    return CPTR_OK;
+  }
+  const bool use_graph = h->op.o.use_graph != 0;
+  auto step = [&]() {
+    if (m <= 32) arnoldi_step<ZT, 32>(h, st);
+    else arnoldi_step<ZT, 64>(h, st);
+  };
+  if (use_graph && h->graph_m != m) {
+    if (h->graph_exec) {
+      (void)hipGraphExecDestroy(h->graph_exec);
+      (void)hipGraphDestroy(h->graph);
+      h->graph_exec = nullptr;
+    }
+    CPTR_HIP_TRY(hipStreamSynchronize(st));
+    CPTR_HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    try {
+      step();
+    } catch (...) {
+      hipGraph_t junk;
+      (void)hipStreamEndCapture(st, &junk);
+      if (junk) (void)hipGraphDestroy(junk);
+      throw;
+    }
+    CPTR_HIP_TRY(hipStreamEndCapture(st, &h->graph));
+    CPTR_HIP_TRY(hipGraphInstantiate(&h->graph_exec, h->graph, nullptr, nullptr, 0));
+    h->graph_m = m;
+  }
+  int iters = 0, cycles = 0, converged = 0;
+  double est = 0.0, truer = 0.0;
+  for (;;) {
+    spmv<double>(h, st, x, b, devp<double>(h->r));
+    norm2(h, st, devp<double>(h->r), N, 1);
+    const double beta = fetch(h, st, scal + 1);
+    truer = beta / bnorm;
+    if (!std::isfinite(beta)) throw Error{CPTR_ERR_NONFINITE, "non-finite residual"};
+    if (truer <= so.rtol) {
+      converged = 1;
+      if (cycles == 0) est = truer;
+      break;
+    }
+    if (iters >= so.maxit) break;
+    hipLaunchKernelGGL(k_cycle_init, dim3(1), dim3(64), 0, st, ks, (const double *)(scal + 1),
+                       devp<double>(h->g), m);
+    hipLaunchKernelGGL(k_first_vector, dim3(sgrid(N)), dim3(kBlock), 0, st, devp<double>(h->V), N,
+                       (const double *)devp<double>(h->r), (const double *)(scal + 1));
+    LAUNCH_CHECK();
+    int j = 0;
+    while (j < m && iters < so.maxit) {
+      if (use_graph) CPTR_HIP_TRY(hipGraphLaunch(h->graph_exec, st));
+      else step();
+      j++;
+      iters++;
+      h->stats.applies++;
+      CPTR_HIP_TRY(hipMemcpyAsync(h->pinned, &ks->hn, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+      CPTR_HIP_TRY(hipStreamSynchronize(st));
+      const double hn = h->pinned[0], absg = h->pinned[1];
+      est = absg / bnorm;
+      if (!std::isfinite(est)) throw Error{CPTR_ERR_NONFINITE, "non-finite Arnoldi step"};
+      if (est <= so.rtol || hn == 0.0) break;
+    }
+    hipLaunchKernelGGL(k_solve_y, dim3(1), dim3(64), 0, st, (const KState *)ks,
+                       (const double *)devp<double>(h->R), (const double *)devp<double>(h->g),
+                       devp<double>(h->y));
+    hipLaunchKernelGGL((k_update_x<ZT>), dim3(sgrid(N)), dim3(kBlock), 0, st, x, (const ZT *)h->Z.p, N,
+                       (const KState *)ks, (const double *)devp<double>(h->y));
+    LAUNCH_CHECK();
+    cycles++;
+  }
+  CPTR_HIP_TRY(hipEventRecord(h->ev_out, st));
+  CPTR_HIP_TRY(hipStreamWaitEvent(user, h->ev_out, 0));
+  CPTR_HIP_TRY(hipStreamSynchronize(st));
+  info.iters = iters;
+  info.restarts = cycles > 0 ? cycles - 1 : 0;
+  info.converged = converged;
+  info.relres_est = est;
+  info.relres_true = truer;
+  info.solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  return converged ? CPTR_OK : CPTR_NOT_CONVERGED;
+}
+
+}  // namespace cptr
+
+using namespace cptr;
+
+extern "C" {
+
+void cptr_default_options(cptr_options *o) {
+  if (!o) return;
+  o->first_stage = CPTR_FIRST_BLOCK;
+  o->second_stage = CPTR_SECOND_BILU0_MC;
+  o->precision = CPTR_FP32;
+  o->ip = 0;
+  o->iT = -1;
+  o->amg_theta = 0.08;
+  o->amg_max_levels = 10;
+  o->amg_coarse_size = 512;
+  o->amg_seed = 0;
+  o->amg_sweeps = 1;
+  o->amg_smooth_p = 1;
+  o->use_graph = 1;
+}
+
+int cptr_setup(cptr_handle **out, const cptr_bsr *A, const cptr_csr *S_T, const cptr_options *opt,
+               void *stream) {
+  if (!out || !A) return fail(Error{CPTR_ERR_INVALID_ARG, "null argument"});
+  *out = nullptr;
+  cptr_handle *h = nullptr;
+  try {
+    auto t0 = std::chrono::steady_clock::now();
+    cptr_options o;
+    if (opt) o = *opt;
+    else cptr_default_options(&o);
+    if (o.iT < 0) o.iT = A->nv - 1;
+    CPTR_HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+    std::vector<int> rp, ci;
+    std::vector<double> vals;
+    HostCSR sh;
+    validate_and_fetch(A, S_T, o, rp, ci, vals, sh);
+    h = new cptr_handle();
+    h->op.o = o;
+    h->op.n = A->n;
+    h->op.nv = A->nv;
+    h->op.nnzb = A->nnzb;
+    h->rp = A->row_ptr;
+    h->ci = A->col_idx;
+    h->vals = A->vals;
+    CPTR_HIP_TRY(hipStreamCreate(&h->stream));
+    CPTR_HIP_TRY(hipEventCreateWithFlags(&h->ev_in, hipEventDisableTiming));
+    CPTR_HIP_TRY(hipEventCreateWithFlags(&h->ev_out, hipEventDisableTiming));
+    h->slots.alloc(sizeof(ApplySlots));
+    if (o.precision == CPTR_FP32) build_precond<float>(h, rp, ci, vals, &sh);
+    else build_precond<double>(h, rp, ci, vals, &sh);
+    const int nv = A->nv;
+    h->stats.spmv_bytes = (double)A->nnzb * (nv * nv * 8.0 + 4) + 4.0 * (A->n + 1) + 2.0 * 8 * A->n * nv;
+    CPTR_HIP_TRY(hipDeviceSynchronize());
+    h->stats.setup_ms =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    *out = h;
+    return CPTR_OK;
+  } catch (const Error &e) {
+    delete h;
+    return fail(e);
+  } catch (const std::bad_alloc &) {
+    delete h;
+    return fail(Error{CPTR_ERR_OOM, "host allocation failed"});
+  } catch (...) {
+    delete h;
+    return fail(Error{CPTR_ERR_SETUP, "unexpected failure in setup"});
+  }
+}
+
+static int apply_common(cptr_handle *h, const double *v, void *z, void *stream, int what, int which) {
+  if (!h || !v || !z) return fail(Error{CPTR_ERR_INVALID_ARG, "null argument"});
+  if ((const void *)v == z) return fail(Error{CPTR_ERR_INVALID_ARG, "input and output alias"});
+  try {
+    hipStream_t st = (hipStream_t)stream;
+    if (what == 2) {
+      h->pc->vcycle(st, which, v, (double *)z);
+      return CPTR_OK;
+    }
+    ApplySlots *sl = devp<ApplySlots>(h->slots);
+    hipLaunchKernelGGL(k_set_slots, dim3(1), dim3(64), 0, st, sl, v, z);
+    LAUNCH_CHECK();
+    if (what == 0) {
+      h->pc->apply(st, sl, true);
+      h->stats.applies++;
+    } else {
+      h->pc->first_stage(st, sl);
+    }
+    return CPTR_OK;
+  } catch (const Error &e) {
+    return fail(e);
+  } catch (...) {
+    return fail(Error{CPTR_ERR_HIP, "unexpected failure"});
+  }
+}
+
+int cptr_apply(cptr_handle *h, const double *v, double *z, void *stream) {
+  return apply_common(h, v, z, stream, 0, 0);
+}
+
+int cptr_first_stage(cptr_handle *h, const double *v, double *x1, void *stream) {
+  if (h && h->op.o.first_stage == CPTR_FIRST_NONE) {
+    try {
+      const size_t N = (size_t)h->op.n * h->op.nv;
+      hipLaunchKernelGGL((k_fill<double>), dim3(sgrid(N)), dim3(kBlock), 0, (hipStream_t)stream, x1, N, 0.0);
+      LAUNCH_CHECK();
+      return CPTR_OK;
+    } catch (const Error &e) {
+      return fail(e);
+    }
+  }
+  return apply_common(h, v, x1, stream, 1, 0);
+}
+
+int cptr_vcycle(cptr_handle *h, int which, const double *b, double *x, void *stream) {
+  if (!h) return fail(Error{CPTR_ERR_INVALID_ARG, "null handle"});
+  if (which != 0 && which != 1) return fail(Error{CPTR_ERR_INVALID_ARG, "which must be 0 or 1"});
+  if (h->op.o.first_stage == CPTR_FIRST_NONE)
+    return fail(Error{CPTR_ERR_INVALID_ARG, "no AMG hierarchy in this handle"});
+  return apply_common(h, b, x, stream, 2, which);
+}
+
+int fgmres_solve(cptr_handle *h, const double *b, double *x, const cptr_solve_opts *so_in,
+                 cptr_solve_info *info_out, void *stream) {
+  if (!h || !b || !x) return fail(Error{CPTR_ERR_INVALID_ARG, "null argument"});
+  cptr_solve_opts so{30, 1e-6, 1000, 0};
+  if (so_in) so = *so_in;
+  if (so.restart < 1 || so.restart > 64) return fail(Error{CPTR_ERR_INVALID_ARG, "restart must be in [1, 64]"});
+  if (!(so.rtol > 0.0) || so.maxit < 0) return fail(Error{CPTR_ERR_INVALID_ARG, "invalid tolerance or maxit"});
+  cptr_solve_info info{};
+  try {
+    int rc = h->op.o.precision == CPTR_FP32 ? fgmres_impl<float>(h, b, x, so, info, (hipStream_t)stream)
+                                            : fgmres_impl<double>(h, b, x, so, info, (hipStream_t)stream);
+    if (info_out) *info_out = info;
+    return rc;
+  } catch (const Error &e) {
+    if (info_out) *info_out = info;
+    return fail(e);
+  } catch (...) {
+    return fail(Error{CPTR_ERR_HIP, "unexpected failure in fgmres_solve"});
+  }
+}
+
+int cptr_update_values(cptr_handle *, const double *, const double *, void *) {
+  return fail(Error{CPTR_ERR_UNSUPPORTED, "numeric re-setup is not available"});
+}
+
+int cptr_get_stats(const cptr_handle *h, cptr_stats *st) {
+  if (!h || !st) return fail(Error{CPTR_ERR_INVALID_ARG, "null argument"});
+  *st = h->stats;
+  return CPTR_OK;
+}
+
+int cptr_get_aggregates(const cptr_handle *h, int which, int level, int *agg_host) {
+  if (!h || (which != 0 && which != 1)) return fail(Error{CPTR_ERR_INVALID_ARG, "bad argument"});
+  const std::vector<std::vector<int>> *agg = nullptr;
+  if (auto a = amg_of<float>(h, which)) agg = &a->agg;
+  if (auto a = amg_of<double>(h, which)) agg = &a->agg;
+  if (!agg || level < 0 || level + 1 >= (int)agg->size())
+    return fail(Error{CPTR_ERR_INVALID_ARG, "no such aggregation level"});
+  const std::vector<int> &v = (*agg)[level];
+  if (agg_host) std::copy(v.begin(), v.end(), agg_host);
+  return (int)v.size();
+}
+
+int cptr_get_ilu_schedule(const cptr_handle *h, int *ll, int *lu, int *color) {
+  if (!h) return fail(Error{CPTR_ERR_INVALID_ARG, "null handle"});
+  const std::vector<int> *a = nullptr, *b = nullptr, *c = nullptr;
+  if (auto f = ilu_of<float>(h)) { a = &f->lev_lower; b = &f->lev_upper; c = &f->color; }
+  if (auto f = ilu_of<double>(h)) { a = &f->lev_lower; b = &f->lev_upper; c = &f->color; }
+  if (!a) return fail(Error{CPTR_ERR_INVALID_ARG, "no ILU(0) second stage in this handle"});
+  if (ll) std::copy(a->begin(), a->end(), ll);
+  if (lu) std::copy(b->begin(), b->end(), lu);
+  if (color) std::copy(c->begin(), c->end(), color);
+  return CPTR_OK;
+}
+
+int cptr_bsr_spmv(int n, int nv, const int *rp, const int *ci, const double *vals, const double *x,
+                  double *y, void *stream) {
+  if (n < 0 || (nv != 3 && nv != 4) || !rp || !ci || !vals || !x || !y)
+    return fail(Error{CPTR_ERR_INVALID_ARG, "bad argument"});
+  if (n == 0) return CPTR_OK;
+  hipStream_t st = (hipStream_t)stream;
+  if (nv == 3)
+    hipLaunchKernelGGL((k_bsr_spmv<3, double, false>), dim3(nblk(n, 64)), dim3(192), 0, st, n, rp, ci, vals, x,
+                       (const ApplySlots *)nullptr, (const double *)nullptr, y);
+  else
+    hipLaunchKernelGGL((k_bsr_spmv<4, double, false>), dim3(nblk(n, 64)), dim3(256), 0, st, n, rp, ci, vals, x,
+                       (const ApplySlots *)nullptr, (const double *)nullptr, y);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(Error{CPTR_ERR_HIP, hipGetErrorString(e)});
+  return CPTR_OK;
+}
+
+const char *cptr_status_string(int s) {
+  switch (s) {
+    case CPTR_OK: return "CPTR_OK";
+    case CPTR_NOT_CONVERGED: return "CPTR_NOT_CONVERGED";
+    case CPTR_ERR_INVALID_ARG: return "CPTR_ERR_INVALID_ARG";
+    case CPTR_ERR_UNSUPPORTED: return "CPTR_ERR_UNSUPPORTED";
+    case CPTR_ERR_NONFINITE: return "CPTR_ERR_NONFINITE";
+    case CPTR_ERR_SINGULAR_BLOCK: return "CPTR_ERR_SINGULAR_BLOCK";
+    case CPTR_ERR_OOM: return "CPTR_ERR_OOM";
+    case CPTR_ERR_HIP: return "CPTR_ERR_HIP";
+    case CPTR_ERR_SETUP: return "CPTR_ERR_SETUP";
+    default: return "unknown status";
+  }
+}
+
+const char *cptr_last_error(void) { return g_last_error.c_str(); }
+
+void cptr_destroy(cptr_handle *h) {
+  if (!h) return;
+  if (h->stream) (void)hipStreamSynchronize(h->stream);
+  if (h->graph_exec) (void)hipGraphExecDestroy(h->graph_exec);
+  if (h->graph) (void)hipGraphDestroy(h->graph);
+  if (h->pinned) (void)hipHostFree(h->pinned);
+  if (h->ev_in) (void)hipEventDestroy(h->ev_in);
+  if (h->ev_out) (void)hipEventDestroy(h->ev_out);
+  h->pc.reset();
+  if (h->stream) (void)hipStreamDestroy(h->stream);
+  delete h;
+}
+
+}  // extern "C"

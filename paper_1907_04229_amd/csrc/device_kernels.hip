@@ -1,0 +1,489 @@
+// Device kernels of libcptr (gfx950).  Included once by cptr.hip.
+#pragma once
+
+#include "kernels.h"
+
+namespace cptr {
+
+constexpr int kBlock = 256;
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// SELL-64 products.  One thread per row; a wave owns one slice.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ T sell_row_dot(const Sell<T> &A, int row, const T *__restrict__ x) {
+  const int s = row >> 6, lane = row & 63;
+  const int b = A.sptr[s], w = (A.sptr[s + 1] - b) >> 6;
+  const int *__restrict__ c = A.col + b + lane;
+  const T *__restrict__ v = A.val + b + lane;
+  T acc = T(0);
+  for (int k = 0; k < w; k++) acc += v[k * kSlice] * x[c[k * kSlice]];
+  return acc;
+}
+
+// y = A x  (mode 0),  y += A x  (mode 1),  y = b - A x  (mode 2)
+template <typename T, int MODE>
+__global__ void __launch_bounds__(kBlock) k_sell_spmv(Sell<T> A, const T *__restrict__ x,
+                                                      const T *__restrict__ b, T *__restrict__ y) {
+  const int row = blockIdx.x * kBlock + threadIdx.x;
+  if (row >= A.nrows) return;
+  const T ax = sell_row_dot(A, row, x);
+  if (MODE == 0) y[row] = ax;
+  if (MODE == 1) y[row] += ax;
+  if (MODE == 2) y[row] = b[row] - ax;
+}
+
+// first l1-Jacobi sweep from a zero guess fused with the residual:
+//   x = D^{-1} b,  r = b - A D^{-1} b
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_smooth0_resid(Sell<T> A, const T *__restrict__ dinv,
+                                                          const T *__restrict__ b, T *__restrict__ x,
+                                                          T *__restrict__ r) {
+  const int row = blockIdx.x * kBlock + threadIdx.x;
+  if (row >= A.nrows) return;
+  const int s = row >> 6, lane = row & 63;
+  const int base = A.sptr[s], w = (A.sptr[s + 1] - base) >> 6;
+  T acc = T(0);
+  for (int k = 0; k < w; k++) {
+    const int c = A.col[base + k * kSlice + lane];
+    acc += A.val[base + k * kSlice + lane] * (dinv[c] * b[c]);
+  }
+  const T bi = b[row];
+  x[row] = dinv[row] * bi;
+  r[row] = bi - acc;
+}
+
+// x_out = x_in + D^{-1} (b - A x_in)
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_jacobi(Sell<T> A, const T *__restrict__ dinv,
+                                                   const T *__restrict__ b, const T *__restrict__ xin,
+                                                   T *__restrict__ xout) {
+  const int row = blockIdx.x * kBlock + threadIdx.x;
+  if (row >= A.nrows) return;
+  const T ax = sell_row_dot(A, row, xin);
+  xout[row] = xin[row] + dinv[row] * (b[row] - ax);
+}
+
+// coarsest level: x = A_c^{-1} b with the explicit FP64 inverse; one wave per row
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_coarse_gemv(const double *__restrict__ inv, int nc,
+                                                        const T *__restrict__ b, T *__restrict__ x) {
+  const int wave = (blockIdx.x * kBlock + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (wave >= nc) return;
+  const double *__restrict__ row = inv + (size_t)wave * nc;
+  double acc = 0.0;
+  for (int c = lane; c < nc; c += 64) acc += row[c] * double(b[c]);
+  acc = wave_sum(acc);
+  if (lane == 0) x[wave] = T(acc);
+}
+
+// ---------------------------------------------------------------------------
+// first stage: restriction, two-stage residual, finishing
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_restrict_pT(int n, int nv, int ip, int iT,
+                                                        const ApplySlots *__restrict__ slots,
+                                                        T *__restrict__ bp, T *__restrict__ bt) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const double *__restrict__ v = slots->v;
+  bp[i] = T(v[(size_t)i * nv + ip]);
+  if (bt) bt[i] = T(v[(size_t)i * nv + iT]);
+}
+
+// b1 = v - A R^T (d_p, d_T): only the p and T columns of each block are used;
+// acol holds them as [block][row r][0: p column, 1: T column].  One thread
+// per (cell, equation).
+template <int NV, typename T>
+__global__ void __launch_bounds__(kBlock) k_resid_pT(int n, const int *__restrict__ rp,
+                                                     const int *__restrict__ ci,
+                                                     const T *__restrict__ acol,
+                                                     const ApplySlots *__restrict__ slots,
+                                                     const T *__restrict__ dp,
+                                                     const T *__restrict__ dT,
+                                                     T *__restrict__ b1) {
+  const int t = blockIdx.x * kBlock + threadIdx.x;
+  const int i = t / NV, r = t - i * NV;
+  if (i >= n) return;
+  T acc = T(0);
+  const int e = rp[i + 1];
+  if (dT) {
+    for (int k = rp[i]; k < e; k++) {
+      const int c = ci[k];
+      const T *a = acol + ((size_t)k * NV + r) * 2;
+      acc += a[0] * dp[c] + a[1] * dT[c];
+    }
+  } else {
+    for (int k = rp[i]; k < e; k++) acc += acol[((size_t)k * NV + r) * 2] * dp[ci[k]];
+  }
+  b1[(size_t)i * NV + r] = T(slots->v[(size_t)i * NV + r]) - acc;
+}
+
+template <typename T, typename ZT>
+__global__ void __launch_bounds__(kBlock) k_finish(int n, int nv, int ip, int iT,
+                                                   const T *__restrict__ b1,
+                                                   const T *__restrict__ dp,
+                                                   const T *__restrict__ dT,
+                                                   const ApplySlots *__restrict__ slots) {
+  const int t = blockIdx.x * kBlock + threadIdx.x;
+  if (t >= n * nv) return;
+  const int i = t / nv, r = t - i * nv;
+  T z = b1 ? b1[t] : T(0);
+  if (dp && r == ip) z += dp[i];
+  if (dT && r == iT) z += dT[i];
+  reinterpret_cast<ZT *>(slots->z)[t] = ZT(z);
+}
+
+// ---------------------------------------------------------------------------
+// BILU(0) triangular solves, one launch per level; NV threads per row
+// ---------------------------------------------------------------------------
+// forward: y_i = b_i - sum_k L_ik y_k   (in place in y, which holds b1)
+template <int NV, typename T>
+__global__ void __launch_bounds__(kBlock) k_ilu_fwd(int p0, int cnt, const int *__restrict__ rows,
+                                                    const int *__restrict__ ptr,
+                                                    const int *__restrict__ col,
+                                                    const T *__restrict__ val, T *__restrict__ y) {
+  const int t = blockIdx.x * kBlock + threadIdx.x;
+  const int q = t / NV, r = t - q * NV;
+  if (q >= cnt) return;
+  const int p = p0 + q;
+  const int i = rows[p];
+  T s = y[(size_t)i * NV + r];
+  for (int k = ptr[p]; k < ptr[p + 1]; k++) {
+    const T *l = val + ((size_t)k * NV + r) * NV;
+    const T *yk = y + (size_t)col[k] * NV;
+#pragma unroll
+    for (int c = 0; c < NV; c++) s -= l[c] * yk[c];
+  }
+  y[(size_t)i * NV + r] = s;
+}
+
+// backward: w_i = U_ii^{-1} (y_i - sum_k U_ik w_k), in place in y; also
+// writes z_i = w_i + x1_i.
+template <int NV, typename T, typename ZT>
+__global__ void __launch_bounds__(kBlock) k_ilu_bwd(int p0, int cnt, const int *__restrict__ rows,
+                                                    const int *__restrict__ ptr,
+                                                    const int *__restrict__ col,
+                                                    const T *__restrict__ val,
+                                                    const T *__restrict__ dinv, T *__restrict__ y,
+                                                    int ip, int iT, const T *__restrict__ dp,
+                                                    const T *__restrict__ dT,
+                                                    const ApplySlots *__restrict__ slots) {
+  // rows never straddle workgroups: kBlock / NV rows per workgroup
+  __shared__ T sh[kBlock];
+  constexpr int kRows = kBlock / NV;
+  const int r = threadIdx.x % NV;
+  const int q = blockIdx.x * kRows + threadIdx.x / NV;
+  const bool live = q < cnt && threadIdx.x < kRows * NV;
+  int i = 0;
+  T s = T(0);
+  if (live) {
+    const int p = p0 + q;
+    i = rows[p];
+    s = y[(size_t)i * NV + r];
+    for (int k = ptr[p]; k < ptr[p + 1]; k++) {
+      const T *u = val + ((size_t)k * NV + r) * NV;
+      const T *wk = y + (size_t)col[k] * NV;
+#pragma unroll
+      for (int c = 0; c < NV; c++) s -= u[c] * wk[c];
+    }
+  }
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  if (!live) return;
+  const T *d = dinv + ((size_t)i * NV + r) * NV;
+  const int base = threadIdx.x - r;
+  T w = T(0);
+#pragma unroll
+  for (int c = 0; c < NV; c++) w += d[c] * sh[base + c];
+  y[(size_t)i * NV + r] = w;
+  T z = w;
+  if (dp && r == ip) z += dp[i];
+  if (dT && r == iT) z += dT[i];
+  reinterpret_cast<ZT *>(slots->z)[(size_t)i * NV + r] = ZT(z);
+}
+
+// ---------------------------------------------------------------------------
+// FP64 BSR product for the Arnoldi step and the true residual
+//   y = A x (RESID = false),  y = b - A x (RESID = true)
+// 64 block rows per workgroup, NV threads per block row (one per equation).
+// ---------------------------------------------------------------------------
+// With `slots` non-null, x is read from slots->z (the current Krylov column).
+template <int NV, typename XT, bool RESID>
+__global__ void __launch_bounds__(64 * NV) k_bsr_spmv(int n, const int *__restrict__ rp,
+                                                      const int *__restrict__ ci,
+                                                      const double *__restrict__ vals,
+                                                      const XT *__restrict__ xarg,
+                                                      const ApplySlots *__restrict__ slots,
+                                                      const double *__restrict__ b,
+                                                      double *__restrict__ y) {
+  const XT *__restrict__ x = slots ? reinterpret_cast<const XT *>(slots->z) : xarg;
+  const int t = threadIdx.x;
+  const int i = blockIdx.x * 64 + t / NV, r = t % NV;
+  if (i >= n) return;
+  double acc = 0.0;
+  const int e = rp[i + 1];
+  for (int k = rp[i]; k < e; k++) {
+    const double *a = vals + ((size_t)k * NV + r) * NV;
+    const XT *xc = x + (size_t)ci[k] * NV;
+#pragma unroll
+    for (int c = 0; c < NV; c++) acc += a[c] * double(xc[c]);
+  }
+  const size_t o = (size_t)i * NV + r;
+  y[o] = RESID ? b[o] - acc : acc;
+}
+
+// ---------------------------------------------------------------------------
+// Krylov kernels (FP64).  Basis V is stored vector after vector: V[k*N + i].
+// Deterministic reductions: per-block partials, then one fixed-order pass.
+// ---------------------------------------------------------------------------
+constexpr int kDotBlocks = 1024;
+
+template <int MAXK>
+__device__ __forceinline__ void block_store_partials(double (&acc)[MAXK], int kk, double *part) {
+  __shared__ double sh[kBlock / 64][MAXK];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < MAXK; k++) {
+    if (k < kk) {
+      double v = wave_sum(acc[k]);
+      if (lane == 0) sh[wv][k] = v;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < kk) {
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < kBlock / 64; w++) s += sh[w][threadIdx.x];
+    part[(size_t)blockIdx.x * MAXK + threadIdx.x] = s;
+  }
+}
+
+// partial[blk][k] = sum_i V[k][i] w[i], k <= j
+template <int MAXK>
+__global__ void __launch_bounds__(kBlock) k_mdot(const double *__restrict__ V, size_t N,
+                                                 const int *__restrict__ jdev,
+                                                 const double *__restrict__ w,
+                                                 double *__restrict__ part) {
+  const int kk = *jdev + 1;
+  double acc[MAXK];
+#pragma unroll
+  for (int k = 0; k < MAXK; k++) acc[k] = 0.0;
+  for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < N; i += (size_t)gridDim.x * kBlock) {
+    const double wi = w[i];
+#pragma unroll
+    for (int k = 0; k < MAXK; k++)
+      if (k < kk) acc[k] += V[(size_t)k * N + i] * wi;
+  }
+  block_store_partials<MAXK>(acc, kk, part);
+}
+
+// w -= V h; then partial[blk][k] = sum_i V[k][i] w[i] (second Gram-Schmidt pass)
+template <int MAXK>
+__global__ void __launch_bounds__(kBlock) k_cgs_update_mdot(const double *__restrict__ V, size_t N,
+                                                            const int *__restrict__ jdev,
+                                                            const double *__restrict__ h,
+                                                            double *__restrict__ w,
+                                                            double *__restrict__ part) {
+  const int kk = *jdev + 1;
+  double acc[MAXK], hk[MAXK];
+#pragma unroll
+  for (int k = 0; k < MAXK; k++) {
+    acc[k] = 0.0;
+    hk[k] = k < kk ? h[k] : 0.0;
+  }
+  for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < N; i += (size_t)gridDim.x * kBlock) {
+    double vk[MAXK];
+    double wi = w[i];
+#pragma unroll
+    for (int k = 0; k < MAXK; k++) {
+      vk[k] = k < kk ? V[(size_t)k * N + i] : 0.0;
+      wi -= vk[k] * hk[k];
+    }
+    w[i] = wi;
+#pragma unroll
+    for (int k = 0; k < MAXK; k++) acc[k] += vk[k] * wi;
+  }
+  block_store_partials<MAXK>(acc, kk, part);
+}
+
+// w -= V h; partial[blk][0] = sum_i w[i]^2
+template <int MAXK>
+__global__ void __launch_bounds__(kBlock) k_cgs_update_norm(const double *__restrict__ V, size_t N,
+                                                            const int *__restrict__ jdev,
+                                                            const double *__restrict__ h,
+                                                            double *__restrict__ w,
+                                                            double *__restrict__ part) {
+  const int kk = *jdev + 1;
+  double hk[MAXK];
+#pragma unroll
+  for (int k = 0; k < MAXK; k++) hk[k] = k < kk ? h[k] : 0.0;
+  double acc[1] = {0.0};
+  for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < N; i += (size_t)gridDim.x * kBlock) {
+    double wi = w[i];
+#pragma unroll
+    for (int k = 0; k < MAXK; k++)
+      if (k < kk) wi -= V[(size_t)k * N + i] * hk[k];
+    w[i] = wi;
+    acc[0] += wi * wi;
+  }
+  block_store_partials<1>(acc, 1, part);
+}
+
+// partial[blk][0] = sum_i x[i]^2
+__global__ void __launch_bounds__(kBlock) k_norm2_partial(const double *__restrict__ x, size_t N,
+                                                          double *__restrict__ part) {
+  double acc[1] = {0.0};
+  for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < N; i += (size_t)gridDim.x * kBlock)
+    acc[0] += x[i] * x[i];
+  block_store_partials<1>(acc, 1, part);
+}
+
+// out[k] = sum_blk partial[blk][k] for k < kk (kk = *jdev + 1, or kfix when jdev is null);
+// fixed order: thread t sums blocks t, t+256, ..., then a fixed tree.
+template <int STRIDE>
+__global__ void __launch_bounds__(kBlock) k_reduce(const double *__restrict__ part, int nblk,
+                                                   const int *__restrict__ jdev, int kfix,
+                                                   double *__restrict__ out, int sqrt_out) {
+  __shared__ double sh[kBlock];
+  const int kk = jdev ? *jdev + 1 : kfix;
+  for (int k = 0; k < kk; k++) {
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += kBlock) s += part[(size_t)b * STRIDE + k];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = kBlock / 2; o > 0; o >>= 1) {
+      if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) out[k] = sqrt_out ? sqrt(sh[0]) : sh[0];
+    __syncthreads();
+  }
+}
+
+// Krylov state kept on the device
+struct KState {
+  int j;          // current column
+  int m;          // restart length
+  double beta;
+  double hn;      // ||w|| of the last step
+  double absg;    // |g_{j+1}|
+};
+
+// v_{j+1} = w / hn  (hn == 0: zero vector)
+__global__ void __launch_bounds__(kBlock) k_scale_next(double *__restrict__ V, size_t N,
+                                                       const KState *__restrict__ st,
+                                                       const double *__restrict__ w) {
+  const double hn = st->hn;
+  const double inv = hn != 0.0 ? 1.0 / hn : 0.0;
+  double *vn = V + (size_t)(st->j + 1) * N;
+  for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < N; i += (size_t)gridDim.x * kBlock)
+    vn[i] = w[i] * inv;
+}
+
+// Hessenberg column j = h1 + h2 (0..j), hn (j+1); previous rotations, a new
+// rotation, g update; j advances.  R is stored (m+1) x m row-major.
+__global__ void k_givens(KState *st, const double *__restrict__ h1, const double *__restrict__ h2,
+                         double *__restrict__ R, double *__restrict__ cs, double *__restrict__ sn,
+                         double *__restrict__ g) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const int j = st->j, m = st->m;
+  for (int k = 0; k <= j; k++) R[(size_t)k * m + j] = h1[k] + h2[k];
+  R[(size_t)(j + 1) * m + j] = st->hn;
+  for (int k = 0; k < j; k++) {
+    const double a = R[(size_t)k * m + j], c = R[(size_t)(k + 1) * m + j];
+    R[(size_t)k * m + j] = cs[k] * a + sn[k] * c;
+    R[(size_t)(k + 1) * m + j] = -sn[k] * a + cs[k] * c;
+  }
+  const double a = R[(size_t)j * m + j], c = R[(size_t)(j + 1) * m + j];
+  const double den = hypot(a, c);
+  cs[j] = den == 0.0 ? 1.0 : a / den;
+  sn[j] = den == 0.0 ? 0.0 : c / den;
+  R[(size_t)j * m + j] = den;
+  R[(size_t)(j + 1) * m + j] = 0.0;
+  g[j + 1] = -sn[j] * g[j];
+  g[j] = cs[j] * g[j];
+  st->absg = fabs(g[j + 1]);
+  st->j = j + 1;
+}
+
+__global__ void k_cycle_init(KState *st, const double *__restrict__ beta, double *__restrict__ g,
+                             int m) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  st->j = 0;
+  st->m = m;
+  st->beta = *beta;
+  st->hn = 0.0;
+  st->absg = *beta;
+  g[0] = *beta;
+  for (int k = 1; k <= m; k++) g[k] = 0.0;
+}
+
+// v_0 = r / beta
+__global__ void __launch_bounds__(kBlock) k_first_vector(double *__restrict__ V, size_t N,
+                                                         const double *__restrict__ r,
+                                                         const double *__restrict__ beta) {
+  const double inv = 1.0 / *beta;
+  for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < N; i += (size_t)gridDim.x * kBlock)
+    V[i] = r[i] * inv;
+}
+
+// y = R^{-1} g over the first j columns (back substitution)
+__global__ void k_solve_y(const KState *st, const double *__restrict__ R,
+                          const double *__restrict__ g, double *__restrict__ y) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const int kk = st->j, m = st->m;
+  for (int i = kk - 1; i >= 0; i--) {
+    double s = g[i];
+    for (int q = i + 1; q < kk; q++) s -= R[(size_t)i * m + q] * y[q];
+    y[i] = s / R[(size_t)i * m + i];
+  }
+}
+
+// x += Z y over the first j columns
+template <typename ZT>
+__global__ void __launch_bounds__(kBlock) k_update_x(double *__restrict__ x, const ZT *__restrict__ Z,
+                                                     size_t N, const KState *__restrict__ st,
+                                                     const double *__restrict__ y) {
+  const int kk = st->j;
+  for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < N; i += (size_t)gridDim.x * kBlock) {
+    double s = x[i];
+    for (int k = 0; k < kk; k++) s += double(Z[(size_t)k * N + i]) * y[k];
+    x[i] = s;
+  }
+}
+
+// slots for Krylov column j: v = V_j, z = Z_j
+__global__ void k_set_slots_krylov(ApplySlots *slots, const double *V, void *Z, size_t N,
+                                   int zbytes, const KState *st) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  slots->v = V + (size_t)st->j * N;
+  slots->z = reinterpret_cast<char *>(Z) + (size_t)st->j * N * zbytes;
+}
+
+__global__ void k_set_slots(ApplySlots *slots, const double *v, void *z) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  slots->v = v;
+  slots->z = z;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_fill(T *__restrict__ x, size_t n, T val) {
+  for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock)
+    x[i] = val;
+}
+
+template <typename A, typename B>
+__global__ void __launch_bounds__(kBlock) k_convert(const A *__restrict__ a, B *__restrict__ b, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock)
+    b[i] = B(a[i]);
+}
+
+}  // namespace cptr

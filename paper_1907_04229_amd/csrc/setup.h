@@ -1,0 +1,72 @@
+// Host-side setup structures and algorithms of libcptr (no HIP dependency,
+// so that the setup can also be built and checked on a machine without a GPU).
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "../../include/cptr.h"
+
+namespace cptr {
+
+// ---------------------------------------------------------------- errors
+struct Error {
+  int code;
+  std::string msg;
+};
+
+
+// ---------------------------------------------------------------- host sparse
+struct HostCSR {
+  int nr = 0, nc = 0;
+  std::vector<int> rp, ci;
+  std::vector<double> v;
+  int nnz() const { return (int)ci.size(); }
+};
+
+// Smoothed-aggregation hierarchy built on the host in FP64.
+struct AmgParams {
+  double theta = 0.08;
+  int max_levels = 10;
+  int coarse_size = 512;
+  unsigned seed = 0;
+  int smooth_p = 1;
+};
+
+struct AmgLevelHost {
+  HostCSR A;            // level operator
+  HostCSR P;            // prolongation to this level from the next (n_l x n_{l+1})
+  HostCSR R;            // restriction = P^T
+  std::vector<int> agg; // aggregate of each row (empty on the coarsest level)
+  double omega = 0.0;
+};
+
+struct AmgHost {
+  std::vector<AmgLevelHost> lev;
+  std::vector<double> coarse_inv;  // explicit FP64 inverse of the coarsest operator, row-major
+};
+
+// Throws Error on failure.
+void amg_build(const HostCSR &fine, const AmgParams &prm, AmgHost &out);
+
+// Block ILU(0) in a given row order, FP64 on the host.
+struct IluHost {
+  int n = 0, nv = 0, ncolor = 0;
+  std::vector<int> order;        // factor position -> cell
+  std::vector<int> color;        // colour of every cell (0 for natural order)
+  std::vector<int> lev_lower;    // level of every cell in the forward sweep
+  std::vector<int> lev_upper;    // level of every cell in the backward sweep
+  // forward sweep, rows in level order
+  std::vector<int> f_rows, f_lev_ptr, f_ptr, f_col;
+  std::vector<double> f_val;     // nv*nv per block, L (unit diagonal implied)
+  // backward sweep, rows in level order
+  std::vector<int> b_rows, b_lev_ptr, b_ptr, b_col;
+  std::vector<double> b_val;     // nv*nv per block, strictly upper U
+  std::vector<double> dinv;      // nv*nv per cell (natural cell index), inverse of U_ii
+};
+
+// Throws Error (CPTR_ERR_SINGULAR_BLOCK on a zero pivot).
+void ilu_build(int n, int nv, const int *rp, const int *ci, const double *vals,
+               bool multicolor, IluHost &out);
+
+}  // namespace cptr

@@ -1,0 +1,104 @@
+// Host-only C entry points of the setup algorithms (libcptr_host.so), so that
+// the integer results of the setup (aggregates, ILU levels and colours) and
+// the FP64 coarse operators can be inspected on a machine without a GPU.
+// The GPU library runs exactly these functions inside cptr_setup.
+#include <cstring>
+
+#include "setup.h"
+
+using namespace cptr;
+
+namespace {
+struct AmgBox {
+  AmgHost h;
+  std::string err;
+};
+struct IluBox {
+  IluHost h;
+};
+thread_local std::string g_err;
+}  // namespace
+
+extern "C" {
+
+const char *cptrh_last_error(void) { return g_err.c_str(); }
+
+void *cptrh_amg_build(int n, const int *rp, const int *ci, const double *v, double theta,
+                      int max_levels, int coarse_size, unsigned seed, int smooth_p, int *status) {
+  auto *b = new AmgBox();
+  try {
+    HostCSR a;
+    a.nr = a.nc = n;
+    a.rp.assign(rp, rp + n + 1);
+    a.ci.assign(ci, ci + rp[n]);
+    a.v.assign(v, v + rp[n]);
+    AmgParams p;
+    p.theta = theta;
+    p.max_levels = max_levels;
+    p.coarse_size = coarse_size;
+    p.seed = seed;
+    p.smooth_p = smooth_p;
+    amg_build(a, p, b->h);
+    *status = 0;
+  } catch (const Error &e) {
+    g_err = e.msg;
+    *status = e.code;
+  }
+  return b;
+}
+
+int cptrh_amg_nlevels(void *h) { return (int)static_cast<AmgBox *>(h)->h.lev.size(); }
+
+int cptrh_amg_level_info(void *h, int l, int *n, int *nnz, int *pnnz) {
+  auto &L = static_cast<AmgBox *>(h)->h.lev.at(l);
+  *n = L.A.nr;
+  *nnz = L.A.nnz();
+  *pnnz = L.P.nnz();
+  return 0;
+}
+
+int cptrh_amg_get(void *h, int l, int *agg, int *arp, int *aci, double *av, int *prp, int *pci,
+                  double *pv, double *omega) {
+  auto &L = static_cast<AmgBox *>(h)->h.lev.at(l);
+  std::memcpy(arp, L.A.rp.data(), sizeof(int) * L.A.rp.size());
+  std::memcpy(aci, L.A.ci.data(), sizeof(int) * L.A.ci.size());
+  std::memcpy(av, L.A.v.data(), sizeof(double) * L.A.v.size());
+  if (!L.agg.empty()) {
+    std::memcpy(agg, L.agg.data(), sizeof(int) * L.agg.size());
+    std::memcpy(prp, L.P.rp.data(), sizeof(int) * L.P.rp.size());
+    std::memcpy(pci, L.P.ci.data(), sizeof(int) * L.P.ci.size());
+    std::memcpy(pv, L.P.v.data(), sizeof(double) * L.P.v.size());
+    *omega = L.omega;
+  }
+  return 0;
+}
+
+void cptrh_amg_free(void *h) { delete static_cast<AmgBox *>(h); }
+
+void *cptrh_ilu_build(int n, int nv, const int *rp, const int *ci, const double *v, int mc,
+                      int *status) {
+  auto *b = new IluBox();
+  try {
+    ilu_build(n, nv, rp, ci, v, mc != 0, b->h);
+    *status = 0;
+  } catch (const Error &e) {
+    g_err = e.msg;
+    *status = e.code;
+  }
+  return b;
+}
+
+int cptrh_ilu_get(void *h, int *order, int *lev_lower, int *lev_upper, int *color, double *dinv) {
+  auto &I = static_cast<IluBox *>(h)->h;
+  size_t n = I.order.size();
+  if (order) std::memcpy(order, I.order.data(), sizeof(int) * n);
+  if (lev_lower) std::memcpy(lev_lower, I.lev_lower.data(), sizeof(int) * n);
+  if (lev_upper) std::memcpy(lev_upper, I.lev_upper.data(), sizeof(int) * n);
+  if (color) std::memcpy(color, I.color.data(), sizeof(int) * n);
+  if (dinv) std::memcpy(dinv, I.dinv.data(), sizeof(double) * I.dinv.size());
+  return I.ncolor;
+}
+
+void cptrh_ilu_free(void *h) { delete static_cast<IluBox *>(h); }
+
+}  // extern "C"

@@ -1,0 +1,187 @@
+// Block ILU(0) factorisation (host, FP64) and the level schedule of its
+// triangular solves.  ILU(0) is the second stage of CPR and CPTR (Section 3;
+// the implementation notes of Section 4 use ILU(0) by default).
+//
+// Factor order: natural cell order, or a greedy multicolour order (colour of
+// a cell = smallest colour not used by its lower-numbered neighbours; cells
+// renumbered colour by colour, ascending inside a colour).  The factor is the
+// IKJ form of ILU(0) on nv x nv blocks: for each row i and each lower block
+// k < i in order, L_ik = A_ik U_kk^{-1}, then A_ij -= L_ik U_kj for every j > k
+// present in both rows.  Diagonal blocks are inverted by Gauss-Jordan
+// elimination with partial pivoting.
+#include <algorithm>
+#include <cmath>
+
+#include "setup.h"
+
+namespace cptr {
+namespace {
+
+void blk_mul(int nv, const double *a, const double *b, double *c) {
+  for (int r = 0; r < nv; r++)
+    for (int q = 0; q < nv; q++) {
+      double s = 0.0;
+      for (int k = 0; k < nv; k++) s += a[r * nv + k] * b[k * nv + q];
+      c[r * nv + q] = s;
+    }
+}
+
+bool blk_inv(int nv, const double *a, double *inv) {
+  double m[4][8];
+  for (int r = 0; r < nv; r++)
+    for (int q = 0; q < 2 * nv; q++) m[r][q] = q < nv ? a[r * nv + q] : (q - nv == r ? 1.0 : 0.0);
+  for (int k = 0; k < nv; k++) {
+    int p = k;
+    for (int r = k + 1; r < nv; r++)
+      if (std::fabs(m[r][k]) > std::fabs(m[p][k])) p = r;
+    if (m[p][k] == 0.0 || !std::isfinite(m[p][k])) return false;
+    if (p != k)
+      for (int q = 0; q < 2 * nv; q++) std::swap(m[k][q], m[p][q]);
+    double d = m[k][k];
+    for (int q = 0; q < 2 * nv; q++) m[k][q] /= d;
+    for (int r = 0; r < nv; r++) {
+      if (r == k) continue;
+      double f = m[r][k];
+      for (int q = 0; q < 2 * nv; q++) m[r][q] -= f * m[k][q];
+    }
+  }
+  for (int r = 0; r < nv; r++)
+    for (int q = 0; q < nv; q++) inv[r * nv + q] = m[r][nv + q];
+  return true;
+}
+
+}  // namespace
+
+void ilu_build(int n, int nv, const int *rp, const int *ci, const double *vals,
+               bool multicolor, IluHost &out) {
+  const int b2 = nv * nv;
+  out.n = n;
+  out.nv = nv;
+  out.color.assign(n, 0);
+  out.order.resize(n);
+  std::vector<int> pos(n);
+  if (multicolor) {
+    int ncol = 0;
+    std::vector<int> mark;
+    for (int i = 0; i < n; i++) {
+      mark.assign(ncol + 2, 0);
+      for (int k = rp[i]; k < rp[i + 1]; k++)
+        if (ci[k] < i) mark[out.color[ci[k]]] = 1;
+      int c = 0;
+      while (mark[c]) c++;
+      out.color[i] = c;
+      ncol = std::max(ncol, c + 1);
+    }
+    out.ncolor = ncol;
+    int p = 0;
+    for (int c = 0; c < ncol; c++)
+      for (int i = 0; i < n; i++)
+        if (out.color[i] == c) out.order[p++] = i;
+  } else {
+    out.ncolor = 0;
+    for (int i = 0; i < n; i++) out.order[i] = i;
+  }
+  for (int p = 0; p < n; p++) pos[out.order[p]] = p;
+
+  // renumbered pattern: row p holds the blocks of cell order[p], columns as
+  // factor positions, ascending
+  std::vector<int> frp(n + 1, 0), fci(rp[n]), src(rp[n]);
+  for (int p = 0; p < n; p++) {
+    int i = out.order[p];
+    int len = rp[i + 1] - rp[i];
+    frp[p + 1] = frp[p] + len;
+    std::vector<std::pair<int, int>> row;
+    for (int k = rp[i]; k < rp[i + 1]; k++) row.push_back({pos[ci[k]], k});
+    std::sort(row.begin(), row.end());
+    for (int t = 0; t < len; t++) {
+      fci[frp[p] + t] = row[t].first;
+      src[frp[p] + t] = row[t].second;
+    }
+  }
+  std::vector<double> lu((size_t)rp[n] * b2);
+  for (int k = 0; k < rp[n]; k++)
+    std::copy(vals + (size_t)src[k] * b2, vals + (size_t)src[k] * b2 + b2, lu.begin() + (size_t)k * b2);
+  std::vector<int> dpos(n, -1);
+  for (int p = 0; p < n; p++)
+    for (int k = frp[p]; k < frp[p + 1]; k++)
+      if (fci[k] == p) dpos[p] = k;
+  std::vector<double> dinv_pos((size_t)n * b2);
+
+  // IKJ factorisation with a column-position map of the current row
+  std::vector<int> where(n, -1);
+  double tmp[16], prod[16];
+  for (int p = 0; p < n; p++) {
+    for (int k = frp[p]; k < frp[p + 1]; k++) where[fci[k]] = k;
+    for (int k = frp[p]; k < dpos[p]; k++) {
+      int q = fci[k];
+      blk_mul(nv, &lu[(size_t)k * b2], &dinv_pos[(size_t)q * b2], tmp);
+      std::copy(tmp, tmp + b2, &lu[(size_t)k * b2]);
+      for (int t = dpos[q] + 1; t < frp[q + 1]; t++) {
+        int s = where[fci[t]];
+        if (s < 0) continue;
+        blk_mul(nv, &lu[(size_t)k * b2], &lu[(size_t)t * b2], prod);
+        for (int e = 0; e < b2; e++) lu[(size_t)s * b2 + e] -= prod[e];
+      }
+    }
+    if (!blk_inv(nv, &lu[(size_t)dpos[p] * b2], &dinv_pos[(size_t)p * b2]))
+      throw Error{CPTR_ERR_SINGULAR_BLOCK,
+                  "zero pivot in the ILU(0) diagonal block of cell " + std::to_string(out.order[p])};
+    for (int k = frp[p]; k < frp[p + 1]; k++) where[fci[k]] = -1;
+  }
+
+  // level sets in factor order
+  std::vector<int> ll(n, 0), lu_(n, 0);
+  int nll = 0, nlu = 0;
+  for (int p = 0; p < n; p++) {
+    int lv = 0;
+    for (int k = frp[p]; k < dpos[p]; k++) lv = std::max(lv, ll[fci[k]] + 1);
+    ll[p] = lv;
+    nll = std::max(nll, lv + 1);
+  }
+  for (int p = n - 1; p >= 0; p--) {
+    int lv = 0;
+    for (int k = dpos[p] + 1; k < frp[p + 1]; k++) lv = std::max(lv, lu_[fci[k]] + 1);
+    lu_[p] = lv;
+    nlu = std::max(nlu, lv + 1);
+  }
+  out.lev_lower.assign(n, 0);
+  out.lev_upper.assign(n, 0);
+  for (int p = 0; p < n; p++) {
+    out.lev_lower[out.order[p]] = ll[p];
+    out.lev_upper[out.order[p]] = lu_[p];
+  }
+  out.dinv.assign((size_t)n * b2, 0.0);
+  for (int p = 0; p < n; p++)
+    std::copy(&dinv_pos[(size_t)p * b2], &dinv_pos[(size_t)p * b2] + b2,
+              &out.dinv[(size_t)out.order[p] * b2]);
+
+  // sweep schedules: positions sorted by (level, position)
+  auto schedule = [&](const std::vector<int> &lev, int nlev, bool lower, std::vector<int> &rows,
+                      std::vector<int> &lev_ptr, std::vector<int> &ptr, std::vector<int> &col,
+                      std::vector<double> &val) {
+    lev_ptr.assign(nlev + 1, 0);
+    for (int p = 0; p < n; p++) lev_ptr[lev[p] + 1]++;
+    for (int l = 0; l < nlev; l++) lev_ptr[l + 1] += lev_ptr[l];
+    std::vector<int> fill(lev_ptr.begin(), lev_ptr.end() - 1), byp(n);
+    for (int p = 0; p < n; p++) byp[fill[lev[p]]++] = p;
+    rows.resize(n);
+    ptr.assign(n + 1, 0);
+    col.clear();
+    val.clear();
+    for (int t = 0; t < n; t++) {
+      int p = byp[t];
+      rows[t] = out.order[p];
+      int b = lower ? frp[p] : dpos[p] + 1;
+      int e = lower ? dpos[p] : frp[p + 1];
+      for (int k = b; k < e; k++) {
+        col.push_back(out.order[fci[k]]);
+        val.insert(val.end(), &lu[(size_t)k * b2], &lu[(size_t)k * b2] + b2);
+      }
+      ptr[t + 1] = int(col.size());
+    }
+  };
+  schedule(ll, nll, true, out.f_rows, out.f_lev_ptr, out.f_ptr, out.f_col, out.f_val);
+  schedule(lu_, nlu, false, out.b_rows, out.b_lev_ptr, out.b_ptr, out.b_col, out.b_val);
+}
+
+}  // namespace cptr

@@ -1,0 +1,74 @@
+"""The library's setup (built for the host) against the oracle, on the CPU.
+
+Aggregation, numbering, the Galerkin coarse operators and the ILU(0) level /
+colour schedules must be bit-identical: both sides take every floating-point
+decision in FP64 in the same stated order, without contraction."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1907_04229_amd import setup_host as H
+from paper_1907_04229_amd.synth import make_problem
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _built():
+    try:
+        H.load()
+    except ImportError:
+        from paper_1907_04229_amd import build
+        build.build_host()
+
+
+CASES = [
+    dict(shape=(8, 7, 5), kind="gaussian", sigma=1.5, corr_len=3.0, seed=12),
+    dict(shape=(16, 12, 6), kind="iid", sigma=1.0, seed=3, heater=True),
+    dict(shape=(12, 10, 8), kind="gaussian", sigma=2.5, corr_len=4.0, seed=4, three_phase=True),
+]
+
+
+@pytest.mark.parametrize("case", range(len(CASES)))
+@pytest.mark.parametrize("which", [0, 1])
+def test_amg_hierarchy_bit_exact(case, which, oracle_lib):
+    pr = make_problem(**CASES[case])
+    nv = pr.nv
+    if which == 0:
+        v = np.ascontiguousarray(pr.vals.reshape(-1, nv, nv)[:, 0, 0])
+        rp, ci = pr.row_ptr, pr.col_idx
+    else:
+        rp, ci, v = pr.st_row_ptr, pr.st_col_idx, pr.st_vals
+    for seed, smooth in ((0, True), (5, True), (0, False)):
+        o = O.Oracle.from_problem(pr, first="cptr", second="none", coarse_size=16, seed=seed,
+                                  smooth_p=smooth)
+        ref = o.amg_levels(which)
+        got = H.amg_levels(rp, ci, v, coarse_size=16, seed=seed, smooth_p=smooth)
+        assert len(got) == len(ref) >= 2
+        for a, b in zip(got, ref):
+            assert a["n"] == b["n"]
+            for x, y in zip(a["A"], b["A"]):
+                assert np.array_equal(x, y)            # bit-identical coarse operators
+            if "agg" in b:
+                assert np.array_equal(a["agg"], b["agg"])
+                assert a["omega"] == b["omega"]
+                for x, y in zip(a["P"], b["P"]):
+                    assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("mc", [False, True])
+def test_ilu_schedule_matches_oracle(mc, oracle_lib):
+    pr = make_problem(shape=(7, 6, 5), kind="iid", seed=9, three_phase=True)
+    o = O.Oracle.from_problem(pr, first="none", second="bilu0_mc" if mc else "bilu0")
+    ref = o.ilu()
+    got = H.ilu_schedule(pr.row_ptr, pr.col_idx, pr.vals, pr.nv, mc)
+    assert np.array_equal(got["order"], ref["perm"])
+    cells = ref["perm"]
+    assert np.array_equal(got["lev_lower"][cells], ref["lev_lower"])
+    assert np.array_equal(got["lev_upper"][cells], ref["lev_upper"])
+    if mc:
+        assert got["ncolor"] == ref["ncolor"]
+        assert np.array_equal(got["color"], ref["color"])
+    # the FP64 factors agree to rounding (same algorithm, same order)
+    nv = pr.nv
+    d_ref = ref["dinv"].reshape(-1, nv, nv)
+    d_got = got["dinv"].reshape(-1, nv, nv)[cells]
+    assert np.abs(d_ref - d_got).max() <= 1e-12 * np.abs(d_ref).max()
