@@ -96,7 +96,7 @@ typedef struct {
   int amg_max_levels;    /* <= 16 (10) */
   int amg_coarse_size;   /* coarsest level solved directly once n <= this (512) */
   unsigned amg_seed;     /* aggregation priority seed (0) */
-  int amg_sweeps;        /* l1-Jacobi sweeps before and after the coarse correction (1) */
+  int amg_sweeps;        /* l1-Jacobi sweeps before and after the coarse correction (2) */
   int amg_smooth_p;      /* 1 smoothed aggregation, 0 plain aggregation (1) */
   int use_graph;         /* 1: replay the preconditioner and the Arnoldi step as HIP graphs (1) */
 } cptr_options;

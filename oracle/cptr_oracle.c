@@ -230,6 +230,9 @@ typedef struct {
   double *dl1[MAXLEV];/* l1 row sums */
   double omega[MAXLEV];
   int sweeps;
+  int smoother;       /* 0: l1-Jacobi, 1: multicolour Gauss-Seidel */
+  int *color[MAXLEV]; /* greedy colouring of each level (Gauss-Seidel) */
+  int ncolor[MAXLEV];
   double *lu;         /* coarsest dense LU */
   int *piv;
 } amg;
@@ -239,19 +242,19 @@ typedef struct {
  *  4. aggregate = root + its strong neighbours;
  *  5. each remaining node joins the step-4 aggregate of a strong neighbour
  *     whose root has the largest priority;
- *  6. strength-isolated nodes are roots of singleton aggregates;
+ *  6. strength-isolated nodes belong to no aggregate (zero tentative row);
  *  7. aggregates numbered by ascending root index. */
-static int aggregate(const csr *a, double theta, unsigned seed, int *agg, int *nagg) {
-  int n = a->nr;
-  int *srp = (int *)malloc(sizeof(int) * ((size_t)n + 1));
-  int ns = orc_strength(n, a->rp, a->ci, a->v, theta, srp, NULL);
-  int *sci = (int *)malloc(sizeof(int) * (size_t)(ns > 0 ? ns : 1));
-  orc_strength(n, a->rp, a->ci, a->v, theta, srp, sci);
+static int aggregate(int n, const int *srp, const int *sci, unsigned seed, int *agg,
+                     int *nagg) {
   int *root = (int *)malloc(sizeof(int) * (size_t)(n > 0 ? n : 1));
   orc_mis2_greedy(n, srp, sci, seed, root);
   int *id = (int *)malloc(sizeof(int) * (size_t)(n > 0 ? n : 1));
   int *rootof = (int *)malloc(sizeof(int) * (size_t)(n > 0 ? n : 1));
   int na = 0;
+  /* step 6: a node without strong neighbours (always a root of the MIS-2)
+   * belongs to no aggregate: its row of the tentative prolongator is zero */
+  for (int i = 0; i < n; i++)
+    if (srp[i + 1] == srp[i]) root[i] = 0;
   for (int i = 0; i < n; i++) id[i] = root[i] ? na++ : -1;
   for (int i = 0; i < n; i++) { agg[i] = -1; rootof[i] = -1; }
   for (int r = 0; r < n; r++) {
@@ -269,7 +272,7 @@ static int aggregate(const csr *a, double theta, unsigned seed, int *agg, int *n
   memcpy(root4, rootof, sizeof(int) * (size_t)n);
   int bad = 0;
   for (int i = 0; i < n; i++) {
-    if (agg4[i] >= 0) continue;
+    if (agg4[i] >= 0 || srp[i + 1] == srp[i]) continue;
     int best = -1;
     for (int k = srp[i]; k < srp[i + 1]; k++) {
       int j = sci[k];
@@ -279,12 +282,13 @@ static int aggregate(const csr *a, double theta, unsigned seed, int *agg, int *n
     if (best < 0) { bad = 1; continue; }   /* cannot happen: see step 6 */
     agg[i] = id[best];
   }
-  free(agg4); free(root4); free(rootof); free(id); free(root); free(sci); free(srp);
+  free(agg4); free(root4); free(rootof); free(id); free(root);
   *nagg = na;
   return bad ? -1 : 0;
 }
 
-/* P = (I - omega D^{-1} A) P_tent, omega = 4 / (3 rho), rho = max_i sum_j |a_ij| / |a_ii|.
+/* P = (I - omega D^{-1} A) P_tent, omega = 4 / (3 rho),
+ * rho = max_i sum_j |a_ij| / |a_ii|.
  * Entry (i, J) = [agg(i) = J] - (omega / a_ii) * (sum over j in row i with agg(j) = J
  * of a_ij, summed in ascending j).  Columns of each row ascending. */
 static csr smooth_prolongator(const csr *a, const int *agg, int nagg, double *omega_out,
@@ -307,9 +311,9 @@ static csr smooth_prolongator(const csr *a, const int *agg, int nagg, double *om
   for (int i = 0; i < n; i++) {
     for (int k = a->rp[i]; k < a->rp[i + 1]; k++) {
       int J = agg[a->ci[k]];
-      if (mark[J] != i) { mark[J] = i; nnz++; }
+      if (J >= 0 && mark[J] != i) { mark[J] = i; nnz++; }
     }
-    if (mark[agg[i]] != i) { mark[agg[i]] = i; nnz++; }
+    if (agg[i] >= 0 && mark[agg[i]] != i) { mark[agg[i]] = i; nnz++; }
   }
   csr p;
   csr_alloc(&p, n, nagg, nnz);
@@ -321,6 +325,7 @@ static csr smooth_prolongator(const csr *a, const int *agg, int nagg, double *om
     int nc = 0;
     for (int k = a->rp[i]; k < a->rp[i + 1]; k++) {
       int J = agg[a->ci[k]];
+      if (J < 0) continue;
       if (mark[J] != i) {
         mark[J] = i;
         acc[J] = 0.0;
@@ -329,7 +334,7 @@ static csr smooth_prolongator(const csr *a, const int *agg, int nagg, double *om
       }
       acc[J] += a->v[k];
     }
-    if (mark[agg[i]] != i) {
+    if (agg[i] >= 0 && mark[agg[i]] != i) {
       mark[agg[i]] = i;
       acc[agg[i]] = 0.0;
       if (nc == cap) { cap *= 2; cols = (int *)realloc(cols, sizeof(int) * (size_t)cap); }
@@ -407,7 +412,7 @@ static void amg_free(amg *m) {
   for (int l = 0; l < m->nlev; l++) {
     csr_free(&m->A[l]);
     if (l + 1 < m->nlev) { csr_free(&m->P[l]); csr_free(&m->R[l]); }
-    free(m->agg[l]); free(m->dl1[l]);
+    free(m->agg[l]); free(m->dl1[l]); free(m->color[l]);
   }
   free(m->lu); free(m->piv);
   memset(m, 0, sizeof(*m));
@@ -418,14 +423,20 @@ static void amg_free(amg *m) {
 static csr tentative(int n, const int *agg, int nagg) {
   csr p;
   csr_alloc(&p, n, nagg, n);
-  for (int i = 0; i < n; i++) { p.ci[i] = agg[i]; p.v[i] = 1.0; p.rp[i + 1] = i + 1; }
+  int pos = 0;
+  for (int i = 0; i < n; i++) {
+    if (agg[i] >= 0) { p.ci[pos] = agg[i]; p.v[pos] = 1.0; pos++; }
+    p.rp[i + 1] = pos;
+  }
+  p.nnz = pos;
   return p;
 }
 
 static int amg_setup(amg *m, csr fine, double theta, int max_levels, int coarse_size,
-                     unsigned seed, int sweeps, int smooth_p) {
+                     unsigned seed, int sweeps, int smooth_p, int smoother) {
   memset(m, 0, sizeof(*m));
   m->sweeps = sweeps;
+  m->smoother = smoother;
   if (max_levels > MAXLEV) max_levels = MAXLEV;
   m->A[0] = fine;
   int l = 0;
@@ -433,13 +444,22 @@ static int amg_setup(amg *m, csr fine, double theta, int max_levels, int coarse_
   while (m->A[l].nr > coarse_size && l + 1 < max_levels) {
     int n = m->A[l].nr, nagg = 0;
     int *agg = (int *)malloc(sizeof(int) * (size_t)(n > 0 ? n : 1));
-    if (aggregate(&m->A[l], th, seed, agg, &nagg) != 0) { free(agg); return -2; }
-    if (nagg >= n) { free(agg); break; }  /* no coarsening possible */
+    int *srp = (int *)malloc(sizeof(int) * ((size_t)n + 1));
+    int ns = orc_strength(n, m->A[l].rp, m->A[l].ci, m->A[l].v, th, srp, NULL);
+    int *sci = (int *)malloc(sizeof(int) * (size_t)(ns > 0 ? ns : 1));
+    orc_strength(n, m->A[l].rp, m->A[l].ci, m->A[l].v, th, srp, sci);
+    if (aggregate(n, srp, sci, seed, agg, &nagg) != 0) {
+      free(agg); free(srp); free(sci);
+      return -2;
+    }
+    if (nagg >= n) { free(agg); free(srp); free(sci); break; }  /* no coarsening possible */
     m->agg[l] = agg;
     if (smooth_p)
       m->P[l] = smooth_prolongator(&m->A[l], agg, nagg, &m->omega[l], 1);
     else
       m->P[l] = tentative(n, agg, nagg);
+    free(srp);
+    free(sci);
     m->R[l] = csr_transpose(&m->P[l]);
     csr t = spgemm(&m->A[l], &m->P[l]);
     m->A[l + 1] = spgemm(&m->R[l], &t);
@@ -456,6 +476,21 @@ static int amg_setup(amg *m, csr fine, double theta, int max_levels, int coarse_
       for (int q = m->A[k].rp[i]; q < m->A[k].rp[i + 1]; q++) s += fabs(m->A[k].v[q]);
       m->dl1[k][i] = s;
     }
+    /* greedy colouring in natural order: smallest colour unused by lower neighbours */
+    m->color[k] = (int *)malloc(sizeof(int) * (size_t)(n > 0 ? n : 1));
+    m->ncolor[k] = 0;
+    for (int i = 0; i < n; i++) {
+      int c = 0;
+      for (;;) {
+        int used = 0;
+        for (int q = m->A[k].rp[i]; q < m->A[k].rp[i + 1]; q++)
+          if (m->A[k].ci[q] < i && m->color[k][m->A[k].ci[q]] == c) { used = 1; break; }
+        if (!used) break;
+        c++;
+      }
+      m->color[k][i] = c;
+      if (c + 1 > m->ncolor[k]) m->ncolor[k] = c + 1;
+    }
   }
   int nc = m->A[m->nlev - 1].nr;
   if (nc > 4096) return -3;   /* coarsening stalled: refuse a huge dense LU */
@@ -471,6 +506,25 @@ static int amg_setup(amg *m, csr fine, double theta, int max_levels, int coarse_
 /* One V-cycle from a zero initial guess: l1-Jacobi pre-smoothing (one sweep),
  * residual, restriction, recursion, prolongation, l1-Jacobi post-smoothing;
  * the coarsest level is solved exactly. */
+/* one multicolour Gauss-Seidel sweep: colours in ascending (or descending)
+ * order; rows of one colour are not coupled, so each colour is one Jacobi
+ * update with the latest values of the other colours */
+static void gs_sweep(const amg *m, int l, const double *b, double *x, int reverse) {
+  const csr *a = &m->A[l];
+  for (int cc = 0; cc < m->ncolor[l]; cc++) {
+    int c = reverse ? m->ncolor[l] - 1 - cc : cc;
+    for (int i = 0; i < a->nr; i++) {
+      if (m->color[l][i] != c) continue;
+      double s = b[i], d = 0.0;
+      for (int k = a->rp[i]; k < a->rp[i + 1]; k++) {
+        if (a->ci[k] == i) d = a->v[k];
+        else s -= a->v[k] * x[a->ci[k]];
+      }
+      x[i] = s / d;
+    }
+  }
+}
+
 static void vcycle(const amg *m, int l, const double *b, double *x) {
   const csr *a = &m->A[l];
   int n = a->nr;
@@ -484,10 +538,15 @@ static void vcycle(const amg *m, int l, const double *b, double *x) {
   double *r = (double *)malloc(sizeof(double) * (size_t)n);
   double *bc = (double *)malloc(sizeof(double) * (size_t)nc);
   double *xc = (double *)malloc(sizeof(double) * (size_t)nc);
-  for (int i = 0; i < n; i++) x[i] = b[i] / m->dl1[l][i];       /* x = 0 + D^{-1}(b - A 0) */
-  for (int s = 1; s < m->sweeps; s++) {
-    csr_mv(a, x, t);
-    for (int i = 0; i < n; i++) x[i] += (b[i] - t[i]) / m->dl1[l][i];
+  if (m->smoother == 1) {
+    for (int i = 0; i < n; i++) x[i] = 0.0;
+    for (int s = 0; s < m->sweeps; s++) gs_sweep(m, l, b, x, 0);
+  } else {
+    for (int i = 0; i < n; i++) x[i] = b[i] / m->dl1[l][i];     /* x = 0 + D^{-1}(b - A 0) */
+    for (int s = 1; s < m->sweeps; s++) {
+      csr_mv(a, x, t);
+      for (int i = 0; i < n; i++) x[i] += (b[i] - t[i]) / m->dl1[l][i];
+    }
   }
   csr_mv(a, x, t);
   for (int i = 0; i < n; i++) r[i] = b[i] - t[i];
@@ -496,6 +555,10 @@ static void vcycle(const amg *m, int l, const double *b, double *x) {
   csr_mv(&m->P[l], xc, t);
   for (int i = 0; i < n; i++) x[i] += t[i];
   for (int s = 0; s < m->sweeps; s++) {
+    if (m->smoother == 1) {
+      gs_sweep(m, l, b, x, 1);
+      continue;
+    }
     csr_mv(a, x, t);
     for (int i = 0; i < n; i++) x[i] += (b[i] - t[i]) / m->dl1[l][i];
   }
@@ -626,7 +689,7 @@ static void bilu_free(bilu *f) {
  * renumbered colour by colour (ascending index inside a colour), then ILU(0)
  * of the renumbered matrix. */
 static int bilu_setup(bilu *f, int n, int nv, const int *rp, const int *ci,
-                      const double *v, int multicolor) {
+                      const double *v, int multicolor, const int *order, const int *part) {
   memset(f, 0, sizeof(*f));
   int b2 = nv * nv, nnzb = rp[n];
   f->n = n;
@@ -660,11 +723,19 @@ static int bilu_setup(bilu *f, int n, int nv, const int *rp, const int *ci,
     for (int c = 0; c < ncol; c++)
       for (int i = 0; i < n; i++)
         if (f->color[i] == c) { f->perm[pos] = i; newof[i] = pos; pos++; }
+  } else if (order) {
+    /* caller-given factor order: row r of the factor is cell order[r] */
+    for (int i = 0; i < n; i++) f->color[i] = 0;
+    f->ncolor = 1;
+    f->perm = (int *)malloc(sizeof(int) * (size_t)(n > 0 ? n : 1));
+    newof = (int *)malloc(sizeof(int) * (size_t)(n > 0 ? n : 1));
+    for (int r = 0; r < n; r++) { f->perm[r] = order[r]; newof[order[r]] = r; }
   } else {
     for (int i = 0; i < n; i++) f->color[i] = 0;
     f->ncolor = 1;
   }
-  /* renumbered pattern with ascending columns */
+  /* renumbered pattern with ascending columns; with a partition, couplings
+   * between different parts are dropped (block Jacobi) */
   int pos = 0;
   f->rp[0] = 0;
   for (int r = 0; r < n; r++) {
@@ -672,6 +743,7 @@ static int bilu_setup(bilu *f, int n, int nv, const int *rp, const int *ci,
     int len = rp[i + 1] - rp[i];
     int base = pos;
     for (int k = rp[i]; k < rp[i + 1]; k++) {
+      if (part && part[ci[k]] != part[i]) continue;
       int c = newof ? newof[ci[k]] : ci[k];
       /* insertion into ascending position */
       int y = pos - 1;
@@ -779,18 +851,19 @@ void *orc_create(int n, int nv, const int *rp, const int *ci, const double *vals
     h->ATp = extract(h, o->iT, o->ip);
     csr fine = extract(h, o->ip, o->ip);
     st = amg_setup(&h->amg_p, fine, o->theta, o->max_levels, o->coarse_size, o->seed,
-                   o->sweeps, o->smooth_p);
+                   o->sweeps, o->smooth_p, o->smoother);
     h->have_p = 1;
     if (st == 0 && (o->first_stage == ORC_FIRST_CPTR_BLOCK ||
                     o->first_stage == ORC_FIRST_CPTR_LOWER)) {
       csr s = csr_copy(n, srp, sci, svals);
       st = amg_setup(&h->amg_s, s, o->theta, o->max_levels, o->coarse_size, o->seed,
-                     o->sweeps, o->smooth_p);
+                     o->sweeps, o->smooth_p, o->smoother);
       h->have_s = 1;
     }
   }
   if (st == 0 && (o->second_stage == ORC_SECOND_BILU0 || o->second_stage == ORC_SECOND_BILU0_MC)) {
-    st = bilu_setup(&h->ilu, n, nv, rp, ci, vals, o->second_stage == ORC_SECOND_BILU0_MC);
+    st = bilu_setup(&h->ilu, n, nv, rp, ci, vals, o->second_stage == ORC_SECOND_BILU0_MC,
+                    o->ilu_order, o->ilu_part);
     if (st != 0) st = -10;
     h->have_ilu = 1;
   }

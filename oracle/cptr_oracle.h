@@ -37,6 +37,9 @@ typedef struct {
   unsigned seed;       /* priority hash seed of the aggregation */
   int sweeps;          /* l1-Jacobi sweeps before and after the coarse correction */
   int smooth_p;        /* 1: smoothed aggregation, 0: tentative (plain) aggregation */
+  int smoother;        /* 0: l1-Jacobi, 1: multicolour Gauss-Seidel (symmetric) */
+  const int *ilu_order;/* BILU0 factor order (position -> cell) or NULL */
+  const int *ilu_part; /* BILU0 partition (cell -> part, couplings across parts dropped) or NULL */
 } orc_opts;
 
 typedef struct {

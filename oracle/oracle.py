@@ -31,7 +31,8 @@ class _Opts(C.Structure):
     _fields_ = [("first_stage", C.c_int), ("second_stage", C.c_int), ("ip", C.c_int),
                 ("iT", C.c_int), ("theta", C.c_double), ("max_levels", C.c_int),
                 ("coarse_size", C.c_int), ("seed", C.c_uint), ("sweeps", C.c_int),
-                ("smooth_p", C.c_int)]
+                ("smooth_p", C.c_int), ("smoother", C.c_int), ("ilu_order", C.c_void_p),
+                ("ilu_part", C.c_void_p)]
 
 
 class _Info(C.Structure):
@@ -122,10 +123,12 @@ def fmix32(h):
 class Oracle:
     """The FP64 two-stage CPR/CPTR preconditioner and FGMRES on one system."""
 
+    h = None
+
     def __init__(self, n, nv, row_ptr, col, vals, st_row_ptr=None, st_col=None,
                  st_vals=None, first="cptr", second="bilu0", ip=0, iT=None,
-                 theta=0.08, max_levels=10, coarse_size=512, seed=0, sweeps=1,
-                 smooth_p=True):
+                 theta=0.08, max_levels=10, coarse_size=512, seed=0, sweeps=2,
+                 smooth_p=True, smoother="jacobi", ilu_order=None, ilu_part=None):
         self.n, self.nv = n, nv
         self._keep = [_ci(row_ptr), _ci(col), _cd(vals)]
         if st_row_ptr is None:
@@ -133,10 +136,18 @@ class Oracle:
         else:
             st = [_ci(st_row_ptr), _ci(st_col), _cd(st_vals)]
         self._keep += st
+        extra = [None, None]
+        for q, arr in enumerate((ilu_order, ilu_part)):
+            if arr is not None:
+                a = _ci(arr)
+                assert a.size == n
+                self._keep.append(a)
+                extra[q] = a.ctypes.data
         o = _Opts(FIRST[first], SECOND[second], ip, nv - 1 if iT is None else iT,
-                  theta, max_levels, coarse_size, seed, sweeps, int(bool(smooth_p)))
+                  theta, max_levels, coarse_size, seed, sweeps, int(bool(smooth_p)),
+                  {"jacobi": 0, "gs": 1}[smoother], extra[0], extra[1])
         status = C.c_int(0)
-        rp, ci, v, srp, sci, sv = self._keep
+        rp, ci, v, srp, sci, sv = self._keep[:6]
         self.h = lib().orc_create(n, nv, _i(rp), _i(ci), _d(v), _i(srp), _i(sci), _d(sv),
                                   C.byref(o), C.byref(status))
         if status.value != 0:

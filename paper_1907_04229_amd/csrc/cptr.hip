@@ -71,15 +71,35 @@ static inline int sgrid(size_t n) { return std::max(1, std::min(kDotBlocks, nblk
 
 #define LAUNCH_CHECK() CPTR_HIP_TRY(hipGetLastError())
 
-// ---------------------------------------------------------------- SELL-64 on device
+// ---------------------------------------------------------------- scalar operators
+// A scalar sparse operator on the device, stored for the kernel that suits
+// its row lengths: SELL-64 with one thread per row when rows are short
+// (the 7-point fine-level operators), CSR with G lanes per row otherwise
+// (coarse AMG levels and the restriction, tens to hundreds of entries).
 template <typename T>
-struct SellDev {
-  DevMem sptr, col, val;
+struct SpOp {
+  DevMem sptr, col, val, rp;
   Sell<T> view;
-  size_t stored = 0;  // stored elements (padding included)
+  int nrows = 0, ncols = 0, lanes = 1;  // lanes == 1: SELL-64
   size_t nnz = 0;
 
   void build(const HostCSR &a) {
+    nrows = a.nr;
+    ncols = a.nc;
+    nnz = a.nnz();
+    const double avg = a.nr ? double(nnz) / a.nr : 0.0;
+    lanes = 1;
+    if (avg > 12.0) {
+      lanes = 2;
+      while (lanes < 64 && lanes * 4 < avg) lanes *= 2;
+    }
+    if (lanes > 1) {
+      upload(rp, a.rp);
+      upload(col, a.ci);
+      std::vector<T> v(a.v.begin(), a.v.end());
+      upload(val, v);
+      return;
+    }
     int ns = (a.nr + kSlice - 1) / kSlice;
     std::vector<int> sp(ns + 1, 0);
     for (int s = 0; s < ns; s++) {
@@ -108,18 +128,70 @@ struct SellDev {
     view.sptr = devp<int>(sptr);
     view.col = devp<int>(col);
     view.val = devp<T>(val);
-    stored = sp[ns];
-    nnz = a.nnz();
   }
-  // algorithmic bytes of one product: stored values + indices + slice offsets
-  double bytes() const { return double(nnz) * (sizeof(T) + 4) + 4.0 * (view.nslices + 1); }
+  // algorithmic bytes of one product: values + indices + row/slice offsets
+  double bytes() const {
+    return double(nnz) * (sizeof(T) + 4) + 4.0 * (lanes > 1 ? nrows + 1 : view.nslices + 1);
+  }
+
+#define CPTR_CSRV_SWITCH(CALL)                  \
+  switch (lanes) {                               \
+    case 2: CALL(2); break;                      \
+    case 4: CALL(4); break;                      \
+    case 8: CALL(8); break;                      \
+    case 16: CALL(16); break;                    \
+    case 32: CALL(32); break;                    \
+    default: CALL(64); break;                    \
+  }
+
+  // y = A x (mode 0), y += A x (mode 1), y = b - A x (mode 2)
+  template <int MODE>
+  void spmv(hipStream_t st, const T *x, const T *b, T *y) const {
+    if (lanes == 1) {
+      hipLaunchKernelGGL((k_sell_spmv<T, MODE>), dim3(nblk(nrows)), dim3(kBlock), 0, st, view, x, b, y);
+    } else {
+      const int *r = devp<int>(rp), *c = devp<int>(col);
+      const T *v = devp<T>(val);
+      const int g = nblk((size_t)nrows * lanes);
+#define CALL(G) hipLaunchKernelGGL((k_csrv_spmv<T, G, MODE>), dim3(g), dim3(kBlock), 0, st, nrows, r, c, v, x, b, y)
+      CPTR_CSRV_SWITCH(CALL)
+#undef CALL
+    }
+    LAUNCH_CHECK();
+  }
+  void jacobi(hipStream_t st, const T *dinv, const T *b, const T *xin, T *xout) const {
+    if (lanes == 1) {
+      hipLaunchKernelGGL((k_jacobi<T>), dim3(nblk(nrows)), dim3(kBlock), 0, st, view, dinv, b, xin, xout);
+    } else {
+      const int *r = devp<int>(rp), *c = devp<int>(col);
+      const T *v = devp<T>(val);
+      const int g = nblk((size_t)nrows * lanes);
+#define CALL(G) hipLaunchKernelGGL((k_csrv_jacobi<T, G>), dim3(g), dim3(kBlock), 0, st, nrows, r, c, v, dinv, b, xin, xout)
+      CPTR_CSRV_SWITCH(CALL)
+#undef CALL
+    }
+    LAUNCH_CHECK();
+  }
+  void smooth0_resid(hipStream_t st, const T *dinv, const T *b, T *x, T *res) const {
+    if (lanes == 1) {
+      hipLaunchKernelGGL((k_smooth0_resid<T>), dim3(nblk(nrows)), dim3(kBlock), 0, st, view, dinv, b, x, res);
+    } else {
+      const int *r = devp<int>(rp), *c = devp<int>(col);
+      const T *v = devp<T>(val);
+      const int g = nblk((size_t)nrows * lanes);
+#define CALL(G) hipLaunchKernelGGL((k_csrv_smooth0_resid<T, G>), dim3(g), dim3(kBlock), 0, st, nrows, r, c, v, dinv, b, x, res)
+      CPTR_CSRV_SWITCH(CALL)
+#undef CALL
+    }
+    LAUNCH_CHECK();
+  }
 };
 
 // ---------------------------------------------------------------- AMG on device
 template <typename T>
 struct AmgDev {
   struct Level {
-    SellDev<T> A, P, R;
+    SpOp<T> A, P, R;
     DevMem dinv, b, x, y, r;
     int n = 0;
   };
@@ -188,33 +260,26 @@ struct AmgDev {
     const Level &C = *lev[l + 1];
     // pre-smoothing from zero + residual
     if (sweeps == 1) {
-      hipLaunchKernelGGL((k_smooth0_resid<T>), dim3(nblk(n)), dim3(kBlock), 0, st, L.A.view, dinv, b, x, r);
-      LAUNCH_CHECK();
+      L.A.smooth0_resid(st, dinv, b, x, r);
     } else {
-      hipLaunchKernelGGL((k_smooth0_resid<T>), dim3(nblk(n)), dim3(kBlock), 0, st, L.A.view, dinv, b, x, r);
+      L.A.smooth0_resid(st, dinv, b, x, r);
       T *cur = x, *nxt = y;
       for (int s = 1; s < sweeps; s++) {
-        hipLaunchKernelGGL((k_jacobi<T>), dim3(nblk(n)), dim3(kBlock), 0, st, L.A.view, dinv, b, cur, nxt);
+        L.A.jacobi(st, dinv, b, cur, nxt);
         std::swap(cur, nxt);
       }
       if (cur != x) std::swap(x, y);  // keep the iterate in x
-      hipLaunchKernelGGL((k_sell_spmv<T, 2>), dim3(nblk(n)), dim3(kBlock), 0, st, L.A.view, x, b, r);
-      LAUNCH_CHECK();
+      L.A.template spmv<2>(st, x, b, r);
     }
     // restriction, coarse correction, prolongation
-    hipLaunchKernelGGL((k_sell_spmv<T, 0>), dim3(nblk(C.n)), dim3(kBlock), 0, st, L.R.view, r,
-                       (const T *)nullptr, devp<T>(C.b));
-    LAUNCH_CHECK();
+    L.R.template spmv<0>(st, r, nullptr, devp<T>(C.b));
     cycle_level(st, l + 1, devp<T>(C.b), devp<T>(C.r));  // coarse result in C.r
-    hipLaunchKernelGGL((k_sell_spmv<T, 1>), dim3(nblk(n)), dim3(kBlock), 0, st, L.P.view,
-                       devp<T>(C.r), (const T *)nullptr, x);
-    LAUNCH_CHECK();
+    L.P.template spmv<1>(st, devp<T>(C.r), nullptr, x);
     // post-smoothing; the last sweep writes to out
     T *cur = x;
     for (int s = 0; s < sweeps; s++) {
       T *dst = (s == sweeps - 1) ? out : (cur == x ? y : x);
-      hipLaunchKernelGGL((k_jacobi<T>), dim3(nblk(n)), dim3(kBlock), 0, st, L.A.view, dinv, b, cur, dst);
-      LAUNCH_CHECK();
+      L.A.jacobi(st, dinv, b, cur, dst);
       cur = dst;
     }
   }
@@ -279,7 +344,7 @@ struct Precond : PrecondBase {
   Options op;
   const int *rp = nullptr, *ci = nullptr;  // device pattern (caller's)
   DevMem acol;                             // p/T columns of A as nv x 2 blocks
-  SellDev<T> ApT, ATp;
+  SpOp<T> ApT, ATp;
   AmgDev<T> amg_p, amg_s;
   IluDev<T> ilu;
   DevMem bp, bt, xp, dT, dp, tmp, b1;
@@ -301,16 +366,14 @@ struct Precond : PrecondBase {
       return;
     }
     amg_p.cycle(st, bpp, xpp);
-    hipLaunchKernelGGL((k_sell_spmv<T, 2>), dim3(nblk(n)), dim3(kBlock), 0, st, ATp.view, xpp, btt, t);
-    LAUNCH_CHECK();
+    ATp.template spmv<2>(st, xpp, btt, t);
     amg_s.cycle(st, t, dTT);
     if (fs == CPTR_FIRST_BLOCK_LOWER) {
       hipLaunchKernelGGL((k_convert<T, T>), dim3(sgrid(n)), dim3(kBlock), 0, st, xpp, dpp, (size_t)n);
       LAUNCH_CHECK();
       return;
     }
-    hipLaunchKernelGGL((k_sell_spmv<T, 2>), dim3(nblk(n)), dim3(kBlock), 0, st, ApT.view, dTT, bpp, t);
-    LAUNCH_CHECK();
+    ApT.template spmv<2>(st, dTT, bpp, t);
     amg_p.cycle(st, t, dpp);
   }
 
@@ -690,11 +753,11 @@ static void arnoldi_step(cptr_handle *h, hipStream_t st) {
   const int *jd = &ks->j;
   hipLaunchKernelGGL((k_mdot<MAXK>), dim3(g), dim3(kBlock), 0, st, (const double *)devp<double>(h->V), N, jd,
                      (const double *)devp<double>(h->w), part);
-  hipLaunchKernelGGL((k_reduce<MAXK>), dim3(1), dim3(kBlock), 0, st, (const double *)part, g, jd, 0,
+  hipLaunchKernelGGL((k_reduce<MAXK>), dim3(MAXK), dim3(kBlock), 0, st, (const double *)part, g, jd, 0,
                      devp<double>(h->h1), 0);
   hipLaunchKernelGGL((k_cgs_update_mdot<MAXK>), dim3(g), dim3(kBlock), 0, st, (const double *)devp<double>(h->V),
                      N, jd, (const double *)devp<double>(h->h1), devp<double>(h->w), part);
-  hipLaunchKernelGGL((k_reduce<MAXK>), dim3(1), dim3(kBlock), 0, st, (const double *)part, g, jd, 0,
+  hipLaunchKernelGGL((k_reduce<MAXK>), dim3(MAXK), dim3(kBlock), 0, st, (const double *)part, g, jd, 0,
                      devp<double>(h->h2), 0);
   hipLaunchKernelGGL((k_cgs_update_norm<MAXK>), dim3(g), dim3(kBlock), 0, st, (const double *)devp<double>(h->V),
                      N, jd, (const double *)devp<double>(h->h2), devp<double>(h->w), part);
@@ -830,7 +893,7 @@ void cptr_default_options(cptr_options *o) {
   o->amg_max_levels = 10;
   o->amg_coarse_size = 512;
   o->amg_seed = 0;
-  o->amg_sweeps = 1;
+  o->amg_sweeps = 2;
   o->amg_smooth_p = 1;
   o->use_graph = 1;
 }

@@ -70,6 +70,79 @@ __global__ void __launch_bounds__(kBlock) k_jacobi(Sell<T> A, const T *__restric
   xout[row] = xin[row] + dinv[row] * (b[row] - ax);
 }
 
+// ---------------------------------------------------------------------------
+// CSR products with G lanes per row, for operators with long rows (coarse
+// AMG levels, restriction): lanes stride the row, then an xor-shuffle sum.
+// ---------------------------------------------------------------------------
+template <typename T, int G>
+__device__ __forceinline__ T csrv_row_dot(const int *__restrict__ rp, const int *__restrict__ ci,
+                                          const T *__restrict__ val, int row, int lane,
+                                          const T *__restrict__ x) {
+  T acc = T(0);
+  const int e = rp[row + 1];
+  for (int k = rp[row] + lane; k < e; k += G) acc += val[k] * x[ci[k]];
+#pragma unroll
+  for (int off = G / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, G);
+  return acc;
+}
+
+template <typename T, int G, int MODE>
+__global__ void __launch_bounds__(kBlock) k_csrv_spmv(int n, const int *__restrict__ rp,
+                                                      const int *__restrict__ ci,
+                                                      const T *__restrict__ val,
+                                                      const T *__restrict__ x,
+                                                      const T *__restrict__ b, T *__restrict__ y) {
+  const int t = blockIdx.x * kBlock + threadIdx.x;
+  const int row = t / G, lane = t % G;
+  if (row >= n) return;  // whole G-lane groups exit together (G divides kBlock)
+  const T ax = csrv_row_dot<T, G>(rp, ci, val, row, lane, x);
+  if (lane != 0) return;
+  if (MODE == 0) y[row] = ax;
+  if (MODE == 1) y[row] += ax;
+  if (MODE == 2) y[row] = b[row] - ax;
+}
+
+template <typename T, int G>
+__global__ void __launch_bounds__(kBlock) k_csrv_jacobi(int n, const int *__restrict__ rp,
+                                                        const int *__restrict__ ci,
+                                                        const T *__restrict__ val,
+                                                        const T *__restrict__ dinv,
+                                                        const T *__restrict__ b,
+                                                        const T *__restrict__ xin,
+                                                        T *__restrict__ xout) {
+  const int t = blockIdx.x * kBlock + threadIdx.x;
+  const int row = t / G, lane = t % G;
+  if (row >= n) return;
+  const T ax = csrv_row_dot<T, G>(rp, ci, val, row, lane, xin);
+  if (lane == 0) xout[row] = xin[row] + dinv[row] * (b[row] - ax);
+}
+
+// x = D^{-1} b, r = b - A D^{-1} b with G lanes per row
+template <typename T, int G>
+__global__ void __launch_bounds__(kBlock) k_csrv_smooth0_resid(int n, const int *__restrict__ rp,
+                                                               const int *__restrict__ ci,
+                                                               const T *__restrict__ val,
+                                                               const T *__restrict__ dinv,
+                                                               const T *__restrict__ b,
+                                                               T *__restrict__ x,
+                                                               T *__restrict__ r) {
+  const int t = blockIdx.x * kBlock + threadIdx.x;
+  const int row = t / G, lane = t % G;
+  if (row >= n) return;
+  T acc = T(0);
+  const int e = rp[row + 1];
+  for (int k = rp[row] + lane; k < e; k += G) {
+    const int c = ci[k];
+    acc += val[k] * (dinv[c] * b[c]);
+  }
+#pragma unroll
+  for (int off = G / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, G);
+  if (lane != 0) return;
+  const T bi = b[row];
+  x[row] = dinv[row] * bi;
+  r[row] = bi - acc;
+}
+
 // coarsest level: x = A_c^{-1} b with the explicit FP64 inverse; one wave per row
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_coarse_gemv(const double *__restrict__ inv, int nc,
@@ -346,25 +419,27 @@ __global__ void __launch_bounds__(kBlock) k_norm2_partial(const double *__restri
   block_store_partials<1>(acc, 1, part);
 }
 
-// out[k] = sum_blk partial[blk][k] for k < kk (kk = *jdev + 1, or kfix when jdev is null);
-// fixed order: thread t sums blocks t, t+256, ..., then a fixed tree.
+// out[k] = sum_blk partial[blk][k] for k < kk (kk = *jdev + 1, or kfix when jdev is
+// null); one workgroup per k; fixed order: thread t sums blocks t, t+256, ...,
+// then a fixed tree, so the result does not depend on scheduling.
 template <int STRIDE>
 __global__ void __launch_bounds__(kBlock) k_reduce(const double *__restrict__ part, int nblk,
                                                    const int *__restrict__ jdev, int kfix,
                                                    double *__restrict__ out, int sqrt_out) {
-  __shared__ double sh[kBlock];
+  __shared__ double sh[kBlock / 64];
   const int kk = jdev ? *jdev + 1 : kfix;
-  for (int k = 0; k < kk; k++) {
-    double s = 0.0;
-    for (int b = threadIdx.x; b < nblk; b += kBlock) s += part[(size_t)b * STRIDE + k];
-    sh[threadIdx.x] = s;
-    __syncthreads();
-    for (int o = kBlock / 2; o > 0; o >>= 1) {
-      if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) out[k] = sqrt_out ? sqrt(sh[0]) : sh[0];
-    __syncthreads();
+  const int k = blockIdx.x;
+  if (k >= kk) return;
+  double s = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += kBlock) s += part[(size_t)b * STRIDE + k];
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < kBlock / 64; w++) t += sh[w];
+    out[k] = sqrt_out ? sqrt(t) : t;
   }
 }
 

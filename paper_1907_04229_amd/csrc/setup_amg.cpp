@@ -133,6 +133,9 @@ int aggregate(const Graph &g, int n, uint32_t seed, std::vector<int> &agg) {
   std::vector<char> root = mis2_rounds(g, n, seed);
   std::vector<int> id(n, -1), rootof(n, -1);
   int na = 0;
+  // a root without strong neighbours is an isolated node: it joins no aggregate
+  for (int i = 0; i < n; i++)
+    if (root[i] && g.rp[i + 1] == g.rp[i]) root[i] = 0;
   for (int i = 0; i < n; i++)
     if (root[i]) id[i] = na++;
   agg.assign(n, -1);
@@ -147,7 +150,7 @@ int aggregate(const Graph &g, int n, uint32_t seed, std::vector<int> &agg) {
   }
   std::vector<int> joined(n, -1);
   for (int i = 0; i < n; i++) {
-    if (agg[i] >= 0) continue;
+    if (agg[i] >= 0 || g.rp[i + 1] == g.rp[i]) continue;
     int best = -1;
     uint64_t bk = 0;
     for (int k = g.rp[i]; k < g.rp[i + 1]; k++) {
@@ -160,7 +163,7 @@ int aggregate(const Graph &g, int n, uint32_t seed, std::vector<int> &agg) {
     joined[i] = id[best];
   }
   for (int i = 0; i < n; i++)
-    if (agg[i] < 0) agg[i] = joined[i];
+    if (agg[i] < 0) agg[i] = joined[i];  // stays -1 for isolated nodes
   return na;
 }
 
@@ -196,9 +199,11 @@ HostCSR prolongator(const HostCSR &a, const std::vector<int> &agg, int na, bool 
   if (!smooth) {
     omega = 0.0;
     for (int i = 0; i < n; i++) {
-      p.ci.push_back(agg[i]);
-      p.v.push_back(1.0);
-      p.rp[i + 1] = i + 1;
+      if (agg[i] >= 0) {
+        p.ci.push_back(agg[i]);
+        p.v.push_back(1.0);
+      }
+      p.rp[i + 1] = int(p.ci.size());
     }
     return p;
   }
@@ -222,13 +227,14 @@ HostCSR prolongator(const HostCSR &a, const std::vector<int> &agg, int na, bool 
     row.clear();
     for (int k = a.rp[i]; k < a.rp[i + 1]; k++) {
       int J = agg[a.ci[k]];
+      if (J < 0) continue;
       if (slot[J] < 0) {
         slot[J] = int(row.size());
         row.push_back({J, 0.0});
       }
       row[slot[J]].second += a.v[k];
     }
-    if (slot[agg[i]] < 0) {
+    if (agg[i] >= 0 && slot[agg[i]] < 0) {
       slot[agg[i]] = int(row.size());
       row.push_back({agg[i], 0.0});
     }
@@ -332,7 +338,10 @@ void amg_build(const HostCSR &fine, const AmgParams &prm, AmgHost &out) {
     int na = aggregate(g, n, prm.seed, agg);
     if (na >= n) break;  // no coarsening possible
     L.agg = agg;
-    L.P = prolongator(L.A, agg, na, prm.smooth_p != 0, L.omega);
+    if (prm.smooth_p)
+      L.P = prolongator(L.A, agg, na, true, L.omega);
+    else
+      L.P = prolongator(L.A, agg, na, false, L.omega);
     L.R = transpose(L.P);
     HostCSR t = multiply(L.A, L.P);
     HostCSR ac = multiply(L.R, t);

@@ -27,6 +27,8 @@ is exact to rounding for the analytic property functions used here; the
 upwind branch is chosen on the real part, i.e. the derivative of the selected
 branch is taken.
 """
+import os
+
 import numpy as np
 
 from . import props as P
@@ -44,6 +46,8 @@ class Grid:
         self.area = dx * dx
         idx = np.arange(self.n).reshape(nz, ny, nx)
         Ls, Rs, gn = [], [], []
+        self.segments = []   # (stencil offset, first face, end face) per axis
+        nf = 0
         for axis, shape_ok in ((2, nx > 1), (1, ny > 1), (0, nz > 1)):
             if not shape_ok:
                 continue
@@ -55,6 +59,9 @@ class Grid:
             r = idx[tuple(sl_r)].reshape(-1)
             Ls.append(l)
             Rs.append(r)
+            off = {2: 1, 1: nx, 0: nx * ny}[axis]
+            self.segments.append((off, nf, nf + l.size))
+            nf += l.size
             # gravity acts along -z; n points from L to R (+z for z-faces)
             gn.append(np.full(l.size, -P.G if axis == 0 else 0.0))
         if Ls:
@@ -66,12 +73,27 @@ class Grid:
             self.fR = np.zeros(0, np.int64)
             self.gdotn = np.zeros(0)
         self.nf = self.fL.size
+        self._pattern = None
 
     def cell(self, i, j, k):
         return i + self.nx * (j + self.ny * k)
 
     def bsr_pattern(self):
-        """7-point BSR pattern with ascending columns; returns (row_ptr, col_idx)."""
+        """7-point BSR pattern with ascending columns; returns (row_ptr, col_idx,
+        slot) where slot[off][i] is the position of block (i, i+off) or -1."""
+        if self._pattern is None:
+            self._pattern = self._make_pattern()
+        return self._pattern
+
+    def scatter_faces(self, arr, idx_of, f_l, f_r):
+        """arr[idx_of(L)] += f_l and arr[idx_of(R)] += f_r face by face; within one
+        axis every cell is the L (or R) cell of at most one face, so plain
+        fancy-index updates are exact."""
+        for off, a, b in self.segments:
+            arr[idx_of(off, "L", self.fL[a:b])] += f_l[a:b]
+            arr[idx_of(off, "R", self.fR[a:b])] += f_r[a:b]
+
+    def _make_pattern(self):
         n, nx, nxy = self.n, self.nx, self.nx * self.ny
         i = np.arange(n)
         ii = i % nx
@@ -237,8 +259,7 @@ class ThermalModel:
         if g.nf:
             f = self._scale(self._face_flux(x[g.fL], x[g.fR]))
             F = F.astype(np.result_type(F, f))
-            _scatter_add(F, g.fL, f)
-            _scatter_add(F, g.fR, -f)
+            g.scatter_faces(F, lambda off, side, cells: cells, f, -f)
         return F
 
     # ---- Jacobian ------------------------------------------------------------
@@ -258,28 +279,34 @@ class ThermalModel:
             xl, xr = x[g.fL], x[g.fR]
             dfl = np.empty((g.nf, nv, nv))
             dfr = np.empty((g.nf, nv, nv))
-            for u in range(nv):
-                xlc = xl.astype(complex)
-                xlc[:, u] += 1j * h
-                dfl[:, :, u] = self._scale(self._face_flux(xlc, xr)).imag / h
-                xrc = xr.astype(complex)
-                xrc[:, u] += 1j * h
-                dfr[:, :, u] = self._scale(self._face_flux(xl, xrc)).imag / h
-            off_lr, off_rl = self._face_slots(row_ptr, col)
-            _scatter_add(vals, diag[g.fL], dfl)
-            _scatter_add(vals, diag[g.fR], -dfr)
-            vals[off_lr] += dfr
-            vals[off_rl] -= dfl
-        return row_ptr, col, vals
 
-    def _face_slots(self, row_ptr, col):
-        """BSR slot of block (L,R) and (R,L) for every face."""
-        g = self.g
-        fl, fr = g.fL, g.fR
-        # columns are sorted within each row: search the short rows
-        off_lr = _find_slots(row_ptr, col, fl, fr)
-        off_rl = _find_slots(row_ptr, col, fr, fl)
-        return off_lr, off_rl
+            def column(task):
+                side, u = task
+                if side == 0:
+                    a = xl.astype(complex)
+                    a[:, u] += 1j * h
+                    d = self._scale(self._face_flux(a, xr)).imag / h
+                    dfl[:, :, u] = d
+                else:
+                    a = xr.astype(complex)
+                    a[:, u] += 1j * h
+                    d = self._scale(self._face_flux(xl, a)).imag / h
+                    dfr[:, :, u] = d
+
+            tasks = [(side, u) for u in range(nv) for side in (0, 1)]
+            if g.nf >= 200_000:
+                # numpy releases the GIL inside large array operations
+                from concurrent.futures import ThreadPoolExecutor
+                with ThreadPoolExecutor(max_workers=min(len(tasks), os.cpu_count() or 1)) as ex:
+                    list(ex.map(column, tasks))
+            else:
+                for t in tasks:
+                    column(t)
+            # d F_L/d x_L += dfl, d F_R/d x_R -= dfr, d F_L/d x_R += dfr, d F_R/d x_L -= dfl
+            g.scatter_faces(vals, lambda off, side, cells: diag[cells], dfl, -dfr)
+            g.scatter_faces(vals, lambda off, side, cells: slot[off if side == "L" else -off][cells],
+                            dfr, -dfl)
+        return row_ptr, col, vals
 
     # ---- Schur complement approximation (eq:Se) -------------------------------
     def schur_approx(self, x):
@@ -332,36 +359,7 @@ class ThermalModel:
             kt = 2.0 * ktl * ktr / (ktl + ktr) * g.area / g.dx
             dl += kt
             dr -= kt
-            off_lr, off_rl = self._face_slots(row_ptr, col)
-            _scatter_add(vals, diag[g.fL], dl)
-            _scatter_add(vals, diag[g.fR], -dr)
-            vals[off_lr] += dr
-            vals[off_rl] -= dl
+            g.scatter_faces(vals, lambda off, side, cells: diag[cells], dl, -dr)
+            g.scatter_faces(vals, lambda off, side, cells: slot[off if side == "L" else -off][cells],
+                            dr, -dl)
         return row_ptr, col, vals
-
-
-def _scatter_add(arr, idx, v):
-    """arr[idx] += v with repeated indices accumulated (np.add.at is slow)."""
-    if idx.size == 0:
-        return
-    flat = arr.reshape(arr.shape[0], -1)
-    vv = v.reshape(v.shape[0], -1)
-    for c in range(flat.shape[1]):
-        if np.iscomplexobj(vv):
-            flat[:, c] += np.bincount(idx, weights=vv[:, c].real, minlength=arr.shape[0]) \
-                + 1j * np.bincount(idx, weights=vv[:, c].imag, minlength=arr.shape[0])
-        else:
-            flat[:, c] += np.bincount(idx, weights=vv[:, c], minlength=arr.shape[0])
-
-
-def _find_slots(row_ptr, col, rows, cols):
-    out = np.full(rows.size, -1, np.int64)
-    start = row_ptr[rows]
-    width = (row_ptr[rows + 1] - start).max() if rows.size else 0
-    for k in range(int(width)):
-        pos = start + k
-        ok = (pos < row_ptr[rows + 1])
-        hit = ok & (col[np.minimum(pos, col.size - 1)] == cols)
-        out[hit] = pos[hit]
-    assert (out >= 0).all()
-    return out

@@ -1,8 +1,11 @@
 """GPU parity: libcptr (HIP, gfx950) against the FP64 CPU oracle, through the C ABI.
 
 Tolerances (relative, max-norm over the vector unless stated):
-  FP64 kernels and single applications   <= 1e-10  (the coarsest AMG level is an
+  FP64 V-cycles and first stage           <= 1e-10  (the coarsest AMG level is an
       explicit inverse on the GPU and an LU solve in the oracle; both FP64)
+  FP64 full application                   <= 1e-9   (rounding differences of the
+      two-stage residual are amplified by the ILU solves; the FP32 runs measure
+      that amplification at up to ~1e6 on the three-phase case, i.e. ~2e-10 in FP64)
   FP32 first stage                         <= 1e-5   (V-cycles and scalar products
       in FP32, coarsest level FP64; observed ~2.5e-7)
   FP32 full application (2-norm)           <= 1e-2 multicolour, <= 0.2 natural
@@ -141,7 +144,7 @@ def test_apply_fp64(name, first, second):
     v = np.random.default_rng(3).standard_normal(pr.n * pr.nv)
     z = s.apply(dev(v))
     torch.cuda.synchronize()
-    assert relerr(z.cpu().numpy(), o.apply(v)) <= 1e-10
+    assert relerr(z.cpu().numpy(), o.apply(v)) <= 1e-9
     s.close()
 
 
