@@ -65,6 +65,7 @@ extern "C" {
 #define CPTR_SECOND_BILU0 1      /* block ILU(0), natural order, level-scheduled solves */
 #define CPTR_SECOND_BILU0_MC 2   /* block ILU(0) in greedy multicolour order */
 #define CPTR_SECOND_IDENTITY 3   /* z = b1 + x1 */
+#define CPTR_SECOND_LEARNED 4    /* learned message-passing stage (cptr_learn.h), BILU(0) multicolour fallback */
 
 /* precision of the preconditioner (FGMRES itself is always FP64) */
 #define CPTR_FP64 0
@@ -115,6 +116,7 @@ typedef struct {
   double relres_est;     /* |g_{j+1}| / ||b|| at exit */
   double relres_true;    /* ||b - A x|| / ||b||, FP64, at exit */
   double solve_ms;       /* wall time inside fgmres_solve */
+  int fell_back;         /* 1 if the learned second stage was replaced by BILU(0) */
 } cptr_solve_info;
 
 typedef struct {
@@ -175,6 +177,16 @@ int cptr_vcycle(cptr_handle *h, int which, const double *b, double *x, void *str
  * CPTR_NOT_CONVERGED (info filled in both cases). */
 int fgmres_solve(cptr_handle *h, const double *b, double *x, const cptr_solve_opts *so,
                  cptr_solve_info *info, void *stream);
+
+/* Copy the Arnoldi basis vector v_j of the most recent FGMRES cycle (device
+ * FP64 [n*nv], orthonormal in the 2-norm; Section 3, right-preconditioned
+ * GMRES) into `out` (device FP64 [n*nv], caller-owned), ordered on `stream`.
+ * These are the vectors the preconditioner was applied to, e.g. training
+ * inputs for a learned second stage.  Valid for 0 <= j <= restart after a
+ * fgmres_solve with that restart length; only j < (iterations of the last
+ * cycle) hold basis vectors of that solve.  CPTR_ERR_INVALID_ARG for a
+ * handle without a solve or j out of range. */
+int cptr_krylov_vector(const cptr_handle *h, int j, double *out, void *stream);
 
 /* Numeric re-setup with an unchanged pattern.  Not available yet: returns
  * CPTR_ERR_UNSUPPORTED. */

@@ -11,8 +11,10 @@ preconditioners": x = M2^{-1} b1 + x1) by a small message-passing network on
 the 7-point cell graph.  Definition (both sides implement exactly this):
 
   inputs      r_i = D_i^{-1} b1_i  (D_i the diagonal nv x nv block of A)
-              s   = sqrt(mean of r^2 over all cells and components); u = r / s
-              e_{i,d} = D_i^{-1} A_{i, nbr(i,d)} (flattened row-major), zero when
+              s_k = sqrt(mean over cells of r_ik^2), one scale per unknown k (the
+                    unknowns have different units); u_ik = r_ik / s_k (0 if s_k = 0)
+              e_{i,d} = S^{-1} D_i^{-1} A_{i, nbr(i,d)} S (flattened row-major),
+              S = diag(s), i.e. the block in the scaled unknowns; zero when
               cell i has no neighbour in direction d; d = 0..5 orders the
               neighbours as (-axis0, +axis0, -axis1, +axis1, -axis2, +axis2),
               axes ordered by increasing |column - row| offset
@@ -22,7 +24,7 @@ the 7-point cell graph.  Definition (both sides implement exactly this):
     m_i       = sum_d g_{i,d} * h^{l-1}_{nbr(i,d)}          (elementwise)
     a_i       = W_s^l h^{l-1}_i + W_m^l m_i + b^l
     h^l_i     = h^{l-1}_i + relu(a_i)
-  output      z2_i = s (u_i + W_out h3_i)
+  output      z2_ik = s_k (u_ik + (W_out h3_i)_k)
 With W_out = 0 the stage is block Jacobi: z2 = D^{-1} b1.
 Loss of one pair (A, b1): ||b1 - A z2||^2 / ||b1||^2.
 """
@@ -106,16 +108,18 @@ def forward(theta, b1, dinv, E, nbr, nv):
     p = unflatten(np.asarray(theta, np.float64), nv)
     n = dinv.shape[0]
     r = np.einsum("irc,ic->ir", dinv, b1.reshape(n, nv))
-    s = np.sqrt(np.mean(r * r))
+    s = np.sqrt(np.mean(r * r, axis=0))
+    inv = np.where(s > 0.0, 1.0 / np.where(s > 0.0, s, 1.0), 0.0)
     cache = dict(s=s, r=r)
-    if s == 0.0:
-        return np.zeros(n * nv), cache
-    u = r / s
+    u = r * inv
+    # edge blocks in the scaled unknowns: e[r][c] * s_c / s_r
+    fac = (inv[:, None] * s[None, :]).reshape(-1)
+    Es = E * fac[None, None, :]
     h = u @ p["W_in"].T
     hs, ms, as_, gs = [h], [], [], []
     mask = (nbr >= 0)
     for l in range(LAYERS):
-        g = E @ p[f"W_e{l}"].T                       # (n, 6, 64)
+        g = Es @ p[f"W_e{l}"].T                      # (n, 6, 64)
         hn = np.where(mask[:, :, None], h[np.maximum(nbr, 0)], 0.0)
         m = np.sum(g * hn, axis=1)
         a = h @ p[f"W_s{l}"].T + m @ p[f"W_m{l}"].T + p[f"b{l}"]
@@ -125,8 +129,8 @@ def forward(theta, b1, dinv, E, nbr, nv):
         as_.append(a)
         gs.append(g)
     out = h @ p["W_out"].T
-    z2 = s * (u + out)
-    cache.update(u=u, hs=hs, ms=ms, as_=as_, gs=gs)
+    z2 = s * (u + out)   # s broadcasts over the unknowns
+    cache.update(u=u, hs=hs, ms=ms, as_=as_, gs=gs, Es=Es)
     return z2.reshape(-1), cache
 
 
@@ -140,10 +144,8 @@ def loss_and_grad(theta, b1, A_dense, dinv, E, nbr, nv):
     res = b1 - A_dense @ z2
     L = float(res @ res) / bb
     grads = {k: np.zeros_like(v) for k, v in p.items()}
-    if c["s"] == 0.0:
-        return L, _flatten(grads, nv)
     dz = (-2.0 / bb) * (A_dense.T @ res)             # dL/dz2
-    dout = c["s"] * dz.reshape(n, nv)
+    dout = c["s"][None, :] * dz.reshape(n, nv)
     h3 = c["hs"][-1]
     grads["W_out"] = dout.T @ h3
     dh = dout @ p["W_out"]
@@ -158,7 +160,7 @@ def loss_and_grad(theta, b1, A_dense, dinv, E, nbr, nv):
         dm = da @ p[f"W_m{l}"]
         hn = np.where(mask[:, :, None], hprev[np.maximum(nbr, 0)], 0.0)
         dg = dm[:, None, :] * hn                     # (n, 6, 64)
-        grads[f"W_e{l}"] = np.einsum("idk,idq->kq", dg, E)
+        grads[f"W_e{l}"] = np.einsum("idk,idq->kq", dg, c["Es"])
         dh_new = dh + da @ p[f"W_s{l}"]
         contrib = dm[:, None, :] * g                 # d loss / d h_nbr(i,d)
         for d in range(NDIR):

@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libcptr.so")
 CPTR_OK = 0
 CPTR_NOT_CONVERGED = 1
 FIRST = {"none": 0, "cptr": 1, "cptr_lower": 2, "cpr": 3}
-SECOND = {"none": 0, "bilu0": 1, "bilu0_mc": 2, "identity": 3}
+SECOND = {"none": 0, "bilu0": 1, "bilu0_mc": 2, "identity": 3, "learned": 4}
 PRECISION = {"fp64": 0, "fp32": 1}
 
 
@@ -46,7 +46,7 @@ class SolveOpts(C.Structure):
 class SolveInfo(C.Structure):
     _fields_ = [("iters", C.c_int), ("restarts", C.c_int), ("converged", C.c_int),
                 ("relres_est", C.c_double), ("relres_true", C.c_double),
-                ("solve_ms", C.c_double)]
+                ("solve_ms", C.c_double), ("fell_back", C.c_int)]
 
 
 class Stats(C.Structure):
@@ -80,6 +80,7 @@ def load():
         L.cptr_first_stage.argtypes = [vp, vp, vp, vp]
         L.cptr_vcycle.argtypes = [vp, ip, vp, vp, vp]
         L.fgmres_solve.argtypes = [vp, vp, vp, C.POINTER(SolveOpts), C.POINTER(SolveInfo), vp]
+        L.cptr_krylov_vector.argtypes = [vp, ip, vp, vp]
         L.cptr_update_values.argtypes = [vp, vp, vp, vp]
         L.cptr_get_stats.argtypes = [vp, C.POINTER(Stats)]
         L.cptr_get_aggregates.argtypes = [vp, ip, ip, C.POINTER(C.c_int)]
@@ -90,6 +91,17 @@ def load():
         L.cptr_status_string.argtypes = [ip]
         L.cptr_last_error.restype = C.c_char_p
         L.cptr_destroy.argtypes = [vp]
+        fp = C.POINTER(C.c_float)
+        L.cptr_learn_param_count.restype = C.c_size_t
+        L.cptr_learn_param_count.argtypes = [ip]
+        L.cptr_learn_create.argtypes = [C.POINTER(vp), ip, fp]
+        L.cptr_learn_set_params.argtypes = [vp, fp]
+        L.cptr_learn_get_params.argtypes = [vp, fp]
+        L.cptr_learn_destroy.argtypes = [vp]
+        L.cptr_learn_attach.argtypes = [vp, vp]
+        L.cptr_learn_forward.argtypes = [vp, vp, vp, vp]
+        L.cptr_learn_grad.argtypes = [vp, vp, ip, fp, fp, vp]
+        L.cptr_learn_train_step.argtypes = [vp, vp, ip, C.c_float, fp, vp]
         _lib = L
     return _lib
 
@@ -164,6 +176,11 @@ def cptr_vcycle(h, which, b, x, stream=None):
                               _stream(stream)))
 
 
+def cptr_krylov_vector(h, j, out, stream=None):
+    import torch
+    _check(load().cptr_krylov_vector(h, j, _ptr(out, torch.float64), _stream(stream)))
+
+
 def fgmres_solve(h, b, x, restart=30, rtol=1e-6, maxit=1000, nonzero_guess=False, stream=None):
     import torch
     so = SolveOpts(restart, rtol, maxit, int(bool(nonzero_guess)))
@@ -172,7 +189,8 @@ def fgmres_solve(h, b, x, restart=30, rtol=1e-6, maxit=1000, nonzero_guess=False
                              C.byref(info), _stream(stream))
     _check(rc, allow=(CPTR_OK, CPTR_NOT_CONVERGED))
     return dict(iters=info.iters, restarts=info.restarts, converged=bool(info.converged),
-                relres_est=info.relres_est, relres_true=info.relres_true, solve_ms=info.solve_ms)
+                relres_est=info.relres_est, relres_true=info.relres_true, solve_ms=info.solve_ms,
+                fell_back=bool(info.fell_back))
 
 
 def cptr_update_values(h, A_vals, S_vals=None, stream=None):
@@ -267,3 +285,74 @@ class Solver:
             self.close()
         except Exception:
             pass
+
+
+# ---------------------------------------------------------------- learned second stage (cptr_learn.h)
+def _fptr(a):
+    return a.ctypes.data_as(C.POINTER(C.c_float))
+
+
+def cptr_learn_param_count(nv):
+    return int(load().cptr_learn_param_count(nv))
+
+
+class LearnModel:
+    """Parameters (FP32 master copy, BF16 operands, Adam state) on the device."""
+
+    def __init__(self, nv, theta):
+        theta = np.ascontiguousarray(theta, np.float32)
+        assert theta.size == cptr_learn_param_count(nv)
+        self.nv = nv
+        self.h = C.c_void_p()
+        _check(load().cptr_learn_create(C.byref(self.h), nv, _fptr(theta)))
+
+    def params(self):
+        out = np.empty(cptr_learn_param_count(self.nv), np.float32)
+        _check(load().cptr_learn_get_params(self.h, _fptr(out)))
+        return out
+
+    def set_params(self, theta):
+        theta = np.ascontiguousarray(theta, np.float32)
+        _check(load().cptr_learn_set_params(self.h, _fptr(theta)))
+
+    def attach(self, solver):
+        _check(load().cptr_learn_attach(solver.h, self.h))
+        solver.model = self
+
+    def close(self):
+        if self.h:
+            load().cptr_learn_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def cptr_learn_forward(solver, b1, stream=None):
+    import torch
+    z = torch.empty_like(b1)
+    _check(load().cptr_learn_forward(solver.h, _ptr(b1, torch.float64), _ptr(z, torch.float64),
+                                     _stream(stream)))
+    return z
+
+
+def cptr_learn_grad(solver, b1_batch, want_grad=True, stream=None):
+    import torch
+    count = b1_batch.shape[0]
+    loss = C.c_float(0.0)
+    g = np.empty(cptr_learn_param_count(solver.nv), np.float32) if want_grad else None
+    _check(load().cptr_learn_grad(solver.h, _ptr(b1_batch.contiguous(), torch.float64), count,
+                                  C.byref(loss), _fptr(g) if want_grad else None, _stream(stream)))
+    return float(loss.value), g
+
+
+def cptr_learn_train_step(solver, b1_batch, lr, stream=None):
+    import torch
+    loss = C.c_float(0.0)
+    _check(load().cptr_learn_train_step(solver.h, _ptr(b1_batch.contiguous(), torch.float64),
+                                        b1_batch.shape[0], float(lr), C.byref(loss),
+                                        _stream(stream)))
+    return float(loss.value)

@@ -23,8 +23,10 @@
 #include <string>
 #include <vector>
 
+#include "../../include/cptr_learn.h"
 #include "common.h"
 #include "device_kernels.hip"
+#include "learned_kernels.hip"
 
 namespace cptr {
 
@@ -324,12 +326,181 @@ struct IluDev {
   }
 };
 
+// ---------------------------------------------------------------- learned stage
+// Parameters of the learned second stage on the device (cptr_learn_model).
+struct LearnModelDev {
+  int nv = 0, np = 0;
+  DevMem theta, packed, am, av, grad;
+  int step = 0;
+  static int nin(int nv) { return kHid * nv; }
+  static int nl(int nv) { return kHid * nv * nv + 2 * kHid * kHid + kHid; }
+  static int count(int nv) { return nin(nv) + 3 * nl(nv) + nv * kHid; }
+  static constexpr int kPacked = kHid * kEdge + 4 * kHid * kHid;  // per layer
+  const float *W_in() const { return devp<float>(theta); }
+  const float *bias(int l) const { return devp<float>(theta) + nin(nv) + l * nl(nv) + kHid * nv * nv + 2 * kHid * kHid; }
+  const float *W_out() const { return devp<float>(theta) + nin(nv) + 3 * nl(nv); }
+  const short *We16(int l) const { return devp<short>(packed) + (size_t)l * kPacked; }
+  const short *Ws(int l) const { return We16(l) + kHid * kEdge; }
+  const short *Wm(int l) const { return Ws(l) + kHid * kHid; }
+  const short *WsT(int l) const { return Wm(l) + kHid * kHid; }
+  const short *WmT(int l) const { return WsT(l) + kHid * kHid; }
+  void pack(hipStream_t st) {
+    if (nv == 3)
+      hipLaunchKernelGGL((k_lrn_pack<3>), dim3(nblk(3 * kPacked)), dim3(kBlock), 0, st, devp<float>(theta), devp<short>(packed));
+    else
+      hipLaunchKernelGGL((k_lrn_pack<4>), dim3(nblk(3 * kPacked)), dim3(kBlock), 0, st, devp<float>(theta), devp<short>(packed));
+    LAUNCH_CHECK();
+  }
+};
+
+static inline short host_bf16(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (short)(u >> 16);
+}
+
+// Matrix-dependent data of the learned stage: neighbour table, BF16 edge
+// features D_i^{-1} A_{i,nbr(i,d)}, FP32 diagonal-block inverses, transpose
+// positions (for A^T in training), and work buffers.
+struct LearnedDev {
+  int n = 0, nv = 0, nnzb = 0;
+  DevMem nbr, E, dinv, tpos, r, s, spart, hA, hB;
+  DevMem H[4], M[3], Aa[3], dh0, dh1, dm, dhown, z2, res, dz, part;
+  bool train_ready = false;
+
+  // neighbours: direction d = 2 axis + (offset > 0), axes by increasing |offset|
+  void build(int n_, int nv_, const std::vector<int> &rp, const std::vector<int> &ci,
+             const std::vector<double> &vals) {
+    n = n_;
+    nv = nv_;
+    nnzb = rp[n];
+    std::vector<int> mags;
+    for (int i = 0; i < n; i++)
+      for (int k = rp[i]; k < rp[i + 1]; k++)
+        if (ci[k] != i) mags.push_back(std::abs(ci[k] - i));
+    std::sort(mags.begin(), mags.end());
+    mags.erase(std::unique(mags.begin(), mags.end()), mags.end());
+    if (mags.size() > 3) throw Error{CPTR_ERR_UNSUPPORTED, "the learned stage needs a 7-point cell graph"};
+    const int b2 = nv * nv;
+    std::vector<int> nb((size_t)n * kDir, -1), tp(nnzb, -1);
+    std::vector<double> dv((size_t)n * b2);
+    std::vector<float> df((size_t)n * b2);
+    std::vector<short> eb((size_t)n * kDir * kEdge, 0);
+    for (int i = 0; i < n; i++) {
+      int dk = -1;
+      for (int k = rp[i]; k < rp[i + 1]; k++) {
+        const int j = ci[k];
+        if (j == i) { dk = k; continue; }
+        const int axis = int(std::lower_bound(mags.begin(), mags.end(), std::abs(j - i)) - mags.begin());
+        const int d = 2 * axis + (j > i ? 1 : 0);
+        if (nb[(size_t)i * kDir + d] >= 0) throw Error{CPTR_ERR_UNSUPPORTED, "not a 7-point cell graph"};
+        nb[(size_t)i * kDir + d] = j;
+        tp[k] = int(std::lower_bound(ci.begin() + rp[j], ci.begin() + rp[j + 1], i) - ci.begin());
+      }
+      tp[dk] = dk;
+      // D_i^{-1} by Gauss-Jordan with partial pivoting
+      double m[4][8];
+      for (int r = 0; r < nv; r++)
+        for (int q = 0; q < 2 * nv; q++)
+          m[r][q] = q < nv ? vals[(size_t)dk * b2 + r * nv + q] : (q - nv == r ? 1.0 : 0.0);
+      for (int c = 0; c < nv; c++) {
+        int p = c;
+        for (int r = c + 1; r < nv; r++) if (std::fabs(m[r][c]) > std::fabs(m[p][c])) p = r;
+        if (m[p][c] == 0.0) throw Error{CPTR_ERR_SINGULAR_BLOCK, "singular diagonal block"};
+        if (p != c) for (int q = 0; q < 2 * nv; q++) std::swap(m[c][q], m[p][q]);
+        const double d = m[c][c];
+        for (int q = 0; q < 2 * nv; q++) m[c][q] /= d;
+        for (int r = 0; r < nv; r++) {
+          if (r == c) continue;
+          const double f = m[r][c];
+          for (int q = 0; q < 2 * nv; q++) m[r][q] -= f * m[c][q];
+        }
+      }
+      for (int r = 0; r < nv; r++)
+        for (int c = 0; c < nv; c++) {
+          dv[(size_t)i * b2 + r * nv + c] = m[r][nv + c];
+          df[(size_t)i * b2 + r * nv + c] = float(m[r][nv + c]);
+        }
+    }
+    for (int i = 0; i < n; i++)
+      for (int d = 0; d < kDir; d++) {
+        const int j = nb[(size_t)i * kDir + d];
+        if (j < 0) continue;
+        const int k = int(std::lower_bound(ci.begin() + rp[i], ci.begin() + rp[i + 1], j) - ci.begin());
+        for (int r = 0; r < nv; r++)
+          for (int c = 0; c < nv; c++) {
+            double acc = 0.0;
+            for (int q = 0; q < nv; q++) acc += dv[(size_t)i * b2 + r * nv + q] * vals[(size_t)k * b2 + q * nv + c];
+            eb[((size_t)i * kDir + d) * kEdge + r * nv + c] = host_bf16(float(acc));
+          }
+      }
+    upload(nbr, nb);
+    upload(E, eb);
+    upload(dinv, df);
+    upload(tpos, tp);
+    r.alloc((size_t)n * nv * 4);
+    s.alloc(4 * 4);
+    spart.alloc((size_t)(nblk(n) + 1) * 4 * 8);
+    hA.alloc((size_t)n * kHid * 4);
+    hB.alloc((size_t)n * kHid * 4);
+  }
+
+  void ensure_train() {
+    if (train_ready) return;
+    const size_t hb = (size_t)n * kHid * 4;
+    for (auto &x : H) x.alloc(hb);
+    for (auto &x : M) x.alloc(hb);
+    for (auto &x : Aa) x.alloc(hb);
+    dh0.alloc(hb);
+    dh1.alloc(hb);
+    dm.alloc(hb);
+    dhown.alloc(hb);
+    z2.alloc((size_t)n * nv * 8);
+    res.alloc((size_t)n * nv * 8);
+    dz.alloc((size_t)n * nv * 8);
+    const size_t p1 = (size_t)bwd_blocks() * 4 * (2 * kHid * kHid + kHid * kEdge + kHid);
+    const size_t p2 = (size_t)nblk((size_t)n * kHid) * kHid * 4;
+    part.alloc(std::max(p1, p2) * 4);
+    train_ready = true;
+  }
+  int ntiles() const { return (n + 15) / 16; }
+  int bwd_blocks() const { return std::max(1, std::min(512, (ntiles() + 3) / 4)); }
+
+  // h3 and friends from b1 (type BT); with `store`, the intermediate values of
+  // the backward pass are kept (training)
+  template <int NV, typename BT>
+  void forward(hipStream_t st, const LearnModelDev &mdl, const BT *b1, bool store) {
+    const int nb = nblk(n);
+    hipLaunchKernelGGL((k_lrn_input<NV, BT>), dim3(nb), dim3(kBlock), 0, st, n, devp<float>(dinv), b1,
+                       devp<float>(r), devp<double>(spart));
+    hipLaunchKernelGGL((k_lrn_scale<NV>), dim3(NV), dim3(kBlock), 0, st, (const double *)devp<double>(spart),
+                       nb, double(n), devp<float>(s));
+    float *h0 = store ? devp<float>(H[0]) : devp<float>(hA);
+    hipLaunchKernelGGL((k_lrn_h0<NV>), dim3(nblk((size_t)n * kHid)), dim3(kBlock), 0, st, n,
+                       (const float *)devp<float>(r), (const float *)devp<float>(s), mdl.W_in(), h0);
+    LAUNCH_CHECK();
+    const int lb = (ntiles() + 3) / 4;
+    for (int l = 0; l < 3; l++) {
+      const float *hin = store ? devp<float>(H[l]) : (l % 2 == 0 ? devp<float>(hA) : devp<float>(hB));
+      float *hout = store ? devp<float>(H[l + 1]) : (l % 2 == 0 ? devp<float>(hB) : devp<float>(hA));
+      hipLaunchKernelGGL((k_lrn_layer<NV>), dim3(lb), dim3(kBlock), 0, st, n, (const int *)devp<int>(nbr),
+                         (const short *)devp<short>(E), (const float *)devp<float>(s), hin, mdl.We16(l), mdl.Ws(l), mdl.Wm(l), mdl.bias(l), hout,
+                         store ? devp<float>(M[l]) : (float *)nullptr, store ? devp<float>(Aa[l]) : (float *)nullptr);
+      LAUNCH_CHECK();
+    }
+  }
+  const float *h3(bool store) const { return store ? devp<float>(H[3]) : devp<float>(hB); }
+};
+
 // ---------------------------------------------------------------- preconditioner
 struct PrecondBase {
   virtual ~PrecondBase() = default;
   virtual void apply(hipStream_t st, const ApplySlots *slots, bool z_double) = 0;
   virtual void first_stage(hipStream_t st, const ApplySlots *slots) = 0;
   virtual void vcycle(hipStream_t st, int which, const double *b, double *x) = 0;
+  virtual void set_learned(LearnedDev *l, const LearnModelDev *m) = 0;
+  virtual bool &fallback_flag() = 0;
   virtual const AmgDev<float> *amgf(int) const { return nullptr; }
   virtual const AmgDev<double> *amgd(int) const { return nullptr; }
 };
@@ -351,6 +522,9 @@ struct Precond : PrecondBase {
   DevMem vtmp, ztmp;  // FP64 staging of cptr_vcycle
   bool have_s = false, have_ilu = false;
   double bytes = 0.0;
+  LearnedDev *lrn = nullptr;             // owned by the handle
+  const LearnModelDev *model = nullptr;  // attached model
+  bool fell_back = false;                // learned stage replaced by BILU(0)
 
   void apply_first(hipStream_t st, const ApplySlots *slots) {
     const int n = op.n, fs = op.o.first_stage;
@@ -398,6 +572,16 @@ struct Precond : PrecondBase {
     hipLaunchKernelGGL((k_resid_pT<NV, T>), dim3(nblk((size_t)n * NV)), dim3(kBlock), 0, st, n, rp, ci,
                        devp<T>(acol), slots, x1p() ? x1p() : (const T *)zero_vec(), x1T(), b1p);
     LAUNCH_CHECK();
+    if (ss == CPTR_SECOND_LEARNED && !fell_back) {
+      if (!model || !lrn) throw Error{CPTR_ERR_INVALID_ARG, "no learned model attached to this handle"};
+      lrn->forward<NV, T>(st, *model, b1p, false);
+      hipLaunchKernelGGL((k_lrn_out<NV, ZT, T>), dim3(nblk((size_t)n * NV)), dim3(kBlock), 0, st, n,
+                         lrn->h3(false), model->W_out(), (const float *)devp<float>(lrn->r),
+                         (const float *)devp<float>(lrn->s), op.o.ip, op.o.iT, x1p(), x1T(), slots,
+                         (double *)nullptr);
+      LAUNCH_CHECK();
+      return;
+    }
     if (ss == CPTR_SECOND_IDENTITY) {
       hipLaunchKernelGGL((k_finish<T, ZT>), dim3(nblk((size_t)n * NV)), dim3(kBlock), 0, st, n, NV,
                          op.o.ip, op.o.iT, (const T *)b1p, x1p(), x1T(), slots);
@@ -439,6 +623,12 @@ struct Precond : PrecondBase {
     }
   }
 
+  void set_learned(LearnedDev *l, const LearnModelDev *m) override {
+    lrn = l;
+    model = m;
+  }
+  bool &fallback_flag() override { return fell_back; }
+
   void first_stage(hipStream_t st, const ApplySlots *slots) override {
     apply_first(st, slots);
     const int n = op.n;
@@ -479,6 +669,12 @@ struct cptr_handle {
   hipGraphExec_t graph_exec = nullptr;
   hipGraph_t graph = nullptr;
   int graph_m = -1;
+  std::unique_ptr<cptr::LearnedDev> lrn;  // learned-stage data of this matrix
+  cptr_learn_model *model = nullptr;      // attached model (not owned)
+};
+
+struct cptr_learn_model {
+  cptr::LearnModelDev dev;
 };
 
 namespace cptr {
@@ -543,12 +739,21 @@ static void build_precond(cptr_handle *h, const std::vector<int> &rp, const std:
       if (o.first_stage == CPTR_FIRST_BLOCK) bytes += P.ApT.bytes() + 3.0 * n * s;
     }
   }
-  if (o.second_stage == CPTR_SECOND_BILU0 || o.second_stage == CPTR_SECOND_BILU0_MC) {
-    IluHost ih;
-    ilu_build(n, nv, rp.data(), ci.data(), vals.data(), o.second_stage == CPTR_SECOND_BILU0_MC, ih);
+  if (o.second_stage == CPTR_SECOND_LEARNED) {
+    h->lrn = std::make_unique<LearnedDev>();
+    h->lrn->build(n, nv, rp, ci, vals);
+    P.lrn = h->lrn.get();
+    // learned stage: r = D^-1 b1, three layers (h read with 7 neighbours,
+    // written once), output
+    bytes += (double)n * (4.0 * nv * nv + 8.0 * nv) + 3.0 * n * (kDir * kEdge * 2 + 8.0 * kHid * 4 + 4.0 * kDir);
+  }
+  if (o.second_stage == CPTR_SECOND_BILU0 || o.second_stage == CPTR_SECOND_BILU0_MC ||
+      o.second_stage == CPTR_SECOND_LEARNED) {
+    IluHost ih;  // with the learned stage: the multicolour factor of the fallback
+    ilu_build(n, nv, rp.data(), ci.data(), vals.data(), o.second_stage != CPTR_SECOND_BILU0, ih);
     P.ilu.build(ih);
     P.have_ilu = true;
-    bytes += P.ilu.bytes;
+    if (o.second_stage != CPTR_SECOND_LEARNED) bytes += P.ilu.bytes;
     h->stats.ilu_levels_lower = int(ih.f_lev_ptr.size()) - 1;
     h->stats.ilu_levels_upper = int(ih.b_lev_ptr.size()) - 1;
     h->stats.ilu_colors = ih.ncolor;
@@ -602,7 +807,7 @@ static void validate_and_fetch(const cptr_bsr *A, const cptr_csr *S, const cptr_
   if (o.amg_max_levels < 1 || o.amg_coarse_size < 1 || o.amg_sweeps < 1 || !(o.amg_theta >= 0.0))
     throw Error{CPTR_ERR_INVALID_ARG, "invalid AMG options"};
   if (o.first_stage < 0 || o.first_stage > 3) throw Error{CPTR_ERR_INVALID_ARG, "invalid first stage"};
-  if (o.second_stage < 0 || o.second_stage > 3)
+  if (o.second_stage < 0 || o.second_stage > 4)
     throw Error{CPTR_ERR_UNSUPPORTED, "unsupported second stage"};
   if (o.precision != CPTR_FP32 && o.precision != CPTR_FP64)
     throw Error{CPTR_ERR_INVALID_ARG, "invalid precision"};
@@ -772,6 +977,20 @@ static void arnoldi_step(cptr_handle *h, hipStream_t st) {
 }
 
 
+// switch the learned second stage to its BILU(0) fallback; the captured
+// Arnoldi graph holds the learned kernels, so it is rebuilt
+static void fall_back(cptr_handle *h, hipStream_t st) {
+  CPTR_HIP_TRY(hipStreamSynchronize(st));
+  h->pc->fallback_flag() = true;
+  if (h->graph_exec) {
+    (void)hipGraphExecDestroy(h->graph_exec);
+    (void)hipGraphDestroy(h->graph);
+    h->graph_exec = nullptr;
+    h->graph = nullptr;
+  }
+  h->graph_m = -1;
+}
+
 template <typename ZT>
 static int fgmres_impl(cptr_handle *h, const double *b, double *x, const cptr_solve_opts &so,
                        cptr_solve_info &info, hipStream_t user) {
@@ -788,6 +1007,7 @@ static int fgmres_impl(cptr_handle *h, const double *b, double *x, const cptr_so
   norm2(h, st, b, N, 0);
   const double bnorm = fetch(h, st, scal);
   info = cptr_solve_info{};
+  info.fell_back = h->pc->fallback_flag() ? 1 : 0;
   if (!std::isfinite(bnorm)) throw Error{CPTR_ERR_NONFINITE, "non-finite right-hand side"};
   if (!so.nonzero_guess || bnorm == 0.0) {
     hipLaunchKernelGGL((k_fill<double>), dim3(sgrid(N)), dim3(kBlock), 0, st, x, N, 0.0);
@@ -803,7 +1023,8 @@ static int fgmres_impl(cptr_handle *h, const double *b, double *x, const cptr_so
     if (m <= 32) arnoldi_step<ZT, 32>(h, st);
     else arnoldi_step<ZT, 64>(h, st);
   };
-  if (use_graph && h->graph_m != m) {
+  auto capture = [&]() {
+    if (!use_graph || h->graph_m == m) return;
     if (h->graph_exec) {
       (void)hipGraphExecDestroy(h->graph_exec);
       (void)hipGraphDestroy(h->graph);
@@ -814,7 +1035,7 @@ static int fgmres_impl(cptr_handle *h, const double *b, double *x, const cptr_so
     try {
       step();
     } catch (...) {
-      hipGraph_t junk;
+      hipGraph_t junk = nullptr;
       (void)hipStreamEndCapture(st, &junk);
       if (junk) (void)hipGraphDestroy(junk);
       throw;
@@ -822,7 +1043,7 @@ static int fgmres_impl(cptr_handle *h, const double *b, double *x, const cptr_so
     CPTR_HIP_TRY(hipStreamEndCapture(st, &h->graph));
     CPTR_HIP_TRY(hipGraphInstantiate(&h->graph_exec, h->graph, nullptr, nullptr, 0));
     h->graph_m = m;
-  }
+  };
   int iters = 0, cycles = 0, converged = 0;
   double est = 0.0, truer = 0.0;
   for (;;) {
@@ -837,12 +1058,14 @@ static int fgmres_impl(cptr_handle *h, const double *b, double *x, const cptr_so
       break;
     }
     if (iters >= so.maxit) break;
+    capture();
     hipLaunchKernelGGL(k_cycle_init, dim3(1), dim3(64), 0, st, ks, (const double *)(scal + 1),
                        devp<double>(h->g), m);
     hipLaunchKernelGGL(k_first_vector, dim3(sgrid(N)), dim3(kBlock), 0, st, devp<double>(h->V), N,
                        (const double *)devp<double>(h->r), (const double *)(scal + 1));
     LAUNCH_CHECK();
     int j = 0;
+    bool discard = false;
     while (j < m && iters < so.maxit) {
       if (use_graph) CPTR_HIP_TRY(hipGraphLaunch(h->graph_exec, st));
       else step();
@@ -853,9 +1076,20 @@ static int fgmres_impl(cptr_handle *h, const double *b, double *x, const cptr_so
       CPTR_HIP_TRY(hipStreamSynchronize(st));
       const double hn = h->pinned[0], absg = h->pinned[1];
       est = absg / bnorm;
-      if (!std::isfinite(est)) throw Error{CPTR_ERR_NONFINITE, "non-finite Arnoldi step"};
+      if (!std::isfinite(est)) {
+        // a non-finite learned-stage output: continue with the BILU(0) fallback
+        // from the current iterate (this cycle's basis is discarded)
+        if (h->op.o.second_stage == CPTR_SECOND_LEARNED && !h->pc->fallback_flag()) {
+          fall_back(h, st);
+          info.fell_back = 1;
+          discard = true;
+          break;
+        }
+        throw Error{CPTR_ERR_NONFINITE, "non-finite Arnoldi step"};
+      }
       if (est <= so.rtol || hn == 0.0) break;
     }
+    if (discard) continue;
     hipLaunchKernelGGL(k_solve_y, dim3(1), dim3(64), 0, st, (const KState *)ks,
                        (const double *)devp<double>(h->R), (const double *)devp<double>(h->g),
                        devp<double>(h->y));
@@ -863,6 +1097,16 @@ static int fgmres_impl(cptr_handle *h, const double *b, double *x, const cptr_so
                        (const KState *)ks, (const double *)devp<double>(h->y));
     LAUNCH_CHECK();
     cycles++;
+    // stagnation of the learned stage over a whole cycle: fall back as well
+    if (h->op.o.second_stage == CPTR_SECOND_LEARNED && !h->pc->fallback_flag() && j == m) {
+      spmv<double>(h, st, x, b, devp<double>(h->r));
+      norm2(h, st, devp<double>(h->r), N, 1);
+      const double after = fetch(h, st, scal + 1) / bnorm;
+      if (!(after <= 0.5 * truer)) {
+        fall_back(h, st);
+        info.fell_back = 1;
+      }
+    }
   }
   CPTR_HIP_TRY(hipEventRecord(h->ev_out, st));
   CPTR_HIP_TRY(hipStreamWaitEvent(user, h->ev_out, 0));
@@ -874,6 +1118,94 @@ static int fgmres_impl(cptr_handle *h, const double *b, double *x, const cptr_so
   info.relres_true = truer;
   info.solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   return converged ? CPTR_OK : CPTR_NOT_CONVERGED;
+}
+
+// ---------------------------------------------------------------- learned-stage training
+// Mean loss over `count` vectors and the mean gradient accumulated in
+// model.grad; every step on the device, the reductions in fixed order.
+template <int NV>
+static double learn_grad_impl(cptr_handle *h, hipStream_t st, const double *b1_all, int count) {
+  LearnedDev &L = *h->lrn;
+  LearnModelDev &M = h->model->dev;
+  L.ensure_train();
+  ensure_krylov(h, 1);
+  const int n = L.n;
+  const size_t N = (size_t)n * NV;
+  const int np = M.np;
+  double *scal = devp<double>(h->scal);
+  float *grad = devp<float>(M.grad);
+  float *part = devp<float>(L.part);
+  hipLaunchKernelGGL((k_fill<float>), dim3(sgrid(np)), dim3(kBlock), 0, st, grad, (size_t)np, 0.f);
+  LAUNCH_CHECK();
+  const int nin = LearnModelDev::nin(NV), nl = LearnModelDev::nl(NV);
+  double loss = 0.0;
+  for (int k = 0; k < count; k++) {
+    const double *b1 = b1_all + (size_t)k * N;
+    norm2(h, st, b1, N, 2);
+    const double bn = fetch(h, st, scal + 2);
+    if (!(bn > 0.0)) continue;
+    const double bb = bn * bn;
+    L.forward<NV, double>(st, M, b1, true);
+    double *z2 = devp<double>(L.z2), *res = devp<double>(L.res), *dz = devp<double>(L.dz);
+    hipLaunchKernelGGL((k_lrn_out<NV, double, double>), dim3(nblk(N)), dim3(kBlock), 0, st, n,
+                       (const float *)devp<float>(L.H[3]), M.W_out(), (const float *)devp<float>(L.r),
+                       (const float *)devp<float>(L.s), 0, 0, (const double *)nullptr, (const double *)nullptr,
+                       (const ApplySlots *)nullptr, z2);
+    spmv<double>(h, st, z2, b1, res);
+    norm2(h, st, res, N, 3);
+    const double rn = fetch(h, st, scal + 3);
+    loss += rn * rn / bb;
+    hipLaunchKernelGGL((k_bsr_spmv_t<NV>), dim3(nblk(N)), dim3(kBlock), 0, st, n, h->rp, h->ci,
+                       (const int *)devp<int>(L.tpos), h->vals, (const double *)res, dz);
+    const double scale = -2.0 / bb / count;
+    float *dh = devp<float>(L.dh0), *dh_next = devp<float>(L.dh1);
+    const int nb64 = nblk((size_t)n * kHid);
+    hipLaunchKernelGGL((k_lrn_out_bwd<NV>), dim3(nb64), dim3(kBlock), 0, st, n, (const double *)dz, scale,
+                       (const float *)devp<float>(L.s), M.W_out(), (const float *)devp<float>(L.H[3]), dh, part);
+    hipLaunchKernelGGL(k_sum_partials, dim3(nblk(NV * kHid)), dim3(kBlock), 0, st, (const float *)part, nb64,
+                       NV * kHid, grad + nin + 3 * nl, 1);
+    LAUNCH_CHECK();
+    const int bb1 = L.bwd_blocks(), lb = (L.ntiles() + 3) / 4;
+    for (int l = 2; l >= 0; l--) {
+      hipLaunchKernelGGL((k_lrn_layer_bwd1<NV>), dim3(bb1), dim3(kBlock), 0, st, n, L.ntiles(),
+                         (const int *)devp<int>(L.nbr), (const short *)devp<short>(L.E),
+                         (const float *)devp<float>(L.s),
+                         (const float *)devp<float>(L.H[l]), (const float *)devp<float>(L.M[l]),
+                         (const float *)devp<float>(L.Aa[l]), (const float *)dh, M.WsT(l), M.WmT(l),
+                         devp<float>(L.dm), devp<float>(L.dhown), part);
+      constexpr int nlay = kHid * NV * NV + 2 * kHid * kHid + kHid;
+      hipLaunchKernelGGL((k_lrn_reduce_layer<NV>), dim3(nblk(nlay)), dim3(kBlock), 0, st, (const float *)part,
+                         bb1 * (kBlock / 64), grad + nin + l * nl);
+      hipLaunchKernelGGL((k_lrn_layer_bwd2<NV>), dim3(lb), dim3(kBlock), 0, st, n, (const int *)devp<int>(L.nbr),
+                         (const short *)devp<short>(L.E), (const float *)devp<float>(L.s), M.We16(l), (const float *)devp<float>(L.dm),
+                         (const float *)devp<float>(L.dhown), dh_next);
+      LAUNCH_CHECK();
+      std::swap(dh, dh_next);
+    }
+    hipLaunchKernelGGL((k_lrn_in_bwd<NV>), dim3(nb64), dim3(kBlock), 0, st, n, (const float *)dh,
+                       (const float *)devp<float>(L.r), (const float *)devp<float>(L.s), part);
+    hipLaunchKernelGGL(k_sum_partials, dim3(nblk(kHid * NV)), dim3(kBlock), 0, st, (const float *)part, nb64,
+                       kHid * NV, grad, 1);
+    LAUNCH_CHECK();
+  }
+  CPTR_HIP_TRY(hipStreamSynchronize(st));
+  return loss / count;
+}
+
+static double learn_grad(cptr_handle *h, hipStream_t st, const double *b1, int count) {
+  return h->op.nv == 3 ? learn_grad_impl<3>(h, st, b1, count) : learn_grad_impl<4>(h, st, b1, count);
+}
+
+static void ensure_learned_data(cptr_handle *h) {
+  if (h->lrn) return;
+  const int n = h->op.n, nv = h->op.nv, nnzb = h->op.nnzb;
+  std::vector<int> rp(n + 1), ci(nnzb);
+  std::vector<double> vals((size_t)nnzb * nv * nv);
+  CPTR_HIP_TRY(hipMemcpy(rp.data(), h->rp, sizeof(int) * (n + 1), hipMemcpyDeviceToHost));
+  CPTR_HIP_TRY(hipMemcpy(ci.data(), h->ci, sizeof(int) * nnzb, hipMemcpyDeviceToHost));
+  CPTR_HIP_TRY(hipMemcpy(vals.data(), h->vals, sizeof(double) * vals.size(), hipMemcpyDeviceToHost));
+  h->lrn = std::make_unique<LearnedDev>();
+  h->lrn->build(n, nv, rp, ci, vals);
 }
 
 }  // namespace cptr
@@ -1020,6 +1352,17 @@ int fgmres_solve(cptr_handle *h, const double *b, double *x, const cptr_solve_op
   }
 }
 
+int cptr_krylov_vector(const cptr_handle *h, int j, double *out, void *stream) {
+  if (!h || !out) return fail(Error{CPTR_ERR_INVALID_ARG, "null argument"});
+  if (h->m_alloc < 1 || j < 0 || j > h->m_alloc)
+    return fail(Error{CPTR_ERR_INVALID_ARG, "no Krylov basis of that index"});
+  const size_t N = (size_t)h->op.n * h->op.nv;
+  const hipError_t e = hipMemcpyAsync(out, devp<double>(h->V) + (size_t)j * N, N * sizeof(double),
+                                      hipMemcpyDeviceToDevice, (hipStream_t)stream);
+  if (e != hipSuccess) return fail(Error{CPTR_ERR_HIP, hipGetErrorString(e)});
+  return CPTR_OK;
+}
+
 int cptr_update_values(cptr_handle *, const double *, const double *, void *) {
   return fail(Error{CPTR_ERR_UNSUPPORTED, "numeric re-setup is not available"});
 }
@@ -1099,6 +1442,146 @@ void cptr_destroy(cptr_handle *h) {
   h->pc.reset();
   if (h->stream) (void)hipStreamDestroy(h->stream);
   delete h;
+}
+
+
+size_t cptr_learn_param_count(int nv) {
+  return (nv == 3 || nv == 4) ? (size_t)LearnModelDev::count(nv) : 0;
+}
+
+int cptr_learn_create(cptr_learn_model **out, int nv, const float *theta_host) {
+  if (!out || !theta_host || (nv != 3 && nv != 4)) return fail(Error{CPTR_ERR_INVALID_ARG, "bad argument"});
+  *out = nullptr;
+  auto *m = new cptr_learn_model();
+  try {
+    LearnModelDev &d = m->dev;
+    d.nv = nv;
+    d.np = LearnModelDev::count(nv);
+    d.theta.alloc((size_t)d.np * 4);
+    d.grad.alloc((size_t)d.np * 4);
+    d.am.alloc((size_t)d.np * 4);
+    d.av.alloc((size_t)d.np * 4);
+    d.packed.alloc((size_t)3 * LearnModelDev::kPacked * 2);
+    CPTR_HIP_TRY(hipMemcpy(d.theta.p, theta_host, (size_t)d.np * 4, hipMemcpyHostToDevice));
+    hipLaunchKernelGGL((k_fill<float>), dim3(sgrid(d.np)), dim3(kBlock), 0, 0, devp<float>(d.am), (size_t)d.np, 0.f);
+    hipLaunchKernelGGL((k_fill<float>), dim3(sgrid(d.np)), dim3(kBlock), 0, 0, devp<float>(d.av), (size_t)d.np, 0.f);
+    d.pack(0);
+    CPTR_HIP_TRY(hipDeviceSynchronize());
+    *out = m;
+    return CPTR_OK;
+  } catch (const Error &e) {
+    delete m;
+    return fail(e);
+  }
+}
+
+int cptr_learn_set_params(cptr_learn_model *m, const float *theta_host) {
+  if (!m || !theta_host) return fail(Error{CPTR_ERR_INVALID_ARG, "null argument"});
+  try {
+    CPTR_HIP_TRY(hipDeviceSynchronize());
+    CPTR_HIP_TRY(hipMemcpy(m->dev.theta.p, theta_host, (size_t)m->dev.np * 4, hipMemcpyHostToDevice));
+    m->dev.pack(0);
+    CPTR_HIP_TRY(hipDeviceSynchronize());
+    return CPTR_OK;
+  } catch (const Error &e) {
+    return fail(e);
+  }
+}
+
+int cptr_learn_get_params(const cptr_learn_model *m, float *theta_host) {
+  if (!m || !theta_host) return fail(Error{CPTR_ERR_INVALID_ARG, "null argument"});
+  try {
+    CPTR_HIP_TRY(hipDeviceSynchronize());
+    CPTR_HIP_TRY(hipMemcpy(theta_host, m->dev.theta.p, (size_t)m->dev.np * 4, hipMemcpyDeviceToHost));
+    return CPTR_OK;
+  } catch (const Error &e) {
+    return fail(e);
+  }
+}
+
+void cptr_learn_destroy(cptr_learn_model *m) {
+  if (!m) return;
+  (void)hipDeviceSynchronize();
+  delete m;
+}
+
+int cptr_learn_attach(cptr_handle *h, cptr_learn_model *m) {
+  if (!h || !m) return fail(Error{CPTR_ERR_INVALID_ARG, "null argument"});
+  if (m->dev.nv != h->op.nv) return fail(Error{CPTR_ERR_INVALID_ARG, "model and matrix nv differ"});
+  try {
+    ensure_learned_data(h);
+    h->model = m;
+    h->pc->set_learned(h->lrn.get(), &m->dev);
+    return CPTR_OK;
+  } catch (const Error &e) {
+    return fail(e);
+  }
+}
+
+int cptr_learn_forward(cptr_handle *h, const double *b1, double *z2, void *stream) {
+  if (!h || !b1 || !z2) return fail(Error{CPTR_ERR_INVALID_ARG, "null argument"});
+  if (!h->model || !h->lrn) return fail(Error{CPTR_ERR_INVALID_ARG, "no learned model attached"});
+  try {
+    hipStream_t st = (hipStream_t)stream;
+    LearnedDev &L = *h->lrn;
+    const LearnModelDev &M = h->model->dev;
+    const size_t N = (size_t)L.n * L.nv;
+    if (L.nv == 3) {
+      L.forward<3, double>(st, M, b1, false);
+      hipLaunchKernelGGL((k_lrn_out<3, double, double>), dim3(nblk(N)), dim3(kBlock), 0, st, L.n, L.h3(false),
+                         M.W_out(), (const float *)devp<float>(L.r), (const float *)devp<float>(L.s), 0, 0,
+                         (const double *)nullptr, (const double *)nullptr, (const ApplySlots *)nullptr, z2);
+    } else {
+      L.forward<4, double>(st, M, b1, false);
+      hipLaunchKernelGGL((k_lrn_out<4, double, double>), dim3(nblk(N)), dim3(kBlock), 0, st, L.n, L.h3(false),
+                         M.W_out(), (const float *)devp<float>(L.r), (const float *)devp<float>(L.s), 0, 0,
+                         (const double *)nullptr, (const double *)nullptr, (const ApplySlots *)nullptr, z2);
+    }
+    LAUNCH_CHECK();
+    return CPTR_OK;
+  } catch (const Error &e) {
+    return fail(e);
+  }
+}
+
+int cptr_learn_grad(cptr_handle *h, const double *b1, int count, float *loss_host, float *grad_host,
+                    void *stream) {
+  if (!h || !b1 || count < 1) return fail(Error{CPTR_ERR_INVALID_ARG, "bad argument"});
+  if (!h->model || !h->lrn) return fail(Error{CPTR_ERR_INVALID_ARG, "no learned model attached"});
+  try {
+    hipStream_t st = (hipStream_t)stream;
+    const double loss = learn_grad(h, st, b1, count);
+    if (loss_host) *loss_host = float(loss);
+    if (grad_host)
+      CPTR_HIP_TRY(hipMemcpy(grad_host, h->model->dev.grad.p, (size_t)h->model->dev.np * 4, hipMemcpyDeviceToHost));
+    return CPTR_OK;
+  } catch (const Error &e) {
+    return fail(e);
+  }
+}
+
+int cptr_learn_train_step(cptr_handle *h, const double *b1, int count, float lr, float *loss_host,
+                          void *stream) {
+  if (!h || !b1 || count < 1 || !(lr > 0.f)) return fail(Error{CPTR_ERR_INVALID_ARG, "bad argument"});
+  if (!h->model || !h->lrn) return fail(Error{CPTR_ERR_INVALID_ARG, "no learned model attached"});
+  try {
+    hipStream_t st = (hipStream_t)stream;
+    const double loss = learn_grad(h, st, b1, count);
+    LearnModelDev &M = h->model->dev;
+    M.step++;
+    const float b1c = 0.9f, b2c = 0.999f;
+    const float c1 = 1.f - std::pow(b1c, (float)M.step), c2 = 1.f - std::pow(b2c, (float)M.step);
+    hipLaunchKernelGGL(k_adam, dim3(nblk(M.np)), dim3(kBlock), 0, st, M.np, devp<float>(M.theta),
+                       (const float *)devp<float>(M.grad), devp<float>(M.am), devp<float>(M.av), lr, b1c, b2c,
+                       1e-8f, c1, c2);
+    LAUNCH_CHECK();
+    M.pack(st);
+    CPTR_HIP_TRY(hipStreamSynchronize(st));
+    if (loss_host) *loss_host = float(loss);
+    return CPTR_OK;
+  } catch (const Error &e) {
+    return fail(e);
+  }
 }
 
 }  // extern "C"

@@ -1,0 +1,626 @@
+// Device kernels of the learned second stage (included once by cptr.hip).
+//
+// A message-passing network on the 7-point cell graph stands in for the ILU(0)
+// second stage (it is not in the paper).  Hidden width 64, 3 layers:
+//   r = D^{-1} b1, s_k = RMS over cells of r_k (per unknown), u_k = r_k / s_k
+//   h0 = W_in u
+//   e_{i,d} = S^{-1} D_i^{-1} A_{i,nbr(i,d)} S, S = diag(s) (scaled unknowns)
+//   g_{i,d} = W_e e_{i,d};  m_i = sum_d g_{i,d} * h_{nbr(i,d)}
+//   a_i = W_s h_i + W_m m_i + b;  h_i <- h_i + relu(a_i)
+//   z2_k = s_k (u_k + (W_out h3)_k)
+// The dense products (edge gating, W_s h, W_m m and the weight gradients,
+// which reduce over cells) run on v_mfma_f32_16x16x16_bf16 with FP32
+// accumulation: one wavefront per tile of 16 cells.  Activations are kept in
+// FP32 in memory and rounded to BF16 only as MFMA operands.
+//
+// MFMA 16x16x16 operand layout (lane l = 0..63, q = 0..3):
+//   A (16 x 16):  lane holds A[l % 16][4 (l / 16) + q]
+//   B (16 x 16):  lane holds B[4 (l / 16) + q][l % 16]
+//   D (16 x 16):  lane holds D[4 (l / 16) + q][l % 16]   (q = register)
+#pragma once
+
+namespace cptr {
+
+constexpr int kHid = 64;   // hidden width
+constexpr int kDir = 6;    // neighbours on the 7-point stencil
+constexpr int kEdge = 16;  // edge features padded to the MFMA depth (nv^2 <= 16)
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ short f2bf(float f) {  // round to nearest even
+  uint32_t u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (short)(u >> 16);
+}
+
+__device__ __forceinline__ f32x4 mfma16(bf16x4 a, bf16x4 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ bf16x4 load_bf4(const short *p) {
+  return *reinterpret_cast<const bf16x4 *>(p);
+}
+
+__device__ __forceinline__ bf16x4 cvt4(float a, float b, float c, float d) {
+  bf16x4 v;
+  v[0] = f2bf(a);
+  v[1] = f2bf(b);
+  v[2] = f2bf(c);
+  v[3] = f2bf(d);
+  return v;
+}
+
+// edge features in the scaled unknowns: e[r][c] * s_c / s_r for the four
+// consecutive flattened entries k0..k0+3 (k = r NV + c; padding stays zero)
+template <int NV>
+__device__ __forceinline__ bf16x4 scale_edge4(bf16x4 e, int k0, const float *__restrict__ s) {
+  bf16x4 o;
+#pragma unroll
+  for (int q = 0; q < 4; q++) {
+    const int k = k0 + q;
+    float v = __uint_as_float(uint32_t((unsigned short)e[q]) << 16);
+    if (k < NV * NV) {
+      const float sr = s[k / NV];
+      v *= sr > 0.f ? s[k % NV] / sr : 0.f;
+    } else {
+      v = 0.f;
+    }
+    o[q] = f2bf(v);
+  }
+  return o;
+}
+
+template <int NV>
+__device__ __forceinline__ float edge_factor(int k, const float *__restrict__ s) {
+  if (k >= NV * NV) return 0.f;
+  const float sr = s[k / NV];
+  return sr > 0.f ? s[k % NV] / sr : 0.f;
+}
+
+// r = D^{-1} b1 (b1 of type BT), partial sums of r_k^2 per workgroup and unknown
+template <int NV, typename BT>
+__global__ void __launch_bounds__(kBlock) k_lrn_input(int n, const float *__restrict__ dinv,
+                                                      const BT *__restrict__ b1,
+                                                      float *__restrict__ r,
+                                                      double *__restrict__ part) {
+  __shared__ double sh[kBlock / 64][NV];
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  double acc[NV];
+#pragma unroll
+  for (int q = 0; q < NV; q++) acc[q] = 0.0;
+  if (i < n) {
+    float b[NV];
+#pragma unroll
+    for (int c = 0; c < NV; c++) b[c] = float(b1[(size_t)i * NV + c]);
+#pragma unroll
+    for (int q = 0; q < NV; q++) {
+      float s = 0.f;
+#pragma unroll
+      for (int c = 0; c < NV; c++) s += dinv[((size_t)i * NV + q) * NV + c] * b[c];
+      r[(size_t)i * NV + q] = s;
+      acc[q] = double(s) * s;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < NV; q++) {
+    const double v = wave_sum(acc[q]);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6][q] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < NV) {
+    double t = 0.0;
+    for (int w = 0; w < kBlock / 64; w++) t += sh[w][threadIdx.x];
+    part[(size_t)blockIdx.x * NV + threadIdx.x] = t;
+  }
+}
+
+// s_k = sqrt(sum_k / n) from the partials (one workgroup per unknown, fixed order)
+template <int NV>
+__global__ void __launch_bounds__(kBlock) k_lrn_scale(const double *__restrict__ part, int nb,
+                                                      double count, float *__restrict__ s_out) {
+  __shared__ double sh[kBlock / 64];
+  const int k = blockIdx.x;
+  double acc = 0.0;
+  for (int b = threadIdx.x; b < nb; b += kBlock) acc += part[(size_t)b * NV + k];
+  acc = wave_sum(acc);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < kBlock / 64; w++) t += sh[w];
+    s_out[k] = float(sqrt(t / count));
+  }
+}
+
+// h0 = W_in u, u_k = r_k / s_k: one thread per (cell, hidden unit)
+template <int NV>
+__global__ void __launch_bounds__(kBlock) k_lrn_h0(int n, const float *__restrict__ r,
+                                                   const float *__restrict__ s_ptr,
+                                                   const float *__restrict__ W_in,
+                                                   float *__restrict__ h) {
+  const size_t t = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  const int i = int(t / kHid), c = int(t % kHid);
+  if (i >= n) return;
+  float acc = 0.f;
+#pragma unroll
+  for (int k = 0; k < NV; k++) {
+    const float s = s_ptr[k];
+    const float inv = s > 0.f ? 1.f / s : 0.f;
+    acc += W_in[c * NV + k] * (r[(size_t)i * NV + k] * inv);
+  }
+  h[t] = acc;
+}
+
+// One message-passing layer; four wavefronts per workgroup, 16 cells per wave.
+// W_e16: 64 x 16 (BF16, zero padded); W_s, W_m: 64 x 64 (BF16, row-major).
+template <int NV>
+__global__ void __launch_bounds__(kBlock) k_lrn_layer(int n, const int *__restrict__ nbr,
+                                                      const short *__restrict__ E,
+                                                      const float *__restrict__ s_ptr,
+                                                      const float *__restrict__ hin,
+                                                      const short *__restrict__ W_e16,
+                                                      const short *__restrict__ W_s,
+                                                      const short *__restrict__ W_m,
+                                                      const float *__restrict__ bias,
+                                                      float *__restrict__ hout,
+                                                      float *__restrict__ m_out,
+                                                      float *__restrict__ a_out) {
+  __shared__ float sm[kBlock / 64][16][kHid + 4];
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int lr = l & 15, lg = l >> 4;  // lane row / lane group
+  const int c0 = (blockIdx.x * (kBlock / 64) + w) * 16;
+  // messages: m = sum_d (E_d W_e^T) * h_nbr
+  f32x4 macc[4];
+#pragma unroll
+  for (int t = 0; t < 4; t++) macc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const int ca = c0 + lr;  // cell of this lane's A-operand row
+  for (int d = 0; d < kDir; d++) {
+    bf16x4 ea = bf16x4{0, 0, 0, 0};
+    if (ca < n) ea = scale_edge4<NV>(load_bf4(E + ((size_t)ca * kDir + d) * kEdge + 4 * lg), 4 * lg, s_ptr);
+    int nb[4];
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+      const int cell = c0 + 4 * lg + q;
+      nb[q] = cell < n ? nbr[(size_t)cell * kDir + d] : -1;
+    }
+#pragma unroll
+    for (int t = 0; t < 4; t++) {
+      const bf16x4 wb = load_bf4(W_e16 + (lr + 16 * t) * kEdge + 4 * lg);
+      const f32x4 g = mfma16(ea, wb, f32x4{0.f, 0.f, 0.f, 0.f});
+#pragma unroll
+      for (int q = 0; q < 4; q++)
+        if (nb[q] >= 0) macc[t][q] += g[q] * hin[(size_t)nb[q] * kHid + lr + 16 * t];
+    }
+  }
+  // layout change of m (D layout -> A layout) through LDS
+#pragma unroll
+  for (int t = 0; t < 4; t++)
+#pragma unroll
+    for (int q = 0; q < 4; q++) sm[w][4 * lg + q][lr + 16 * t] = macc[t][q];
+  __syncthreads();
+  f32x4 acc[4];
+#pragma unroll
+  for (int t = 0; t < 4; t++) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int ks = 0; ks < 4; ks++) {
+    const int k0 = 16 * ks + 4 * lg;
+    bf16x4 ha = bf16x4{0, 0, 0, 0};
+    if (ca < n) {
+      const float *hp = hin + (size_t)ca * kHid + k0;
+      ha = cvt4(hp[0], hp[1], hp[2], hp[3]);
+    }
+    const bf16x4 ma = cvt4(sm[w][lr][k0], sm[w][lr][k0 + 1], sm[w][lr][k0 + 2], sm[w][lr][k0 + 3]);
+#pragma unroll
+    for (int t = 0; t < 4; t++) {
+      acc[t] = mfma16(ha, load_bf4(W_s + (lr + 16 * t) * kHid + k0), acc[t]);
+      acc[t] = mfma16(ma, load_bf4(W_m + (lr + 16 * t) * kHid + k0), acc[t]);
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < 4; t++)
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+      const int cell = c0 + 4 * lg + q, col = lr + 16 * t;
+      if (cell >= n) continue;
+      const size_t o = (size_t)cell * kHid + col;
+      const float a = acc[t][q] + bias[col];
+      hout[o] = hin[o] + fmaxf(a, 0.f);
+      if (m_out) m_out[o] = macc[t][q];
+      if (a_out) a_out[o] = a;
+    }
+}
+
+// z2 = s (r / s + W_out h3) = r + s W_out h3, finished as z = z2 + x1 (the
+// second-stage result) in the output type ZT through the apply slots, or as
+// a plain FP64 vector when `z2_out` is given.
+template <int NV, typename ZT, typename XT>
+__global__ void __launch_bounds__(kBlock) k_lrn_out(int n, const float *__restrict__ h3,
+                                                    const float *__restrict__ W_out,
+                                                    const float *__restrict__ r,
+                                                    const float *__restrict__ s_ptr, int ip,
+                                                    int iT, const XT *__restrict__ dp,
+                                                    const XT *__restrict__ dT,
+                                                    const ApplySlots *__restrict__ slots,
+                                                    double *__restrict__ z2_out) {
+  const int t = blockIdx.x * kBlock + threadIdx.x;
+  const int i = t / NV, k = t - i * NV;
+  if (i >= n) return;
+  const float s = s_ptr[k];
+  float acc = 0.f;
+  const float *hp = h3 + (size_t)i * kHid;
+#pragma unroll 8
+  for (int c = 0; c < kHid; c++) acc += W_out[k * kHid + c] * hp[c];
+  float z = r[t] + s * acc;
+  if (z2_out) {
+    z2_out[t] = z;
+    return;
+  }
+  if (dp && k == ip) z += float(dp[i]);
+  if (dT && k == iT) z += float(dT[i]);
+  reinterpret_cast<ZT *>(slots->z)[t] = ZT(z);
+}
+
+// ---------------------------------------------------------------------------
+// training
+// ---------------------------------------------------------------------------
+// y = A^T x for FP64 BSR with a structurally symmetric pattern; tpos[k] is the
+// position of block (j, i) for the block (i, j) stored at k.  One thread per
+// (block row, component).
+template <int NV>
+__global__ void __launch_bounds__(kBlock) k_bsr_spmv_t(int n, const int *__restrict__ rp,
+                                                       const int *__restrict__ ci,
+                                                       const int *__restrict__ tpos,
+                                                       const double *__restrict__ vals,
+                                                       const double *__restrict__ x,
+                                                       double *__restrict__ y) {
+  const int t = blockIdx.x * kBlock + threadIdx.x;
+  const int j = t / NV, c = t - j * NV;
+  if (j >= n) return;
+  double acc = 0.0;
+  for (int k = rp[j]; k < rp[j + 1]; k++) {
+    const int i = ci[k];
+    const double *blk = vals + (size_t)tpos[k] * NV * NV;  // block (i, j)
+#pragma unroll
+    for (int r = 0; r < NV; r++) acc += blk[r * NV + c] * x[(size_t)i * NV + r];
+  }
+  y[t] = acc;
+}
+
+// dout = s * scale * dz;  dh3 = W_out^T dout;  partial dW_out (per workgroup)
+template <int NV>
+__global__ void __launch_bounds__(kBlock) k_lrn_out_bwd(int n, const double *__restrict__ dz,
+                                                        double scale, const float *__restrict__ s_ptr,
+                                                        const float *__restrict__ W_out,
+                                                        const float *__restrict__ h3,
+                                                        float *__restrict__ dh3,
+                                                        float *__restrict__ part) {
+  // thread = (cell, hidden unit); partial dW_out[k][c] over the cells of the block
+  __shared__ float red[kBlock / kHid][NV][kHid];
+  const int t = blockIdx.x * kBlock + threadIdx.x;
+  const int i = t / kHid, c = t % kHid;
+  float dout[NV];
+  float acc = 0.f;
+  const bool live = i < n;
+#pragma unroll
+  for (int k = 0; k < NV; k++) {
+    dout[k] = live ? float(scale * dz[(size_t)i * NV + k]) * s_ptr[k] : 0.f;
+    acc += W_out[k * kHid + c] * dout[k];
+  }
+  const float hv = live ? h3[(size_t)i * kHid + c] : 0.f;
+  if (live) dh3[(size_t)i * kHid + c] = acc;
+  const int slot = threadIdx.x / kHid;
+#pragma unroll
+  for (int k = 0; k < NV; k++) red[slot][k][c] = dout[k] * hv;
+  __syncthreads();
+  if (threadIdx.x < kHid) {
+#pragma unroll
+    for (int k = 0; k < NV; k++) {
+      float sum = 0.f;
+      for (int q = 0; q < kBlock / kHid; q++) sum += red[q][k][threadIdx.x];
+      part[(size_t)blockIdx.x * NV * kHid + k * kHid + threadIdx.x] = sum;
+    }
+  }
+}
+
+// Per layer, first backward pass (one wave per 16-cell tile, grid-stride):
+//   da = dh * [a > 0];  dm = da W_m;  dh_own = dh + da W_s
+//   dW_s += da^T h, dW_m += da^T m, db += sum da, dW_e += sum_d (dm * h_nbr)^T E_d
+// The weight-gradient partials of every wave go to `part` (reduced later in a
+// fixed order).  W_sT / W_mT are the transposes in BF16.
+template <int NV>
+__global__ void __launch_bounds__(kBlock) k_lrn_layer_bwd1(
+    int n, int ntiles, const int *__restrict__ nbr, const short *__restrict__ E,
+    const float *__restrict__ s_ptr,
+    const float *__restrict__ hprev, const float *__restrict__ m, const float *__restrict__ a,
+    const float *__restrict__ dh, const short *__restrict__ W_sT, const short *__restrict__ W_mT,
+    float *__restrict__ dm_out, float *__restrict__ dh_own, float *__restrict__ part) {
+  __shared__ float sda[kBlock / 64][16][kHid + 4];
+  __shared__ float sdm[kBlock / 64][16][kHid + 4];
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int lr = l & 15, lg = l >> 4;
+  f32x4 gWs[4][4], gWm[4][4], gWe[4];
+  float gb[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int x = 0; x < 4; x++) {
+    gWe[x] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int y = 0; y < 4; y++) gWs[x][y] = gWm[x][y] = f32x4{0.f, 0.f, 0.f, 0.f};
+  }
+  const int wave_id = blockIdx.x * (kBlock / 64) + w;
+  // every wave of a workgroup runs the same number of iterations (the loop
+  // holds workgroup barriers); tiles past the end are all-padding tiles
+  for (int base = blockIdx.x * (kBlock / 64); base < ntiles; base += gridDim.x * (kBlock / 64)) {
+    const int tile = base + w;
+    const int c0 = tile * 16;
+    const int ca = c0 + lr;
+    // da in A layout (rows = cells) and into LDS
+    f32x4 dmacc[4], dhacc[4];
+#pragma unroll
+    for (int t = 0; t < 4; t++) dmacc[t] = dhacc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ks = 0; ks < 4; ks++) {
+      const int k0 = 16 * ks + 4 * lg;
+      float v[4] = {0.f, 0.f, 0.f, 0.f};
+      if (ca < n) {
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+          const size_t o = (size_t)ca * kHid + k0 + q;
+          v[q] = a[o] > 0.f ? dh[o] : 0.f;
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 4; q++) sda[w][lr][k0 + q] = v[q];
+      const bf16x4 dav = cvt4(v[0], v[1], v[2], v[3]);
+#pragma unroll
+      for (int t = 0; t < 4; t++) {
+        dmacc[t] = mfma16(dav, load_bf4(W_mT + (lr + 16 * t) * kHid + k0), dmacc[t]);
+        dhacc[t] = mfma16(dav, load_bf4(W_sT + (lr + 16 * t) * kHid + k0), dhacc[t]);
+      }
+    }
+    // outputs in D layout; dm also into LDS
+#pragma unroll
+    for (int t = 0; t < 4; t++)
+#pragma unroll
+      for (int q = 0; q < 4; q++) {
+        const int cell = c0 + 4 * lg + q, col = lr + 16 * t;
+        sdm[w][4 * lg + q][col] = dmacc[t][q];
+        if (cell < n) {
+          const size_t o = (size_t)cell * kHid + col;
+          dm_out[o] = dmacc[t][q];
+          dh_own[o] = dh[o] + dhacc[t][q];
+        }
+      }
+    __syncthreads();
+    // weight gradients, cells as the reduction dimension:
+    //   A[c][cell] = da[cell][c] (lane: c = lr + 16 mt, cell = 4 lg + q)
+    //   B[cell][k] = h[cell][k] or m[cell][k] (lane: cell = 4 lg + q, k = lr + 16 nt)
+#pragma unroll
+    for (int mt = 0; mt < 4; mt++) {
+      const bf16x4 A = cvt4(sda[w][4 * lg + 0][lr + 16 * mt], sda[w][4 * lg + 1][lr + 16 * mt],
+                            sda[w][4 * lg + 2][lr + 16 * mt], sda[w][4 * lg + 3][lr + 16 * mt]);
+      gb[mt] += sda[w][4 * lg + 0][lr + 16 * mt] + sda[w][4 * lg + 1][lr + 16 * mt] +
+                sda[w][4 * lg + 2][lr + 16 * mt] + sda[w][4 * lg + 3][lr + 16 * mt];
+#pragma unroll
+      for (int nt = 0; nt < 4; nt++) {
+        float hb[4], mb[4];
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+          const int cell = c0 + 4 * lg + q;
+          const size_t o = (size_t)cell * kHid + lr + 16 * nt;
+          hb[q] = cell < n ? hprev[o] : 0.f;
+          mb[q] = cell < n ? m[o] : 0.f;
+        }
+        gWs[mt][nt] = mfma16(A, cvt4(hb[0], hb[1], hb[2], hb[3]), gWs[mt][nt]);
+        gWm[mt][nt] = mfma16(A, cvt4(mb[0], mb[1], mb[2], mb[3]), gWm[mt][nt]);
+      }
+    }
+    // dW_e[c][e] += sum_{cell,d} dm[cell][c] h[nbr(cell,d)][c] E[cell][d][e]
+    for (int d = 0; d < kDir; d++) {
+      int nb[4];
+#pragma unroll
+      for (int q = 0; q < 4; q++) {
+        const int cell = c0 + 4 * lg + q;
+        nb[q] = cell < n ? nbr[(size_t)cell * kDir + d] : -1;
+      }
+      // B[cell][e] = E[cell][d][e]: lane cell = 4 lg + q, e = lr
+      float eb[4];
+      const float ef = edge_factor<NV>(lr, s_ptr);
+#pragma unroll
+      for (int q = 0; q < 4; q++) {
+        const int cell = c0 + 4 * lg + q;
+        eb[q] = cell < n ? ef * __uint_as_float(uint32_t((unsigned short)E[((size_t)cell * kDir + d) * kEdge + lr]) << 16) : 0.f;
+      }
+      const bf16x4 B = cvt4(eb[0], eb[1], eb[2], eb[3]);
+#pragma unroll
+      for (int mt = 0; mt < 4; mt++) {
+        float av[4];
+#pragma unroll
+        for (int q = 0; q < 4; q++)
+          av[q] = nb[q] >= 0 ? sdm[w][4 * lg + q][lr + 16 * mt] * hprev[(size_t)nb[q] * kHid + lr + 16 * mt]
+                             : 0.f;
+        gWe[mt] = mfma16(cvt4(av[0], av[1], av[2], av[3]), B, gWe[mt]);
+      }
+    }
+    __syncthreads();
+  }
+  // per-wave partials: [W_s 64x64 | W_m 64x64 | W_e 64x16 | b 64]
+  constexpr int P = 2 * kHid * kHid + kHid * kEdge + kHid;
+  float *out = part + (size_t)wave_id * P;
+#pragma unroll
+  for (int mt = 0; mt < 4; mt++)
+#pragma unroll
+    for (int nt = 0; nt < 4; nt++)
+#pragma unroll
+      for (int q = 0; q < 4; q++) {
+        const int row = 16 * mt + 4 * lg + q, col = 16 * nt + lr;
+        out[row * kHid + col] = gWs[mt][nt][q];
+        out[kHid * kHid + row * kHid + col] = gWm[mt][nt][q];
+      }
+#pragma unroll
+  for (int mt = 0; mt < 4; mt++)
+#pragma unroll
+    for (int q = 0; q < 4; q++) out[2 * kHid * kHid + (16 * mt + 4 * lg + q) * kEdge + lr] = gWe[mt][q];
+  // db: lanes with the same lr hold partial sums of column lr + 16 mt over their 4 cells
+#pragma unroll
+  for (int mt = 0; mt < 4; mt++) {
+    float v = gb[mt];
+    v += __shfl_xor(v, 16, 64);
+    v += __shfl_xor(v, 32, 64);
+    if (lg == 0) out[2 * kHid * kHid + kHid * kEdge + lr + 16 * mt] = v;
+  }
+}
+
+// Per layer, second backward pass: dh_prev_j = dh_own_j + sum over the
+// neighbours i of j, with j = nbr(i, d), of dm_i * (W_e e_{i,d}).
+// nbr_opp(j, d) = i with nbr(i, d) = j (the neighbour in the opposite direction).
+template <int NV>
+__global__ void __launch_bounds__(kBlock) k_lrn_layer_bwd2(int n, const int *__restrict__ nbr,
+                                                           const short *__restrict__ E,
+                                                           const float *__restrict__ s_ptr,
+                                                           const short *__restrict__ W_e16,
+                                                           const float *__restrict__ dm,
+                                                           const float *__restrict__ dh_own,
+                                                           float *__restrict__ dh_prev) {
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int lr = l & 15, lg = l >> 4;
+  const int c0 = (blockIdx.x * (kBlock / 64) + w) * 16;
+  f32x4 acc[4];
+#pragma unroll
+  for (int t = 0; t < 4; t++) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int d = 0; d < kDir; d++) {
+    const int od = d ^ 1;  // opposite direction
+    // A row (lane lr): edge features of i = nbr(cell, od) in direction d
+    const int cell_a = c0 + lr;
+    const int ia = cell_a < n ? nbr[(size_t)cell_a * kDir + od] : -1;
+    bf16x4 ea = bf16x4{0, 0, 0, 0};
+    if (ia >= 0) ea = scale_edge4<NV>(load_bf4(E + ((size_t)ia * kDir + d) * kEdge + 4 * lg), 4 * lg, s_ptr);
+    int ib[4];
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+      const int cell = c0 + 4 * lg + q;
+      ib[q] = cell < n ? nbr[(size_t)cell * kDir + od] : -1;
+    }
+#pragma unroll
+    for (int t = 0; t < 4; t++) {
+      const f32x4 g = mfma16(ea, load_bf4(W_e16 + (lr + 16 * t) * kEdge + 4 * lg), f32x4{0.f, 0.f, 0.f, 0.f});
+#pragma unroll
+      for (int q = 0; q < 4; q++)
+        if (ib[q] >= 0) acc[t][q] += g[q] * dm[(size_t)ib[q] * kHid + lr + 16 * t];
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < 4; t++)
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+      const int cell = c0 + 4 * lg + q;
+      if (cell >= n) continue;
+      const size_t o = (size_t)cell * kHid + lr + 16 * t;
+      dh_prev[o] = dh_own[o] + acc[t][q];
+    }
+}
+
+// partial dW_in[c][k] = sum_cells dh0[cell][c] * r[cell][k] / s_k (per workgroup)
+template <int NV>
+__global__ void __launch_bounds__(kBlock) k_lrn_in_bwd(int n, const float *__restrict__ dh0,
+                                                       const float *__restrict__ r,
+                                                       const float *__restrict__ s_ptr,
+                                                       float *__restrict__ part) {
+  __shared__ float red[kBlock / kHid][kHid][NV];
+  const int t = blockIdx.x * kBlock + threadIdx.x;
+  const int i = t / kHid, c = t % kHid;
+  const int slot = threadIdx.x / kHid;
+  const float g = i < n ? dh0[(size_t)i * kHid + c] : 0.f;
+#pragma unroll
+  for (int k = 0; k < NV; k++) {
+    const float s = s_ptr[k];
+    const float inv = s > 0.f ? 1.f / s : 0.f;
+    red[slot][c][k] = i < n ? g * (r[(size_t)i * NV + k] * inv) : 0.f;
+  }
+  __syncthreads();
+  if (threadIdx.x < kHid) {
+#pragma unroll
+    for (int k = 0; k < NV; k++) {
+      float sum = 0.f;
+      for (int q = 0; q < kBlock / kHid; q++) sum += red[q][threadIdx.x][k];
+      part[(size_t)blockIdx.x * kHid * NV + threadIdx.x * NV + k] = sum;
+    }
+  }
+}
+
+// out[e] (+)= sum_p part[p][e], fixed order over p
+__global__ void __launch_bounds__(kBlock) k_sum_partials(const float *__restrict__ part, int np,
+                                                         int len, float *__restrict__ out,
+                                                         int accumulate) {
+  const int e = blockIdx.x * kBlock + threadIdx.x;
+  if (e >= len) return;
+  float s = 0.f;
+  for (int p = 0; p < np; p++) s += part[(size_t)p * len + e];
+  out[e] = accumulate ? out[e] + s : s;
+}
+
+// Adam step on the FP32 master weights (gradient already averaged)
+__global__ void __launch_bounds__(kBlock) k_adam(int np, float *__restrict__ theta,
+                                                 const float *__restrict__ grad,
+                                                 float *__restrict__ m, float *__restrict__ v,
+                                                 float lr, float b1, float b2, float eps,
+                                                 float c1, float c2) {
+  const int e = blockIdx.x * kBlock + threadIdx.x;
+  if (e >= np) return;
+  const float g = grad[e];
+  const float mm = b1 * m[e] + (1.f - b1) * g;
+  const float vv = b2 * v[e] + (1.f - b2) * g * g;
+  m[e] = mm;
+  v[e] = vv;
+  theta[e] -= lr * (mm / c1) / (sqrtf(vv / c2) + eps);
+}
+
+// BF16 operands from the FP32 master weights: per layer W_e (64 x 16, padded),
+// W_s, W_m and their transposes.
+template <int NV>
+__global__ void __launch_bounds__(kBlock) k_lrn_pack(const float *__restrict__ theta,
+                                                     short *__restrict__ packed) {
+  constexpr int NIN = kHid * NV;
+  constexpr int NL = kHid * NV * NV + 2 * kHid * kHid + kHid;
+  constexpr int PL = kHid * kEdge + 4 * kHid * kHid;  // packed floats per layer
+  const int e = blockIdx.x * kBlock + threadIdx.x;
+  if (e >= 3 * PL) return;
+  const int layer = e / PL, o = e % PL;
+  const float *L = theta + NIN + layer * NL;
+  float v;
+  if (o < kHid * kEdge) {
+    const int c = o / kEdge, k = o % kEdge;
+    v = k < NV * NV ? L[c * NV * NV + k] : 0.f;
+  } else {
+    const int q = o - kHid * kEdge, which = q / (kHid * kHid), p = q % (kHid * kHid);
+    const int row = p / kHid, col = p % kHid;
+    const float *Ws = L + kHid * NV * NV, *Wm = Ws + kHid * kHid;
+    switch (which) {
+      case 0: v = Ws[row * kHid + col]; break;
+      case 1: v = Wm[row * kHid + col]; break;
+      case 2: v = Ws[col * kHid + row]; break;
+      default: v = Wm[col * kHid + row]; break;
+    }
+  }
+  packed[e] = f2bf(v);
+}
+
+// grad_layer[e] += sum over waves of the layer partials, mapped from the
+// partial layout [W_s | W_m | W_e (64 x 16) | b] to the parameter layout
+// [W_e (64 x nv^2) | W_s | W_m | b]
+template <int NV>
+__global__ void __launch_bounds__(kBlock) k_lrn_reduce_layer(const float *__restrict__ part, int nw,
+                                                             float *__restrict__ grad) {
+  constexpr int NE = kHid * NV * NV, P = 2 * kHid * kHid + kHid * kEdge + kHid;
+  const int e = blockIdx.x * kBlock + threadIdx.x;
+  if (e >= NE + 2 * kHid * kHid + kHid) return;
+  int src;
+  if (e < NE) src = 2 * kHid * kHid + (e / (NV * NV)) * kEdge + e % (NV * NV);
+  else if (e < NE + 2 * kHid * kHid) src = e - NE;
+  else src = 2 * kHid * kHid + kHid * kEdge + (e - NE - 2 * kHid * kHid);
+  float s = 0.f;
+  for (int w = 0; w < nw; w++) s += part[(size_t)w * P + src];
+  grad[e] += s;
+}
+
+}  // namespace cptr

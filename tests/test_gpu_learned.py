@@ -1,0 +1,198 @@
+"""GPU checks of the learned second stage against the FP64 oracle
+(oracle/learned.py), through the C ABI.
+
+Tolerances: the GPU stage rounds its MFMA operands (activations, messages,
+edge features, weights) to BF16 (8-bit mantissa, relative rounding 2^-9 ~
+2e-3) and accumulates in FP32; three layers compound this, so forward outputs
+are checked at 2e-2 in the relative 2-norm and gradients at 5e-2; quantities
+that involve no BF16 operand (W_out = 0, block Jacobi) at FP32 accuracy.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import learned as OL  # noqa: E402
+from oracle import oracle as O  # noqa: E402
+from paper_1907_04229_amd import cptr  # noqa: E402
+from paper_1907_04229_amd.learned import train, training_pairs  # noqa: E402
+from paper_1907_04229_amd.learned_init import init_params, neumann_params  # noqa: E402
+from paper_1907_04229_amd.synth import make_problem  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+CASES = {
+    "nv3": dict(shape=(9, 7, 5), kind="gaussian", sigma=1.5, corr_len=3.0, seed=41),
+    "nv4": dict(shape=(8, 6, 5), kind="gaussian", sigma=1.5, corr_len=3.0, seed=42, three_phase=True),
+}
+_cache = {}
+
+
+def case(name):
+    if name not in _cache:
+        pr = make_problem(**CASES[name])
+        nbr = OL.neighbors(pr.row_ptr, pr.col_idx, pr.n)
+        dinv, E = OL.edge_features(pr.row_ptr, pr.col_idx, pr.vals, pr.nv, nbr)
+        A = OL.bsr_dense(pr.row_ptr, pr.col_idx, pr.vals, pr.nv)
+        _cache[name] = (pr, nbr, dinv, E, A)
+    return _cache[name]
+
+
+def banner(msg):
+    print(f"\n[gpu-learned] {msg}", flush=True)
+
+
+def rel2(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(b))
+
+
+def solver_with(pr, theta, **kw):
+    s = cptr.Solver(pr, device=DEV, **kw)
+    m = cptr.LearnModel(pr.nv, theta)
+    m.attach(s)
+    return s, m
+
+
+@pytest.mark.parametrize("name", ["nv3", "nv4"])
+def test_forward_matches_oracle(name):
+    banner(f"forward {name}")
+    pr, nbr, dinv, E, A = case(name)
+    theta = init_params(pr.nv, seed=5, out_scale=0.3)
+    s, m = solver_with(pr, theta)
+    b1 = np.random.default_rng(6).standard_normal(pr.n * pr.nv)
+    z = cptr.cptr_learn_forward(s, torch.as_tensor(b1, device=DEV)).cpu().numpy()
+    zo, _ = OL.forward(theta.astype(np.float64), b1, dinv, E, nbr, pr.nv)
+    err = rel2(z, zo)
+    print(f"forward rel err {err:.2e}")
+    assert err <= 2e-2
+    # the Neumann-series initialisation
+    thn = neumann_params(pr.nv, seed=3)
+    m.set_params(thn)
+    zn = cptr.cptr_learn_forward(s, torch.as_tensor(b1, device=DEV)).cpu().numpy()
+    zno, _ = OL.forward(thn.astype(np.float64), b1, dinv, E, nbr, pr.nv)
+    print(f"neumann forward rel err {rel2(zn, zno):.2e}")
+    assert rel2(zn, zno) <= 2e-2
+    # W_out = 0: block Jacobi, no BF16 operand involved
+    theta0 = init_params(pr.nv, seed=5, out_scale=0.0)
+    m.set_params(theta0)
+    z0 = cptr.cptr_learn_forward(s, torch.as_tensor(b1, device=DEV)).cpu().numpy()
+    want = np.einsum("irc,ic->ir", dinv, b1.reshape(-1, pr.nv)).reshape(-1)
+    assert rel2(z0, want) <= 1e-6
+    # positive homogeneity: exact for a power of two (every rounding scales
+    # with it); for 7.5 the FP32 scale factors differ in the last bits, which
+    # can move a BF16 operand across a rounding boundary (2^-8 relative)
+    m.set_params(theta)
+    z8 = cptr.cptr_learn_forward(s, torch.as_tensor(8.0 * b1, device=DEV)).cpu().numpy()
+    assert rel2(z8, 8.0 * z) <= 1e-12
+    z7 = cptr.cptr_learn_forward(s, torch.as_tensor(7.5 * b1, device=DEV)).cpu().numpy()
+    print(f"homogeneity (7.5) rel err {rel2(z7, 7.5 * z):.2e}")
+    assert rel2(z7, 7.5 * z) <= 1e-3
+    s.close()
+
+
+@pytest.mark.parametrize("name", ["nv3", "nv4"])
+def test_gradient_matches_oracle(name):
+    banner(f"gradient {name}")
+    pr, nbr, dinv, E, A = case(name)
+    theta = init_params(pr.nv, seed=7, out_scale=0.2)
+    theta[theta.size // 2] += 0.05
+    s, m = solver_with(pr, theta)
+    rng = np.random.default_rng(8)
+    b1s = rng.standard_normal((2, pr.n * pr.nv))
+    loss, g = cptr.cptr_learn_grad(s, torch.as_tensor(b1s, device=DEV))
+    lo, go = 0.0, np.zeros(theta.size)
+    for b1 in b1s:
+        l1, g1 = OL.loss_and_grad(theta.astype(np.float64), b1, A, dinv, E, nbr, pr.nv)
+        lo += l1 / 2
+        go += g1 / 2
+    p = OL.unflatten(np.arange(theta.size), pr.nv)
+    print(f"loss gpu {loss:.6f} oracle {lo:.6f}; gradient rel err {rel2(g, go):.2e}")
+    assert abs(loss - lo) <= 4e-2 * abs(lo)   # quadratic in the forward output
+    assert rel2(g, go) <= 5e-2
+    for key in ("W_in", "W_out", "W_s0", "W_m2", "W_e1", "b2"):
+        idx = p[key].reshape(-1).astype(int)
+        e = rel2(g[idx], go[idx])
+        print(f"  {key}: rel err {e:.2e}")
+        assert e <= 1e-1
+    s.close()
+
+
+def test_training_reduces_loss():
+    """Full-batch Adam steps at a small learning rate lower the full-batch loss."""
+    banner("training")
+    pr = make_problem(shape=(16, 16, 8), kind="gaussian", sigma=2.0, corr_len=4.0, seed=100)
+    s, m = solver_with(pr, neumann_params(pr.nv, seed=1), precision="fp32", second_stage="bilu0_mc")
+    data = training_pairs(s, 8, seed=11)
+    l0, _ = cptr.cptr_learn_grad(s, data, want_grad=False)
+    losses = [cptr.cptr_learn_train_step(s, data, 1e-5) for _ in range(40)]
+    l1, _ = cptr.cptr_learn_grad(s, data, want_grad=False)
+    print(f"full-batch loss {l0:.5f} -> {l1:.5f}")
+    assert np.all(np.isfinite(losses))
+    assert abs(losses[0] - l0) <= 1e-3 * l0      # the first step sees the initial weights
+    assert l1 < l0
+    s.close()
+
+
+def _fgmres_iters(pr, **kw):
+    s = cptr.Solver(pr, device=DEV, **{"precision": "fp32", **kw})
+    x, info = s.solve(torch.as_tensor(pr.b, device=DEV), restart=30, rtol=1e-6)
+    s.close()
+    assert info["converged"] and info["relres_true"] <= 1e-6
+    return info["iters"]
+
+
+def _learned_iters(pr, theta):
+    s, m = solver_with(pr, theta, precision="fp32", second_stage="learned")
+    x, info = s.solve(torch.as_tensor(pr.b, device=DEV), restart=30, rtol=1e-6)
+    s.close()
+    m.close()
+    assert info["converged"] and info["relres_true"] <= 1e-6
+    return info["iters"], bool(info["fell_back"])
+
+
+def test_gain_on_held_out_seeds():
+    """What training gains: FGMRES(30) iterations to 1e-6 on held-out seeds for
+    the trained network, its two initialisations and the BILU(0) stages."""
+    banner("gain test")
+    kw = dict(shape=(20, 20, 10), kind="gaussian", sigma=2.0, corr_len=4.0)
+    train_probs = [make_problem(seed=s, **kw) for s in (110, 111)]
+    model, hist = train(train_probs, 3, steps=100, batch=4, pairs=16, lr=1e-5, seed=1,
+                        precision="fp32", second_stage="bilu0_mc")
+    theta = model.params()
+    model.close()
+    print("validation losses", [(k, round(v, 5)) for k, v in hist["val"]], "kept step", hist["best_step"])
+    assert hist["val"][0][1] >= min(v for _, v in hist["val"])
+    for seed in (120, 121):
+        pr = make_problem(seed=seed, **kw)
+        jac, jf = _learned_iters(pr, init_params(3, seed=1))
+        neu, nf = _learned_iters(pr, neumann_params(3, seed=1))
+        trn, tf = _learned_iters(pr, theta)
+        ilu = _fgmres_iters(pr, second_stage="bilu0")
+        mc = _fgmres_iters(pr, second_stage="bilu0_mc")
+        print(f"seed {seed}: iterations block-Jacobi {jac}, Neumann init {neu}, trained {trn} "
+              f"(fell back {tf}); BILU(0) natural {ilu}, multicolour {mc}")
+        assert not tf and not nf
+        assert trn < jac
+        assert trn <= neu + 2
+
+
+def test_learned_stage_in_fgmres_and_fallback():
+    banner("fgmres with the learned stage")
+    pr = make_problem(shape=(16, 16, 8), kind="gaussian", sigma=2.0, corr_len=4.0, seed=101)
+    theta = init_params(pr.nv, seed=2, out_scale=0.05)
+    s, m = solver_with(pr, theta, precision="fp32", second_stage="learned")
+    x, info = s.solve(torch.as_tensor(pr.b, device=DEV), restart=30, rtol=1e-6)
+    xo, io = O.Oracle.from_problem(pr, first="cptr", second="bilu0_mc").fgmres(pr.b, m=30, rtol=1e-6)
+    err = rel2(x.cpu().numpy(), xo)
+    print(f"learned: iters {info['iters']} fell_back {info['fell_back']} relres "
+          f"{info['relres_true']:.2e}, error vs oracle {err:.2e}")
+    assert info["converged"] and info["relres_true"] <= 1e-6
+    # a broken network (non-finite output) falls back to BILU(0) and still converges
+    bad = theta.copy()
+    bad[-1] = np.nan
+    m.set_params(bad)
+    x, info = s.solve(torch.as_tensor(pr.b, device=DEV), restart=30, rtol=1e-6)
+    print(f"NaN weights: iters {info['iters']} fell_back {info['fell_back']}")
+    assert info["fell_back"] and info["converged"] and info["relres_true"] <= 1e-6
+    s.close()

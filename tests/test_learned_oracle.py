@@ -72,3 +72,28 @@ def test_gradient_central_differences(setup):
         fd = (L.loss_and_grad(tp, b1, A, dinv, E, nbr, nv)[0]
               - L.loss_and_grad(tm, b1, A, dinv, E, nbr, nv)[0]) / (2 * h)
         assert abs(fd - g[k]) <= 1e-6 * max(1.0, abs(g).max()), (k, fd, g[k])
+
+
+def test_neumann_initialisation_is_the_series():
+    """neumann_params makes the network compute sum_k (-D^{-1} O)^k D^{-1} b1
+    (K = 3 for nv = 3, K = 2 for nv = 4), checked against the series formed
+    from the dense matrix."""
+    from paper_1907_04229_amd.learned_init import neumann_params, neumann_order
+    for kw in [dict(shape=(6, 5, 4), seed=3), dict(shape=(5, 4, 3), seed=4, three_phase=True)]:
+        pr = make_problem(kind="gaussian", sigma=1.5, corr_len=3.0, **kw)
+        n, nv = pr.n, pr.nv
+        nbr = L.neighbors(pr.row_ptr, pr.col_idx, n)
+        dinv, E = L.edge_features(pr.row_ptr, pr.col_idx, pr.vals, nv, nbr)
+        A = L.bsr_dense(pr.row_ptr, pr.col_idx, pr.vals, nv)
+        Dinv = np.zeros_like(A)
+        for i in range(n):
+            Dinv[i * nv:(i + 1) * nv, i * nv:(i + 1) * nv] = dinv[i]
+        J = Dinv @ A - np.eye(n * nv)
+        b1 = np.random.default_rng(1).standard_normal(n * nv)
+        t = Dinv @ b1
+        want = t.copy()
+        for _ in range(neumann_order(nv)):
+            t = -J @ t
+            want += t
+        z, _ = L.forward(neumann_params(nv, seed=2).astype(np.float64), b1, dinv, E, nbr, nv)
+        assert np.linalg.norm(z - want) <= 1e-11 * np.linalg.norm(want)
