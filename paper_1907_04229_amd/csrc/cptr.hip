@@ -340,6 +340,7 @@ struct LearnModelDev {
   const float *bias(int l) const { return devp<float>(theta) + nin(nv) + l * nl(nv) + kHid * nv * nv + 2 * kHid * kHid; }
   const float *W_out() const { return devp<float>(theta) + nin(nv) + 3 * nl(nv); }
   const short *We16(int l) const { return devp<short>(packed) + (size_t)l * kPacked; }
+  const float *We32(int l) const { return devp<float>(theta) + nin(nv) + l * nl(nv); }
   const short *Ws(int l) const { return We16(l) + kHid * kEdge; }
   const short *Wm(int l) const { return Ws(l) + kHid * kHid; }
   const short *WsT(int l) const { return Wm(l) + kHid * kHid; }
@@ -365,7 +366,8 @@ static inline short host_bf16(float f) {
 // positions (for A^T in training), and work buffers.
 struct LearnedDev {
   int n = 0, nv = 0, nnzb = 0;
-  DevMem nbr, E, dinv, tpos, r, s, spart, hA, hB;
+  DevMem nbr, nmask, E, dinv, tpos, r, s, spart, hA, hB;
+  int stride[3] = {0, 0, 0};  // |column - row| of the neighbours along each axis
   DevMem H[4], M[3], Aa[3], dh0, dh1, dm, dhown, z2, res, dz, part;
   bool train_ready = false;
 
@@ -435,15 +437,26 @@ struct LearnedDev {
             eb[((size_t)i * kDir + d) * kEdge + r * nv + c] = host_bf16(float(acc));
           }
       }
+    // the neighbour in direction d is i -+ stride[d / 2]: a presence bit per direction
+    for (size_t a = 0; a < mags.size(); a++) stride[a] = mags[a];
+    std::vector<unsigned char> mk(n, 0);
+    for (int i = 0; i < n; i++)
+      for (int d = 0; d < kDir; d++) {
+        const int j = nb[(size_t)i * kDir + d];
+        if (j < 0) continue;
+        if (j != i + (d & 1 ? 1 : -1) * stride[d / 2]) throw Error{CPTR_ERR_UNSUPPORTED, "not a 7-point cell graph"};
+        mk[i] |= (unsigned char)(1u << d);
+      }
     upload(nbr, nb);
+    upload(nmask, mk);
     upload(E, eb);
     upload(dinv, df);
     upload(tpos, tp);
     r.alloc((size_t)n * nv * 4);
     s.alloc(4 * 4);
     spart.alloc((size_t)(nblk(n) + 1) * 4 * 8);
-    hA.alloc((size_t)n * kHid * 4);
-    hB.alloc((size_t)n * kHid * 4);
+    hA.alloc((size_t)n * kHid * 2);  // BF16 activations of the inference pass
+    hB.alloc((size_t)n * kHid * 2);
   }
 
   void ensure_train() {
@@ -467,30 +480,51 @@ struct LearnedDev {
   int ntiles() const { return (n + 15) / 16; }
   int bwd_blocks() const { return std::max(1, std::min(512, (ntiles() + 3) / 4)); }
 
-  // h3 and friends from b1 (type BT); with `store`, the intermediate values of
-  // the backward pass are kept (training)
-  template <int NV, typename BT>
-  void forward(hipStream_t st, const LearnModelDev &mdl, const BT *b1, bool store) {
+  // The network on b1 (type BT), finished by the read-out `out`; with `store`,
+  // the intermediate values of the backward pass are kept (training).
+  template <int NV, typename BT, typename ZT, typename XT>
+  void forward(hipStream_t st, const LearnModelDev &mdl, const BT *b1, bool store, LrnOut<ZT, XT> out) {
     const int nb = nblk(n);
     hipLaunchKernelGGL((k_lrn_input<NV, BT>), dim3(nb), dim3(kBlock), 0, st, n, devp<float>(dinv), b1,
                        devp<float>(r), devp<double>(spart));
     hipLaunchKernelGGL((k_lrn_scale<NV>), dim3(NV), dim3(kBlock), 0, st, (const double *)devp<double>(spart),
                        nb, double(n), devp<float>(s));
-    float *h0 = store ? devp<float>(H[0]) : devp<float>(hA);
-    hipLaunchKernelGGL((k_lrn_h0<NV>), dim3(nblk((size_t)n * kHid)), dim3(kBlock), 0, st, n,
-                       (const float *)devp<float>(r), (const float *)devp<float>(s), mdl.W_in(), h0);
     LAUNCH_CHECK();
-    const int lb = (ntiles() + 3) / 4;
-    for (int l = 0; l < 3; l++) {
-      const float *hin = store ? devp<float>(H[l]) : (l % 2 == 0 ? devp<float>(hA) : devp<float>(hB));
-      float *hout = store ? devp<float>(H[l + 1]) : (l % 2 == 0 ? devp<float>(hB) : devp<float>(hA));
-      hipLaunchKernelGGL((k_lrn_layer<NV>), dim3(lb), dim3(kBlock), 0, st, n, (const int *)devp<int>(nbr),
-                         (const short *)devp<short>(E), (const float *)devp<float>(s), hin, mdl.We16(l), mdl.Ws(l), mdl.Wm(l), mdl.bias(l), hout,
-                         store ? devp<float>(M[l]) : (float *)nullptr, store ? devp<float>(Aa[l]) : (float *)nullptr);
-      LAUNCH_CHECK();
+    const int lb = std::max(1, std::min(kLayerMaxBlocks, (ntiles() + 3) / 4));
+    const unsigned char *nbp = devp<unsigned char>(nmask);
+    const int3 str = make_int3(stride[0], stride[1], stride[2]);
+    const short *Ep = devp<short>(E);
+    const float *sp = devp<float>(s), *rp_ = devp<float>(r);
+    const LrnOut<float, float> none{nullptr, 0, 0, nullptr, nullptr, nullptr, nullptr};
+    if (store) {
+      // training: FP32 activations, everything the backward pass reads is kept
+      hipLaunchKernelGGL((k_lrn_layer<NV, true, false, float, float, float>), dim3(lb), dim3(kBlock), 0, st, n,
+                         nbp, str, Ep, sp, (const float *)nullptr, rp_, mdl.W_in(), mdl.We32(0), mdl.Ws(0), mdl.Wm(0),
+                         mdl.bias(0), devp<float>(H[1]), devp<float>(H[0]), devp<float>(M[0]), devp<float>(Aa[0]),
+                         none);
+      hipLaunchKernelGGL((k_lrn_layer<NV, false, false, float, float, float>), dim3(lb), dim3(kBlock), 0, st, n,
+                         nbp, str, Ep, sp, (const float *)devp<float>(H[1]), rp_, mdl.W_in(), mdl.We32(1), mdl.Ws(1),
+                         mdl.Wm(1), mdl.bias(1), devp<float>(H[2]), (float *)nullptr, devp<float>(M[1]),
+                         devp<float>(Aa[1]), none);
+      hipLaunchKernelGGL((k_lrn_layer<NV, false, true, float, ZT, XT>), dim3(lb), dim3(kBlock), 0, st, n, nbp, str, Ep,
+                         sp, (const float *)devp<float>(H[2]), rp_, mdl.W_in(), mdl.We32(2), mdl.Ws(2), mdl.Wm(2),
+                         mdl.bias(2), devp<float>(H[3]), (float *)nullptr, devp<float>(M[2]), devp<float>(Aa[2]),
+                         out);
+    } else {
+      // inference: BF16 activations between the layers, nothing else kept
+      short *ha = devp<short>(hA), *hb = devp<short>(hB);
+      hipLaunchKernelGGL((k_lrn_layer<NV, true, false, short, float, float>), dim3(lb), dim3(kBlock), 0, st, n,
+                         nbp, str, Ep, sp, (const short *)nullptr, rp_, mdl.W_in(), mdl.We32(0), mdl.Ws(0), mdl.Wm(0),
+                         mdl.bias(0), ha, (float *)nullptr, (float *)nullptr, (float *)nullptr, none);
+      hipLaunchKernelGGL((k_lrn_layer<NV, false, false, short, float, float>), dim3(lb), dim3(kBlock), 0, st, n,
+                         nbp, str, Ep, sp, (const short *)ha, rp_, mdl.W_in(), mdl.We32(1), mdl.Ws(1), mdl.Wm(1),
+                         mdl.bias(1), hb, (float *)nullptr, (float *)nullptr, (float *)nullptr, none);
+      hipLaunchKernelGGL((k_lrn_layer<NV, false, true, short, ZT, XT>), dim3(lb), dim3(kBlock), 0, st, n, nbp, str, Ep,
+                         sp, (const short *)hb, rp_, mdl.W_in(), mdl.We32(2), mdl.Ws(2), mdl.Wm(2), mdl.bias(2),
+                         (short *)nullptr, (float *)nullptr, (float *)nullptr, (float *)nullptr, out);
     }
+    LAUNCH_CHECK();
   }
-  const float *h3(bool store) const { return store ? devp<float>(H[3]) : devp<float>(hB); }
 };
 
 // ---------------------------------------------------------------- preconditioner
@@ -574,11 +608,8 @@ struct Precond : PrecondBase {
     LAUNCH_CHECK();
     if (ss == CPTR_SECOND_LEARNED && !fell_back) {
       if (!model || !lrn) throw Error{CPTR_ERR_INVALID_ARG, "no learned model attached to this handle"};
-      lrn->forward<NV, T>(st, *model, b1p, false);
-      hipLaunchKernelGGL((k_lrn_out<NV, ZT, T>), dim3(nblk((size_t)n * NV)), dim3(kBlock), 0, st, n,
-                         lrn->h3(false), model->W_out(), (const float *)devp<float>(lrn->r),
-                         (const float *)devp<float>(lrn->s), op.o.ip, op.o.iT, x1p(), x1T(), slots,
-                         (double *)nullptr);
+      lrn->forward<NV, T, ZT, T>(st, *model, b1p, false,
+                                 LrnOut<ZT, T>{model->W_out(), op.o.ip, op.o.iT, x1p(), x1T(), slots, nullptr});
       LAUNCH_CHECK();
       return;
     }
@@ -1145,12 +1176,9 @@ static double learn_grad_impl(cptr_handle *h, hipStream_t st, const double *b1_a
     const double bn = fetch(h, st, scal + 2);
     if (!(bn > 0.0)) continue;
     const double bb = bn * bn;
-    L.forward<NV, double>(st, M, b1, true);
     double *z2 = devp<double>(L.z2), *res = devp<double>(L.res), *dz = devp<double>(L.dz);
-    hipLaunchKernelGGL((k_lrn_out<NV, double, double>), dim3(nblk(N)), dim3(kBlock), 0, st, n,
-                       (const float *)devp<float>(L.H[3]), M.W_out(), (const float *)devp<float>(L.r),
-                       (const float *)devp<float>(L.s), 0, 0, (const double *)nullptr, (const double *)nullptr,
-                       (const ApplySlots *)nullptr, z2);
+    L.forward<NV, double, double, double>(st, M, b1, true,
+                                          LrnOut<double, double>{M.W_out(), 0, 0, nullptr, nullptr, nullptr, z2});
     spmv<double>(h, st, z2, b1, res);
     norm2(h, st, res, N, 3);
     const double rn = fetch(h, st, scal + 3);
@@ -1525,18 +1553,9 @@ int cptr_learn_forward(cptr_handle *h, const double *b1, double *z2, void *strea
     hipStream_t st = (hipStream_t)stream;
     LearnedDev &L = *h->lrn;
     const LearnModelDev &M = h->model->dev;
-    const size_t N = (size_t)L.n * L.nv;
-    if (L.nv == 3) {
-      L.forward<3, double>(st, M, b1, false);
-      hipLaunchKernelGGL((k_lrn_out<3, double, double>), dim3(nblk(N)), dim3(kBlock), 0, st, L.n, L.h3(false),
-                         M.W_out(), (const float *)devp<float>(L.r), (const float *)devp<float>(L.s), 0, 0,
-                         (const double *)nullptr, (const double *)nullptr, (const ApplySlots *)nullptr, z2);
-    } else {
-      L.forward<4, double>(st, M, b1, false);
-      hipLaunchKernelGGL((k_lrn_out<4, double, double>), dim3(nblk(N)), dim3(kBlock), 0, st, L.n, L.h3(false),
-                         M.W_out(), (const float *)devp<float>(L.r), (const float *)devp<float>(L.s), 0, 0,
-                         (const double *)nullptr, (const double *)nullptr, (const ApplySlots *)nullptr, z2);
-    }
+    const LrnOut<double, double> out{M.W_out(), 0, 0, nullptr, nullptr, nullptr, z2};
+    if (L.nv == 3) L.forward<3, double, double, double>(st, M, b1, false, out);
+    else L.forward<4, double, double, double>(st, M, b1, false, out);
     LAUNCH_CHECK();
     return CPTR_OK;
   } catch (const Error &e) {

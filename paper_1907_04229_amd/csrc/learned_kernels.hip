@@ -28,10 +28,8 @@ constexpr int kEdge = 16;  // edge features padded to the MFMA depth (nv^2 <= 16
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ short f2bf(float f) {  // round to nearest even
-  uint32_t u = __float_as_uint(f);
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return (short)(u >> 16);
+__device__ __forceinline__ short f2bf(float f) {  // round to nearest even (v_cvt_pk_bf16_f32)
+  return __builtin_bit_cast(short, (__bf16)f);
 }
 
 __device__ __forceinline__ f32x4 mfma16(bf16x4 a, bf16x4 b, f32x4 c) {
@@ -42,13 +40,9 @@ __device__ __forceinline__ bf16x4 load_bf4(const short *p) {
   return *reinterpret_cast<const bf16x4 *>(p);
 }
 
+typedef __bf16 bf16x4_t __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ bf16x4 cvt4(float a, float b, float c, float d) {
-  bf16x4 v;
-  v[0] = f2bf(a);
-  v[1] = f2bf(b);
-  v[2] = f2bf(c);
-  v[3] = f2bf(d);
-  return v;
+  return __builtin_bit_cast(bf16x4, __builtin_convertvector((f32x4{a, b, c, d}), bf16x4_t));
 }
 
 // edge features in the scaled unknowns: e[r][c] * s_c / s_r for the four
@@ -133,132 +127,257 @@ __global__ void __launch_bounds__(kBlock) k_lrn_scale(const double *__restrict__
   }
 }
 
-// h0 = W_in u, u_k = r_k / s_k: one thread per (cell, hidden unit)
+// Read-out of the last layer: z_k = r_k + s_k (W_out h3)_k, written as the
+// FP64 vector `z2_out` when given, otherwise as z = z2 + x1 (the full
+// two-stage result, x1 holding only the p and T components dp, dT) in the
+// output type ZT through the apply slots.
+template <typename ZT, typename XT>
+struct LrnOut {
+  const float *W_out;
+  int ip, iT;
+  const XT *dp, *dT;
+  const ApplySlots *slots;
+  double *z2_out;
+};
+
+__device__ __forceinline__ f32x4 load_f4(const float *p) { return *reinterpret_cast<const f32x4 *>(p); }
+__device__ __forceinline__ void store_f4(float *p, f32x4 v) { *reinterpret_cast<f32x4 *>(p) = v; }
+__device__ __forceinline__ float bf2f(short b) { return __uint_as_float(uint32_t((unsigned short)b) << 16); }
+
+// activations in memory: FP32, or BF16 (short) where only the forward pass needs them
+__device__ __forceinline__ f32x4 load_h4(const float *p) { return load_f4(p); }
+__device__ __forceinline__ f32x4 load_h4(const short *p) {
+  const bf16x4 v = load_bf4(p);
+  return f32x4{bf2f(v[0]), bf2f(v[1]), bf2f(v[2]), bf2f(v[3])};
+}
+__device__ __forceinline__ void store_h4(float *p, f32x4 v) { store_f4(p, v); }
+__device__ __forceinline__ void store_h4(short *p, f32x4 v) {
+  *reinterpret_cast<bf16x4 *>(p) = cvt4(v[0], v[1], v[2], v[3]);
+}
+
+// Neighbour activations as loaded (before conversion): BF16 or FP32 rows of
+// the lane's 16 channels, or, for the first layer, the nv values of r from
+// which h0 = W_in (r / s) is formed.
+template <typename HT, int NV, bool FIRST>
+struct RawAct;
 template <int NV>
-__global__ void __launch_bounds__(kBlock) k_lrn_h0(int n, const float *__restrict__ r,
-                                                   const float *__restrict__ s_ptr,
-                                                   const float *__restrict__ W_in,
-                                                   float *__restrict__ h) {
-  const size_t t = (size_t)blockIdx.x * kBlock + threadIdx.x;
-  const int i = int(t / kHid), c = int(t % kHid);
-  if (i >= n) return;
-  float acc = 0.f;
+struct RawAct<short, NV, false> {
+  struct type { bf16x4 v[4]; };
+  static __device__ __forceinline__ type load(int cell, int lg, const short *h, const float *) {
+    type o;
+#pragma unroll
+    for (int t = 0; t < 4; t++) o.v[t] = load_bf4(h + (size_t)cell * kHid + 16 * t + 4 * lg);
+    return o;
+  }
+  static __device__ __forceinline__ f32x4 get(const type &o, int t, int, const float *, const float *) {
+    return f32x4{bf2f(o.v[t][0]), bf2f(o.v[t][1]), bf2f(o.v[t][2]), bf2f(o.v[t][3])};
+  }
+};
+template <int NV>
+struct RawAct<float, NV, false> {
+  struct type { f32x4 v[4]; };
+  static __device__ __forceinline__ type load(int cell, int lg, const float *h, const float *) {
+    type o;
+#pragma unroll
+    for (int t = 0; t < 4; t++) o.v[t] = load_f4(h + (size_t)cell * kHid + 16 * t + 4 * lg);
+    return o;
+  }
+  static __device__ __forceinline__ f32x4 get(const type &o, int t, int, const float *, const float *) {
+    return o.v[t];
+  }
+};
+template <typename HT, int NV>
+struct RawAct<HT, NV, true> {
+  struct type { float u[NV]; };
+  static __device__ __forceinline__ type load(int cell, int, const HT *, const float *r) {
+    type o;
+#pragma unroll
+    for (int k = 0; k < NV; k++) o.u[k] = r[(size_t)cell * NV + k];
+    return o;
+  }
+  static __device__ __forceinline__ f32x4 get(const type &o, int t, int lg, const float *W_in,
+                                              const float *inv_s) {
+    f32x4 h;
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+      const int ch = 16 * t + 4 * lg + q;
+      float v = 0.f;
+#pragma unroll
+      for (int k = 0; k < NV; k++) v += W_in[ch * NV + k] * (o.u[k] * inv_s[k]);
+      h[q] = v;
+    }
+    return h;
+  }
+};
+
+// Workgroups of the layer kernel: enough to fill the chip several times over;
+// each wave loops over tiles.
+constexpr int kLayerMaxBlocks = 2048;
+constexpr int kWPad = kHid + 4;  // LDS row of W_s / W_m (BF16), padded against bank conflicts
+
+// One message-passing layer.  One wavefront per tile of 16 consecutive cells;
+// lane l owns cell c0 + l % 16 and the hidden channels 16 t + 4 (l / 16) + q
+// (t, q = 0..3).  The weights are the MFMA A operand and the activations the
+// B operand, so every product comes out with cells along the lanes:
+//   g^T = W_e e^T (per direction),  a^T = W_s h^T + W_m m^T
+// and the messages m = sum_d g * h_nbr, accumulated in that layout, are
+// directly the B operand of W_m.  Activations are read and written as four
+// consecutive channels per lane (HT: FP32 or BF16 in memory).  W_s and W_m
+// are staged in LDS once per workgroup; W_e stays in registers.
+// FIRST: the input activations h0 = W_in (r / s) are formed on the fly for the
+//        cell and its neighbours (stored to h0_out when given).
+// LAST:  the read-out (LrnOut) is written; h_out may then be null.
+// m_out / a_out (optional) keep the messages and pre-activations for the
+// backward pass.
+template <int NV, bool FIRST, bool LAST, typename HT, typename ZT, typename XT>
+__global__ void __launch_bounds__(kBlock) k_lrn_layer(
+    int n, const unsigned char *__restrict__ nmask, int3 stride, const short *__restrict__ E,
+    const float *__restrict__ s_ptr, const HT *__restrict__ hin, const float *__restrict__ r, const float *__restrict__ W_in,
+    const float *__restrict__ W_e, const short *__restrict__ W_s, const short *__restrict__ W_m,
+    const float *__restrict__ bias, HT *__restrict__ hout, float *__restrict__ h0_out,
+    float *__restrict__ m_out, float *__restrict__ a_out, LrnOut<ZT, XT> out) {
+  __shared__ short Wl[2][kHid][kWPad];
+  for (int v = threadIdx.x; v < 2 * kHid * kHid / 4; v += kBlock) {
+    const int mtx = v / (kHid * kHid / 4), e = (v % (kHid * kHid / 4)) * 4;
+    const short *src = (mtx == 0 ? W_s : W_m) + e;
+    *reinterpret_cast<bf16x4 *>(&Wl[mtx][e / kHid][e % kHid]) = load_bf4(src);
+  }
+  __syncthreads();
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int lr = l & 15, lg = l >> 4;
+  const int ntiles = (n + 15) / 16;
+  float inv_s[NV];
 #pragma unroll
   for (int k = 0; k < NV; k++) {
-    const float s = s_ptr[k];
-    const float inv = s > 0.f ? 1.f / s : 0.f;
-    acc += W_in[c * NV + k] * (r[(size_t)i * NV + k] * inv);
+    const float sk = s_ptr[k];
+    inv_s[k] = sk > 0.f ? 1.f / sk : 0.f;
   }
-  h[t] = acc;
-}
-
-// One message-passing layer; four wavefronts per workgroup, 16 cells per wave.
-// W_e16: 64 x 16 (BF16, zero padded); W_s, W_m: 64 x 64 (BF16, row-major).
-template <int NV>
-__global__ void __launch_bounds__(kBlock) k_lrn_layer(int n, const int *__restrict__ nbr,
-                                                      const short *__restrict__ E,
-                                                      const float *__restrict__ s_ptr,
-                                                      const float *__restrict__ hin,
-                                                      const short *__restrict__ W_e16,
-                                                      const short *__restrict__ W_s,
-                                                      const short *__restrict__ W_m,
-                                                      const float *__restrict__ bias,
-                                                      float *__restrict__ hout,
-                                                      float *__restrict__ m_out,
-                                                      float *__restrict__ a_out) {
-  __shared__ float sm[kBlock / 64][16][kHid + 4];
-  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-  const int lr = l & 15, lg = l >> 4;  // lane row / lane group
-  const int c0 = (blockIdx.x * (kBlock / 64) + w) * 16;
-  // messages: m = sum_d (E_d W_e^T) * h_nbr
-  f32x4 macc[4];
-#pragma unroll
-  for (int t = 0; t < 4; t++) macc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
-  const int ca = c0 + lr;  // cell of this lane's A-operand row
-  for (int d = 0; d < kDir; d++) {
-    bf16x4 ea = bf16x4{0, 0, 0, 0};
-    if (ca < n) ea = scale_edge4<NV>(load_bf4(E + ((size_t)ca * kDir + d) * kEdge + 4 * lg), 4 * lg, s_ptr);
-    int nb[4];
-#pragma unroll
-    for (int q = 0; q < 4; q++) {
-      const int cell = c0 + 4 * lg + q;
-      nb[q] = cell < n ? nbr[(size_t)cell * kDir + d] : -1;
-    }
-#pragma unroll
-    for (int t = 0; t < 4; t++) {
-      const bf16x4 wb = load_bf4(W_e16 + (lr + 16 * t) * kEdge + 4 * lg);
-      const f32x4 g = mfma16(ea, wb, f32x4{0.f, 0.f, 0.f, 0.f});
-#pragma unroll
-      for (int q = 0; q < 4; q++)
-        if (nb[q] >= 0) macc[t][q] += g[q] * hin[(size_t)nb[q] * kHid + lr + 16 * t];
-    }
-  }
-  // layout change of m (D layout -> A layout) through LDS
-#pragma unroll
-  for (int t = 0; t < 4; t++)
-#pragma unroll
-    for (int q = 0; q < 4; q++) sm[w][4 * lg + q][lr + 16 * t] = macc[t][q];
-  __syncthreads();
-  f32x4 acc[4];
-#pragma unroll
-  for (int t = 0; t < 4; t++) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-  for (int ks = 0; ks < 4; ks++) {
-    const int k0 = 16 * ks + 4 * lg;
-    bf16x4 ha = bf16x4{0, 0, 0, 0};
-    if (ca < n) {
-      const float *hp = hin + (size_t)ca * kHid + k0;
-      ha = cvt4(hp[0], hp[1], hp[2], hp[3]);
-    }
-    const bf16x4 ma = cvt4(sm[w][lr][k0], sm[w][lr][k0 + 1], sm[w][lr][k0 + 2], sm[w][lr][k0 + 3]);
-#pragma unroll
-    for (int t = 0; t < 4; t++) {
-      acc[t] = mfma16(ha, load_bf4(W_s + (lr + 16 * t) * kHid + k0), acc[t]);
-      acc[t] = mfma16(ma, load_bf4(W_m + (lr + 16 * t) * kHid + k0), acc[t]);
-    }
-  }
+  // W_e with the edge scaling folded in: (W_e S^{-1} e S)_j = sum_k W_e[j][k] f_k e_k,
+  // f_k = s_c / s_r for k = r NV + c, so the stored edge blocks are the B operand as they are
+  bf16x4 we[4];
 #pragma unroll
   for (int t = 0; t < 4; t++)
 #pragma unroll
     for (int q = 0; q < 4; q++) {
-      const int cell = c0 + 4 * lg + q, col = lr + 16 * t;
-      if (cell >= n) continue;
-      const size_t o = (size_t)cell * kHid + col;
-      const float a = acc[t][q] + bias[col];
-      hout[o] = hin[o] + fmaxf(a, 0.f);
-      if (m_out) m_out[o] = macc[t][q];
-      if (a_out) a_out[o] = a;
+      const int k = 4 * lg + q;
+      we[t][q] = k < NV * NV ? f2bf(W_e[(16 * t + lr) * NV * NV + k] * edge_factor<NV>(k, s_ptr)) : short(0);
     }
-}
-
-// z2 = s (r / s + W_out h3) = r + s W_out h3, finished as z = z2 + x1 (the
-// second-stage result) in the output type ZT through the apply slots, or as
-// a plain FP64 vector when `z2_out` is given.
-template <int NV, typename ZT, typename XT>
-__global__ void __launch_bounds__(kBlock) k_lrn_out(int n, const float *__restrict__ h3,
-                                                    const float *__restrict__ W_out,
-                                                    const float *__restrict__ r,
-                                                    const float *__restrict__ s_ptr, int ip,
-                                                    int iT, const XT *__restrict__ dp,
-                                                    const XT *__restrict__ dT,
-                                                    const ApplySlots *__restrict__ slots,
-                                                    double *__restrict__ z2_out) {
-  const int t = blockIdx.x * kBlock + threadIdx.x;
-  const int i = t / NV, k = t - i * NV;
-  if (i >= n) return;
-  const float s = s_ptr[k];
-  float acc = 0.f;
-  const float *hp = h3 + (size_t)i * kHid;
-#pragma unroll 8
-  for (int c = 0; c < kHid; c++) acc += W_out[k * kHid + c] * hp[c];
-  float z = r[t] + s * acc;
-  if (z2_out) {
-    z2_out[t] = z;
-    return;
+  // activations of `cell` at this lane's channels (FIRST: from r)
+  auto act = [&](int cell, f32x4 *h) {
+    if constexpr (FIRST) {
+      float u[NV];
+#pragma unroll
+      for (int k = 0; k < NV; k++) u[k] = r[(size_t)cell * NV + k] * inv_s[k];
+#pragma unroll
+      for (int t = 0; t < 4; t++)
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+          const int ch = 16 * t + 4 * lg + q;
+          float v = 0.f;
+#pragma unroll
+          for (int k = 0; k < NV; k++) v += W_in[ch * NV + k] * u[k];
+          h[t][q] = v;
+        }
+    } else {
+#pragma unroll
+      for (int t = 0; t < 4; t++) h[t] = load_h4(hin + (size_t)cell * kHid + 16 * t + 4 * lg);
+    }
+  };
+  const int off[kDir] = {-stride.x, stride.x, -stride.y, stride.y, -stride.z, stride.z};
+  for (int tile = blockIdx.x * (kBlock / 64) + w; tile < ntiles; tile += gridDim.x * (kBlock / 64)) {
+    const int cell = tile * 16 + lr;
+    const bool ok = cell < n;
+    // lanes past the end read the last cell; their results are never stored
+    const int cl = ok ? cell : n - 1;
+    const unsigned mk = nmask[cl];  // bit d: neighbour cell + off[d] exists
+    f32x4 hv[4];
+    act(cl, hv);
+    // messages: all loads are issued first and consumed direction by
+    // direction.  An absent neighbour has a zero edge block, so its (any
+    // finite) activations -- the cell's own are read in its place -- add zero.
+    typename RawAct<HT, NV, FIRST>::type raw[kDir];
+    bf16x4 rawe[kDir];
+#pragma unroll
+    for (int d = 0; d < kDir; d++) {
+      rawe[d] = load_bf4(E + ((size_t)cl * kDir + d) * kEdge + 4 * lg);
+      raw[d] = RawAct<HT, NV, FIRST>::load((mk >> d) & 1u ? cl + off[d] : cl, lg, hin, r);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    f32x4 macc[4];
+#pragma unroll
+    for (int t = 0; t < 4; t++) macc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int d = 0; d < kDir; d++) {
+#pragma unroll
+      for (int t = 0; t < 4; t++) {
+        const f32x4 g = mfma16(we[t], rawe[d], f32x4{0.f, 0.f, 0.f, 0.f});
+        macc[t] += g * RawAct<HT, NV, FIRST>::get(raw[d], t, lg, W_in, inv_s);
+      }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    f32x4 acc[4];
+#pragma unroll
+    for (int t = 0; t < 4; t++) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ks = 0; ks < 4; ks++) {
+      const bf16x4 hb = cvt4(hv[ks][0], hv[ks][1], hv[ks][2], hv[ks][3]);
+      const bf16x4 mb = cvt4(macc[ks][0], macc[ks][1], macc[ks][2], macc[ks][3]);
+#pragma unroll
+      for (int t = 0; t < 4; t++) {
+        const bf16x4 ws = *reinterpret_cast<const bf16x4 *>(&Wl[0][16 * t + lr][16 * ks + 4 * lg]);
+        const bf16x4 wm = *reinterpret_cast<const bf16x4 *>(&Wl[1][16 * t + lr][16 * ks + 4 * lg]);
+        acc[t] = mfma16(ws, hb, acc[t]);
+        acc[t] = mfma16(wm, mb, acc[t]);
+      }
+    }
+    f32x4 hnew[4];
+#pragma unroll
+    for (int t = 0; t < 4; t++) {
+      f32x4 a;
+#pragma unroll
+      for (int q = 0; q < 4; q++) {
+        a[q] = acc[t][q] + bias[16 * t + 4 * lg + q];
+        hnew[t][q] = hv[t][q] + fmaxf(a[q], 0.f);
+      }
+      if (ok) {
+        const size_t o = (size_t)cell * kHid + 16 * t + 4 * lg;
+        if (hout) store_h4(hout + o, hnew[t]);
+        if (m_out) store_f4(m_out + o, macc[t]);
+        if (a_out) store_f4(a_out + o, a);
+        if (FIRST && h0_out) store_f4(h0_out + o, hv[t]);
+      }
+    }
+    if constexpr (LAST) {
+      float p[NV];
+#pragma unroll
+      for (int k = 0; k < NV; k++) {
+        float v = 0.f;
+#pragma unroll
+        for (int t = 0; t < 4; t++)
+#pragma unroll
+          for (int q = 0; q < 4; q++) v += out.W_out[k * kHid + 16 * t + 4 * lg + q] * hnew[t][q];
+        v += __shfl_xor(v, 16);
+        v += __shfl_xor(v, 32);
+        p[k] = v;
+      }
+      // lane group lg writes component k = lg of its cell
+      float pk = 0.f;
+#pragma unroll
+      for (int k = 0; k < NV; k++)
+        if (k == lg) pk = p[k];
+      if (ok && lg < NV) {
+        const size_t t = (size_t)cell * NV + lg;
+        float z = r[t] + s_ptr[lg] * pk;
+        if (out.z2_out) {
+          out.z2_out[t] = z;
+        } else {
+          if (out.dp && lg == out.ip) z += float(out.dp[cell]);
+          if (out.dT && lg == out.iT) z += float(out.dT[cell]);
+          reinterpret_cast<ZT *>(out.slots->z)[t] = ZT(z);
+        }
+      }
+    }
   }
-  if (dp && k == ip) z += float(dp[i]);
-  if (dT && k == iT) z += float(dT[i]);
-  reinterpret_cast<ZT *>(slots->z)[t] = ZT(z);
 }
 
 // ---------------------------------------------------------------------------
