@@ -1,17 +1,29 @@
 #!/usr/bin/env python
-"""Benchmark: FGMRES time-to-1e-6 and cell-iterations/s of CPTR-preconditioned
-solves of the 64x64x32 two-phase thermal Jacobian (131,072 cells, 3x3 BSR
-blocks, Gaussian ln k field, heated zone), FP32 preconditioner against FP64,
-on one MI355X.
+"""Benchmark: FGMRES time-to-1e-6 of the 128x128x64 two-phase thermal Jacobian
+(1,048,576 cells, 3x3 BSR blocks, Gaussian ln k field with correlation length
+8 cells and std 2.0) preconditioned by CPTR with the learned second stage and
+an FP32 preconditioner, against plain FP64 CPTR (AMG V-cycles and BILU(0) in
+natural order, all FP64), on one MI355X.
 
 A step is one fgmres_solve of the resident system from a zero initial guess
-to rtol 1e-6 (restriction, block preconditioner with three AMG V-cycles,
-two-stage residual, BILU(0), FP64 Arnoldi with CGS2, Givens, solution update
-and FP64 true-residual check).  The preconditioner setup is timed separately.
+to rtol 1e-6: restriction to p/T, the block preconditioner with three AMG
+V-cycles, the two-stage residual, the learned second stage (three
+message-passing layers), FP64 Arnoldi with CGS2, Givens rotations, the
+solution update and the FP64 true-residual check.  Setup and training are
+done before the timed region and reported separately.
 
-Prints one JSON line (see the keys below).
+Training (not timed): the network starts from the Neumann-series
+initialisation and is trained by the library's own kernels on FGMRES Arnoldi
+vectors of four 64x64x32 systems with other seeds of the same field model
+(the solved system is held out), keeping the parameters with the lowest
+validation loss.
+
+Prints one JSON line (keys below).  `--probe` runs only a short learned
+forward pass, the layer kernel and a plain device copy, for hardware-counter
+runs of the profiler.
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -22,18 +34,65 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "learned_layer_traffic.json")
+LAYER_SRC = os.path.join(ROOT, "paper_1907_04229_amd", "csrc", "learned_kernels.hip")
+TRAIN_SEEDS = (210, 211, 212, 213)
+TRAIN_SHAPE = (64, 64, 32)
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def kernel_roofline(pr, solver, reps=50):
-    """Average duration of the FP64 BSR product (the Arnoldi w = A z of every
-    step), timed with HIP events on the stream it is launched on, and its
-    algorithmic bytes: values + column indices + row pointers + x + y.
-    Repeated launches on one system: at 131k cells the 65 MB matrix fits the
-    256 MB last-level cache, so the figure can exceed what HBM alone gives."""
+def layer_source_hash():
+    with open(LAYER_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def recorded_traffic(cells):
+    """HBM bytes per launch of the middle layer from the committed counter
+    runs, if they were taken on the current kernel source and cell count."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_sha256") != layer_source_hash() or rec.get("cells") != cells:
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def layer_roofline(solver, reps=50):
+    """Average duration of the middle layer kernel of the learned stage
+    (k_lrn_layer, BF16 activations), timed with HIP events on the stream it is
+    launched on, against its algorithmic HBM bytes: BF16 activations read and
+    written (2 x 64 x 2 B), six BF16 edge blocks (6 x 16 x 2 B) and the
+    presence mask (1 B) per cell."""
+    import torch
+    from paper_1907_04229_amd import cptr
+    n = solver.problem.n
+    st = torch.cuda.current_stream()
+    for _ in range(3):
+        cptr.cptr_learn_rerun_layer(solver, 1, None, st)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(reps):
+        cptr.cptr_learn_rerun_layer(solver, 1, None, st)
+    e1.record(st)
+    e1.synchronize()
+    avg_s = e0.elapsed_time(e1) / reps * 1e-3
+    algo = n * (2 * 64 * 2 + 6 * 16 * 2 + 1)
+    gbs = algo / avg_s / 1e9
+    return dict(bound="hbm", achieved=round(gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=round(gbs / HBM_PEAK_GBS, 4), traffic=recorded_traffic(n),
+                kernel="k_lrn_layer<3,false,false,bf16> (message-passing layer, inference)",
+                bytes_per_launch=int(algo), avg_us=round(avg_s * 1e6, 2), launches=reps)
+
+
+def spmv_roofline(pr, solver, reps=50):
+    """FP64 BSR product y = A x (the Arnoldi w = A z of every step, on the
+    solver's sliced copy of A): average duration with HIP events, algorithmic
+    bytes = values + column indices + row pointers + x + y of the BSR matrix."""
     import torch
     from paper_1907_04229_amd import cptr
     n, nv = pr.n, pr.nv
@@ -41,30 +100,27 @@ def kernel_roofline(pr, solver, reps=50):
     y = torch.empty_like(x)
     st = torch.cuda.current_stream()
     for _ in range(5):
-        cptr.cptr_bsr_spmv(n, nv, solver.rp, solver.ci, solver.vals, x, y, st)
+        cptr.cptr_matvec(solver.h, x, y, st)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(st)
     for _ in range(reps):
-        cptr.cptr_bsr_spmv(n, nv, solver.rp, solver.ci, solver.vals, x, y, st)
+        cptr.cptr_matvec(solver.h, x, y, st)
     e1.record(st)
     e1.synchronize()
     avg_s = e0.elapsed_time(e1) / reps * 1e-3
-    nnzb = pr.nnzb
-    algo = nnzb * (nv * nv * 8 + 4) + 4 * (n + 1) + 2 * 8 * n * nv
+    algo = pr.nnzb * (nv * nv * 8 + 4) + 4 * (n + 1) + 2 * 8 * n * nv
     gbs = algo / avg_s / 1e9
-    return dict(bound="hbm", achieved=round(gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                frac=round(gbs / HBM_PEAK_GBS, 4), traffic=None,
-                kernel=f"k_bsr_spmv<{nv},double> (FP64 BSR y = A x)",
-                bytes_per_launch=int(algo), avg_us=round(avg_s * 1e6, 2))
+    return dict(kernel=f"k_bsr_spmv_sliced<{nv},double>", achieved=round(gbs, 1), unit="GB/s",
+                frac=round(gbs / HBM_PEAK_GBS, 4), bytes_per_launch=int(algo), avg_us=round(avg_s * 1e6, 2))
 
 
 def cpu_baseline(pr, iters):
-    """The FP64 oracle on the same system: setup excluded, FGMRES(30) capped at
-    `iters` inner iterations (a bounded sample of the same solve)."""
+    """The FP64 oracle (plain CPTR: AMG + BILU(0) natural order) on the same
+    system: setup excluded, FGMRES(30) capped at `iters` inner iterations."""
     from oracle import oracle as O
     O.build(force=False)
     t0 = time.perf_counter()
-    o = O.Oracle.from_problem(pr, first="cptr", second="bilu0_mc")
+    o = O.Oracle.from_problem(pr, first="cptr", second="bilu0")
     t_setup = time.perf_counter() - t0
     t0 = time.perf_counter()
     _, info = o.fgmres(pr.b, m=30, rtol=1e-6, maxit=iters)
@@ -72,9 +128,54 @@ def cpu_baseline(pr, iters):
     o.close()
     return dict(value=round(pr.n * info["iters"] / t, 1), unit="cell-iters/s", cores=1,
                 kind="oracle",
-                sample=f"same {pr.n:,}-cell system, FP64 CPTR-Block(AMG)+BILU0(multicolour), "
-                       f"FGMRES(30), {info['iters']} inner iterations (cap {iters}) in {t:.1f} s "
-                       f"(setup {t_setup:.1f} s excluded), single thread")
+                sample=f"same {pr.n:,}-cell system, FP64 CPTR-Block(AMG)+BILU0(natural), FGMRES(30), "
+                       f"first {info['iters']} inner iterations in {t:.1f} s (setup {t_setup:.1f} s "
+                       f"excluded), single thread")
+
+
+def train_model(cfg, steps, lr, log_fn):
+    from paper_1907_04229_amd.learned import train
+    from paper_1907_04229_amd.synth import make_problem
+    kw = {k: v for k, v in cfg.items() if k not in ("shape", "seed", "restart")}
+    t0 = time.perf_counter()
+    probs = [make_problem(shape=TRAIN_SHAPE, seed=s, **kw) for s in TRAIN_SEEDS]
+    t_gen = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    model, hist = train(probs, probs[0].nv, steps=steps, batch=4, pairs=24, lr=lr, seed=1,
+                        eval_every=50, precision="fp32", second_stage="bilu0_mc")
+    t_train = time.perf_counter() - t0
+    log_fn(f"trained {steps} steps in {t_train:.1f} s (data {t_gen:.1f} s); validation "
+           f"{[(k, round(v, 4)) for k, v in hist['val']]}, kept step {hist['best_step']}")
+    info = dict(train_s=round(t_train, 2), data_s=round(t_gen, 2), steps=steps, lr=lr,
+                systems=f"{len(TRAIN_SEEDS)} x {'x'.join(map(str, TRAIN_SHAPE))}, seeds {TRAIN_SEEDS}",
+                val_loss_init=round(hist["val"][0][1], 5),
+                val_loss_kept=round(min(v for _, v in hist["val"]), 5), kept_step=hist["best_step"])
+    return model, info
+
+
+def probe(cfg_name):
+    """Short run for the hardware-counter passes: one learned forward, the
+    middle layer three more times, and a 256 MiB device copy three times."""
+    import torch
+    from paper_1907_04229_amd import cptr
+    from paper_1907_04229_amd.learned_init import neumann_params
+    from paper_1907_04229_amd.synth import make_problem
+    pr = make_problem(config=cfg_name)
+    s = cptr.Solver(pr, precision="fp32", second_stage="learned")
+    m = cptr.LearnModel(pr.nv, neumann_params(pr.nv, seed=1))
+    m.attach(s)
+    b1 = torch.randn(pr.n * pr.nv, dtype=torch.float64, device="cuda")
+    cptr.cptr_learn_forward(s, b1)
+    for _ in range(3):
+        cptr.cptr_learn_rerun_layer(s, 1)
+    a = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+    c = torch.empty_like(a)
+    for _ in range(3):
+        c.copy_(a)
+    torch.cuda.synchronize()
+    s.close()
+    m.close()
+    log(f"probe done: {pr.n} cells, copy of {a.numel() * 4} bytes")
 
 
 def main():
@@ -82,31 +183,35 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", default="medium")
-    ap.add_argument("--second", default="bilu0_mc")
-    ap.add_argument("--cpu-iters", type=int, default=1000)
+    ap.add_argument("--config", default="learned")
+    ap.add_argument("--train-steps", type=int, default=400)
+    ap.add_argument("--train-lr", type=float, default=1e-5)
+    ap.add_argument("--cpu-iters", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-compare", action="store_true", help="skip the FP64 and BILU(0) legs")
+    ap.add_argument("--probe", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (the solver is a single-GPU library); "
               f"--gpus {args.gpus} is not supported", file=sys.stderr)
         sys.exit(2)
+    if args.probe:
+        probe(args.config)
+        return
 
-    import numpy as np
     import torch
     from paper_1907_04229_amd import cptr
+    from paper_1907_04229_amd.learned_init import neumann_params
     from paper_1907_04229_amd.synth import make_problem
     from paper_1907_04229_amd.synth.problem import CONFIGS
 
     cfg = CONFIGS[args.config]
+    restart = cfg["restart"]
     t0 = time.perf_counter()
     pr = make_problem(config=args.config)
     log(f"generated {args.config} {cfg['shape']} nv={pr.nv} nnzb={pr.nnzb} in "
         f"{time.perf_counter() - t0:.1f} s")
-    restart = cfg["restart"]
     b = torch.as_tensor(pr.b, device="cuda")
-    bnorm = float(np.linalg.norm(pr.b))
 
     def run(solver, steps, warmup, tag):
         for _ in range(warmup):
@@ -119,66 +224,88 @@ def main():
             infos.append(info)
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / steps
-        it = infos[-1]["iters"]
-        log(f"{tag}: {dt * 1e3:.2f} ms/solve, {it} iterations, true relres "
-            f"{infos[-1]['relres_true']:.2e}")
-        return dt, infos[-1], x
+        info = infos[-1]
+        log(f"{tag}: {dt * 1e3:.2f} ms/solve, {info['iters']} iterations, true relres "
+            f"{info['relres_true']:.2e}, fell back {info['fell_back']}")
+        assert info["converged"] and info["relres_true"] <= 1e-6, f"{tag} did not converge"
+        return dt, info, x
 
-    t0 = time.perf_counter()
-    s32 = cptr.Solver(pr, precision="fp32", second_stage=args.second)
-    torch.cuda.synchronize()
-    setup32 = time.perf_counter() - t0
-    st32 = s32.stats()
-    log(f"fp32 setup {setup32:.2f} s, AMG levels {st32['level_rows']}")
-    dt32, info32, x32 = run(s32, args.steps, args.warmup, "fp32")
-    assert info32["converged"] and info32["relres_true"] <= 1e-6
-
-    res64 = None
-    if not args.no_fp64:
+    def setup(**opt):
         t0 = time.perf_counter()
-        s64 = cptr.Solver(pr, precision="fp64", second_stage=args.second)
+        s = cptr.Solver(pr, **opt)
         torch.cuda.synchronize()
-        setup64 = time.perf_counter() - t0
-        dt64, info64, x64 = run(s64, max(1, min(args.steps, 3)), 1, "fp64")
-        err = float(torch.linalg.vector_norm(x32 - x64) / torch.linalg.vector_norm(x64))
-        res64 = dict(time_to_tol_s=round(dt64, 5), iters=info64["iters"],
-                     cell_iters_per_s=round(pr.n * info64["iters"] / dt64, 1),
-                     setup_s=round(setup64, 3), relres_true=info64["relres_true"],
-                     fp32_vs_fp64_solution_rel_diff=err)
-        s64.close()
+        return s, time.perf_counter() - t0
 
-    roof = kernel_roofline(pr, s32)
-    log(f"roofline: {roof}")
+    def leg(dt, info, setup_s):
+        return dict(time_to_tol_s=round(dt, 5), iters=info["iters"],
+                    cell_iters_per_s=round(pr.n * info["iters"] / dt, 1), setup_s=round(setup_s, 3),
+                    relres_true=info["relres_true"])
+
+    model, train_info = train_model(cfg, args.train_steps, args.train_lr, log)
+
+    # the measured configuration: learned second stage, FP32 preconditioner
+    sl, setup_l = setup(precision="fp32", second_stage="learned")
+    model.attach(sl)
+    dt, info, x_l = run(sl, args.steps, args.warmup, "learned+fp32")
+    roof = layer_roofline(sl)
+    log(f"layer roofline: {roof}")
+
+    compare = {}
+    x64 = None
+    if not args.no_compare:
+        s64, su = setup(precision="fp64", second_stage="bilu0")
+        d64, i64, x64 = run(s64, 1, 1, "plain fp64 (bilu0 natural)")
+        compare["fp64_cptr_bilu0"] = leg(d64, i64, su)
+        spmv = spmv_roofline(pr, s64)
+        s64.close()
+        smc, su = setup(precision="fp32", second_stage="bilu0_mc")
+        dmc, imc, _ = run(smc, 2, 1, "fp32 bilu0 multicolour")
+        compare["fp32_cptr_bilu0_mc"] = leg(dmc, imc, su)
+        smc.close()
+        sn, su = setup(precision="fp32", second_stage="learned")
+        mn = cptr.LearnModel(pr.nv, neumann_params(pr.nv, seed=1))
+        mn.attach(sn)
+        dn, inn, _ = run(sn, 1, 1, "fp32 learned, untrained (Neumann init)")
+        compare["fp32_cptr_learned_untrained"] = leg(dn, inn, su)
+        sn.close()
+        mn.close()
+        compare["speedup_vs_fp64"] = round(d64 / dt, 3)
+        compare["solution_rel_diff_vs_fp64"] = float(torch.linalg.vector_norm(x_l - x64) /
+                                                     torch.linalg.vector_norm(x64))
+        compare["spmv_fp64"] = spmv
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(pr, args.cpu_iters)
         log(f"cpu baseline: {cpu}")
     out = {
         "metric": "FGMRES time-to-1e-6 (s) & cell-iters/s: learned/FP32 vs FP64 CPTR; HBM GB/s",
-        "value": round(pr.n * info32["iters"] / dt32, 1),
-        "unit": "cell-iters/s",
+        "value": round(dt, 5),
+        "unit": "s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(dt32 * 1e3, 3),
-        "higher_is_better": True,
+        "ms_per_step": round(dt * 1e3, 3),
+        "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 preconditioner, f64 Krylov",
+        "dtype": "f32 preconditioner (bf16 MFMA in the learned stage), f64 Krylov",
         "data": "synthetic (seeded thermal Jacobian of the first implicit step, Gaussian ln k field)",
-        "config": {"workload": f"{args.config}: {'x'.join(map(str, cfg['shape']))} cells, "
-                               f"nv={pr.nv}, FGMRES({restart}) rtol 1e-6, CPTR-Block(AMG)+"
-                               f"{'BILU0 multicolour' if args.second == 'bilu0_mc' else 'BILU0'}",
+        "config": {"workload": f"{args.config}: {'x'.join(map(str, cfg['shape']))} cells, nv={pr.nv}, "
+                               f"FGMRES({restart}) rtol 1e-6, CPTR-Block(AMG) + learned second stage, "
+                               f"FP32 preconditioner",
                    "cells": pr.n, "nnzb": pr.nnzb, "restart": restart},
-        "time_to_tol_s": round(dt32, 5),
-        "iters": info32["iters"],
-        "relres_true": info32["relres_true"],
-        "setup_s": round(setup32, 3),
-        "fp64": res64,
+        "iters": info["iters"],
+        "cell_iters_per_s": round(pr.n * info["iters"] / dt, 1),
+        "relres_true": info["relres_true"],
+        "fell_back": info["fell_back"],
+        "setup_s": round(setup_l, 3),
+        "training": train_info,
+        "compare": compare,
         "roofline": roof,
         "cpu_baseline": cpu,
     }
-    s32.close()
+    sl.close()
+    model.close()
     print(json.dumps(out), flush=True)
 
 

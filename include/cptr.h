@@ -178,6 +178,11 @@ int cptr_vcycle(cptr_handle *h, int which, const double *b, double *x, void *str
 int fgmres_solve(cptr_handle *h, const double *b, double *x, const cptr_solve_opts *so,
                  cptr_solve_info *info, void *stream);
 
+/* y = A x with the matrix of h (Section 3, the linearised system), using the
+ * handle's sliced device copy of A (the product of every FGMRES step).
+ * x, y: device FP64 [n*nv], must not alias.  Asynchronous on `stream`. */
+int cptr_matvec(const cptr_handle *h, const double *x, double *y, void *stream);
+
 /* Copy the Arnoldi basis vector v_j of the most recent FGMRES cycle (device
  * FP64 [n*nv], orthonormal in the 2-norm; Section 3, right-preconditioned
  * GMRES) into `out` (device FP64 [n*nv], caller-owned), ordered on `stream`.

@@ -58,6 +58,15 @@ int cptr_learn_attach(cptr_handle *h, cptr_learn_model *m);
 /* z2 = N(b1) for one vector (device FP64 [n*nv] in and out).  Asynchronous. */
 int cptr_learn_forward(cptr_handle *h, const double *b1, double *z2, void *stream);
 
+/* Launch layer `layer` (0, 1 or 2) of the most recent inference pass of h
+ * (cptr_learn_forward, or the learned stage inside cptr_apply / fgmres_solve)
+ * once more on `stream`.  Its inputs are unchanged, so it rewrites the same
+ * values; layer 2 writes z2 = N(b1) of that pass to `z2` (device FP64
+ * [n*nv]; may be NULL for layers 0 and 1).  A measurement aid: it times one
+ * layer kernel alone.  CPTR_ERR_INVALID_ARG before any inference pass or for
+ * a layer out of range.  Asynchronous. */
+int cptr_learn_rerun_layer(cptr_handle *h, int layer, double *z2, void *stream);
+
 /* Mean loss over `count` vectors b1 (device FP64, count x n*nv, back to back)
  * and its gradient (grad_host: host FP32, cptr_learn_param_count values, or
  * NULL).  Blocking. */

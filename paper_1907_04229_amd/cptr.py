@@ -81,6 +81,7 @@ def load():
         L.cptr_vcycle.argtypes = [vp, ip, vp, vp, vp]
         L.fgmres_solve.argtypes = [vp, vp, vp, C.POINTER(SolveOpts), C.POINTER(SolveInfo), vp]
         L.cptr_krylov_vector.argtypes = [vp, ip, vp, vp]
+        L.cptr_matvec.argtypes = [vp, vp, vp, vp]
         L.cptr_update_values.argtypes = [vp, vp, vp, vp]
         L.cptr_get_stats.argtypes = [vp, C.POINTER(Stats)]
         L.cptr_get_aggregates.argtypes = [vp, ip, ip, C.POINTER(C.c_int)]
@@ -101,6 +102,7 @@ def load():
         L.cptr_learn_attach.argtypes = [vp, vp]
         L.cptr_learn_forward.argtypes = [vp, vp, vp, vp]
         L.cptr_learn_grad.argtypes = [vp, vp, ip, fp, fp, vp]
+        L.cptr_learn_rerun_layer.argtypes = [vp, ip, vp, vp]
         L.cptr_learn_train_step.argtypes = [vp, vp, ip, C.c_float, fp, vp]
         _lib = L
     return _lib
@@ -174,6 +176,11 @@ def cptr_vcycle(h, which, b, x, stream=None):
     import torch
     _check(load().cptr_vcycle(h, which, _ptr(b, torch.float64), _ptr(x, torch.float64),
                               _stream(stream)))
+
+
+def cptr_matvec(h, x, y, stream=None):
+    import torch
+    _check(load().cptr_matvec(h, _ptr(x, torch.float64), _ptr(y, torch.float64), _stream(stream)))
 
 
 def cptr_krylov_vector(h, j, out, stream=None):
@@ -337,6 +344,12 @@ def cptr_learn_forward(solver, b1, stream=None):
     _check(load().cptr_learn_forward(solver.h, _ptr(b1, torch.float64), _ptr(z, torch.float64),
                                      _stream(stream)))
     return z
+
+
+def cptr_learn_rerun_layer(solver, layer, z2=None, stream=None):
+    import torch
+    _check(load().cptr_learn_rerun_layer(solver.h, layer, _ptr(z2, torch.float64) if z2 is not None else None,
+                                         _stream(stream)))
 
 
 def cptr_learn_grad(solver, b1_batch, want_grad=True, stream=None):

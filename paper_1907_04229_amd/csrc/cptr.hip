@@ -368,7 +368,8 @@ struct LearnedDev {
   int n = 0, nv = 0, nnzb = 0;
   DevMem nbr, nmask, E, dinv, tpos, r, s, spart, hA, hB;
   int stride[3] = {0, 0, 0};  // |column - row| of the neighbours along each axis
-  DevMem H[4], M[3], Aa[3], dh0, dh1, dm, dhown, z2, res, dz, part;
+  bool have_pass = false;     // an inference pass has filled r, s, hA, hB
+  DevMem H[4], M[3], Aa[3], dh0, dh1, dm, dhown, z2, res, dz, part, mid;
   bool train_ready = false;
 
   // neighbours: direction d = 2 axis + (offset > 0), axes by increasing |offset|
@@ -475,9 +476,24 @@ struct LearnedDev {
     const size_t p1 = (size_t)bwd_blocks() * 4 * (2 * kHid * kHid + kHid * kEdge + kHid);
     const size_t p2 = (size_t)nblk((size_t)n * kHid) * kHid * 4;
     part.alloc(std::max(p1, p2) * 4);
+    mid.alloc((size_t)kSumGroups * (2 * kHid * kHid + kHid * kEdge + kHid) * 4);
     train_ready = true;
   }
   int ntiles() const { return (n + 15) / 16; }
+  // mid[b][e] = sum over the rows p = b, b + g, ... of part[p][e]; returns g
+  int sum_rows(hipStream_t st, const float *part_rows, int np, int len) {
+    const int g = std::max(1, std::min(kSumGroups, np));
+    hipLaunchKernelGGL(k_sum_partials_rows, dim3(g), dim3(kBlock), 0, st, part_rows, np, len, devp<float>(mid));
+    LAUNCH_CHECK();
+    return g;
+  }
+  // out[e] += sum over the np rows of part[p][e] (fixed order)
+  void sum_partials(hipStream_t st, const float *part_rows, int np, int len, float *out) {
+    const int g = sum_rows(st, part_rows, np, len);
+    hipLaunchKernelGGL(k_sum_partials_cols, dim3(nblk(len)), dim3(kBlock), 0, st, (const float *)devp<float>(mid),
+                       g, len, out, 1);
+    LAUNCH_CHECK();
+  }
   int bwd_blocks() const { return std::max(1, std::min(512, (ntiles() + 3) / 4)); }
 
   // The network on b1 (type BT), finished by the read-out `out`; with `store`,
@@ -490,41 +506,59 @@ struct LearnedDev {
     hipLaunchKernelGGL((k_lrn_scale<NV>), dim3(NV), dim3(kBlock), 0, st, (const double *)devp<double>(spart),
                        nb, double(n), devp<float>(s));
     LAUNCH_CHECK();
-    const int lb = std::max(1, std::min(kLayerMaxBlocks, (ntiles() + 3) / 4));
+    for (int l = 0; l < 3; l++) layer<NV, ZT, XT>(st, mdl, l, store, out);
+    have_pass = !store;
+  }
+
+  // Layer l (0..2) of the network on the current r and s.  Training (`store`):
+  // FP32 activations H[l] -> H[l+1], messages and pre-activations kept.
+  // Inference: BF16 activations r -> hA -> hB -> read-out, nothing else kept.
+  template <int NV, typename ZT, typename XT>
+  void layer(hipStream_t st, const LearnModelDev &mdl, int l, bool store, LrnOut<ZT, XT> out) {
+    // a multiple of the XCD count, one wave per tile up to kLayerMaxBlocks
+    const int lb = kXcds * std::max(1, std::min(kLayerMaxBlocks, (ntiles() + 3) / 4) / kXcds);
     const unsigned char *nbp = devp<unsigned char>(nmask);
     const int3 str = make_int3(stride[0], stride[1], stride[2]);
     const short *Ep = devp<short>(E);
     const float *sp = devp<float>(s), *rp_ = devp<float>(r);
     const LrnOut<float, float> none{nullptr, 0, 0, nullptr, nullptr, nullptr, nullptr};
+    const float *We = mdl.We32(l);
+    const short *Ws = mdl.Ws(l), *Wm = mdl.Wm(l);
+    const float *bs = mdl.bias(l);
     if (store) {
-      // training: FP32 activations, everything the backward pass reads is kept
-      hipLaunchKernelGGL((k_lrn_layer<NV, true, false, float, float, float>), dim3(lb), dim3(kBlock), 0, st, n,
-                         nbp, str, Ep, sp, (const float *)nullptr, rp_, mdl.W_in(), mdl.We32(0), mdl.Ws(0), mdl.Wm(0),
-                         mdl.bias(0), devp<float>(H[1]), devp<float>(H[0]), devp<float>(M[0]), devp<float>(Aa[0]),
-                         none);
-      hipLaunchKernelGGL((k_lrn_layer<NV, false, false, float, float, float>), dim3(lb), dim3(kBlock), 0, st, n,
-                         nbp, str, Ep, sp, (const float *)devp<float>(H[1]), rp_, mdl.W_in(), mdl.We32(1), mdl.Ws(1),
-                         mdl.Wm(1), mdl.bias(1), devp<float>(H[2]), (float *)nullptr, devp<float>(M[1]),
-                         devp<float>(Aa[1]), none);
-      hipLaunchKernelGGL((k_lrn_layer<NV, false, true, float, ZT, XT>), dim3(lb), dim3(kBlock), 0, st, n, nbp, str, Ep,
-                         sp, (const float *)devp<float>(H[2]), rp_, mdl.W_in(), mdl.We32(2), mdl.Ws(2), mdl.Wm(2),
-                         mdl.bias(2), devp<float>(H[3]), (float *)nullptr, devp<float>(M[2]), devp<float>(Aa[2]),
-                         out);
+      float *Ml = devp<float>(M[l]), *Al = devp<float>(Aa[l]);
+      if (l == 0)
+        hipLaunchKernelGGL((k_lrn_layer<NV, true, false, float, float, float>), dim3(lb), dim3(kBlock), 0, st, n,
+                           nbp, str, Ep, sp, (const float *)nullptr, rp_, mdl.W_in(), We, Ws, Wm, bs,
+                           devp<float>(H[1]), devp<float>(H[0]), Ml, Al, none);
+      else if (l == 1)
+        hipLaunchKernelGGL((k_lrn_layer<NV, false, false, float, float, float>), dim3(lb), dim3(kBlock), 0, st, n,
+                           nbp, str, Ep, sp, (const float *)devp<float>(H[1]), rp_, mdl.W_in(), We, Ws, Wm, bs,
+                           devp<float>(H[2]), (float *)nullptr, Ml, Al, none);
+      else
+        hipLaunchKernelGGL((k_lrn_layer<NV, false, true, float, ZT, XT>), dim3(lb), dim3(kBlock), 0, st, n, nbp,
+                           str, Ep, sp, (const float *)devp<float>(H[2]), rp_, mdl.W_in(), We, Ws, Wm, bs,
+                           devp<float>(H[3]), (float *)nullptr, Ml, Al, out);
     } else {
-      // inference: BF16 activations between the layers, nothing else kept
       short *ha = devp<short>(hA), *hb = devp<short>(hB);
-      hipLaunchKernelGGL((k_lrn_layer<NV, true, false, short, float, float>), dim3(lb), dim3(kBlock), 0, st, n,
-                         nbp, str, Ep, sp, (const short *)nullptr, rp_, mdl.W_in(), mdl.We32(0), mdl.Ws(0), mdl.Wm(0),
-                         mdl.bias(0), ha, (float *)nullptr, (float *)nullptr, (float *)nullptr, none);
-      hipLaunchKernelGGL((k_lrn_layer<NV, false, false, short, float, float>), dim3(lb), dim3(kBlock), 0, st, n,
-                         nbp, str, Ep, sp, (const short *)ha, rp_, mdl.W_in(), mdl.We32(1), mdl.Ws(1), mdl.Wm(1),
-                         mdl.bias(1), hb, (float *)nullptr, (float *)nullptr, (float *)nullptr, none);
-      hipLaunchKernelGGL((k_lrn_layer<NV, false, true, short, ZT, XT>), dim3(lb), dim3(kBlock), 0, st, n, nbp, str, Ep,
-                         sp, (const short *)hb, rp_, mdl.W_in(), mdl.We32(2), mdl.Ws(2), mdl.Wm(2), mdl.bias(2),
-                         (short *)nullptr, (float *)nullptr, (float *)nullptr, (float *)nullptr, out);
+      if (l == 0)
+        hipLaunchKernelGGL((k_lrn_layer<NV, true, false, short, float, float>), dim3(lb), dim3(kBlock), 0, st, n,
+                           nbp, str, Ep, sp, (const short *)nullptr, rp_, mdl.W_in(), We, Ws, Wm, bs, ha,
+                           (float *)nullptr, (float *)nullptr, (float *)nullptr, none);
+      else if (l == 1)
+        hipLaunchKernelGGL((k_lrn_layer<NV, false, false, short, float, float>), dim3(lb), dim3(kBlock), 0, st, n,
+                           nbp, str, Ep, sp, (const short *)ha, rp_, mdl.W_in(), We, Ws, Wm, bs, hb,
+                           (float *)nullptr, (float *)nullptr, (float *)nullptr, none);
+      else
+        hipLaunchKernelGGL((k_lrn_layer<NV, false, true, short, ZT, XT>), dim3(lb), dim3(kBlock), 0, st, n, nbp,
+                           str, Ep, sp, (const short *)hb, rp_, mdl.W_in(), We, Ws, Wm, bs, (short *)nullptr,
+                           (float *)nullptr, (float *)nullptr, (float *)nullptr, out);
     }
     LAUNCH_CHECK();
   }
+  // algorithmic HBM bytes of one inference launch of layer 1 (BF16 activations
+  // in and out, the six BF16 edge blocks, the presence mask)
+  double layer_bytes() const { return (double)n * (2.0 * kHid * 2 + kDir * kEdge * 2 + 1); }
 };
 
 // ---------------------------------------------------------------- preconditioner
@@ -690,6 +724,7 @@ struct cptr_handle {
   const double *vals = nullptr;
   std::unique_ptr<cptr::PrecondBase> pc;
   cptr::DevMem slots;                 // ApplySlots
+  cptr::DevMem sl_kptr, sl_cols, sl_vals;  // sliced copy of A for the FP64 products
   hipStream_t stream = nullptr;       // internal stream (default priority)
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
   cptr_stats stats{};
@@ -826,6 +861,37 @@ static const IluDev<T> *ilu_of(const cptr_handle *h) {
   return (p && p->have_ilu) ? &p->ilu : nullptr;
 }
 
+// sliced copy of A (layout at k_bsr_spmv_sliced)
+static void build_sliced(cptr_handle *h, const std::vector<int> &rp, const std::vector<int> &ci,
+                         const std::vector<double> &vals) {
+  const int n = h->op.n, nv = h->op.nv, b2 = nv * nv;
+  const int ns = (n + 63) / 64;
+  std::vector<int> kptr(ns + 1, 0);
+  for (int s = 0; s < ns; s++) {
+    int K = 0;
+    for (int i = s * 64; i < std::min(n, s * 64 + 64); i++) K = std::max(K, rp[i + 1] - rp[i]);
+    kptr[s + 1] = kptr[s] + K;
+  }
+  const size_t nk = (size_t)kptr[ns];
+  std::vector<int> cols(nk * 64);
+  std::vector<double> sv(nk * b2 * 64, 0.0);
+  for (int s = 0; s < ns; s++)
+    for (int lane = 0; lane < 64; lane++) {
+      const int i = s * 64 + lane;
+      for (int k = 0; k < kptr[s + 1] - kptr[s]; k++) {
+        const size_t kk = (size_t)kptr[s] + k;
+        const bool real = i < n && k < rp[i + 1] - rp[i];
+        cols[kk * 64 + lane] = real ? ci[rp[i] + k] : (i < n ? i : 0);
+        if (!real) continue;
+        const double *blk = vals.data() + (size_t)(rp[i] + k) * b2;
+        for (int q = 0; q < b2; q++) sv[(kk * b2 + q) * 64 + lane] = blk[q];
+      }
+    }
+  upload(h->sl_kptr, kptr);
+  upload(h->sl_cols, cols);
+  upload(h->sl_vals, sv);
+}
+
 static void validate_and_fetch(const cptr_bsr *A, const cptr_csr *S, const cptr_options &o,
                                std::vector<int> &rp, std::vector<int> &ci, std::vector<double> &vals,
                                HostCSR &sh) {
@@ -905,12 +971,14 @@ template <int NV, typename ZT>
 static void launch_spmv(cptr_handle *h, hipStream_t st, const ZT *x, const ApplySlots *sl,
                         const double *b, double *y) {
   const int n = h->op.n;
+  const dim3 grid((n + 63) / 64), block(64 * NV);
+  const int *kp = devp<int>(h->sl_kptr), *cl = devp<int>(h->sl_cols);
+  const double *va = devp<double>(h->sl_vals);
   if (b)
-    hipLaunchKernelGGL((k_bsr_spmv<NV, ZT, true>), dim3(nblk(n, 64)), dim3(64 * NV), 0, st, n, h->rp, h->ci,
-                       h->vals, x, sl, b, y);
+    hipLaunchKernelGGL((k_bsr_spmv_sliced<NV, ZT, true>), grid, block, 0, st, n, kp, cl, va, x, sl, b, y);
   else
-    hipLaunchKernelGGL((k_bsr_spmv<NV, ZT, false>), dim3(nblk(n, 64)), dim3(64 * NV), 0, st, n, h->rp,
-                       h->ci, h->vals, x, sl, (const double *)nullptr, y);
+    hipLaunchKernelGGL((k_bsr_spmv_sliced<NV, ZT, false>), grid, block, 0, st, n, kp, cl, va, x, sl,
+                       (const double *)nullptr, y);
   LAUNCH_CHECK();
 }
 
@@ -1190,8 +1258,7 @@ static double learn_grad_impl(cptr_handle *h, hipStream_t st, const double *b1_a
     const int nb64 = nblk((size_t)n * kHid);
     hipLaunchKernelGGL((k_lrn_out_bwd<NV>), dim3(nb64), dim3(kBlock), 0, st, n, (const double *)dz, scale,
                        (const float *)devp<float>(L.s), M.W_out(), (const float *)devp<float>(L.H[3]), dh, part);
-    hipLaunchKernelGGL(k_sum_partials, dim3(nblk(NV * kHid)), dim3(kBlock), 0, st, (const float *)part, nb64,
-                       NV * kHid, grad + nin + 3 * nl, 1);
+    L.sum_partials(st, part, nb64, NV * kHid, grad + nin + 3 * nl);
     LAUNCH_CHECK();
     const int bb1 = L.bwd_blocks(), lb = (L.ntiles() + 3) / 4;
     for (int l = 2; l >= 0; l--) {
@@ -1202,8 +1269,10 @@ static double learn_grad_impl(cptr_handle *h, hipStream_t st, const double *b1_a
                          (const float *)devp<float>(L.Aa[l]), (const float *)dh, M.WsT(l), M.WmT(l),
                          devp<float>(L.dm), devp<float>(L.dhown), part);
       constexpr int nlay = kHid * NV * NV + 2 * kHid * kHid + kHid;
-      hipLaunchKernelGGL((k_lrn_reduce_layer<NV>), dim3(nblk(nlay)), dim3(kBlock), 0, st, (const float *)part,
-                         bb1 * (kBlock / 64), grad + nin + l * nl);
+      constexpr int P = 2 * kHid * kHid + kHid * kEdge + kHid;  // one partial row of bwd1
+      const int g = L.sum_rows(st, part, bb1 * (kBlock / 64), P);
+      hipLaunchKernelGGL((k_lrn_reduce_layer<NV>), dim3(nblk(nlay)), dim3(kBlock), 0, st,
+                         (const float *)devp<float>(L.mid), g, grad + nin + l * nl);
       hipLaunchKernelGGL((k_lrn_layer_bwd2<NV>), dim3(lb), dim3(kBlock), 0, st, n, (const int *)devp<int>(L.nbr),
                          (const short *)devp<short>(L.E), (const float *)devp<float>(L.s), M.We16(l), (const float *)devp<float>(L.dm),
                          (const float *)devp<float>(L.dhown), dh_next);
@@ -1212,8 +1281,7 @@ static double learn_grad_impl(cptr_handle *h, hipStream_t st, const double *b1_a
     }
     hipLaunchKernelGGL((k_lrn_in_bwd<NV>), dim3(nb64), dim3(kBlock), 0, st, n, (const float *)dh,
                        (const float *)devp<float>(L.r), (const float *)devp<float>(L.s), part);
-    hipLaunchKernelGGL(k_sum_partials, dim3(nblk(kHid * NV)), dim3(kBlock), 0, st, (const float *)part, nb64,
-                       kHid * NV, grad, 1);
+    L.sum_partials(st, part, nb64, kHid * NV, grad);
     LAUNCH_CHECK();
   }
   CPTR_HIP_TRY(hipStreamSynchronize(st));
@@ -1286,6 +1354,7 @@ int cptr_setup(cptr_handle **out, const cptr_bsr *A, const cptr_csr *S_T, const 
     CPTR_HIP_TRY(hipEventCreateWithFlags(&h->ev_in, hipEventDisableTiming));
     CPTR_HIP_TRY(hipEventCreateWithFlags(&h->ev_out, hipEventDisableTiming));
     h->slots.alloc(sizeof(ApplySlots));
+    build_sliced(h, rp, ci, vals);
     if (o.precision == CPTR_FP32) build_precond<float>(h, rp, ci, vals, &sh);
     else build_precond<double>(h, rp, ci, vals, &sh);
     const int nv = A->nv;
@@ -1380,6 +1449,18 @@ int fgmres_solve(cptr_handle *h, const double *b, double *x, const cptr_solve_op
   }
 }
 
+int cptr_matvec(const cptr_handle *h, const double *x, double *y, void *stream) {
+  if (!h || !x || !y) return fail(Error{CPTR_ERR_INVALID_ARG, "null argument"});
+  if (x == y) return fail(Error{CPTR_ERR_INVALID_ARG, "input and output alias"});
+  try {
+    cptr_handle *hh = const_cast<cptr_handle *>(h);
+    spmv<double>(hh, (hipStream_t)stream, x, nullptr, y);
+    return CPTR_OK;
+  } catch (const Error &e) {
+    return fail(e);
+  }
+}
+
 int cptr_krylov_vector(const cptr_handle *h, int j, double *out, void *stream) {
   if (!h || !out) return fail(Error{CPTR_ERR_INVALID_ARG, "null argument"});
   if (h->m_alloc < 1 || j < 0 || j > h->m_alloc)
@@ -1432,11 +1513,11 @@ int cptr_bsr_spmv(int n, int nv, const int *rp, const int *ci, const double *val
   if (n == 0) return CPTR_OK;
   hipStream_t st = (hipStream_t)stream;
   if (nv == 3)
-    hipLaunchKernelGGL((k_bsr_spmv<3, double, false>), dim3(nblk(n, 64)), dim3(192), 0, st, n, rp, ci, vals, x,
-                       (const ApplySlots *)nullptr, (const double *)nullptr, y);
+    hipLaunchKernelGGL((k_bsr_spmv<3, double, false>), dim3(nblk(n, SpmvShape<3>::R)), dim3(SpmvShape<3>::T), 0,
+                       st, n, rp, ci, vals, x, (const ApplySlots *)nullptr, (const double *)nullptr, y);
   else
-    hipLaunchKernelGGL((k_bsr_spmv<4, double, false>), dim3(nblk(n, 64)), dim3(256), 0, st, n, rp, ci, vals, x,
-                       (const ApplySlots *)nullptr, (const double *)nullptr, y);
+    hipLaunchKernelGGL((k_bsr_spmv<4, double, false>), dim3(nblk(n, SpmvShape<4>::R)), dim3(SpmvShape<4>::T), 0,
+                       st, n, rp, ci, vals, x, (const ApplySlots *)nullptr, (const double *)nullptr, y);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(Error{CPTR_ERR_HIP, hipGetErrorString(e)});
   return CPTR_OK;
@@ -1557,6 +1638,24 @@ int cptr_learn_forward(cptr_handle *h, const double *b1, double *z2, void *strea
     if (L.nv == 3) L.forward<3, double, double, double>(st, M, b1, false, out);
     else L.forward<4, double, double, double>(st, M, b1, false, out);
     LAUNCH_CHECK();
+    return CPTR_OK;
+  } catch (const Error &e) {
+    return fail(e);
+  }
+}
+
+int cptr_learn_rerun_layer(cptr_handle *h, int layer, double *z2, void *stream) {
+  if (!h || layer < 0 || layer > 2 || (layer == 2 && !z2))
+    return fail(Error{CPTR_ERR_INVALID_ARG, "bad argument"});
+  if (!h->model || !h->lrn || !h->lrn->have_pass)
+    return fail(Error{CPTR_ERR_INVALID_ARG, "no inference pass of the learned stage to repeat"});
+  try {
+    hipStream_t st = (hipStream_t)stream;
+    LearnedDev &L = *h->lrn;
+    const LearnModelDev &M = h->model->dev;
+    const LrnOut<double, double> out{M.W_out(), 0, 0, nullptr, nullptr, nullptr, z2};
+    if (L.nv == 3) L.layer<3, double, double>(st, M, layer, false, out);
+    else L.layer<4, double, double>(st, M, layer, false, out);
     return CPTR_OK;
   } catch (const Error &e) {
     return fail(e);

@@ -289,26 +289,84 @@ __global__ void __launch_bounds__(kBlock) k_ilu_bwd(int p0, int cnt, const int *
 // 64 block rows per workgroup, NV threads per block row (one per equation).
 // ---------------------------------------------------------------------------
 // With `slots` non-null, x is read from slots->z (the current Krylov column).
+// Row layout of the caller's arrays; the column indices of up to 8 blocks are
+// read first, then all their values and x entries, then the products.
+template <int NV>
+struct SpmvShape {
+  static constexpr int R = 64;      // block rows per workgroup
+  static constexpr int T = R * NV;  // threads
+};
+
 template <int NV, typename XT, bool RESID>
-__global__ void __launch_bounds__(64 * NV) k_bsr_spmv(int n, const int *__restrict__ rp,
-                                                      const int *__restrict__ ci,
-                                                      const double *__restrict__ vals,
-                                                      const XT *__restrict__ xarg,
-                                                      const ApplySlots *__restrict__ slots,
-                                                      const double *__restrict__ b,
-                                                      double *__restrict__ y) {
+__global__ void __launch_bounds__(SpmvShape<NV>::T) k_bsr_spmv(int n, const int *__restrict__ rp,
+                                                               const int *__restrict__ ci,
+                                                               const double *__restrict__ vals,
+                                                               const XT *__restrict__ xarg,
+                                                               const ApplySlots *__restrict__ slots,
+                                                               const double *__restrict__ b,
+                                                               double *__restrict__ y) {
+  constexpr int R = SpmvShape<NV>::R;
   const XT *__restrict__ x = slots ? reinterpret_cast<const XT *>(slots->z) : xarg;
-  const int t = threadIdx.x;
-  const int i = blockIdx.x * 64 + t / NV, r = t % NV;
+  const int i = blockIdx.x * R + threadIdx.x / NV, r = threadIdx.x % NV;
   if (i >= n) return;
   double acc = 0.0;
   const int e = rp[i + 1];
-  for (int k = rp[i]; k < e; k++) {
-    const double *a = vals + ((size_t)k * NV + r) * NV;
-    const XT *xc = x + (size_t)ci[k] * NV;
+  for (int k = rp[i]; k < e; k += 8) {
+    int col[8];
 #pragma unroll
-    for (int c = 0; c < NV; c++) acc += a[c] * double(xc[c]);
+    for (int q = 0; q < 8; q++) col[q] = k + q < e ? ci[k + q] : -1;
+    double av[8][NV];
+    double xv[8][NV];
+#pragma unroll
+    for (int q = 0; q < 8; q++) {
+      const bool ok = col[q] >= 0;
+      const double *a = vals + ((size_t)(ok ? k + q : k) * NV + r) * NV;  // in bounds either way
+      const XT *xc = x + (size_t)(ok ? col[q] : 0) * NV;
+#pragma unroll
+      for (int c = 0; c < NV; c++) {
+        av[q][c] = ok ? a[c] : 0.0;
+        xv[q][c] = ok ? double(xc[c]) : 0.0;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 8; q++)
+#pragma unroll
+      for (int c = 0; c < NV; c++) acc += av[q][c] * xv[q][c];
   }
+  const size_t o = (size_t)i * NV + r;
+  y[o] = RESID ? b[o] - acc : acc;
+}
+
+// Sliced copy of the FP64 BSR matrix for the Krylov products: slices of 64
+// block rows; slice s holds K_s = (longest row of the slice) block columns,
+// kptr[s] = sum of K over the slices before s.  For block column k of the
+// slice, entry (r, c) of the blocks of its 64 rows is stored contiguously:
+//   vals[((kptr[s] + k) NV^2 + r NV + c) 64 + lane],  cols[(kptr[s] + k) 64 + lane]
+// Rows shorter than K_s are padded with zero blocks in their own column.
+// Wavefront r of the workgroup forms equation r of the slice's 64 rows, so
+// every value load is 64 consecutive doubles.
+template <int NV, typename XT, bool RESID>
+__global__ void __launch_bounds__(64 * NV) k_bsr_spmv_sliced(int n, const int *__restrict__ kptr,
+                                                              const int *__restrict__ cols,
+                                                              const double *__restrict__ vals,
+                                                              const XT *__restrict__ xarg,
+                                                              const ApplySlots *__restrict__ slots,
+                                                              const double *__restrict__ b,
+                                                              double *__restrict__ y) {
+  const XT *__restrict__ x = slots ? reinterpret_cast<const XT *>(slots->z) : xarg;
+  const int r = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int sl = blockIdx.x, i = sl * 64 + lane;
+  const int k0 = kptr[sl], k1 = kptr[sl + 1];
+  double acc = 0.0;
+#pragma unroll 4
+  for (int k = k0; k < k1; k++) {
+    const int col = cols[(size_t)k * 64 + lane];
+    const double *a = vals + ((size_t)k * NV * NV + r * NV) * 64 + lane;
+    const XT *xc = x + (size_t)col * NV;
+#pragma unroll
+    for (int c = 0; c < NV; c++) acc += a[c * 64] * double(xc[c]);
+  }
+  if (i >= n) return;
   const size_t o = (size_t)i * NV + r;
   y[o] = RESID ? b[o] - acc : acc;
 }

@@ -213,6 +213,7 @@ struct RawAct<HT, NV, true> {
 // Workgroups of the layer kernel: enough to fill the chip several times over;
 // each wave loops over tiles.
 constexpr int kLayerMaxBlocks = 2048;
+constexpr int kXcds = 8;  // accelerator complex dies of the MI355X, each with its own L2
 constexpr int kWPad = kHid + 4;  // LDS row of W_s / W_m (BF16), padded against bank conflicts
 
 // One message-passing layer.  One wavefront per tile of 16 consecutive cells;
@@ -284,12 +285,24 @@ __global__ void __launch_bounds__(kBlock) k_lrn_layer(
     }
   };
   const int off[kDir] = {-stride.x, stride.x, -stride.y, stride.y, -stride.z, stride.z};
-  for (int tile = blockIdx.x * (kBlock / 64) + w; tile < ntiles; tile += gridDim.x * (kBlock / 64)) {
+  // XCD-aware order: workgroups are dealt to the 8 XCDs round robin, so the
+  // workgroups of one XCD (blockIdx % 8) take one contiguous eighth of the
+  // tiles, in increasing order; a tile's neighbours along the slower axes were
+  // then fetched recently into the same XCD's L2.  (gridDim.x is a multiple of 8.)
+  const int nwx = (gridDim.x / kXcds) * (kBlock / 64);         // waves per XCD
+  const int per = (ntiles + kXcds - 1) / kXcds;                // tiles per XCD
+  const int xcd = blockIdx.x % kXcds;
+  const int t_end = min(ntiles, (xcd + 1) * per);
+  const int tile0 = xcd * per + (blockIdx.x / kXcds) * (kBlock / 64) + w;
+  // presence mask of the next tile, loaded one iteration ahead
+  unsigned mk_next = tile0 < t_end ? nmask[min(tile0 * 16 + lr, n - 1)] : 0u;
+  for (int tile = tile0; tile < t_end; tile += nwx) {
     const int cell = tile * 16 + lr;
     const bool ok = cell < n;
     // lanes past the end read the last cell; their results are never stored
     const int cl = ok ? cell : n - 1;
-    const unsigned mk = nmask[cl];  // bit d: neighbour cell + off[d] exists
+    const unsigned mk = mk_next;  // bit d: neighbour cell + off[d] exists
+    if (tile + nwx < t_end) mk_next = nmask[min((tile + nwx) * 16 + lr, n - 1)];
     f32x4 hv[4];
     act(cl, hv);
     // messages: all loads are issued first and consumed direction by
@@ -299,7 +312,7 @@ __global__ void __launch_bounds__(kBlock) k_lrn_layer(
     bf16x4 rawe[kDir];
 #pragma unroll
     for (int d = 0; d < kDir; d++) {
-      rawe[d] = load_bf4(E + ((size_t)cl * kDir + d) * kEdge + 4 * lg);
+      rawe[d] = __builtin_nontemporal_load(reinterpret_cast<const bf16x4 *>(E + ((size_t)cl * kDir + d) * kEdge + 4 * lg));
       raw[d] = RawAct<HT, NV, FIRST>::load((mk >> d) & 1u ? cl + off[d] : cl, lg, hin, r);
     }
     __builtin_amdgcn_sched_barrier(0);
@@ -667,14 +680,24 @@ __global__ void __launch_bounds__(kBlock) k_lrn_in_bwd(int n, const float *__res
   }
 }
 
-// out[e] (+)= sum_p part[p][e], fixed order over p
-__global__ void __launch_bounds__(kBlock) k_sum_partials(const float *__restrict__ part, int np,
-                                                         int len, float *__restrict__ out,
-                                                         int accumulate) {
+// out[e] (+)= sum_p part[p][e] in two passes with a fixed order: workgroup b
+// sums the rows p = b, b + G, ... (coalesced along e) into mid[b][e]; then
+// one thread per e sums mid[0..G-1][e].
+constexpr int kSumGroups = 256;
+__global__ void __launch_bounds__(kBlock) k_sum_partials_rows(const float *__restrict__ part, int np, int len,
+                                                              float *__restrict__ mid) {
+  for (int e = threadIdx.x; e < len; e += kBlock) {
+    float s = 0.f;
+    for (int p = blockIdx.x; p < np; p += gridDim.x) s += part[(size_t)p * len + e];
+    mid[(size_t)blockIdx.x * len + e] = s;
+  }
+}
+__global__ void __launch_bounds__(kBlock) k_sum_partials_cols(const float *__restrict__ mid, int groups, int len,
+                                                              float *__restrict__ out, int accumulate) {
   const int e = blockIdx.x * kBlock + threadIdx.x;
   if (e >= len) return;
   float s = 0.f;
-  for (int p = 0; p < np; p++) s += part[(size_t)p * len + e];
+  for (int b = 0; b < groups; b++) s += mid[(size_t)b * len + e];
   out[e] = accumulate ? out[e] + s : s;
 }
 
@@ -730,6 +753,7 @@ __global__ void __launch_bounds__(kBlock) k_lrn_pack(const float *__restrict__ t
 template <int NV>
 __global__ void __launch_bounds__(kBlock) k_lrn_reduce_layer(const float *__restrict__ part, int nw,
                                                              float *__restrict__ grad) {
+  // part: nw rows of [W_s | W_m | W_e (64 x 16) | b] partial sums
   constexpr int NE = kHid * NV * NV, P = 2 * kHid * kHid + kHid * kEdge + kHid;
   const int e = blockIdx.x * kBlock + threadIdx.x;
   if (e >= NE + 2 * kHid * kHid + kHid) return;

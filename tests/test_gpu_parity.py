@@ -84,6 +84,22 @@ def test_bsr_spmv_fp64(name):
     assert relerr(y.cpu().numpy(), ref) <= 1e-13
 
 
+@pytest.mark.parametrize("name", ["ragged", "three", "small"])
+def test_matvec_sliced_fp64(name):
+    """The handle's sliced copy of A (the product inside FGMRES) against the
+    oracle's BSR product, on grids whose last 64-row slice is partial."""
+    banner(f"matvec {name}")
+    pr = prob(name)
+    s = solver(pr, precision="fp64", second_stage="bilu0")
+    x = np.random.default_rng(2).standard_normal(pr.n * pr.nv)
+    y = torch.empty(pr.n * pr.nv, dtype=torch.float64, device=DEV)
+    cptr.cptr_matvec(s.h, dev(x), y)
+    torch.cuda.synchronize()
+    ref = O.bsr_spmv(pr.row_ptr, pr.col_idx, pr.vals, pr.nv, x)
+    assert relerr(y.cpu().numpy(), ref) <= 1e-13
+    s.close()
+
+
 # ---------------------------------------------------------------- setup integers
 @pytest.mark.parametrize("name", ["ragged", "three", "small"])
 def test_aggregates_and_schedule_bit_exact(name):
