@@ -14,9 +14,12 @@ done before the timed region and reported separately.
 
 Training (not timed): the network starts from the Neumann-series
 initialisation and is trained by the library's own kernels on FGMRES Arnoldi
-vectors of four 64x64x32 systems with other seeds of the same field model
-(the solved system is held out), keeping the parameters with the lowest
-validation loss.
+vectors of four 64x64x32 systems with seeds 100-103 of the same field model
+(the solved system, seed 200, is held out), keeping the parameters with the
+lowest validation loss.  After the timed run the 128x128x64 systems of seeds
+200-204 are solved with the trained network, the untrained one and the
+BILU(0) second stages, and their iterations and times reported (skipped with
+`--no-held-out`).
 
 Prints one JSON line (keys below).  `--probe` runs only a short learned
 forward pass, the layer kernel and a plain device copy, for hardware-counter
@@ -36,7 +39,8 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "learned_layer_traffic.json")
 LAYER_SRC = os.path.join(ROOT, "paper_1907_04229_amd", "csrc", "learned_kernels.hip")
-TRAIN_SEEDS = (210, 211, 212, 213)
+TRAIN_SEEDS = (100, 101, 102, 103)
+HELD_OUT_SEEDS = (200, 201, 202, 203, 204)
 TRAIN_SHAPE = (64, 64, 32)
 
 
@@ -153,6 +157,44 @@ def train_model(cfg, steps, lr, log_fn):
     return model, info
 
 
+def held_out_eval(cfg, model, restart, log_fn):
+    """FGMRES iterations and time-to-1e-6 on the held-out 128x128x64 systems:
+    learned (trained and untrained) with the FP32 preconditioner, BILU(0)
+    natural order in FP64 (plain CPTR) and BILU(0) multicolour in FP32."""
+    import torch
+    from paper_1907_04229_amd import cptr
+    from paper_1907_04229_amd.learned_init import neumann_params
+    from paper_1907_04229_amd.synth import make_problem
+    kw = {k: v for k, v in cfg.items() if k not in ("seed", "restart")}
+    rows = []
+    for seed in HELD_OUT_SEEDS:
+        pr = make_problem(seed=seed, **kw)
+        b = torch.as_tensor(pr.b, device="cuda")
+        row = {"seed": seed}
+        untrained = cptr.LearnModel(pr.nv, neumann_params(pr.nv, seed=1))
+        for tag, opt, mdl in (("learned", dict(precision="fp32", second_stage="learned"), model),
+                              ("untrained", dict(precision="fp32", second_stage="learned"), untrained),
+                              ("fp64_bilu0", dict(precision="fp64", second_stage="bilu0"), None),
+                              ("fp32_bilu0_mc", dict(precision="fp32", second_stage="bilu0_mc"), None)):
+            s = cptr.Solver(pr, **opt)
+            if mdl is not None:
+                mdl.attach(s)
+            s.solve(b, restart=restart, rtol=1e-6)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, info = s.solve(b, restart=restart, rtol=1e-6)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            s.close()
+            assert info["converged"] and info["relres_true"] <= 1e-6, f"seed {seed} {tag} did not converge"
+            row[tag] = dict(iters=info["iters"], time_s=round(dt, 5), fell_back=info["fell_back"])
+        untrained.close()
+        log_fn(f"held-out seed {seed}: " + ", ".join(f"{k} {v['iters']} its {v['time_s'] * 1e3:.1f} ms"
+                                                      for k, v in row.items() if k != "seed"))
+        rows.append(row)
+    return rows
+
+
 def probe(cfg_name):
     """Short run for the hardware-counter passes: one learned forward, the
     middle layer three more times, and a 256 MiB device copy three times."""
@@ -189,6 +231,7 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the FP64 and BILU(0) legs")
+    ap.add_argument("--no-held-out", action="store_true", help="skip the held-out seed evaluation")
     ap.add_argument("--probe", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -273,6 +316,9 @@ def main():
         compare["solution_rel_diff_vs_fp64"] = float(torch.linalg.vector_norm(x_l - x64) /
                                                      torch.linalg.vector_norm(x64))
         compare["spmv_fp64"] = spmv
+    held = None
+    if not args.no_held_out:
+        held = held_out_eval(cfg, model, restart, log)
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(pr, args.cpu_iters)
@@ -301,6 +347,7 @@ def main():
         "setup_s": round(setup_l, 3),
         "training": train_info,
         "compare": compare,
+        "held_out": held,
         "roofline": roof,
         "cpu_baseline": cpu,
     }
