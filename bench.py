@@ -14,7 +14,7 @@ done before the timed region and reported separately.
 
 Training (not timed): the network starts from the Neumann-series
 initialisation and is trained by the library's own kernels on FGMRES Arnoldi
-vectors of four 64x64x32 systems with seeds 100-103 of the same field model
+vectors of eight 64x64x32 systems with seeds 100-107 of the same field model
 (the solved system, seed 200, is held out), keeping the parameters with the
 lowest validation loss.  After the timed run the 128x128x64 systems of seeds
 200-204 are solved with the trained network, the untrained one and the
@@ -39,7 +39,8 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "learned_layer_traffic.json")
 LAYER_SRC = os.path.join(ROOT, "paper_1907_04229_amd", "csrc", "learned_kernels.hip")
-TRAIN_SEEDS = (100, 101, 102, 103)
+FIRST_NAME = {"cptr": "CPTR-Block", "cptr_lower": "CPTR-BlockLower", "cpr": "CPR"}
+TRAIN_SEED0 = 100  # --train-systems N takes the seeds 100 .. 100 + N - 1
 HELD_OUT_SEEDS = (200, 201, 202, 203, 204)
 TRAIN_SHAPE = (64, 64, 32)
 
@@ -137,27 +138,29 @@ def cpu_baseline(pr, iters):
                        f"excluded), single thread")
 
 
-def train_model(cfg, steps, lr, log_fn):
+def train_model(cfg, steps, lr, systems, pairs, batch, first, log_fn):
     from paper_1907_04229_amd.learned import train
     from paper_1907_04229_amd.synth import make_problem
     kw = {k: v for k, v in cfg.items() if k not in ("shape", "seed", "restart")}
     t0 = time.perf_counter()
-    probs = [make_problem(shape=TRAIN_SHAPE, seed=s, **kw) for s in TRAIN_SEEDS]
+    seeds = tuple(range(TRAIN_SEED0, TRAIN_SEED0 + systems))
+    probs = [make_problem(shape=TRAIN_SHAPE, seed=s, **kw) for s in seeds]
     t_gen = time.perf_counter() - t0
     t0 = time.perf_counter()
-    model, hist = train(probs, probs[0].nv, steps=steps, batch=4, pairs=24, lr=lr, seed=1,
-                        eval_every=50, precision="fp32", second_stage="bilu0_mc")
+    model, hist = train(probs, probs[0].nv, steps=steps, batch=batch, pairs=pairs, lr=lr, seed=1,
+                        eval_every=50, precision="fp32", second_stage="bilu0_mc", first_stage=first)
     t_train = time.perf_counter() - t0
     log_fn(f"trained {steps} steps in {t_train:.1f} s (data {t_gen:.1f} s); validation "
            f"{[(k, round(v, 4)) for k, v in hist['val']]}, kept step {hist['best_step']}")
     info = dict(train_s=round(t_train, 2), data_s=round(t_gen, 2), steps=steps, lr=lr,
-                systems=f"{len(TRAIN_SEEDS)} x {'x'.join(map(str, TRAIN_SHAPE))}, seeds {TRAIN_SEEDS}",
+                systems=f"{len(seeds)} x {'x'.join(map(str, TRAIN_SHAPE))}, seeds {seeds}", pairs=pairs,
+                batch=batch,
                 val_loss_init=round(hist["val"][0][1], 5),
                 val_loss_kept=round(min(v for _, v in hist["val"]), 5), kept_step=hist["best_step"])
     return model, info
 
 
-def held_out_eval(cfg, model, restart, log_fn):
+def held_out_eval(cfg, model, restart, first, log_fn):
     """FGMRES iterations and time-to-1e-6 on the held-out 128x128x64 systems:
     learned (trained and untrained) with the FP32 preconditioner, BILU(0)
     natural order in FP64 (plain CPTR) and BILU(0) multicolour in FP32."""
@@ -172,10 +175,12 @@ def held_out_eval(cfg, model, restart, log_fn):
         b = torch.as_tensor(pr.b, device="cuda")
         row = {"seed": seed}
         untrained = cptr.LearnModel(pr.nv, neumann_params(pr.nv, seed=1))
-        for tag, opt, mdl in (("learned", dict(precision="fp32", second_stage="learned"), model),
-                              ("untrained", dict(precision="fp32", second_stage="learned"), untrained),
-                              ("fp64_bilu0", dict(precision="fp64", second_stage="bilu0"), None),
-                              ("fp32_bilu0_mc", dict(precision="fp32", second_stage="bilu0_mc"), None)):
+        for tag, opt, mdl in (("learned", dict(precision="fp32", second_stage="learned", first_stage=first), model),
+                              ("untrained", dict(precision="fp32", second_stage="learned", first_stage=first),
+                               untrained),
+                              ("fp64_bilu0", dict(precision="fp64", second_stage="bilu0", first_stage="cptr"), None),
+                              ("fp32_bilu0_mc", dict(precision="fp32", second_stage="bilu0_mc", first_stage=first),
+                               None)):
             s = cptr.Solver(pr, **opt)
             if mdl is not None:
                 mdl.attach(s)
@@ -226,8 +231,13 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="learned")
-    ap.add_argument("--train-steps", type=int, default=400)
+    ap.add_argument("--train-steps", type=int, default=1000)
     ap.add_argument("--train-lr", type=float, default=1e-5)
+    ap.add_argument("--train-systems", type=int, default=8)
+    ap.add_argument("--train-pairs", type=int, default=48)
+    ap.add_argument("--train-batch", type=int, default=8)
+    ap.add_argument("--first", default="cptr", choices=["cptr", "cptr_lower", "cpr"],
+                    help="first stage of the learned and BILU(0)-FP32 legs (plain FP64 CPTR stays cptr)")
     ap.add_argument("--cpu-iters", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the FP64 and BILU(0) legs")
@@ -284,10 +294,11 @@ def main():
                     cell_iters_per_s=round(pr.n * info["iters"] / dt, 1), setup_s=round(setup_s, 3),
                     relres_true=info["relres_true"])
 
-    model, train_info = train_model(cfg, args.train_steps, args.train_lr, log)
+    model, train_info = train_model(cfg, args.train_steps, args.train_lr, args.train_systems,
+                                    args.train_pairs, args.train_batch, args.first, log)
 
     # the measured configuration: learned second stage, FP32 preconditioner
-    sl, setup_l = setup(precision="fp32", second_stage="learned")
+    sl, setup_l = setup(precision="fp32", second_stage="learned", first_stage=args.first)
     model.attach(sl)
     dt, info, x_l = run(sl, args.steps, args.warmup, "learned+fp32")
     roof = layer_roofline(sl)
@@ -301,11 +312,11 @@ def main():
         compare["fp64_cptr_bilu0"] = leg(d64, i64, su)
         spmv = spmv_roofline(pr, s64)
         s64.close()
-        smc, su = setup(precision="fp32", second_stage="bilu0_mc")
+        smc, su = setup(precision="fp32", second_stage="bilu0_mc", first_stage=args.first)
         dmc, imc, _ = run(smc, 2, 1, "fp32 bilu0 multicolour")
         compare["fp32_cptr_bilu0_mc"] = leg(dmc, imc, su)
         smc.close()
-        sn, su = setup(precision="fp32", second_stage="learned")
+        sn, su = setup(precision="fp32", second_stage="learned", first_stage=args.first)
         mn = cptr.LearnModel(pr.nv, neumann_params(pr.nv, seed=1))
         mn.attach(sn)
         dn, inn, _ = run(sn, 1, 1, "fp32 learned, untrained (Neumann init)")
@@ -318,7 +329,7 @@ def main():
         compare["spmv_fp64"] = spmv
     held = None
     if not args.no_held_out:
-        held = held_out_eval(cfg, model, restart, log)
+        held = held_out_eval(cfg, model, restart, args.first, log)
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(pr, args.cpu_iters)
@@ -337,8 +348,9 @@ def main():
         "dtype": "f32 preconditioner (bf16 MFMA in the learned stage), f64 Krylov",
         "data": "synthetic (seeded thermal Jacobian of the first implicit step, Gaussian ln k field)",
         "config": {"workload": f"{args.config}: {'x'.join(map(str, cfg['shape']))} cells, nv={pr.nv}, "
-                               f"FGMRES({restart}) rtol 1e-6, CPTR-Block(AMG) + learned second stage, "
-                               f"FP32 preconditioner",
+                               f"FGMRES({restart}) rtol 1e-6, {FIRST_NAME[args.first]}(AMG) + learned "
+                               f"second stage, FP32 preconditioner",
+                   "first_stage": args.first,
                    "cells": pr.n, "nnzb": pr.nnzb, "restart": restart},
         "iters": info["iters"],
         "cell_iters_per_s": round(pr.n * info["iters"] / dt, 1),

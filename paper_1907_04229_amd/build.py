@@ -17,6 +17,9 @@ ARCH = os.environ.get("CPTR_OFFLOAD_ARCH", "gfx950")
 HIP_FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
              "-Wall", "-Wno-unused-function", "-Wno-unused-result"]
+# device code: MFMA results in ordinary VGPRs (no AGPR copies); this keeps the
+# learned layer kernel at 128 registers, 4 waves per SIMD
+DEVICE_FLAGS = ["-mllvm", "-amdgpu-mfma-vgpr-form"]
 # host setup code: no floating-point contraction, so that the aggregation
 # decisions and the Galerkin entries are reproducible bit for bit
 HOST_EXACT = ["-ffp-contract=off"]
@@ -41,7 +44,7 @@ def build(verbose=True):
     hipcc = os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "bin", "hipcc")
     objs = []
     for src, extra in (("setup_amg.cpp", HOST_EXACT), ("setup_ilu.cpp", HOST_EXACT),
-                       ("cptr.hip", [])):
+                       ("cptr.hip", DEVICE_FLAGS)):
         obj = os.path.join(CSRC, os.path.splitext(src)[0] + ".o")
         _run([hipcc] + HIP_FLAGS + extra + ["-c", os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)

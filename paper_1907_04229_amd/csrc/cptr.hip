@@ -174,6 +174,21 @@ struct SpOp {
     }
     LAUNCH_CHECK();
   }
+  void jacobi_resid(hipStream_t st, const T *dinv, const T *b, const T *xin, const T *rin, T *xout,
+                    T *rout) const {
+    if (lanes == 1) {
+      hipLaunchKernelGGL((k_jacobi_resid<T>), dim3(nblk(nrows)), dim3(kBlock), 0, st, view, dinv, b, xin, rin,
+                         xout, rout);
+    } else {
+      const int *r = devp<int>(rp), *c = devp<int>(col);
+      const T *v = devp<T>(val);
+      const int g = nblk((size_t)nrows * lanes);
+#define CALL(G) hipLaunchKernelGGL((k_csrv_jacobi_resid<T, G>), dim3(g), dim3(kBlock), 0, st, nrows, r, c, v, dinv, b, xin, rin, xout, rout)
+      CPTR_CSRV_SWITCH(CALL)
+#undef CALL
+    }
+    LAUNCH_CHECK();
+  }
   void smooth0_resid(hipStream_t st, const T *dinv, const T *b, T *x, T *res) const {
     if (lanes == 1) {
       hipLaunchKernelGGL((k_smooth0_resid<T>), dim3(nblk(nrows)), dim3(kBlock), 0, st, view, dinv, b, x, res);
@@ -194,7 +209,7 @@ template <typename T>
 struct AmgDev {
   struct Level {
     SpOp<T> A, P, R;
-    DevMem dinv, b, x, y, r;
+    DevMem dinv, b, x, y, r, r2;
     int n = 0;
   };
   std::vector<std::unique_ptr<Level>> lev;
@@ -219,6 +234,7 @@ struct AmgDev {
       L->x.alloc(L->n * s);
       L->y.alloc(L->n * s);
       L->r.alloc(L->n * s);
+      if (sweeps > 1) L->r2.alloc(L->n * s);
       if (l + 1 < h.lev.size()) {
         L->A.build(H.A);
         L->P.build(H.P);
@@ -230,8 +246,8 @@ struct AmgDev {
           d[i] = T(1.0 / sum);
         }
         upload(L->dinv, d);
-        // pre: sweeps products with A (first fused with the residual), post: sweeps;
-        // restriction and prolongation once each
+        // pre: sweeps passes over A, each leaving the residual of its iterate;
+        // post: sweeps Jacobi passes; restriction and prolongation once each
         double n = L->n;
         bytes_per_cycle += (2.0 * sweeps) * (L->A.bytes() + 3 * n * s)  // A x, b, dinv, x
                            + L->R.bytes() + n * s + H.R.nr * s          // R r
@@ -260,18 +276,18 @@ struct AmgDev {
     T *x = devp<T>(L.x), *y = devp<T>(L.y), *r = devp<T>(L.r);
     const T *dinv = devp<T>(L.dinv);
     const Level &C = *lev[l + 1];
-    // pre-smoothing from zero + residual
-    if (sweeps == 1) {
-      L.A.smooth0_resid(st, dinv, b, x, r);
-    } else {
-      L.A.smooth0_resid(st, dinv, b, x, r);
-      T *cur = x, *nxt = y;
+    // pre-smoothing from zero; every pass leaves the residual of its iterate
+    L.A.smooth0_resid(st, dinv, b, x, r);
+    if (sweeps > 1) {
+      T *cx = x, *nx = y, *cr = r, *nr = devp<T>(L.r2);
       for (int s = 1; s < sweeps; s++) {
-        L.A.jacobi(st, dinv, b, cur, nxt);
-        std::swap(cur, nxt);
+        L.A.jacobi_resid(st, dinv, b, cx, cr, nx, nr);
+        std::swap(cx, nx);
+        std::swap(cr, nr);
       }
-      if (cur != x) std::swap(x, y);  // keep the iterate in x
-      L.A.template spmv<2>(st, x, b, r);
+      x = cx;  // the iterate and its residual, wherever they ended
+      y = nx;
+      r = cr;
     }
     // restriction, coarse correction, prolongation
     L.R.template spmv<0>(st, r, nullptr, devp<T>(C.b));
@@ -582,7 +598,8 @@ template <typename T>
 struct Precond : PrecondBase {
   Options op;
   const int *rp = nullptr, *ci = nullptr;  // device pattern (caller's)
-  DevMem acol;                             // p/T columns of A as nv x 2 blocks
+  DevMem acol;                             // p/T columns of A (nv x 2 per block), sliced layout
+  const int *sl_kptr = nullptr, *sl_cols = nullptr;  // slicing of the handle's copy of A
   SpOp<T> ApT, ATp;
   AmgDev<T> amg_p, amg_s;
   IluDev<T> ilu;
@@ -637,7 +654,7 @@ struct Precond : PrecondBase {
       LAUNCH_CHECK();
       return;
     }
-    hipLaunchKernelGGL((k_resid_pT<NV, T>), dim3(nblk((size_t)n * NV)), dim3(kBlock), 0, st, n, rp, ci,
+    hipLaunchKernelGGL((k_resid_pT_sliced<NV, T>), dim3((n + 63) / 64), dim3(64 * NV), 0, st, n, sl_kptr, sl_cols,
                        devp<T>(acol), slots, x1p() ? x1p() : (const T *)zero_vec(), x1T(), b1p);
     LAUNCH_CHECK();
     if (ss == CPTR_SECOND_LEARNED && !fell_back) {
@@ -725,6 +742,7 @@ struct cptr_handle {
   std::unique_ptr<cptr::PrecondBase> pc;
   cptr::DevMem slots;                 // ApplySlots
   cptr::DevMem sl_kptr, sl_cols, sl_vals;  // sliced copy of A for the FP64 products
+  std::vector<int> sl_kptr_host;          // its slice pointers (setup only)
   hipStream_t stream = nullptr;       // internal stream (default priority)
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
   cptr_stats stats{};
@@ -756,14 +774,26 @@ static void build_precond(cptr_handle *h, const std::vector<int> &rp, const std:
   P.rp = h->rp;
   P.ci = h->ci;
   const size_t s = sizeof(T);
-  // a0: p/T columns of A and the scalar sub-blocks on the cell graph
-  std::vector<T> acol((size_t)nnzb * nv * 2);
-  for (int k = 0; k < nnzb; k++)
-    for (int r = 0; r < nv; r++) {
-      acol[((size_t)k * nv + r) * 2 + 0] = T(vals[((size_t)k * nv + r) * nv + o.ip]);
-      acol[((size_t)k * nv + r) * 2 + 1] = T(vals[((size_t)k * nv + r) * nv + o.iT]);
+  // a0: p/T columns of A (in the slicing of the handle's copy of A) and the
+  // scalar sub-blocks on the cell graph
+  const std::vector<int> &kp = h->sl_kptr_host;
+  const int ns = (n + 63) / 64;
+  std::vector<T> acol((size_t)kp[ns] * 64 * nv * 2, T(0));
+  for (int sl = 0; sl < ns; sl++)
+    for (int lane = 0; lane < 64; lane++) {
+      const int i = sl * 64 + lane;
+      if (i >= n) break;
+      for (int k = 0; k < rp[i + 1] - rp[i]; k++) {
+        const size_t kk = (size_t)kp[sl] + k, blk = (size_t)rp[i] + k;
+        for (int r = 0; r < nv; r++) {
+          acol[((kk * nv + r) * 2 + 0) * 64 + lane] = T(vals[(blk * nv + r) * nv + o.ip]);
+          acol[((kk * nv + r) * 2 + 1) * 64 + lane] = T(vals[(blk * nv + r) * nv + o.iT]);
+        }
+      }
     }
   upload(P.acol, acol);
+  P.sl_kptr = devp<int>(h->sl_kptr);
+  P.sl_cols = devp<int>(h->sl_cols);
   auto sub = [&](int r, int c) {
     HostCSR a;
     a.nr = a.nc = n;
@@ -890,6 +920,7 @@ static void build_sliced(cptr_handle *h, const std::vector<int> &rp, const std::
   upload(h->sl_kptr, kptr);
   upload(h->sl_cols, cols);
   upload(h->sl_vals, sv);
+  h->sl_kptr_host = std::move(kptr);
 }
 
 static void validate_and_fetch(const cptr_bsr *A, const cptr_csr *S, const cptr_options &o,

@@ -70,6 +70,28 @@ __global__ void __launch_bounds__(kBlock) k_jacobi(Sell<T> A, const T *__restric
   xout[row] = xin[row] + dinv[row] * (b[row] - ax);
 }
 
+// One Jacobi sweep from an iterate whose residual is known, and the residual
+// of the result, in one pass over A:
+//   x_out = x_in + D^{-1} r_in,  r_out = b - A x_out
+// (x_out of the neighbours formed on the fly from x_in, r_in, D^{-1}).
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_jacobi_resid(Sell<T> A, const T *__restrict__ dinv,
+                                                         const T *__restrict__ b, const T *__restrict__ xin,
+                                                         const T *__restrict__ rin, T *__restrict__ xout,
+                                                         T *__restrict__ rout) {
+  const int row = blockIdx.x * kBlock + threadIdx.x;
+  if (row >= A.nrows) return;
+  const int s = row >> 6, lane = row & 63;
+  const int base = A.sptr[s], w = (A.sptr[s + 1] - base) >> 6;
+  T acc = T(0);
+  for (int k = 0; k < w; k++) {
+    const int c = A.col[base + k * kSlice + lane];
+    acc += A.val[base + k * kSlice + lane] * (xin[c] + dinv[c] * rin[c]);
+  }
+  xout[row] = xin[row] + dinv[row] * rin[row];
+  rout[row] = b[row] - acc;
+}
+
 // ---------------------------------------------------------------------------
 // CSR products with G lanes per row, for operators with long rows (coarse
 // AMG levels, restriction): lanes stride the row, then an xor-shuffle sum.
@@ -143,6 +165,32 @@ __global__ void __launch_bounds__(kBlock) k_csrv_smooth0_resid(int n, const int 
   r[row] = bi - acc;
 }
 
+// x_out = x_in + D^{-1} r_in, r_out = b - A x_out with G lanes per row
+template <typename T, int G>
+__global__ void __launch_bounds__(kBlock) k_csrv_jacobi_resid(int n, const int *__restrict__ rp,
+                                                              const int *__restrict__ ci,
+                                                              const T *__restrict__ val,
+                                                              const T *__restrict__ dinv,
+                                                              const T *__restrict__ b,
+                                                              const T *__restrict__ xin,
+                                                              const T *__restrict__ rin,
+                                                              T *__restrict__ xout, T *__restrict__ rout) {
+  const int t = blockIdx.x * kBlock + threadIdx.x;
+  const int row = t / G, lane = t % G;
+  if (row >= n) return;
+  T acc = T(0);
+  const int e = rp[row + 1];
+  for (int k = rp[row] + lane; k < e; k += G) {
+    const int c = ci[k];
+    acc += val[k] * (xin[c] + dinv[c] * rin[c]);
+  }
+#pragma unroll
+  for (int off = G / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, G);
+  if (lane != 0) return;
+  xout[row] = xin[row] + dinv[row] * rin[row];
+  rout[row] = b[row] - acc;
+}
+
 // coarsest level: x = A_c^{-1} b with the explicit FP64 inverse; one wave per row
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_coarse_gemv(const double *__restrict__ inv, int nc,
@@ -171,31 +219,36 @@ __global__ void __launch_bounds__(kBlock) k_restrict_pT(int n, int nv, int ip, i
   if (bt) bt[i] = T(v[(size_t)i * nv + iT]);
 }
 
-// b1 = v - A R^T (d_p, d_T): only the p and T columns of each block are used;
-// acol holds them as [block][row r][0: p column, 1: T column].  One thread
-// per (cell, equation).
+// b1 = v - A R^T (d_p, d_T): only the p and T columns of each block are used.
+// On the sliced layout of the FP64 product (slices of 64 block rows;
+// for block column k of slice s the entries (r, j) of its 64 rows are stored
+// contiguously: acol[((kptr[s] + k) NV + r) 2 + j) 64 + lane], padding blocks
+// zero).  Wavefront r forms equation r of the slice's rows.
 template <int NV, typename T>
-__global__ void __launch_bounds__(kBlock) k_resid_pT(int n, const int *__restrict__ rp,
-                                                     const int *__restrict__ ci,
-                                                     const T *__restrict__ acol,
-                                                     const ApplySlots *__restrict__ slots,
-                                                     const T *__restrict__ dp,
-                                                     const T *__restrict__ dT,
-                                                     T *__restrict__ b1) {
-  const int t = blockIdx.x * kBlock + threadIdx.x;
-  const int i = t / NV, r = t - i * NV;
-  if (i >= n) return;
+__global__ void __launch_bounds__(64 * NV) k_resid_pT_sliced(int n, const int *__restrict__ kptr,
+                                                              const int *__restrict__ cols,
+                                                              const T *__restrict__ acol,
+                                                              const ApplySlots *__restrict__ slots,
+                                                              const T *__restrict__ dp,
+                                                              const T *__restrict__ dT,
+                                                              T *__restrict__ b1) {
+  const int r = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int sl = blockIdx.x, i = sl * 64 + lane;
+  const int k0 = kptr[sl], k1 = kptr[sl + 1];
   T acc = T(0);
-  const int e = rp[i + 1];
   if (dT) {
-    for (int k = rp[i]; k < e; k++) {
-      const int c = ci[k];
-      const T *a = acol + ((size_t)k * NV + r) * 2;
-      acc += a[0] * dp[c] + a[1] * dT[c];
+#pragma unroll 4
+    for (int k = k0; k < k1; k++) {
+      const int c = cols[(size_t)k * 64 + lane];
+      const T *a = acol + ((size_t)k * NV + r) * 2 * 64 + lane;
+      acc += a[0] * dp[c] + a[64] * dT[c];
     }
   } else {
-    for (int k = rp[i]; k < e; k++) acc += acol[((size_t)k * NV + r) * 2] * dp[ci[k]];
+#pragma unroll 4
+    for (int k = k0; k < k1; k++)
+      acc += acol[((size_t)k * NV + r) * 2 * 64 + lane] * dp[cols[(size_t)k * 64 + lane]];
   }
+  if (i >= n) return;
   b1[(size_t)i * NV + r] = T(slots->v[(size_t)i * NV + r]) - acc;
 }
 

@@ -36,6 +36,18 @@ __device__ __forceinline__ f32x4 mfma16(bf16x4 a, bf16x4 b, f32x4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
 }
 
+// 16x16x32 BF16 MFMA (gfx950): A 16 x 32, lane holds A[l % 16][8 (l / 16) + j];
+// B 32 x 16, lane holds B[8 (l / 16) + j][l % 16]; D as for 16x16x16.
+typedef short bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+__device__ __forceinline__ f32x4 mfma32(bf16x8 a, bf16x8 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, a), __builtin_bit_cast(bf16x8_t, b),
+                                                 c, 0, 0, 0);
+}
+__device__ __forceinline__ bf16x8 cat8(bf16x4 x, bf16x4 y) {
+  return __builtin_shufflevector(x, y, 0, 1, 2, 3, 4, 5, 6, 7);
+}
+
 __device__ __forceinline__ bf16x4 load_bf4(const short *p) {
   return *reinterpret_cast<const bf16x4 *>(p);
 }
@@ -155,6 +167,13 @@ __device__ __forceinline__ void store_h4(short *p, f32x4 v) {
   *reinterpret_cast<bf16x4 *>(p) = cvt4(v[0], v[1], v[2], v[3]);
 }
 
+// Channel map of the layer kernel: register slot t (0..3) of a lane in lane
+// group lg holds the four consecutive hidden channels lch(t, lg) .. + 3.  With
+// this order the slots 2 ks and 2 ks + 1 of a lane are exactly the eight
+// consecutive channels 32 ks + 8 lg .. + 7 that a 16x16x32 B operand takes;
+// activations stay in channel order in memory.
+__device__ __forceinline__ int lch(int t, int lg) { return 32 * (t >> 1) + 8 * lg + 4 * (t & 1); }
+
 // Neighbour activations as loaded (before conversion): BF16 or FP32 rows of
 // the lane's 16 channels, or, for the first layer, the nv values of r from
 // which h0 = W_in (r / s) is formed.
@@ -166,7 +185,7 @@ struct RawAct<short, NV, false> {
   static __device__ __forceinline__ type load(int cell, int lg, const short *h, const float *) {
     type o;
 #pragma unroll
-    for (int t = 0; t < 4; t++) o.v[t] = load_bf4(h + (size_t)cell * kHid + 16 * t + 4 * lg);
+    for (int t = 0; t < 4; t++) o.v[t] = load_bf4(h + (size_t)cell * kHid + lch(t, lg));
     return o;
   }
   static __device__ __forceinline__ f32x4 get(const type &o, int t, int, const float *, const float *) {
@@ -179,7 +198,7 @@ struct RawAct<float, NV, false> {
   static __device__ __forceinline__ type load(int cell, int lg, const float *h, const float *) {
     type o;
 #pragma unroll
-    for (int t = 0; t < 4; t++) o.v[t] = load_f4(h + (size_t)cell * kHid + 16 * t + 4 * lg);
+    for (int t = 0; t < 4; t++) o.v[t] = load_f4(h + (size_t)cell * kHid + lch(t, lg));
     return o;
   }
   static __device__ __forceinline__ f32x4 get(const type &o, int t, int, const float *, const float *) {
@@ -200,7 +219,7 @@ struct RawAct<HT, NV, true> {
     f32x4 h;
 #pragma unroll
     for (int q = 0; q < 4; q++) {
-      const int ch = 16 * t + 4 * lg + q;
+      const int ch = lch(t, lg) + q;
       float v = 0.f;
 #pragma unroll
       for (int k = 0; k < NV; k++) v += W_in[ch * NV + k] * (o.u[k] * inv_s[k]);
@@ -214,13 +233,13 @@ struct RawAct<HT, NV, true> {
 // each wave loops over tiles.
 constexpr int kLayerMaxBlocks = 2048;
 constexpr int kXcds = 8;  // accelerator complex dies of the MI355X, each with its own L2
-constexpr int kWPad = kHid + 4;  // LDS row of W_s / W_m (BF16), padded against bank conflicts
+constexpr int kWPad = kHid + 8;  // LDS row of W_s / W_m (BF16): padded, 16-byte aligned
 
 // One message-passing layer.  One wavefront per tile of 16 consecutive cells;
-// lane l owns cell c0 + l % 16 and the hidden channels 16 t + 4 (l / 16) + q
+// lane l owns cell c0 + l % 16 and the hidden channels lch(t, l / 16) + q
 // (t, q = 0..3).  The weights are the MFMA A operand and the activations the
 // B operand, so every product comes out with cells along the lanes:
-//   g^T = W_e e^T (per direction),  a^T = W_s h^T + W_m m^T
+//   g^T = W_e e^T (per direction, 16x16x16),  a^T = W_s h^T + W_m m^T (16x16x32)
 // and the messages m = sum_d g * h_nbr, accumulated in that layout, are
 // directly the B operand of W_m.  Activations are read and written as four
 // consecutive channels per lane (HT: FP32 or BF16 in memory).  W_s and W_m
@@ -237,7 +256,7 @@ __global__ void __launch_bounds__(kBlock) k_lrn_layer(
     const float *__restrict__ W_e, const short *__restrict__ W_s, const short *__restrict__ W_m,
     const float *__restrict__ bias, HT *__restrict__ hout, float *__restrict__ h0_out,
     float *__restrict__ m_out, float *__restrict__ a_out, LrnOut<ZT, XT> out) {
-  __shared__ short Wl[2][kHid][kWPad];
+  __shared__ __attribute__((aligned(16))) short Wl[2][kHid][kWPad];
   for (int v = threadIdx.x; v < 2 * kHid * kHid / 4; v += kBlock) {
     const int mtx = v / (kHid * kHid / 4), e = (v % (kHid * kHid / 4)) * 4;
     const short *src = (mtx == 0 ? W_s : W_m) + e;
@@ -260,8 +279,9 @@ __global__ void __launch_bounds__(kBlock) k_lrn_layer(
   for (int t = 0; t < 4; t++)
 #pragma unroll
     for (int q = 0; q < 4; q++) {
-      const int k = 4 * lg + q;
-      we[t][q] = k < NV * NV ? f2bf(W_e[(16 * t + lr) * NV * NV + k] * edge_factor<NV>(k, s_ptr)) : short(0);
+      // row lr of output tile t is channel lch(t, lr / 4) + lr % 4
+      const int k = 4 * lg + q, row = lch(t, lr >> 2) + (lr & 3);
+      we[t][q] = k < NV * NV ? f2bf(W_e[row * NV * NV + k] * edge_factor<NV>(k, s_ptr)) : short(0);
     }
   // activations of `cell` at this lane's channels (FIRST: from r)
   auto act = [&](int cell, f32x4 *h) {
@@ -273,7 +293,7 @@ __global__ void __launch_bounds__(kBlock) k_lrn_layer(
       for (int t = 0; t < 4; t++)
 #pragma unroll
         for (int q = 0; q < 4; q++) {
-          const int ch = 16 * t + 4 * lg + q;
+          const int ch = lch(t, lg) + q;
           float v = 0.f;
 #pragma unroll
           for (int k = 0; k < NV; k++) v += W_in[ch * NV + k] * u[k];
@@ -281,7 +301,7 @@ __global__ void __launch_bounds__(kBlock) k_lrn_layer(
         }
     } else {
 #pragma unroll
-      for (int t = 0; t < 4; t++) h[t] = load_h4(hin + (size_t)cell * kHid + 16 * t + 4 * lg);
+      for (int t = 0; t < 4; t++) h[t] = load_h4(hin + (size_t)cell * kHid + lch(t, lg));
     }
   };
   const int off[kDir] = {-stride.x, stride.x, -stride.y, stride.y, -stride.z, stride.z};
@@ -332,15 +352,19 @@ __global__ void __launch_bounds__(kBlock) k_lrn_layer(
 #pragma unroll
     for (int t = 0; t < 4; t++) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int ks = 0; ks < 4; ks++) {
-      const bf16x4 hb = cvt4(hv[ks][0], hv[ks][1], hv[ks][2], hv[ks][3]);
-      const bf16x4 mb = cvt4(macc[ks][0], macc[ks][1], macc[ks][2], macc[ks][3]);
+    for (int ks = 0; ks < 2; ks++) {
+      // B operands: channels 32 ks + 8 lg .. + 7 = slots 2 ks, 2 ks + 1
+      const bf16x8 hb = cat8(cvt4(hv[2 * ks][0], hv[2 * ks][1], hv[2 * ks][2], hv[2 * ks][3]),
+                             cvt4(hv[2 * ks + 1][0], hv[2 * ks + 1][1], hv[2 * ks + 1][2], hv[2 * ks + 1][3]));
+      const bf16x8 mb = cat8(cvt4(macc[2 * ks][0], macc[2 * ks][1], macc[2 * ks][2], macc[2 * ks][3]),
+                             cvt4(macc[2 * ks + 1][0], macc[2 * ks + 1][1], macc[2 * ks + 1][2], macc[2 * ks + 1][3]));
 #pragma unroll
       for (int t = 0; t < 4; t++) {
-        const bf16x4 ws = *reinterpret_cast<const bf16x4 *>(&Wl[0][16 * t + lr][16 * ks + 4 * lg]);
-        const bf16x4 wm = *reinterpret_cast<const bf16x4 *>(&Wl[1][16 * t + lr][16 * ks + 4 * lg]);
-        acc[t] = mfma16(ws, hb, acc[t]);
-        acc[t] = mfma16(wm, mb, acc[t]);
+        const int row = lch(t, lr >> 2) + (lr & 3);
+        const bf16x8 ws = *reinterpret_cast<const bf16x8 *>(&Wl[0][row][32 * ks + 8 * lg]);
+        const bf16x8 wm = *reinterpret_cast<const bf16x8 *>(&Wl[1][row][32 * ks + 8 * lg]);
+        acc[t] = mfma32(ws, hb, acc[t]);
+        acc[t] = mfma32(wm, mb, acc[t]);
       }
     }
     f32x4 hnew[4];
@@ -349,11 +373,11 @@ __global__ void __launch_bounds__(kBlock) k_lrn_layer(
       f32x4 a;
 #pragma unroll
       for (int q = 0; q < 4; q++) {
-        a[q] = acc[t][q] + bias[16 * t + 4 * lg + q];
+        a[q] = acc[t][q] + bias[lch(t, lg) + q];
         hnew[t][q] = hv[t][q] + fmaxf(a[q], 0.f);
       }
       if (ok) {
-        const size_t o = (size_t)cell * kHid + 16 * t + 4 * lg;
+        const size_t o = (size_t)cell * kHid + lch(t, lg);
         if (hout) store_h4(hout + o, hnew[t]);
         if (m_out) store_f4(m_out + o, macc[t]);
         if (a_out) store_f4(a_out + o, a);
@@ -368,7 +392,7 @@ __global__ void __launch_bounds__(kBlock) k_lrn_layer(
 #pragma unroll
         for (int t = 0; t < 4; t++)
 #pragma unroll
-          for (int q = 0; q < 4; q++) v += out.W_out[k * kHid + 16 * t + 4 * lg + q] * hnew[t][q];
+          for (int q = 0; q < 4; q++) v += out.W_out[k * kHid + lch(t, lg) + q] * hnew[t][q];
         v += __shfl_xor(v, 16);
         v += __shfl_xor(v, 32);
         p[k] = v;
