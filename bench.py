@@ -323,6 +323,21 @@ def main():
         compare["fp32_cptr_learned_untrained"] = leg(dn, inn, su)
         sn.close()
         mn.close()
+        # context: the same stages behind the CPR first stage (one A_pp V-cycle)
+        for tag, opt, mdl_needed in (("fp64_cpr_bilu0", dict(precision="fp64", second_stage="bilu0"), False),
+                                     ("fp32_cpr_bilu0_mc", dict(precision="fp32", second_stage="bilu0_mc"), False),
+                                     ("fp32_cpr_learned_untrained", dict(precision="fp32", second_stage="learned"),
+                                      True)):
+            sc, su = setup(first_stage="cpr", **opt)
+            mc_ = None
+            if mdl_needed:
+                mc_ = cptr.LearnModel(pr.nv, neumann_params(pr.nv, seed=1))
+                mc_.attach(sc)
+            dc, ic, _ = run(sc, 1, 1, tag)
+            compare[tag] = leg(dc, ic, su)
+            sc.close()
+            if mc_ is not None:
+                mc_.close()
         compare["speedup_vs_fp64"] = round(d64 / dt, 3)
         compare["solution_rel_diff_vs_fp64"] = float(torch.linalg.vector_norm(x_l - x64) /
                                                      torch.linalg.vector_norm(x64))
