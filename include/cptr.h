@@ -65,7 +65,7 @@ extern "C" {
 #define CPTR_SECOND_BILU0 1      /* block ILU(0), natural order, level-scheduled solves */
 #define CPTR_SECOND_BILU0_MC 2   /* block ILU(0) in greedy multicolour order */
 #define CPTR_SECOND_IDENTITY 3   /* z = b1 + x1 */
-#define CPTR_SECOND_LEARNED 4    /* learned message-passing stage (cptr_learn.h), BILU(0) multicolour fallback */
+#define CPTR_SECOND_LEARNED 4    /* learned message-passing stage (cptr_learn.h), BILU(0) natural-order fallback */
 
 /* precision of the preconditioner (FGMRES itself is always FP64) */
 #define CPTR_FP64 0
@@ -99,7 +99,15 @@ typedef struct {
   unsigned amg_seed;     /* aggregation priority seed (0) */
   int amg_sweeps;        /* l1-Jacobi sweeps before and after the coarse correction (2) */
   int amg_smooth_p;      /* 1 smoothed aggregation, 0 plain aggregation (1) */
+  int amg_smooth_p_T;    /* the same for the S~_T hierarchy alone; -1: as amg_smooth_p (0).
+                            Plain aggregation keeps the S~_T V-cycle convergent where the
+                            smoothed prolongator does not (rows that are not diagonally
+                            dominant, three-phase systems) and needs fewer FGMRES iterations
+                            on the two-phase systems too */
   int use_graph;         /* 1: replay the preconditioner and the Arnoldi step as HIP graphs (1) */
+  int resid_fp64;        /* FP32 mode: form the two-stage residual b1 = v - A x1 from the FP64
+                            values of A with FP64 accumulation, then round b1 to FP32 (0).
+                            Avoids the FP32 cancellation of b1 on badly scaled systems. */
 } cptr_options;
 
 typedef struct {

@@ -857,7 +857,7 @@ void *orc_create(int n, int nv, const int *rp, const int *ci, const double *vals
                     o->first_stage == ORC_FIRST_CPTR_LOWER)) {
       csr s = csr_copy(n, srp, sci, svals);
       st = amg_setup(&h->amg_s, s, o->theta, o->max_levels, o->coarse_size, o->seed,
-                     o->sweeps, o->smooth_p, o->smoother);
+                     o->sweeps, o->smooth_p_T < 0 ? o->smooth_p : o->smooth_p_T, o->smoother);
       h->have_s = 1;
     }
   }

@@ -40,6 +40,7 @@ typedef struct {
   int smoother;        /* 0: l1-Jacobi, 1: multicolour Gauss-Seidel (symmetric) */
   const int *ilu_order;/* BILU0 factor order (position -> cell) or NULL */
   const int *ilu_part; /* BILU0 partition (cell -> part, couplings across parts dropped) or NULL */
+  int smooth_p_T;      /* prolongator of the S~_T hierarchy: 1 smoothed, 0 plain, -1 as smooth_p */
 } orc_opts;
 
 typedef struct {

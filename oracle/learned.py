@@ -103,12 +103,15 @@ def n_params(nv):
     return HIDDEN * nv + LAYERS * (HIDDEN * nv * nv + 2 * HIDDEN * HIDDEN + HIDDEN) + nv * HIDDEN
 
 
-def forward(theta, b1, dinv, E, nbr, nv):
-    """z2 and the intermediate values of the backward pass."""
+def forward(theta, b1, dinv, E, nbr, nv, s=None):
+    """z2 and the intermediate values of the backward pass.  `s` (optional)
+    gives the per-unknown scales instead of the RMS over these cells, so that
+    a neighbourhood cut out of a larger system uses that system's scales."""
     p = unflatten(np.asarray(theta, np.float64), nv)
     n = dinv.shape[0]
     r = np.einsum("irc,ic->ir", dinv, b1.reshape(n, nv))
-    s = np.sqrt(np.mean(r * r, axis=0))
+    if s is None:
+        s = np.sqrt(np.mean(r * r, axis=0))
     inv = np.where(s > 0.0, 1.0 / np.where(s > 0.0, s, 1.0), 0.0)
     cache = dict(s=s, r=r)
     u = r * inv

@@ -32,7 +32,7 @@ class _Opts(C.Structure):
                 ("iT", C.c_int), ("theta", C.c_double), ("max_levels", C.c_int),
                 ("coarse_size", C.c_int), ("seed", C.c_uint), ("sweeps", C.c_int),
                 ("smooth_p", C.c_int), ("smoother", C.c_int), ("ilu_order", C.c_void_p),
-                ("ilu_part", C.c_void_p)]
+                ("ilu_part", C.c_void_p), ("smooth_p_T", C.c_int)]
 
 
 class _Info(C.Structure):
@@ -128,7 +128,7 @@ class Oracle:
     def __init__(self, n, nv, row_ptr, col, vals, st_row_ptr=None, st_col=None,
                  st_vals=None, first="cptr", second="bilu0", ip=0, iT=None,
                  theta=0.08, max_levels=10, coarse_size=512, seed=0, sweeps=2,
-                 smooth_p=True, smoother="jacobi", ilu_order=None, ilu_part=None):
+                 smooth_p=True, smoother="jacobi", ilu_order=None, ilu_part=None, smooth_p_T=False):
         self.n, self.nv = n, nv
         self._keep = [_ci(row_ptr), _ci(col), _cd(vals)]
         if st_row_ptr is None:
@@ -145,7 +145,8 @@ class Oracle:
                 extra[q] = a.ctypes.data
         o = _Opts(FIRST[first], SECOND[second], ip, nv - 1 if iT is None else iT,
                   theta, max_levels, coarse_size, seed, sweeps, int(bool(smooth_p)),
-                  {"jacobi": 0, "gs": 1}[smoother], extra[0], extra[1])
+                  {"jacobi": 0, "gs": 1}[smoother], extra[0], extra[1],
+                  -1 if smooth_p_T is None else int(bool(smooth_p_T)))
         status = C.c_int(0)
         rp, ci, v, srp, sci, sv = self._keep[:6]
         self.h = lib().orc_create(n, nv, _i(rp), _i(ci), _d(v), _i(srp), _i(sci), _d(sv),

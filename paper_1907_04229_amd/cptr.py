@@ -25,7 +25,8 @@ class Options(C.Structure):
                 ("ip", C.c_int), ("iT", C.c_int), ("amg_theta", C.c_double),
                 ("amg_max_levels", C.c_int), ("amg_coarse_size", C.c_int),
                 ("amg_seed", C.c_uint), ("amg_sweeps", C.c_int), ("amg_smooth_p", C.c_int),
-                ("use_graph", C.c_int)]
+                ("amg_smooth_p_T", C.c_int),
+                ("use_graph", C.c_int), ("resid_fp64", C.c_int)]
 
 
 class Bsr(C.Structure):

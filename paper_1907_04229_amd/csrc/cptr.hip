@@ -600,6 +600,7 @@ struct Precond : PrecondBase {
   const int *rp = nullptr, *ci = nullptr;  // device pattern (caller's)
   DevMem acol;                             // p/T columns of A (nv x 2 per block), sliced layout
   const int *sl_kptr = nullptr, *sl_cols = nullptr;  // slicing of the handle's copy of A
+  const double *sl_vals64 = nullptr;  // its FP64 values, when b1 is formed in FP64
   SpOp<T> ApT, ATp;
   AmgDev<T> amg_p, amg_s;
   IluDev<T> ilu;
@@ -654,8 +655,13 @@ struct Precond : PrecondBase {
       LAUNCH_CHECK();
       return;
     }
-    hipLaunchKernelGGL((k_resid_pT_sliced<NV, T>), dim3((n + 63) / 64), dim3(64 * NV), 0, st, n, sl_kptr, sl_cols,
-                       devp<T>(acol), slots, x1p() ? x1p() : (const T *)zero_vec(), x1T(), b1p);
+    if (sl_vals64)
+      hipLaunchKernelGGL((k_resid_pT_sliced64<NV, T>), dim3((n + 63) / 64), dim3(64 * NV), 0, st, n, sl_kptr,
+                         sl_cols, sl_vals64, op.o.ip, op.o.iT, slots, x1p() ? x1p() : (const T *)zero_vec(), x1T(),
+                         b1p);
+    else
+      hipLaunchKernelGGL((k_resid_pT_sliced<NV, T>), dim3((n + 63) / 64), dim3(64 * NV), 0, st, n, sl_kptr,
+                         sl_cols, devp<T>(acol), slots, x1p() ? x1p() : (const T *)zero_vec(), x1T(), b1p);
     LAUNCH_CHECK();
     if (ss == CPTR_SECOND_LEARNED && !fell_back) {
       if (!model || !lrn) throw Error{CPTR_ERR_INVALID_ARG, "no learned model attached to this handle"};
@@ -778,8 +784,14 @@ static void build_precond(cptr_handle *h, const std::vector<int> &rp, const std:
   // scalar sub-blocks on the cell graph
   const std::vector<int> &kp = h->sl_kptr_host;
   const int ns = (n + 63) / 64;
-  std::vector<T> acol((size_t)kp[ns] * 64 * nv * 2, T(0));
-  for (int sl = 0; sl < ns; sl++)
+  P.sl_kptr = devp<int>(h->sl_kptr);
+  P.sl_cols = devp<int>(h->sl_cols);
+  // b1 from the FP64 values of the sliced copy (FP64 mode, or on request), else
+  // from FP32 copies of the p and T columns
+  const bool b1_fp64 = o.resid_fp64 || sizeof(T) == 8;
+  if (b1_fp64) P.sl_vals64 = devp<double>(h->sl_vals);
+  std::vector<T> acol(b1_fp64 ? 0 : (size_t)kp[ns] * 64 * nv * 2, T(0));
+  for (int sl = 0; sl < (b1_fp64 ? 0 : ns); sl++)
     for (int lane = 0; lane < 64; lane++) {
       const int i = sl * 64 + lane;
       if (i >= n) break;
@@ -791,9 +803,7 @@ static void build_precond(cptr_handle *h, const std::vector<int> &rp, const std:
         }
       }
     }
-  upload(P.acol, acol);
-  P.sl_kptr = devp<int>(h->sl_kptr);
-  P.sl_cols = devp<int>(h->sl_cols);
+  if (!b1_fp64) upload(P.acol, acol);
   auto sub = [&](int r, int c) {
     HostCSR a;
     a.nr = a.nc = n;
@@ -820,7 +830,9 @@ static void build_precond(cptr_handle *h, const std::vector<int> &rp, const std:
     P.amg_p.build(hp, o.amg_sweeps);
     if (o.first_stage != CPTR_FIRST_CPR) {
       AmgHost hs;
-      amg_build(*S, prm, hs);
+      AmgParams prm_s = prm;
+      if (o.amg_smooth_p_T >= 0) prm_s.smooth_p = o.amg_smooth_p_T;
+      amg_build(*S, prm_s, hs);
       P.amg_s.build(hs, o.amg_sweeps);
       P.have_s = true;
       P.ApT.build(sub(o.ip, o.iT));
@@ -845,8 +857,8 @@ static void build_precond(cptr_handle *h, const std::vector<int> &rp, const std:
   }
   if (o.second_stage == CPTR_SECOND_BILU0 || o.second_stage == CPTR_SECOND_BILU0_MC ||
       o.second_stage == CPTR_SECOND_LEARNED) {
-    IluHost ih;  // with the learned stage: the multicolour factor of the fallback
-    ilu_build(n, nv, rp.data(), ci.data(), vals.data(), o.second_stage != CPTR_SECOND_BILU0, ih);
+    IluHost ih;  // with the learned stage: the natural-order factor of the fallback (plain ILU(0))
+    ilu_build(n, nv, rp.data(), ci.data(), vals.data(), o.second_stage == CPTR_SECOND_BILU0_MC, ih);
     P.ilu.build(ih);
     P.have_ilu = true;
     if (o.second_stage != CPTR_SECOND_LEARNED) bytes += P.ilu.bytes;
@@ -1354,7 +1366,9 @@ void cptr_default_options(cptr_options *o) {
   o->amg_seed = 0;
   o->amg_sweeps = 2;
   o->amg_smooth_p = 1;
+  o->amg_smooth_p_T = 0;
   o->use_graph = 1;
+  o->resid_fp64 = 0;
 }
 
 int cptr_setup(cptr_handle **out, const cptr_bsr *A, const cptr_csr *S_T, const cptr_options *opt,

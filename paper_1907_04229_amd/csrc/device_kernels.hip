@@ -252,6 +252,38 @@ __global__ void __launch_bounds__(64 * NV) k_resid_pT_sliced(int n, const int *_
   b1[(size_t)i * NV + r] = T(slots->v[(size_t)i * NV + r]) - acc;
 }
 
+// The same from the FP64 values of the sliced copy of A (columns ip and iT of
+// each block are contiguous runs of 64), accumulated in FP64, b1 rounded to T.
+template <int NV, typename T>
+__global__ void __launch_bounds__(64 * NV) k_resid_pT_sliced64(int n, const int *__restrict__ kptr,
+                                                                const int *__restrict__ cols,
+                                                                const double *__restrict__ vals, int ip, int iT,
+                                                                const ApplySlots *__restrict__ slots,
+                                                                const T *__restrict__ dp,
+                                                                const T *__restrict__ dT,
+                                                                T *__restrict__ b1) {
+  const int r = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int sl = blockIdx.x, i = sl * 64 + lane;
+  const int k0 = kptr[sl], k1 = kptr[sl + 1];
+  double acc = 0.0;
+  if (dT) {
+#pragma unroll 4
+    for (int k = k0; k < k1; k++) {
+      const int c = cols[(size_t)k * 64 + lane];
+      const double *a = vals + ((size_t)k * NV * NV + r * NV) * 64 + lane;
+      acc += a[ip * 64] * double(dp[c]) + a[iT * 64] * double(dT[c]);
+    }
+  } else {
+#pragma unroll 4
+    for (int k = k0; k < k1; k++) {
+      const int c = cols[(size_t)k * 64 + lane];
+      acc += vals[((size_t)k * NV * NV + r * NV + ip) * 64 + lane] * double(dp[c]);
+    }
+  }
+  if (i >= n) return;
+  b1[(size_t)i * NV + r] = T(slots->v[(size_t)i * NV + r] - acc);
+}
+
 template <typename T, typename ZT>
 __global__ void __launch_bounds__(kBlock) k_finish(int n, int nv, int ip, int iT,
                                                    const T *__restrict__ b1,

@@ -148,6 +148,32 @@ def test_vcycle_and_first_stage_fp64(name, first):
     s.close()
 
 
+@pytest.mark.parametrize("name", ["ragged", "three", "small"])
+def test_plain_aggregation_for_s_t(name):
+    """amg_smooth_p_T = 0: plain aggregation for the S~_T hierarchy only, against
+    the oracle with the same choice (integers bit-exact, FP64 first stage)."""
+    banner(f"plain S_T hierarchy {name}")
+    pr = prob(name)
+    s = solver(pr, precision="fp64", second_stage="none", amg_coarse_size=16, amg_smooth_p_T=0)
+    o = O.Oracle.from_problem(pr, first="cptr", second="none", coarse_size=16, smooth_p_T=False)
+    for which in (0, 1):
+        ref = o.amg_levels(which)
+        for lev in range(len(ref) - 1):
+            assert np.array_equal(cptr.cptr_get_aggregates(s.h, which, lev, ref[lev]["n"]), ref[lev]["agg"])
+    rng = np.random.default_rng(12)
+    b = rng.standard_normal(pr.n)
+    x = torch.empty(pr.n, dtype=torch.float64, device=DEV)
+    cptr.cptr_vcycle(s.h, 1, dev(b), x)
+    torch.cuda.synchronize()
+    assert relerr(x.cpu().numpy(), o.vcycle(1, b)) <= 1e-10
+    v = rng.standard_normal(pr.n * pr.nv)
+    x1 = torch.empty_like(dev(v))
+    cptr.cptr_first_stage(s.h, dev(v), x1)
+    torch.cuda.synchronize()
+    assert relerr(x1.cpu().numpy(), o.first_stage(v)) <= 1e-10
+    s.close()
+
+
 @pytest.mark.parametrize("name", ["ragged", "three", "small", "chain", "single"])
 @pytest.mark.parametrize("first,second", [("cptr", "bilu0"), ("cptr", "bilu0_mc"),
                                           ("cpr", "bilu0"), ("none", "bilu0"),

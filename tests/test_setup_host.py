@@ -39,7 +39,7 @@ def test_amg_hierarchy_bit_exact(case, which, oracle_lib):
         rp, ci, v = pr.st_row_ptr, pr.st_col_idx, pr.st_vals
     for seed, smooth in ((0, True), (5, True), (0, False)):
         o = O.Oracle.from_problem(pr, first="cptr", second="none", coarse_size=16, seed=seed,
-                                  smooth_p=smooth)
+                                  smooth_p=smooth, smooth_p_T=smooth)
         ref = o.amg_levels(which)
         got = H.amg_levels(rp, ci, v, coarse_size=16, seed=seed, smooth_p=smooth)
         assert len(got) == len(ref) >= 2
