@@ -201,8 +201,18 @@ int cptr_matvec(const cptr_handle *h, const double *x, double *y, void *stream);
  * handle without a solve or j out of range. */
 int cptr_krylov_vector(const cptr_handle *h, int j, double *out, void *stream);
 
-/* Numeric re-setup with an unchanged pattern.  Not available yet: returns
- * CPTR_ERR_UNSUPPORTED. */
+/* Numeric re-setup for a new Jacobian with the pattern of the one given to
+ * cptr_setup (the next Newton iterate or time step; Section 4 solves one such
+ * system per nonlinear iteration).  A_vals: device FP64 BSR values in the
+ * layout of cptr_bsr.vals (the handle borrows this pointer from now on, as it
+ * did the original); S_vals: device FP64 values of S~_T in the pattern given
+ * to cptr_setup (required for CPTR_FIRST_BLOCK / _BLOCK_LOWER, else ignored).
+ * The aggregates of both AMG hierarchies and the BILU(0) schedule are kept;
+ * prolongator values, Galerkin products, the coarsest inverse, the BILU(0)
+ * factor, the sliced copy of A and the learned stage's edge features are
+ * recomputed.  Blocking.  CPTR_ERR_INVALID_ARG for a missing argument,
+ * CPTR_ERR_NONFINITE for a non-finite value, CPTR_ERR_SINGULAR_BLOCK as in
+ * cptr_setup; on error the handle must be destroyed. */
 int cptr_update_values(cptr_handle *h, const double *A_vals, const double *S_vals,
                        void *stream);
 

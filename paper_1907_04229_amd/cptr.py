@@ -265,6 +265,18 @@ class Solver:
         self.h = cptr_setup(self.n, self.nv, self.rp, self.ci, self.vals, self.srp, self.sci,
                             self.svals, self.options)
 
+    def update_values(self, problem):
+        """Numeric re-setup for a system with the same pattern (cptr_update_values)."""
+        import torch
+        assert problem.n == self.n and problem.nv == self.nv
+        assert np.array_equal(problem.row_ptr, self.problem.row_ptr)
+        assert np.array_equal(problem.col_idx, self.problem.col_idx)
+        dev = self.vals.device
+        vals = torch.as_tensor(np.ascontiguousarray(problem.vals), dtype=torch.float64, device=dev)
+        svals = torch.as_tensor(np.ascontiguousarray(problem.st_vals), dtype=torch.float64, device=dev)
+        cptr_update_values(self.h, vals, svals)
+        self.vals, self.svals, self.problem = vals, svals, problem  # the handle borrows them now
+
     def solve(self, b, x=None, **kw):
         import torch
         if not torch.is_tensor(b):

@@ -749,6 +749,7 @@ struct cptr_handle {
   cptr::DevMem slots;                 // ApplySlots
   cptr::DevMem sl_kptr, sl_cols, sl_vals;  // sliced copy of A for the FP64 products
   std::vector<int> sl_kptr_host;          // its slice pointers (setup only)
+  std::vector<int> st_rp, st_ci;          // pattern of S~_T (numeric re-setup)
   hipStream_t stream = nullptr;       // internal stream (default priority)
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
   cptr_stats stats{};
@@ -771,7 +772,9 @@ namespace cptr {
 
 template <typename T>
 static void build_precond(cptr_handle *h, const std::vector<int> &rp, const std::vector<int> &ci,
-                          const std::vector<double> &vals, const HostCSR *S) {
+                          const std::vector<double> &vals, const HostCSR *S,
+                          const std::vector<std::vector<int>> *agg_p = nullptr,
+                          const std::vector<std::vector<int>> *agg_s = nullptr) {
   auto pc = std::make_unique<Precond<T>>();
   Precond<T> &P = *pc;
   const cptr_options &o = h->op.o;
@@ -826,13 +829,13 @@ static void build_precond(cptr_handle *h, const std::vector<int> &rp, const std:
   double bytes = 0.0;
   if (o.first_stage != CPTR_FIRST_NONE) {
     AmgHost hp;
-    amg_build(sub(o.ip, o.ip), prm, hp);
+    amg_build(sub(o.ip, o.ip), prm, hp, agg_p);
     P.amg_p.build(hp, o.amg_sweeps);
     if (o.first_stage != CPTR_FIRST_CPR) {
       AmgHost hs;
       AmgParams prm_s = prm;
       if (o.amg_smooth_p_T >= 0) prm_s.smooth_p = o.amg_smooth_p_T;
-      amg_build(*S, prm_s, hs);
+      amg_build(*S, prm_s, hs, agg_s);
       P.amg_s.build(hs, o.amg_sweeps);
       P.have_s = true;
       P.ApT.build(sub(o.ip, o.iT));
@@ -1402,6 +1405,8 @@ int cptr_setup(cptr_handle **out, const cptr_bsr *A, const cptr_csr *S_T, const 
     build_sliced(h, rp, ci, vals);
     if (o.precision == CPTR_FP32) build_precond<float>(h, rp, ci, vals, &sh);
     else build_precond<double>(h, rp, ci, vals, &sh);
+    h->st_rp = sh.rp;
+    h->st_ci = sh.ci;
     const int nv = A->nv;
     h->stats.spmv_bytes = (double)A->nnzb * (nv * nv * 8.0 + 4) + 4.0 * (A->n + 1) + 2.0 * 8 * A->n * nv;
     CPTR_HIP_TRY(hipDeviceSynchronize());
@@ -1517,8 +1522,70 @@ int cptr_krylov_vector(const cptr_handle *h, int j, double *out, void *stream) {
   return CPTR_OK;
 }
 
-int cptr_update_values(cptr_handle *, const double *, const double *, void *) {
-  return fail(Error{CPTR_ERR_UNSUPPORTED, "numeric re-setup is not available"});
+int cptr_update_values(cptr_handle *h, const double *A_vals, const double *S_vals, void *stream) {
+  if (!h || !A_vals) return fail(Error{CPTR_ERR_INVALID_ARG, "null argument"});
+  const int fs = h->op.o.first_stage;
+  const bool need_s = fs == CPTR_FIRST_BLOCK || fs == CPTR_FIRST_BLOCK_LOWER;
+  if (need_s && !S_vals) return fail(Error{CPTR_ERR_INVALID_ARG, "S~_T values required by this first stage"});
+  try {
+    auto t0 = std::chrono::steady_clock::now();
+    CPTR_HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+    CPTR_HIP_TRY(hipDeviceSynchronize());
+    const int n = h->op.n, nv = h->op.nv, nnzb = h->op.nnzb;
+    std::vector<int> rp(n + 1), ci(nnzb);
+    std::vector<double> vals((size_t)nnzb * nv * nv);
+    CPTR_HIP_TRY(hipMemcpy(rp.data(), h->rp, sizeof(int) * (n + 1), hipMemcpyDeviceToHost));
+    CPTR_HIP_TRY(hipMemcpy(ci.data(), h->ci, sizeof(int) * nnzb, hipMemcpyDeviceToHost));
+    CPTR_HIP_TRY(hipMemcpy(vals.data(), A_vals, sizeof(double) * vals.size(), hipMemcpyDeviceToHost));
+    for (double v : vals)
+      if (!std::isfinite(v)) throw Error{CPTR_ERR_NONFINITE, "non-finite matrix value"};
+    HostCSR sh;
+    if (need_s) {
+      sh.nr = sh.nc = n;
+      sh.rp = h->st_rp;
+      sh.ci = h->st_ci;
+      sh.v.resize(sh.ci.size());
+      CPTR_HIP_TRY(hipMemcpy(sh.v.data(), S_vals, sizeof(double) * sh.v.size(), hipMemcpyDeviceToHost));
+    }
+    // the aggregates of the current hierarchies are kept
+    std::vector<std::vector<int>> agg_p, agg_s;
+    if (fs != CPTR_FIRST_NONE) {
+      const auto *Pf = dynamic_cast<const Precond<float> *>(h->pc.get());
+      const auto *Pd = dynamic_cast<const Precond<double> *>(h->pc.get());
+      auto strip = [](std::vector<std::vector<int>> a) {
+        if (!a.empty()) a.pop_back();  // the coarsest level has no aggregates
+        return a;
+      };
+      agg_p = strip(Pf ? Pf->amg_p.agg : Pd->amg_p.agg);
+      if (need_s) agg_s = strip(Pf ? Pf->amg_s.agg : Pd->amg_s.agg);
+    }
+    h->vals = A_vals;
+    build_sliced(h, rp, ci, vals);
+    LearnedDev *lrn = h->lrn.get();
+    if (h->op.o.precision == CPTR_FP32)
+      build_precond<float>(h, rp, ci, vals, need_s ? &sh : nullptr, &agg_p, need_s ? &agg_s : nullptr);
+    else
+      build_precond<double>(h, rp, ci, vals, need_s ? &sh : nullptr, &agg_p, need_s ? &agg_s : nullptr);
+    if (lrn) {
+      lrn->build(n, nv, rp, ci, vals);  // edge features of the new values
+      if (h->model) h->pc->set_learned(lrn, &h->model->dev);
+    }
+    if (h->graph_exec) {
+      (void)hipGraphExecDestroy(h->graph_exec);
+      (void)hipGraphDestroy(h->graph);
+      h->graph_exec = nullptr;
+      h->graph = nullptr;
+    }
+    h->graph_m = -1;
+    CPTR_HIP_TRY(hipDeviceSynchronize());
+    h->stats.setup_ms =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    return CPTR_OK;
+  } catch (const Error &e) {
+    return fail(e);
+  } catch (const std::bad_alloc &) {
+    return fail(Error{CPTR_ERR_OOM, "host allocation failed"});
+  }
 }
 
 int cptr_get_stats(const cptr_handle *h, cptr_stats *st) {

@@ -46,8 +46,12 @@ struct AmgHost {
   std::vector<double> coarse_inv;  // explicit FP64 inverse of the coarsest operator, row-major
 };
 
-// Throws Error on failure.
-void amg_build(const HostCSR &fine, const AmgParams &prm, AmgHost &out);
+// Throws Error on failure.  With `fixed` (aggregates of every non-coarsest
+// level of an earlier hierarchy on the same pattern), strength and aggregation
+// are skipped and those aggregates reused: only the numerical values of the
+// prolongators, the Galerkin products and the coarsest inverse are recomputed.
+void amg_build(const HostCSR &fine, const AmgParams &prm, AmgHost &out,
+               const std::vector<std::vector<int>> *fixed = nullptr);
 
 // Block ILU(0) in a given row order, FP64 on the host.
 struct IluHost {

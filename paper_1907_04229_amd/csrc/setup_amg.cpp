@@ -324,19 +324,30 @@ std::vector<double> dense_inverse(const HostCSR &a) {
 
 }  // namespace
 
-void amg_build(const HostCSR &fine, const AmgParams &prm, AmgHost &out) {
+void amg_build(const HostCSR &fine, const AmgParams &prm, AmgHost &out,
+               const std::vector<std::vector<int>> *fixed) {
   out.lev.clear();
   out.lev.emplace_back();
   out.lev[0].A = fine;
   double theta = prm.theta;
   int max_levels = std::min(prm.max_levels, 16);
-  while (out.lev.back().A.nr > prm.coarse_size && (int)out.lev.size() < max_levels) {
+  for (;;) {
+    const size_t l = out.lev.size() - 1;
+    if (fixed ? l >= fixed->size() : (out.lev.back().A.nr <= prm.coarse_size || (int)out.lev.size() >= max_levels))
+      break;
     AmgLevelHost &L = out.lev.back();
     int n = L.A.nr;
-    Graph g = strength(L.A, theta);
     std::vector<int> agg;
-    int na = aggregate(g, n, prm.seed, agg);
-    if (na >= n) break;  // no coarsening possible
+    int na = 0;
+    if (fixed) {
+      agg = (*fixed)[l];
+      if ((int)agg.size() != n) throw Error{CPTR_ERR_SETUP, "aggregates do not match the level size"};
+      for (int a : agg) na = std::max(na, a + 1);
+    } else {
+      Graph g = strength(L.A, theta);
+      na = aggregate(g, n, prm.seed, agg);
+      if (na >= n) break;  // no coarsening possible
+    }
     L.agg = agg;
     if (prm.smooth_p)
       L.P = prolongator(L.A, agg, na, true, L.omega);

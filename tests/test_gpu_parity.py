@@ -305,6 +305,66 @@ def test_invalid_inputs_are_rejected():
     assert e.value.code in (-4, -7)
 
 
+@pytest.mark.parametrize("name", ["three", "small"])
+def test_update_values_equals_fresh_setup(name):
+    """cptr_update_values with 2A (and 2 S~_T): the strength test, the
+    prolongator weights and the Galerkin products scale exactly, so the kept
+    aggregates are those a fresh setup of 2A builds, and the results must be
+    bit-identical to it (FP64: first stage, full application, FGMRES)."""
+    banner(f"update_values {name}")
+    pr = prob(name)
+    import copy
+    pr2 = copy.copy(pr)
+    pr2.vals = pr.vals * 2.0
+    pr2.st_vals = pr.st_vals * 2.0
+    s = solver(pr, precision="fp64", second_stage="bilu0", amg_coarse_size=16)
+    s.update_values(pr2)
+    f = solver(pr2, precision="fp64", second_stage="bilu0", amg_coarse_size=16)
+    v = dev(np.random.default_rng(13).standard_normal(pr.n * pr.nv))
+    a, b = torch.empty_like(v), torch.empty_like(v)
+    cptr.cptr_first_stage(s.h, v, a)
+    cptr.cptr_first_stage(f.h, v, b)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    assert torch.equal(s.apply(v), f.apply(v))
+    xa, ia = s.solve(dev(pr.b), restart=30, rtol=1e-6)
+    xb, ib = f.solve(dev(pr.b), restart=30, rtol=1e-6)
+    assert ia["iters"] == ib["iters"] and torch.equal(xa, xb)
+    s.close()
+    f.close()
+
+
+def test_update_values_new_field_converges():
+    """Re-setup for a different permeability field on the same grid: the
+    aggregates of the first field are kept; FGMRES reaches the tolerance with
+    the FP64 true residual recomputed by the oracle, in all precision modes."""
+    banner("update_values, new field")
+    a = make_problem(shape=(12, 10, 6), kind="gaussian", sigma=2.0, corr_len=3.0, seed=31)
+    b = make_problem(shape=(12, 10, 6), kind="gaussian", sigma=2.0, corr_len=3.0, seed=32)
+    for prec, second in (("fp64", "bilu0"), ("fp32", "bilu0_mc")):
+        s = solver(a, precision=prec, second_stage=second)
+        s.update_values(b)
+        x, info = s.solve(dev(b.b), restart=30, rtol=1e-6)
+        r = b.b - O.bsr_spmv(b.row_ptr, b.col_idx, b.vals, b.nv, x.cpu().numpy())
+        rr = np.linalg.norm(r) / np.linalg.norm(b.b)
+        print(f"{prec}: iters {info['iters']} true relres {rr:.2e}")
+        assert info["converged"] and rr <= 1.0001e-6
+        s.close()
+
+
+def test_update_values_rejects_bad_input():
+    banner("update_values errors")
+    pr = prob("small")
+    s = solver(pr, precision="fp64")
+    with pytest.raises(cptr.CptrError):
+        cptr.cptr_update_values(s.h, dev(pr.vals), None)   # CPTR needs S~_T values
+    bad = pr.vals.copy()
+    bad[5] = np.nan
+    with pytest.raises(cptr.CptrError):
+        cptr.cptr_update_values(s.h, dev(bad), dev(pr.st_vals))
+    s.close()
+
+
 def test_deterministic_solution():
     banner("determinism")
     pr = prob("three")
