@@ -15,8 +15,9 @@ done before the timed region and reported separately.
 Training (not timed): the network starts from the Neumann-series
 initialisation and is trained by the library's own kernels on FGMRES Arnoldi
 vectors of eight 64x64x32 systems with seeds 100-107 of the same field model
-(the solved system, seed 200, is held out), keeping the parameters with the
-lowest validation loss.  After the timed run the 128x128x64 systems of seeds
+(the solved system, seed 200, is held out), keeping the parameters whose
+learned-stage FGMRES solves of two validation systems of the solved size
+(seeds 190, 191) take the fewest iterations in total.  After the timed run the 128x128x64 systems of seeds
 200-204 are solved with the trained network, the untrained one and the
 BILU(0) second stages, and their iterations and times reported (skipped with
 `--no-held-out`).
@@ -41,6 +42,7 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "learned_layer_traffic.json")
 LAYER_SRC = os.path.join(ROOT, "paper_1907_04229_amd", "csrc", "learned_kernels.hip")
 FIRST_NAME = {"cptr": "CPTR-Block", "cptr_lower": "CPTR-BlockLower", "cpr": "CPR"}
 TRAIN_SEED0 = 100  # --train-systems N takes the seeds 100 .. 100 + N - 1
+VAL_SEEDS = (190, 191)  # validation fields of the model selection, at full size
 HELD_OUT_SEEDS = (200, 201, 202, 203, 204)
 TRAIN_SHAPE = (64, 64, 32)
 
@@ -145,18 +147,24 @@ def train_model(cfg, steps, lr, systems, pairs, batch, first, log_fn):
     t0 = time.perf_counter()
     seeds = tuple(range(TRAIN_SEED0, TRAIN_SEED0 + systems))
     probs = [make_problem(shape=TRAIN_SHAPE, seed=s, **kw) for s in seeds]
+    # model selection at the size of the solved system (one validation field)
+    vseeds = VAL_SEEDS
+    vprobs = [make_problem(shape=cfg["shape"], seed=s, **kw) for s in vseeds]
     t_gen = time.perf_counter() - t0
     t0 = time.perf_counter()
     model, hist = train(probs, probs[0].nv, steps=steps, batch=batch, pairs=pairs, lr=lr, seed=1,
-                        eval_every=50, precision="fp32", second_stage="bilu0_mc", first_stage=first)
+                        eval_every=50, val_problems=vprobs, val_restart=cfg["restart"], precision="fp32",
+                        second_stage="bilu0_mc", first_stage=first)
     t_train = time.perf_counter() - t0
     log_fn(f"trained {steps} steps in {t_train:.1f} s (data {t_gen:.1f} s); validation "
-           f"{[(k, round(v, 4)) for k, v in hist['val']]}, kept step {hist['best_step']}")
+           f"{[(k, round(v, 4), it) for k, v, it in hist['val']]}, kept step {hist['best_step']}")
     info = dict(train_s=round(t_train, 2), data_s=round(t_gen, 2), steps=steps, lr=lr,
                 systems=f"{len(seeds)} x {'x'.join(map(str, TRAIN_SHAPE))}, seeds {seeds}", pairs=pairs,
                 batch=batch,
-                val_loss_init=round(hist["val"][0][1], 5),
-                val_loss_kept=round(min(v for _, v in hist["val"]), 5), kept_step=hist["best_step"])
+                validation_systems=f"{len(vseeds)} x {'x'.join(map(str, cfg['shape']))}, seeds {vseeds}",
+                val_loss_init=round(hist["val"][0][1], 5), val_iters_init=hist["val"][0][2],
+                val_kept=[(k, round(v, 5), it) for k, v, it in hist["val"] if k == hist["best_step"]][0],
+                kept_step=hist["best_step"])
     return model, info
 
 

@@ -52,7 +52,8 @@ void cptr_learn_destroy(cptr_learn_model *m);
  * must outlive its use by h; nv must match.  Builds the matrix data of the
  * stage on first use (neighbour table, edge features).  A handle of any
  * second stage may be attached for training; only CPTR_SECOND_LEARNED
- * handles apply the model inside cptr_apply / fgmres_solve. */
+ * handles apply the model inside cptr_apply / fgmres_solve.  Attaching (again)
+ * also re-enables the learned stage of a handle that fell back to BILU(0). */
 int cptr_learn_attach(cptr_handle *h, cptr_learn_model *m);
 
 /* z2 = N(b1) for one vector (device FP64 [n*nv] in and out).  Asynchronous. */

@@ -714,6 +714,7 @@ struct Precond : PrecondBase {
   void set_learned(LearnedDev *l, const LearnModelDev *m) override {
     lrn = l;
     model = m;
+    fell_back = false;  // a (re)attached model is tried again
   }
   bool &fallback_flag() override { return fell_back; }
 
@@ -1733,6 +1734,14 @@ int cptr_learn_attach(cptr_handle *h, cptr_learn_model *m) {
     ensure_learned_data(h);
     h->model = m;
     h->pc->set_learned(h->lrn.get(), &m->dev);
+    if (h->graph_exec) {  // a graph captured after a fallback holds the BILU(0) stage
+      CPTR_HIP_TRY(hipDeviceSynchronize());
+      (void)hipGraphExecDestroy(h->graph_exec);
+      (void)hipGraphDestroy(h->graph);
+      h->graph_exec = nullptr;
+      h->graph = nullptr;
+    }
+    h->graph_m = -1;
     return CPTR_OK;
   } catch (const Error &e) {
     return fail(e);

@@ -57,15 +57,20 @@ def training_pairs(solver, count, seed, restart=30, rtol=1e-6):
 
 
 def train(problems, nv, steps=200, batch=4, pairs=16, lr=1e-5, seed=0, log=None,
-          theta0=None, val_frac=0.25, eval_every=25, **solver_opts):
+          theta0=None, val_frac=0.25, eval_every=25, val_problems=None, val_restart=30, **solver_opts):
     """Train one model on the given systems.
 
     The pairs of every system are split into a training and a validation part
-    (the last `val_frac` of them); the parameters with the lowest validation
-    loss seen (checked every `eval_every` steps, the initial ones included)
-    are kept.  Returns (model, history) with history = {"train": loss per step,
-    "val": [(step, validation loss)], "best_step": step of the kept parameters}.
+    (the last `val_frac` of them).  Model selection: with `val_problems`, the
+    parameters (checked every `eval_every` steps, the initial ones included)
+    whose FP32 learned-stage FGMRES(val_restart) solves of those systems to
+    1e-6 take the fewest iterations in total are kept, ties broken by the
+    validation loss; without them, the lowest validation loss.  Returns
+    (model, history) with history = {"train": loss per step, "val":
+    [(step, validation loss, iterations or None)], "best_step": step of the
+    kept parameters}.
     """
+    import torch
     theta = neumann_params(nv, seed=seed) if theta0 is None else theta0
     model = cptr.LearnModel(nv, theta)
     sets = []
@@ -75,6 +80,12 @@ def train(problems, nv, steps=200, batch=4, pairs=16, lr=1e-5, seed=0, log=None,
         data = training_pairs(s, pairs, seed + 1000 + q)
         nval = int(round(val_frac * pairs))
         sets.append((s, data[:pairs - nval], data[pairs - nval:]))
+    vsolv = []
+    for pr in val_problems or ():
+        opts = dict(solver_opts, precision="fp32", second_stage="learned")
+        vs = cptr.Solver(pr, **opts)
+        model.attach(vs)
+        vsolv.append((vs, torch.as_tensor(pr.b, device=vs.vals.device)))
 
     def val_loss():
         tot, cnt = 0.0, 0
@@ -85,10 +96,25 @@ def train(problems, nv, steps=200, batch=4, pairs=16, lr=1e-5, seed=0, log=None,
                 cnt += val.shape[0]
         return tot / cnt if cnt else float("nan")
 
+    def val_iters():
+        if not vsolv:
+            return None
+        total = 0
+        for vs, b in vsolv:
+            model.attach(vs)
+            _, info = vs.solve(b, restart=val_restart, rtol=1e-6, maxit=10 * val_restart)
+            # a fallback or no convergence counts as the iteration cap
+            total += info["iters"] if info["converged"] and not info["fell_back"] else 10 * val_restart
+        return total
+
+    def key(v, it):
+        return (it if it is not None else 0, v)
+
     rng = np.random.Generator(np.random.PCG64(seed + 7))
     hist = {"train": [], "val": [], "best_step": 0}
-    best = (val_loss(), model.params())
-    hist["val"].append((0, best[0]))
+    v0, i0 = val_loss(), val_iters()
+    best = (key(v0, i0), model.params())
+    hist["val"].append((0, v0, i0))
     for step in range(steps):
         s, data, _ = sets[step % len(sets)]
         model.attach(s)
@@ -96,14 +122,17 @@ def train(problems, nv, steps=200, batch=4, pairs=16, lr=1e-5, seed=0, log=None,
         loss = cptr.cptr_learn_train_step(s, data[idx], lr)
         hist["train"].append(loss)
         if (step + 1) % eval_every == 0 or step == steps - 1:
-            v = val_loss()
-            hist["val"].append((step + 1, v))
-            if v < best[0]:
-                best = (v, model.params())
+            v, it = val_loss(), val_iters()
+            hist["val"].append((step + 1, v, it))
+            if key(v, it) < best[0]:
+                best = (key(v, it), model.params())
                 hist["best_step"] = step + 1
             if log:
-                log(f"step {step + 1}: train loss {loss:.4f}, validation loss {v:.4f}")
+                log(f"step {step + 1}: train loss {loss:.4f}, validation loss {v:.4f}"
+                    + (f", validation iterations {it}" if it is not None else ""))
     model.set_params(best[1])
     for s, _, _ in sets:
         s.close()
+    for vs, _ in vsolv:
+        vs.close()
     return model, hist

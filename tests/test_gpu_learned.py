@@ -161,8 +161,8 @@ def test_gain_on_held_out_seeds():
                         precision="fp32", second_stage="bilu0_mc")
     theta = model.params()
     model.close()
-    print("validation losses", [(k, round(v, 5)) for k, v in hist["val"]], "kept step", hist["best_step"])
-    assert hist["val"][0][1] >= min(v for _, v in hist["val"])
+    print("validation losses", [(k, round(v, 5)) for k, v, _ in hist["val"]], "kept step", hist["best_step"])
+    assert hist["val"][0][1] >= min(v for _, v, _ in hist["val"])
     for seed in (120, 121):
         pr = make_problem(seed=seed, **kw)
         jac, jf = _learned_iters(pr, init_params(3, seed=1))
@@ -180,14 +180,15 @@ def test_gain_on_held_out_seeds():
 def test_learned_stage_in_fgmres_and_fallback():
     banner("fgmres with the learned stage")
     pr = make_problem(shape=(16, 16, 8), kind="gaussian", sigma=2.0, corr_len=4.0, seed=101)
-    theta = init_params(pr.nv, seed=2, out_scale=0.05)
+    theta = neumann_params(pr.nv, seed=2)
     s, m = solver_with(pr, theta, precision="fp32", second_stage="learned")
     x, info = s.solve(torch.as_tensor(pr.b, device=DEV), restart=30, rtol=1e-6)
     xo, io = O.Oracle.from_problem(pr, first="cptr", second="bilu0_mc").fgmres(pr.b, m=30, rtol=1e-6)
     err = rel2(x.cpu().numpy(), xo)
     print(f"learned: iters {info['iters']} fell_back {info['fell_back']} relres "
           f"{info['relres_true']:.2e}, error vs oracle {err:.2e}")
-    assert info["converged"] and info["relres_true"] <= 1e-6
+    assert info["converged"] and not info["fell_back"] and info["relres_true"] <= 1e-6
+    first_iters = info["iters"]
     # a broken network (non-finite output) falls back to BILU(0) and still converges
     bad = theta.copy()
     bad[-1] = np.nan
@@ -195,4 +196,10 @@ def test_learned_stage_in_fgmres_and_fallback():
     x, info = s.solve(torch.as_tensor(pr.b, device=DEV), restart=30, rtol=1e-6)
     print(f"NaN weights: iters {info['iters']} fell_back {info['fell_back']}")
     assert info["fell_back"] and info["converged"] and info["relres_true"] <= 1e-6
+    # attaching good weights again re-enables the learned stage
+    m.set_params(theta)
+    m.attach(s)
+    x2, info2 = s.solve(torch.as_tensor(pr.b, device=DEV), restart=30, rtol=1e-6)
+    print(f"re-attached: iters {info2['iters']} fell_back {info2['fell_back']}")
+    assert not info2["fell_back"] and info2["converged"] and info2["iters"] == first_iters
     s.close()
