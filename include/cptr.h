@@ -108,6 +108,11 @@ typedef struct {
   int resid_fp64;        /* FP32 mode: form the two-stage residual b1 = v - A x1 from the FP64
                             values of A with FP64 accumulation, then round b1 to FP32 (0).
                             Avoids the FP32 cancellation of b1 on badly scaled systems. */
+  int scalar_dia;        /* 1: scalar operators of at least 4096 rows whose entries lie on at
+                            most 8 diagonals (the 7-point blocks of a structured grid) are
+                            stored by diagonals, without column indices; 0: SELL-64 for all
+                            short-row operators (1).  Both give the same sums in the same
+                            order. */
 } cptr_options;
 
 typedef struct {

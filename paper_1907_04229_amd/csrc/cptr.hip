@@ -75,17 +75,57 @@ static inline int sgrid(size_t n) { return std::max(1, std::min(kDotBlocks, nblk
 
 // ---------------------------------------------------------------- scalar operators
 // A scalar sparse operator on the device, stored for the kernel that suits
-// its row lengths: SELL-64 with one thread per row when rows are short
-// (the 7-point fine-level operators), CSR with G lanes per row otherwise
+// its pattern: DIA when every entry lies on one of a few diagonals (the
+// 7-point fine-level operators of a structured grid), SELL-64 with one thread
+// per row for other short rows, CSR with G lanes per row for long rows
 // (coarse AMG levels and the restriction, tens to hundreds of entries).
+constexpr int kDiaMinRows = 4096;
+
 template <typename T>
 struct SpOp {
+  enum Fmt { kSell, kDia, kCsrv };
   DevMem sptr, col, val, rp;
   Sell<T> view;
-  int nrows = 0, ncols = 0, lanes = 1;  // lanes == 1: SELL-64
+  Dia<T> dia;
+  Fmt fmt = kSell;
+  int nrows = 0, ncols = 0, lanes = 1;  // lanes: CSR lanes per row
   size_t nnz = 0;
 
-  void build(const HostCSR &a) {
+  // Diagonal storage if the pattern spans at most kMaxDiag diagonals and they
+  // are at least half full; false leaves the operator untouched.
+  bool build_dia(const HostCSR &a) {
+    if (a.nr != a.nc || a.nr < kDiaMinRows) return false;
+    int off[kMaxDiag], nd = 0;
+    for (int r = 0; r < a.nr; r++)
+      for (int q = a.rp[r]; q < a.rp[r + 1]; q++) {
+        const int o = a.ci[q] - r;
+        int d = 0;
+        while (d < nd && off[d] != o) d++;
+        if (d == nd) {
+          if (nd == kMaxDiag) return false;
+          off[nd++] = o;
+        }
+      }
+    if (nd == 0 || 2 * (size_t)a.nnz() < (size_t)nd * a.nr) return false;
+    std::sort(off, off + nd);
+    std::vector<T> v((size_t)nd * a.nr, T(0));
+    std::vector<double> acc((size_t)nd * a.nr, 0.0);
+    for (int r = 0; r < a.nr; r++)
+      for (int q = a.rp[r]; q < a.rp[r + 1]; q++) {
+        const int d = int(std::lower_bound(off, off + nd, a.ci[q] - r) - off);
+        acc[(size_t)d * a.nr + r] += a.v[q];
+      }
+    for (size_t i = 0; i < v.size(); i++) v[i] = T(acc[i]);
+    upload(val, v);
+    dia.nrows = a.nr;
+    dia.ndiag = nd;
+    for (int d = 0; d < kMaxDiag; d++) dia.off[d] = off[std::min(d, nd - 1)];  // padded: see row_sum
+    dia.val = devp<T>(val);
+    fmt = kDia;
+    return true;
+  }
+
+  void build(const HostCSR &a, bool allow_dia = true) {
     nrows = a.nr;
     ncols = a.nc;
     nnz = a.nnz();
@@ -96,12 +136,15 @@ struct SpOp {
       while (lanes < 64 && lanes * 4 < avg) lanes *= 2;
     }
     if (lanes > 1) {
+      fmt = kCsrv;
       upload(rp, a.rp);
       upload(col, a.ci);
       std::vector<T> v(a.v.begin(), a.v.end());
       upload(val, v);
       return;
     }
+    if (allow_dia && build_dia(a)) return;
+    fmt = kSell;
     int ns = (a.nr + kSlice - 1) / kSlice;
     std::vector<int> sp(ns + 1, 0);
     for (int s = 0; s < ns; s++) {
@@ -131,9 +174,10 @@ struct SpOp {
     view.col = devp<int>(col);
     view.val = devp<T>(val);
   }
-  // algorithmic bytes of one product: values + indices + row/slice offsets
+  // algorithmic bytes of one product: stored values, indices, row/slice offsets
   double bytes() const {
-    return double(nnz) * (sizeof(T) + 4) + 4.0 * (lanes > 1 ? nrows + 1 : view.nslices + 1);
+    if (fmt == kDia) return double(dia.ndiag) * nrows * sizeof(T);
+    return double(nnz) * (sizeof(T) + 4) + 4.0 * (fmt == kCsrv ? nrows + 1 : view.nslices + 1);
   }
 
 #define CPTR_CSRV_SWITCH(CALL)                  \
@@ -145,12 +189,22 @@ struct SpOp {
     case 32: CALL(32); break;                    \
     default: CALL(64); break;                    \
   }
+// one-thread-per-row kernel K over the SELL or DIA view
+#define CPTR_ROW_LAUNCH(K, ...)                                                                    \
+  do {                                                                                             \
+    if (fmt == kDia)                                                                               \
+      hipLaunchKernelGGL((K<Dia<T>, ##__VA_ARGS__>), dim3(nblk(nrows)), dim3(kBlock), 0, st, dia, ROW_ARGS); \
+    else                                                                                           \
+      hipLaunchKernelGGL((K<Sell<T>, ##__VA_ARGS__>), dim3(nblk(nrows)), dim3(kBlock), 0, st, view, ROW_ARGS); \
+  } while (0)
 
   // y = A x (mode 0), y += A x (mode 1), y = b - A x (mode 2)
   template <int MODE>
   void spmv(hipStream_t st, const T *x, const T *b, T *y) const {
-    if (lanes == 1) {
-      hipLaunchKernelGGL((k_sell_spmv<T, MODE>), dim3(nblk(nrows)), dim3(kBlock), 0, st, view, x, b, y);
+    if (fmt != kCsrv) {
+#define ROW_ARGS x, b, y
+      CPTR_ROW_LAUNCH(k_spmv, MODE);
+#undef ROW_ARGS
     } else {
       const int *r = devp<int>(rp), *c = devp<int>(col);
       const T *v = devp<T>(val);
@@ -162,8 +216,10 @@ struct SpOp {
     LAUNCH_CHECK();
   }
   void jacobi(hipStream_t st, const T *dinv, const T *b, const T *xin, T *xout) const {
-    if (lanes == 1) {
-      hipLaunchKernelGGL((k_jacobi<T>), dim3(nblk(nrows)), dim3(kBlock), 0, st, view, dinv, b, xin, xout);
+    if (fmt != kCsrv) {
+#define ROW_ARGS dinv, b, xin, xout
+      CPTR_ROW_LAUNCH(k_jacobi);
+#undef ROW_ARGS
     } else {
       const int *r = devp<int>(rp), *c = devp<int>(col);
       const T *v = devp<T>(val);
@@ -176,9 +232,10 @@ struct SpOp {
   }
   void jacobi_resid(hipStream_t st, const T *dinv, const T *b, const T *xin, const T *rin, T *xout,
                     T *rout) const {
-    if (lanes == 1) {
-      hipLaunchKernelGGL((k_jacobi_resid<T>), dim3(nblk(nrows)), dim3(kBlock), 0, st, view, dinv, b, xin, rin,
-                         xout, rout);
+    if (fmt != kCsrv) {
+#define ROW_ARGS dinv, b, xin, rin, xout, rout
+      CPTR_ROW_LAUNCH(k_jacobi_resid);
+#undef ROW_ARGS
     } else {
       const int *r = devp<int>(rp), *c = devp<int>(col);
       const T *v = devp<T>(val);
@@ -190,8 +247,10 @@ struct SpOp {
     LAUNCH_CHECK();
   }
   void smooth0_resid(hipStream_t st, const T *dinv, const T *b, T *x, T *res) const {
-    if (lanes == 1) {
-      hipLaunchKernelGGL((k_smooth0_resid<T>), dim3(nblk(nrows)), dim3(kBlock), 0, st, view, dinv, b, x, res);
+    if (fmt != kCsrv) {
+#define ROW_ARGS dinv, b, x, res
+      CPTR_ROW_LAUNCH(k_smooth0_resid);
+#undef ROW_ARGS
     } else {
       const int *r = devp<int>(rp), *c = devp<int>(col);
       const T *v = devp<T>(val);
@@ -202,6 +261,7 @@ struct SpOp {
     }
     LAUNCH_CHECK();
   }
+#undef CPTR_ROW_LAUNCH
 };
 
 // ---------------------------------------------------------------- AMG on device
@@ -219,7 +279,7 @@ struct AmgDev {
   std::vector<std::vector<int>> agg;  // host copy of the aggregates (introspection)
   double bytes_per_cycle = 0.0;
 
-  void build(const AmgHost &h, int nsweeps) {
+  void build(const AmgHost &h, int nsweeps, bool dia) {
     sweeps = std::max(1, nsweeps);
     lev.clear();
     agg.clear();
@@ -236,9 +296,9 @@ struct AmgDev {
       L->r.alloc(L->n * s);
       if (sweeps > 1) L->r2.alloc(L->n * s);
       if (l + 1 < h.lev.size()) {
-        L->A.build(H.A);
-        L->P.build(H.P);
-        L->R.build(H.R);
+        L->A.build(H.A, dia);
+        L->P.build(H.P, dia);
+        L->R.build(H.R, dia);
         std::vector<T> d(L->n);
         for (int i = 0; i < L->n; i++) {
           double sum = 0.0;
@@ -265,7 +325,6 @@ struct AmgDev {
 
   void cycle_level(hipStream_t st, size_t l, const T *b, T *out) const {
     const Level &L = *lev[l];
-    const int n = L.n;
     if (l + 1 == lev.size()) {
       const int waves_per_block = kBlock / 64;
       hipLaunchKernelGGL((k_coarse_gemv<T>), dim3(nblk(nc, waves_per_block)), dim3(kBlock), 0, st,
@@ -831,16 +890,16 @@ static void build_precond(cptr_handle *h, const std::vector<int> &rp, const std:
   if (o.first_stage != CPTR_FIRST_NONE) {
     AmgHost hp;
     amg_build(sub(o.ip, o.ip), prm, hp, agg_p);
-    P.amg_p.build(hp, o.amg_sweeps);
+    P.amg_p.build(hp, o.amg_sweeps, o.scalar_dia != 0);
     if (o.first_stage != CPTR_FIRST_CPR) {
       AmgHost hs;
       AmgParams prm_s = prm;
       if (o.amg_smooth_p_T >= 0) prm_s.smooth_p = o.amg_smooth_p_T;
       amg_build(*S, prm_s, hs, agg_s);
-      P.amg_s.build(hs, o.amg_sweeps);
+      P.amg_s.build(hs, o.amg_sweeps, o.scalar_dia != 0);
       P.have_s = true;
-      P.ApT.build(sub(o.ip, o.iT));
-      P.ATp.build(sub(o.iT, o.ip));
+      P.ApT.build(sub(o.ip, o.iT), o.scalar_dia != 0);
+      P.ATp.build(sub(o.iT, o.ip), o.scalar_dia != 0);
     }
     int ncyc = o.first_stage == CPTR_FIRST_BLOCK ? 2 : 1;
     bytes += 8.0 * n * 2 + 2.0 * n * s;                         // restriction
@@ -1373,6 +1432,7 @@ void cptr_default_options(cptr_options *o) {
   o->amg_smooth_p_T = 0;
   o->use_graph = 1;
   o->resid_fp64 = 0;
+  o->scalar_dia = 1;
 }
 
 int cptr_setup(cptr_handle **out, const cptr_bsr *A, const cptr_csr *S_T, const cptr_options *opt,

@@ -14,26 +14,47 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 // ---------------------------------------------------------------------------
-// SELL-64 products.  One thread per row; a wave owns one slice.
+// One-thread-per-row products over SELL-64 or DIA storage.  row_sum(A, row, f)
+// returns sum_j a_{row,j} f(j) in ascending column order, f(j) being the
+// column's operand (x_j, or a value formed on the fly from several vectors).
 // ---------------------------------------------------------------------------
-template <typename T>
-__device__ __forceinline__ T sell_row_dot(const Sell<T> &A, int row, const T *__restrict__ x) {
+template <typename T, typename F>
+__device__ __forceinline__ T row_sum(const Sell<T> &A, int row, F f) {
   const int s = row >> 6, lane = row & 63;
   const int b = A.sptr[s], w = (A.sptr[s + 1] - b) >> 6;
   const int *__restrict__ c = A.col + b + lane;
   const T *__restrict__ v = A.val + b + lane;
   T acc = T(0);
-  for (int k = 0; k < w; k++) acc += v[k * kSlice] * x[c[k * kSlice]];
+  for (int k = 0; k < w; k++) acc += v[k * kSlice] * f(c[k * kSlice]);
+  return acc;
+}
+
+// Slots off the pattern hold zero; their column is clamped into range so the
+// operand load stays in bounds, and the operand is replaced by zero so that
+// they add exactly nothing.  Diagonals past ndiag repeat the last one (its
+// offset is padded on the host) and are masked the same way: the loop has no
+// branch, so all loads of the row are in flight together.
+template <typename T, typename F>
+__device__ __forceinline__ T row_sum(const Dia<T> &A, int row, F f) {
+  T v[kMaxDiag], xc[kMaxDiag];
+#pragma unroll
+  for (int d = 0; d < kMaxDiag; d++) {
+    v[d] = A.val[(size_t)min(d, A.ndiag - 1) * A.nrows + row];
+    xc[d] = f(min(max(row + A.off[d], 0), A.nrows - 1));
+  }
+  T acc = T(0);
+#pragma unroll
+  for (int d = 0; d < kMaxDiag; d++) acc += v[d] * (d < A.ndiag && v[d] != T(0) ? xc[d] : T(0));
   return acc;
 }
 
 // y = A x  (mode 0),  y += A x  (mode 1),  y = b - A x  (mode 2)
-template <typename T, int MODE>
-__global__ void __launch_bounds__(kBlock) k_sell_spmv(Sell<T> A, const T *__restrict__ x,
-                                                      const T *__restrict__ b, T *__restrict__ y) {
+template <typename Op, int MODE, typename T = typename Op::value_type>
+__global__ void __launch_bounds__(kBlock) k_spmv(Op A, const T *__restrict__ x, const T *__restrict__ b,
+                                                 T *__restrict__ y) {
   const int row = blockIdx.x * kBlock + threadIdx.x;
   if (row >= A.nrows) return;
-  const T ax = sell_row_dot(A, row, x);
+  const T ax = row_sum(A, row, [&](int c) { return x[c]; });
   if (MODE == 0) y[row] = ax;
   if (MODE == 1) y[row] += ax;
   if (MODE == 2) y[row] = b[row] - ax;
@@ -41,32 +62,25 @@ __global__ void __launch_bounds__(kBlock) k_sell_spmv(Sell<T> A, const T *__rest
 
 // first l1-Jacobi sweep from a zero guess fused with the residual:
 //   x = D^{-1} b,  r = b - A D^{-1} b
-template <typename T>
-__global__ void __launch_bounds__(kBlock) k_smooth0_resid(Sell<T> A, const T *__restrict__ dinv,
+template <typename Op, typename T = typename Op::value_type>
+__global__ void __launch_bounds__(kBlock) k_smooth0_resid(Op A, const T *__restrict__ dinv,
                                                           const T *__restrict__ b, T *__restrict__ x,
                                                           T *__restrict__ r) {
   const int row = blockIdx.x * kBlock + threadIdx.x;
   if (row >= A.nrows) return;
-  const int s = row >> 6, lane = row & 63;
-  const int base = A.sptr[s], w = (A.sptr[s + 1] - base) >> 6;
-  T acc = T(0);
-  for (int k = 0; k < w; k++) {
-    const int c = A.col[base + k * kSlice + lane];
-    acc += A.val[base + k * kSlice + lane] * (dinv[c] * b[c]);
-  }
+  const T acc = row_sum(A, row, [&](int c) { return dinv[c] * b[c]; });
   const T bi = b[row];
   x[row] = dinv[row] * bi;
   r[row] = bi - acc;
 }
 
 // x_out = x_in + D^{-1} (b - A x_in)
-template <typename T>
-__global__ void __launch_bounds__(kBlock) k_jacobi(Sell<T> A, const T *__restrict__ dinv,
-                                                   const T *__restrict__ b, const T *__restrict__ xin,
-                                                   T *__restrict__ xout) {
+template <typename Op, typename T = typename Op::value_type>
+__global__ void __launch_bounds__(kBlock) k_jacobi(Op A, const T *__restrict__ dinv, const T *__restrict__ b,
+                                                   const T *__restrict__ xin, T *__restrict__ xout) {
   const int row = blockIdx.x * kBlock + threadIdx.x;
   if (row >= A.nrows) return;
-  const T ax = sell_row_dot(A, row, xin);
+  const T ax = row_sum(A, row, [&](int c) { return xin[c]; });
   xout[row] = xin[row] + dinv[row] * (b[row] - ax);
 }
 
@@ -74,20 +88,14 @@ __global__ void __launch_bounds__(kBlock) k_jacobi(Sell<T> A, const T *__restric
 // of the result, in one pass over A:
 //   x_out = x_in + D^{-1} r_in,  r_out = b - A x_out
 // (x_out of the neighbours formed on the fly from x_in, r_in, D^{-1}).
-template <typename T>
-__global__ void __launch_bounds__(kBlock) k_jacobi_resid(Sell<T> A, const T *__restrict__ dinv,
+template <typename Op, typename T = typename Op::value_type>
+__global__ void __launch_bounds__(kBlock) k_jacobi_resid(Op A, const T *__restrict__ dinv,
                                                          const T *__restrict__ b, const T *__restrict__ xin,
                                                          const T *__restrict__ rin, T *__restrict__ xout,
                                                          T *__restrict__ rout) {
   const int row = blockIdx.x * kBlock + threadIdx.x;
   if (row >= A.nrows) return;
-  const int s = row >> 6, lane = row & 63;
-  const int base = A.sptr[s], w = (A.sptr[s + 1] - base) >> 6;
-  T acc = T(0);
-  for (int k = 0; k < w; k++) {
-    const int c = A.col[base + k * kSlice + lane];
-    acc += A.val[base + k * kSlice + lane] * (xin[c] + dinv[c] * rin[c]);
-  }
+  const T acc = row_sum(A, row, [&](int c) { return xin[c] + dinv[c] * rin[c]; });
   xout[row] = xin[row] + dinv[row] * rin[row];
   rout[row] = b[row] - acc;
 }
@@ -96,13 +104,32 @@ __global__ void __launch_bounds__(kBlock) k_jacobi_resid(Sell<T> A, const T *__r
 // CSR products with G lanes per row, for operators with long rows (coarse
 // AMG levels, restriction): lanes stride the row, then an xor-shuffle sum.
 // ---------------------------------------------------------------------------
-template <typename T, int G>
-__device__ __forceinline__ T csrv_row_dot(const int *__restrict__ rp, const int *__restrict__ ci,
-                                          const T *__restrict__ val, int row, int lane,
-                                          const T *__restrict__ x) {
-  T acc = T(0);
+// Each lane takes entries lane, lane + G, ... of the row, kCsrvUnroll at a
+// time: the index and value loads of a round are all issued before its
+// operands are gathered (column clamped into the row, so no load depends on
+// a branch), and slots past the row end add exactly nothing.
+constexpr int kCsrvUnroll = 4;
+
+template <typename T, int G, typename F>
+__device__ __forceinline__ T csrv_row_sum(const int *__restrict__ rp, const int *__restrict__ ci,
+                                          const T *__restrict__ val, int row, int lane, F f) {
   const int e = rp[row + 1];
-  for (int k = rp[row] + lane; k < e; k += G) acc += val[k] * x[ci[k]];
+  T acc = T(0);
+  for (int k0 = rp[row] + lane; k0 < e; k0 += kCsrvUnroll * G) {
+    int c[kCsrvUnroll];
+    T v[kCsrvUnroll];
+#pragma unroll
+    for (int u = 0; u < kCsrvUnroll; u++) {
+      const int k = min(k0 + u * G, e - 1);
+      c[u] = ci[k];
+      v[u] = val[k];
+    }
+#pragma unroll
+    for (int u = 0; u < kCsrvUnroll; u++) {
+      const T xc = f(c[u]);
+      acc += v[u] * (k0 + u * G < e ? xc : T(0));
+    }
+  }
 #pragma unroll
   for (int off = G / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, G);
   return acc;
@@ -117,7 +144,7 @@ __global__ void __launch_bounds__(kBlock) k_csrv_spmv(int n, const int *__restri
   const int t = blockIdx.x * kBlock + threadIdx.x;
   const int row = t / G, lane = t % G;
   if (row >= n) return;  // whole G-lane groups exit together (G divides kBlock)
-  const T ax = csrv_row_dot<T, G>(rp, ci, val, row, lane, x);
+  const T ax = csrv_row_sum<T, G>(rp, ci, val, row, lane, [&](int c) { return x[c]; });
   if (lane != 0) return;
   if (MODE == 0) y[row] = ax;
   if (MODE == 1) y[row] += ax;
@@ -135,8 +162,9 @@ __global__ void __launch_bounds__(kBlock) k_csrv_jacobi(int n, const int *__rest
   const int t = blockIdx.x * kBlock + threadIdx.x;
   const int row = t / G, lane = t % G;
   if (row >= n) return;
-  const T ax = csrv_row_dot<T, G>(rp, ci, val, row, lane, xin);
-  if (lane == 0) xout[row] = xin[row] + dinv[row] * (b[row] - ax);
+  const T bi = b[row], di = dinv[row], xi = xin[row];  // issued before the row's loads
+  const T ax = csrv_row_sum<T, G>(rp, ci, val, row, lane, [&](int c) { return xin[c]; });
+  if (lane == 0) xout[row] = xi + di * (bi - ax);
 }
 
 // x = D^{-1} b, r = b - A D^{-1} b with G lanes per row
@@ -151,17 +179,10 @@ __global__ void __launch_bounds__(kBlock) k_csrv_smooth0_resid(int n, const int 
   const int t = blockIdx.x * kBlock + threadIdx.x;
   const int row = t / G, lane = t % G;
   if (row >= n) return;
-  T acc = T(0);
-  const int e = rp[row + 1];
-  for (int k = rp[row] + lane; k < e; k += G) {
-    const int c = ci[k];
-    acc += val[k] * (dinv[c] * b[c]);
-  }
-#pragma unroll
-  for (int off = G / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, G);
+  const T bi = b[row], di = dinv[row];
+  const T acc = csrv_row_sum<T, G>(rp, ci, val, row, lane, [&](int c) { return dinv[c] * b[c]; });
   if (lane != 0) return;
-  const T bi = b[row];
-  x[row] = dinv[row] * bi;
+  x[row] = di * bi;
   r[row] = bi - acc;
 }
 
@@ -178,17 +199,12 @@ __global__ void __launch_bounds__(kBlock) k_csrv_jacobi_resid(int n, const int *
   const int t = blockIdx.x * kBlock + threadIdx.x;
   const int row = t / G, lane = t % G;
   if (row >= n) return;
-  T acc = T(0);
-  const int e = rp[row + 1];
-  for (int k = rp[row] + lane; k < e; k += G) {
-    const int c = ci[k];
-    acc += val[k] * (xin[c] + dinv[c] * rin[c]);
-  }
-#pragma unroll
-  for (int off = G / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, G);
+  const T bi = b[row], di = dinv[row], xi = xin[row], ri = rin[row];
+  const T acc = csrv_row_sum<T, G>(rp, ci, val, row, lane,
+                                   [&](int c) { return xin[c] + dinv[c] * rin[c]; });
   if (lane != 0) return;
-  xout[row] = xin[row] + dinv[row] * rin[row];
-  rout[row] = b[row] - acc;
+  xout[row] = xi + di * ri;
+  rout[row] = bi - acc;
 }
 
 // coarsest level: x = A_c^{-1} b with the explicit FP64 inverse; one wave per row
@@ -493,10 +509,13 @@ __global__ void __launch_bounds__(kBlock) k_mdot(const double *__restrict__ V, s
 #pragma unroll
   for (int k = 0; k < MAXK; k++) acc[k] = 0.0;
   for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < N; i += (size_t)gridDim.x * kBlock) {
+    // every load of the row is issued before the first product waits on one
+    double vk[MAXK];
     const double wi = w[i];
 #pragma unroll
-    for (int k = 0; k < MAXK; k++)
-      if (k < kk) acc[k] += V[(size_t)k * N + i] * wi;
+    for (int k = 0; k < MAXK; k++) vk[k] = k < kk ? V[(size_t)k * N + i] : 0.0;
+#pragma unroll
+    for (int k = 0; k < MAXK; k++) acc[k] += vk[k] * wi;
   }
   block_store_partials<MAXK>(acc, kk, part);
 }
@@ -543,10 +562,12 @@ __global__ void __launch_bounds__(kBlock) k_cgs_update_norm(const double *__rest
   for (int k = 0; k < MAXK; k++) hk[k] = k < kk ? h[k] : 0.0;
   double acc[1] = {0.0};
   for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < N; i += (size_t)gridDim.x * kBlock) {
+    double vk[MAXK];
     double wi = w[i];
 #pragma unroll
-    for (int k = 0; k < MAXK; k++)
-      if (k < kk) wi -= V[(size_t)k * N + i] * hk[k];
+    for (int k = 0; k < MAXK; k++) vk[k] = k < kk ? V[(size_t)k * N + i] : 0.0;
+#pragma unroll
+    for (int k = 0; k < MAXK; k++) wi -= vk[k] * hk[k];
     w[i] = wi;
     acc[0] += wi * wi;
   }

@@ -5,10 +5,14 @@
 //     products w = A z and the true residual;
 //   * SELL-64 ("sliced ELLPACK", one slice per wavefront of 64 rows, each
 //     slice padded to its longest row and stored column-major inside the
-//     slice) for every scalar operator: the sub-blocks A_pp, A_pT, A_Tp, S~_T,
-//     every AMG level and the transfer operators P, R.  A lane reads element
-//     k of its row at slice_base + 64 k + lane, so each load instruction of a
-//     wave is one contiguous 256 B (FP32) segment;
+//     slice) for scalar operators with short rows: the sub-blocks A_pp, A_pT,
+//     A_Tp, S~_T on unstructured patterns, the prolongators P.  A lane reads
+//     element k of its row at slice_base + 64 k + lane, so each load
+//     instruction of a wave is one contiguous 256 B (FP32) segment;
+//   * DIA (diagonal storage) for the same sub-blocks when their entries lie
+//     on a few diagonals, as on a structured grid;
+//   * CSR with several lanes per row for long rows (coarse AMG levels, the
+//     restrictions R);
 //   * the p/T columns of A as nv x 2 blocks in the BSR pattern (two-stage
 //     residual);
 //   * BILU(0) factors grouped by level of the triangular solves.
@@ -22,10 +26,27 @@ constexpr int kSlice = 64;
 
 template <typename T>
 struct Sell {
+  using value_type = T;
   int nrows = 0;
   int nslices = 0;
   const int *sptr = nullptr;  // element offset of each slice, nslices + 1
   const int *col = nullptr;
+  const T *val = nullptr;
+};
+
+// Diagonal storage of a square operator whose entries all lie on at most
+// kMaxDiag diagonals (the 7-point couplings of a structured grid): entry
+// (row, row + off[d]) is val[d * nrows + row], zero where the pattern has no
+// entry.  No column indices are read, so an FP32 entry costs 4 B of traffic
+// instead of the 8 B of a value + index pair.
+constexpr int kMaxDiag = 8;
+
+template <typename T>
+struct Dia {
+  using value_type = T;
+  int nrows = 0;
+  int ndiag = 0;
+  int off[kMaxDiag] = {};  // ascending column offsets; entries past ndiag repeat the last
   const T *val = nullptr;
 };
 

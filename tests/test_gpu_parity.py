@@ -37,6 +37,11 @@ SHAPES = {
     "small": dict(config="small"),                                                   # 500 cells
     "chain": dict(shape=(13, 1, 1), kind="iid", seed=23),
     "single": dict(shape=(1, 1, 1), kind="iid", seed=24),
+    # >= 4096 cells: fine-level operators in diagonal storage
+    "dia2": dict(shape=(20, 16, 14), kind="gaussian", sigma=2.0, corr_len=4.0, seed=25,
+                 heater=True),                                                       # 4480 cells
+    "dia3": dict(shape=(17, 16, 16), kind="gaussian", sigma=2.0, corr_len=4.0, seed=26,
+                 three_phase=True),                                                  # nv = 4
 }
 
 
@@ -172,6 +177,40 @@ def test_plain_aggregation_for_s_t(name):
     torch.cuda.synchronize()
     assert relerr(x1.cpu().numpy(), o.first_stage(v)) <= 1e-10
     s.close()
+
+
+@pytest.mark.parametrize("name", ["dia2", "dia3"])
+def test_diagonal_storage(name):
+    """Fine-level 7-point operators of >= 4096 rows are stored by diagonals
+    (scalar_dia = 1): FP64 V-cycles and first stage against the oracle, and the
+    same sums in the same order as SELL-64 (scalar_dia = 0), bit for bit, for
+    the FP32 and FP64 applications."""
+    banner(f"diagonal storage {name}")
+    pr = prob(name)
+    assert pr.n >= 4096
+    s = solver(pr, precision="fp64", second_stage="none", amg_coarse_size=16)
+    o = O.Oracle.from_problem(pr, first="cptr", second="none", coarse_size=16)
+    rng = np.random.default_rng(13)
+    for which in (0, 1):
+        b = rng.standard_normal(pr.n)
+        x = torch.empty(pr.n, dtype=torch.float64, device=DEV)
+        cptr.cptr_vcycle(s.h, which, dev(b), x)
+        torch.cuda.synchronize()
+        assert relerr(x.cpu().numpy(), o.vcycle(which, b)) <= 1e-10
+    v = rng.standard_normal(pr.n * pr.nv)
+    x1 = torch.empty_like(dev(v))
+    cptr.cptr_first_stage(s.h, dev(v), x1)
+    torch.cuda.synchronize()
+    assert relerr(x1.cpu().numpy(), o.first_stage(v)) <= 1e-10
+    s.close()
+    for precision in ("fp64", "fp32"):
+        zs = []
+        for dia in (1, 0):
+            s = solver(pr, precision=precision, second_stage="bilu0_mc", scalar_dia=dia)
+            zs.append(s.apply(dev(v)))
+            torch.cuda.synchronize()
+            s.close()
+        assert torch.equal(zs[0], zs[1]), precision
 
 
 @pytest.mark.parametrize("name", ["ragged", "three", "small", "chain", "single"])
