@@ -230,17 +230,16 @@ struct SpOp {
     }
     LAUNCH_CHECK();
   }
-  void jacobi_resid(hipStream_t st, const T *dinv, const T *b, const T *xin, const T *rin, T *xout,
-                    T *rout) const {
+  void smooth0_next(hipStream_t st, const T *dinv, const T *b, T *x) const {
     if (fmt != kCsrv) {
-#define ROW_ARGS dinv, b, xin, rin, xout, rout
-      CPTR_ROW_LAUNCH(k_jacobi_resid);
+#define ROW_ARGS dinv, b, x
+      CPTR_ROW_LAUNCH(k_smooth0_next);
 #undef ROW_ARGS
     } else {
       const int *r = devp<int>(rp), *c = devp<int>(col);
       const T *v = devp<T>(val);
       const int g = nblk((size_t)nrows * lanes);
-#define CALL(G) hipLaunchKernelGGL((k_csrv_jacobi_resid<T, G>), dim3(g), dim3(kBlock), 0, st, nrows, r, c, v, dinv, b, xin, rin, xout, rout)
+#define CALL(G) hipLaunchKernelGGL((k_csrv_smooth0_next<T, G>), dim3(g), dim3(kBlock), 0, st, nrows, r, c, v, dinv, b, x)
       CPTR_CSRV_SWITCH(CALL)
 #undef CALL
     }
@@ -269,7 +268,7 @@ template <typename T>
 struct AmgDev {
   struct Level {
     SpOp<T> A, P, R;
-    DevMem dinv, b, x, y, r, r2;
+    DevMem dinv, b, x, y, r;
     int n = 0;
   };
   std::vector<std::unique_ptr<Level>> lev;
@@ -294,7 +293,6 @@ struct AmgDev {
       L->x.alloc(L->n * s);
       L->y.alloc(L->n * s);
       L->r.alloc(L->n * s);
-      if (sweeps > 1) L->r2.alloc(L->n * s);
       if (l + 1 < h.lev.size()) {
         L->A.build(H.A, dia);
         L->P.build(H.P, dia);
@@ -335,18 +333,17 @@ struct AmgDev {
     T *x = devp<T>(L.x), *y = devp<T>(L.y), *r = devp<T>(L.r);
     const T *dinv = devp<T>(L.dinv);
     const Level &C = *lev[l + 1];
-    // pre-smoothing from zero; every pass leaves the residual of its iterate
-    L.A.smooth0_resid(st, dinv, b, x, r);
-    if (sweeps > 1) {
-      T *cx = x, *nx = y, *cr = r, *nr = devp<T>(L.r2);
-      for (int s = 1; s < sweeps; s++) {
-        L.A.jacobi_resid(st, dinv, b, cx, cr, nx, nr);
-        std::swap(cx, nx);
-        std::swap(cr, nr);
+    // pre-smoothing from zero: one pass for the first two sweeps, one per
+    // further sweep, the last forming the residual of the smoothed iterate
+    if (sweeps == 1) {
+      L.A.smooth0_resid(st, dinv, b, x, r);
+    } else {
+      L.A.smooth0_next(st, dinv, b, x);
+      for (int s = 2; s < sweeps; s++) {
+        L.A.jacobi(st, dinv, b, x, y);
+        std::swap(x, y);
       }
-      x = cx;  // the iterate and its residual, wherever they ended
-      y = nx;
-      r = cr;
+      L.A.template spmv<2>(st, x, b, r);
     }
     // restriction, coarse correction, prolongation
     L.R.template spmv<0>(st, r, nullptr, devp<T>(C.b));
@@ -1135,7 +1132,7 @@ static void ensure_krylov(cptr_handle *h, int m) {
 static void norm2(cptr_handle *h, hipStream_t st, const double *x, size_t N, int slot) {
   const int g = sgrid(N);
   hipLaunchKernelGGL(k_norm2_partial, dim3(g), dim3(kBlock), 0, st, x, N, devp<double>(h->part));
-  hipLaunchKernelGGL((k_reduce<1>), dim3(1), dim3(kBlock), 0, st, (const double *)devp<double>(h->part), g,
+  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlock), 0, st, (const double *)devp<double>(h->part), g,
                      (const int *)nullptr, 1, devp<double>(h->scal) + slot, 1);
   LAUNCH_CHECK();
 }
@@ -1163,15 +1160,15 @@ static void arnoldi_step(cptr_handle *h, hipStream_t st) {
   const int *jd = &ks->j;
   hipLaunchKernelGGL((k_mdot<MAXK>), dim3(g), dim3(kBlock), 0, st, (const double *)devp<double>(h->V), N, jd,
                      (const double *)devp<double>(h->w), part);
-  hipLaunchKernelGGL((k_reduce<MAXK>), dim3(MAXK), dim3(kBlock), 0, st, (const double *)part, g, jd, 0,
+  hipLaunchKernelGGL(k_reduce, dim3(MAXK), dim3(kBlock), 0, st, (const double *)part, g, jd, 0,
                      devp<double>(h->h1), 0);
   hipLaunchKernelGGL((k_cgs_update_mdot<MAXK>), dim3(g), dim3(kBlock), 0, st, (const double *)devp<double>(h->V),
                      N, jd, (const double *)devp<double>(h->h1), devp<double>(h->w), part);
-  hipLaunchKernelGGL((k_reduce<MAXK>), dim3(MAXK), dim3(kBlock), 0, st, (const double *)part, g, jd, 0,
+  hipLaunchKernelGGL(k_reduce, dim3(MAXK), dim3(kBlock), 0, st, (const double *)part, g, jd, 0,
                      devp<double>(h->h2), 0);
   hipLaunchKernelGGL((k_cgs_update_norm<MAXK>), dim3(g), dim3(kBlock), 0, st, (const double *)devp<double>(h->V),
                      N, jd, (const double *)devp<double>(h->h2), devp<double>(h->w), part);
-  hipLaunchKernelGGL((k_reduce<1>), dim3(1), dim3(kBlock), 0, st, (const double *)part, g, (const int *)nullptr,
+  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlock), 0, st, (const double *)part, g, (const int *)nullptr,
                      1, &ks->hn, 1);
   hipLaunchKernelGGL(k_scale_next, dim3(g), dim3(kBlock), 0, st, devp<double>(h->V), N, (const KState *)ks,
                      (const double *)devp<double>(h->w));

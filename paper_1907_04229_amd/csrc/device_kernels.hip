@@ -18,6 +18,12 @@ __device__ __forceinline__ double wave_sum(double v) {
 // returns sum_j a_{row,j} f(j) in ascending column order, f(j) being the
 // column's operand (x_j, or a value formed on the fly from several vectors).
 // ---------------------------------------------------------------------------
+// Slots 0 .. w-1 of the slice, kSellUnroll at a time: a round's index and
+// value loads are all issued before its operands are gathered (slot clamped
+// to the slice width, so no load depends on a branch); slots past the width
+// add exactly nothing, padding slots (column 0, value 0) add 0 * x_0.
+constexpr int kSellUnroll = 4;
+
 template <typename T, typename F>
 __device__ __forceinline__ T row_sum(const Sell<T> &A, int row, F f) {
   const int s = row >> 6, lane = row & 63;
@@ -25,7 +31,21 @@ __device__ __forceinline__ T row_sum(const Sell<T> &A, int row, F f) {
   const int *__restrict__ c = A.col + b + lane;
   const T *__restrict__ v = A.val + b + lane;
   T acc = T(0);
-  for (int k = 0; k < w; k++) acc += v[k * kSlice] * f(c[k * kSlice]);
+  for (int k0 = 0; k0 < w; k0 += kSellUnroll) {
+    int cc[kSellUnroll];
+    T vv[kSellUnroll];
+#pragma unroll
+    for (int u = 0; u < kSellUnroll; u++) {
+      const int k = min(k0 + u, w - 1);
+      cc[u] = c[k * kSlice];
+      vv[u] = v[k * kSlice];
+    }
+#pragma unroll
+    for (int u = 0; u < kSellUnroll; u++) {
+      const T xc = f(cc[u]);
+      acc += vv[u] * (k0 + u < w ? xc : T(0));
+    }
+  }
   return acc;
 }
 
@@ -74,6 +94,20 @@ __global__ void __launch_bounds__(kBlock) k_smooth0_resid(Op A, const T *__restr
   r[row] = bi - acc;
 }
 
+// the first two l1-Jacobi sweeps from a zero guess in one pass over A:
+//   x1 = D^{-1} b,  r1 = b - A x1,  x = x1 + D^{-1} r1
+// (the same roundings as a sweep that stores x1 and r1 and one that reads them)
+template <typename Op, typename T = typename Op::value_type>
+__global__ void __launch_bounds__(kBlock) k_smooth0_next(Op A, const T *__restrict__ dinv,
+                                                         const T *__restrict__ b, T *__restrict__ x) {
+  const int row = blockIdx.x * kBlock + threadIdx.x;
+  if (row >= A.nrows) return;
+  const T acc = row_sum(A, row, [&](int c) { return dinv[c] * b[c]; });
+  const T bi = b[row], di = dinv[row];
+  const T x1 = di * bi, r1 = bi - acc;
+  x[row] = x1 + di * r1;
+}
+
 // x_out = x_in + D^{-1} (b - A x_in)
 template <typename Op, typename T = typename Op::value_type>
 __global__ void __launch_bounds__(kBlock) k_jacobi(Op A, const T *__restrict__ dinv, const T *__restrict__ b,
@@ -82,22 +116,6 @@ __global__ void __launch_bounds__(kBlock) k_jacobi(Op A, const T *__restrict__ d
   if (row >= A.nrows) return;
   const T ax = row_sum(A, row, [&](int c) { return xin[c]; });
   xout[row] = xin[row] + dinv[row] * (b[row] - ax);
-}
-
-// One Jacobi sweep from an iterate whose residual is known, and the residual
-// of the result, in one pass over A:
-//   x_out = x_in + D^{-1} r_in,  r_out = b - A x_out
-// (x_out of the neighbours formed on the fly from x_in, r_in, D^{-1}).
-template <typename Op, typename T = typename Op::value_type>
-__global__ void __launch_bounds__(kBlock) k_jacobi_resid(Op A, const T *__restrict__ dinv,
-                                                         const T *__restrict__ b, const T *__restrict__ xin,
-                                                         const T *__restrict__ rin, T *__restrict__ xout,
-                                                         T *__restrict__ rout) {
-  const int row = blockIdx.x * kBlock + threadIdx.x;
-  if (row >= A.nrows) return;
-  const T acc = row_sum(A, row, [&](int c) { return xin[c] + dinv[c] * rin[c]; });
-  xout[row] = xin[row] + dinv[row] * rin[row];
-  rout[row] = b[row] - acc;
 }
 
 // ---------------------------------------------------------------------------
@@ -186,25 +204,21 @@ __global__ void __launch_bounds__(kBlock) k_csrv_smooth0_resid(int n, const int 
   r[row] = bi - acc;
 }
 
-// x_out = x_in + D^{-1} r_in, r_out = b - A x_out with G lanes per row
+// the first two sweeps from a zero guess (k_smooth0_next) with G lanes per row
 template <typename T, int G>
-__global__ void __launch_bounds__(kBlock) k_csrv_jacobi_resid(int n, const int *__restrict__ rp,
+__global__ void __launch_bounds__(kBlock) k_csrv_smooth0_next(int n, const int *__restrict__ rp,
                                                               const int *__restrict__ ci,
                                                               const T *__restrict__ val,
                                                               const T *__restrict__ dinv,
-                                                              const T *__restrict__ b,
-                                                              const T *__restrict__ xin,
-                                                              const T *__restrict__ rin,
-                                                              T *__restrict__ xout, T *__restrict__ rout) {
+                                                              const T *__restrict__ b, T *__restrict__ x) {
   const int t = blockIdx.x * kBlock + threadIdx.x;
   const int row = t / G, lane = t % G;
   if (row >= n) return;
-  const T bi = b[row], di = dinv[row], xi = xin[row], ri = rin[row];
-  const T acc = csrv_row_sum<T, G>(rp, ci, val, row, lane,
-                                   [&](int c) { return xin[c] + dinv[c] * rin[c]; });
+  const T bi = b[row], di = dinv[row];
+  const T acc = csrv_row_sum<T, G>(rp, ci, val, row, lane, [&](int c) { return dinv[c] * b[c]; });
   if (lane != 0) return;
-  xout[row] = xi + di * ri;
-  rout[row] = bi - acc;
+  const T x1 = di * bi, r1 = bi - acc;
+  x[row] = x1 + di * r1;
 }
 
 // coarsest level: x = A_c^{-1} b with the explicit FP64 inverse; one wave per row
@@ -230,7 +244,7 @@ __global__ void __launch_bounds__(kBlock) k_restrict_pT(int n, int nv, int ip, i
                                                         T *__restrict__ bp, T *__restrict__ bt) {
   const int i = blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
-  const double *__restrict__ v = slots->v;
+  const gmem<const double> *__restrict__ v = as_global(slots->v);
   bp[i] = T(v[(size_t)i * nv + ip]);
   if (bt) bt[i] = T(v[(size_t)i * nv + iT]);
 }
@@ -265,7 +279,7 @@ __global__ void __launch_bounds__(64 * NV) k_resid_pT_sliced(int n, const int *_
       acc += acol[((size_t)k * NV + r) * 2 * 64 + lane] * dp[cols[(size_t)k * 64 + lane]];
   }
   if (i >= n) return;
-  b1[(size_t)i * NV + r] = T(slots->v[(size_t)i * NV + r]) - acc;
+  b1[(size_t)i * NV + r] = T(as_global(slots->v)[(size_t)i * NV + r]) - acc;
 }
 
 // The same from the FP64 values of the sliced copy of A (columns ip and iT of
@@ -297,7 +311,7 @@ __global__ void __launch_bounds__(64 * NV) k_resid_pT_sliced64(int n, const int 
     }
   }
   if (i >= n) return;
-  b1[(size_t)i * NV + r] = T(slots->v[(size_t)i * NV + r] - acc);
+  b1[(size_t)i * NV + r] = T(as_global(slots->v)[(size_t)i * NV + r] - acc);
 }
 
 template <typename T, typename ZT>
@@ -312,7 +326,7 @@ __global__ void __launch_bounds__(kBlock) k_finish(int n, int nv, int ip, int iT
   T z = b1 ? b1[t] : T(0);
   if (dp && r == ip) z += dp[i];
   if (dT && r == iT) z += dT[i];
-  reinterpret_cast<ZT *>(slots->z)[t] = ZT(z);
+  as_global(reinterpret_cast<ZT *>(slots->z))[t] = ZT(z);
 }
 
 // ---------------------------------------------------------------------------
@@ -381,7 +395,7 @@ __global__ void __launch_bounds__(kBlock) k_ilu_bwd(int p0, int cnt, const int *
   T z = w;
   if (dp && r == ip) z += dp[i];
   if (dT && r == iT) z += dT[i];
-  reinterpret_cast<ZT *>(slots->z)[(size_t)i * NV + r] = ZT(z);
+  as_global(reinterpret_cast<ZT *>(slots->z))[(size_t)i * NV + r] = ZT(z);
 }
 
 // ---------------------------------------------------------------------------
@@ -407,7 +421,7 @@ __global__ void __launch_bounds__(SpmvShape<NV>::T) k_bsr_spmv(int n, const int 
                                                                const double *__restrict__ b,
                                                                double *__restrict__ y) {
   constexpr int R = SpmvShape<NV>::R;
-  const XT *__restrict__ x = slots ? reinterpret_cast<const XT *>(slots->z) : xarg;
+  const gmem<const XT> *__restrict__ x = as_global(slots ? reinterpret_cast<const XT *>(slots->z) : xarg);
   const int i = blockIdx.x * R + threadIdx.x / NV, r = threadIdx.x % NV;
   if (i >= n) return;
   double acc = 0.0;
@@ -422,7 +436,7 @@ __global__ void __launch_bounds__(SpmvShape<NV>::T) k_bsr_spmv(int n, const int 
     for (int q = 0; q < 8; q++) {
       const bool ok = col[q] >= 0;
       const double *a = vals + ((size_t)(ok ? k + q : k) * NV + r) * NV;  // in bounds either way
-      const XT *xc = x + (size_t)(ok ? col[q] : 0) * NV;
+      const gmem<const XT> *xc = x + (size_t)(ok ? col[q] : 0) * NV;
 #pragma unroll
       for (int c = 0; c < NV; c++) {
         av[q][c] = ok ? a[c] : 0.0;
@@ -454,7 +468,7 @@ __global__ void __launch_bounds__(64 * NV) k_bsr_spmv_sliced(int n, const int *_
                                                               const ApplySlots *__restrict__ slots,
                                                               const double *__restrict__ b,
                                                               double *__restrict__ y) {
-  const XT *__restrict__ x = slots ? reinterpret_cast<const XT *>(slots->z) : xarg;
+  const gmem<const XT> *__restrict__ x = as_global(slots ? reinterpret_cast<const XT *>(slots->z) : xarg);
   const int r = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int sl = blockIdx.x, i = sl * 64 + lane;
   const int k0 = kptr[sl], k1 = kptr[sl + 1];
@@ -463,7 +477,7 @@ __global__ void __launch_bounds__(64 * NV) k_bsr_spmv_sliced(int n, const int *_
   for (int k = k0; k < k1; k++) {
     const int col = cols[(size_t)k * 64 + lane];
     const double *a = vals + ((size_t)k * NV * NV + r * NV) * 64 + lane;
-    const XT *xc = x + (size_t)col * NV;
+    const gmem<const XT> *xc = x + (size_t)col * NV;
 #pragma unroll
     for (int c = 0; c < NV; c++) acc += a[c * 64] * double(xc[c]);
   }
@@ -494,7 +508,7 @@ __device__ __forceinline__ void block_store_partials(double (&acc)[MAXK], int kk
     double s = 0.0;
 #pragma unroll
     for (int w = 0; w < kBlock / 64; w++) s += sh[w][threadIdx.x];
-    part[(size_t)blockIdx.x * MAXK + threadIdx.x] = s;
+    part[(size_t)threadIdx.x * gridDim.x + blockIdx.x] = s;  // k-major: the reduction reads rows
   }
 }
 
@@ -583,10 +597,10 @@ __global__ void __launch_bounds__(kBlock) k_norm2_partial(const double *__restri
   block_store_partials<1>(acc, 1, part);
 }
 
-// out[k] = sum_blk partial[blk][k] for k < kk (kk = *jdev + 1, or kfix when jdev is
+// out[k] = sum_blk partial[k][blk] for k < kk (kk = *jdev + 1, or kfix when jdev is
 // null); one workgroup per k; fixed order: thread t sums blocks t, t+256, ...,
-// then a fixed tree, so the result does not depend on scheduling.
-template <int STRIDE>
+// then a fixed tree, so the result does not depend on scheduling.  The loads of
+// a thread (nblk <= kDotBlocks) are all issued before the first add.
 __global__ void __launch_bounds__(kBlock) k_reduce(const double *__restrict__ part, int nblk,
                                                    const int *__restrict__ jdev, int kfix,
                                                    double *__restrict__ out, int sqrt_out) {
@@ -594,8 +608,15 @@ __global__ void __launch_bounds__(kBlock) k_reduce(const double *__restrict__ pa
   const int kk = jdev ? *jdev + 1 : kfix;
   const int k = blockIdx.x;
   if (k >= kk) return;
+  const double *__restrict__ row = part + (size_t)k * nblk;
+  constexpr int kPer = kDotBlocks / kBlock;
+  double v[kPer];
+#pragma unroll
+  for (int q = 0; q < kPer; q++) v[q] = row[min((int)threadIdx.x + q * kBlock, nblk - 1)];
   double s = 0.0;
-  for (int b = threadIdx.x; b < nblk; b += kBlock) s += part[(size_t)b * STRIDE + k];
+#pragma unroll
+  for (int q = 0; q < kPer; q++)
+    if ((int)threadIdx.x + q * kBlock < nblk) s += v[q];
   s = wave_sum(s);
   if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
   __syncthreads();

@@ -50,6 +50,17 @@ struct Dia {
   const T *val = nullptr;
 };
 
+// Global-memory view of a pointer that a kernel reads from device memory (the
+// slots below): accesses through it compile to global, not flat, loads and
+// stores, which keeps them off the LDS counter and lets them be scheduled
+// with the other global loads.
+template <typename T>
+using gmem = T __attribute__((address_space(1)));
+template <typename T>
+__device__ __forceinline__ gmem<T> *as_global(T *p) {
+  return (gmem<T> *)p;
+}
+
 // pointer slots read by the first and last kernels of a preconditioner
 // application, so that one captured graph serves every Krylov column
 struct ApplySlots {
