@@ -911,9 +911,11 @@ static void build_precond(cptr_handle *h, const std::vector<int> &rp, const std:
     h->lrn = std::make_unique<LearnedDev>();
     h->lrn->build(n, nv, rp, ci, vals);
     P.lrn = h->lrn.get();
-    // learned stage: r = D^-1 b1, three layers (h read with 7 neighbours,
-    // written once), output
-    bytes += (double)n * (4.0 * nv * nv + 8.0 * nv) + 3.0 * n * (kDir * kEdge * 2 + 8.0 * kHid * 4 + 4.0 * kDir);
+    // learned stage: r = D^-1 b1 (FP32 diagonal blocks, b1, r), then three
+    // layers, each reading the presence mask, the BF16 edge blocks and the
+    // BF16 activations of its cells (neighbours' from cache) and writing
+    // theirs; the output layer's read-out is counted with z below
+    bytes += (double)n * (4.0 * nv * nv + 8.0 * nv) + 3.0 * h->lrn->layer_bytes();
   }
   if (o.second_stage == CPTR_SECOND_BILU0 || o.second_stage == CPTR_SECOND_BILU0_MC ||
       o.second_stage == CPTR_SECOND_LEARNED) {
