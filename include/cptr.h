@@ -113,6 +113,12 @@ typedef struct {
                             stored by diagonals, without column indices; 0: SELL-64 for all
                             short-row operators (1).  Both give the same sums in the same
                             order. */
+  int lrn_columns;       /* 1: the learned stage's inference layers after the first walk
+                            columns of tiles along the slowest axis when the cells form a grid
+                            numbered with the fastest axis first and a plane is a multiple of
+                            16 cells (rows of the -z/+z neighbours kept in registers, -x/+x by
+                            lane shuffles); 0: tiles in cell order with every neighbour row
+                            gathered (1).  Both give the same result bit for bit. */
 } cptr_options;
 
 typedef struct {

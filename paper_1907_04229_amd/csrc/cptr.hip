@@ -440,6 +440,10 @@ struct LearnedDev {
   int n = 0, nv = 0, nnzb = 0;
   DevMem nbr, nmask, E, dinv, tpos, r, s, spart, hA, hB;
   int stride[3] = {0, 0, 0};  // |column - row| of the neighbours along each axis
+  // z-column schedule of the inference layers (k_lrn_layer_col): planes of
+  // colP whole tiles, colNZ planes; colP = 0 when the grid does not allow it
+  int colP = 0, colNZ = 0;
+  bool use_col = true;
   bool have_pass = false;     // an inference pass has filled r, s, hA, hB
   DevMem H[4], M[3], Aa[3], dh0, dh1, dm, dhown, z2, res, dz, part, mid;
   bool train_ready = false;
@@ -512,6 +516,11 @@ struct LearnedDev {
       }
     // the neighbour in direction d is i -+ stride[d / 2]: a presence bit per direction
     for (size_t a = 0; a < mags.size(); a++) stride[a] = mags[a];
+    colP = colNZ = 0;
+    if (mags.size() == 3 && stride[0] == 1 && stride[2] % 16 == 0 && n % stride[2] == 0) {
+      colP = stride[2] / 16;
+      colNZ = n / stride[2];
+    }
     std::vector<unsigned char> mk(n, 0);
     for (int i = 0; i < n; i++)
       for (int d = 0; d < kDir; d++) {
@@ -611,6 +620,24 @@ struct LearnedDev {
         hipLaunchKernelGGL((k_lrn_layer<NV, false, true, float, ZT, XT>), dim3(lb), dim3(kBlock), 0, st, n, nbp,
                            str, Ep, sp, (const float *)devp<float>(H[2]), rp_, mdl.W_in(), We, Ws, Wm, bs,
                            devp<float>(H[3]), (float *)nullptr, Ml, Al, out);
+    } else if (use_col && colP > 0 && l > 0) {
+      // the layers after the first (whose input rows are nv floats, not 64
+      // BF16 channels); about four waves per SIMD, each walking zlen planes
+      // of one column
+      const int nchunk = std::max(1, std::min(colNZ, kColWaves / colP));
+      const int zlen = (colNZ + nchunk - 1) / nchunk;
+      const int items = colP * ((colNZ + zlen - 1) / zlen);
+      const int cb = kXcds * std::max(1, (items + 4 * kXcds - 1) / (4 * kXcds));
+      short *ha = devp<short>(hA), *hb = devp<short>(hB);
+      const int sy = stride[1];
+      if (l == 1)
+        hipLaunchKernelGGL((k_lrn_layer_col<NV, false, false, short, float, float>), dim3(cb), dim3(kBlock), 0, st,
+                           n, colP, colNZ, zlen, sy, Ep, sp, (const short *)ha, rp_, mdl.W_in(), We, Ws, Wm, bs, hb,
+                           none);
+      else
+        hipLaunchKernelGGL((k_lrn_layer_col<NV, false, true, short, ZT, XT>), dim3(cb), dim3(kBlock), 0, st, n,
+                           colP, colNZ, zlen, sy, Ep, sp, (const short *)hb, rp_, mdl.W_in(), We, Ws, Wm, bs,
+                           (short *)nullptr, out);
     } else {
       short *ha = devp<short>(hA), *hb = devp<short>(hB);
       if (l == 0)
@@ -910,6 +937,7 @@ static void build_precond(cptr_handle *h, const std::vector<int> &rp, const std:
   if (o.second_stage == CPTR_SECOND_LEARNED) {
     h->lrn = std::make_unique<LearnedDev>();
     h->lrn->build(n, nv, rp, ci, vals);
+    h->lrn->use_col = o.lrn_columns != 0;
     P.lrn = h->lrn.get();
     // learned stage: r = D^-1 b1 (FP32 diagonal blocks, b1, r), then three
     // layers, each reading the presence mask, the BF16 edge blocks and the
@@ -1407,6 +1435,7 @@ static void ensure_learned_data(cptr_handle *h) {
   CPTR_HIP_TRY(hipMemcpy(vals.data(), h->vals, sizeof(double) * vals.size(), hipMemcpyDeviceToHost));
   h->lrn = std::make_unique<LearnedDev>();
   h->lrn->build(n, nv, rp, ci, vals);
+  h->lrn->use_col = h->op.o.lrn_columns != 0;
 }
 
 }  // namespace cptr
@@ -1432,6 +1461,7 @@ void cptr_default_options(cptr_options *o) {
   o->use_graph = 1;
   o->resid_fp64 = 0;
   o->scalar_dia = 1;
+  o->lrn_columns = 1;
 }
 
 int cptr_setup(cptr_handle **out, const cptr_bsr *A, const cptr_csr *S_T, const cptr_options *opt,

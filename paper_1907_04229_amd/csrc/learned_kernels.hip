@@ -234,6 +234,7 @@ struct RawAct<HT, NV, true> {
 constexpr int kLayerMaxBlocks = 2048;
 constexpr int kXcds = 8;  // accelerator complex dies of the MI355X, each with its own L2
 constexpr int kWPad = kHid + 8;  // LDS row of W_s / W_m (BF16): padded, 16-byte aligned
+constexpr int kColWaves = 4096;  // target wave count of the z-column schedule (4 per SIMD)
 
 // One message-passing layer.  One wavefront per tile of 16 consecutive cells;
 // lane l owns cell c0 + l % 16 and the hidden channels lch(t, l / 16) + q
@@ -249,32 +250,26 @@ constexpr int kWPad = kHid + 8;  // LDS row of W_s / W_m (BF16): padded, 16-byte
 // LAST:  the read-out (LrnOut) is written; h_out may then be null.
 // m_out / a_out (optional) keep the messages and pre-activations for the
 // backward pass.
-template <int NV, bool FIRST, bool LAST, typename HT, typename ZT, typename XT>
-__global__ void __launch_bounds__(kBlock) k_lrn_layer(
-    int n, const unsigned char *__restrict__ nmask, int3 stride, const short *__restrict__ E,
-    const float *__restrict__ s_ptr, const HT *__restrict__ hin, const float *__restrict__ r, const float *__restrict__ W_in,
-    const float *__restrict__ W_e, const short *__restrict__ W_s, const short *__restrict__ W_m,
-    const float *__restrict__ bias, HT *__restrict__ hout, float *__restrict__ h0_out,
-    float *__restrict__ m_out, float *__restrict__ a_out, LrnOut<ZT, XT> out) {
-  __shared__ __attribute__((aligned(16))) short Wl[2][kHid][kWPad];
+// Per-workgroup set-up shared by both layer kernels: W_s and W_m staged in
+// LDS, 1 / s_k, and this lane's slice of W_e with the edge scaling folded in:
+// (W_e S^{-1} e S)_j = sum_k W_e[j][k] f_k e_k, f_k = s_c / s_r for k = r NV + c,
+// so the stored edge blocks are the B operand as they are.
+template <int NV>
+__device__ __forceinline__ void layer_setup(short (&Wl)[2][kHid][kWPad], const short *__restrict__ W_s,
+                                            const short *__restrict__ W_m, const float *__restrict__ W_e,
+                                            const float *__restrict__ s_ptr, int lr, int lg, float (&inv_s)[NV],
+                                            bf16x4 (&we)[4]) {
   for (int v = threadIdx.x; v < 2 * kHid * kHid / 4; v += kBlock) {
     const int mtx = v / (kHid * kHid / 4), e = (v % (kHid * kHid / 4)) * 4;
     const short *src = (mtx == 0 ? W_s : W_m) + e;
     *reinterpret_cast<bf16x4 *>(&Wl[mtx][e / kHid][e % kHid]) = load_bf4(src);
   }
   __syncthreads();
-  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-  const int lr = l & 15, lg = l >> 4;
-  const int ntiles = (n + 15) / 16;
-  float inv_s[NV];
 #pragma unroll
   for (int k = 0; k < NV; k++) {
     const float sk = s_ptr[k];
     inv_s[k] = sk > 0.f ? 1.f / sk : 0.f;
   }
-  // W_e with the edge scaling folded in: (W_e S^{-1} e S)_j = sum_k W_e[j][k] f_k e_k,
-  // f_k = s_c / s_r for k = r NV + c, so the stored edge blocks are the B operand as they are
-  bf16x4 we[4];
 #pragma unroll
   for (int t = 0; t < 4; t++)
 #pragma unroll
@@ -283,27 +278,121 @@ __global__ void __launch_bounds__(kBlock) k_lrn_layer(
       const int k = 4 * lg + q, row = lch(t, lr >> 2) + (lr & 3);
       we[t][q] = k < NV * NV ? f2bf(W_e[row * NV * NV + k] * edge_factor<NV>(k, s_ptr)) : short(0);
     }
-  // activations of `cell` at this lane's channels (FIRST: from r)
-  auto act = [&](int cell, f32x4 *h) {
-    if constexpr (FIRST) {
-      float u[NV];
+}
+
+// The arithmetic of one tile, shared by both layer kernels: given the cell's
+// activations hv, the raw activations of its six neighbours (direction d =
+// -x, +x, -y, +y, -z, +z; for an absent neighbour any finite row, its edge
+// block being zero) and the six edge blocks, form the messages, the K = 32
+// products, the update and the stores.  Lanes with ok == false store nothing.
+template <int NV, bool FIRST, bool LAST, typename HT, typename ZT, typename XT>
+__device__ __forceinline__ void layer_tile(int cell, bool ok, int lr, int lg, const f32x4 (&hv)[4],
+                                           const typename RawAct<HT, NV, FIRST>::type (&raw)[kDir],
+                                           const bf16x4 (&rawe)[kDir], const bf16x4 (&we)[4],
+                                           const short (&Wl)[2][kHid][kWPad], const float *__restrict__ W_in,
+                                           const float (&inv_s)[NV], const float *__restrict__ bias,
+                                           const float *__restrict__ r, const float *__restrict__ s_ptr,
+                                           HT *__restrict__ hout, float *__restrict__ h0_out,
+                                           float *__restrict__ m_out, float *__restrict__ a_out,
+                                           const LrnOut<ZT, XT> &out) {
+  __builtin_amdgcn_sched_barrier(0);
+  f32x4 macc[4];
 #pragma unroll
-      for (int k = 0; k < NV; k++) u[k] = r[(size_t)cell * NV + k] * inv_s[k];
+  for (int t = 0; t < 4; t++) macc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int d = 0; d < kDir; d++) {
+#pragma unroll
+    for (int t = 0; t < 4; t++) {
+      const f32x4 g = mfma16(we[t], rawe[d], f32x4{0.f, 0.f, 0.f, 0.f});
+      macc[t] += g * RawAct<HT, NV, FIRST>::get(raw[d], t, lg, W_in, inv_s);
+    }
+  }
+  __builtin_amdgcn_sched_barrier(0);
+  f32x4 acc[4];
+#pragma unroll
+  for (int t = 0; t < 4; t++) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int ks = 0; ks < 2; ks++) {
+    // B operands: channels 32 ks + 8 lg .. + 7 = slots 2 ks, 2 ks + 1
+    const bf16x8 hb = cat8(cvt4(hv[2 * ks][0], hv[2 * ks][1], hv[2 * ks][2], hv[2 * ks][3]),
+                           cvt4(hv[2 * ks + 1][0], hv[2 * ks + 1][1], hv[2 * ks + 1][2], hv[2 * ks + 1][3]));
+    const bf16x8 mb = cat8(cvt4(macc[2 * ks][0], macc[2 * ks][1], macc[2 * ks][2], macc[2 * ks][3]),
+                           cvt4(macc[2 * ks + 1][0], macc[2 * ks + 1][1], macc[2 * ks + 1][2], macc[2 * ks + 1][3]));
+#pragma unroll
+    for (int t = 0; t < 4; t++) {
+      const int row = lch(t, lr >> 2) + (lr & 3);
+      const bf16x8 ws = *reinterpret_cast<const bf16x8 *>(&Wl[0][row][32 * ks + 8 * lg]);
+      const bf16x8 wm = *reinterpret_cast<const bf16x8 *>(&Wl[1][row][32 * ks + 8 * lg]);
+      acc[t] = mfma32(ws, hb, acc[t]);
+      acc[t] = mfma32(wm, mb, acc[t]);
+    }
+  }
+  f32x4 hnew[4];
+#pragma unroll
+  for (int t = 0; t < 4; t++) {
+    f32x4 a;
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+      a[q] = acc[t][q] + bias[lch(t, lg) + q];
+      hnew[t][q] = hv[t][q] + fmaxf(a[q], 0.f);
+    }
+    if (ok) {
+      const size_t o = (size_t)cell * kHid + lch(t, lg);
+      if (hout) store_h4(hout + o, hnew[t]);
+      if (m_out) store_f4(m_out + o, macc[t]);
+      if (a_out) store_f4(a_out + o, a);
+      if (FIRST && h0_out) store_f4(h0_out + o, hv[t]);
+    }
+  }
+  if constexpr (LAST) {
+    float p[NV];
+#pragma unroll
+    for (int k = 0; k < NV; k++) {
+      float v = 0.f;
 #pragma unroll
       for (int t = 0; t < 4; t++)
 #pragma unroll
-        for (int q = 0; q < 4; q++) {
-          const int ch = lch(t, lg) + q;
-          float v = 0.f;
-#pragma unroll
-          for (int k = 0; k < NV; k++) v += W_in[ch * NV + k] * u[k];
-          h[t][q] = v;
-        }
-    } else {
-#pragma unroll
-      for (int t = 0; t < 4; t++) h[t] = load_h4(hin + (size_t)cell * kHid + lch(t, lg));
+        for (int q = 0; q < 4; q++) v += out.W_out[k * kHid + lch(t, lg) + q] * hnew[t][q];
+      v += __shfl_xor(v, 16);
+      v += __shfl_xor(v, 32);
+      p[k] = v;
     }
-  };
+    // lane group lg writes component k = lg of its cell
+    float pk = 0.f;
+#pragma unroll
+    for (int k = 0; k < NV; k++)
+      if (k == lg) pk = p[k];
+    if (ok && lg < NV) {
+      const size_t t = (size_t)cell * NV + lg;
+      float z = r[t] + s_ptr[lg] * pk;
+      if (out.z2_out) {
+        out.z2_out[t] = z;
+      } else {
+        if (out.dp && lg == out.ip) z += float(out.dp[cell]);
+        if (out.dT && lg == out.iT) z += float(out.dT[cell]);
+        reinterpret_cast<ZT *>(out.slots->z)[t] = ZT(z);
+      }
+    }
+  }
+}
+
+// One message-passing layer over tiles in cell order.  Any 7-point cell graph
+// (neighbours by presence mask and the three axis strides).
+template <int NV, bool FIRST, bool LAST, typename HT, typename ZT, typename XT>
+__global__ void __launch_bounds__(kBlock) k_lrn_layer(
+    int n, const unsigned char *__restrict__ nmask, int3 stride, const short *__restrict__ E,
+    const float *__restrict__ s_ptr, const HT *__restrict__ hin, const float *__restrict__ r, const float *__restrict__ W_in,
+    const float *__restrict__ W_e, const short *__restrict__ W_s, const short *__restrict__ W_m,
+    const float *__restrict__ bias, HT *__restrict__ hout, float *__restrict__ h0_out,
+    float *__restrict__ m_out, float *__restrict__ a_out, LrnOut<ZT, XT> out) {
+  __shared__ __attribute__((aligned(16))) short Wl[2][kHid][kWPad];
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int lr = l & 15, lg = l >> 4;
+  const int ntiles = (n + 15) / 16;
+  float inv_s[NV];
+  bf16x4 we[4];
+  layer_setup<NV>(Wl, W_s, W_m, W_e, s_ptr, lr, lg, inv_s, we);
+  using Raw = RawAct<HT, NV, FIRST>;
   const int off[kDir] = {-stride.x, stride.x, -stride.y, stride.y, -stride.z, stride.z};
   // XCD-aware order: workgroups are dealt to the 8 XCDs round robin, so the
   // workgroups of one XCD (blockIdx % 8) take one contiguous eighth of the
@@ -323,96 +412,100 @@ __global__ void __launch_bounds__(kBlock) k_lrn_layer(
     const int cl = ok ? cell : n - 1;
     const unsigned mk = mk_next;  // bit d: neighbour cell + off[d] exists
     if (tile + nwx < t_end) mk_next = nmask[min((tile + nwx) * 16 + lr, n - 1)];
-    f32x4 hv[4];
-    act(cl, hv);
-    // messages: all loads are issued first and consumed direction by
-    // direction.  An absent neighbour has a zero edge block, so its (any
-    // finite) activations -- the cell's own are read in its place -- add zero.
-    typename RawAct<HT, NV, FIRST>::type raw[kDir];
+    // all loads are issued first and consumed direction by direction.  An
+    // absent neighbour has a zero edge block, so its (any finite) activations
+    // -- the cell's own are read in its place -- add zero.
+    const typename Raw::type own = Raw::load(cl, lg, hin, r);
+    typename Raw::type raw[kDir];
     bf16x4 rawe[kDir];
 #pragma unroll
     for (int d = 0; d < kDir; d++) {
       rawe[d] = __builtin_nontemporal_load(reinterpret_cast<const bf16x4 *>(E + ((size_t)cl * kDir + d) * kEdge + 4 * lg));
-      raw[d] = RawAct<HT, NV, FIRST>::load((mk >> d) & 1u ? cl + off[d] : cl, lg, hin, r);
+      raw[d] = Raw::load((mk >> d) & 1u ? cl + off[d] : cl, lg, hin, r);
     }
-    __builtin_amdgcn_sched_barrier(0);
-    f32x4 macc[4];
+    f32x4 hv[4];
 #pragma unroll
-    for (int t = 0; t < 4; t++) macc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int t = 0; t < 4; t++) hv[t] = Raw::get(own, t, lg, W_in, inv_s);
+    layer_tile<NV, FIRST, LAST, HT, ZT, XT>(cell, ok, lr, lg, hv, raw, rawe, we, Wl, W_in, inv_s, bias, r, s_ptr,
+                                           hout, h0_out, m_out, a_out, out);
+  }
+}
+
+// x-neighbour rows by lane shuffle: lane lr of each 16-lane DPP row takes the
+// value of lane lr - 1 (row_shr:1) or lr + 1 (row_shl:1); the lane at the end
+// of the row, which has no such lane, keeps `edge` (bound_ctrl off).
+template <typename R, int CTRL>
+__device__ __forceinline__ R shuffle_row(const R &own, const R &edge) {
+  static_assert(sizeof(R) % 4 == 0, "raw activations are whole dwords");
+  constexpr int nd = sizeof(R) / 4;
+  struct D { int v[nd]; };
+  const D o = __builtin_bit_cast(D, own), e = __builtin_bit_cast(D, edge);
+  D res;
 #pragma unroll
-    for (int d = 0; d < kDir; d++) {
+  for (int i = 0; i < nd; i++) res.v[i] = __builtin_amdgcn_update_dpp(e.v[i], o.v[i], CTRL, 0xf, 0xf, false);
+  return __builtin_bit_cast(R, res);
+}
+constexpr int kDppRowShr1 = 0x111;  // lane i <- lane i - 1 within a row of 16
+constexpr int kDppRowShl1 = 0x101;  // lane i <- lane i + 1 within a row of 16
+
+// The same layer on a structured grid whose cells are numbered x fastest with
+// a plane (stride.z) of P whole tiles: a wave walks a column of tiles along z
+// (tile (p, z) = cells (z P + p) 16 ..), so the -z row is the previous tile's
+// own and the +z row the next tile's own, kept in registers; -x and +x come
+// from the lanes next door, with one load for the two lanes at the tile ends;
+// only +-y are gathered.  Columns are cut into chunks of zlen planes; each
+// XCD takes a contiguous range of columns (with all their chunks), so the
+// waves that share +-y rows run on the same L2 at the same time.  The result
+// is the one of k_lrn_layer, bit for bit: every neighbour row that is present
+// is the same row, every absent one finite (and multiplied by zero).
+template <int NV, bool FIRST, bool LAST, typename HT, typename ZT, typename XT>
+__global__ void __launch_bounds__(kBlock) k_lrn_layer_col(
+    int n, int P, int nz, int zlen, int sy, const short *__restrict__ E, const float *__restrict__ s_ptr,
+    const HT *__restrict__ hin, const float *__restrict__ r, const float *__restrict__ W_in,
+    const float *__restrict__ W_e, const short *__restrict__ W_s, const short *__restrict__ W_m,
+    const float *__restrict__ bias, HT *__restrict__ hout, LrnOut<ZT, XT> out) {
+  __shared__ __attribute__((aligned(16))) short Wl[2][kHid][kWPad];
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int lr = l & 15, lg = l >> 4;
+  float inv_s[NV];
+  bf16x4 we[4];
+  layer_setup<NV>(Wl, W_s, W_m, W_e, s_ptr, lr, lg, inv_s, we);
+  using Raw = RawAct<HT, NV, FIRST>;
+  using RT = typename Raw::type;
+  const int sz = P * 16;
+  const int nchunk = (nz + zlen - 1) / zlen;
+  const int items = P * nchunk;                       // (column, chunk) pairs
+  const int per = (items + kXcds - 1) / kXcds;        // per XCD, column-major
+  const int nwx = (gridDim.x / kXcds) * (kBlock / 64);
+  const int xcd = blockIdx.x % kXcds;
+  const int i_end = min(items, (xcd + 1) * per);
+  for (int item = xcd * per + (blockIdx.x / kXcds) * (kBlock / 64) + w; item < i_end; item += nwx) {
+    const int p = item / nchunk, z0 = (item % nchunk) * zlen, z1 = min(nz, z0 + zlen);
+    int cell = (z0 * P + p) * 16 + lr;
+    RT rp = Raw::load(z0 > 0 ? cell - sz : cell, lg, hin, r);
+    RT rc = Raw::load(cell, lg, hin, r);
+    for (int z = z0; z < z1; z++, cell += sz) {
+      const RT rn = Raw::load(z + 1 < nz ? cell + sz : cell, lg, hin, r);
+      RT raw[kDir];
+      raw[2] = Raw::load(max(cell - sy, 0), lg, hin, r);
+      raw[3] = Raw::load(min(cell + sy, n - 1), lg, hin, r);
+      RT xe = rc;
+      if (lr == 0 || lr == 15) xe = Raw::load(lr == 0 ? max(cell - 1, 0) : min(cell + 1, n - 1), lg, hin, r);
+      bf16x4 rawe[kDir];
 #pragma unroll
-      for (int t = 0; t < 4; t++) {
-        const f32x4 g = mfma16(we[t], rawe[d], f32x4{0.f, 0.f, 0.f, 0.f});
-        macc[t] += g * RawAct<HT, NV, FIRST>::get(raw[d], t, lg, W_in, inv_s);
-      }
-    }
-    __builtin_amdgcn_sched_barrier(0);
-    f32x4 acc[4];
+      for (int d = 0; d < kDir; d++)
+        rawe[d] = __builtin_nontemporal_load(reinterpret_cast<const bf16x4 *>(E + ((size_t)cell * kDir + d) * kEdge + 4 * lg));
+      raw[0] = shuffle_row<RT, kDppRowShr1>(rc, xe);
+      raw[1] = shuffle_row<RT, kDppRowShl1>(rc, xe);
+      raw[4] = rp;
+      raw[5] = rn;
+      f32x4 hv[4];
 #pragma unroll
-    for (int t = 0; t < 4; t++) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int ks = 0; ks < 2; ks++) {
-      // B operands: channels 32 ks + 8 lg .. + 7 = slots 2 ks, 2 ks + 1
-      const bf16x8 hb = cat8(cvt4(hv[2 * ks][0], hv[2 * ks][1], hv[2 * ks][2], hv[2 * ks][3]),
-                             cvt4(hv[2 * ks + 1][0], hv[2 * ks + 1][1], hv[2 * ks + 1][2], hv[2 * ks + 1][3]));
-      const bf16x8 mb = cat8(cvt4(macc[2 * ks][0], macc[2 * ks][1], macc[2 * ks][2], macc[2 * ks][3]),
-                             cvt4(macc[2 * ks + 1][0], macc[2 * ks + 1][1], macc[2 * ks + 1][2], macc[2 * ks + 1][3]));
-#pragma unroll
-      for (int t = 0; t < 4; t++) {
-        const int row = lch(t, lr >> 2) + (lr & 3);
-        const bf16x8 ws = *reinterpret_cast<const bf16x8 *>(&Wl[0][row][32 * ks + 8 * lg]);
-        const bf16x8 wm = *reinterpret_cast<const bf16x8 *>(&Wl[1][row][32 * ks + 8 * lg]);
-        acc[t] = mfma32(ws, hb, acc[t]);
-        acc[t] = mfma32(wm, mb, acc[t]);
-      }
-    }
-    f32x4 hnew[4];
-#pragma unroll
-    for (int t = 0; t < 4; t++) {
-      f32x4 a;
-#pragma unroll
-      for (int q = 0; q < 4; q++) {
-        a[q] = acc[t][q] + bias[lch(t, lg) + q];
-        hnew[t][q] = hv[t][q] + fmaxf(a[q], 0.f);
-      }
-      if (ok) {
-        const size_t o = (size_t)cell * kHid + lch(t, lg);
-        if (hout) store_h4(hout + o, hnew[t]);
-        if (m_out) store_f4(m_out + o, macc[t]);
-        if (a_out) store_f4(a_out + o, a);
-        if (FIRST && h0_out) store_f4(h0_out + o, hv[t]);
-      }
-    }
-    if constexpr (LAST) {
-      float p[NV];
-#pragma unroll
-      for (int k = 0; k < NV; k++) {
-        float v = 0.f;
-#pragma unroll
-        for (int t = 0; t < 4; t++)
-#pragma unroll
-          for (int q = 0; q < 4; q++) v += out.W_out[k * kHid + lch(t, lg) + q] * hnew[t][q];
-        v += __shfl_xor(v, 16);
-        v += __shfl_xor(v, 32);
-        p[k] = v;
-      }
-      // lane group lg writes component k = lg of its cell
-      float pk = 0.f;
-#pragma unroll
-      for (int k = 0; k < NV; k++)
-        if (k == lg) pk = p[k];
-      if (ok && lg < NV) {
-        const size_t t = (size_t)cell * NV + lg;
-        float z = r[t] + s_ptr[lg] * pk;
-        if (out.z2_out) {
-          out.z2_out[t] = z;
-        } else {
-          if (out.dp && lg == out.ip) z += float(out.dp[cell]);
-          if (out.dT && lg == out.iT) z += float(out.dT[cell]);
-          reinterpret_cast<ZT *>(out.slots->z)[t] = ZT(z);
-        }
-      }
+      for (int t = 0; t < 4; t++) hv[t] = Raw::get(rc, t, lg, W_in, inv_s);
+      layer_tile<NV, FIRST, LAST, HT, ZT, XT>(cell, true, lr, lg, hv, raw, rawe, we, Wl, W_in, inv_s, bias, r, s_ptr,
+                                             hout, nullptr, nullptr, nullptr, out);
+      rp = rc;
+      rc = rn;
     }
   }
 }

@@ -23,8 +23,12 @@ pytestmark = pytest.mark.gpu
 DEV = "cuda"
 
 CASES = {
+    # planes of 63 cells: tiles in cell order (k_lrn_layer)
     "nv3": dict(shape=(9, 7, 5), kind="gaussian", sigma=1.5, corr_len=3.0, seed=41),
+    # planes of 48 and 48 cells: the z-column schedule (k_lrn_layer_col) after the
+    # first layer; rows of 8 and 12 cells, so tiles straddle rows
     "nv4": dict(shape=(8, 6, 5), kind="gaussian", sigma=1.5, corr_len=3.0, seed=42, three_phase=True),
+    "nv3c": dict(shape=(12, 4, 6), kind="gaussian", sigma=1.5, corr_len=3.0, seed=43),
 }
 _cache = {}
 
@@ -54,7 +58,7 @@ def solver_with(pr, theta, **kw):
     return s, m
 
 
-@pytest.mark.parametrize("name", ["nv3", "nv4"])
+@pytest.mark.parametrize("name", ["nv3", "nv4", "nv3c"])
 def test_forward_matches_oracle(name):
     banner(f"forward {name}")
     pr, nbr, dinv, E, A = case(name)
@@ -89,6 +93,42 @@ def test_forward_matches_oracle(name):
     print(f"homogeneity (7.5) rel err {rel2(z7, 7.5 * z):.2e}")
     assert rel2(z7, 7.5 * z) <= 1e-3
     s.close()
+
+
+COLUMN_SHAPES = [
+    dict(shape=(12, 4, 6), kind="gaussian", sigma=1.5, corr_len=3.0, seed=43),          # rows straddle tiles
+    dict(shape=(16, 8, 9), kind="gaussian", sigma=1.5, corr_len=3.0, seed=44),          # one tile per row
+    dict(shape=(8, 6, 5), kind="gaussian", sigma=1.5, corr_len=3.0, seed=42, three_phase=True),
+    dict(shape=(64, 32, 40), kind="gaussian", sigma=2.0, corr_len=6.0, seed=45),        # 2 planes per wave
+    dict(shape=(128, 64, 22), kind="gaussian", sigma=2.0, corr_len=6.0, seed=46),       # 3, last chunk 1
+]
+
+
+@pytest.mark.parametrize("k", range(len(COLUMN_SHAPES)))
+def test_column_schedule_is_bit_exact(k):
+    """The z-column schedule of the inference layers (lrn_columns = 1: -z/+z
+    rows from registers, -x/+x by lane shuffles) gives the result of the
+    tile-order kernel (lrn_columns = 0) bit for bit: the stage output, and
+    FGMRES iterations and solution."""
+    pr = make_problem(**COLUMN_SHAPES[k])
+    banner(f"column schedule {pr.shape} nv={pr.nv}")
+    theta = init_params(pr.nv, seed=7, out_scale=0.3)
+    b1 = torch.as_tensor(np.random.default_rng(8).standard_normal(pr.n * pr.nv), device=DEV)
+    b = torch.as_tensor(pr.b, device=DEV)
+    res = []
+    for col in (1, 0):
+        s, m = solver_with(pr, neumann_params(pr.nv, seed=1), precision="fp32", second_stage="learned",
+                           lrn_columns=col)
+        x, info = s.solve(b, restart=30, rtol=1e-6)
+        m.set_params(theta)
+        z = cptr.cptr_learn_forward(s, b1)
+        torch.cuda.synchronize()
+        res.append((z, info["iters"], x))
+        s.close()
+        m.close()
+    assert torch.equal(res[0][0], res[1][0])
+    assert res[0][1] == res[1][1]
+    assert torch.equal(res[0][2], res[1][2])
 
 
 @pytest.mark.parametrize("name", ["nv3", "nv4"])
