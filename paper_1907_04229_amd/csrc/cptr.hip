@@ -656,8 +656,11 @@ struct LearnedDev {
     LAUNCH_CHECK();
   }
   // algorithmic HBM bytes of one inference launch of layer 1 (BF16 activations
-  // in and out, the six BF16 edge blocks, the presence mask)
-  double layer_bytes() const { return (double)n * (2.0 * kHid * 2 + kDir * kEdge * 2 + 1); }
+  // in and out, the six BF16 edge blocks; the presence mask unless the
+  // z-column kernel runs, which reads none)
+  double layer_bytes() const {
+    return (double)n * (2.0 * kHid * 2 + kDir * kEdge * 2 + (use_col && colP > 0 ? 0 : 1));
+  }
 };
 
 // ---------------------------------------------------------------- preconditioner
