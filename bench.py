@@ -145,7 +145,7 @@ def cpu_baseline(pr, iters):
                        f"excluded), single thread")
 
 
-def train_model(cfg, steps, lr, systems, pairs, batch, first, log_fn):
+def train_model(cfg, steps, lr, systems, pairs, batch, first, log_fn, lr_final=None, rollback=None):
     from paper_1907_04229_amd.learned import train
     from paper_1907_04229_amd.synth import make_problem
     kw = {k: v for k, v in cfg.items() if k not in ("shape", "seed", "restart")}
@@ -158,12 +158,13 @@ def train_model(cfg, steps, lr, systems, pairs, batch, first, log_fn):
     t_gen = time.perf_counter() - t0
     t0 = time.perf_counter()
     model, hist = train(probs, probs[0].nv, steps=steps, batch=batch, pairs=pairs, lr=lr, seed=1,
-                        eval_every=50, val_problems=vprobs, val_restart=cfg["restart"], precision="fp32",
-                        second_stage="bilu0_mc", first_stage=first)
+                        eval_every=50, val_problems=vprobs, val_restart=cfg["restart"], rollback=rollback,
+                        lr_final=lr_final, precision="fp32", second_stage="bilu0_mc", first_stage=first)
     t_train = time.perf_counter() - t0
     log_fn(f"trained {steps} steps in {t_train:.1f} s (data {t_gen:.1f} s); validation "
            f"{[(k, round(v, 4), it) for k, v, it in hist['val']]}, kept step {hist['best_step']}")
-    info = dict(train_s=round(t_train, 2), data_s=round(t_gen, 2), steps=steps, lr=lr,
+    info = dict(train_s=round(t_train, 2), data_s=round(t_gen, 2), steps=steps, lr=lr, lr_final=lr_final,
+                rollback=rollback, rollbacks=hist["rollbacks"],
                 systems=f"{len(seeds)} x {'x'.join(map(str, TRAIN_SHAPE))}, seeds {seeds}", pairs=pairs,
                 batch=batch,
                 validation_systems=f"{len(vseeds)} x {'x'.join(map(str, cfg['shape']))}, seeds {vseeds}",
@@ -244,8 +245,13 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="learned")
-    ap.add_argument("--train-steps", type=int, default=1000)
+    ap.add_argument("--train-steps", type=int, default=2000)
     ap.add_argument("--train-lr", type=float, default=1e-5)
+    ap.add_argument("--train-lr-final", type=float, default=1e-6,
+                    help="step size at the last step (half-cosine decay from --train-lr)")
+    ap.add_argument("--train-rollback", type=float, default=3.0,
+                    help="continue from the kept parameters when the validation loss exceeds this "
+                         "multiple of its lowest value (0: off)")
     ap.add_argument("--train-systems", type=int, default=8)
     ap.add_argument("--train-pairs", type=int, default=48)
     ap.add_argument("--train-batch", type=int, default=8)
@@ -308,7 +314,8 @@ def main():
                     relres_true=info["relres_true"])
 
     model, train_info = train_model(cfg, args.train_steps, args.train_lr, args.train_systems,
-                                    args.train_pairs, args.train_batch, args.first, log)
+                                    args.train_pairs, args.train_batch, args.first, log,
+                                    lr_final=args.train_lr_final, rollback=args.train_rollback or None)
 
     # the measured configuration: learned second stage, FP32 preconditioner
     sl, setup_l = setup(precision="fp32", second_stage="learned", first_stage=args.first)

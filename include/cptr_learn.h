@@ -44,6 +44,8 @@ size_t cptr_learn_param_count(int nv);
 /* New model on the current device with parameters theta_host (host FP32,
  * cptr_learn_param_count(nv) values).  Adam state starts at zero. */
 int cptr_learn_create(cptr_learn_model **out, int nv, const float *theta_host);
+/* Replace the parameters (host, count as above).  New parameters start a new
+ * optimisation: the Adam moments and step count are reset to zero. */
 int cptr_learn_set_params(cptr_learn_model *m, const float *theta_host);
 int cptr_learn_get_params(const cptr_learn_model *m, float *theta_host);
 void cptr_learn_destroy(cptr_learn_model *m);

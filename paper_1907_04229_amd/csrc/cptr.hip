@@ -1794,6 +1794,10 @@ int cptr_learn_set_params(cptr_learn_model *m, const float *theta_host) {
   try {
     CPTR_HIP_TRY(hipDeviceSynchronize());
     CPTR_HIP_TRY(hipMemcpy(m->dev.theta.p, theta_host, (size_t)m->dev.np * 4, hipMemcpyHostToDevice));
+    // new parameters start a new optimisation: Adam moments and step count reset
+    CPTR_HIP_TRY(hipMemset(m->dev.am.p, 0, (size_t)m->dev.np * 4));
+    CPTR_HIP_TRY(hipMemset(m->dev.av.p, 0, (size_t)m->dev.np * 4));
+    m->dev.step = 0;
     m->dev.pack(0);
     CPTR_HIP_TRY(hipDeviceSynchronize());
     return CPTR_OK;

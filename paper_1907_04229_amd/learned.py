@@ -57,7 +57,8 @@ def training_pairs(solver, count, seed, restart=30, rtol=1e-6):
 
 
 def train(problems, nv, steps=200, batch=4, pairs=16, lr=1e-5, seed=0, log=None,
-          theta0=None, val_frac=0.25, eval_every=25, val_problems=None, val_restart=30, **solver_opts):
+          theta0=None, val_frac=0.25, eval_every=25, val_problems=None, val_restart=30,
+          rollback=None, lr_final=None, **solver_opts):
     """Train one model on the given systems.
 
     The pairs of every system are split into a training and a validation part
@@ -68,7 +69,13 @@ def train(problems, nv, steps=200, batch=4, pairs=16, lr=1e-5, seed=0, log=None,
     validation loss; without them, the lowest validation loss.  Returns
     (model, history) with history = {"train": loss per step, "val":
     [(step, validation loss, iterations or None)], "best_step": step of the
-    kept parameters}.
+    kept parameters, "rollbacks": steps at which training was rolled back}.
+
+    rollback: when a validation loss is not finite or exceeds `rollback` times
+    the lowest one so far, training continues from the kept parameters with a
+    fresh Adam state (a divergence guard).  lr_final: the step size decays
+    from `lr` to `lr_final` on a half cosine over the steps (constant when
+    None).
     """
     import torch
     theta = neumann_params(nv, seed=seed) if theta0 is None else theta0
@@ -111,15 +118,22 @@ def train(problems, nv, steps=200, batch=4, pairs=16, lr=1e-5, seed=0, log=None,
         return (it if it is not None else 0, v)
 
     rng = np.random.Generator(np.random.PCG64(seed + 7))
-    hist = {"train": [], "val": [], "best_step": 0}
+    hist = {"train": [], "val": [], "best_step": 0, "rollbacks": []}
     v0, i0 = val_loss(), val_iters()
     best = (key(v0, i0), model.params())
+    lowest = v0
     hist["val"].append((0, v0, i0))
+
+    def step_size(step):
+        if lr_final is None or steps <= 1:
+            return lr
+        return lr_final + 0.5 * (lr - lr_final) * (1.0 + np.cos(np.pi * step / (steps - 1)))
+
     for step in range(steps):
         s, data, _ = sets[step % len(sets)]
         model.attach(s)
         idx = rng.choice(data.shape[0], size=min(batch, data.shape[0]), replace=False)
-        loss = cptr.cptr_learn_train_step(s, data[idx], lr)
+        loss = cptr.cptr_learn_train_step(s, data[idx], step_size(step))
         hist["train"].append(loss)
         if (step + 1) % eval_every == 0 or step == steps - 1:
             v, it = val_loss(), val_iters()
@@ -127,6 +141,11 @@ def train(problems, nv, steps=200, batch=4, pairs=16, lr=1e-5, seed=0, log=None,
             if key(v, it) < best[0]:
                 best = (key(v, it), model.params())
                 hist["best_step"] = step + 1
+            if rollback is not None and (not np.isfinite(v) or v > rollback * lowest):
+                model.set_params(best[1])  # and a fresh Adam state
+                hist["rollbacks"].append(step + 1)
+            elif np.isfinite(v):
+                lowest = min(lowest, v)
             if log:
                 log(f"step {step + 1}: train loss {loss:.4f}, validation loss {v:.4f}"
                     + (f", validation iterations {it}" if it is not None else ""))

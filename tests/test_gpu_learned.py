@@ -174,6 +174,34 @@ def test_training_reduces_loss():
     s.close()
 
 
+def test_set_params_restarts_adam():
+    """Setting parameters resets the Adam moments and step count: Adam steps
+    from theta after other steps and set_params(theta) give the parameters
+    of the same steps taken by a new model, bit for bit (the divergence guard
+    of training relies on this)."""
+    banner("set_params restarts Adam")
+    pr = make_problem(shape=(16, 16, 8), kind="gaussian", sigma=2.0, corr_len=4.0, seed=101)
+    theta = neumann_params(pr.nv, seed=1)
+    s, m = solver_with(pr, theta, precision="fp32", second_stage="bilu0_mc")
+    data = training_pairs(s, 8, seed=12)
+    for _ in range(3):
+        cptr.cptr_learn_train_step(s, data[:4], 1e-4)
+    m.set_params(theta)
+    for _ in range(2):
+        cptr.cptr_learn_train_step(s, data[4:], 1e-5)
+    after_reset = m.params()
+    s.close()
+    m.close()
+    s, m = solver_with(pr, theta, precision="fp32", second_stage="bilu0_mc")
+    for _ in range(2):
+        cptr.cptr_learn_train_step(s, data[4:], 1e-5)
+    fresh = m.params()
+    s.close()
+    m.close()
+    assert not np.array_equal(fresh, theta)
+    assert np.array_equal(after_reset, fresh)
+
+
 def _fgmres_iters(pr, **kw):
     s = cptr.Solver(pr, device=DEV, **{"precision": "fp32", **kw})
     x, info = s.solve(torch.as_tensor(pr.b, device=DEV), restart=30, rtol=1e-6)
