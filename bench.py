@@ -56,15 +56,17 @@ def layer_source_hash():
         return hashlib.sha256(f.read()).hexdigest()
 
 
-def recorded_traffic(cells):
+def recorded_traffic(cells, nv):
     """HBM bytes per launch of the middle layer from the committed counter
-    runs, if they were taken on the current kernel source and cell count."""
+    runs, if they were taken on the current kernel source, cell count and
+    number of unknowns per cell."""
     try:
         with open(TRAFFIC_FILE) as f:
             rec = json.load(f)
     except (OSError, ValueError):
         return None
-    if rec.get("source_sha256") != layer_source_hash() or rec.get("cells") != cells:
+    if (rec.get("source_sha256") != layer_source_hash() or rec.get("cells") != cells
+            or f"<{nv}," not in rec.get("kernel", "")):
         return None
     return rec.get("bytes_per_launch")
 
@@ -79,7 +81,7 @@ def layer_roofline(solver, reps=50):
     no mask."""
     import torch
     from paper_1907_04229_amd import cptr
-    n = solver.problem.n
+    n, nv = solver.problem.n, solver.problem.nv
     nx, ny, _ = solver.problem.shape
     column = (nx * ny) % 16 == 0
     st = torch.cuda.current_stream()
@@ -94,10 +96,10 @@ def layer_roofline(solver, reps=50):
     avg_s = e0.elapsed_time(e1) / reps * 1e-3
     algo = n * (2 * 64 * 2 + 6 * 16 * 2 + (0 if column else 1))
     gbs = algo / avg_s / 1e9
-    name = ("k_lrn_layer_col<3,false,false,bf16> (message-passing layer, inference, z-column schedule)"
-            if column else "k_lrn_layer<3,false,false,bf16> (message-passing layer, inference)")
+    name = (f"k_lrn_layer_col<{nv},false,false,bf16> (message-passing layer, inference, z-column schedule)"
+            if column else f"k_lrn_layer<{nv},false,false,bf16> (message-passing layer, inference)")
     return dict(bound="hbm", achieved=round(gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                frac=round(gbs / HBM_PEAK_GBS, 4), traffic=recorded_traffic(n), kernel=name,
+                frac=round(gbs / HBM_PEAK_GBS, 4), traffic=recorded_traffic(n, nv), kernel=name,
                 bytes_per_launch=int(algo), avg_us=round(avg_s * 1e6, 2), launches=reps)
 
 
@@ -205,8 +207,8 @@ def held_out_eval(cfg, model, restart, first, log_fn):
             torch.cuda.synchronize()
             dt = time.perf_counter() - t0
             s.close()
-            assert info["converged"] and info["relres_true"] <= 1e-6, f"seed {seed} {tag} did not converge"
-            row[tag] = dict(iters=info["iters"], time_s=round(dt, 5), fell_back=info["fell_back"])
+            row[tag] = dict(iters=info["iters"], time_s=round(dt, 5), fell_back=info["fell_back"],
+                            converged=bool(info["converged"] and info["relres_true"] <= 1e-6))
         untrained.close()
         log_fn(f"held-out seed {seed}: " + ", ".join(f"{k} {v['iters']} its {v['time_s'] * 1e3:.1f} ms"
                                                       for k, v in row.items() if k != "seed"))
@@ -285,7 +287,7 @@ def main():
         f"{time.perf_counter() - t0:.1f} s")
     b = torch.as_tensor(pr.b, device="cuda")
 
-    def run(solver, steps, warmup, tag):
+    def run(solver, steps, warmup, tag, measured=False):
         for _ in range(warmup):
             solver.solve(b, restart=restart, rtol=1e-6)
         torch.cuda.synchronize()
@@ -299,7 +301,10 @@ def main():
         info = infos[-1]
         log(f"{tag}: {dt * 1e3:.2f} ms/solve, {info['iters']} iterations, true relres "
             f"{info['relres_true']:.2e}, fell back {info['fell_back']}")
-        assert info["converged"] and info["relres_true"] <= 1e-6, f"{tag} did not converge"
+        # the measured configuration must converge; a comparison leg that does
+        # not is reported as such
+        if measured:
+            assert info["converged"] and info["relres_true"] <= 1e-6, f"{tag} did not converge"
         return dt, info, x
 
     def setup(**opt):
@@ -311,7 +316,9 @@ def main():
     def leg(dt, info, setup_s):
         return dict(time_to_tol_s=round(dt, 5), iters=info["iters"],
                     cell_iters_per_s=round(pr.n * info["iters"] / dt, 1), setup_s=round(setup_s, 3),
-                    relres_true=info["relres_true"])
+                    relres_true=info["relres_true"],
+                    converged=bool(info["converged"] and info["relres_true"] <= 1e-6),
+                    fell_back=info["fell_back"])
 
     model, train_info = train_model(cfg, args.train_steps, args.train_lr, args.train_systems,
                                     args.train_pairs, args.train_batch, args.first, log,
@@ -320,7 +327,7 @@ def main():
     # the measured configuration: learned second stage, FP32 preconditioner
     sl, setup_l = setup(precision="fp32", second_stage="learned", first_stage=args.first)
     model.attach(sl)
-    dt, info, x_l = run(sl, args.steps, args.warmup, "learned+fp32")
+    dt, info, x_l = run(sl, args.steps, args.warmup, "learned+fp32", measured=True)
     roof = layer_roofline(sl)
     log(f"layer roofline: {roof}")
 
