@@ -59,6 +59,8 @@ extern "C" {
 #define CPTR_FIRST_BLOCK 1       /* CPTR-Block: the five steps of eq:Aschur */
 #define CPTR_FIRST_BLOCK_LOWER 2 /* right factor of eq:Aschur dropped (block lower triangular) */
 #define CPTR_FIRST_CPR 3         /* CPR: x1 = R_p^T V(A_pp) R_p v */
+#define CPTR_FIRST_BD 4          /* CPTR-BD(AMG) (Section 4.4): block-diagonal first stage,
+                                    d_p = V(A_pp) b_p, d_T = V(A_TT) b_T (couplings left out) */
 
 /* second stage */
 #define CPTR_SECOND_NONE 0       /* z = x1 */
@@ -99,7 +101,8 @@ typedef struct {
   unsigned amg_seed;     /* aggregation priority seed (0) */
   int amg_sweeps;        /* l1-Jacobi sweeps before and after the coarse correction (2) */
   int amg_smooth_p;      /* 1 smoothed aggregation, 0 plain aggregation (1) */
-  int amg_smooth_p_T;    /* the same for the S~_T hierarchy alone; -1: as amg_smooth_p (0).
+  int amg_smooth_p_T;    /* the same for the second hierarchy alone (S~_T; A_TT for
+                            CPTR_FIRST_BD); -1: as amg_smooth_p (0).
                             Plain aggregation keeps the S~_T V-cycle convergent where the
                             smoothed prolongator does not (rows that are not diagonally
                             dominant, three-phase systems) and needs fewer FGMRES iterations
@@ -157,7 +160,8 @@ typedef struct cptr_handle cptr_handle;
 void cptr_default_options(cptr_options *opt);
 
 /* Build the preconditioner for A (first stage: sub-block extraction eq:A00,
- * two AMG hierarchies for A_pp and S~_T; second stage: BILU(0) factors).
+ * two AMG hierarchies for A_pp and S~_T -- A_TT for CPTR_FIRST_BD; second
+ * stage: BILU(0) factors).
  *   out   receives the handle (NULL on failure).
  *   A     must stay alive and unchanged until cptr_destroy: A->vals (FP64) is
  *         BORROWED for the FP64 Arnoldi products; everything derived is owned.
@@ -181,8 +185,9 @@ int cptr_apply(cptr_handle *h, const double *v, double *z, void *stream);
  * the saturation slots).  Device FP64 [n*nv].  Asynchronous. */
 int cptr_first_stage(cptr_handle *h, const double *v, double *x1, void *stream);
 
-/* One AMG V-cycle from a zero initial guess on A_pp (which = 0) or S~_T
- * (which = 1), in the handle's precision: x = V(b).  Device FP64 [n].
+/* One AMG V-cycle from a zero initial guess on A_pp (which = 0) or the
+ * second hierarchy (which = 1: S~_T, or A_TT with CPTR_FIRST_BD), in the
+ * handle's precision: x = V(b).  Device FP64 [n].
  * Asynchronous. */
 int cptr_vcycle(cptr_handle *h, int which, const double *b, double *x, void *stream);
 

@@ -854,8 +854,9 @@ void *orc_create(int n, int nv, const int *rp, const int *ci, const double *vals
                    o->sweeps, o->smooth_p, o->smoother);
     h->have_p = 1;
     if (st == 0 && (o->first_stage == ORC_FIRST_CPTR_BLOCK ||
-                    o->first_stage == ORC_FIRST_CPTR_LOWER)) {
-      csr s = csr_copy(n, srp, sci, svals);
+                    o->first_stage == ORC_FIRST_CPTR_LOWER || o->first_stage == ORC_FIRST_CPTR_BD)) {
+      /* the second hierarchy: S~_T (eq:Se), or A_TT for the block-diagonal stage */
+      csr s = o->first_stage == ORC_FIRST_CPTR_BD ? extract(h, o->iT, o->iT) : csr_copy(n, srp, sci, svals);
       st = amg_setup(&h->amg_s, s, o->theta, o->max_levels, o->coarse_size, o->seed,
                      o->sweeps, o->smooth_p_T < 0 ? o->smooth_p : o->smooth_p_T, o->smoother);
       h->have_s = 1;
@@ -904,6 +905,8 @@ void orc_destroy(void *hv) {
  *    b~_p = b_p - A_pT d_T;  d_p = A_pp^{-1} b~_p
  *  CPTR lower (right factor of eq:Aschur dropped): d_p = x_p.
  *  CPR (Section 3.1): d_p = A_pp^{-1} b_p, d_T = 0.
+ *  CPTR-BD(AMG) (Section 4.4, block-diagonal first stage): d_p = A_pp^{-1} b_p,
+ *    d_T = A_TT^{-1} b_T, the couplings A_pT, A_Tp left out.
  *  Each inverse is one AMG V-cycle. */
 int orc_first_stage(void *hv, const double *v, double *x1) {
   orc *h = (orc *)hv;
@@ -915,6 +918,14 @@ int orc_first_stage(void *hv, const double *v, double *x1) {
     h->bt[i] = v[(size_t)i * nv + iT];
   }
   vcycle(&h->amg_p, 0, h->bp, h->xp);
+  if (h->o.first_stage == ORC_FIRST_CPTR_BD) {
+    vcycle(&h->amg_s, 0, h->bt, h->dt);
+    for (int i = 0; i < n; i++) {
+      x1[(size_t)i * nv + ip] = h->xp[i];
+      x1[(size_t)i * nv + iT] = h->dt[i];
+    }
+    return 0;
+  }
   if (h->o.first_stage == ORC_FIRST_CPR) {
     for (int i = 0; i < n; i++) x1[(size_t)i * nv + ip] = h->xp[i];
     return 0;

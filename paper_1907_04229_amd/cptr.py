@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(_HERE, "libcptr.so")
 
 CPTR_OK = 0
 CPTR_NOT_CONVERGED = 1
-FIRST = {"none": 0, "cptr": 1, "cptr_lower": 2, "cpr": 3}
+FIRST = {"none": 0, "cptr": 1, "cptr_lower": 2, "cpr": 3, "cptr_bd": 4}
 SECOND = {"none": 0, "bilu0": 1, "bilu0_mc": 2, "identity": 3, "learned": 4}
 PRECISION = {"fp64": 0, "fp32": 1}
 

@@ -711,6 +711,11 @@ struct Precond : PrecondBase {
       amg_p.cycle(st, bpp, dpp);
       return;
     }
+    if (fs == CPTR_FIRST_BD) {  // block-diagonal: d_p = V(A_pp) b_p, d_T = V(A_TT) b_T
+      amg_p.cycle(st, bpp, dpp);
+      amg_s.cycle(st, btt, dTT);
+      return;
+    }
     amg_p.cycle(st, bpp, xpp);
     ATp.template spmv<2>(st, xpp, btt, t);
     amg_s.cycle(st, t, dTT);
@@ -919,21 +924,27 @@ static void build_precond(cptr_handle *h, const std::vector<int> &rp, const std:
     amg_build(sub(o.ip, o.ip), prm, hp, agg_p);
     P.amg_p.build(hp, o.amg_sweeps, o.scalar_dia != 0);
     if (o.first_stage != CPTR_FIRST_CPR) {
+      // the second hierarchy: S~_T, or A_TT for the block-diagonal stage
       AmgHost hs;
       AmgParams prm_s = prm;
       if (o.amg_smooth_p_T >= 0) prm_s.smooth_p = o.amg_smooth_p_T;
-      amg_build(*S, prm_s, hs, agg_s);
+      if (o.first_stage == CPTR_FIRST_BD)
+        amg_build(sub(o.iT, o.iT), prm_s, hs, agg_s);
+      else
+        amg_build(*S, prm_s, hs, agg_s);
       P.amg_s.build(hs, o.amg_sweeps, o.scalar_dia != 0);
       P.have_s = true;
-      P.ApT.build(sub(o.ip, o.iT), o.scalar_dia != 0);
-      P.ATp.build(sub(o.iT, o.ip), o.scalar_dia != 0);
+      if (o.first_stage != CPTR_FIRST_BD) {
+        P.ApT.build(sub(o.ip, o.iT), o.scalar_dia != 0);
+        P.ATp.build(sub(o.iT, o.ip), o.scalar_dia != 0);
+      }
     }
     int ncyc = o.first_stage == CPTR_FIRST_BLOCK ? 2 : 1;
     bytes += 8.0 * n * 2 + 2.0 * n * s;                         // restriction
     bytes += ncyc * P.amg_p.bytes_per_cycle;
     if (P.have_s) {
       bytes += P.amg_s.bytes_per_cycle;
-      bytes += P.ATp.bytes() + 3.0 * n * s;                     // b~_T
+      if (o.first_stage != CPTR_FIRST_BD) bytes += P.ATp.bytes() + 3.0 * n * s;  // b~_T
       if (o.first_stage == CPTR_FIRST_BLOCK) bytes += P.ApT.bytes() + 3.0 * n * s;
     }
   }
@@ -1039,7 +1050,7 @@ static void validate_and_fetch(const cptr_bsr *A, const cptr_csr *S, const cptr_
     throw Error{CPTR_ERR_INVALID_ARG, "invalid p/T slots"};
   if (o.amg_max_levels < 1 || o.amg_coarse_size < 1 || o.amg_sweeps < 1 || !(o.amg_theta >= 0.0))
     throw Error{CPTR_ERR_INVALID_ARG, "invalid AMG options"};
-  if (o.first_stage < 0 || o.first_stage > 3) throw Error{CPTR_ERR_INVALID_ARG, "invalid first stage"};
+  if (o.first_stage < 0 || o.first_stage > 4) throw Error{CPTR_ERR_INVALID_ARG, "invalid first stage"};
   if (o.second_stage < 0 || o.second_stage > 4)
     throw Error{CPTR_ERR_UNSUPPORTED, "unsupported second stage"};
   if (o.precision != CPTR_FP32 && o.precision != CPTR_FP64)
@@ -1619,6 +1630,7 @@ int cptr_update_values(cptr_handle *h, const double *A_vals, const double *S_val
   if (!h || !A_vals) return fail(Error{CPTR_ERR_INVALID_ARG, "null argument"});
   const int fs = h->op.o.first_stage;
   const bool need_s = fs == CPTR_FIRST_BLOCK || fs == CPTR_FIRST_BLOCK_LOWER;
+  const bool two_hier = need_s || fs == CPTR_FIRST_BD;  // a second AMG hierarchy to keep
   if (need_s && !S_vals) return fail(Error{CPTR_ERR_INVALID_ARG, "S~_T values required by this first stage"});
   try {
     auto t0 = std::chrono::steady_clock::now();
@@ -1650,15 +1662,15 @@ int cptr_update_values(cptr_handle *h, const double *A_vals, const double *S_val
         return a;
       };
       agg_p = strip(Pf ? Pf->amg_p.agg : Pd->amg_p.agg);
-      if (need_s) agg_s = strip(Pf ? Pf->amg_s.agg : Pd->amg_s.agg);
+      if (two_hier) agg_s = strip(Pf ? Pf->amg_s.agg : Pd->amg_s.agg);
     }
     h->vals = A_vals;
     build_sliced(h, rp, ci, vals);
     LearnedDev *lrn = h->lrn.get();
     if (h->op.o.precision == CPTR_FP32)
-      build_precond<float>(h, rp, ci, vals, need_s ? &sh : nullptr, &agg_p, need_s ? &agg_s : nullptr);
+      build_precond<float>(h, rp, ci, vals, need_s ? &sh : nullptr, &agg_p, two_hier ? &agg_s : nullptr);
     else
-      build_precond<double>(h, rp, ci, vals, need_s ? &sh : nullptr, &agg_p, need_s ? &agg_s : nullptr);
+      build_precond<double>(h, rp, ci, vals, need_s ? &sh : nullptr, &agg_p, two_hier ? &agg_s : nullptr);
     if (lrn) {
       lrn->build(n, nv, rp, ci, vals);  // edge features of the new values
       if (h->model) h->pc->set_learned(lrn, &h->model->dev);

@@ -107,13 +107,14 @@ def test_matvec_sliced_fp64(name):
 
 # ---------------------------------------------------------------- setup integers
 @pytest.mark.parametrize("name", ["ragged", "three", "small"])
-def test_aggregates_and_schedule_bit_exact(name):
-    banner(f"setup integers {name}")
+@pytest.mark.parametrize("first", ["cptr", "cptr_bd"])
+def test_aggregates_and_schedule_bit_exact(name, first):
+    banner(f"setup integers {name} {first}")
     pr = prob(name)
     for mc in (False, True):
-        s = solver(pr, precision="fp64", second_stage="bilu0_mc" if mc else "bilu0",
+        s = solver(pr, precision="fp64", first_stage=first, second_stage="bilu0_mc" if mc else "bilu0",
                    amg_coarse_size=16)
-        o = O.Oracle.from_problem(pr, first="cptr", second="bilu0_mc" if mc else "bilu0",
+        o = O.Oracle.from_problem(pr, first=first, second="bilu0_mc" if mc else "bilu0",
                                   coarse_size=16)
         for which in (0, 1):
             ref = o.amg_levels(which)
@@ -132,7 +133,7 @@ def test_aggregates_and_schedule_bit_exact(name):
 
 # ---------------------------------------------------------------- one application
 @pytest.mark.parametrize("name", ["ragged", "three", "small", "chain", "single"])
-@pytest.mark.parametrize("first", ["cptr", "cptr_lower", "cpr"])
+@pytest.mark.parametrize("first", ["cptr", "cptr_lower", "cpr", "cptr_bd"])
 def test_vcycle_and_first_stage_fp64(name, first):
     banner(f"first stage fp64 {name} {first}")
     pr = prob(name)
@@ -216,7 +217,8 @@ def test_diagonal_storage(name):
 @pytest.mark.parametrize("name", ["ragged", "three", "small", "chain", "single"])
 @pytest.mark.parametrize("first,second", [("cptr", "bilu0"), ("cptr", "bilu0_mc"),
                                           ("cpr", "bilu0"), ("none", "bilu0"),
-                                          ("cptr", "identity"), ("cptr_lower", "bilu0_mc")])
+                                          ("cptr", "identity"), ("cptr_lower", "bilu0_mc"),
+                                          ("cptr_bd", "bilu0_mc")])
 def test_apply_fp64(name, first, second):
     banner(f"apply fp64 {name} {first}+{second}")
     pr = prob(name)
@@ -259,7 +261,7 @@ def test_apply_fp32(name, second):
 # ---------------------------------------------------------------- FGMRES
 @pytest.mark.parametrize("name", ["ragged", "three", "small", "chain"])
 @pytest.mark.parametrize("first,second", [("cptr", "bilu0"), ("cptr", "bilu0_mc"),
-                                          ("cpr", "bilu0_mc")])
+                                          ("cpr", "bilu0_mc"), ("cptr_bd", "bilu0")])
 @pytest.mark.parametrize("graph", [1, 0])
 def test_fgmres_fp64_matches_oracle(name, first, second, graph):
     banner(f"fgmres fp64 {name} {first}+{second} graph={graph}")
@@ -345,20 +347,21 @@ def test_invalid_inputs_are_rejected():
 
 
 @pytest.mark.parametrize("name", ["three", "small"])
-def test_update_values_equals_fresh_setup(name):
+@pytest.mark.parametrize("first", ["cptr", "cptr_bd"])
+def test_update_values_equals_fresh_setup(name, first):
     """cptr_update_values with 2A (and 2 S~_T): the strength test, the
     prolongator weights and the Galerkin products scale exactly, so the kept
     aggregates are those a fresh setup of 2A builds, and the results must be
     bit-identical to it (FP64: first stage, full application, FGMRES)."""
-    banner(f"update_values {name}")
+    banner(f"update_values {name} {first}")
     pr = prob(name)
     import copy
     pr2 = copy.copy(pr)
     pr2.vals = pr.vals * 2.0
     pr2.st_vals = pr.st_vals * 2.0
-    s = solver(pr, precision="fp64", second_stage="bilu0", amg_coarse_size=16)
+    s = solver(pr, precision="fp64", first_stage=first, second_stage="bilu0", amg_coarse_size=16)
     s.update_values(pr2)
-    f = solver(pr2, precision="fp64", second_stage="bilu0", amg_coarse_size=16)
+    f = solver(pr2, precision="fp64", first_stage=first, second_stage="bilu0", amg_coarse_size=16)
     v = dev(np.random.default_rng(13).standard_normal(pr.n * pr.nv))
     a, b = torch.empty_like(v), torch.empty_like(v)
     cptr.cptr_first_stage(s.h, v, a)

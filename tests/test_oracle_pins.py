@@ -340,11 +340,34 @@ def test_block_preconditioner_with_exact_solves_is_A00_inverse(tiny, oracle_lib)
     del full
 
 
+def test_block_diagonal_stage_with_exact_solves(tiny, oracle_lib):
+    # CPTR-BD (Section 4.4) with one-level hierarchies (exact LU solves): the
+    # first stage is diag(A_pp^{-1}, A_TT^{-1}) on (v_p, v_T), and its second
+    # hierarchy is built on the temperature block A_TT itself.
+    A, App, ApT, ATp, ATT, S = _dense_Ainv00(tiny, True)
+    n, nv = tiny.n, tiny.nv
+    o = O.Oracle.from_problem(tiny, first="cptr_bd", second="none", coarse_size=10_000)
+    lv = o.amg_levels(1)
+    assert len(lv) == 1
+    rp, ci, v = lv[0]["A"]
+    dense = np.zeros((n, n))
+    for i in range(n):
+        dense[i, ci[rp[i]:rp[i + 1]]] = v[rp[i]:rp[i + 1]]
+    assert np.array_equal(dense, ATT)
+    vin = np.random.default_rng(2).standard_normal(n * nv)
+    x1 = o.first_stage(vin)
+    for got, M, rhs in ((x1[0::nv], App, vin[0::nv]), (x1[nv - 1::nv], ATT, vin[nv - 1::nv])):
+        want = np.linalg.solve(M, rhs)
+        assert np.allclose(got, want, rtol=1e-10, atol=1e-10 * np.abs(want).max())
+    for u in range(1, nv - 1):
+        assert (x1[u::nv] == 0).all()
+
+
 def _vcycle_matrix(o, which, n):
     return _columns(lambda e: o.vcycle(which, e), n)
 
 
-@pytest.mark.parametrize("first", ["cptr", "cptr_lower", "cpr"])
+@pytest.mark.parametrize("first", ["cptr", "cptr_lower", "cpr", "cptr_bd"])
 def test_first_stage_product_form(mid, first, oracle_lib):
     # eq:Aschur as a product of its three factors, each inverse replaced by the
     # (linear) V-cycle operator; CPR: R_p^T V(A_pp) R_p (Section 3.1).
@@ -357,6 +380,9 @@ def test_first_stage_product_form(mid, first, oracle_lib):
     I, Z = np.eye(n), np.zeros((n, n))
     if first == "cpr":
         M1 = np.block([[Vp, Z], [Z, Z]])
+    elif first == "cptr_bd":
+        # block-diagonal first stage (Section 4.4): V-cycles on A_pp and A_TT
+        M1 = np.block([[Vp, Z], [Z, _vcycle_matrix(o, 1, n)]])
     else:
         Vs = _vcycle_matrix(o, 1, n)
         left = np.block([[I, -Vp @ ApT], [Z, I]]) if first == "cptr" else np.eye(2 * n)
