@@ -351,14 +351,19 @@ def main():
         sn.close()
         mn.close()
         # context: the same stages behind the CPR first stage (one A_pp V-cycle)
-        # and behind the block-diagonal CPTR-BD(AMG) first stage (V-cycles on
-        # A_pp and A_TT, Section 4.4)
+        # (also with the True-IMPES decoupling operator, Section 3.1) and behind
+        # the block-diagonal CPTR-BD(AMG) first stage (V-cycles on A_pp and
+        # A_TT, Section 4.4)
         for tag, first, opt, mdl_needed in (
                 ("fp64_cpr_bilu0", "cpr", dict(precision="fp64", second_stage="bilu0"), False),
                 ("fp32_cpr_bilu0_mc", "cpr", dict(precision="fp32", second_stage="bilu0_mc"), False),
                 ("fp32_cpr_learned_untrained", "cpr", dict(precision="fp32", second_stage="learned"), True),
                 ("fp64_cptr_bd_bilu0", "cptr_bd", dict(precision="fp64", second_stage="bilu0"), False),
-                ("fp32_cptr_bd_bilu0_mc", "cptr_bd", dict(precision="fp32", second_stage="bilu0_mc"), False)):
+                ("fp32_cptr_bd_bilu0_mc", "cptr_bd", dict(precision="fp32", second_stage="bilu0_mc"), False),
+                ("fp64_cpr_ti_bilu0", "cpr", dict(precision="fp64", second_stage="bilu0", decoupling="ti"),
+                 False),
+                ("fp32_cpr_ti_bilu0_mc", "cpr", dict(precision="fp32", second_stage="bilu0_mc", decoupling="ti"),
+                 False)):
             sc, su = setup(first_stage=first, **opt)
             mc_ = None
             if mdl_needed:

@@ -62,6 +62,13 @@ extern "C" {
 #define CPTR_FIRST_BD 4          /* CPTR-BD(AMG) (Section 4.4): block-diagonal first stage,
                                     d_p = V(A_pp) b_p, d_T = V(A_TT) b_T (couplings left out) */
 
+/* Decoupling operators G = [I, -D; 0, I] for the CPR first stage (Section 3.1;
+ * p = pressure, s = every other unknown in slot order, D one 1 x (nv-1) block
+ * per cell): the first stage solves S_p = A_pp - D A_sp with b_p = v_p - D v_s. */
+#define CPTR_DECOUPLE_NONE 0
+#define CPTR_DECOUPLE_QI 1       /* Quasi-IMPES: D = diag(A_ps) diag(A_ss)^-1 */
+#define CPTR_DECOUPLE_TI 2       /* True-IMPES:  D = colsum(A_ps) colsum(A_ss)^-1 */
+
 /* second stage */
 #define CPTR_SECOND_NONE 0       /* z = x1 */
 #define CPTR_SECOND_BILU0 1      /* block ILU(0), natural order, level-scheduled solves */
@@ -122,6 +129,9 @@ typedef struct {
                             16 cells (rows of the -z/+z neighbours kept in registers, -x/+x by
                             lane shuffles); 0: tiles in cell order with every neighbour row
                             gathered (1).  Both give the same result bit for bit. */
+  int decoupling;        /* CPTR_DECOUPLE_* for CPTR_FIRST_CPR (NONE); other first stages
+                            reject QI / TI with CPTR_ERR_UNSUPPORTED, a singular block of D
+                            gives CPTR_ERR_SINGULAR_BLOCK */
 } cptr_options;
 
 typedef struct {

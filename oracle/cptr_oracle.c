@@ -811,6 +811,7 @@ typedef struct {
   double *dense_lu;        /* exact second stage */
   int *dense_piv;
   double *bp, *bt, *xp, *dt, *dp, *tmp, *x1, *b1, *wb, *wx;
+  double *dcp;             /* decoupling weights D, [n][nv-1] (CPR with QI / TI) */
 } orc;
 
 static csr extract(const orc *h, int r, int c) {
@@ -821,6 +822,43 @@ static csr extract(const orc *h, int r, int c) {
   memcpy(a.ci, h->ci, sizeof(int) * (size_t)h->rp[n]);
   for (int k = 0; k < h->rp[n]; k++) a.v[k] = h->v[(size_t)k * nv * nv + r * nv + c];
   return a;
+}
+
+/* Decoupling operator G = [I, -D; 0, I] of Section 3.1 for the split of the
+ * unknowns into pressure p and the secondary unknowns s (all the others, in
+ * slot order).  D is block diagonal with one 1 x (nv-1) block per cell:
+ *   Quasi-IMPES  D_i = A_ps[i,i] A_ss[i,i]^{-1}            (diagonal blocks)
+ *   True-IMPES   D_i = colsum(A_ps)_i colsum(A_ss)_i^{-1}  (sums over the rows
+ *                of block column i).
+ * D_i solves D_i C = a for the row a and the (nv-1) x (nv-1) matrix C, i.e.
+ * C^T D_i^T = a^T.  Returns -1 if a C is singular. */
+static int decoupling_weights(const orc *h, int kind, double *D) {
+  int n = h->n, nv = h->nv, ip = h->o.ip, ns = nv - 1;
+  int sl[4], q = 0;
+  for (int k = 0; k < nv; k++)
+    if (k != ip) sl[q++] = k;
+  double *blk = (double *)calloc((size_t)n * nv * nv, sizeof(double));
+  for (int j = 0; j < n; j++)
+    for (int k = h->rp[j]; k < h->rp[j + 1]; k++) {
+      int i = h->ci[k];
+      if (kind == 1 && i != j) continue;  /* QI: the diagonal block only */
+      for (int e = 0; e < nv * nv; e++) blk[(size_t)i * nv * nv + e] += h->v[(size_t)k * nv * nv + e];
+    }
+  int st = 0;
+  for (int i = 0; i < n && st == 0; i++) {
+    const double *B = blk + (size_t)i * nv * nv;
+    double CT[9], d[3];
+    int piv[3];
+    for (int a = 0; a < ns; a++) {
+      d[a] = B[ip * nv + sl[a]];
+      for (int b = 0; b < ns; b++) CT[a * ns + b] = B[sl[b] * nv + sl[a]];
+    }
+    if (lu_factor(CT, piv, ns) != 0) { st = -1; break; }
+    lu_solve(CT, piv, ns, d);
+    for (int a = 0; a < ns; a++) D[(size_t)i * ns + a] = d[a];
+  }
+  free(blk);
+  return st;
 }
 
 void *orc_create(int n, int nv, const int *rp, const int *ci, const double *vals,
@@ -850,8 +888,24 @@ void *orc_create(int n, int nv, const int *rp, const int *ci, const double *vals
     h->ApT = extract(h, o->ip, o->iT);
     h->ATp = extract(h, o->iT, o->ip);
     csr fine = extract(h, o->ip, o->ip);
-    st = amg_setup(&h->amg_p, fine, o->theta, o->max_levels, o->coarse_size, o->seed,
-                   o->sweeps, o->smooth_p, o->smoother);
+    if (o->decoupling != 0 && o->first_stage != ORC_FIRST_CPR) st = -12;
+    if (st == 0 && o->decoupling != 0) {
+      /* S_p = A_pp - D A_sp on the pattern of A_pp */
+      int ns = nv - 1, sl[4], q = 0;
+      for (int k = 0; k < nv; k++)
+        if (k != o->ip) sl[q++] = k;
+      h->dcp = (double *)calloc((size_t)n * ns + 1, sizeof(double));
+      if (decoupling_weights(h, o->decoupling, h->dcp) != 0) st = -13;
+      for (int i = 0; st == 0 && i < n; i++)
+        for (int k = rp[i]; k < rp[i + 1]; k++)
+          for (int a = 0; a < ns; a++)
+            fine.v[k] -= h->dcp[(size_t)i * ns + a] * vals[(size_t)k * nv * nv + sl[a] * nv + o->ip];
+    }
+    if (st == 0)
+      st = amg_setup(&h->amg_p, fine, o->theta, o->max_levels, o->coarse_size, o->seed,
+                     o->sweeps, o->smooth_p, o->smoother);
+    else
+      csr_free(&fine);
     h->have_p = 1;
     if (st == 0 && (o->first_stage == ORC_FIRST_CPTR_BLOCK ||
                     o->first_stage == ORC_FIRST_CPTR_LOWER || o->first_stage == ORC_FIRST_CPTR_BD)) {
@@ -895,7 +949,7 @@ void orc_destroy(void *hv) {
   if (h->have_ilu) bilu_free(&h->ilu);
   free(h->dense_lu); free(h->dense_piv);
   free(h->bp); free(h->bt); free(h->xp); free(h->dt); free(h->dp); free(h->tmp);
-  free(h->x1); free(h->b1); free(h->wb); free(h->wx);
+  free(h->x1); free(h->b1); free(h->wb); free(h->wx); free(h->dcp);
   free(h);
 }
 
@@ -904,7 +958,8 @@ void orc_destroy(void *hv) {
  *    x_p = A_pp^{-1} b_p;  b~_T = b_T - A_Tp x_p;  d_T = S~_T^{-1} b~_T;
  *    b~_p = b_p - A_pT d_T;  d_p = A_pp^{-1} b~_p
  *  CPTR lower (right factor of eq:Aschur dropped): d_p = x_p.
- *  CPR (Section 3.1): d_p = A_pp^{-1} b_p, d_T = 0.
+ *  CPR (Section 3.1): d_p = A_pp^{-1} b_p, d_T = 0; with a decoupling
+ *    operator G: d_p = S_p^{-1} (G v)_p, S_p = A_pp - D A_sp, (G v)_p = v_p - D v_s.
  *  CPTR-BD(AMG) (Section 4.4, block-diagonal first stage): d_p = A_pp^{-1} b_p,
  *    d_T = A_TT^{-1} b_T, the couplings A_pT, A_Tp left out.
  *  Each inverse is one AMG V-cycle. */
@@ -916,6 +971,14 @@ int orc_first_stage(void *hv, const double *v, double *x1) {
   for (int i = 0; i < n; i++) {
     h->bp[i] = v[(size_t)i * nv + ip];
     h->bt[i] = v[(size_t)i * nv + iT];
+  }
+  if (h->o.decoupling != 0) {
+    int q = 0;
+    for (int k = 0; k < nv; k++) {
+      if (k == ip) continue;
+      for (int i = 0; i < n; i++) h->bp[i] -= h->dcp[(size_t)i * (nv - 1) + q] * v[(size_t)i * nv + k];
+      q++;
+    }
   }
   vcycle(&h->amg_p, 0, h->bp, h->xp);
   if (h->o.first_stage == ORC_FIRST_CPTR_BD) {

@@ -41,6 +41,7 @@ typedef struct {
   const int *ilu_order;/* BILU0 factor order (position -> cell) or NULL */
   const int *ilu_part; /* BILU0 partition (cell -> part, couplings across parts dropped) or NULL */
   int smooth_p_T;      /* prolongator of the S~_T hierarchy: 1 smoothed, 0 plain, -1 as smooth_p */
+  int decoupling;      /* CPR first stage only: 0 none, 1 Quasi-IMPES, 2 True-IMPES (Section 3.1) */
 } orc_opts;
 
 typedef struct {

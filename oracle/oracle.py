@@ -15,6 +15,7 @@ _SO = os.path.join(_HERE, "liborc.so")
 _SRC = os.path.join(_HERE, "cptr_oracle.c")
 
 FIRST = {"none": 0, "cptr": 1, "cptr_lower": 2, "cpr": 3, "cptr_bd": 4}
+DECOUPLING = {"none": 0, "qi": 1, "ti": 2}
 SECOND = {"none": 0, "bilu0": 1, "bilu0_mc": 2, "identity": 3, "exact": 4}
 
 
@@ -32,7 +33,7 @@ class _Opts(C.Structure):
                 ("iT", C.c_int), ("theta", C.c_double), ("max_levels", C.c_int),
                 ("coarse_size", C.c_int), ("seed", C.c_uint), ("sweeps", C.c_int),
                 ("smooth_p", C.c_int), ("smoother", C.c_int), ("ilu_order", C.c_void_p),
-                ("ilu_part", C.c_void_p), ("smooth_p_T", C.c_int)]
+                ("ilu_part", C.c_void_p), ("smooth_p_T", C.c_int), ("decoupling", C.c_int)]
 
 
 class _Info(C.Structure):
@@ -128,7 +129,8 @@ class Oracle:
     def __init__(self, n, nv, row_ptr, col, vals, st_row_ptr=None, st_col=None,
                  st_vals=None, first="cptr", second="bilu0", ip=0, iT=None,
                  theta=0.08, max_levels=10, coarse_size=512, seed=0, sweeps=2,
-                 smooth_p=True, smoother="jacobi", ilu_order=None, ilu_part=None, smooth_p_T=False):
+                 smooth_p=True, smoother="jacobi", ilu_order=None, ilu_part=None, smooth_p_T=False,
+                 decoupling="none"):
         self.n, self.nv = n, nv
         self._keep = [_ci(row_ptr), _ci(col), _cd(vals)]
         if st_row_ptr is None:
@@ -146,7 +148,8 @@ class Oracle:
         o = _Opts(FIRST[first], SECOND[second], ip, nv - 1 if iT is None else iT,
                   theta, max_levels, coarse_size, seed, sweeps, int(bool(smooth_p)),
                   {"jacobi": 0, "gs": 1}[smoother], extra[0], extra[1],
-                  -1 if smooth_p_T is None else int(bool(smooth_p_T)))
+                  -1 if smooth_p_T is None else int(bool(smooth_p_T)),
+                  DECOUPLING[decoupling])
         status = C.c_int(0)
         rp, ci, v, srp, sci, sv = self._keep[:6]
         self.h = lib().orc_create(n, nv, _i(rp), _i(ci), _d(v), _i(srp), _i(sci), _d(sv),

@@ -18,6 +18,7 @@ CPTR_NOT_CONVERGED = 1
 FIRST = {"none": 0, "cptr": 1, "cptr_lower": 2, "cpr": 3, "cptr_bd": 4}
 SECOND = {"none": 0, "bilu0": 1, "bilu0_mc": 2, "identity": 3, "learned": 4}
 PRECISION = {"fp64": 0, "fp32": 1}
+DECOUPLING = {"none": 0, "qi": 1, "ti": 2}
 
 
 class Options(C.Structure):
@@ -27,7 +28,7 @@ class Options(C.Structure):
                 ("amg_seed", C.c_uint), ("amg_sweeps", C.c_int), ("amg_smooth_p", C.c_int),
                 ("amg_smooth_p_T", C.c_int),
                 ("use_graph", C.c_int), ("resid_fp64", C.c_int),
-                ("scalar_dia", C.c_int), ("lrn_columns", C.c_int)]
+                ("scalar_dia", C.c_int), ("lrn_columns", C.c_int), ("decoupling", C.c_int)]
 
 
 class Bsr(C.Structure):
@@ -143,6 +144,8 @@ def cptr_default_options(**kw):
             v = SECOND[v]
         if k == "precision" and isinstance(v, str):
             v = PRECISION[v]
+        if k == "decoupling" and isinstance(v, str):
+            v = DECOUPLING[v]
         setattr(o, k, v)
     return o
 

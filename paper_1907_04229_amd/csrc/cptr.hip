@@ -691,6 +691,7 @@ struct Precond : PrecondBase {
   AmgDev<T> amg_p, amg_s;
   IluDev<T> ilu;
   DevMem bp, bt, xp, dT, dp, tmp, b1;
+  DevMem dcp;  // decoupling weights D [n][nv-1] of the CPR first stage (empty without)
   DevMem vtmp, ztmp;  // FP64 staging of cptr_vcycle
   bool have_s = false, have_ilu = false;
   double bytes = 0.0;
@@ -705,7 +706,7 @@ struct Precond : PrecondBase {
     T *bpp = devp<T>(bp), *btt = devp<T>(bt), *xpp = devp<T>(xp), *dTT = devp<T>(dT),
       *dpp = devp<T>(dp), *t = devp<T>(tmp);
     hipLaunchKernelGGL((k_restrict_pT<T>), dim3(nblk(n)), dim3(kBlock), 0, st, n, op.nv, ip, iT, slots,
-                       bpp, fs == CPTR_FIRST_CPR ? (T *)nullptr : btt);
+                       dcp.p ? (const T *)devp<T>(dcp) : (const T *)nullptr, bpp, fs == CPTR_FIRST_CPR ? (T *)nullptr : btt);
     LAUNCH_CHECK();
     if (fs == CPTR_FIRST_CPR) {
       amg_p.cycle(st, bpp, dpp);
@@ -921,7 +922,54 @@ static void build_precond(cptr_handle *h, const std::vector<int> &rp, const std:
   double bytes = 0.0;
   if (o.first_stage != CPTR_FIRST_NONE) {
     AmgHost hp;
-    amg_build(sub(o.ip, o.ip), prm, hp, agg_p);
+    HostCSR pp = sub(o.ip, o.ip);
+    if (o.decoupling != 0) {
+      // Section 3.1: the first stage solves S_p = A_pp - D A_sp, with D from
+      // Quasi-IMPES (diagonal blocks) or True-IMPES (column sums of the block
+      // columns), D_i C_i = a_i for C_i the s-s part and a_i the p-s part
+      const int ns = nv - 1;
+      std::vector<int> sl;
+      for (int k = 0; k < nv; k++)
+        if (k != o.ip) sl.push_back(k);
+      std::vector<double> blk((size_t)n * nv * nv, 0.0);
+      for (int j = 0; j < n; j++)
+        for (int k = rp[j]; k < rp[j + 1]; k++) {
+          const int i = ci[k];
+          if (o.decoupling == CPTR_DECOUPLE_QI && i != j) continue;
+          for (int e = 0; e < nv * nv; e++) blk[(size_t)i * nv * nv + e] += vals[(size_t)k * nv * nv + e];
+        }
+      std::vector<double> D((size_t)n * ns);
+      for (int i = 0; i < n; i++) {
+        const double *B = &blk[(size_t)i * nv * nv];
+        double m[3][4];  // [C_i^T | a_i^T], Gauss-Jordan with partial pivoting
+        for (int a = 0; a < ns; a++) {
+          for (int b = 0; b < ns; b++) m[a][b] = B[sl[b] * nv + sl[a]];
+          m[a][ns] = B[o.ip * nv + sl[a]];
+        }
+        for (int c = 0; c < ns; c++) {
+          int pr = c;
+          for (int r = c + 1; r < ns; r++)
+            if (std::fabs(m[r][c]) > std::fabs(m[pr][c])) pr = r;
+          if (m[pr][c] == 0.0)
+            throw Error{CPTR_ERR_SINGULAR_BLOCK, "singular decoupling block at cell " + std::to_string(i)};
+          for (int b = 0; b <= ns; b++) std::swap(m[c][b], m[pr][b]);
+          for (int r = 0; r < ns; r++) {
+            if (r == c) continue;
+            const double f = m[r][c] / m[c][c];
+            for (int b = c; b <= ns; b++) m[r][b] -= f * m[c][b];
+          }
+        }
+        for (int a = 0; a < ns; a++) D[(size_t)i * ns + a] = m[a][ns] / m[a][a];
+      }
+      for (int i = 0; i < n; i++)
+        for (int k = rp[i]; k < rp[i + 1]; k++)
+          for (int a = 0; a < ns; a++)
+            pp.v[k] -= D[(size_t)i * ns + a] * vals[((size_t)k * nv + sl[a]) * nv + o.ip];
+      std::vector<T> Dt(D.begin(), D.end());
+      upload(P.dcp, Dt);
+      bytes += (double)n * ns * (s + 8);  // D and v_s in the restriction
+    }
+    amg_build(pp, prm, hp, agg_p);
     P.amg_p.build(hp, o.amg_sweeps, o.scalar_dia != 0);
     if (o.first_stage != CPTR_FIRST_CPR) {
       // the second hierarchy: S~_T, or A_TT for the block-diagonal stage
@@ -1051,6 +1099,9 @@ static void validate_and_fetch(const cptr_bsr *A, const cptr_csr *S, const cptr_
   if (o.amg_max_levels < 1 || o.amg_coarse_size < 1 || o.amg_sweeps < 1 || !(o.amg_theta >= 0.0))
     throw Error{CPTR_ERR_INVALID_ARG, "invalid AMG options"};
   if (o.first_stage < 0 || o.first_stage > 4) throw Error{CPTR_ERR_INVALID_ARG, "invalid first stage"};
+  if (o.decoupling < 0 || o.decoupling > 2) throw Error{CPTR_ERR_INVALID_ARG, "invalid decoupling"};
+  if (o.decoupling != 0 && o.first_stage != CPTR_FIRST_CPR)
+    throw Error{CPTR_ERR_UNSUPPORTED, "decoupling operators apply to the CPR first stage only"};
   if (o.second_stage < 0 || o.second_stage > 4)
     throw Error{CPTR_ERR_UNSUPPORTED, "unsupported second stage"};
   if (o.precision != CPTR_FP32 && o.precision != CPTR_FP64)
@@ -1476,6 +1527,7 @@ void cptr_default_options(cptr_options *o) {
   o->resid_fp64 = 0;
   o->scalar_dia = 1;
   o->lrn_columns = 1;
+  o->decoupling = CPTR_DECOUPLE_NONE;
 }
 
 int cptr_setup(cptr_handle **out, const cptr_bsr *A, const cptr_csr *S_T, const cptr_options *opt,

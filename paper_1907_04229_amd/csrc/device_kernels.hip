@@ -238,14 +238,26 @@ __global__ void __launch_bounds__(kBlock) k_coarse_gemv(const double *__restrict
 // ---------------------------------------------------------------------------
 // first stage: restriction, two-stage residual, finishing
 // ---------------------------------------------------------------------------
+// b_p = v_p (or, with decoupling weights D [n][nv-1], (G v)_p = v_p - D_i v_s
+// over the secondary slots in order, Section 3.1), b_T = v_T
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_restrict_pT(int n, int nv, int ip, int iT,
                                                         const ApplySlots *__restrict__ slots,
-                                                        T *__restrict__ bp, T *__restrict__ bt) {
+                                                        const T *__restrict__ D, T *__restrict__ bp,
+                                                        T *__restrict__ bt) {
   const int i = blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
   const gmem<const double> *__restrict__ v = as_global(slots->v);
-  bp[i] = T(v[(size_t)i * nv + ip]);
+  T p = T(v[(size_t)i * nv + ip]);
+  if (D) {
+    int q = 0;
+    for (int k = 0; k < nv; k++) {
+      if (k == ip) continue;
+      p -= D[(size_t)i * (nv - 1) + q] * T(v[(size_t)i * nv + k]);
+      q++;
+    }
+  }
+  bp[i] = p;
   if (bt) bt[i] = T(v[(size_t)i * nv + iT]);
 }
 

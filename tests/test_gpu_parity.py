@@ -258,6 +258,43 @@ def test_apply_fp32(name, second):
     s.close()
 
 
+@pytest.mark.parametrize("name", ["ragged", "three", "small"])
+@pytest.mark.parametrize("kind", ["qi", "ti"])
+def test_decoupled_cpr_fp64(name, kind):
+    """CPR with a Quasi- or True-IMPES decoupling operator (Section 3.1):
+    pressure-hierarchy aggregates bit-exact, V-cycle on S_p, first stage and
+    application (FP64) and FGMRES against the oracle."""
+    banner(f"decoupled cpr {name} {kind}")
+    pr = prob(name)
+    s = solver(pr, precision="fp64", first_stage="cpr", second_stage="bilu0", decoupling=kind,
+               amg_coarse_size=16)
+    o = O.Oracle.from_problem(pr, first="cpr", second="bilu0", decoupling=kind, coarse_size=16)
+    ref = o.amg_levels(0)
+    for lev in range(len(ref) - 1):
+        assert np.array_equal(cptr.cptr_get_aggregates(s.h, 0, lev, ref[lev]["n"]), ref[lev]["agg"])
+    rng = np.random.default_rng(14)
+    b = rng.standard_normal(pr.n)
+    x = torch.empty(pr.n, dtype=torch.float64, device=DEV)
+    cptr.cptr_vcycle(s.h, 0, dev(b), x)
+    v = rng.standard_normal(pr.n * pr.nv)
+    x1 = torch.empty_like(dev(v))
+    cptr.cptr_first_stage(s.h, dev(v), x1)
+    z = s.apply(dev(v))
+    torch.cuda.synchronize()
+    assert relerr(x.cpu().numpy(), o.vcycle(0, b)) <= 1e-10
+    assert relerr(x1.cpu().numpy(), o.first_stage(v)) <= 1e-10
+    assert relerr(z.cpu().numpy(), o.apply(v)) <= 1e-9
+    s.close()
+    s = solver(pr, precision="fp64", first_stage="cpr", second_stage="bilu0", decoupling=kind)
+    o = O.Oracle.from_problem(pr, first="cpr", second="bilu0", decoupling=kind)
+    xg, info = s.solve(dev(pr.b), restart=30, rtol=1e-6)
+    xo, io = o.fgmres(pr.b, m=30, rtol=1e-6)
+    err = np.linalg.norm(xg.cpu().numpy() - xo) / np.linalg.norm(xo)
+    print(f"iters gpu {info['iters']} oracle {io['iters']} err {err:.2e}")
+    assert info["converged"] and abs(info["iters"] - io["iters"]) <= 1 and err <= 1e-8
+    s.close()
+
+
 # ---------------------------------------------------------------- FGMRES
 @pytest.mark.parametrize("name", ["ragged", "three", "small", "chain"])
 @pytest.mark.parametrize("first,second", [("cptr", "bilu0"), ("cptr", "bilu0_mc"),
@@ -344,6 +381,10 @@ def test_invalid_inputs_are_rejected():
     with pytest.raises(cptr.CptrError) as e:
         cptr.Solver(replace(pr, vals=sing.reshape(-1)), device=DEV, first_stage="cpr")
     assert e.value.code in (-4, -7)
+    # decoupling operators belong to the CPR first stage
+    with pytest.raises(cptr.CptrError) as e:
+        cptr.Solver(pr, device=DEV, first_stage="cptr", decoupling="ti")
+    assert e.value.code == -2
 
 
 @pytest.mark.parametrize("name", ["three", "small"])

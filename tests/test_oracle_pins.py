@@ -363,6 +363,77 @@ def test_block_diagonal_stage_with_exact_solves(tiny, oracle_lib):
         assert (x1[u::nv] == 0).all()
 
 
+def _local_secondary(pr, zero):
+    """Values of pr with the secondary (non-pressure, pressure in slot 0)
+    columns (zero = "cols") or rows (zero = "rows") of every off-diagonal
+    block set to zero."""
+    nv = pr.nv
+    vals = pr.vals.reshape(-1, nv, nv).copy()
+    rows = np.repeat(np.arange(pr.n), np.diff(pr.row_ptr))
+    off = pr.col_idx != rows
+    if zero == "cols":
+        vals[off, :, 1:] = 0.0
+    else:
+        vals[off, 1:, :] = 0.0
+    return np.ascontiguousarray(vals.reshape(-1))
+
+
+def _schur_p(A, nv):
+    N = A.shape[0]
+    p = np.arange(0, N, nv)
+    q = np.array([k for k in range(N) if k % nv != 0])
+    return A[np.ix_(p, p)] - A[np.ix_(p, q)] @ np.linalg.solve(A[np.ix_(q, q)], A[np.ix_(q, p)])
+
+
+def _pressure_operator(o):
+    rp, ci, v = o.amg_levels(0)[0]["A"]
+    return dense_csr(rp, ci, v)
+
+
+@pytest.mark.parametrize("kind", ["qi", "ti"])
+def test_decoupling_is_exact_when_secondary_columns_are_local(tiny, kind, oracle_lib):
+    # Section 3.1: with the secondary columns of the off-diagonal blocks zero,
+    # A_ps and A_ss are block diagonal, so D = A_ps A_ss^{-1} for Quasi- and
+    # True-IMPES alike and S_p = A_pp - D A_sp is the exact Schur complement of
+    # the secondary unknowns: CPR with G and an exact pressure solve returns
+    # the pressure part of A^{-1} v.
+    n, nv = tiny.n, tiny.nv
+    vals = _local_secondary(tiny, "cols")
+    o = O.Oracle(n, nv, tiny.row_ptr, tiny.col_idx, vals, first="cpr", second="none",
+                 coarse_size=10_000, decoupling=kind)
+    A = dense_bsr(tiny.row_ptr, tiny.col_idx, vals, nv)
+    S = _schur_p(A, nv)
+    assert np.allclose(_pressure_operator(o), S, rtol=1e-12, atol=1e-12 * np.abs(S).max())
+    v = np.random.default_rng(4).standard_normal(n * nv)
+    got = o.first_stage(v)[0::nv]
+    want = np.linalg.solve(A, v)[0::nv]
+    assert np.allclose(got, want, rtol=1e-9, atol=1e-9 * np.abs(want).max())
+
+
+def test_true_impes_keeps_the_column_sums_of_the_schur_complement(tiny, oracle_lib):
+    # With the secondary rows of the off-diagonal blocks zero (cell-local
+    # secondary equations), True-IMPES gives S_p the column sums of the exact
+    # Schur complement A_pp - A_ps A_ss^{-1} A_sp (summing the pressure rows
+    # conserves what the secondary unknowns exchange); Quasi-IMPES does not.
+    n, nv = tiny.n, tiny.nv
+    vals = _local_secondary(tiny, "rows")
+    A = dense_bsr(tiny.row_ptr, tiny.col_idx, vals, nv)
+    want = _schur_p(A, nv).sum(axis=0)
+    sums = {}
+    for kind in ("ti", "qi"):
+        o = O.Oracle(n, nv, tiny.row_ptr, tiny.col_idx, vals, first="cpr", second="none",
+                     coarse_size=10_000, decoupling=kind)
+        sums[kind] = _pressure_operator(o).sum(axis=0)
+    scale = np.abs(want).max()
+    assert np.allclose(sums["ti"], want, rtol=1e-10, atol=1e-10 * scale)
+    assert not np.allclose(sums["qi"], want, rtol=1e-6, atol=1e-6 * scale)
+
+
+def test_decoupling_needs_the_cpr_first_stage(tiny, oracle_lib):
+    with pytest.raises(RuntimeError):
+        O.Oracle.from_problem(tiny, first="cptr", second="none", decoupling="ti")
+
+
 def _vcycle_matrix(o, which, n):
     return _columns(lambda e: o.vcycle(which, e), n)
 
