@@ -351,9 +351,9 @@ def main():
         sn.close()
         mn.close()
         # context: the same stages behind the CPR first stage (one A_pp V-cycle)
-        # (also with the True-IMPES decoupling operator, Section 3.1) and behind
+        # (also with the True-IMPES decoupling operator, Section 3.1), behind
         # the block-diagonal CPTR-BD(AMG) first stage (V-cycles on A_pp and
-        # A_TT, Section 4.4)
+        # A_TT, Section 4.4), and CPTR with the BILU(1) second stage
         for tag, first, opt, mdl_needed in (
                 ("fp64_cpr_bilu0", "cpr", dict(precision="fp64", second_stage="bilu0"), False),
                 ("fp32_cpr_bilu0_mc", "cpr", dict(precision="fp32", second_stage="bilu0_mc"), False),
@@ -363,6 +363,9 @@ def main():
                 ("fp64_cpr_ti_bilu0", "cpr", dict(precision="fp64", second_stage="bilu0", decoupling="ti"),
                  False),
                 ("fp32_cpr_ti_bilu0_mc", "cpr", dict(precision="fp32", second_stage="bilu0_mc", decoupling="ti"),
+                 False),
+                ("fp64_cptr_bilu1", args.first, dict(precision="fp64", second_stage="bilu0", ilu_level=1), False),
+                ("fp32_cptr_bilu1_mc", args.first, dict(precision="fp32", second_stage="bilu0_mc", ilu_level=1),
                  False)):
             sc, su = setup(first_stage=first, **opt)
             mc_ = None

@@ -132,6 +132,9 @@ typedef struct {
   int decoupling;        /* CPTR_DECOUPLE_* for CPTR_FIRST_CPR (NONE); other first stages
                             reject QI / TI with CPTR_ERR_UNSUPPORTED, a singular block of D
                             gives CPTR_ERR_SINGULAR_BLOCK */
+  int ilu_level;         /* level of fill of the BILU second stages: 0 (BILU(0)) or 1 (BILU(1):
+                            the blocks of A and the level-1 fill, Section 4's ILU(1)) (0);
+                            the learned stage's fallback stays BILU(0) */
 } cptr_options;
 
 typedef struct {

@@ -688,8 +688,74 @@ static void bilu_free(bilu *f) {
  * natural order (smallest colour unused by earlier neighbours), rows
  * renumbered colour by colour (ascending index inside a colour), then ILU(0)
  * of the renumbered matrix. */
+/* Level-1 fill of block ILU(1) (Section 4: ILU(1) as the second stage of
+ * CPR-AMG-ILU(1)): with lev = 0 on the blocks of A, a block (i, j) has level
+ * 1 when some k < i has (i, k) and (k, j) of level 0 with j > k; the pattern
+ * keeps the blocks of level <= 1.  Replaces the (factor-order) pattern of f,
+ * fill blocks zero. */
+static void bilu_add_fill1(bilu *f) {
+  int n = f->n, b2 = f->nv * f->nv;
+  int *mark = (int *)malloc(sizeof(int) * (size_t)(n > 0 ? n : 1));
+  int *slot = (int *)malloc(sizeof(int) * (size_t)(n > 0 ? n : 1));
+  for (int c = 0; c < n; c++) mark[c] = -1;
+  int *nrp = (int *)calloc((size_t)n + 1, sizeof(int));
+  for (int r = 0; r < n; r++) {
+    int cnt = 0;
+    for (int t = f->rp[r]; t < f->rp[r + 1]; t++) { mark[f->ci[t]] = r; cnt++; }
+    for (int t = f->rp[r]; t < f->rp[r + 1]; t++) {
+      int k = f->ci[t];
+      if (k >= r) continue;
+      for (int u = f->rp[k]; u < f->rp[k + 1]; u++) {
+        int j = f->ci[u];
+        if (j > k && mark[j] != r) { mark[j] = r; cnt++; }
+      }
+    }
+    nrp[r + 1] = nrp[r] + cnt;
+  }
+  int nnz = nrp[n];
+  int *nci = (int *)malloc(sizeof(int) * (size_t)(nnz > 0 ? nnz : 1));
+  double *nlu = (double *)calloc((size_t)nnz * b2 + 1, sizeof(double));
+  for (int c = 0; c < n; c++) mark[c] = -1;
+  for (int r = 0; r < n; r++) {
+    int pos = nrp[r];
+    for (int t = f->rp[r]; t < f->rp[r + 1]; t++) {
+      mark[f->ci[t]] = r;
+      slot[f->ci[t]] = t;
+      nci[pos++] = f->ci[t];
+    }
+    for (int t = f->rp[r]; t < f->rp[r + 1]; t++) {
+      int k = f->ci[t];
+      if (k >= r) continue;
+      for (int u = f->rp[k]; u < f->rp[k + 1]; u++) {
+        int j = f->ci[u];
+        if (j > k && mark[j] != r) { mark[j] = r; slot[j] = -1; nci[pos++] = j; }
+      }
+    }
+    /* ascending columns (insertion sort), values of the original blocks */
+    for (int a = nrp[r] + 1; a < nrp[r + 1]; a++) {
+      int c = nci[a], b = a - 1;
+      while (b >= nrp[r] && nci[b] > c) { nci[b + 1] = nci[b]; b--; }
+      nci[b + 1] = c;
+    }
+    for (int a = nrp[r]; a < nrp[r + 1]; a++)
+      if (slot[nci[a]] >= 0)
+        memcpy(nlu + (size_t)a * b2, f->lu + (size_t)slot[nci[a]] * b2, sizeof(double) * b2);
+  }
+  free(f->rp); free(f->ci); free(f->lu);
+  f->rp = nrp;
+  f->ci = nci;
+  f->lu = nlu;
+  for (int r = 0; r < n; r++) {
+    f->diag[r] = -1;
+    for (int k = f->rp[r]; k < f->rp[r + 1]; k++) if (f->ci[k] == r) f->diag[r] = k;
+  }
+  free(mark);
+  free(slot);
+}
+
 static int bilu_setup(bilu *f, int n, int nv, const int *rp, const int *ci,
-                      const double *v, int multicolor, const int *order, const int *part) {
+                      const double *v, int multicolor, const int *order, const int *part,
+                      int level) {
   memset(f, 0, sizeof(*f));
   int b2 = nv * nv, nnzb = rp[n];
   f->n = n;
@@ -763,6 +829,7 @@ static int bilu_setup(bilu *f, int n, int nv, const int *rp, const int *ci,
     if (f->diag[r] < 0) { free(newof); return -1; }
   }
   free(newof);
+  if (level == 1) bilu_add_fill1(f);
   /* level sets of the triangular solves in factor order */
   f->lev_lower = (int *)malloc(sizeof(int) * (size_t)(n > 0 ? n : 1));
   f->lev_upper = (int *)malloc(sizeof(int) * (size_t)(n > 0 ? n : 1));
@@ -918,7 +985,8 @@ void *orc_create(int n, int nv, const int *rp, const int *ci, const double *vals
   }
   if (st == 0 && (o->second_stage == ORC_SECOND_BILU0 || o->second_stage == ORC_SECOND_BILU0_MC)) {
     st = bilu_setup(&h->ilu, n, nv, rp, ci, vals, o->second_stage == ORC_SECOND_BILU0_MC,
-                    o->ilu_order, o->ilu_part);
+                    o->ilu_order, o->ilu_part,
+                    o->ilu_level);
     if (st != 0) st = -10;
     h->have_ilu = 1;
   }
@@ -1208,4 +1276,13 @@ int orc_ilu_get(void *hv, int *perm, int *color, int *lev_lower, int *lev_upper,
   if (lu_vals) memcpy(lu_vals, f->lu, sizeof(double) * (size_t)f->rp[n] * b2);
   if (dinv) memcpy(dinv, f->dinv, sizeof(double) * (size_t)n * b2);
   return f->ncolor;
+}
+
+int orc_ilu_pattern(void *hv, int *rp, int *ci) {
+  orc *h = (orc *)hv;
+  if (!h->have_ilu) return -1;
+  bilu *f = &h->ilu;
+  if (rp) memcpy(rp, f->rp, sizeof(int) * ((size_t)f->n + 1));
+  if (ci) memcpy(ci, f->ci, sizeof(int) * (size_t)f->rp[f->n]);
+  return f->rp[f->n];
 }

@@ -42,6 +42,7 @@ typedef struct {
   const int *ilu_part; /* BILU0 partition (cell -> part, couplings across parts dropped) or NULL */
   int smooth_p_T;      /* prolongator of the S~_T hierarchy: 1 smoothed, 0 plain, -1 as smooth_p */
   int decoupling;      /* CPR first stage only: 0 none, 1 Quasi-IMPES, 2 True-IMPES (Section 3.1) */
+  int ilu_level;       /* level of fill of the block ILU second stage: 0 (BILU(0)) or 1 (BILU(1)) */
 } orc_opts;
 
 typedef struct {
@@ -58,6 +59,9 @@ void *orc_create(int n, int nv, const int *rp, const int *ci, const double *vals
 void orc_destroy(void *h);
 int orc_apply(void *h, const double *v, double *z);
 int orc_first_stage(void *h, const double *v, double *x1);
+/* block ILU factor pattern in factor order: returns the number of blocks;
+ * rp [n+1] and ci [nnz] are filled when non-NULL */
+int orc_ilu_pattern(void *h, int *rp, int *ci);
 int orc_fgmres(void *h, const double *b, double *x, int m, double rtol, int maxit,
                orc_info *info, double *V, double *Z, double *H);
 

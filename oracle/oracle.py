@@ -33,7 +33,8 @@ class _Opts(C.Structure):
                 ("iT", C.c_int), ("theta", C.c_double), ("max_levels", C.c_int),
                 ("coarse_size", C.c_int), ("seed", C.c_uint), ("sweeps", C.c_int),
                 ("smooth_p", C.c_int), ("smoother", C.c_int), ("ilu_order", C.c_void_p),
-                ("ilu_part", C.c_void_p), ("smooth_p_T", C.c_int), ("decoupling", C.c_int)]
+                ("ilu_part", C.c_void_p), ("smooth_p_T", C.c_int), ("decoupling", C.c_int),
+                ("ilu_level", C.c_int)]
 
 
 class _Info(C.Structure):
@@ -65,6 +66,7 @@ def lib():
                                         ip_, dp, dp]
         L.orc_amg_vcycle.argtypes = [vp, C.c_int, dp, dp]
         L.orc_ilu_get.argtypes = [vp, ip_, ip_, ip_, ip_, dp, dp]
+        L.orc_ilu_pattern.argtypes = [vp, ip_, ip_]
         L.orc_bsr_spmv.argtypes = [C.c_int, C.c_int, ip_, ip_, dp, dp, dp]
         L.orc_strength.argtypes = [C.c_int, ip_, ip_, dp, C.c_double, ip_, ip_]
         L.orc_mis2_greedy.argtypes = [C.c_int, ip_, ip_, C.c_uint, ip_]
@@ -130,7 +132,7 @@ class Oracle:
                  st_vals=None, first="cptr", second="bilu0", ip=0, iT=None,
                  theta=0.08, max_levels=10, coarse_size=512, seed=0, sweeps=2,
                  smooth_p=True, smoother="jacobi", ilu_order=None, ilu_part=None, smooth_p_T=False,
-                 decoupling="none"):
+                 decoupling="none", ilu_level=0):
         self.n, self.nv = n, nv
         self._keep = [_ci(row_ptr), _ci(col), _cd(vals)]
         if st_row_ptr is None:
@@ -149,7 +151,7 @@ class Oracle:
                   theta, max_levels, coarse_size, seed, sweeps, int(bool(smooth_p)),
                   {"jacobi": 0, "gs": 1}[smoother], extra[0], extra[1],
                   -1 if smooth_p_T is None else int(bool(smooth_p_T)),
-                  DECOUPLING[decoupling])
+                  DECOUPLING[decoupling], int(ilu_level))
         status = C.c_int(0)
         rp, ci, v, srp, sci, sv = self._keep[:6]
         self.h = lib().orc_create(n, nv, _i(rp), _i(ci), _d(v), _i(srp), _i(sci), _d(sv),
@@ -237,7 +239,12 @@ class Oracle:
 
     def ilu(self):
         n, nv = self.n, self.nv
-        nnzb = self._keep[1].size
+        nnzb = lib().orc_ilu_pattern(self.h, None, None)
+        if nnzb < 0:
+            raise RuntimeError("no ILU")
+        frp = np.zeros(n + 1, np.int32)
+        fci = np.zeros(max(nnzb, 1), np.int32)
+        lib().orc_ilu_pattern(self.h, _i(frp), _i(fci))
         perm = np.zeros(n, np.int32)
         color = np.zeros(n, np.int32)
         ll = np.zeros(n, np.int32)
@@ -248,4 +255,4 @@ class Oracle:
         if nc < 0:
             raise RuntimeError("no ILU")
         return dict(perm=perm, color=color, lev_lower=ll, lev_upper=lu_, lu=luv,
-                    dinv=dinv, ncolor=nc)
+                    dinv=dinv, ncolor=nc, rp=frp, ci=fci[:nnzb])

@@ -28,7 +28,8 @@ class Options(C.Structure):
                 ("amg_seed", C.c_uint), ("amg_sweeps", C.c_int), ("amg_smooth_p", C.c_int),
                 ("amg_smooth_p_T", C.c_int),
                 ("use_graph", C.c_int), ("resid_fp64", C.c_int),
-                ("scalar_dia", C.c_int), ("lrn_columns", C.c_int), ("decoupling", C.c_int)]
+                ("scalar_dia", C.c_int), ("lrn_columns", C.c_int), ("decoupling", C.c_int),
+                ("ilu_level", C.c_int)]
 
 
 class Bsr(C.Structure):

@@ -1010,7 +1010,9 @@ static void build_precond(cptr_handle *h, const std::vector<int> &rp, const std:
   if (o.second_stage == CPTR_SECOND_BILU0 || o.second_stage == CPTR_SECOND_BILU0_MC ||
       o.second_stage == CPTR_SECOND_LEARNED) {
     IluHost ih;  // with the learned stage: the natural-order factor of the fallback (plain ILU(0))
-    ilu_build(n, nv, rp.data(), ci.data(), vals.data(), o.second_stage == CPTR_SECOND_BILU0_MC, ih);
+    // the learned stage's fallback is the plain natural-order BILU(0)
+    ilu_build(n, nv, rp.data(), ci.data(), vals.data(), o.second_stage == CPTR_SECOND_BILU0_MC, ih,
+              o.second_stage == CPTR_SECOND_LEARNED ? 0 : o.ilu_level);
     P.ilu.build(ih);
     P.have_ilu = true;
     if (o.second_stage != CPTR_SECOND_LEARNED) bytes += P.ilu.bytes;
@@ -1100,6 +1102,7 @@ static void validate_and_fetch(const cptr_bsr *A, const cptr_csr *S, const cptr_
     throw Error{CPTR_ERR_INVALID_ARG, "invalid AMG options"};
   if (o.first_stage < 0 || o.first_stage > 4) throw Error{CPTR_ERR_INVALID_ARG, "invalid first stage"};
   if (o.decoupling < 0 || o.decoupling > 2) throw Error{CPTR_ERR_INVALID_ARG, "invalid decoupling"};
+  if (o.ilu_level != 0 && o.ilu_level != 1) throw Error{CPTR_ERR_UNSUPPORTED, "ilu_level must be 0 or 1"};
   if (o.decoupling != 0 && o.first_stage != CPTR_FIRST_CPR)
     throw Error{CPTR_ERR_UNSUPPORTED, "decoupling operators apply to the CPR first stage only"};
   if (o.second_stage < 0 || o.second_stage > 4)
@@ -1528,6 +1531,7 @@ void cptr_default_options(cptr_options *o) {
   o->scalar_dia = 1;
   o->lrn_columns = 1;
   o->decoupling = CPTR_DECOUPLE_NONE;
+  o->ilu_level = 0;
 }
 
 int cptr_setup(cptr_handle **out, const cptr_bsr *A, const cptr_csr *S_T, const cptr_options *opt,

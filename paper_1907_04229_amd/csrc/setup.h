@@ -70,7 +70,8 @@ struct IluHost {
 };
 
 // Throws Error (CPTR_ERR_SINGULAR_BLOCK on a zero pivot).
+// level: 0 for BILU(0), 1 for BILU(1) (level-1 fill of the block pattern).
 void ilu_build(int n, int nv, const int *rp, const int *ci, const double *vals,
-               bool multicolor, IluHost &out);
+               bool multicolor, IluHost &out, int level = 0);
 
 }  // namespace cptr

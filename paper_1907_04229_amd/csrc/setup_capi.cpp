@@ -76,10 +76,10 @@ int cptrh_amg_get(void *h, int l, int *agg, int *arp, int *aci, double *av, int 
 void cptrh_amg_free(void *h) { delete static_cast<AmgBox *>(h); }
 
 void *cptrh_ilu_build(int n, int nv, const int *rp, const int *ci, const double *v, int mc,
-                      int *status) {
+                      int level, int *status) {
   auto *b = new IluBox();
   try {
-    ilu_build(n, nv, rp, ci, v, mc != 0, b->h);
+    ilu_build(n, nv, rp, ci, v, mc != 0, b->h, level);
     *status = 0;
   } catch (const Error &e) {
     g_err = e.msg;

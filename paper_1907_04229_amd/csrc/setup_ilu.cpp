@@ -1,6 +1,7 @@
-// Block ILU(0) factorisation (host, FP64) and the level schedule of its
-// triangular solves.  ILU(0) is the second stage of CPR and CPTR (Section 3;
-// the implementation notes of Section 4 use ILU(0) by default).
+// Block ILU(0) / ILU(1) factorisation (host, FP64) and the level schedule of
+// its triangular solves.  ILU(0) is the second stage of CPR and CPTR (Section
+// 3; the implementation notes of Section 4 use ILU(0) by default, ILU(1) in
+// CPR-AMG-ILU(1)).  ILU(1) factors on the blocks of A plus the level-1 fill.
 //
 // Factor order: natural cell order, or a greedy multicolour order (colour of
 // a cell = smallest colour not used by its lower-numbered neighbours; cells
@@ -53,7 +54,7 @@ bool blk_inv(int nv, const double *a, double *inv) {
 }  // namespace
 
 void ilu_build(int n, int nv, const int *rp, const int *ci, const double *vals,
-               bool multicolor, IluHost &out) {
+               bool multicolor, IluHost &out, int level) {
   const int b2 = nv * nv;
   out.n = n;
   out.nv = nv;
@@ -98,9 +99,46 @@ void ilu_build(int n, int nv, const int *rp, const int *ci, const double *vals,
       src[frp[p] + t] = row[t].second;
     }
   }
-  std::vector<double> lu((size_t)rp[n] * b2);
-  for (int k = 0; k < rp[n]; k++)
-    std::copy(vals + (size_t)src[k] * b2, vals + (size_t)src[k] * b2 + b2, lu.begin() + (size_t)k * b2);
+  if (level == 1) {
+    // ILU(1): the blocks of A (level 0) and the level-1 fill (p, j) for every
+    // lower block (p, q) of A and upper block (q, j) of A, j > q; fill blocks
+    // start at zero (src = -1)
+    std::vector<int> nrp(n + 1, 0), nci, nsrc;
+    std::vector<int> seen(n, -1);
+    std::vector<std::pair<int, int>> row;
+    for (int p = 0; p < n; p++) {
+      row.clear();
+      for (int k = frp[p]; k < frp[p + 1]; k++) {
+        seen[fci[k]] = p;
+        row.push_back({fci[k], src[k]});
+      }
+      for (int k = frp[p]; k < frp[p + 1]; k++) {
+        const int q = fci[k];
+        if (q >= p) continue;
+        for (int t = frp[q]; t < frp[q + 1]; t++) {
+          const int j = fci[t];
+          if (j > q && seen[j] != p) {
+            seen[j] = p;
+            row.push_back({j, -1});
+          }
+        }
+      }
+      std::sort(row.begin(), row.end());
+      for (const auto &e : row) {
+        nci.push_back(e.first);
+        nsrc.push_back(e.second);
+      }
+      nrp[p + 1] = int(nci.size());
+    }
+    frp.swap(nrp);
+    fci.swap(nci);
+    src.swap(nsrc);
+  }
+  const int nnzf = frp[n];
+  std::vector<double> lu((size_t)nnzf * b2, 0.0);
+  for (int k = 0; k < nnzf; k++)
+    if (src[k] >= 0)
+      std::copy(vals + (size_t)src[k] * b2, vals + (size_t)src[k] * b2 + b2, lu.begin() + (size_t)k * b2);
   std::vector<int> dpos(n, -1);
   for (int p = 0; p < n; p++)
     for (int k = frp[p]; k < frp[p + 1]; k++)

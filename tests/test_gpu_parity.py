@@ -295,6 +295,34 @@ def test_decoupled_cpr_fp64(name, kind):
     s.close()
 
 
+@pytest.mark.parametrize("name", ["ragged", "three", "small"])
+@pytest.mark.parametrize("second", ["bilu0", "bilu0_mc"])
+def test_bilu1_fp64(name, second):
+    """BILU(1) second stage (ilu_level = 1): level schedule bit-exact, FP64
+    application and FGMRES against the oracle."""
+    banner(f"bilu1 {name} {second}")
+    pr = prob(name)
+    s = solver(pr, precision="fp64", second_stage=second, ilu_level=1, amg_coarse_size=16)
+    o = O.Oracle.from_problem(pr, first="cptr", second=second, ilu_level=1, coarse_size=16)
+    ll, lu, col = cptr.cptr_get_ilu_schedule(s.h, pr.n)
+    f = o.ilu()
+    cells = f["perm"]
+    assert np.array_equal(ll[cells], f["lev_lower"]) and np.array_equal(lu[cells], f["lev_upper"])
+    v = np.random.default_rng(15).standard_normal(pr.n * pr.nv)
+    z = s.apply(dev(v))
+    torch.cuda.synchronize()
+    assert relerr(z.cpu().numpy(), o.apply(v)) <= 1e-9
+    s.close()
+    s = solver(pr, precision="fp64", second_stage=second, ilu_level=1)
+    o = O.Oracle.from_problem(pr, first="cptr", second=second, ilu_level=1)
+    xg, info = s.solve(dev(pr.b), restart=30, rtol=1e-6)
+    xo, io = o.fgmres(pr.b, m=30, rtol=1e-6)
+    err = np.linalg.norm(xg.cpu().numpy() - xo) / np.linalg.norm(xo)
+    print(f"iters gpu {info['iters']} oracle {io['iters']} err {err:.2e}")
+    assert info["converged"] and abs(info["iters"] - io["iters"]) <= 1 and err <= 1e-8
+    s.close()
+
+
 # ---------------------------------------------------------------- FGMRES
 @pytest.mark.parametrize("name", ["ragged", "three", "small", "chain"])
 @pytest.mark.parametrize("first,second", [("cptr", "bilu0"), ("cptr", "bilu0_mc"),

@@ -272,6 +272,64 @@ def test_bilu0_defining_property(tiny, second, oracle_lib):
     assert np.abs((LU - A)[~M]).max() > 0                           # ... and fill is dropped
 
 
+@pytest.mark.parametrize("second", ["bilu0", "bilu0_mc"])
+def test_bilu1_defining_property(tiny, second, oracle_lib):
+    # block ILU(1): (LU)_ij = A_ij on the level-1 pattern (zero at its fill
+    # blocks), which holds the pattern of A; fill of level 2 is dropped
+    o = O.Oracle.from_problem(tiny, first="none", second=second, ilu_level=1)
+    f = o.ilu()
+    n, nv = tiny.n, tiny.nv
+    rp0, ci0, bl = _permuted(tiny, f["perm"])
+    A = dense_bsr(rp0, ci0, bl.reshape(-1), nv)
+    rp, ci = f["rp"], f["ci"]
+    L, U = _lu_dense(f, rp, ci, nv, n)
+    LU = L @ U
+    mask = np.zeros((n, n), bool)
+    for i in range(n):
+        mask[i, ci[rp[i]:rp[i + 1]]] = True
+    mask0 = np.zeros((n, n), bool)
+    for i in range(n):
+        mask0[i, ci0[rp0[i]:rp0[i + 1]]] = True
+    assert (mask | mask0 == mask).all() and mask.sum() > mask0.sum()
+    M = np.kron(mask, np.ones((nv, nv), bool))
+    assert np.abs((LU - A)[M]).max() <= 1e-12 * np.abs(A).max()
+    assert np.abs((LU - A)[~M]).max() > 0
+
+
+def test_bilu1_pattern_closed_form(oracle_lib):
+    # natural order on an nx x ny x nz grid: the level-1 fill of a cell comes
+    # from its lower neighbours k = i - 1, i - nx, i - nx ny and their upper
+    # neighbours k + 1, k + nx, k + nx ny: offsets +-(nx - 1), +-(nx ny - 1),
+    # +-(nx ny - nx), where the path through k stays on the grid
+    nx, ny, nz = 5, 4, 3
+    pr = make_problem(shape=(nx, ny, nz), kind="iid", seed=2)
+    o = O.Oracle.from_problem(pr, first="none", second="bilu0", ilu_level=1)
+    f = o.ilu()
+    rp, ci = f["rp"], f["ci"]
+    steps = [(1, 0, 0), (0, 1, 0), (0, 0, 1)]
+
+    def cell(x, y, z):
+        return x + nx * (y + ny * z) if 0 <= x < nx and 0 <= y < ny and 0 <= z < nz else None
+
+    for i in range(pr.n):
+        x, y, z = i % nx, (i // nx) % ny, i // (nx * ny)
+        want = {i}
+        for d in steps:
+            for sgn in (1, -1):
+                c = cell(x + sgn * d[0], y + sgn * d[1], z + sgn * d[2])
+                if c is not None:
+                    want.add(c)
+        for a in steps:            # through k = i - a (lower), then k + b (upper, b != a)
+            for b in steps:
+                if a == b:
+                    continue
+                k = cell(x - a[0], y - a[1], z - a[2])
+                j = cell(x - a[0] + b[0], y - a[1] + b[1], z - a[2] + b[2])
+                if k is not None and j is not None:
+                    want.add(j)
+        assert set(ci[rp[i]:rp[i + 1]].tolist()) == want, i
+
+
 def test_bilu0_levels_and_colours_closed_form(oracle_lib):
     pr = make_problem(shape=(5, 4, 3), kind="iid", seed=2)
     o = O.Oracle.from_problem(pr, first="none", second="bilu0")

@@ -55,11 +55,14 @@ def test_amg_hierarchy_bit_exact(case, which, oracle_lib):
 
 
 @pytest.mark.parametrize("mc", [False, True])
-def test_ilu_schedule_matches_oracle(mc, oracle_lib):
+@pytest.mark.parametrize("level", [0, 1])
+def test_ilu_schedule_matches_oracle(mc, level, oracle_lib):
+    # BILU(0) and BILU(1): factor order, level sets of both sweeps, colours,
+    # bit for bit; the factors to rounding
     pr = make_problem(shape=(7, 6, 5), kind="iid", seed=9, three_phase=True)
-    o = O.Oracle.from_problem(pr, first="none", second="bilu0_mc" if mc else "bilu0")
+    o = O.Oracle.from_problem(pr, first="none", second="bilu0_mc" if mc else "bilu0", ilu_level=level)
     ref = o.ilu()
-    got = H.ilu_schedule(pr.row_ptr, pr.col_idx, pr.vals, pr.nv, mc)
+    got = H.ilu_schedule(pr.row_ptr, pr.col_idx, pr.vals, pr.nv, mc, level)
     assert np.array_equal(got["order"], ref["perm"])
     cells = ref["perm"]
     assert np.array_equal(got["lev_lower"][cells], ref["lev_lower"])
