@@ -438,7 +438,7 @@ static inline short host_bf16(float f) {
 // positions (for A^T in training), and work buffers.
 struct LearnedDev {
   int n = 0, nv = 0, nnzb = 0;
-  DevMem nbr, nmask, E, dinv, tpos, r, s, spart, hA, hB;
+  DevMem nbr, nmask, E, Et, dinv, tpos, r, s, spart, hA, hB;  // Et: E in tile order (k_lrn_edge)
   int stride[3] = {0, 0, 0};  // |column - row| of the neighbours along each axis
   // z-column schedule of the inference layers (k_lrn_layer_col): planes of
   // colP whole tiles, colNZ planes; colP = 0 when the grid does not allow it
@@ -532,6 +532,19 @@ struct LearnedDev {
     upload(nbr, nb);
     upload(nmask, mk);
     upload(E, eb);
+    // the forward layers read the edge blocks in tile order: for tile t,
+    // direction d and lane group g, the 16 cells' four entries 4g .. 4g + 3
+    // are 128 contiguous bytes (one load instruction of a wave reads 512)
+    {
+      const int nt = (n + 15) / 16;
+      std::vector<short> et((size_t)nt * 16 * kDir * kEdge, 0);
+      for (int i = 0; i < n; i++)
+        for (int d = 0; d < kDir; d++)
+          for (int e = 0; e < kEdge; e++)
+            et[(((size_t)(i / 16) * kDir + d) * 4 + e / 4) * 64 + (i % 16) * 4 + e % 4] =
+                eb[((size_t)i * kDir + d) * kEdge + e];
+      upload(Et, et);
+    }
     upload(dinv, df);
     upload(tpos, tp);
     r.alloc((size_t)n * nv * 4);
@@ -600,7 +613,7 @@ struct LearnedDev {
     const int lb = kXcds * std::max(1, std::min(kLayerMaxBlocks, (ntiles() + 3) / 4) / kXcds);
     const unsigned char *nbp = devp<unsigned char>(nmask);
     const int3 str = make_int3(stride[0], stride[1], stride[2]);
-    const short *Ep = devp<short>(E);
+    const short *Ep = devp<short>(Et);  // tile order
     const float *sp = devp<float>(s), *rp_ = devp<float>(r);
     const LrnOut<float, float> none{nullptr, 0, 0, nullptr, nullptr, nullptr, nullptr};
     const float *We = mdl.We32(l);

@@ -229,6 +229,16 @@ struct RawAct<HT, NV, true> {
   }
 };
 
+// Edge blocks in tile order (what the forward layers read): for tile t,
+// direction d and lane group g, the entries 4g .. 4g + 3 of the 16 cells of
+// the tile are 16 x 4 consecutive BF16, so a wave's load of one direction is
+// 512 contiguous bytes.  Cells past n (last tile) hold zeros.
+__device__ __forceinline__ bf16x4 load_edge_tiled(const short *__restrict__ Et, int tile, int d, int lg,
+                                                  int lr) {
+  return __builtin_nontemporal_load(
+      reinterpret_cast<const bf16x4 *>(Et + ((((size_t)tile * kDir + d) * 4 + lg) * 16 + lr) * 4));
+}
+
 // Workgroups of the layer kernel: enough to fill the chip several times over;
 // each wave loops over tiles.
 constexpr int kLayerMaxBlocks = 2048;
@@ -380,7 +390,7 @@ __device__ __forceinline__ void layer_tile(int cell, bool ok, int lr, int lg, co
 // (neighbours by presence mask and the three axis strides).
 template <int NV, bool FIRST, bool LAST, typename HT, typename ZT, typename XT>
 __global__ void __launch_bounds__(kBlock) k_lrn_layer(
-    int n, const unsigned char *__restrict__ nmask, int3 stride, const short *__restrict__ E,
+    int n, const unsigned char *__restrict__ nmask, int3 stride, const short *__restrict__ Et,
     const float *__restrict__ s_ptr, const HT *__restrict__ hin, const float *__restrict__ r, const float *__restrict__ W_in,
     const float *__restrict__ W_e, const short *__restrict__ W_s, const short *__restrict__ W_m,
     const float *__restrict__ bias, HT *__restrict__ hout, float *__restrict__ h0_out,
@@ -420,7 +430,7 @@ __global__ void __launch_bounds__(kBlock) k_lrn_layer(
     bf16x4 rawe[kDir];
 #pragma unroll
     for (int d = 0; d < kDir; d++) {
-      rawe[d] = __builtin_nontemporal_load(reinterpret_cast<const bf16x4 *>(E + ((size_t)cl * kDir + d) * kEdge + 4 * lg));
+      rawe[d] = load_edge_tiled(Et, tile, d, lg, lr);
       raw[d] = Raw::load((mk >> d) & 1u ? cl + off[d] : cl, lg, hin, r);
     }
     f32x4 hv[4];
@@ -460,7 +470,7 @@ constexpr int kDppRowShl1 = 0x101;  // lane i <- lane i + 1 within a row of 16
 // is the same row, every absent one finite (and multiplied by zero).
 template <int NV, bool FIRST, bool LAST, typename HT, typename ZT, typename XT>
 __global__ void __launch_bounds__(kBlock) k_lrn_layer_col(
-    int n, int P, int nz, int zlen, int sy, const short *__restrict__ E, const float *__restrict__ s_ptr,
+    int n, int P, int nz, int zlen, int sy, const short *__restrict__ Et, const float *__restrict__ s_ptr,
     const HT *__restrict__ hin, const float *__restrict__ r, const float *__restrict__ W_in,
     const float *__restrict__ W_e, const short *__restrict__ W_s, const short *__restrict__ W_m,
     const float *__restrict__ bias, HT *__restrict__ hout, LrnOut<ZT, XT> out) {
@@ -494,7 +504,7 @@ __global__ void __launch_bounds__(kBlock) k_lrn_layer_col(
       bf16x4 rawe[kDir];
 #pragma unroll
       for (int d = 0; d < kDir; d++)
-        rawe[d] = __builtin_nontemporal_load(reinterpret_cast<const bf16x4 *>(E + ((size_t)cell * kDir + d) * kEdge + 4 * lg));
+        rawe[d] = load_edge_tiled(Et, cell >> 4, d, lg, lr);
       raw[0] = shuffle_row<RT, kDppRowShr1>(rc, xe);
       raw[1] = shuffle_row<RT, kDppRowShl1>(rc, xe);
       raw[4] = rp;
