@@ -438,7 +438,7 @@ static inline short host_bf16(float f) {
 // positions (for A^T in training), and work buffers.
 struct LearnedDev {
   int n = 0, nv = 0, nnzb = 0;
-  DevMem nbr, nmask, E, Et, dinv, tpos, r, s, spart, hA, hB;  // Et: E in tile order (k_lrn_edge)
+  DevMem nbr, nmask, E, Et, dinv, tpos, r, s, spart, hA, hB;  // Et: E in tile order (load_edge_tiled)
   int stride[3] = {0, 0, 0};  // |column - row| of the neighbours along each axis
   // z-column schedule of the inference layers (k_lrn_layer_col): planes of
   // colP whole tiles, colNZ planes; colP = 0 when the grid does not allow it
@@ -550,8 +550,9 @@ struct LearnedDev {
     r.alloc((size_t)n * nv * 4);
     s.alloc(4 * 4);
     spart.alloc((size_t)(nblk(n) + 1) * 4 * 8);
-    hA.alloc((size_t)n * kHid * 2);  // BF16 activations of the inference pass
-    hB.alloc((size_t)n * kHid * 2);
+    // BF16 activations of the inference pass, tile order, padded to whole tiles
+    hA.alloc((size_t)((n + 15) / 16) * 16 * kHid * 2);
+    hB.alloc((size_t)((n + 15) / 16) * 16 * kHid * 2);
   }
 
   void ensure_train() {
@@ -654,7 +655,7 @@ struct LearnedDev {
     } else {
       short *ha = devp<short>(hA), *hb = devp<short>(hB);
       if (l == 0)
-        hipLaunchKernelGGL((k_lrn_layer<NV, true, false, short, float, float>), dim3(lb), dim3(kBlock), 0, st, n,
+        hipLaunchKernelGGL((k_lrn_layer_first<NV, true, false, short, float, float>), dim3(lb), dim3(kBlock), 0, st, n,
                            nbp, str, Ep, sp, (const short *)nullptr, rp_, mdl.W_in(), We, Ws, Wm, bs, ha,
                            (float *)nullptr, (float *)nullptr, (float *)nullptr, none);
       else if (l == 1)

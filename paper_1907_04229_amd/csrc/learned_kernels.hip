@@ -174,6 +174,22 @@ __device__ __forceinline__ void store_h4(short *p, f32x4 v) {
 // activations stay in channel order in memory.
 __device__ __forceinline__ int lch(int t, int lg) { return 32 * (t >> 1) + 8 * lg + 4 * (t & 1); }
 
+// Offset of channel ch of a cell's activations.  FP32 activations (training)
+// are rows of 64 channels; the BF16 activations of the forward pass are in
+// tile order: for tile t = cell / 16, half ks = ch / 32 and lane group
+// g = (ch % 32) / 8, the eight channels of the 16 cells are 16 x 8
+// consecutive BF16, so a wave's load of one half is 1 KB contiguous (the
+// arrays are padded to whole tiles).
+__device__ __forceinline__ size_t h_off(const float *, int cell, int ch) {
+  return (size_t)cell * kHid + ch;
+}
+// (32-bit offsets: 64 n < 2^32 for the grids this library takes; they keep
+// the address arithmetic in single registers)
+__device__ __forceinline__ uint32_t h_off(const short *, int cell, int ch) {
+  return (uint32_t)(cell >> 4) * 1024u + (uint32_t)(ch >> 5) * 512u + (uint32_t)((ch >> 3) & 3) * 128u +
+         (uint32_t)(cell & 15) * 8u + (uint32_t)(ch & 7);
+}
+
 // Neighbour activations as loaded (before conversion): BF16 or FP32 rows of
 // the lane's 16 channels, or, for the first layer, the nv values of r from
 // which h0 = W_in (r / s) is formed.
@@ -185,7 +201,7 @@ struct RawAct<short, NV, false> {
   static __device__ __forceinline__ type load(int cell, int lg, const short *h, const float *) {
     type o;
 #pragma unroll
-    for (int t = 0; t < 4; t++) o.v[t] = load_bf4(h + (size_t)cell * kHid + lch(t, lg));
+    for (int t = 0; t < 4; t++) o.v[t] = load_bf4(h + h_off(h, cell, lch(t, lg)));
     return o;
   }
   static __device__ __forceinline__ f32x4 get(const type &o, int t, int, const float *, const float *) {
@@ -198,7 +214,7 @@ struct RawAct<float, NV, false> {
   static __device__ __forceinline__ type load(int cell, int lg, const float *h, const float *) {
     type o;
 #pragma unroll
-    for (int t = 0; t < 4; t++) o.v[t] = load_f4(h + (size_t)cell * kHid + lch(t, lg));
+    for (int t = 0; t < 4; t++) o.v[t] = load_f4(h + h_off(h, cell, lch(t, lg)));
     return o;
   }
   static __device__ __forceinline__ f32x4 get(const type &o, int t, int, const float *, const float *) {
@@ -253,7 +269,8 @@ constexpr int kColWaves = 4096;  // target wave count of the z-column schedule (
 //   g^T = W_e e^T (per direction, 16x16x16),  a^T = W_s h^T + W_m m^T (16x16x32)
 // and the messages m = sum_d g * h_nbr, accumulated in that layout, are
 // directly the B operand of W_m.  Activations are read and written as four
-// consecutive channels per lane (HT: FP32 or BF16 in memory).  W_s and W_m
+// consecutive channels per lane (HT: FP32 rows, or BF16 in tile order, see
+// h_off).  W_s and W_m
 // are staged in LDS once per workgroup; W_e stays in registers.
 // FIRST: the input activations h0 = W_in (r / s) are formed on the fly for the
 //        cell and its neighbours (stored to h0_out when given).
@@ -348,7 +365,7 @@ __device__ __forceinline__ void layer_tile(int cell, bool ok, int lr, int lg, co
     }
     if (ok) {
       const size_t o = (size_t)cell * kHid + lch(t, lg);
-      if (hout) store_h4(hout + o, hnew[t]);
+      if (hout) store_h4(hout + h_off(hout, cell, lch(t, lg)), hnew[t]);
       if (m_out) store_f4(m_out + o, macc[t]);
       if (a_out) store_f4(a_out + o, a);
       if (FIRST && h0_out) store_f4(h0_out + o, hv[t]);
@@ -389,12 +406,12 @@ __device__ __forceinline__ void layer_tile(int cell, bool ok, int lr, int lg, co
 // One message-passing layer over tiles in cell order.  Any 7-point cell graph
 // (neighbours by presence mask and the three axis strides).
 template <int NV, bool FIRST, bool LAST, typename HT, typename ZT, typename XT>
-__global__ void __launch_bounds__(kBlock) k_lrn_layer(
+__device__ __forceinline__ void lrn_layer_tiles(
     int n, const unsigned char *__restrict__ nmask, int3 stride, const short *__restrict__ Et,
     const float *__restrict__ s_ptr, const HT *__restrict__ hin, const float *__restrict__ r, const float *__restrict__ W_in,
     const float *__restrict__ W_e, const short *__restrict__ W_s, const short *__restrict__ W_m,
     const float *__restrict__ bias, HT *__restrict__ hout, float *__restrict__ h0_out,
-    float *__restrict__ m_out, float *__restrict__ a_out, LrnOut<ZT, XT> out) {
+    float *__restrict__ m_out, float *__restrict__ a_out, const LrnOut<ZT, XT> &out) {
   __shared__ __attribute__((aligned(16))) short Wl[2][kHid][kWPad];
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int lr = l & 15, lg = l >> 4;
@@ -440,6 +457,31 @@ __global__ void __launch_bounds__(kBlock) k_lrn_layer(
                                            hout, h0_out, m_out, a_out, out);
   }
 }
+
+#define CPTR_LRN_LAYER_ARGS                                                                                 \
+  int n, const unsigned char *__restrict__ nmask, int3 stride, const short *__restrict__ Et,              \
+      const float *__restrict__ s_ptr, const HT *__restrict__ hin, const float *__restrict__ r,           \
+      const float *__restrict__ W_in, const float *__restrict__ W_e, const short *__restrict__ W_s,       \
+      const short *__restrict__ W_m, const float *__restrict__ bias, HT *__restrict__ hout,                \
+      float *__restrict__ h0_out, float *__restrict__ m_out, float *__restrict__ a_out, LrnOut<ZT, XT> out
+#define CPTR_LRN_LAYER_CALL \
+  lrn_layer_tiles<NV, FIRST, LAST, HT, ZT, XT>(n, nmask, stride, Et, s_ptr, hin, r, W_in, W_e, W_s, W_m, bias, hout, \
+                                              h0_out, m_out, a_out, out)
+
+template <int NV, bool FIRST, bool LAST, typename HT, typename ZT, typename XT>
+__global__ void __launch_bounds__(kBlock) k_lrn_layer(CPTR_LRN_LAYER_ARGS) {
+  CPTR_LRN_LAYER_CALL;
+}
+
+// the same for the first layer of the forward pass, whose h0 = W_in (r / s)
+// of seven cells per tile needs many registers: held to three waves per SIMD
+template <int NV, bool FIRST, bool LAST, typename HT, typename ZT, typename XT>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3)))
+k_lrn_layer_first(CPTR_LRN_LAYER_ARGS) {
+  CPTR_LRN_LAYER_CALL;
+}
+#undef CPTR_LRN_LAYER_CALL
+#undef CPTR_LRN_LAYER_ARGS
 
 // x-neighbour rows by lane shuffle: lane lr of each 16-lane DPP row takes the
 // value of lane lr - 1 (row_shr:1) or lr + 1 (row_shl:1); the lane at the end
