@@ -654,11 +654,16 @@ struct LearnedDev {
                            (short *)nullptr, out);
     } else {
       short *ha = devp<short>(hA), *hb = devp<short>(hB);
-      if (l == 0)
-        hipLaunchKernelGGL((k_lrn_layer_first<NV, true, false, short, float, float>), dim3(lb), dim3(kBlock), 0, st, n,
-                           nbp, str, Ep, sp, (const short *)nullptr, rp_, mdl.W_in(), We, Ws, Wm, bs, ha,
-                           (float *)nullptr, (float *)nullptr, (float *)nullptr, none);
-      else if (l == 1)
+      if (l == 0) {
+        if constexpr (NV == 3)  // held to three waves per SIMD (it would spill at NV = 4)
+          hipLaunchKernelGGL((k_lrn_layer_first<NV, true, false, short, float, float>), dim3(lb), dim3(kBlock), 0,
+                             st, n, nbp, str, Ep, sp, (const short *)nullptr, rp_, mdl.W_in(), We, Ws, Wm, bs, ha,
+                             (float *)nullptr, (float *)nullptr, (float *)nullptr, none);
+        else
+          hipLaunchKernelGGL((k_lrn_layer<NV, true, false, short, float, float>), dim3(lb), dim3(kBlock), 0, st, n,
+                             nbp, str, Ep, sp, (const short *)nullptr, rp_, mdl.W_in(), We, Ws, Wm, bs, ha,
+                             (float *)nullptr, (float *)nullptr, (float *)nullptr, none);
+      } else if (l == 1)
         hipLaunchKernelGGL((k_lrn_layer<NV, false, false, short, float, float>), dim3(lb), dim3(kBlock), 0, st, n,
                            nbp, str, Ep, sp, (const short *)ha, rp_, mdl.W_in(), We, Ws, Wm, bs, hb,
                            (float *)nullptr, (float *)nullptr, (float *)nullptr, none);
