@@ -41,6 +41,18 @@ def test_symbol_exported(lib, name):
     assert hasattr(lib, name), f"{name} declared in include/ but not exported"
 
 
+def _options_size_from_header():
+    """sizeof(cptr_options) by a C compiler from include/cptr.h."""
+    import subprocess
+    import tempfile
+    src = '#include "cptr.h"\n#include <stdio.h>\nint main(void){printf("%zu", sizeof(cptr_options));return 0;}\n'
+    with tempfile.TemporaryDirectory() as d:
+        c, exe = os.path.join(d, "s.c"), os.path.join(d, "s")
+        open(c, "w").write(src)
+        subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), c, "-o", exe])
+        return int(subprocess.check_output([exe]).decode())
+
+
 def test_status_strings_and_defaults(lib):
     from paper_1907_04229_amd import cptr
     L = cptr.load()
@@ -49,6 +61,10 @@ def test_status_strings_and_defaults(lib):
     o = cptr.cptr_default_options()
     assert (o.first_stage, o.second_stage, o.precision, o.amg_sweeps) == (1, 2, 1, 2)
     assert abs(o.amg_theta - 0.08) < 1e-15 and o.amg_coarse_size == 512
+    # the fields appended to cptr_options, in the header's order and defaults
+    assert (o.amg_smooth_p_T, o.use_graph, o.resid_fp64, o.scalar_dia, o.lrn_columns, o.decoupling,
+            o.ilu_level) == (0, 1, 0, 1, 1, 0, 0)
+    assert ctypes.sizeof(cptr.Options) == _options_size_from_header()
     # argument validation happens before any device call
     h = ctypes.c_void_p()
     assert L.cptr_setup(ctypes.byref(h), None, None, None, None) == -1
