@@ -432,6 +432,8 @@ static csr tentative(int n, const int *agg, int nagg) {
   return p;
 }
 
+static int amg_finish(amg *m);
+
 static int amg_setup(amg *m, csr fine, double theta, int max_levels, int coarse_size,
                      unsigned seed, int sweeps, int smooth_p, int smoother) {
   memset(m, 0, sizeof(*m));
@@ -468,6 +470,12 @@ static int amg_setup(amg *m, csr fine, double theta, int max_levels, int coarse_
     th *= 0.5;
   }
   m->nlev = l + 1;
+  return amg_finish(m);
+}
+
+/* Per-level smoother data (l1 row sums, colouring) and the coarsest dense LU of
+ * a hierarchy whose operators and transfers are built. */
+static int amg_finish(amg *m) {
   for (int k = 0; k < m->nlev; k++) {
     int n = m->A[k].nr;
     m->dl1[k] = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
@@ -501,6 +509,107 @@ static int amg_setup(amg *m, csr fine, double theta, int max_levels, int coarse_
     for (int q = c->rp[i]; q < c->rp[i + 1]; q++) m->lu[(size_t)i * nc + c->ci[q]] = c->v[q];
   if (lu_factor(m->lu, m->piv, nc) != 0) return -4;
   return 0;
+}
+
+/* Rows and columns r0 .. r1-1 of a square CSR, renumbered from 0. */
+static csr sub_block(const csr *a, int r0, int r1) {
+  int n = r1 - r0, cnt = 0;
+  for (int i = r0; i < r1; i++)
+    for (int k = a->rp[i]; k < a->rp[i + 1]; k++) cnt += a->ci[k] >= r0 && a->ci[k] < r1;
+  csr b;
+  csr_alloc(&b, n, n, cnt);
+  int pos = 0;
+  for (int i = r0; i < r1; i++) {
+    for (int k = a->rp[i]; k < a->rp[i + 1]; k++)
+      if (a->ci[k] >= r0 && a->ci[k] < r1) { b.ci[pos] = a->ci[k] - r0; b.v[pos] = a->v[k]; pos++; }
+    b.rp[i - r0 + 1] = pos;
+  }
+  return b;
+}
+
+/* Unknown-based AMG (Section 3.4) for the pressure-temperature operator A_00
+ * in unknown-wise order: the np pressure rows, then the temperature rows.  At
+ * every level each unknown is coarsened on its own: strength, aggregation and
+ * prolongator are those of the scalar hierarchy above, applied to the diagonal
+ * block of that unknown (pressure: smooth_p, temperature: smooth_pT).  So
+ * P = diag(P_p, P_T), the Galerkin coarse operator P^T A P keeps the
+ * pressure-temperature couplings, and the coarse unknowns are again in
+ * unknown-wise order (pressure aggregates first, temperature aggregates
+ * numbered after them).  Smoothing acts on the whole coupled rows.  The
+ * hierarchy stops on the total size, as the scalar one does, and when neither
+ * block coarsens.  omega[l] records the pressure block's weight. */
+static int uamg_setup(amg *m, csr fine, int np, double theta, int max_levels, int coarse_size,
+                      unsigned seed, int sweeps, int smooth_p, int smooth_pT, int smoother) {
+  memset(m, 0, sizeof(*m));
+  m->sweeps = sweeps;
+  m->smoother = smoother;
+  if (max_levels > MAXLEV) max_levels = MAXLEV;
+  m->A[0] = fine;
+  int l = 0, npl = np;
+  double th = theta;
+  while (m->A[l].nr > coarse_size && l + 1 < max_levels) {
+    int n = m->A[l].nr;
+    int r0[2] = {0, npl}, r1[2] = {npl, n}, na[2] = {0, 0};
+    int *ab[2];
+    csr d[2];
+    int bad = 0;
+    for (int u = 0; u < 2; u++) {
+      int nb = r1[u] - r0[u];
+      d[u] = sub_block(&m->A[l], r0[u], r1[u]);
+      ab[u] = (int *)malloc(sizeof(int) * (size_t)(nb > 0 ? nb : 1));
+      int *srp = (int *)malloc(sizeof(int) * ((size_t)nb + 1));
+      int ns = orc_strength(nb, d[u].rp, d[u].ci, d[u].v, th, srp, NULL);
+      int *sci = (int *)malloc(sizeof(int) * (size_t)(ns > 0 ? ns : 1));
+      orc_strength(nb, d[u].rp, d[u].ci, d[u].v, th, srp, sci);
+      if (aggregate(nb, srp, sci, seed, ab[u], &na[u]) != 0) bad = 1;
+      free(srp);
+      free(sci);
+    }
+    if (bad || na[0] + na[1] >= n) {
+      for (int u = 0; u < 2; u++) { csr_free(&d[u]); free(ab[u]); }
+      if (bad) return -2;
+      break;  /* no coarsening possible */
+    }
+    csr pb[2];
+    double om[2] = {0.0, 0.0};
+    for (int u = 0; u < 2; u++) {
+      int nb = r1[u] - r0[u];
+      if ((u == 0 ? smooth_p : smooth_pT) && nb > 0)
+        pb[u] = smooth_prolongator(&d[u], ab[u], na[u], &om[u], 1);
+      else
+        pb[u] = tentative(nb, ab[u], na[u]);
+    }
+    /* P = diag(P_p, P_T), aggregates of the temperature block shifted by na_p */
+    int *agg = (int *)malloc(sizeof(int) * (size_t)(n > 0 ? n : 1));
+    csr P;
+    csr_alloc(&P, n, na[0] + na[1], pb[0].nnz + pb[1].nnz);
+    int pos = 0;
+    for (int u = 0; u < 2; u++) {
+      int off = u == 0 ? 0 : na[0];
+      for (int i = 0; i < r1[u] - r0[u]; i++) {
+        agg[r0[u] + i] = ab[u][i] < 0 ? -1 : ab[u][i] + off;
+        for (int k = pb[u].rp[i]; k < pb[u].rp[i + 1]; k++) {
+          P.ci[pos] = pb[u].ci[k] + off;
+          P.v[pos] = pb[u].v[k];
+          pos++;
+        }
+        P.rp[r0[u] + i + 1] = pos;
+      }
+    }
+    for (int u = 0; u < 2; u++) { csr_free(&d[u]); csr_free(&pb[u]); free(ab[u]); }
+    m->agg[l] = agg;
+    m->P[l] = P;
+    m->omega[l] = om[0];
+    m->R[l] = csr_transpose(&m->P[l]);
+    csr t = spgemm(&m->A[l], &m->P[l]);
+    m->A[l + 1] = spgemm(&m->R[l], &t);
+    csr_free(&t);
+    npl = na[0];
+    l++;
+    th *= 0.5;
+  }
+  m->nlev = l + 1;
+  return amg_finish(m);
 }
 
 /* One V-cycle from a zero initial guess: l1-Jacobi pre-smoothing (one sweep),
@@ -891,6 +1000,28 @@ static csr extract(const orc *h, int r, int c) {
   return a;
 }
 
+/* The pressure-temperature operator A_00 of eq:A00 in unknown-wise order:
+ * [A_pp A_pT; A_Tp A_TT], pressure rows (and columns) 0..n-1, temperature
+ * rows n..2n-1, each block on the cell pattern of A. */
+static csr coupled_pT(const orc *h) {
+  int n = h->n, nv = h->nv, nnz = h->rp[n];
+  int sl[2] = {h->o.ip, h->o.iT};
+  csr a;
+  csr_alloc(&a, 2 * n, 2 * n, 4 * nnz);
+  int pos = 0;
+  for (int u = 0; u < 2; u++)
+    for (int i = 0; i < n; i++) {
+      for (int w = 0; w < 2; w++)
+        for (int k = h->rp[i]; k < h->rp[i + 1]; k++) {
+          a.ci[pos] = w * n + h->ci[k];
+          a.v[pos] = h->v[(size_t)k * nv * nv + sl[u] * nv + sl[w]];
+          pos++;
+        }
+      a.rp[u * n + i + 1] = pos;
+    }
+  return a;
+}
+
 /* Decoupling operator G = [I, -D; 0, I] of Section 3.1 for the split of the
  * unknowns into pressure p and the secondary unknowns s (all the others, in
  * slot order).  D is block diagonal with one 1 x (nv-1) block per cell:
@@ -940,9 +1071,9 @@ void *orc_create(int n, int nv, const int *rp, const int *ci, const double *vals
   h->v = vals;
   int st = 0;
   size_t N = (size_t)n;
-  h->bp = (double *)calloc(N + 1, sizeof(double));
+  h->bp = (double *)calloc(2 * N + 1, sizeof(double));  /* [b_p; b_T] for the unknown-based stage */
   h->bt = (double *)calloc(N + 1, sizeof(double));
-  h->xp = (double *)calloc(N + 1, sizeof(double));
+  h->xp = (double *)calloc(2 * N + 1, sizeof(double));
   h->dt = (double *)calloc(N + 1, sizeof(double));
   h->dp = (double *)calloc(N + 1, sizeof(double));
   h->tmp = (double *)calloc(N + 1, sizeof(double));
@@ -968,11 +1099,18 @@ void *orc_create(int n, int nv, const int *rp, const int *ci, const double *vals
           for (int a = 0; a < ns; a++)
             fine.v[k] -= h->dcp[(size_t)i * ns + a] * vals[(size_t)k * nv * nv + sl[a] * nv + o->ip];
     }
-    if (st == 0)
+    if (st == 0 && o->first_stage == ORC_FIRST_CPTR_UAMG) {
+      /* one unknown-based hierarchy on the coupled A_00 (Section 3.4) */
+      csr_free(&fine);
+      st = uamg_setup(&h->amg_p, coupled_pT(h), n, o->theta, o->max_levels, o->coarse_size,
+                      o->seed, o->sweeps, o->smooth_p, o->smooth_p_T < 0 ? o->smooth_p : o->smooth_p_T,
+                      o->smoother);
+    } else if (st == 0) {
       st = amg_setup(&h->amg_p, fine, o->theta, o->max_levels, o->coarse_size, o->seed,
                      o->sweeps, o->smooth_p, o->smoother);
-    else
+    } else {
       csr_free(&fine);
+    }
     h->have_p = 1;
     if (st == 0 && (o->first_stage == ORC_FIRST_CPTR_BLOCK ||
                     o->first_stage == ORC_FIRST_CPTR_LOWER || o->first_stage == ORC_FIRST_CPTR_BD)) {
@@ -1030,6 +1168,8 @@ void orc_destroy(void *hv) {
  *    operator G: d_p = S_p^{-1} (G v)_p, S_p = A_pp - D A_sp, (G v)_p = v_p - D v_s.
  *  CPTR-BD(AMG) (Section 4.4, block-diagonal first stage): d_p = A_pp^{-1} b_p,
  *    d_T = A_TT^{-1} b_T, the couplings A_pT, A_Tp left out.
+ *  CPTR-uAMG (Section 3.4): (d_p; d_T) = A_00^{-1} (b_p; b_T) by one V-cycle of
+ *    the unknown-based hierarchy of the coupled A_00.
  *  Each inverse is one AMG V-cycle. */
 int orc_first_stage(void *hv, const double *v, double *x1) {
   orc *h = (orc *)hv;
@@ -1047,6 +1187,15 @@ int orc_first_stage(void *hv, const double *v, double *x1) {
       for (int i = 0; i < n; i++) h->bp[i] -= h->dcp[(size_t)i * (nv - 1) + q] * v[(size_t)i * nv + k];
       q++;
     }
+  }
+  if (h->o.first_stage == ORC_FIRST_CPTR_UAMG) {
+    memcpy(h->bp + n, h->bt, sizeof(double) * (size_t)n);
+    vcycle(&h->amg_p, 0, h->bp, h->xp);
+    for (int i = 0; i < n; i++) {
+      x1[(size_t)i * nv + ip] = h->xp[i];
+      x1[(size_t)i * nv + iT] = h->xp[n + i];
+    }
+    return 0;
   }
   vcycle(&h->amg_p, 0, h->bp, h->xp);
   if (h->o.first_stage == ORC_FIRST_CPTR_BD) {

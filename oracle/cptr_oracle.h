@@ -23,7 +23,7 @@ extern "C" {
 #endif
 
 enum { ORC_FIRST_NONE = 0, ORC_FIRST_CPTR_BLOCK = 1, ORC_FIRST_CPTR_LOWER = 2,
-       ORC_FIRST_CPR = 3, ORC_FIRST_CPTR_BD = 4 };
+       ORC_FIRST_CPR = 3, ORC_FIRST_CPTR_BD = 4, ORC_FIRST_CPTR_UAMG = 5 };
 enum { ORC_SECOND_NONE = 0, ORC_SECOND_BILU0 = 1, ORC_SECOND_BILU0_MC = 2,
        ORC_SECOND_IDENTITY = 3, ORC_SECOND_EXACT = 4 };
 
@@ -40,7 +40,8 @@ typedef struct {
   int smoother;        /* 0: l1-Jacobi, 1: multicolour Gauss-Seidel (symmetric) */
   const int *ilu_order;/* BILU0 factor order (position -> cell) or NULL */
   const int *ilu_part; /* BILU0 partition (cell -> part, couplings across parts dropped) or NULL */
-  int smooth_p_T;      /* prolongator of the S~_T hierarchy: 1 smoothed, 0 plain, -1 as smooth_p */
+  int smooth_p_T;      /* prolongator of the S~_T (or A_TT) hierarchy, and of the temperature block of
+                          the unknown-based hierarchy: 1 smoothed, 0 plain, -1 as smooth_p */
   int decoupling;      /* CPR first stage only: 0 none, 1 Quasi-IMPES, 2 True-IMPES (Section 3.1) */
   int ilu_level;       /* level of fill of the block ILU second stage: 0 (BILU(0)) or 1 (BILU(1)) */
 } orc_opts;

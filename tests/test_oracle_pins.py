@@ -192,9 +192,12 @@ def test_prolongator_galerkin_and_omega(mid, oracle_lib):
         assert np.abs(Ac - ref).max() <= 1e-12 * np.abs(ref).max()
 
 
+@pytest.mark.parametrize("first", ["cptr", "cptr_uamg"])
 @pytest.mark.parametrize("sweeps", [1, 2])
-def test_two_grid_cycle_is_textbook(mid, sweeps, oracle_lib):
-    o = O.Oracle.from_problem(mid, coarse_size=8, max_levels=2, sweeps=sweeps)
+def test_two_grid_cycle_is_textbook(mid, sweeps, first, oracle_lib):
+    # cptr_uamg: the same cycle on the coupled 2n x 2n operator, l1 sums over
+    # whole coupled rows
+    o = O.Oracle.from_problem(mid, first=first, coarse_size=8, max_levels=2, sweeps=sweeps)
     lv = o.amg_levels(0)
     assert len(lv) == 2
     A = dense_csr(*lv[0]["A"])
@@ -421,6 +424,106 @@ def test_block_diagonal_stage_with_exact_solves(tiny, oracle_lib):
         assert (x1[u::nv] == 0).all()
 
 
+# ---------------------------------------------------------------- unknown-based AMG
+def _blocks(M, np_):
+    return M[:np_, :np_], M[:np_, np_:], M[np_:, :np_], M[np_:, np_:]
+
+
+def test_unknown_based_fine_operator_is_A00(tiny, oracle_lib):
+    # the unknown-wise ordering of Section 3.4: [A_pp A_pT; A_Tp A_TT]
+    A, App, ApT, ATp, ATT, S = _dense_Ainv00(tiny, True)
+    o = O.Oracle.from_problem(tiny, first="cptr_uamg", second="none", coarse_size=8)
+    lv = o.amg_levels(0)
+    assert np.array_equal(dense_csr(*lv[0]["A"]), np.block([[App, ApT], [ATp, ATT]]))
+    assert o.amg_levels(1) == []
+
+
+@pytest.mark.parametrize("smooth_p_T", [False, True])
+def test_unknown_based_hierarchy_coarsens_each_unknown_alone(mid, smooth_p_T, oracle_lib):
+    # Section 3.4: coarsening and interpolation of each unknown come from its own
+    # diagonal block, so the aggregates, the prolongator blocks and the diagonal
+    # blocks of every coarse operator are those of two scalar hierarchies on
+    # A_pp and A_TT (the block-diagonal stage's), while the coupling blocks of
+    # the coarse operators are P_p^T A_pT P_T and P_T^T A_Tp P_p.
+    kw = dict(second="none", coarse_size=0, max_levels=3, smooth_p_T=smooth_p_T)
+    u = O.Oracle.from_problem(mid, first="cptr_uamg", **kw).amg_levels(0)
+    bd = O.Oracle.from_problem(mid, first="cptr_bd", **kw)
+    hp, hT = bd.amg_levels(0), bd.amg_levels(1)
+    assert len(u) == len(hp) == len(hT) == 3
+    for l in range(3):
+        np_ = hp[l]["n"]
+        assert u[l]["n"] == np_ + hT[l]["n"]
+        Au = dense_csr(*u[l]["A"])
+        Upp, UpT, UTp, UTT = _blocks(Au, np_)
+        for got, ref in ((Upp, dense_csr(*hp[l]["A"])), (UTT, dense_csr(*hT[l]["A"]))):
+            assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max()
+        if l == 0:
+            continue
+        Pp = dense_csr(*hp[l - 1]["P"], ncol=hp[l]["n"])
+        PT = dense_csr(*hT[l - 1]["P"], ncol=hT[l]["n"])
+        Ap = dense_csr(*u[l - 1]["A"])
+        _, fpT, fTp, _ = _blocks(Ap, hp[l - 1]["n"])
+        for got, ref in ((UpT, Pp.T @ fpT @ PT), (UTp, PT.T @ fTp @ Pp)):
+            assert np.abs(ref).max() > 0
+            assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
+    for l in range(2):
+        np_, nap = hp[l]["n"], hp[l + 1]["n"]
+        aT = hT[l]["agg"]
+        assert np.array_equal(u[l]["agg"][:np_], hp[l]["agg"])
+        assert np.array_equal(u[l]["agg"][np_:], np.where(aT >= 0, aT + nap, -1))
+        Pu = dense_csr(*u[l]["P"], ncol=u[l + 1]["n"])
+        Pp = dense_csr(*hp[l]["P"], ncol=nap)
+        PT = dense_csr(*hT[l]["P"], ncol=hT[l + 1]["n"])
+        assert np.array_equal(Pu, np.block([[Pp, np.zeros((np_, PT.shape[1]))],
+                                            [np.zeros((PT.shape[0], nap)), PT]]))
+        assert u[l]["omega"] == hp[l]["omega"]
+
+
+def test_unknown_based_stage_without_coupling_is_block_diagonal(mid, oracle_lib):
+    # with A_pT = A_Tp = 0 the coupled hierarchy splits into the two scalar
+    # ones, and CPTR-uAMG reduces to CPTR-BD(AMG) (Section 4.4 footnote: the two
+    # differ only through the coupling blocks in the coarse correction)
+    nv = mid.nv
+    v = mid.vals.reshape(-1, nv, nv).copy()
+    v[:, 0, nv - 1] = 0.0
+    v[:, nv - 1, 0] = 0.0
+    pr = type(mid)(shape=mid.shape, nv=nv, row_ptr=mid.row_ptr, col_idx=mid.col_idx,
+                   vals=np.ascontiguousarray(v.reshape(-1)), st_row_ptr=mid.st_row_ptr,
+                   st_col_idx=mid.st_col_idx, st_vals=mid.st_vals, b=mid.b, b_star=mid.b_star,
+                   x_true=mid.x_true, meta=mid.meta)
+    kw = dict(second="none", coarse_size=0, max_levels=3)
+    u = O.Oracle.from_problem(pr, first="cptr_uamg", **kw)
+    bd = O.Oracle.from_problem(pr, first="cptr_bd", **kw)
+    r = np.random.default_rng(8).standard_normal(mid.n * nv)
+    want = bd.first_stage(r)
+    got = u.first_stage(r)
+    assert np.allclose(got, want, rtol=1e-11, atol=1e-12 * np.abs(want).max())
+    # and with the coupling present the two stages differ
+    u2 = O.Oracle.from_problem(mid, first="cptr_uamg", **kw).first_stage(r)
+    bd2 = O.Oracle.from_problem(mid, first="cptr_bd", **kw).first_stage(r)
+    assert np.abs(u2 - bd2).max() > 1e-3 * np.abs(bd2).max()
+
+
+def test_single_level_unknown_based_stage_is_A00_inverse(tiny, oracle_lib):
+    A, App, ApT, ATp, ATT, S = _dense_Ainv00(tiny, True)
+    n, nv = tiny.n, tiny.nv
+    o = O.Oracle.from_problem(tiny, first="cptr_uamg", second="none", coarse_size=10_000)
+    assert len(o.amg_levels(0)) == 1
+    v = np.random.default_rng(9).standard_normal(n * nv)
+    x1 = o.first_stage(v)
+    want = np.linalg.solve(np.block([[App, ApT], [ATp, ATT]]),
+                           np.concatenate([v[0::nv], v[nv - 1::nv]]))
+    got = np.concatenate([x1[0::nv], x1[nv - 1::nv]])
+    assert np.allclose(got, want, rtol=1e-10, atol=1e-10 * np.abs(want).max())
+    for k in range(1, nv - 1):
+        assert (x1[k::nv] == 0).all()
+
+
+def test_unknown_based_stage_rejects_decoupling(tiny, oracle_lib):
+    with pytest.raises(RuntimeError):
+        O.Oracle.from_problem(tiny, first="cptr_uamg", second="none", decoupling="ti")
+
+
 def _local_secondary(pr, zero):
     """Values of pr with the secondary (non-pressure, pressure in slot 0)
     columns (zero = "cols") or rows (zero = "rows") of every off-diagonal
@@ -496,7 +599,7 @@ def _vcycle_matrix(o, which, n):
     return _columns(lambda e: o.vcycle(which, e), n)
 
 
-@pytest.mark.parametrize("first", ["cptr", "cptr_lower", "cpr", "cptr_bd"])
+@pytest.mark.parametrize("first", ["cptr", "cptr_lower", "cpr", "cptr_bd", "cptr_uamg"])
 def test_first_stage_product_form(mid, first, oracle_lib):
     # eq:Aschur as a product of its three factors, each inverse replaced by the
     # (linear) V-cycle operator; CPR: R_p^T V(A_pp) R_p (Section 3.1).
@@ -505,13 +608,16 @@ def test_first_stage_product_form(mid, first, oracle_lib):
     A = dense_bsr(mid.row_ptr, mid.col_idx, mid.vals, nv)
     ApT = A[0::nv, nv - 1::nv]
     ATp = A[nv - 1::nv, 0::nv]
-    Vp = _vcycle_matrix(o, 0, n)
+    Vp = _vcycle_matrix(o, 0, n) if first != "cptr_uamg" else None
     I, Z = np.eye(n), np.zeros((n, n))
     if first == "cpr":
         M1 = np.block([[Vp, Z], [Z, Z]])
     elif first == "cptr_bd":
         # block-diagonal first stage (Section 4.4): V-cycles on A_pp and A_TT
         M1 = np.block([[Vp, Z], [Z, _vcycle_matrix(o, 1, n)]])
+    elif first == "cptr_uamg":
+        # unknown-based stage (Section 3.4): one V-cycle on the coupled A_00
+        M1 = _vcycle_matrix(o, 0, 2 * n)
     else:
         Vs = _vcycle_matrix(o, 1, n)
         left = np.block([[I, -Vp @ ApT], [Z, I]]) if first == "cptr" else np.eye(2 * n)
