@@ -40,7 +40,8 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "learned_layer_traffic.json")
 LAYER_SRC = os.path.join(ROOT, "paper_1907_04229_amd", "csrc", "learned_kernels.hip")
-FIRST_NAME = {"cptr": "CPTR-Block", "cptr_lower": "CPTR-BlockLower", "cpr": "CPR", "cptr_bd": "CPTR-BD"}
+FIRST_NAME = {"cptr": "CPTR-Block", "cptr_lower": "CPTR-BlockLower", "cpr": "CPR", "cptr_bd": "CPTR-BD",
+              "cptr_uamg": "CPTR-uAMG"}
 TRAIN_SEED0 = 100  # --train-systems N takes the seeds 100 .. 100 + N - 1
 VAL_SEEDS = (190, 191)  # validation fields of the model selection, at full size
 HELD_OUT_SEEDS = (200, 201, 202, 203, 204)
@@ -257,7 +258,7 @@ def main():
     ap.add_argument("--train-systems", type=int, default=8)
     ap.add_argument("--train-pairs", type=int, default=48)
     ap.add_argument("--train-batch", type=int, default=8)
-    ap.add_argument("--first", default="cptr", choices=["cptr", "cptr_lower", "cpr", "cptr_bd"],
+    ap.add_argument("--first", default="cptr", choices=["cptr", "cptr_lower", "cpr", "cptr_bd", "cptr_uamg"],
                     help="first stage of the learned and BILU(0)-FP32 legs (plain FP64 CPTR stays cptr)")
     ap.add_argument("--cpu-iters", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -353,13 +354,16 @@ def main():
         # context: the same stages behind the CPR first stage (one A_pp V-cycle)
         # (also with the True-IMPES decoupling operator, Section 3.1), behind
         # the block-diagonal CPTR-BD(AMG) first stage (V-cycles on A_pp and
-        # A_TT, Section 4.4), and CPTR with the BILU(1) second stage
+        # A_TT, Section 4.4), behind CPTR-uAMG (one V-cycle of the unknown-based
+        # hierarchy of A_00, Section 3.4), and CPTR with the BILU(1) second stage
         for tag, first, opt, mdl_needed in (
                 ("fp64_cpr_bilu0", "cpr", dict(precision="fp64", second_stage="bilu0"), False),
                 ("fp32_cpr_bilu0_mc", "cpr", dict(precision="fp32", second_stage="bilu0_mc"), False),
                 ("fp32_cpr_learned_untrained", "cpr", dict(precision="fp32", second_stage="learned"), True),
                 ("fp64_cptr_bd_bilu0", "cptr_bd", dict(precision="fp64", second_stage="bilu0"), False),
                 ("fp32_cptr_bd_bilu0_mc", "cptr_bd", dict(precision="fp32", second_stage="bilu0_mc"), False),
+                ("fp64_cptr_uamg_bilu0", "cptr_uamg", dict(precision="fp64", second_stage="bilu0"), False),
+                ("fp32_cptr_uamg_bilu0_mc", "cptr_uamg", dict(precision="fp32", second_stage="bilu0_mc"), False),
                 ("fp64_cpr_ti_bilu0", "cpr", dict(precision="fp64", second_stage="bilu0", decoupling="ti"),
                  False),
                 ("fp32_cpr_ti_bilu0_mc", "cpr", dict(precision="fp32", second_stage="bilu0_mc", decoupling="ti"),

@@ -61,6 +61,11 @@ extern "C" {
 #define CPTR_FIRST_CPR 3         /* CPR: x1 = R_p^T V(A_pp) R_p v */
 #define CPTR_FIRST_BD 4          /* CPTR-BD(AMG) (Section 4.4): block-diagonal first stage,
                                     d_p = V(A_pp) b_p, d_T = V(A_TT) b_T (couplings left out) */
+#define CPTR_FIRST_UAMG 5        /* CPTR-uAMG (Section 3.4): (d_p; d_T) = V(A_00) (b_p; b_T), one
+                                    V-cycle of an unknown-based hierarchy of the coupled
+                                    pressure-temperature block in unknown-wise order (each unknown
+                                    coarsened on its own diagonal block, couplings kept in the
+                                    Galerkin coarse operators) */
 
 /* Decoupling operators G = [I, -D; 0, I] for the CPR first stage (Section 3.1;
  * p = pressure, s = every other unknown in slot order, D one 1 x (nv-1) block
@@ -109,7 +114,8 @@ typedef struct {
   int amg_sweeps;        /* l1-Jacobi sweeps before and after the coarse correction (2) */
   int amg_smooth_p;      /* 1 smoothed aggregation, 0 plain aggregation (1) */
   int amg_smooth_p_T;    /* the same for the second hierarchy alone (S~_T; A_TT for
-                            CPTR_FIRST_BD); -1: as amg_smooth_p (0).
+                            CPTR_FIRST_BD; the temperature block of the CPTR_FIRST_UAMG
+                            hierarchy); -1: as amg_smooth_p (0).
                             Plain aggregation keeps the S~_T V-cycle convergent where the
                             smoothed prolongator does not (rows that are not diagonally
                             dominant, three-phase systems) and needs fewer FGMRES iterations
@@ -173,7 +179,8 @@ typedef struct cptr_handle cptr_handle;
 void cptr_default_options(cptr_options *opt);
 
 /* Build the preconditioner for A (first stage: sub-block extraction eq:A00,
- * two AMG hierarchies for A_pp and S~_T -- A_TT for CPTR_FIRST_BD; second
+ * two AMG hierarchies for A_pp and S~_T -- A_TT for CPTR_FIRST_BD; one on the
+ * coupled 2n x 2n A_00 for CPTR_FIRST_UAMG; second
  * stage: BILU(0) factors).
  *   out   receives the handle (NULL on failure).
  *   A     must stay alive and unchanged until cptr_destroy: A->vals (FP64) is
@@ -200,7 +207,8 @@ int cptr_first_stage(cptr_handle *h, const double *v, double *x1, void *stream);
 
 /* One AMG V-cycle from a zero initial guess on A_pp (which = 0) or the
  * second hierarchy (which = 1: S~_T, or A_TT with CPTR_FIRST_BD), in the
- * handle's precision: x = V(b).  Device FP64 [n].
+ * handle's precision: x = V(b).  Device FP64 [n]; with CPTR_FIRST_UAMG,
+ * which = 0 is the coupled A_00 hierarchy and b, x are [2n] (p rows, then T).
  * Asynchronous. */
 int cptr_vcycle(cptr_handle *h, int which, const double *b, double *x, void *stream);
 

@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(_HERE, "libcptr.so")
 
 CPTR_OK = 0
 CPTR_NOT_CONVERGED = 1
-FIRST = {"none": 0, "cptr": 1, "cptr_lower": 2, "cpr": 3, "cptr_bd": 4}
+FIRST = {"none": 0, "cptr": 1, "cptr_lower": 2, "cpr": 3, "cptr_bd": 4, "cptr_uamg": 5}
 SECOND = {"none": 0, "bilu0": 1, "bilu0_mc": 2, "identity": 3, "learned": 4}
 PRECISION = {"fp64": 0, "fp32": 1}
 DECOUPLING = {"none": 0, "qi": 1, "ti": 2}

@@ -724,9 +724,14 @@ struct Precond : PrecondBase {
     if (fs == CPTR_FIRST_NONE) return;
     T *bpp = devp<T>(bp), *btt = devp<T>(bt), *xpp = devp<T>(xp), *dTT = devp<T>(dT),
       *dpp = devp<T>(dp), *t = devp<T>(tmp);
+    if (fs == CPTR_FIRST_UAMG) btt = bpp + n;  // (b_p; b_T) in unknown-wise order
     hipLaunchKernelGGL((k_restrict_pT<T>), dim3(nblk(n)), dim3(kBlock), 0, st, n, op.nv, ip, iT, slots,
                        dcp.p ? (const T *)devp<T>(dcp) : (const T *)nullptr, bpp, fs == CPTR_FIRST_CPR ? (T *)nullptr : btt);
     LAUNCH_CHECK();
+    if (fs == CPTR_FIRST_UAMG) {  // unknown-based: (d_p; d_T) = V(A_00) (b_p; b_T)
+      amg_p.cycle(st, bpp, dpp);
+      return;
+    }
     if (fs == CPTR_FIRST_CPR) {
       amg_p.cycle(st, bpp, dpp);
       return;
@@ -751,6 +756,7 @@ struct Precond : PrecondBase {
   const T *x1p() const { return op.o.first_stage == CPTR_FIRST_NONE ? nullptr : devp<T>(dp); }
   const T *x1T() const {
     int fs = op.o.first_stage;
+    if (fs == CPTR_FIRST_UAMG) return devp<T>(dp) + op.n;
     return (fs == CPTR_FIRST_NONE || fs == CPTR_FIRST_CPR) ? nullptr : devp<T>(dT);
   }
 
@@ -840,7 +846,7 @@ struct Precond : PrecondBase {
   void vcycle(hipStream_t st, int which, const double *b, double *x) override {
     const AmgDev<T> &a = which == 0 ? amg_p : amg_s;
     if (which == 1 && !have_s) throw Error{CPTR_ERR_INVALID_ARG, "no S~_T hierarchy in this handle"};
-    const int n = op.n;
+    const int n = a.lev[0]->n;  // 2n for the coupled unknown-based hierarchy
     T *bb = devp<T>(tmp), *xx = devp<T>(xp);
     hipLaunchKernelGGL((k_convert<double, T>), dim3(sgrid(n)), dim3(kBlock), 0, st, b, bb, (size_t)n);
     a.cycle(st, bb, xx);
@@ -928,7 +934,10 @@ static void build_precond(cptr_handle *h, const std::vector<int> &rp, const std:
     for (int k = 0; k < nnzb; k++) a.v[k] = vals[((size_t)k * nv + r) * nv + c];
     return a;
   };
-  for (DevMem *m : {&P.bp, &P.bt, &P.xp, &P.dT, &P.dp, &P.tmp, &P.zeros}) m->alloc(n * s);
+  for (DevMem *m : {&P.bt, &P.dT, &P.zeros}) m->alloc(n * s);
+  // the unknown-based stage works on (p; T) vectors of 2n
+  const size_t nu = o.first_stage == CPTR_FIRST_UAMG ? 2 * (size_t)n : n;
+  for (DevMem *m : {&P.bp, &P.xp, &P.dp, &P.tmp}) m->alloc(nu * s);
   P.b1.alloc((size_t)n * nv * s);
   hipLaunchKernelGGL((k_fill<T>), dim3(sgrid(n)), dim3(kBlock), 0, 0, devp<T>(P.zeros), (size_t)n, T(0));
   LAUNCH_CHECK();
@@ -988,13 +997,34 @@ static void build_precond(cptr_handle *h, const std::vector<int> &rp, const std:
       upload(P.dcp, Dt);
       bytes += (double)n * ns * (s + 8);  // D and v_s in the restriction
     }
-    amg_build(pp, prm, hp, agg_p);
+    AmgParams prm_s = prm;  // the second hierarchy, or the temperature block of the coupled one
+    if (o.amg_smooth_p_T >= 0) prm_s.smooth_p = o.amg_smooth_p_T;
+    if (o.first_stage == CPTR_FIRST_UAMG) {
+      // Section 3.4: A_00 = [A_pp A_pT; A_Tp A_TT] in unknown-wise order, one
+      // hierarchy coarsened per unknown
+      HostCSR c;
+      c.nr = c.nc = 2 * n;
+      c.rp.assign(2 * n + 1, 0);
+      c.ci.reserve(4 * (size_t)nnzb);
+      c.v.reserve(4 * (size_t)nnzb);
+      const int sl[2] = {o.ip, o.iT};
+      for (int u = 0; u < 2; u++)
+        for (int i = 0; i < n; i++) {
+          for (int w = 0; w < 2; w++)
+            for (int k = rp[i]; k < rp[i + 1]; k++) {
+              c.ci.push_back(w * n + ci[k]);
+              c.v.push_back(vals[((size_t)k * nv + sl[u]) * nv + sl[w]]);
+            }
+          c.rp[u * n + i + 1] = int(c.ci.size());
+        }
+      uamg_build(c, n, prm, prm_s, hp, agg_p);
+    } else {
+      amg_build(pp, prm, hp, agg_p);
+    }
     P.amg_p.build(hp, o.amg_sweeps, o.scalar_dia != 0);
-    if (o.first_stage != CPTR_FIRST_CPR) {
+    if (o.first_stage != CPTR_FIRST_CPR && o.first_stage != CPTR_FIRST_UAMG) {
       // the second hierarchy: S~_T, or A_TT for the block-diagonal stage
       AmgHost hs;
-      AmgParams prm_s = prm;
-      if (o.amg_smooth_p_T >= 0) prm_s.smooth_p = o.amg_smooth_p_T;
       if (o.first_stage == CPTR_FIRST_BD)
         amg_build(sub(o.iT, o.iT), prm_s, hs, agg_s);
       else
@@ -1119,7 +1149,7 @@ static void validate_and_fetch(const cptr_bsr *A, const cptr_csr *S, const cptr_
     throw Error{CPTR_ERR_INVALID_ARG, "invalid p/T slots"};
   if (o.amg_max_levels < 1 || o.amg_coarse_size < 1 || o.amg_sweeps < 1 || !(o.amg_theta >= 0.0))
     throw Error{CPTR_ERR_INVALID_ARG, "invalid AMG options"};
-  if (o.first_stage < 0 || o.first_stage > 4) throw Error{CPTR_ERR_INVALID_ARG, "invalid first stage"};
+  if (o.first_stage < 0 || o.first_stage > 5) throw Error{CPTR_ERR_INVALID_ARG, "invalid first stage"};
   if (o.decoupling < 0 || o.decoupling > 2) throw Error{CPTR_ERR_INVALID_ARG, "invalid decoupling"};
   if (o.ilu_level != 0 && o.ilu_level != 1) throw Error{CPTR_ERR_UNSUPPORTED, "ilu_level must be 0 or 1"};
   if (o.decoupling != 0 && o.first_stage != CPTR_FIRST_CPR)

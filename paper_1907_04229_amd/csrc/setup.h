@@ -53,6 +53,16 @@ struct AmgHost {
 void amg_build(const HostCSR &fine, const AmgParams &prm, AmgHost &out,
                const std::vector<std::vector<int>> *fixed = nullptr);
 
+// Unknown-based hierarchy (Section 3.4) of the pressure-temperature operator
+// in unknown-wise order: rows 0 .. np-1 pressure, np .. n-1 temperature.  Each
+// unknown is coarsened on its own diagonal block exactly as amg_build does
+// (prm_p for pressure, prm_T's smooth_p for temperature), P = diag(P_p, P_T),
+// and the Galerkin coarse operator keeps the couplings; coarse unknowns stay in
+// unknown-wise order, temperature aggregates numbered after the pressure ones.
+// `fixed` as for amg_build (aggregates in that numbering).
+void uamg_build(const HostCSR &fine, int np, const AmgParams &prm_p, const AmgParams &prm_T, AmgHost &out,
+                const std::vector<std::vector<int>> *fixed = nullptr);
+
 // Block ILU(0) in a given row order, FP64 on the host.
 struct IluHost {
   int n = 0, nv = 0, ncolor = 0;

@@ -1,7 +1,9 @@
 // Smoothed-aggregation AMG setup (host, FP64).
 //
 // The hierarchy approximates A_pp^{-1} and S~_T^{-1} in the block
-// preconditioner of Section 3.3 (the paper uses one AMG V-cycle per inverse).
+// preconditioner of Section 3.3 (the paper uses one AMG V-cycle per inverse),
+// and, built per unknown, the coupled A_00^{-1} of the unknown-based first
+// stage (Section 3.4).
 // Aggregation follows Vanek, Mandel and Brezina (1996) with a distance-2
 // maximal independent set computed in parallel rounds (each undecided node
 // whose priority is the largest among the undecided nodes within distance 2
@@ -322,7 +324,107 @@ std::vector<double> dense_inverse(const HostCSR &a) {
   return inv;
 }
 
+// the square diagonal block of rows and columns r0 .. r1-1, renumbered from 0
+HostCSR diag_block(const HostCSR &a, int r0, int r1) {
+  HostCSR b;
+  b.nr = b.nc = r1 - r0;
+  b.rp.assign(b.nr + 1, 0);
+  for (int i = r0; i < r1; i++) {
+    for (int k = a.rp[i]; k < a.rp[i + 1]; k++)
+      if (a.ci[k] >= r0 && a.ci[k] < r1) {
+        b.ci.push_back(a.ci[k] - r0);
+        b.v.push_back(a.v[k]);
+      }
+    b.rp[i - r0 + 1] = int(b.ci.size());
+  }
+  return b;
+}
+
+void finish(AmgHost &out) {
+  const HostCSR &c = out.lev.back().A;
+  if (c.nr > 4096) throw Error{CPTR_ERR_SETUP, "AMG coarsening stalled above 4096 rows"};
+  out.coarse_inv = dense_inverse(c);
+}
+
 }  // namespace
+
+void uamg_build(const HostCSR &fine, int np, const AmgParams &prm_p, const AmgParams &prm_T, AmgHost &out,
+                const std::vector<std::vector<int>> *fixed) {
+  if (np < 0 || np > fine.nr) throw Error{CPTR_ERR_INVALID_ARG, "unknown-based AMG: bad pressure block size"};
+  out.lev.clear();
+  out.lev.emplace_back();
+  out.lev[0].A = fine;
+  double theta = prm_p.theta;
+  const int max_levels = std::min(prm_p.max_levels, 16);
+  int npl = np;  // pressure rows of the current level
+  for (;;) {
+    const size_t l = out.lev.size() - 1;
+    if (fixed ? l >= fixed->size()
+              : (out.lev.back().A.nr <= prm_p.coarse_size || (int)out.lev.size() >= max_levels))
+      break;
+    AmgLevelHost &L = out.lev.back();
+    const int n = L.A.nr;
+    const int lo[2] = {0, npl}, hi[2] = {npl, n};
+    HostCSR blk[2];
+    std::vector<int> ab[2];
+    int na[2] = {0, 0};
+    for (int u = 0; u < 2; u++) blk[u] = diag_block(L.A, lo[u], hi[u]);
+    if (fixed) {
+      const std::vector<int> &f = (*fixed)[l];
+      if ((int)f.size() != n) throw Error{CPTR_ERR_SETUP, "aggregates do not match the level size"};
+      int top[2] = {0, 0};
+      for (int i = 0; i < n; i++) top[i >= npl] = std::max(top[i >= npl], f[i] + 1);
+      na[0] = top[0];
+      na[1] = std::max(0, top[1] - na[0]);
+      for (int u = 0; u < 2; u++) {
+        ab[u].resize(hi[u] - lo[u]);
+        for (int i = lo[u]; i < hi[u]; i++) {
+          const int a = f[i] < 0 ? -1 : f[i] - (u ? na[0] : 0);
+          if (a < -1 || a >= na[u]) throw Error{CPTR_ERR_SETUP, "aggregates mix the unknowns"};
+          ab[u][i - lo[u]] = a;
+        }
+      }
+    } else {
+      for (int u = 0; u < 2; u++) {
+        Graph g = strength(blk[u], theta);
+        na[u] = aggregate(g, hi[u] - lo[u], prm_p.seed, ab[u]);
+      }
+      if (na[0] + na[1] >= n) break;  // no coarsening possible
+    }
+    HostCSR pb[2];
+    double om[2] = {0.0, 0.0};
+    for (int u = 0; u < 2; u++) {
+      const bool smooth = (u == 0 ? prm_p.smooth_p : prm_T.smooth_p) && hi[u] > lo[u];
+      pb[u] = prolongator(blk[u], ab[u], na[u], smooth, om[u]);
+    }
+    // P = diag(P_p, P_T): temperature columns and aggregates shifted by na_p
+    L.agg.assign(n, -1);
+    L.P = HostCSR();
+    L.P.nr = n;
+    L.P.nc = na[0] + na[1];
+    L.P.rp.assign(n + 1, 0);
+    for (int u = 0; u < 2; u++) {
+      const int off = u == 0 ? 0 : na[0];
+      for (int i = 0; i < hi[u] - lo[u]; i++) {
+        if (ab[u][i] >= 0) L.agg[lo[u] + i] = ab[u][i] + off;
+        for (int k = pb[u].rp[i]; k < pb[u].rp[i + 1]; k++) {
+          L.P.ci.push_back(pb[u].ci[k] + off);
+          L.P.v.push_back(pb[u].v[k]);
+        }
+        L.P.rp[lo[u] + i + 1] = L.P.nnz();
+      }
+    }
+    L.omega = om[0];
+    L.R = transpose(L.P);
+    HostCSR t = multiply(L.A, L.P);
+    HostCSR ac = multiply(L.R, t);
+    out.lev.emplace_back();
+    out.lev.back().A = std::move(ac);
+    npl = na[0];
+    theta *= 0.5;
+  }
+  finish(out);
+}
 
 void amg_build(const HostCSR &fine, const AmgParams &prm, AmgHost &out,
                const std::vector<std::vector<int>> *fixed) {
@@ -360,9 +462,7 @@ void amg_build(const HostCSR &fine, const AmgParams &prm, AmgHost &out,
     out.lev.back().A = std::move(ac);
     theta *= 0.5;
   }
-  const HostCSR &c = out.lev.back().A;
-  if (c.nr > 4096) throw Error{CPTR_ERR_SETUP, "AMG coarsening stalled above 4096 rows"};
-  out.coarse_inv = dense_inverse(c);
+  finish(out);
 }
 
 }  // namespace cptr

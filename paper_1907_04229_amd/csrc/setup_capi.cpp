@@ -47,6 +47,35 @@ void *cptrh_amg_build(int n, const int *rp, const int *ci, const double *v, doub
   return b;
 }
 
+// The unknown-based hierarchy of a coupled operator in unknown-wise order
+// (rows 0 .. np-1 pressure, the rest temperature).
+void *cptrh_uamg_build(int n, int np, const int *rp, const int *ci, const double *v, double theta,
+                       int max_levels, int coarse_size, unsigned seed, int smooth_p, int smooth_p_T,
+                       int *status) {
+  auto *b = new AmgBox();
+  try {
+    HostCSR a;
+    a.nr = a.nc = n;
+    a.rp.assign(rp, rp + n + 1);
+    a.ci.assign(ci, ci + rp[n]);
+    a.v.assign(v, v + rp[n]);
+    AmgParams p;
+    p.theta = theta;
+    p.max_levels = max_levels;
+    p.coarse_size = coarse_size;
+    p.seed = seed;
+    p.smooth_p = smooth_p;
+    AmgParams pT = p;
+    pT.smooth_p = smooth_p_T;
+    uamg_build(a, np, p, pT, b->h);
+    *status = 0;
+  } catch (const Error &e) {
+    g_err = e.msg;
+    *status = e.code;
+  }
+  return b;
+}
+
 int cptrh_amg_nlevels(void *h) { return (int)static_cast<AmgBox *>(h)->h.lev.size(); }
 
 int cptrh_amg_level_info(void *h, int l, int *n, int *nnz, int *pnnz) {

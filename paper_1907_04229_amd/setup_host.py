@@ -20,6 +20,9 @@ def load():
         L.cptrh_amg_build.restype = vp
         L.cptrh_amg_build.argtypes = [C.c_int, ip, ip, dp, C.c_double, C.c_int, C.c_int, C.c_uint,
                                       C.c_int, ip]
+        L.cptrh_uamg_build.restype = vp
+        L.cptrh_uamg_build.argtypes = [C.c_int, C.c_int, ip, ip, dp, C.c_double, C.c_int, C.c_int,
+                                       C.c_uint, C.c_int, C.c_int, ip]
         L.cptrh_amg_nlevels.argtypes = [vp]
         L.cptrh_amg_level_info.argtypes = [vp, C.c_int, ip, ip, ip]
         L.cptrh_amg_get.argtypes = [vp, C.c_int, ip, ip, ip, dp, ip, ip, dp, dp]
@@ -50,6 +53,23 @@ def amg_levels(row_ptr, col, vals, theta=0.08, max_levels=10, coarse_size=512, s
     st = C.c_int(0)
     h = L.cptrh_amg_build(rp.size - 1, _i(rp), _i(ci), _d(v), theta, max_levels, coarse_size,
                           seed, int(bool(smooth_p)), C.byref(st))
+    return _levels(L, h, st)
+
+
+def uamg_levels(row_ptr, col, vals, np_, theta=0.08, max_levels=10, coarse_size=512, seed=0,
+                smooth_p=True, smooth_p_T=True):
+    """The unknown-based hierarchy of a coupled operator whose first np_ rows are pressure."""
+    rp = np.ascontiguousarray(row_ptr, np.int32)
+    ci = np.ascontiguousarray(col, np.int32)
+    v = np.ascontiguousarray(vals, np.float64)
+    L = load()
+    st = C.c_int(0)
+    h = L.cptrh_uamg_build(rp.size - 1, np_, _i(rp), _i(ci), _d(v), theta, max_levels, coarse_size,
+                           seed, int(bool(smooth_p)), int(bool(smooth_p_T)), C.byref(st))
+    return _levels(L, h, st)
+
+
+def _levels(L, h, st):
     try:
         if st.value != 0:
             raise RuntimeError(f"setup failed ({st.value}): {L.cptrh_last_error().decode()}")

@@ -69,3 +69,20 @@ def test_status_strings_and_defaults(lib):
     h = ctypes.c_void_p()
     assert L.cptr_setup(ctypes.byref(h), None, None, None, None) == -1
     assert b"null" in L.cptr_last_error()
+
+
+def test_binding_stage_codes_match_the_header():
+    """The binding's names for the first and second stages and the decoupling
+    operators carry the values the header defines."""
+    from paper_1907_04229_amd import cptr
+    text = open(os.path.join(ROOT, "include", "cptr.h")).read()
+    defs = {m.group(1): int(m.group(2)) for m in re.finditer(r"#define\s+(CPTR_\w+)\s+(-?\d+)", text)}
+    first = {"none": "NONE", "cptr": "BLOCK", "cptr_lower": "BLOCK_LOWER", "cpr": "CPR",
+             "cptr_bd": "BD", "cptr_uamg": "UAMG"}
+    assert set(first) == set(cptr.FIRST)
+    for k, v in first.items():
+        assert cptr.FIRST[k] == defs["CPTR_FIRST_" + v], k
+    for k, v in cptr.DECOUPLING.items():
+        assert v == defs["CPTR_DECOUPLE_" + k.upper()], k
+    for k, v in cptr.SECOND.items():
+        assert v == defs["CPTR_SECOND_" + k.upper()], k

@@ -107,7 +107,7 @@ def test_matvec_sliced_fp64(name):
 
 # ---------------------------------------------------------------- setup integers
 @pytest.mark.parametrize("name", ["ragged", "three", "small"])
-@pytest.mark.parametrize("first", ["cptr", "cptr_bd"])
+@pytest.mark.parametrize("first", ["cptr", "cptr_bd", "cptr_uamg"])
 def test_aggregates_and_schedule_bit_exact(name, first):
     banner(f"setup integers {name} {first}")
     pr = prob(name)
@@ -133,16 +133,17 @@ def test_aggregates_and_schedule_bit_exact(name, first):
 
 # ---------------------------------------------------------------- one application
 @pytest.mark.parametrize("name", ["ragged", "three", "small", "chain", "single"])
-@pytest.mark.parametrize("first", ["cptr", "cptr_lower", "cpr", "cptr_bd"])
+@pytest.mark.parametrize("first", ["cptr", "cptr_lower", "cpr", "cptr_bd", "cptr_uamg"])
 def test_vcycle_and_first_stage_fp64(name, first):
     banner(f"first stage fp64 {name} {first}")
     pr = prob(name)
     s = solver(pr, precision="fp64", first_stage=first, second_stage="none", amg_coarse_size=16)
     o = O.Oracle.from_problem(pr, first=first, second="none", coarse_size=16)
     rng = np.random.default_rng(2)
-    for which in ((0, 1) if first != "cpr" else (0,)):
-        b = rng.standard_normal(pr.n)
-        x = torch.empty(pr.n, dtype=torch.float64, device=DEV)
+    for which in ((0, 1) if first not in ("cpr", "cptr_uamg") else (0,)):
+        m = 2 * pr.n if first == "cptr_uamg" else pr.n  # the coupled (p; T) hierarchy
+        b = rng.standard_normal(m)
+        x = torch.empty(m, dtype=torch.float64, device=DEV)
         cptr.cptr_vcycle(s.h, which, dev(b), x)
         torch.cuda.synchronize()
         assert relerr(x.cpu().numpy(), o.vcycle(which, b)) <= 1e-10
@@ -218,7 +219,7 @@ def test_diagonal_storage(name):
 @pytest.mark.parametrize("first,second", [("cptr", "bilu0"), ("cptr", "bilu0_mc"),
                                           ("cpr", "bilu0"), ("none", "bilu0"),
                                           ("cptr", "identity"), ("cptr_lower", "bilu0_mc"),
-                                          ("cptr_bd", "bilu0_mc")])
+                                          ("cptr_bd", "bilu0_mc"), ("cptr_uamg", "bilu0")])
 def test_apply_fp64(name, first, second):
     banner(f"apply fp64 {name} {first}+{second}")
     pr = prob(name)
@@ -326,7 +327,8 @@ def test_bilu1_fp64(name, second):
 # ---------------------------------------------------------------- FGMRES
 @pytest.mark.parametrize("name", ["ragged", "three", "small", "chain"])
 @pytest.mark.parametrize("first,second", [("cptr", "bilu0"), ("cptr", "bilu0_mc"),
-                                          ("cpr", "bilu0_mc"), ("cptr_bd", "bilu0")])
+                                          ("cpr", "bilu0_mc"), ("cptr_bd", "bilu0"),
+                                          ("cptr_uamg", "bilu0_mc")])
 @pytest.mark.parametrize("graph", [1, 0])
 def test_fgmres_fp64_matches_oracle(name, first, second, graph):
     banner(f"fgmres fp64 {name} {first}+{second} graph={graph}")
@@ -348,11 +350,12 @@ def test_fgmres_fp64_matches_oracle(name, first, second, graph):
 
 @pytest.mark.parametrize("name", ["ragged", "three", "small"])
 @pytest.mark.parametrize("second", ["bilu0", "bilu0_mc"])
-def test_fgmres_fp32_converges(name, second):
-    banner(f"fgmres fp32 {name} {second}")
+@pytest.mark.parametrize("first", ["cptr", "cptr_uamg"])
+def test_fgmres_fp32_converges(name, second, first):
+    banner(f"fgmres fp32 {name} {first}+{second}")
     pr = prob(name)
-    s = solver(pr, precision="fp32", second_stage=second)
-    o = O.Oracle.from_problem(pr, first="cptr", second=second)
+    s = solver(pr, precision="fp32", first_stage=first, second_stage=second)
+    o = O.Oracle.from_problem(pr, first=first, second=second)
     x, info = s.solve(dev(pr.b_star), restart=30, rtol=1e-6)
     xo, io = o.fgmres(pr.b_star, m=30, rtol=1e-6)
     xg = x.cpu().numpy()
@@ -410,13 +413,14 @@ def test_invalid_inputs_are_rejected():
         cptr.Solver(replace(pr, vals=sing.reshape(-1)), device=DEV, first_stage="cpr")
     assert e.value.code in (-4, -7)
     # decoupling operators belong to the CPR first stage
-    with pytest.raises(cptr.CptrError) as e:
-        cptr.Solver(pr, device=DEV, first_stage="cptr", decoupling="ti")
-    assert e.value.code == -2
+    for first in ("cptr", "cptr_uamg"):
+        with pytest.raises(cptr.CptrError) as e:
+            cptr.Solver(pr, device=DEV, first_stage=first, decoupling="ti")
+        assert e.value.code == -2
 
 
 @pytest.mark.parametrize("name", ["three", "small"])
-@pytest.mark.parametrize("first", ["cptr", "cptr_bd"])
+@pytest.mark.parametrize("first", ["cptr", "cptr_bd", "cptr_uamg"])
 def test_update_values_equals_fresh_setup(name, first):
     """cptr_update_values with 2A (and 2 S~_T): the strength test, the
     prolongator weights and the Galerkin products scale exactly, so the kept

@@ -54,6 +54,29 @@ def test_amg_hierarchy_bit_exact(case, which, oracle_lib):
                     assert np.array_equal(x, y)
 
 
+@pytest.mark.parametrize("case", range(len(CASES)))
+def test_unknown_based_hierarchy_bit_exact(case, oracle_lib):
+    # the coupled pressure-temperature hierarchy of the unknown-based stage
+    pr = make_problem(**CASES[case])
+    for seed, smooth, smooth_T in ((0, True, False), (5, True, True), (0, False, False)):
+        o = O.Oracle.from_problem(pr, first="cptr_uamg", second="none", coarse_size=16, seed=seed,
+                                  smooth_p=smooth, smooth_p_T=smooth_T)
+        ref = o.amg_levels(0)
+        rp, ci, v = ref[0]["A"]
+        got = H.uamg_levels(rp, ci, v, pr.n, coarse_size=16, seed=seed, smooth_p=smooth,
+                            smooth_p_T=smooth_T)
+        assert len(got) == len(ref) >= 2
+        for a, b in zip(got, ref):
+            assert a["n"] == b["n"]
+            for x, y in zip(a["A"], b["A"]):
+                assert np.array_equal(x, y)            # bit-identical coarse operators
+            if "agg" in b:
+                assert np.array_equal(a["agg"], b["agg"])
+                assert a["omega"] == b["omega"]
+                for x, y in zip(a["P"], b["P"]):
+                    assert np.array_equal(x, y)
+
+
 @pytest.mark.parametrize("mc", [False, True])
 @pytest.mark.parametrize("level", [0, 1])
 def test_ilu_schedule_matches_oracle(mc, level, oracle_lib):
