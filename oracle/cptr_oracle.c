@@ -1000,41 +1000,26 @@ static csr extract(const orc *h, int r, int c) {
   return a;
 }
 
-/* The pressure-temperature operator A_00 of eq:A00 in unknown-wise order:
- * [A_pp A_pT; A_Tp A_TT], pressure rows (and columns) 0..n-1, temperature
- * rows n..2n-1, each block on the cell pattern of A. */
-static csr coupled_pT(const orc *h) {
-  int n = h->n, nv = h->nv, nnz = h->rp[n];
-  int sl[2] = {h->o.ip, h->o.iT};
-  csr a;
-  csr_alloc(&a, 2 * n, 2 * n, 4 * nnz);
-  int pos = 0;
-  for (int u = 0; u < 2; u++)
-    for (int i = 0; i < n; i++) {
-      for (int w = 0; w < 2; w++)
-        for (int k = h->rp[i]; k < h->rp[i + 1]; k++) {
-          a.ci[pos] = w * n + h->ci[k];
-          a.v[pos] = h->v[(size_t)k * nv * nv + sl[u] * nv + sl[w]];
-          pos++;
-        }
-      a.rp[u * n + i + 1] = pos;
-    }
-  return a;
-}
 
-/* Decoupling operator G = [I, -D; 0, I] of Section 3.1 for the split of the
- * unknowns into pressure p and the secondary unknowns s (all the others, in
- * slot order).  D is block diagonal with one 1 x (nv-1) block per cell:
- *   Quasi-IMPES  D_i = A_ps[i,i] A_ss[i,i]^{-1}            (diagonal blocks)
- *   True-IMPES   D_i = colsum(A_ps)_i colsum(A_ss)_i^{-1}  (sums over the rows
+/* Decoupling operator G = [I, -D; 0, I] of Section 3.1 for a split of the
+ * unknowns into primary ones (pressure for CPR; pressure and temperature for
+ * the CPTR extension of Section 3.2, S_0 = A_00 - D A_s0) and the secondary
+ * unknowns s (all the others, in slot order).  D is block diagonal with one
+ * npri x ns block per cell:
+ *   Quasi-IMPES  D_i = A_0s[i,i] A_ss[i,i]^{-1}            (diagonal blocks)
+ *   True-IMPES   D_i = colsum(A_0s)_i colsum(A_ss)_i^{-1}  (sums over the rows
  *                of block column i).
- * D_i solves D_i C = a for the row a and the (nv-1) x (nv-1) matrix C, i.e.
- * C^T D_i^T = a^T.  Returns -1 if a C is singular. */
-static int decoupling_weights(const orc *h, int kind, double *D) {
-  int n = h->n, nv = h->nv, ip = h->o.ip, ns = nv - 1;
+ * Each row d of D_i solves d C = a for the matching row a of the 0-s part and
+ * the ns x ns s-s part C, i.e. C^T d^T = a^T.  Layout D[i][row][ns].  Returns
+ * -1 if a C is singular. */
+static int decoupling_weights(const orc *h, int kind, const int *pri, int npri, double *D) {
+  int n = h->n, nv = h->nv, ns = nv - npri;
   int sl[4], q = 0;
-  for (int k = 0; k < nv; k++)
-    if (k != ip) sl[q++] = k;
+  for (int k = 0; k < nv; k++) {
+    int prim = 0;
+    for (int a = 0; a < npri; a++) prim |= k == pri[a];
+    if (!prim) sl[q++] = k;
+  }
   double *blk = (double *)calloc((size_t)n * nv * nv, sizeof(double));
   for (int j = 0; j < n; j++)
     for (int k = h->rp[j]; k < h->rp[j + 1]; k++) {
@@ -1047,16 +1032,46 @@ static int decoupling_weights(const orc *h, int kind, double *D) {
     const double *B = blk + (size_t)i * nv * nv;
     double CT[9], d[3];
     int piv[3];
-    for (int a = 0; a < ns; a++) {
-      d[a] = B[ip * nv + sl[a]];
+    for (int a = 0; a < ns; a++)
       for (int b = 0; b < ns; b++) CT[a * ns + b] = B[sl[b] * nv + sl[a]];
-    }
     if (lu_factor(CT, piv, ns) != 0) { st = -1; break; }
-    lu_solve(CT, piv, ns, d);
-    for (int a = 0; a < ns; a++) D[(size_t)i * ns + a] = d[a];
+    for (int r = 0; r < npri; r++) {
+      for (int a = 0; a < ns; a++) d[a] = B[pri[r] * nv + sl[a]];
+      lu_solve(CT, piv, ns, d);
+      for (int a = 0; a < ns; a++) D[((size_t)i * npri + r) * ns + a] = d[a];
+    }
   }
   free(blk);
   return st;
+}
+
+/* The pressure-temperature operator A_00 of eq:A00 in unknown-wise order:
+ * [A_pp A_pT; A_Tp A_TT], pressure rows (and columns) 0..n-1, temperature
+ * rows n..2n-1, each block on the cell pattern of A.  With decoupling weights
+ * D ([n][2][nv-2]) it is S_0 = A_00 - D A_s0 instead (Section 3.2). */
+static csr coupled_pT(const orc *h, const double *D) {
+  int n = h->n, nv = h->nv, nnz = h->rp[n], ns = nv - 2;
+  int sl[2] = {h->o.ip, h->o.iT}, ss[4], q = 0;
+  for (int k = 0; k < nv; k++)
+    if (k != h->o.ip && k != h->o.iT) ss[q++] = k;
+  csr a;
+  csr_alloc(&a, 2 * n, 2 * n, 4 * nnz);
+  int pos = 0;
+  for (int u = 0; u < 2; u++)
+    for (int i = 0; i < n; i++) {
+      for (int w = 0; w < 2; w++)
+        for (int k = h->rp[i]; k < h->rp[i + 1]; k++) {
+          const double *B = h->v + (size_t)k * nv * nv;
+          double x = B[sl[u] * nv + sl[w]];
+          if (D)
+            for (int b = 0; b < ns; b++) x -= D[((size_t)i * 2 + u) * ns + b] * B[ss[b] * nv + sl[w]];
+          a.ci[pos] = w * n + h->ci[k];
+          a.v[pos] = x;
+          pos++;
+        }
+      a.rp[u * n + i + 1] = pos;
+    }
+  return a;
 }
 
 void *orc_create(int n, int nv, const int *rp, const int *ci, const double *vals,
@@ -1086,14 +1101,21 @@ void *orc_create(int n, int nv, const int *rp, const int *ci, const double *vals
     h->ApT = extract(h, o->ip, o->iT);
     h->ATp = extract(h, o->iT, o->ip);
     csr fine = extract(h, o->ip, o->ip);
-    if (o->decoupling != 0 && o->first_stage != ORC_FIRST_CPR) st = -12;
-    if (st == 0 && o->decoupling != 0) {
+    if (o->decoupling != 0 && o->first_stage != ORC_FIRST_CPR && o->first_stage != ORC_FIRST_CPTR_UAMG)
+      st = -12;
+    if (st == 0 && o->decoupling != 0 && o->first_stage == ORC_FIRST_CPTR_UAMG) {
+      /* the CPTR extension (Section 3.2): weights of the p and T rows */
+      int pri[2] = {o->ip, o->iT};
+      if (nv < 3) st = -12;
+      h->dcp = (double *)calloc((size_t)n * 2 * (nv - 2) + 1, sizeof(double));
+      if (st == 0 && decoupling_weights(h, o->decoupling, pri, 2, h->dcp) != 0) st = -13;
+    } else if (st == 0 && o->decoupling != 0) {
       /* S_p = A_pp - D A_sp on the pattern of A_pp */
       int ns = nv - 1, sl[4], q = 0;
       for (int k = 0; k < nv; k++)
         if (k != o->ip) sl[q++] = k;
       h->dcp = (double *)calloc((size_t)n * ns + 1, sizeof(double));
-      if (decoupling_weights(h, o->decoupling, h->dcp) != 0) st = -13;
+      if (decoupling_weights(h, o->decoupling, &o->ip, 1, h->dcp) != 0) st = -13;
       for (int i = 0; st == 0 && i < n; i++)
         for (int k = rp[i]; k < rp[i + 1]; k++)
           for (int a = 0; a < ns; a++)
@@ -1102,7 +1124,7 @@ void *orc_create(int n, int nv, const int *rp, const int *ci, const double *vals
     if (st == 0 && o->first_stage == ORC_FIRST_CPTR_UAMG) {
       /* one unknown-based hierarchy on the coupled A_00 (Section 3.4) */
       csr_free(&fine);
-      st = uamg_setup(&h->amg_p, coupled_pT(h), n, o->theta, o->max_levels, o->coarse_size,
+      st = uamg_setup(&h->amg_p, coupled_pT(h, h->dcp), n, o->theta, o->max_levels, o->coarse_size,
                       o->seed, o->sweeps, o->smooth_p, o->smooth_p_T < 0 ? o->smooth_p : o->smooth_p_T,
                       o->smoother);
     } else if (st == 0) {
@@ -1180,7 +1202,18 @@ int orc_first_stage(void *hv, const double *v, double *x1) {
     h->bp[i] = v[(size_t)i * nv + ip];
     h->bt[i] = v[(size_t)i * nv + iT];
   }
-  if (h->o.decoupling != 0) {
+  if (h->o.decoupling != 0 && h->o.first_stage == ORC_FIRST_CPTR_UAMG) {
+    /* (b_p; b_T) = (v_p; v_T) - D v_s, s the slots other than p and T */
+    int q = 0, ns = nv - 2;
+    for (int k = 0; k < nv; k++) {
+      if (k == ip || k == iT) continue;
+      for (int i = 0; i < n; i++) {
+        h->bp[i] -= h->dcp[((size_t)i * 2 + 0) * ns + q] * v[(size_t)i * nv + k];
+        h->bt[i] -= h->dcp[((size_t)i * 2 + 1) * ns + q] * v[(size_t)i * nv + k];
+      }
+      q++;
+    }
+  } else if (h->o.decoupling != 0) {
     int q = 0;
     for (int k = 0; k < nv; k++) {
       if (k == ip) continue;

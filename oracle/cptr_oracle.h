@@ -42,7 +42,8 @@ typedef struct {
   const int *ilu_part; /* BILU0 partition (cell -> part, couplings across parts dropped) or NULL */
   int smooth_p_T;      /* prolongator of the S~_T (or A_TT) hierarchy, and of the temperature block of
                           the unknown-based hierarchy: 1 smoothed, 0 plain, -1 as smooth_p */
-  int decoupling;      /* CPR first stage only: 0 none, 1 Quasi-IMPES, 2 True-IMPES (Section 3.1) */
+  int decoupling;      /* CPR and CPTR-uAMG first stages: 0 none, 1 Quasi-IMPES, 2 True-IMPES
+                          (Section 3.1; its extension to p-T in Section 3.2) */
   int ilu_level;       /* level of fill of the block ILU second stage: 0 (BILU(0)) or 1 (BILU(1)) */
 } orc_opts;
 

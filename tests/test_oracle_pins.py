@@ -519,9 +519,92 @@ def test_single_level_unknown_based_stage_is_A00_inverse(tiny, oracle_lib):
         assert (x1[k::nv] == 0).all()
 
 
-def test_unknown_based_stage_rejects_decoupling(tiny, oracle_lib):
-    with pytest.raises(RuntimeError):
-        O.Oracle.from_problem(tiny, first="cptr_uamg", second="none", decoupling="ti")
+def _local_saturation(pr, zero):
+    """Values of pr with the saturation (every slot but pressure 0 and
+    temperature nv-1) columns (zero = "cols") or rows (zero = "rows") of every
+    off-diagonal block set to zero."""
+    nv = pr.nv
+    vals = pr.vals.reshape(-1, nv, nv).copy()
+    rows = np.repeat(np.arange(pr.n), np.diff(pr.row_ptr))
+    off = pr.col_idx != rows
+    if zero == "cols":
+        vals[off, :, 1:nv - 1] = 0.0
+    else:
+        vals[off, 1:nv - 1, :] = 0.0
+    return np.ascontiguousarray(vals.reshape(-1))
+
+
+def _schur_0(A, nv):
+    """Schur complement of the saturations, pressure-temperature in unknown-wise order."""
+    N = A.shape[0]
+    z = np.concatenate([np.arange(0, N, nv), np.arange(nv - 1, N, nv)])
+    q = np.array([k for k in range(N) if k % nv not in (0, nv - 1)])
+    return A[np.ix_(z, z)] - A[np.ix_(z, q)] @ np.linalg.solve(A[np.ix_(q, q)], A[np.ix_(q, z)])
+
+
+@pytest.mark.parametrize("three_phase", [False, True])
+@pytest.mark.parametrize("kind", ["qi", "ti"])
+def test_pT_decoupling_is_exact_when_saturation_columns_are_local(tiny, kind, three_phase, oracle_lib):
+    # Section 3.2's extension of the decoupling operators to the pressure-
+    # temperature system: with the saturation columns of the off-diagonal
+    # blocks zero, A_0s and A_ss are block diagonal, D = A_0s A_ss^{-1} for QI
+    # and TI alike, and S_0 = A_00 - D A_s0 is the exact Schur complement of the
+    # saturations: CPTR-uAMG with G and an exact (one-level) solve returns the
+    # pressure and temperature parts of A^{-1} v.  Three-phase: two saturations,
+    # D_i is 2 x 2.
+    if three_phase:
+        tiny = in_scaled_units(make_problem(shape=(4, 3, 3), kind="iid", seed=11, three_phase=True))
+        assert tiny.nv == 4
+    n, nv = tiny.n, tiny.nv
+    vals = _local_saturation(tiny, "cols")
+    o = O.Oracle(n, nv, tiny.row_ptr, tiny.col_idx, vals, first="cptr_uamg", second="none",
+                 coarse_size=10_000, decoupling=kind)
+    A = dense_bsr(tiny.row_ptr, tiny.col_idx, vals, nv)
+    S = _schur_0(A, nv)
+    assert np.allclose(_pressure_operator(o), S, rtol=1e-12, atol=1e-12 * np.abs(S).max())
+    v = np.random.default_rng(6).standard_normal(n * nv)
+    x1 = o.first_stage(v)
+    x = np.linalg.solve(A, v)
+    for k in (0, nv - 1):
+        assert np.allclose(x1[k::nv], x[k::nv], rtol=1e-9, atol=1e-9 * np.abs(x[k::nv]).max())
+    for k in range(1, nv - 1):
+        assert (x1[k::nv] == 0).all()
+
+
+def test_pT_true_impes_keeps_the_column_sums_of_the_schur_complement(tiny, oracle_lib):
+    # with cell-local saturation equations (their rows zero off the diagonal
+    # blocks), True-IMPES gives S_0 the column sums of the exact Schur
+    # complement of the saturations; Quasi-IMPES does not
+    n, nv = tiny.n, tiny.nv
+    vals = _local_saturation(tiny, "rows")
+    A = dense_bsr(tiny.row_ptr, tiny.col_idx, vals, nv)
+    S = _schur_0(A, nv)
+    sums = {}
+    for kind in ("ti", "qi"):
+        o = O.Oracle(n, nv, tiny.row_ptr, tiny.col_idx, vals, first="cptr_uamg", second="none",
+                     coarse_size=10_000, decoupling=kind)
+        sums[kind] = _pressure_operator(o)
+    for part in (slice(0, n), slice(n, 2 * n)):  # pressure and temperature rows summed apart
+        want = S[part].sum(axis=0)
+        scale = np.abs(want).max()
+        assert np.allclose(sums["ti"][part].sum(axis=0), want, rtol=1e-10, atol=1e-10 * scale)
+    want = S[:n].sum(axis=0)
+    assert not np.allclose(sums["qi"][:n].sum(axis=0), want, rtol=1e-6, atol=1e-6 * np.abs(want).max())
+
+
+def test_pT_decoupling_without_saturation_coupling_changes_nothing(tiny, oracle_lib):
+    # A_0s = 0 gives D = 0: the decoupled stage is the plain CPTR-uAMG
+    n, nv = tiny.n, tiny.nv
+    vals = tiny.vals.reshape(-1, nv, nv).copy()
+    vals[:, 0, 1:nv - 1] = 0.0
+    vals[:, nv - 1, 1:nv - 1] = 0.0
+    vals = np.ascontiguousarray(vals.reshape(-1))
+    v = np.random.default_rng(7).standard_normal(n * nv)
+    plain = O.Oracle(n, nv, tiny.row_ptr, tiny.col_idx, vals, first="cptr_uamg", second="none",
+                     coarse_size=8).first_stage(v)
+    ti = O.Oracle(n, nv, tiny.row_ptr, tiny.col_idx, vals, first="cptr_uamg", second="none",
+                  coarse_size=8, decoupling="ti").first_stage(v)
+    assert np.array_equal(plain, ti)
 
 
 def _local_secondary(pr, zero):
