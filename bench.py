@@ -355,7 +355,9 @@ def main():
         # (also with the True-IMPES decoupling operator, Section 3.1), behind
         # the block-diagonal CPTR-BD(AMG) first stage (V-cycles on A_pp and
         # A_TT, Section 4.4), behind CPTR-uAMG (one V-cycle of the unknown-based
-        # hierarchy of A_00, Section 3.4), and CPTR with the BILU(1) second stage
+        # hierarchy of A_00, Section 3.4; also with True-IMPES extended to the
+        # pressure-temperature system, Section 3.2), and CPTR with the BILU(1)
+        # second stage
         for tag, first, opt, mdl_needed in (
                 ("fp64_cpr_bilu0", "cpr", dict(precision="fp64", second_stage="bilu0"), False),
                 ("fp32_cpr_bilu0_mc", "cpr", dict(precision="fp32", second_stage="bilu0_mc"), False),
@@ -364,6 +366,10 @@ def main():
                 ("fp32_cptr_bd_bilu0_mc", "cptr_bd", dict(precision="fp32", second_stage="bilu0_mc"), False),
                 ("fp64_cptr_uamg_bilu0", "cptr_uamg", dict(precision="fp64", second_stage="bilu0"), False),
                 ("fp32_cptr_uamg_bilu0_mc", "cptr_uamg", dict(precision="fp32", second_stage="bilu0_mc"), False),
+                ("fp64_cptr_uamg_ti_bilu0", "cptr_uamg", dict(precision="fp64", second_stage="bilu0",
+                                                              decoupling="ti"), False),
+                ("fp32_cptr_uamg_ti_bilu0_mc", "cptr_uamg", dict(precision="fp32", second_stage="bilu0_mc",
+                                                                 decoupling="ti"), False),
                 ("fp64_cpr_ti_bilu0", "cpr", dict(precision="fp64", second_stage="bilu0", decoupling="ti"),
                  False),
                 ("fp32_cpr_ti_bilu0_mc", "cpr", dict(precision="fp32", second_stage="bilu0_mc", decoupling="ti"),

@@ -67,12 +67,15 @@ extern "C" {
                                     coarsened on its own diagonal block, couplings kept in the
                                     Galerkin coarse operators) */
 
-/* Decoupling operators G = [I, -D; 0, I] for the CPR first stage (Section 3.1;
- * p = pressure, s = every other unknown in slot order, D one 1 x (nv-1) block
- * per cell): the first stage solves S_p = A_pp - D A_sp with b_p = v_p - D v_s. */
+/* Decoupling operators G = [I, -D; 0, I] (Section 3.1).  CPR: p = pressure,
+ * s = every other unknown in slot order, D one 1 x (nv-1) block per cell; the
+ * first stage solves S_p = A_pp - D A_sp with b_p = v_p - D v_s.  CPTR-uAMG
+ * (the pressure-temperature extension of Section 3.2): 0 = (p, T), s = the
+ * saturations, D one 2 x (nv-2) block per cell; the first stage solves
+ * S_0 = A_00 - D A_s0 with b_0 = v_0 - D v_s. */
 #define CPTR_DECOUPLE_NONE 0
-#define CPTR_DECOUPLE_QI 1       /* Quasi-IMPES: D = diag(A_ps) diag(A_ss)^-1 */
-#define CPTR_DECOUPLE_TI 2       /* True-IMPES:  D = colsum(A_ps) colsum(A_ss)^-1 */
+#define CPTR_DECOUPLE_QI 1       /* Quasi-IMPES: D = diag(A_0s) diag(A_ss)^-1 */
+#define CPTR_DECOUPLE_TI 2       /* True-IMPES:  D = colsum(A_0s) colsum(A_ss)^-1 */
 
 /* second stage */
 #define CPTR_SECOND_NONE 0       /* z = x1 */
@@ -135,9 +138,9 @@ typedef struct {
                             16 cells (rows of the -z/+z neighbours kept in registers, -x/+x by
                             lane shuffles); 0: tiles in cell order with every neighbour row
                             gathered (1).  Both give the same result bit for bit. */
-  int decoupling;        /* CPTR_DECOUPLE_* for CPTR_FIRST_CPR (NONE); other first stages
-                            reject QI / TI with CPTR_ERR_UNSUPPORTED, a singular block of D
-                            gives CPTR_ERR_SINGULAR_BLOCK */
+  int decoupling;        /* CPTR_DECOUPLE_* for CPTR_FIRST_CPR and CPTR_FIRST_UAMG (NONE);
+                            other first stages reject QI / TI with CPTR_ERR_UNSUPPORTED, a
+                            singular block of D gives CPTR_ERR_SINGULAR_BLOCK */
   int ilu_level;         /* level of fill of the BILU second stages: 0 (BILU(0)) or 1 (BILU(1):
                             the blocks of A and the level-1 fill, Section 4's ILU(1)) (0);
                             the learned stage's fallback stays BILU(0) */

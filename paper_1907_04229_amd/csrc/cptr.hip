@@ -710,7 +710,7 @@ struct Precond : PrecondBase {
   AmgDev<T> amg_p, amg_s;
   IluDev<T> ilu;
   DevMem bp, bt, xp, dT, dp, tmp, b1;
-  DevMem dcp;  // decoupling weights D [n][nv-1] of the CPR first stage (empty without)
+  DevMem dcp;  // decoupling weights: CPR D [n][nv-1], CPTR-uAMG D [n][2][nv-2] (empty without)
   DevMem vtmp, ztmp;  // FP64 staging of cptr_vcycle
   bool have_s = false, have_ilu = false;
   double bytes = 0.0;
@@ -726,7 +726,8 @@ struct Precond : PrecondBase {
       *dpp = devp<T>(dp), *t = devp<T>(tmp);
     if (fs == CPTR_FIRST_UAMG) btt = bpp + n;  // (b_p; b_T) in unknown-wise order
     hipLaunchKernelGGL((k_restrict_pT<T>), dim3(nblk(n)), dim3(kBlock), 0, st, n, op.nv, ip, iT, slots,
-                       dcp.p ? (const T *)devp<T>(dcp) : (const T *)nullptr, bpp, fs == CPTR_FIRST_CPR ? (T *)nullptr : btt);
+                       dcp.p ? (const T *)devp<T>(dcp) : (const T *)nullptr, fs == CPTR_FIRST_UAMG ? 2 : 1, bpp,
+                       fs == CPTR_FIRST_CPR ? (T *)nullptr : btt);
     LAUNCH_CHECK();
     if (fs == CPTR_FIRST_UAMG) {  // unknown-based: (d_p; d_T) = V(A_00) (b_p; b_T)
       amg_p.cycle(st, bpp, dpp);
@@ -951,14 +952,19 @@ static void build_precond(cptr_handle *h, const std::vector<int> &rp, const std:
   if (o.first_stage != CPTR_FIRST_NONE) {
     AmgHost hp;
     HostCSR pp = sub(o.ip, o.ip);
+    // Decoupling (Section 3.1; extended to pressure-temperature in Section
+    // 3.2): D from Quasi-IMPES (diagonal blocks) or True-IMPES (column sums of
+    // the block columns); each row d of D_i solves d C_i = a_i for C_i the s-s
+    // part and a_i the matching row of the primary-s part.  Primary rows: p
+    // (CPR, s = every other slot) or p and T (CPTR-uAMG, s = the rest).
+    std::vector<int> pri{o.ip}, sl;
+    if (o.first_stage == CPTR_FIRST_UAMG) pri.push_back(o.iT);
+    for (int k = 0; k < nv; k++)
+      if (std::find(pri.begin(), pri.end(), k) == pri.end()) sl.push_back(k);
+    const int npri = int(pri.size()), ns = int(sl.size());
+    std::vector<double> D;
     if (o.decoupling != 0) {
-      // Section 3.1: the first stage solves S_p = A_pp - D A_sp, with D from
-      // Quasi-IMPES (diagonal blocks) or True-IMPES (column sums of the block
-      // columns), D_i C_i = a_i for C_i the s-s part and a_i the p-s part
-      const int ns = nv - 1;
-      std::vector<int> sl;
-      for (int k = 0; k < nv; k++)
-        if (k != o.ip) sl.push_back(k);
+      if (ns < 1) throw Error{CPTR_ERR_UNSUPPORTED, "decoupling needs a secondary unknown"};
       std::vector<double> blk((size_t)n * nv * nv, 0.0);
       for (int j = 0; j < n; j++)
         for (int k = rp[j]; k < rp[j + 1]; k++) {
@@ -966,36 +972,41 @@ static void build_precond(cptr_handle *h, const std::vector<int> &rp, const std:
           if (o.decoupling == CPTR_DECOUPLE_QI && i != j) continue;
           for (int e = 0; e < nv * nv; e++) blk[(size_t)i * nv * nv + e] += vals[(size_t)k * nv * nv + e];
         }
-      std::vector<double> D((size_t)n * ns);
+      D.resize((size_t)n * npri * ns);
       for (int i = 0; i < n; i++) {
         const double *B = &blk[(size_t)i * nv * nv];
-        double m[3][4];  // [C_i^T | a_i^T], Gauss-Jordan with partial pivoting
+        double m[3][5];  // [C_i^T | a_i^T for each primary row], Gauss-Jordan with partial pivoting
         for (int a = 0; a < ns; a++) {
           for (int b = 0; b < ns; b++) m[a][b] = B[sl[b] * nv + sl[a]];
-          m[a][ns] = B[o.ip * nv + sl[a]];
+          for (int r = 0; r < npri; r++) m[a][ns + r] = B[pri[r] * nv + sl[a]];
         }
+        const int nc = ns + npri;
         for (int c = 0; c < ns; c++) {
           int pr = c;
           for (int r = c + 1; r < ns; r++)
             if (std::fabs(m[r][c]) > std::fabs(m[pr][c])) pr = r;
           if (m[pr][c] == 0.0)
             throw Error{CPTR_ERR_SINGULAR_BLOCK, "singular decoupling block at cell " + std::to_string(i)};
-          for (int b = 0; b <= ns; b++) std::swap(m[c][b], m[pr][b]);
+          for (int b = 0; b < nc; b++) std::swap(m[c][b], m[pr][b]);
           for (int r = 0; r < ns; r++) {
             if (r == c) continue;
             const double f = m[r][c] / m[c][c];
-            for (int b = c; b <= ns; b++) m[r][b] -= f * m[c][b];
+            for (int b = c; b < nc; b++) m[r][b] -= f * m[c][b];
           }
         }
-        for (int a = 0; a < ns; a++) D[(size_t)i * ns + a] = m[a][ns] / m[a][a];
+        for (int r = 0; r < npri; r++)
+          for (int a = 0; a < ns; a++) D[((size_t)i * npri + r) * ns + a] = m[a][ns + r] / m[a][a];
       }
+      std::vector<T> Dt(D.begin(), D.end());
+      upload(P.dcp, Dt);
+      bytes += (double)n * npri * ns * s + 8.0 * n * ns;  // D and v_s in the restriction
+    }
+    if (o.decoupling != 0 && o.first_stage == CPTR_FIRST_CPR) {
+      // S_p = A_pp - D A_sp
       for (int i = 0; i < n; i++)
         for (int k = rp[i]; k < rp[i + 1]; k++)
           for (int a = 0; a < ns; a++)
             pp.v[k] -= D[(size_t)i * ns + a] * vals[((size_t)k * nv + sl[a]) * nv + o.ip];
-      std::vector<T> Dt(D.begin(), D.end());
-      upload(P.dcp, Dt);
-      bytes += (double)n * ns * (s + 8);  // D and v_s in the restriction
     }
     AmgParams prm_s = prm;  // the second hierarchy, or the temperature block of the coupled one
     if (o.amg_smooth_p_T >= 0) prm_s.smooth_p = o.amg_smooth_p_T;
@@ -1007,13 +1018,18 @@ static void build_precond(cptr_handle *h, const std::vector<int> &rp, const std:
       c.rp.assign(2 * n + 1, 0);
       c.ci.reserve(4 * (size_t)nnzb);
       c.v.reserve(4 * (size_t)nnzb);
-      const int sl[2] = {o.ip, o.iT};
+      // (with decoupling: S_0 = A_00 - D A_s0, Section 3.2)
+      const int pt[2] = {o.ip, o.iT};
       for (int u = 0; u < 2; u++)
         for (int i = 0; i < n; i++) {
           for (int w = 0; w < 2; w++)
             for (int k = rp[i]; k < rp[i + 1]; k++) {
+              const double *Bk = &vals[(size_t)k * nv * nv];
+              double x = Bk[pt[u] * nv + pt[w]];
+              if (!D.empty())
+                for (int b = 0; b < ns; b++) x -= D[((size_t)i * 2 + u) * ns + b] * Bk[sl[b] * nv + pt[w]];
               c.ci.push_back(w * n + ci[k]);
-              c.v.push_back(vals[((size_t)k * nv + sl[u]) * nv + sl[w]]);
+              c.v.push_back(x);
             }
           c.rp[u * n + i + 1] = int(c.ci.size());
         }
@@ -1152,8 +1168,8 @@ static void validate_and_fetch(const cptr_bsr *A, const cptr_csr *S, const cptr_
   if (o.first_stage < 0 || o.first_stage > 5) throw Error{CPTR_ERR_INVALID_ARG, "invalid first stage"};
   if (o.decoupling < 0 || o.decoupling > 2) throw Error{CPTR_ERR_INVALID_ARG, "invalid decoupling"};
   if (o.ilu_level != 0 && o.ilu_level != 1) throw Error{CPTR_ERR_UNSUPPORTED, "ilu_level must be 0 or 1"};
-  if (o.decoupling != 0 && o.first_stage != CPTR_FIRST_CPR)
-    throw Error{CPTR_ERR_UNSUPPORTED, "decoupling operators apply to the CPR first stage only"};
+  if (o.decoupling != 0 && o.first_stage != CPTR_FIRST_CPR && o.first_stage != CPTR_FIRST_UAMG)
+    throw Error{CPTR_ERR_UNSUPPORTED, "decoupling operators apply to the CPR and CPTR-uAMG first stages only"};
   if (o.second_stage < 0 || o.second_stage > 4)
     throw Error{CPTR_ERR_UNSUPPORTED, "unsupported second stage"};
   if (o.precision != CPTR_FP32 && o.precision != CPTR_FP64)

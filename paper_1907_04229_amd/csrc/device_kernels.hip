@@ -238,27 +238,40 @@ __global__ void __launch_bounds__(kBlock) k_coarse_gemv(const double *__restrict
 // ---------------------------------------------------------------------------
 // first stage: restriction, two-stage residual, finishing
 // ---------------------------------------------------------------------------
-// b_p = v_p (or, with decoupling weights D [n][nv-1], (G v)_p = v_p - D_i v_s
-// over the secondary slots in order, Section 3.1), b_T = v_T
+// b_p = v_p, b_T = v_T; with decoupling weights (G v restricted, Section 3.1):
+// d_rows = 1, D [n][nv-1]: b_p = v_p - D_i v_s over every slot but p, in order;
+// d_rows = 2, D [n][2][nv-2]: (b_p; b_T) = (v_p; v_T) - D_i v_s over every slot
+// but p and T (the pressure-temperature extension of Section 3.2)
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_restrict_pT(int n, int nv, int ip, int iT,
                                                         const ApplySlots *__restrict__ slots,
-                                                        const T *__restrict__ D, T *__restrict__ bp,
-                                                        T *__restrict__ bt) {
+                                                        const T *__restrict__ D, int d_rows,
+                                                        T *__restrict__ bp, T *__restrict__ bt) {
   const int i = blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
   const gmem<const double> *__restrict__ v = as_global(slots->v);
   T p = T(v[(size_t)i * nv + ip]);
-  if (D) {
+  T t = T(v[(size_t)i * nv + iT]);
+  if (D && d_rows == 1) {  // pressure row over every other slot: D [n][nv-1]
     int q = 0;
     for (int k = 0; k < nv; k++) {
       if (k == ip) continue;
       p -= D[(size_t)i * (nv - 1) + q] * T(v[(size_t)i * nv + k]);
       q++;
     }
+  } else if (D) {  // pressure and temperature rows over the remaining slots: D [n][2][nv-2]
+    const int ns = nv - 2;
+    int q = 0;
+    for (int k = 0; k < nv; k++) {
+      if (k == ip || k == iT) continue;
+      const T vk = T(v[(size_t)i * nv + k]);
+      p -= D[((size_t)i * 2 + 0) * ns + q] * vk;
+      t -= D[((size_t)i * 2 + 1) * ns + q] * vk;
+      q++;
+    }
   }
   bp[i] = p;
-  if (bt) bt[i] = T(v[(size_t)i * nv + iT]);
+  if (bt) bt[i] = t;
 }
 
 // b1 = v - A R^T (d_p, d_T): only the p and T columns of each block are used.

@@ -261,21 +261,24 @@ def test_apply_fp32(name, second):
 
 @pytest.mark.parametrize("name", ["ragged", "three", "small"])
 @pytest.mark.parametrize("kind", ["qi", "ti"])
-def test_decoupled_cpr_fp64(name, kind):
-    """CPR with a Quasi- or True-IMPES decoupling operator (Section 3.1):
-    pressure-hierarchy aggregates bit-exact, V-cycle on S_p, first stage and
+@pytest.mark.parametrize("first", ["cpr", "cptr_uamg"])
+def test_decoupled_first_stage_fp64(name, kind, first):
+    """CPR with a Quasi- or True-IMPES decoupling operator (Section 3.1), and
+    CPTR-uAMG with its pressure-temperature extension (Section 3.2):
+    hierarchy aggregates bit-exact, V-cycle on S_p (S_0), first stage and
     application (FP64) and FGMRES against the oracle."""
-    banner(f"decoupled cpr {name} {kind}")
+    banner(f"decoupled {first} {name} {kind}")
     pr = prob(name)
-    s = solver(pr, precision="fp64", first_stage="cpr", second_stage="bilu0", decoupling=kind,
+    s = solver(pr, precision="fp64", first_stage=first, second_stage="bilu0", decoupling=kind,
                amg_coarse_size=16)
-    o = O.Oracle.from_problem(pr, first="cpr", second="bilu0", decoupling=kind, coarse_size=16)
+    o = O.Oracle.from_problem(pr, first=first, second="bilu0", decoupling=kind, coarse_size=16)
     ref = o.amg_levels(0)
     for lev in range(len(ref) - 1):
         assert np.array_equal(cptr.cptr_get_aggregates(s.h, 0, lev, ref[lev]["n"]), ref[lev]["agg"])
     rng = np.random.default_rng(14)
-    b = rng.standard_normal(pr.n)
-    x = torch.empty(pr.n, dtype=torch.float64, device=DEV)
+    m = 2 * pr.n if first == "cptr_uamg" else pr.n
+    b = rng.standard_normal(m)
+    x = torch.empty(m, dtype=torch.float64, device=DEV)
     cptr.cptr_vcycle(s.h, 0, dev(b), x)
     v = rng.standard_normal(pr.n * pr.nv)
     x1 = torch.empty_like(dev(v))
@@ -286,8 +289,8 @@ def test_decoupled_cpr_fp64(name, kind):
     assert relerr(x1.cpu().numpy(), o.first_stage(v)) <= 1e-10
     assert relerr(z.cpu().numpy(), o.apply(v)) <= 1e-9
     s.close()
-    s = solver(pr, precision="fp64", first_stage="cpr", second_stage="bilu0", decoupling=kind)
-    o = O.Oracle.from_problem(pr, first="cpr", second="bilu0", decoupling=kind)
+    s = solver(pr, precision="fp64", first_stage=first, second_stage="bilu0", decoupling=kind)
+    o = O.Oracle.from_problem(pr, first=first, second="bilu0", decoupling=kind)
     xg, info = s.solve(dev(pr.b), restart=30, rtol=1e-6)
     xo, io = o.fgmres(pr.b, m=30, rtol=1e-6)
     err = np.linalg.norm(xg.cpu().numpy() - xo) / np.linalg.norm(xo)
@@ -412,8 +415,8 @@ def test_invalid_inputs_are_rejected():
     with pytest.raises(cptr.CptrError) as e:
         cptr.Solver(replace(pr, vals=sing.reshape(-1)), device=DEV, first_stage="cpr")
     assert e.value.code in (-4, -7)
-    # decoupling operators belong to the CPR first stage
-    for first in ("cptr", "cptr_uamg"):
+    # decoupling operators belong to the CPR and CPTR-uAMG first stages
+    for first in ("cptr", "cptr_lower", "cptr_bd"):
         with pytest.raises(cptr.CptrError) as e:
             cptr.Solver(pr, device=DEV, first_stage=first, decoupling="ti")
         assert e.value.code == -2
