@@ -247,10 +247,11 @@ int cptr_krylov_vector(const cptr_handle *h, int j, double *out, void *stream);
  * layout of cptr_bsr.vals (the handle borrows this pointer from now on, as it
  * did the original); S_vals: device FP64 values of S~_T in the pattern given
  * to cptr_setup (required for CPTR_FIRST_BLOCK / _BLOCK_LOWER, else ignored).
- * The aggregates of both AMG hierarchies and the BILU(0) schedule are kept;
- * prolongator values, Galerkin products, the coarsest inverse, the BILU(0)
- * factor, the sliced copy of A and the learned stage's edge features are
- * recomputed.  Blocking.  CPTR_ERR_INVALID_ARG for a missing argument,
+ * The aggregates of both AMG hierarchies and the block ILU's order, pattern
+ * and level schedules are kept; prolongator values, Galerkin products and the
+ * coarsest inverse are recomputed on the host, the block ILU factors on the
+ * GPU (the same FP64 factorisation, bit for bit), and the sliced copy of A and
+ * the learned stage's edge features are rebuilt.  Blocking.  CPTR_ERR_INVALID_ARG for a missing argument,
  * CPTR_ERR_NONFINITE for a non-finite value, CPTR_ERR_SINGULAR_BLOCK as in
  * cptr_setup; on error the handle must be destroyed. */
 int cptr_update_values(cptr_handle *h, const double *A_vals, const double *S_vals,

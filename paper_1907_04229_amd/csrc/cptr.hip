@@ -40,6 +40,20 @@ struct DevMem {
   DevMem() = default;
   DevMem(const DevMem &) = delete;
   DevMem &operator=(const DevMem &) = delete;
+  DevMem(DevMem &&o) noexcept : p(o.p), bytes(o.bytes) {
+    o.p = nullptr;
+    o.bytes = 0;
+  }
+  DevMem &operator=(DevMem &&o) noexcept {
+    if (this != &o) {
+      if (p) (void)hipFree(p);
+      p = o.p;
+      bytes = o.bytes;
+      o.p = nullptr;
+      o.bytes = 0;
+    }
+    return *this;
+  }
   ~DevMem() {
     if (p) (void)hipFree(p);
   }
@@ -363,6 +377,9 @@ struct AmgDev {
 template <typename T>
 struct IluDev {
   DevMem f_rows, f_ptr, f_col, f_val, b_rows, b_ptr, b_col, b_val, dinv;
+  // factor pattern for a numeric refactorisation (IluHost's frp .. fwd, order)
+  DevMem r_frp, r_fci, r_src, r_dpos, r_dst, r_fwd, r_order;
+  int n = 0, nv = 0, nnzf = 0;
   std::vector<int> f_lev_ptr, b_lev_ptr;
   std::vector<char> f_nonempty;  // forward levels holding at least one L block
   std::vector<int> lev_lower, lev_upper, color;
@@ -390,11 +407,62 @@ struct IluDev {
     lev_upper = h.lev_upper;
     color = h.color;
     ncolor = h.ncolor;
+    n = h.n;
+    nv = h.nv;
+    nnzf = int(h.fci.size());
+    upload(r_frp, h.frp);
+    upload(r_fci, h.fci);
+    upload(r_src, h.src);
+    upload(r_dpos, h.dpos);
+    upload(r_dst, h.dst);
+    upload(r_fwd, h.fwd);
+    upload(r_order, h.order);
     const double s = sizeof(T), b2 = double(h.nv) * h.nv;
     const double n = h.n;
     bytes = (h.f_col.size() + h.b_col.size()) * (b2 * s + 4) + 2 * 4 * (n + 1) + 2 * 4 * n  // factors
             + n * b2 * s                                                                      // D^-1
             + 4 * n * h.nv * s;                                                               // b1, y, w
+  }
+
+  // New factors from new device FP64 values A (BSR, the pattern the factor was
+  // built on), on the GPU: the same IKJ factorisation in FP64 as the host's,
+  // bit for bit, then rounded to T.  Blocking; throws on a zero pivot.
+  void refactor(const double *A, hipStream_t st) {
+    if (nv == 3)
+      refactor_nv<3>(A, st);
+    else if (nv == 4)
+      refactor_nv<4>(A, st);
+    else
+      throw Error{CPTR_ERR_UNSUPPORTED, "refactorisation for nv = 3 or 4 only"};
+  }
+
+  template <int NV>
+  void refactor_nv(const double *A, hipStream_t st) {
+    constexpr int B2 = NV * NV;
+    DevMem lu, dv, bad;
+    lu.alloc((size_t)nnzf * B2 * sizeof(double));
+    dv.alloc((size_t)n * B2 * sizeof(double));
+    bad.alloc(sizeof(int));
+    hipLaunchKernelGGL((k_fill<int>), dim3(1), dim3(kBlock), 0, st, (int *)bad.p, (size_t)1, 0);
+    hipLaunchKernelGGL((k_ilu_load<NV>), dim3(nblk((size_t)nnzf * B2)), dim3(kBlock), 0, st, nnzf,
+                       devp<int>(r_src), A, (double *)lu.p);
+    LAUNCH_CHECK();
+    for (size_t l = 0; l + 1 < f_lev_ptr.size(); l++) {
+      const int p0 = f_lev_ptr[l], cnt = f_lev_ptr[l + 1] - p0;
+      if (cnt <= 0) continue;
+      hipLaunchKernelGGL((k_ilu_factor<NV>), dim3(nblk(cnt)), dim3(kBlock), 0, st, p0, cnt, devp<int>(r_fwd),
+                         devp<int>(r_frp), devp<int>(r_fci), devp<int>(r_dpos), (double *)lu.p, (double *)dv.p,
+                         (int *)bad.p);
+      LAUNCH_CHECK();
+    }
+    hipLaunchKernelGGL((k_ilu_store<NV, T>), dim3(nblk(((size_t)nnzf + n) * B2)), dim3(kBlock), 0, st, nnzf, n,
+                       devp<int>(r_dst), devp<int>(r_order), (const double *)lu.p, (const double *)dv.p,
+                       devp<T>(f_val), devp<T>(b_val), devp<T>(dinv));
+    LAUNCH_CHECK();
+    int hb = 0;
+    CPTR_HIP_TRY(hipMemcpyAsync(&hb, bad.p, sizeof(int), hipMemcpyDeviceToHost, st));
+    CPTR_HIP_TRY(hipStreamSynchronize(st));
+    if (hb) throw Error{CPTR_ERR_SINGULAR_BLOCK, "zero pivot in a block ILU diagonal block"};
   }
 };
 
@@ -893,7 +961,8 @@ template <typename T>
 static void build_precond(cptr_handle *h, const std::vector<int> &rp, const std::vector<int> &ci,
                           const std::vector<double> &vals, const HostCSR *S,
                           const std::vector<std::vector<int>> *agg_p = nullptr,
-                          const std::vector<std::vector<int>> *agg_s = nullptr) {
+                          const std::vector<std::vector<int>> *agg_s = nullptr,
+                          IluDev<T> *keep_ilu = nullptr) {
   auto pc = std::make_unique<Precond<T>>();
   Precond<T> &P = *pc;
   const cptr_options &o = h->op.o;
@@ -1074,16 +1143,23 @@ static void build_precond(cptr_handle *h, const std::vector<int> &rp, const std:
   }
   if (o.second_stage == CPTR_SECOND_BILU0 || o.second_stage == CPTR_SECOND_BILU0_MC ||
       o.second_stage == CPTR_SECOND_LEARNED) {
-    IluHost ih;  // with the learned stage: the natural-order factor of the fallback (plain ILU(0))
-    // the learned stage's fallback is the plain natural-order BILU(0)
-    ilu_build(n, nv, rp.data(), ci.data(), vals.data(), o.second_stage == CPTR_SECOND_BILU0_MC, ih,
-              o.second_stage == CPTR_SECOND_LEARNED ? 0 : o.ilu_level);
-    P.ilu.build(ih);
+    if (keep_ilu) {
+      // numeric re-setup: the kept order, pattern and schedules, new factors
+      // computed on the GPU from the handle's device values
+      P.ilu = std::move(*keep_ilu);
+      P.ilu.refactor(h->vals, 0);
+    } else {
+      IluHost ih;  // with the learned stage: the natural-order factor of the fallback (plain ILU(0))
+      // the learned stage's fallback is the plain natural-order BILU(0)
+      ilu_build(n, nv, rp.data(), ci.data(), vals.data(), o.second_stage == CPTR_SECOND_BILU0_MC, ih,
+                o.second_stage == CPTR_SECOND_LEARNED ? 0 : o.ilu_level);
+      P.ilu.build(ih);
+      h->stats.ilu_levels_lower = int(ih.f_lev_ptr.size()) - 1;
+      h->stats.ilu_levels_upper = int(ih.b_lev_ptr.size()) - 1;
+      h->stats.ilu_colors = ih.ncolor;
+    }
     P.have_ilu = true;
     if (o.second_stage != CPTR_SECOND_LEARNED) bytes += P.ilu.bytes;
-    h->stats.ilu_levels_lower = int(ih.f_lev_ptr.size()) - 1;
-    h->stats.ilu_levels_upper = int(ih.b_lev_ptr.size()) - 1;
-    h->stats.ilu_colors = ih.ncolor;
   }
   if (o.second_stage != CPTR_SECOND_NONE)  // two-stage residual
     bytes += (double)nnzb * (nv * 2 * s + 4) + 4.0 * (n + 1) + 8.0 * n * nv + 2.0 * n * s + n * nv * s;
@@ -1785,13 +1861,27 @@ int cptr_update_values(cptr_handle *h, const double *A_vals, const double *S_val
       agg_p = strip(Pf ? Pf->amg_p.agg : Pd->amg_p.agg);
       if (two_hier) agg_s = strip(Pf ? Pf->amg_s.agg : Pd->amg_s.agg);
     }
+    // the block ILU's order, pattern and schedules are kept too: its factors
+    // are recomputed on the GPU
+    std::unique_ptr<IluDev<float>> ilu_f;
+    std::unique_ptr<IluDev<double>> ilu_d;
+    if (auto *Pf = dynamic_cast<Precond<float> *>(h->pc.get()); Pf && Pf->have_ilu) {
+      ilu_f = std::make_unique<IluDev<float>>(std::move(Pf->ilu));
+      Pf->have_ilu = false;
+    }
+    if (auto *Pd = dynamic_cast<Precond<double> *>(h->pc.get()); Pd && Pd->have_ilu) {
+      ilu_d = std::make_unique<IluDev<double>>(std::move(Pd->ilu));
+      Pd->have_ilu = false;
+    }
     h->vals = A_vals;
     build_sliced(h, rp, ci, vals);
     LearnedDev *lrn = h->lrn.get();
     if (h->op.o.precision == CPTR_FP32)
-      build_precond<float>(h, rp, ci, vals, need_s ? &sh : nullptr, &agg_p, two_hier ? &agg_s : nullptr);
+      build_precond<float>(h, rp, ci, vals, need_s ? &sh : nullptr, &agg_p, two_hier ? &agg_s : nullptr,
+                           ilu_f.get());
     else
-      build_precond<double>(h, rp, ci, vals, need_s ? &sh : nullptr, &agg_p, two_hier ? &agg_s : nullptr);
+      build_precond<double>(h, rp, ci, vals, need_s ? &sh : nullptr, &agg_p, two_hier ? &agg_s : nullptr,
+                            ilu_d.get());
     if (lrn) {
       lrn->build(n, nv, rp, ci, vals);  // edge features of the new values
       if (h->model) h->pc->set_learned(lrn, &h->model->dev);

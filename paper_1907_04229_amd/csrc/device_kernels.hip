@@ -424,6 +424,138 @@ __global__ void __launch_bounds__(kBlock) k_ilu_bwd(int p0, int cnt, const int *
 }
 
 // ---------------------------------------------------------------------------
+// BILU numeric refactorisation on a kept pattern: the IKJ form in FP64, one
+// thread per factor row, one launch per level of the forward sweep (a row
+// reads only rows of earlier levels).  Every product and sum is rounded on
+// its own, in the order of the host factorisation, so the factors are the
+// host's bit for bit.
+// ---------------------------------------------------------------------------
+// lu[k] = the block of A that factor entry k starts from (zero for fill)
+template <int NV>
+__global__ void __launch_bounds__(kBlock) k_ilu_load(int nnzf, const int *__restrict__ src,
+                                                     const double *__restrict__ A, double *__restrict__ lu) {
+  constexpr int B2 = NV * NV;
+  const size_t t = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  if (t >= (size_t)nnzf * B2) return;
+  const size_t k = t / B2;
+  const int s = src[k];
+  lu[t] = s >= 0 ? A[(size_t)s * B2 + (t - k * B2)] : 0.0;
+}
+
+// c = a b (nv x nv, row-major), each entry summed from 0 over ascending k
+template <int NV>
+__device__ __forceinline__ void ilu_blk_mul(const double *a, const double *b, double *c) {
+#pragma clang fp contract(off)
+  for (int r = 0; r < NV; r++)
+    for (int q = 0; q < NV; q++) {
+      double s = 0.0;
+      for (int k = 0; k < NV; k++) s += a[r * NV + k] * b[k * NV + q];
+      c[r * NV + q] = s;
+    }
+}
+
+// inverse by Gauss-Jordan elimination with partial pivoting; false on a zero
+// or non-finite pivot
+template <int NV>
+__device__ __forceinline__ bool ilu_blk_inv(const double *a, double *inv) {
+#pragma clang fp contract(off)
+  double m[NV][2 * NV];
+  for (int r = 0; r < NV; r++)
+    for (int q = 0; q < 2 * NV; q++) m[r][q] = q < NV ? a[r * NV + q] : (q - NV == r ? 1.0 : 0.0);
+  for (int k = 0; k < NV; k++) {
+    int p = k;
+    for (int r = k + 1; r < NV; r++)
+      if (fabs(m[r][k]) > fabs(m[p][k])) p = r;
+    if (m[p][k] == 0.0 || !isfinite(m[p][k])) return false;
+    if (p != k)
+      for (int q = 0; q < 2 * NV; q++) {
+        const double x = m[k][q];
+        m[k][q] = m[p][q];
+        m[p][q] = x;
+      }
+    const double d = m[k][k];
+    for (int q = 0; q < 2 * NV; q++) m[k][q] /= d;
+    for (int r = 0; r < NV; r++) {
+      if (r == k) continue;
+      const double f = m[r][k];
+      for (int q = 0; q < 2 * NV; q++) m[r][q] -= f * m[k][q];
+    }
+  }
+  for (int r = 0; r < NV; r++)
+    for (int q = 0; q < NV; q++) inv[r * NV + q] = m[r][NV + q];
+  return true;
+}
+
+// rows fwd[p0 .. p0+cnt-1] (factor positions of one forward level):
+// L_pq = A_pq U_qq^{-1} for the lower entries in column order, then
+// A_pj -= L_pq U_qj for every upper entry (q, j) whose column is in row p;
+// finally dinvp[p] = U_pp^{-1} (*bad = 1 on a zero pivot)
+template <int NV>
+__global__ void __launch_bounds__(kBlock) k_ilu_factor(int p0, int cnt, const int *__restrict__ fwd,
+                                                       const int *__restrict__ frp, const int *__restrict__ fci,
+                                                       const int *__restrict__ dpos, double *__restrict__ lu,
+                                                       double *__restrict__ dinvp, int *__restrict__ bad) {
+#pragma clang fp contract(off)
+  constexpr int B2 = NV * NV;
+  const int t = blockIdx.x * kBlock + threadIdx.x;
+  if (t >= cnt) return;
+  const int p = fwd[p0 + t];
+  const int e = frp[p + 1], dp = dpos[p];
+  double L[B2], prod[B2], inv[B2];
+  for (int k = frp[p]; k < dp; k++) {
+    const int q = fci[k];
+    ilu_blk_mul<NV>(lu + (size_t)k * B2, dinvp + (size_t)q * B2, L);
+    for (int x = 0; x < B2; x++) lu[(size_t)k * B2 + x] = L[x];
+    for (int u = dpos[q] + 1; u < frp[q + 1]; u++) {
+      const int j = fci[u];
+      int lo = k + 1, hi = e - 1, at = -1;  // columns of row p ascending; j > q puts it after k
+      while (lo <= hi) {
+        const int mid = (lo + hi) >> 1, c = fci[mid];
+        if (c == j) {
+          at = mid;
+          break;
+        }
+        if (c < j)
+          lo = mid + 1;
+        else
+          hi = mid - 1;
+      }
+      if (at < 0) continue;
+      ilu_blk_mul<NV>(L, lu + (size_t)u * B2, prod);
+      for (int x = 0; x < B2; x++) lu[(size_t)at * B2 + x] -= prod[x];
+    }
+  }
+  if (!ilu_blk_inv<NV>(lu + (size_t)dp * B2, inv)) {
+    *bad = 1;
+    for (int x = 0; x < B2; x++) inv[x] = 0.0;
+  }
+  for (int x = 0; x < B2; x++) dinvp[(size_t)p * B2 + x] = inv[x];
+}
+
+// the factor entries into the blocks of the two sweeps (dst >= 0: f_val,
+// dst <= -2: b_val at -dst-2, -1: diagonal), U_pp^{-1} into cell order
+template <int NV, typename T>
+__global__ void __launch_bounds__(kBlock) k_ilu_store(int nnzf, int n, const int *__restrict__ dst,
+                                                      const int *__restrict__ order, const double *__restrict__ lu,
+                                                      const double *__restrict__ dinvp, T *__restrict__ f_val,
+                                                      T *__restrict__ b_val, T *__restrict__ dinv) {
+  constexpr int B2 = NV * NV;
+  const size_t t = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  const size_t ne = (size_t)nnzf * B2;
+  if (t < ne) {
+    const size_t k = t / B2, x = t - k * B2;
+    const int d = dst[k];
+    if (d >= 0)
+      f_val[(size_t)d * B2 + x] = T(lu[t]);
+    else if (d <= -2)
+      b_val[(size_t)(-d - 2) * B2 + x] = T(lu[t]);
+  } else if (t < ne + (size_t)n * B2) {
+    const size_t u = t - ne, p = u / B2;
+    dinv[(size_t)order[p] * B2 + (u - p * B2)] = T(dinvp[u]);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // FP64 BSR product for the Arnoldi step and the true residual
 //   y = A x (RESID = false),  y = b - A x (RESID = true)
 // 64 block rows per workgroup, NV threads per block row (one per equation).

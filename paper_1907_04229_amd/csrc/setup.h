@@ -77,6 +77,14 @@ struct IluHost {
   std::vector<int> b_rows, b_lev_ptr, b_ptr, b_col;
   std::vector<double> b_val;     // nv*nv per block, strictly upper U
   std::vector<double> dinv;      // nv*nv per cell (natural cell index), inverse of U_ii
+  // the factor pattern in factor order, kept for a numeric refactorisation of
+  // new values on the same pattern: row p (cell order[p]) holds entries
+  // frp[p] .. frp[p+1]-1, columns fci (factor positions, ascending), each the
+  // block src of A (-1: fill, starts at zero); dpos[p] is its diagonal entry;
+  // dst[k] places entry k in the sweeps: >= 0 block index in f_val, <= -2
+  // block index -dst[k]-2 in b_val, -1 the diagonal; fwd: factor positions in
+  // forward-sweep order (f_lev_ptr delimits its levels)
+  std::vector<int> frp, fci, src, dpos, dst, fwd;
 };
 
 // Throws Error (CPTR_ERR_SINGULAR_BLOCK on a zero pivot).

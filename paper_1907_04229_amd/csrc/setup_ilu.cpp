@@ -194,14 +194,16 @@ void ilu_build(int n, int nv, const int *rp, const int *ci, const double *vals,
               &out.dinv[(size_t)out.order[p] * b2]);
 
   // sweep schedules: positions sorted by (level, position)
+  out.dst.assign(nnzf, -1);
   auto schedule = [&](const std::vector<int> &lev, int nlev, bool lower, std::vector<int> &rows,
                       std::vector<int> &lev_ptr, std::vector<int> &ptr, std::vector<int> &col,
-                      std::vector<double> &val) {
+                      std::vector<double> &val, std::vector<int> *order_out) {
     lev_ptr.assign(nlev + 1, 0);
     for (int p = 0; p < n; p++) lev_ptr[lev[p] + 1]++;
     for (int l = 0; l < nlev; l++) lev_ptr[l + 1] += lev_ptr[l];
     std::vector<int> fill(lev_ptr.begin(), lev_ptr.end() - 1), byp(n);
     for (int p = 0; p < n; p++) byp[fill[lev[p]]++] = p;
+    if (order_out) *order_out = byp;
     rows.resize(n);
     ptr.assign(n + 1, 0);
     col.clear();
@@ -212,14 +214,19 @@ void ilu_build(int n, int nv, const int *rp, const int *ci, const double *vals,
       int b = lower ? frp[p] : dpos[p] + 1;
       int e = lower ? dpos[p] : frp[p + 1];
       for (int k = b; k < e; k++) {
+        out.dst[k] = lower ? int(col.size()) : -int(col.size()) - 2;
         col.push_back(out.order[fci[k]]);
         val.insert(val.end(), &lu[(size_t)k * b2], &lu[(size_t)k * b2] + b2);
       }
       ptr[t + 1] = int(col.size());
     }
   };
-  schedule(ll, nll, true, out.f_rows, out.f_lev_ptr, out.f_ptr, out.f_col, out.f_val);
-  schedule(lu_, nlu, false, out.b_rows, out.b_lev_ptr, out.b_ptr, out.b_col, out.b_val);
+  schedule(ll, nll, true, out.f_rows, out.f_lev_ptr, out.f_ptr, out.f_col, out.f_val, &out.fwd);
+  schedule(lu_, nlu, false, out.b_rows, out.b_lev_ptr, out.b_ptr, out.b_col, out.b_val, nullptr);
+  out.frp.swap(frp);
+  out.fci.swap(fci);
+  out.src.swap(src);
+  out.dpos.swap(dpos);
 }
 
 }  // namespace cptr

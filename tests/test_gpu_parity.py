@@ -452,6 +452,50 @@ def test_update_values_equals_fresh_setup(name, first):
     f.close()
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("second,level", [("bilu0", 0), ("bilu0_mc", 0), ("bilu0", 1), ("bilu0_mc", 1)])
+def test_update_values_refactors_the_ilu_bit_exact(precision, second, level):
+    """Numeric re-setup of the block ILU on the GPU (kept order, pattern and
+    schedules): for the values of a different field on the same grid the
+    factors, and so the application, equal a fresh host setup bit for bit."""
+    banner(f"ilu refactorisation {precision} {second} level {level}")
+    a = make_problem(shape=(12, 10, 6), kind="gaussian", sigma=2.0, corr_len=3.0, seed=31, three_phase=True)
+    b = make_problem(shape=(12, 10, 6), kind="gaussian", sigma=2.0, corr_len=3.0, seed=32, three_phase=True)
+    for pa, pb in ((a, b), (prob("ragged"), None)):
+        if pb is None:  # a two-phase ragged grid: new values 2A with one block row perturbed
+            import copy
+            pb = copy.copy(pa)
+            v = pa.vals.reshape(-1, pa.nv, pa.nv) * 2.0
+            v[pa.row_ptr[3]:pa.row_ptr[4]] *= 1.5
+            pb.vals = np.ascontiguousarray(v.reshape(-1))
+        s = solver(pa, precision=precision, first_stage="none", second_stage=second, ilu_level=level)
+        s.update_values(pb)
+        f = solver(pb, precision=precision, first_stage="none", second_stage=second, ilu_level=level)
+        v = dev(np.random.default_rng(17).standard_normal(pa.n * pa.nv))
+        assert torch.equal(s.apply(v), f.apply(v))
+        s.close()
+        f.close()
+
+
+def test_update_values_reports_a_zero_ilu_pivot():
+    """A zero diagonal block in the new values: the GPU refactorisation reports
+    CPTR_ERR_SINGULAR_BLOCK (the handle is then destroyed)."""
+    banner("ilu refactorisation, zero pivot")
+    import copy
+    pr = prob("small")
+    s = solver(pr, precision="fp64", first_stage="none", second_stage="bilu0")
+    pb = copy.copy(pr)
+    v = pr.vals.reshape(-1, pr.nv, pr.nv).copy()
+    i = 5
+    d = [k for k in range(pr.row_ptr[i], pr.row_ptr[i + 1]) if pr.col_idx[k] == i][0]
+    v[d] = 0.0
+    pb.vals = np.ascontiguousarray(v.reshape(-1))
+    with pytest.raises(cptr.CptrError) as e:
+        s.update_values(pb)
+    assert e.value.code == -4
+    s.close()
+
+
 def test_update_values_new_field_converges():
     """Re-setup for a different permeability field on the same grid: the
     aggregates of the first field are kept; FGMRES reaches the tolerance with
