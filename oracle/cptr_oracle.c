@@ -1001,6 +1001,64 @@ static csr extract(const orc *h, int r, int c) {
 }
 
 
+/* The simple algebraic Schur complement approximation of Section 3.3.1:
+ * S = A_TT - A_Tp diag(A_pp)^{-1} A_pT.  Row i holds every cell l reached
+ * from i in at most two steps of the cell graph, columns ascending.  Entry
+ * (i, l) is A_TT(i, l) (zero where A has no block), then for every block
+ * (i, j) of row i in ascending j and every block (j, l) of row j in ascending l
+ * it loses (A_Tp(i, j) / A_pp(j, j)) * A_pT(j, l).  Returns 0 and leaves *out
+ * empty if some A_pp(j, j) is zero. */
+static int schur_diag(const orc *h, csr *out) {
+  int n = h->n, nv = h->nv, ip = h->o.ip, iT = h->o.iT;
+  const int *rp = h->rp, *ci = h->ci;
+  const double *v = h->v;
+  int *mark = (int *)malloc(sizeof(int) * (size_t)(n > 0 ? n : 1));
+  double *acc = (double *)calloc((size_t)(n > 0 ? n : 1), sizeof(double));
+  double *app = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+  for (int i = 0; i < n; i++) {
+    mark[i] = -1;
+    app[i] = 0.0;
+    for (int k = rp[i]; k < rp[i + 1]; k++)
+      if (ci[k] == i) app[i] = v[(size_t)k * nv * nv + ip * nv + ip];
+  }
+  int ok = 1;
+  for (int i = 0; i < n; i++) ok &= app[i] != 0.0;
+  /* pattern: count, then fill and sort each row */
+  int total = 0;
+  for (int i = 0; i < n; i++)
+    for (int k = rp[i]; k < rp[i + 1]; k++)
+      for (int m = rp[ci[k]]; m < rp[ci[k] + 1]; m++)
+        if (mark[ci[m]] != i) { mark[ci[m]] = i; total++; }
+  csr s;
+  csr_alloc(&s, n, n, total);
+  for (int i = 0; i < n; i++) mark[i] = -1;
+  int pos = 0;
+  for (int i = 0; i < n && ok; i++) {
+    int b = pos;
+    for (int k = rp[i]; k < rp[i + 1]; k++)
+      for (int m = rp[ci[k]]; m < rp[ci[k] + 1]; m++)
+        if (mark[ci[m]] != i) { mark[ci[m]] = i; s.ci[pos++] = ci[m]; }
+    for (int x = b + 1; x < pos; x++) {  /* insertion sort of the row's columns */
+      int c = s.ci[x], y = x - 1;
+      while (y >= b && s.ci[y] > c) { s.ci[y + 1] = s.ci[y]; y--; }
+      s.ci[y + 1] = c;
+    }
+    for (int x = b; x < pos; x++) acc[s.ci[x]] = 0.0;
+    for (int k = rp[i]; k < rp[i + 1]; k++) acc[ci[k]] = v[(size_t)k * nv * nv + iT * nv + iT];
+    for (int k = rp[i]; k < rp[i + 1]; k++) {
+      int j = ci[k];
+      double a = v[(size_t)k * nv * nv + iT * nv + ip] / app[j];
+      for (int m = rp[j]; m < rp[j + 1]; m++) acc[ci[m]] -= a * v[(size_t)m * nv * nv + ip * nv + iT];
+    }
+    for (int x = b; x < pos; x++) s.v[x] = acc[s.ci[x]];
+    s.rp[i + 1] = pos;
+  }
+  free(mark); free(acc); free(app);
+  if (!ok) { csr_free(&s); return 0; }
+  *out = s;
+  return 1;
+}
+
 /* Decoupling operator G = [I, -D; 0, I] of Section 3.1 for a split of the
  * unknowns into primary ones (pressure for CPR; pressure and temperature for
  * the CPTR extension of Section 3.2, S_0 = A_00 - D A_s0) and the secondary
@@ -1136,11 +1194,20 @@ void *orc_create(int n, int nv, const int *rp, const int *ci, const double *vals
     h->have_p = 1;
     if (st == 0 && (o->first_stage == ORC_FIRST_CPTR_BLOCK ||
                     o->first_stage == ORC_FIRST_CPTR_LOWER || o->first_stage == ORC_FIRST_CPTR_BD)) {
-      /* the second hierarchy: S~_T (eq:Se), or A_TT for the block-diagonal stage */
-      csr s = o->first_stage == ORC_FIRST_CPTR_BD ? extract(h, o->iT, o->iT) : csr_copy(n, srp, sci, svals);
-      st = amg_setup(&h->amg_s, s, o->theta, o->max_levels, o->coarse_size, o->seed,
-                     o->sweeps, o->smooth_p_T < 0 ? o->smooth_p : o->smooth_p_T, o->smoother);
-      h->have_s = 1;
+      /* the second hierarchy: S~_T (eq:Se, or one of the algebraic
+       * approximations of Section 3.3.1), or A_TT for the block-diagonal stage */
+      csr s;
+      if (o->first_stage == ORC_FIRST_CPTR_BD || o->schur == 1)
+        s = extract(h, o->iT, o->iT);
+      else if (o->schur == 2) {
+        if (!schur_diag(h, &s)) st = -14;
+      } else
+        s = csr_copy(n, srp, sci, svals);
+      if (st == 0) {
+        st = amg_setup(&h->amg_s, s, o->theta, o->max_levels, o->coarse_size, o->seed,
+                       o->sweeps, o->smooth_p_T < 0 ? o->smooth_p : o->smooth_p_T, o->smoother);
+        h->have_s = 1;
+      }
     }
   }
   if (st == 0 && (o->second_stage == ORC_SECOND_BILU0 || o->second_stage == ORC_SECOND_BILU0_MC)) {

@@ -45,6 +45,8 @@ typedef struct {
   int decoupling;      /* CPR and CPTR-uAMG first stages: 0 none, 1 Quasi-IMPES, 2 True-IMPES
                           (Section 3.1; its extension to p-T in Section 3.2) */
   int ilu_level;       /* level of fill of the block ILU second stage: 0 (BILU(0)) or 1 (BILU(1)) */
+  int schur;           /* S~_T of the block first stages: 0 the assembled one passed in (eq:Se),
+                          1 A_TT, 2 A_TT - A_Tp diag(A_pp)^{-1} A_pT (Section 3.3.1) */
 } orc_opts;
 
 typedef struct {

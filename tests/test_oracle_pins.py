@@ -607,6 +607,65 @@ def test_pT_decoupling_without_saturation_coupling_changes_nothing(tiny, oracle_
     assert np.array_equal(plain, ti)
 
 
+# ---------------------------------------------------------------- algebraic S~_T
+def test_schur_diag_pattern_is_the_two_step_neighbourhood(oracle_lib):
+    # Section 3.3.1's S~_diag = A_TT - A_Tp diag(A_pp)^-1 A_pT couples each
+    # cell to the cells within two steps of the 7-point graph: on a box grid,
+    # offsets with |dx| + |dy| + |dz| <= 2 that stay inside
+    nx, ny, nz = 5, 4, 3
+    pr = make_problem(shape=(nx, ny, nz), kind="iid", seed=21)
+    o = O.Oracle.from_problem(pr, first="cptr", second="none", coarse_size=10_000, schur="diag")
+    rp, ci, _ = o.amg_levels(1)[0]["A"]
+    for c in range(pr.n):
+        x, y, z = c % nx, (c // nx) % ny, c // (nx * ny)
+        want = sorted(xx + nx * (yy + ny * zz) for xx in range(nx) for yy in range(ny) for zz in range(nz)
+                      if abs(xx - x) + abs(yy - y) + abs(zz - z) <= 2)
+        assert list(ci[rp[c]:rp[c + 1]]) == want
+
+
+def _diagonal_pressure_block(pr):
+    """Values of pr with the pressure-pressure couplings between cells removed."""
+    nv = pr.nv
+    vals = pr.vals.reshape(-1, nv, nv).copy()
+    rows = np.repeat(np.arange(pr.n), np.diff(pr.row_ptr))
+    vals[pr.col_idx != rows, 0, 0] = 0.0
+    return np.ascontiguousarray(vals.reshape(-1))
+
+
+def test_schur_diag_is_exact_when_A_pp_is_diagonal(tiny, oracle_lib):
+    # with A_pp diagonal, diag(A_pp) = A_pp and S~_diag is the exact Schur
+    # complement: the block preconditioner with exact solves gives A00^{-1}
+    # (eq:Afact, eq:Ainv), whatever S~_T the caller passed
+    n, nv = tiny.n, tiny.nv
+    vals = _diagonal_pressure_block(tiny)
+    junk = np.ones_like(tiny.st_vals)
+    o = O.Oracle(n, nv, tiny.row_ptr, tiny.col_idx, vals, tiny.st_row_ptr, tiny.st_col_idx, junk,
+                 first="cptr", second="none", coarse_size=10_000, schur="diag")
+    A = dense_bsr(tiny.row_ptr, tiny.col_idx, vals, nv)
+    App, ApT, ATp, ATT = A[0::nv, 0::nv], A[0::nv, nv - 1::nv], A[nv - 1::nv, 0::nv], A[nv - 1::nv, nv - 1::nv]
+    S = dense_csr(*o.amg_levels(1)[0]["A"])
+    want_S = ATT - ATp @ np.linalg.solve(App, ApT)
+    assert np.allclose(S, want_S, rtol=1e-12, atol=1e-12 * np.abs(want_S).max())
+    v = np.random.default_rng(11).standard_normal(n * nv)
+    x1 = o.first_stage(v)
+    want = np.linalg.solve(np.block([[App, ApT], [ATp, ATT]]), np.concatenate([v[0::nv], v[nv - 1::nv]]))
+    got = np.concatenate([x1[0::nv], x1[nv - 1::nv]])
+    assert np.allclose(got, want, rtol=1e-9, atol=1e-9 * np.abs(want).max())
+
+
+def test_schur_att_is_the_temperature_block(tiny, oracle_lib):
+    # S~_ATT = A_TT (Section 3.3.1), the caller's S~_T ignored
+    n, nv = tiny.n, tiny.nv
+    A = dense_bsr(tiny.row_ptr, tiny.col_idx, tiny.vals, nv)
+    junk = np.ones_like(tiny.st_vals)
+    o = O.Oracle(n, nv, tiny.row_ptr, tiny.col_idx, tiny.vals, tiny.st_row_ptr, tiny.st_col_idx, junk,
+                 first="cptr", second="none", coarse_size=8, schur="att")
+    assert np.array_equal(dense_csr(*o.amg_levels(1)[0]["A"]), A[nv - 1::nv, nv - 1::nv])
+    ref = O.Oracle.from_problem(tiny, first="cptr_bd", second="none", coarse_size=8)
+    for a, b in zip(o.amg_levels(1), ref.amg_levels(1)):
+        assert all(np.array_equal(x, y) for x, y in zip(a["A"], b["A"]))
+
+
 def _local_secondary(pr, zero):
     """Values of pr with the secondary (non-pressure, pressure in slot 0)
     columns (zero = "cols") or rows (zero = "rows") of every off-diagonal
