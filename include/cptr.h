@@ -77,6 +77,14 @@ extern "C" {
 #define CPTR_DECOUPLE_QI 1       /* Quasi-IMPES: D = diag(A_0s) diag(A_ss)^-1 */
 #define CPTR_DECOUPLE_TI 2       /* True-IMPES:  D = colsum(A_0s) colsum(A_ss)^-1 */
 
+/* The Schur complement approximation S~_T of the block first stages */
+#define CPTR_SCHUR_ASSEMBLED 0   /* the caller's S~_T of eq:Se (needs the PDE; passed to cptr_setup) */
+#define CPTR_SCHUR_ATT 1         /* A_TT (Section 3.3.1) */
+#define CPTR_SCHUR_DIAG 2        /* A_TT - A_Tp diag(A_pp)^-1 A_pT (Section 3.3.1), on the cells
+                                    within two steps of the cell graph; entry (i, l) starts from
+                                    A_TT(i, l) and loses (A_Tp(i,j) / A_pp(j,j)) A_pT(j,l) for the
+                                    blocks (i, j) of row i, then (j, l) of row j, both ascending */
+
 /* second stage */
 #define CPTR_SECOND_NONE 0       /* z = x1 */
 #define CPTR_SECOND_BILU0 1      /* block ILU(0), natural order, level-scheduled solves */
@@ -144,6 +152,7 @@ typedef struct {
   int ilu_level;         /* level of fill of the BILU second stages: 0 (BILU(0)) or 1 (BILU(1):
                             the blocks of A and the level-1 fill, Section 4's ILU(1)) (0);
                             the learned stage's fallback stays BILU(0) */
+  int schur;             /* S~_T of CPTR_FIRST_BLOCK(_LOWER): CPTR_SCHUR_* (ASSEMBLED) */
 } cptr_options;
 
 typedef struct {
@@ -188,8 +197,10 @@ void cptr_default_options(cptr_options *opt);
  *   out   receives the handle (NULL on failure).
  *   A     must stay alive and unchanged until cptr_destroy: A->vals (FP64) is
  *         BORROWED for the FP64 Arnoldi products; everything derived is owned.
- *   S_T   the assembled S~_T of eq:Se; required for CPTR_FIRST_BLOCK(_LOWER),
- *         ignored (may be NULL) otherwise.
+ *   S_T   the assembled S~_T of eq:Se; required for CPTR_FIRST_BLOCK(_LOWER)
+ *         with CPTR_SCHUR_ASSEMBLED, ignored (may be NULL) otherwise; with
+ *         CPTR_SCHUR_ATT / _DIAG the library forms S~_T from A (a zero A_pp
+ *         diagonal entry gives CPTR_ERR_SINGULAR_BLOCK).
  *   opt   NULL for defaults.
  * Blocks until setup is complete.  Errors: CPTR_ERR_INVALID_ARG (sizes,
  * unsorted or out-of-range columns, missing diagonal, nv not 3/4, ip == iT,
@@ -246,7 +257,9 @@ int cptr_krylov_vector(const cptr_handle *h, int j, double *out, void *stream);
  * system per nonlinear iteration).  A_vals: device FP64 BSR values in the
  * layout of cptr_bsr.vals (the handle borrows this pointer from now on, as it
  * did the original); S_vals: device FP64 values of S~_T in the pattern given
- * to cptr_setup (required for CPTR_FIRST_BLOCK / _BLOCK_LOWER, else ignored).
+ * to cptr_setup (required for CPTR_FIRST_BLOCK / _BLOCK_LOWER with
+ * CPTR_SCHUR_ASSEMBLED, else ignored: the algebraic S~_T is formed anew from
+ * A_vals).
  * The aggregates of both AMG hierarchies and the block ILU's order, pattern
  * and level schedules are kept; prolongator values, Galerkin products and the
  * coarsest inverse are recomputed on the host, the block ILU factors on the

@@ -19,6 +19,7 @@ FIRST = {"none": 0, "cptr": 1, "cptr_lower": 2, "cpr": 3, "cptr_bd": 4, "cptr_ua
 SECOND = {"none": 0, "bilu0": 1, "bilu0_mc": 2, "identity": 3, "learned": 4}
 PRECISION = {"fp64": 0, "fp32": 1}
 DECOUPLING = {"none": 0, "qi": 1, "ti": 2}
+SCHUR = {"assembled": 0, "att": 1, "diag": 2}
 
 
 class Options(C.Structure):
@@ -29,7 +30,7 @@ class Options(C.Structure):
                 ("amg_smooth_p_T", C.c_int),
                 ("use_graph", C.c_int), ("resid_fp64", C.c_int),
                 ("scalar_dia", C.c_int), ("lrn_columns", C.c_int), ("decoupling", C.c_int),
-                ("ilu_level", C.c_int)]
+                ("ilu_level", C.c_int), ("schur", C.c_int)]
 
 
 class Bsr(C.Structure):
@@ -147,6 +148,8 @@ def cptr_default_options(**kw):
             v = PRECISION[v]
         if k == "decoupling" and isinstance(v, str):
             v = DECOUPLING[v]
+        if k == "schur" and isinstance(v, str):
+            v = SCHUR[v]
         setattr(o, k, v)
     return o
 

@@ -963,6 +963,7 @@ static void build_precond(cptr_handle *h, const std::vector<int> &rp, const std:
                           const std::vector<std::vector<int>> *agg_p = nullptr,
                           const std::vector<std::vector<int>> *agg_s = nullptr,
                           IluDev<T> *keep_ilu = nullptr) {
+#pragma clang fp contract(off)  // the FP64 setup arithmetic here rounds every operation, as the oracle does
   auto pc = std::make_unique<Precond<T>>();
   Precond<T> &P = *pc;
   const cptr_options &o = h->op.o;
@@ -1244,6 +1245,7 @@ static void validate_and_fetch(const cptr_bsr *A, const cptr_csr *S, const cptr_
   if (o.first_stage < 0 || o.first_stage > 5) throw Error{CPTR_ERR_INVALID_ARG, "invalid first stage"};
   if (o.decoupling < 0 || o.decoupling > 2) throw Error{CPTR_ERR_INVALID_ARG, "invalid decoupling"};
   if (o.ilu_level != 0 && o.ilu_level != 1) throw Error{CPTR_ERR_UNSUPPORTED, "ilu_level must be 0 or 1"};
+  if (o.schur < CPTR_SCHUR_ASSEMBLED || o.schur > CPTR_SCHUR_DIAG) throw Error{CPTR_ERR_INVALID_ARG, "invalid schur"};
   if (o.decoupling != 0 && o.first_stage != CPTR_FIRST_CPR && o.first_stage != CPTR_FIRST_UAMG)
     throw Error{CPTR_ERR_UNSUPPORTED, "decoupling operators apply to the CPR and CPTR-uAMG first stages only"};
   if (o.second_stage < 0 || o.second_stage > 4)
@@ -1279,7 +1281,10 @@ static void validate_and_fetch(const cptr_bsr *A, const cptr_csr *S, const cptr_
   for (double v : vals)
     if (!std::isfinite(v)) throw Error{CPTR_ERR_NONFINITE, "non-finite value in A"};
   const bool need_s = o.first_stage == CPTR_FIRST_BLOCK || o.first_stage == CPTR_FIRST_BLOCK_LOWER;
-  if (need_s) {
+  if (need_s && o.schur != CPTR_SCHUR_ASSEMBLED) {
+    // Section 3.3.1's algebraic approximations, formed from A
+    sh = schur_algebraic(n, nv, o.ip, o.iT, rp.data(), ci.data(), vals.data(), o.schur == CPTR_SCHUR_DIAG);
+  } else if (need_s) {
     if (!S || S->n != n || S->nnz <= 0 || !S->row_ptr || !S->col_idx || !S->vals)
       throw Error{CPTR_ERR_INVALID_ARG, "the block first stage needs S~_T on the cell graph"};
     sh.nr = sh.nc = n;
@@ -1671,6 +1676,7 @@ void cptr_default_options(cptr_options *o) {
   o->resid_fp64 = 0;
   o->scalar_dia = 1;
   o->lrn_columns = 1;
+  o->schur = CPTR_SCHUR_ASSEMBLED;
   o->decoupling = CPTR_DECOUPLE_NONE;
   o->ilu_level = 0;
 }
@@ -1828,7 +1834,8 @@ int cptr_update_values(cptr_handle *h, const double *A_vals, const double *S_val
   const int fs = h->op.o.first_stage;
   const bool need_s = fs == CPTR_FIRST_BLOCK || fs == CPTR_FIRST_BLOCK_LOWER;
   const bool two_hier = need_s || fs == CPTR_FIRST_BD;  // a second AMG hierarchy to keep
-  if (need_s && !S_vals) return fail(Error{CPTR_ERR_INVALID_ARG, "S~_T values required by this first stage"});
+  const bool caller_s = need_s && h->op.o.schur == CPTR_SCHUR_ASSEMBLED;
+  if (caller_s && !S_vals) return fail(Error{CPTR_ERR_INVALID_ARG, "S~_T values required by this first stage"});
   try {
     auto t0 = std::chrono::steady_clock::now();
     CPTR_HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
@@ -1842,7 +1849,10 @@ int cptr_update_values(cptr_handle *h, const double *A_vals, const double *S_val
     for (double v : vals)
       if (!std::isfinite(v)) throw Error{CPTR_ERR_NONFINITE, "non-finite matrix value"};
     HostCSR sh;
-    if (need_s) {
+    if (need_s && !caller_s) {
+      sh = schur_algebraic(n, nv, h->op.o.ip, h->op.o.iT, rp.data(), ci.data(), vals.data(),
+                           h->op.o.schur == CPTR_SCHUR_DIAG);
+    } else if (need_s) {
       sh.nr = sh.nc = n;
       sh.rp = h->st_rp;
       sh.ci = h->st_ci;

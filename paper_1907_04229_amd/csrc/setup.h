@@ -63,6 +63,14 @@ void amg_build(const HostCSR &fine, const AmgParams &prm, AmgHost &out,
 void uamg_build(const HostCSR &fine, int np, const AmgParams &prm_p, const AmgParams &prm_T, AmgHost &out,
                 const std::vector<std::vector<int>> *fixed = nullptr);
 
+// Algebraic S~_T from the blocks of A (Section 3.3.1): diag = false: A_TT on
+// the cell graph; diag = true: A_TT - A_Tp diag(A_pp)^{-1} A_pT on the cells
+// within two steps, entry (i, l) from A_TT(i, l), then minus
+// (A_Tp(i,j) / A_pp(j,j)) * A_pT(j,l) for (i, j) in row i, (j, l) in row j, both
+// ascending.  Throws CPTR_ERR_SINGULAR_BLOCK on a zero A_pp(j,j).
+HostCSR schur_algebraic(int n, int nv, int ip, int iT, const int *rp, const int *ci, const double *vals,
+                        bool diag);
+
 // Block ILU(0) in a given row order, FP64 on the host.
 struct IluHost {
   int n = 0, nv = 0, ncolor = 0;

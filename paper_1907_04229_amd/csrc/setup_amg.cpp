@@ -348,6 +348,52 @@ void finish(AmgHost &out) {
 
 }  // namespace
 
+HostCSR schur_algebraic(int n, int nv, int ip, int iT, const int *rp, const int *ci, const double *vals,
+                        bool diag) {
+  auto blk = [&](int k, int r, int c) { return vals[((size_t)k * nv + r) * nv + c]; };
+  HostCSR s;
+  s.nr = s.nc = n;
+  s.rp.assign(rp, rp + n + 1);
+  if (!diag) {
+    s.ci.assign(ci, ci + rp[n]);
+    s.v.resize(rp[n]);
+    for (int k = 0; k < rp[n]; k++) s.v[k] = blk(k, iT, iT);
+    return s;
+  }
+  std::vector<double> app(n, 0.0), acc(n, 0.0);
+  for (int i = 0; i < n; i++)
+    for (int k = rp[i]; k < rp[i + 1]; k++)
+      if (ci[k] == i) app[i] = blk(k, ip, ip);
+  for (int i = 0; i < n; i++)
+    if (app[i] == 0.0)
+      throw Error{CPTR_ERR_SINGULAR_BLOCK, "zero pressure diagonal entry in cell " + std::to_string(i)};
+  std::vector<int> mark(n, -1), cols;
+  s.rp.assign(n + 1, 0);
+  for (int i = 0; i < n; i++) {
+    cols.clear();
+    for (int k = rp[i]; k < rp[i + 1]; k++)
+      for (int m = rp[ci[k]]; m < rp[ci[k] + 1]; m++)
+        if (mark[ci[m]] != i) {
+          mark[ci[m]] = i;
+          cols.push_back(ci[m]);
+        }
+    std::sort(cols.begin(), cols.end());
+    for (int l : cols) acc[l] = 0.0;
+    for (int k = rp[i]; k < rp[i + 1]; k++) acc[ci[k]] = blk(k, iT, iT);
+    for (int k = rp[i]; k < rp[i + 1]; k++) {
+      const int j = ci[k];
+      const double a = blk(k, iT, ip) / app[j];
+      for (int m = rp[j]; m < rp[j + 1]; m++) acc[ci[m]] -= a * blk(m, ip, iT);
+    }
+    for (int l : cols) {
+      s.ci.push_back(l);
+      s.v.push_back(acc[l]);
+    }
+    s.rp[i + 1] = int(s.ci.size());
+  }
+  return s;
+}
+
 void uamg_build(const HostCSR &fine, int np, const AmgParams &prm_p, const AmgParams &prm_T, AmgHost &out,
                 const std::vector<std::vector<int>> *fixed) {
   if (np < 0 || np > fine.nr) throw Error{CPTR_ERR_INVALID_ARG, "unknown-based AMG: bad pressure block size"};

@@ -300,6 +300,70 @@ def test_decoupled_first_stage_fp64(name, kind, first):
 
 
 @pytest.mark.parametrize("name", ["ragged", "three", "small"])
+@pytest.mark.parametrize("schur", ["att", "diag"])
+def test_algebraic_schur_fp64(name, schur):
+    """S~_T formed by the library from A (Section 3.3.1: A_TT, or
+    A_TT - A_Tp diag(A_pp)^-1 A_pT), with no S~_T passed: aggregates of both
+    hierarchies bit-exact, the S~_T V-cycle, first stage, application and
+    FGMRES (FP64) against the oracle."""
+    banner(f"algebraic schur {schur} {name}")
+    pr = prob(name)
+    rp, ci, vals = dev(pr.row_ptr, torch.int32), dev(pr.col_idx, torch.int32), dev(pr.vals)
+    opts = cptr.cptr_default_options(precision="fp64", first_stage="cptr", second_stage="bilu0",
+                                     schur=schur, amg_coarse_size=16)
+    h = cptr.cptr_setup(pr.n, pr.nv, rp, ci, vals, None, None, None, opts)
+    o = O.Oracle.from_problem(pr, first="cptr", second="bilu0", coarse_size=16, schur=schur)
+    for which in (0, 1):
+        ref = o.amg_levels(which)
+        for lev in range(len(ref) - 1):
+            assert np.array_equal(cptr.cptr_get_aggregates(h, which, lev, ref[lev]["n"]), ref[lev]["agg"])
+    rng = np.random.default_rng(19)
+    b = rng.standard_normal(pr.n)
+    x = torch.empty(pr.n, dtype=torch.float64, device=DEV)
+    cptr.cptr_vcycle(h, 1, dev(b), x)
+    v = rng.standard_normal(pr.n * pr.nv)
+    x1 = torch.empty_like(dev(v))
+    cptr.cptr_first_stage(h, dev(v), x1)
+    z = torch.empty_like(x1)
+    cptr.cptr_apply(h, dev(v), z)
+    torch.cuda.synchronize()
+    assert relerr(x.cpu().numpy(), o.vcycle(1, b)) <= 1e-10
+    assert relerr(x1.cpu().numpy(), o.first_stage(v)) <= 1e-10
+    assert relerr(z.cpu().numpy(), o.apply(v)) <= 1e-9
+    cptr.cptr_destroy(h)
+    s = solver(pr, precision="fp64", first_stage="cptr", second_stage="bilu0", schur=schur)
+    o = O.Oracle.from_problem(pr, first="cptr", second="bilu0", schur=schur)
+    xg, info = s.solve(dev(pr.b), restart=30, rtol=1e-6)
+    xo, io = o.fgmres(pr.b, m=30, rtol=1e-6)
+    err = np.linalg.norm(xg.cpu().numpy() - xo) / np.linalg.norm(xo)
+    print(f"iters gpu {info['iters']} oracle {io['iters']} err {err:.2e}")
+    assert info["converged"] == io["converged"] and abs(info["iters"] - io["iters"]) <= 1
+    if io["converged"]:
+        assert err <= 1e-8
+    s.close()
+
+
+@pytest.mark.parametrize("schur", ["att", "diag"])
+def test_update_values_with_algebraic_schur(schur):
+    """Re-setup with S~_T formed from the new values (none passed): bit-identical
+    to a fresh setup of 2A."""
+    banner(f"update_values, algebraic schur {schur}")
+    import copy
+    pr = prob("three")
+    pr2 = copy.copy(pr)
+    pr2.vals = pr.vals * 2.0
+    s = solver(pr, precision="fp64", second_stage="bilu0", schur=schur, amg_coarse_size=16)
+    vals2 = dev(pr2.vals)
+    cptr.cptr_update_values(s.h, vals2, None)
+    s.vals = vals2
+    f = solver(pr2, precision="fp64", second_stage="bilu0", schur=schur, amg_coarse_size=16)
+    v = dev(np.random.default_rng(23).standard_normal(pr.n * pr.nv))
+    assert torch.equal(s.apply(v), f.apply(v))
+    s.close()
+    f.close()
+
+
+@pytest.mark.parametrize("name", ["ragged", "three", "small"])
 @pytest.mark.parametrize("second", ["bilu0", "bilu0_mc"])
 def test_bilu1_fp64(name, second):
     """BILU(1) second stage (ilu_level = 1): level schedule bit-exact, FP64
