@@ -215,6 +215,47 @@ def test_two_grid_cycle_is_textbook(mid, sweeps, first, oracle_lib):
     assert np.allclose(got, x, rtol=1e-9, atol=1e-12 * np.abs(x).max())
 
 
+def _greedy_colours(A):
+    """Smallest colour not taken by a lower-numbered neighbour, natural order."""
+    n = A.shape[0]
+    col = np.zeros(n, int)
+    for i in range(n):
+        used = {col[j] for j in np.nonzero(A[i, :i])[0]}
+        c = 0
+        while c in used:
+            c += 1
+        col[i] = c
+    return col
+
+
+@pytest.mark.parametrize("first", ["cptr", "cptr_uamg"])
+@pytest.mark.parametrize("sweeps", [1, 2])
+def test_two_grid_gauss_seidel_is_textbook(mid, sweeps, first, oracle_lib):
+    # symmetric multicolour Gauss-Seidel as a matrix splitting: with colours
+    # c(i), a forward sweep is x <- (D + L_c)^{-1} (b - U_c x) (L_c: entries with
+    # c(j) < c(i), U_c: c(j) > c(i); same-colour rows are not coupled), a
+    # backward sweep x <- (D + U_c)^{-1} (b - L_c x); exact coarse correction
+    o = O.Oracle.from_problem(mid, first=first, coarse_size=8, max_levels=2, sweeps=sweeps, smoother="gs")
+    lv = o.amg_levels(0)
+    assert len(lv) == 2
+    A = dense_csr(*lv[0]["A"])
+    Pm = dense_csr(*lv[0]["P"], ncol=lv[1]["n"])
+    c = _greedy_colours(A)
+    off = A - np.diag(np.diag(A))
+    assert not (off[c[:, None] == c[None, :]]).any()   # a proper colouring
+    Lc = np.where(c[:, None] > c[None, :], A, 0.0)
+    Uc = np.where(c[:, None] < c[None, :], A, 0.0)
+    D = np.diag(np.diag(A))
+    b = np.random.default_rng(31).standard_normal(A.shape[0])
+    x = np.zeros_like(b)
+    for _ in range(sweeps):
+        x = np.linalg.solve(D + Lc, b - Uc @ x)
+    x = x + Pm @ np.linalg.solve(Pm.T @ A @ Pm, Pm.T @ (b - A @ x))
+    for _ in range(sweeps):
+        x = np.linalg.solve(D + Uc, b - Lc @ x)
+    assert np.allclose(o.vcycle(0, b), x, rtol=1e-9, atol=1e-12 * np.abs(x).max())
+
+
 def test_single_level_amg_is_exact(tiny, oracle_lib):
     o = O.Oracle.from_problem(tiny, coarse_size=1000)
     A = dense_csr(*csr_block(tiny, 0, 0))
