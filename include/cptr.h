@@ -77,6 +77,12 @@ extern "C" {
 #define CPTR_DECOUPLE_QI 1       /* Quasi-IMPES: D = diag(A_0s) diag(A_ss)^-1 */
 #define CPTR_DECOUPLE_TI 2       /* True-IMPES:  D = colsum(A_0s) colsum(A_ss)^-1 */
 
+/* AMG smoother (amg_sweeps passes before and after the coarse correction) */
+#define CPTR_SMOOTHER_L1JACOBI 0 /* x += D_l1^-1 (b - A x), D_l1 = diag(sum_j |a_ij|) */
+#define CPTR_SMOOTHER_GS 1       /* symmetric multicolour Gauss-Seidel: greedy colouring of each level
+                                    in natural order, colours ascending before the coarse correction
+                                    (from x = 0) and descending after it */
+
 /* The Schur complement approximation S~_T of the block first stages */
 #define CPTR_SCHUR_ASSEMBLED 0   /* the caller's S~_T of eq:Se (needs the PDE; passed to cptr_setup) */
 #define CPTR_SCHUR_ATT 1         /* A_TT (Section 3.3.1) */
@@ -153,6 +159,11 @@ typedef struct {
                             the blocks of A and the level-1 fill, Section 4's ILU(1)) (0);
                             the learned stage's fallback stays BILU(0) */
   int schur;             /* S~_T of CPTR_FIRST_BLOCK(_LOWER): CPTR_SCHUR_* (ASSEMBLED) */
+  int lrn_fallback;      /* CPTR_SECOND_LEARNED in fgmres_solve: 1 switch to the BILU(0)
+                            fallback on a non-finite Arnoldi step or a restart cycle whose true
+                            residual did not halve; 0 never (a non-finite step is then
+                            CPTR_ERR_NONFINITE) (1) */
+  int amg_smoother;      /* CPTR_SMOOTHER_* of every AMG hierarchy (L1JACOBI) */
 } cptr_options;
 
 typedef struct {

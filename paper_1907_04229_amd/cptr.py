@@ -20,6 +20,7 @@ SECOND = {"none": 0, "bilu0": 1, "bilu0_mc": 2, "identity": 3, "learned": 4}
 PRECISION = {"fp64": 0, "fp32": 1}
 DECOUPLING = {"none": 0, "qi": 1, "ti": 2}
 SCHUR = {"assembled": 0, "att": 1, "diag": 2}
+SMOOTHER = {"l1jacobi": 0, "gs": 1}
 
 
 class Options(C.Structure):
@@ -30,7 +31,8 @@ class Options(C.Structure):
                 ("amg_smooth_p_T", C.c_int),
                 ("use_graph", C.c_int), ("resid_fp64", C.c_int),
                 ("scalar_dia", C.c_int), ("lrn_columns", C.c_int), ("decoupling", C.c_int),
-                ("ilu_level", C.c_int), ("schur", C.c_int)]
+                ("ilu_level", C.c_int), ("schur", C.c_int), ("lrn_fallback", C.c_int),
+                ("amg_smoother", C.c_int)]
 
 
 class Bsr(C.Structure):
@@ -150,6 +152,8 @@ def cptr_default_options(**kw):
             v = DECOUPLING[v]
         if k == "schur" and isinstance(v, str):
             v = SCHUR[v]
+        if k == "amg_smoother" and isinstance(v, str):
+            v = SMOOTHER[v]
         setattr(o, k, v)
     return o
 

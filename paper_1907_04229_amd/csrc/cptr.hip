@@ -283,17 +283,21 @@ struct AmgDev {
   struct Level {
     SpOp<T> A, P, R;
     DevMem dinv, b, x, y, r;
+    DevMem gs_rp, gs_ci, gs_v, gs_rows;  // Gauss-Seidel: A as CSR, rows grouped by colour
+    std::vector<int> gs_ptr;             // colour c holds gs_rows[gs_ptr[c] .. gs_ptr[c+1])
     int n = 0;
   };
   std::vector<std::unique_ptr<Level>> lev;
   DevMem coarse_inv;
   int nc = 0;
   int sweeps = 1;
+  int smoother = CPTR_SMOOTHER_L1JACOBI;
   std::vector<std::vector<int>> agg;  // host copy of the aggregates (introspection)
   double bytes_per_cycle = 0.0;
 
-  void build(const AmgHost &h, int nsweeps, bool dia) {
+  void build(const AmgHost &h, int nsweeps, bool dia, int smoother_kind = CPTR_SMOOTHER_L1JACOBI) {
     sweeps = std::max(1, nsweeps);
+    smoother = smoother_kind;
     lev.clear();
     agg.clear();
     bytes_per_cycle = 0.0;
@@ -318,6 +322,32 @@ struct AmgDev {
           d[i] = T(1.0 / sum);
         }
         upload(L->dinv, d);
+        if (smoother == CPTR_SMOOTHER_GS) {
+          // greedy colouring in natural order: the smallest colour not taken
+          // by a lower-numbered neighbour (a proper colouring: the pattern is
+          // symmetric); rows grouped by colour, ascending inside a colour
+          std::vector<int> col(L->n, 0), mark;
+          int ncol = 0;
+          for (int i = 0; i < L->n; i++) {
+            mark.assign(ncol + 1, 0);
+            for (int k = H.A.rp[i]; k < H.A.rp[i + 1]; k++)
+              if (H.A.ci[k] < i) mark[col[H.A.ci[k]]] = 1;
+            int c = 0;
+            while (mark[c]) c++;
+            col[i] = c;
+            ncol = std::max(ncol, c + 1);
+          }
+          L->gs_ptr.assign(ncol + 1, 0);
+          for (int i = 0; i < L->n; i++) L->gs_ptr[col[i] + 1]++;
+          for (int c = 0; c < ncol; c++) L->gs_ptr[c + 1] += L->gs_ptr[c];
+          std::vector<int> fill(L->gs_ptr.begin(), L->gs_ptr.end() - 1), rows(L->n);
+          for (int i = 0; i < L->n; i++) rows[fill[col[i]]++] = i;
+          upload(L->gs_rows, rows);
+          upload(L->gs_rp, H.A.rp);
+          upload(L->gs_ci, H.A.ci);
+          std::vector<T> av(H.A.v.begin(), H.A.v.end());
+          upload(L->gs_v, av);
+        }
         // pre: sweeps passes over A, each leaving the residual of its iterate;
         // post: sweeps Jacobi passes; restriction and prolongation once each
         double n = L->n;
@@ -347,6 +377,34 @@ struct AmgDev {
     T *x = devp<T>(L.x), *y = devp<T>(L.y), *r = devp<T>(L.r);
     const T *dinv = devp<T>(L.dinv);
     const Level &C = *lev[l + 1];
+    if (smoother == CPTR_SMOOTHER_GS) {
+      // symmetric multicolour Gauss-Seidel: colours ascending before the
+      // coarse correction (from x = 0), descending after it
+      auto sweep = [&](bool reverse) {
+        const int ncol = int(L.gs_ptr.size()) - 1;
+        for (int cc = 0; cc < ncol; cc++) {
+          const int c = reverse ? ncol - 1 - cc : cc;
+          const int cnt = L.gs_ptr[c + 1] - L.gs_ptr[c];
+          if (cnt <= 0) continue;
+          hipLaunchKernelGGL((k_gs_color<T>), dim3(nblk(cnt)), dim3(kBlock), 0, st, cnt,
+                             devp<int>(L.gs_rows) + L.gs_ptr[c], devp<int>(L.gs_rp), devp<int>(L.gs_ci),
+                             devp<T>(L.gs_v), b, x);
+          LAUNCH_CHECK();
+        }
+      };
+      hipLaunchKernelGGL((k_fill<T>), dim3(sgrid(L.n)), dim3(kBlock), 0, st, x, (size_t)L.n, T(0));
+      LAUNCH_CHECK();
+      for (int s = 0; s < sweeps; s++) sweep(false);
+      L.A.template spmv<2>(st, x, b, r);
+      L.R.template spmv<0>(st, r, nullptr, devp<T>(C.b));
+      cycle_level(st, l + 1, devp<T>(C.b), devp<T>(C.r));
+      L.P.template spmv<1>(st, devp<T>(C.r), nullptr, x);
+      for (int s = 0; s < sweeps; s++) sweep(true);
+      hipLaunchKernelGGL((k_convert<T, T>), dim3(sgrid(L.n)), dim3(kBlock), 0, st, (const T *)x, out,
+                         (size_t)L.n);
+      LAUNCH_CHECK();
+      return;
+    }
     // pre-smoothing from zero: one pass for the first two sweeps, one per
     // further sweep, the last forming the residual of the smoothed iterate
     if (sweeps == 1) {
@@ -1107,7 +1165,7 @@ static void build_precond(cptr_handle *h, const std::vector<int> &rp, const std:
     } else {
       amg_build(pp, prm, hp, agg_p);
     }
-    P.amg_p.build(hp, o.amg_sweeps, o.scalar_dia != 0);
+    P.amg_p.build(hp, o.amg_sweeps, o.scalar_dia != 0, o.amg_smoother);
     if (o.first_stage != CPTR_FIRST_CPR && o.first_stage != CPTR_FIRST_UAMG) {
       // the second hierarchy: S~_T, or A_TT for the block-diagonal stage
       AmgHost hs;
@@ -1115,7 +1173,7 @@ static void build_precond(cptr_handle *h, const std::vector<int> &rp, const std:
         amg_build(sub(o.iT, o.iT), prm_s, hs, agg_s);
       else
         amg_build(*S, prm_s, hs, agg_s);
-      P.amg_s.build(hs, o.amg_sweeps, o.scalar_dia != 0);
+      P.amg_s.build(hs, o.amg_sweeps, o.scalar_dia != 0, o.amg_smoother);
       P.have_s = true;
       if (o.first_stage != CPTR_FIRST_BD) {
         P.ApT.build(sub(o.ip, o.iT), o.scalar_dia != 0);
@@ -1246,6 +1304,8 @@ static void validate_and_fetch(const cptr_bsr *A, const cptr_csr *S, const cptr_
   if (o.decoupling < 0 || o.decoupling > 2) throw Error{CPTR_ERR_INVALID_ARG, "invalid decoupling"};
   if (o.ilu_level != 0 && o.ilu_level != 1) throw Error{CPTR_ERR_UNSUPPORTED, "ilu_level must be 0 or 1"};
   if (o.schur < CPTR_SCHUR_ASSEMBLED || o.schur > CPTR_SCHUR_DIAG) throw Error{CPTR_ERR_INVALID_ARG, "invalid schur"};
+  if (o.amg_smoother != CPTR_SMOOTHER_L1JACOBI && o.amg_smoother != CPTR_SMOOTHER_GS)
+    throw Error{CPTR_ERR_INVALID_ARG, "invalid amg_smoother"};
   if (o.decoupling != 0 && o.first_stage != CPTR_FIRST_CPR && o.first_stage != CPTR_FIRST_UAMG)
     throw Error{CPTR_ERR_UNSUPPORTED, "decoupling operators apply to the CPR and CPTR-uAMG first stages only"};
   if (o.second_stage < 0 || o.second_stage > 4)
@@ -1525,7 +1585,7 @@ static int fgmres_impl(cptr_handle *h, const double *b, double *x, const cptr_so
       if (!std::isfinite(est)) {
         // a non-finite learned-stage output: continue with the BILU(0) fallback
         // from the current iterate (this cycle's basis is discarded)
-        if (h->op.o.second_stage == CPTR_SECOND_LEARNED && !h->pc->fallback_flag()) {
+        if (h->op.o.second_stage == CPTR_SECOND_LEARNED && h->op.o.lrn_fallback && !h->pc->fallback_flag()) {
           fall_back(h, st);
           info.fell_back = 1;
           discard = true;
@@ -1544,7 +1604,8 @@ static int fgmres_impl(cptr_handle *h, const double *b, double *x, const cptr_so
     LAUNCH_CHECK();
     cycles++;
     // stagnation of the learned stage over a whole cycle: fall back as well
-    if (h->op.o.second_stage == CPTR_SECOND_LEARNED && !h->pc->fallback_flag() && j == m) {
+    if (h->op.o.second_stage == CPTR_SECOND_LEARNED && h->op.o.lrn_fallback && !h->pc->fallback_flag() &&
+        j == m) {
       spmv<double>(h, st, x, b, devp<double>(h->r));
       norm2(h, st, devp<double>(h->r), N, 1);
       const double after = fetch(h, st, scal + 1) / bnorm;
@@ -1677,6 +1738,8 @@ void cptr_default_options(cptr_options *o) {
   o->scalar_dia = 1;
   o->lrn_columns = 1;
   o->schur = CPTR_SCHUR_ASSEMBLED;
+  o->lrn_fallback = 1;
+  o->amg_smoother = CPTR_SMOOTHER_L1JACOBI;
   o->decoupling = CPTR_DECOUPLE_NONE;
   o->ilu_level = 0;
 }

@@ -424,6 +424,29 @@ __global__ void __launch_bounds__(kBlock) k_ilu_bwd(int p0, int cnt, const int *
 }
 
 // ---------------------------------------------------------------------------
+// multicolour Gauss-Seidel smoothing: the rows of one colour (not coupled to
+// each other) take x_i = (b_i - sum_{j != i} a_ij x_j) / a_ii with the current
+// x of the other colours; one launch per colour
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_gs_color(int cnt, const int *__restrict__ rows,
+                                                     const int *__restrict__ rp, const int *__restrict__ ci,
+                                                     const T *__restrict__ v, const T *__restrict__ b, T *x) {
+  const int t = blockIdx.x * kBlock + threadIdx.x;
+  if (t >= cnt) return;
+  const int i = rows[t];
+  T s = b[i], d = T(1);
+  for (int k = rp[i]; k < rp[i + 1]; k++) {
+    const int j = ci[k];
+    if (j == i)
+      d = v[k];
+    else
+      s -= v[k] * x[j];
+  }
+  x[i] = s / d;
+}
+
+// ---------------------------------------------------------------------------
 // BILU numeric refactorisation on a kept pattern: the IKJ form in FP64, one
 // thread per factor row, one launch per level of the forward sweep (a row
 // reads only rows of earlier levels).  Every product and sum is rounded on

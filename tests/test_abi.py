@@ -63,7 +63,7 @@ def test_status_strings_and_defaults(lib):
     assert abs(o.amg_theta - 0.08) < 1e-15 and o.amg_coarse_size == 512
     # the fields appended to cptr_options, in the header's order and defaults
     assert (o.amg_smooth_p_T, o.use_graph, o.resid_fp64, o.scalar_dia, o.lrn_columns, o.decoupling,
-            o.ilu_level, o.schur) == (0, 1, 0, 1, 1, 0, 0, 0)
+            o.ilu_level, o.schur, o.lrn_fallback, o.amg_smoother) == (0, 1, 0, 1, 1, 0, 0, 0, 1, 0)
     assert ctypes.sizeof(cptr.Options) == _options_size_from_header()
     # argument validation happens before any device call
     h = ctypes.c_void_p()
@@ -88,3 +88,5 @@ def test_binding_stage_codes_match_the_header():
         assert v == defs["CPTR_SECOND_" + k.upper()], k
     for k, v in cptr.SCHUR.items():
         assert v == defs["CPTR_SCHUR_" + k.upper()], k
+    for k, v in cptr.SMOOTHER.items():
+        assert v == defs["CPTR_SMOOTHER_" + k.upper()], k

@@ -276,3 +276,9 @@ def test_learned_stage_in_fgmres_and_fallback():
     print(f"re-attached: iters {info2['iters']} fell_back {info2['fell_back']}")
     assert not info2["fell_back"] and info2["converged"] and info2["iters"] == first_iters
     s.close()
+    # with the fallback switched off a broken network is an error, not a switch
+    s, m = solver_with(pr, bad, precision="fp32", second_stage="learned", lrn_fallback=0)
+    with pytest.raises(cptr.CptrError) as e:
+        s.solve(torch.as_tensor(pr.b, device=DEV), restart=30, rtol=1e-6)
+    assert e.value.code == -3
+    s.close()

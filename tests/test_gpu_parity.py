@@ -299,6 +299,43 @@ def test_decoupled_first_stage_fp64(name, kind, first):
     s.close()
 
 
+@pytest.mark.parametrize("name", ["ragged", "three", "small", "chain"])
+@pytest.mark.parametrize("first", ["cptr", "cptr_uamg"])
+def test_gauss_seidel_smoother_fp64(name, first):
+    """amg_smoother = GS, symmetric multicolour Gauss-Seidel on every level:
+    V-cycles, first stage, application and FGMRES (FP64) against the oracle
+    with the same smoother."""
+    banner(f"gauss-seidel smoother {first} {name}")
+    pr = prob(name)
+    s = solver(pr, precision="fp64", first_stage=first, second_stage="bilu0", amg_smoother="gs",
+               amg_coarse_size=16)
+    o = O.Oracle.from_problem(pr, first=first, second="bilu0", coarse_size=16, smoother="gs")
+    rng = np.random.default_rng(29)
+    for which in ((0, 1) if first == "cptr" else (0,)):
+        m = 2 * pr.n if first == "cptr_uamg" else pr.n
+        b = rng.standard_normal(m)
+        x = torch.empty(m, dtype=torch.float64, device=DEV)
+        cptr.cptr_vcycle(s.h, which, dev(b), x)
+        torch.cuda.synchronize()
+        assert relerr(x.cpu().numpy(), o.vcycle(which, b)) <= 1e-10
+    v = rng.standard_normal(pr.n * pr.nv)
+    x1 = torch.empty_like(dev(v))
+    cptr.cptr_first_stage(s.h, dev(v), x1)
+    z = s.apply(dev(v))
+    torch.cuda.synchronize()
+    assert relerr(x1.cpu().numpy(), o.first_stage(v)) <= 1e-10
+    assert relerr(z.cpu().numpy(), o.apply(v)) <= 1e-9
+    s.close()
+    s = solver(pr, precision="fp64", first_stage=first, second_stage="bilu0", amg_smoother="gs")
+    o = O.Oracle.from_problem(pr, first=first, second="bilu0", smoother="gs")
+    xg, info = s.solve(dev(pr.b), restart=30, rtol=1e-6)
+    xo, io = o.fgmres(pr.b, m=30, rtol=1e-6)
+    err = np.linalg.norm(xg.cpu().numpy() - xo) / np.linalg.norm(xo)
+    print(f"iters gpu {info['iters']} oracle {io['iters']} err {err:.2e}")
+    assert info["converged"] and abs(info["iters"] - io["iters"]) <= 1 and err <= 1e-8
+    s.close()
+
+
 @pytest.mark.parametrize("name", ["ragged", "three", "small"])
 @pytest.mark.parametrize("schur", ["att", "diag"])
 def test_algebraic_schur_fp64(name, schur):
