@@ -278,12 +278,14 @@ struct SpOp {
 };
 
 // ---------------------------------------------------------------- AMG on device
+constexpr int kGsOneBlock = 8192;  // Gauss-Seidel levels up to this many rows: one workgroup per sweep
+
 template <typename T>
 struct AmgDev {
   struct Level {
     SpOp<T> A, P, R;
     DevMem dinv, b, x, y, r;
-    DevMem gs_rp, gs_ci, gs_v, gs_rows;  // Gauss-Seidel: A as CSR, rows grouped by colour
+    DevMem gs_rp, gs_ci, gs_v, gs_rows, gs_cptr;  // Gauss-Seidel: A as CSR, rows grouped by colour
     std::vector<int> gs_ptr;             // colour c holds gs_rows[gs_ptr[c] .. gs_ptr[c+1])
     int n = 0;
   };
@@ -343,6 +345,7 @@ struct AmgDev {
           std::vector<int> fill(L->gs_ptr.begin(), L->gs_ptr.end() - 1), rows(L->n);
           for (int i = 0; i < L->n; i++) rows[fill[col[i]]++] = i;
           upload(L->gs_rows, rows);
+          upload(L->gs_cptr, L->gs_ptr);
           upload(L->gs_rp, H.A.rp);
           upload(L->gs_ci, H.A.ci);
           std::vector<T> av(H.A.v.begin(), H.A.v.end());
@@ -382,6 +385,13 @@ struct AmgDev {
       // coarse correction (from x = 0), descending after it
       auto sweep = [&](bool reverse) {
         const int ncol = int(L.gs_ptr.size()) - 1;
+        if (L.n <= kGsOneBlock) {  // coarse levels: many colours, few rows each
+          hipLaunchKernelGGL((k_gs_level<T>), dim3(1), dim3(kBlock), 0, st, ncol, reverse ? 1 : 0,
+                             devp<int>(L.gs_cptr), devp<int>(L.gs_rows), devp<int>(L.gs_rp), devp<int>(L.gs_ci),
+                             devp<T>(L.gs_v), b, x);
+          LAUNCH_CHECK();
+          return;
+        }
         for (int cc = 0; cc < ncol; cc++) {
           const int c = reverse ? ncol - 1 - cc : cc;
           const int cnt = L.gs_ptr[c + 1] - L.gs_ptr[c];

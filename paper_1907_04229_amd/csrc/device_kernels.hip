@@ -446,6 +446,31 @@ __global__ void __launch_bounds__(kBlock) k_gs_color(int cnt, const int *__restr
   x[i] = s / d;
 }
 
+// a whole sweep of a small level in one workgroup: colours in order (reverse:
+// descending), a barrier between colours
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_gs_level(int ncol, int reverse, const int *__restrict__ cptr,
+                                                     const int *__restrict__ rows, const int *__restrict__ rp,
+                                                     const int *__restrict__ ci, const T *__restrict__ v,
+                                                     const T *__restrict__ b, T *x) {
+  for (int cc = 0; cc < ncol; cc++) {
+    const int c = reverse ? ncol - 1 - cc : cc;
+    for (int t = cptr[c] + threadIdx.x; t < cptr[c + 1]; t += kBlock) {
+      const int i = rows[t];
+      T s = b[i], d = T(1);
+      for (int k = rp[i]; k < rp[i + 1]; k++) {
+        const int j = ci[k];
+        if (j == i)
+          d = v[k];
+        else
+          s -= v[k] * x[j];
+      }
+      x[i] = s / d;
+    }
+    __syncthreads();
+  }
+}
+
 // ---------------------------------------------------------------------------
 // BILU numeric refactorisation on a kept pattern: the IKJ form in FP64, one
 // thread per factor row, one launch per level of the forward sweep (a row

@@ -299,14 +299,19 @@ def test_decoupled_first_stage_fp64(name, kind, first):
     s.close()
 
 
-@pytest.mark.parametrize("name", ["ragged", "three", "small", "chain"])
+@pytest.mark.parametrize("name", ["ragged", "three", "small", "chain", "gs_large"])
 @pytest.mark.parametrize("first", ["cptr", "cptr_uamg"])
 def test_gauss_seidel_smoother_fp64(name, first):
     """amg_smoother = GS, symmetric multicolour Gauss-Seidel on every level:
     V-cycles, first stage, application and FGMRES (FP64) against the oracle
-    with the same smoother."""
+    with the same smoother.  gs_large: a fine level above 8192 rows, swept one
+    launch per colour (smaller levels: one workgroup per sweep)."""
     banner(f"gauss-seidel smoother {first} {name}")
-    pr = prob(name)
+    if name == "gs_large":
+        pr = make_problem(shape=(24, 24, 16), kind="gaussian", sigma=1.5, corr_len=4.0, seed=37)
+        assert pr.n > 8192
+    else:
+        pr = prob(name)
     s = solver(pr, precision="fp64", first_stage=first, second_stage="bilu0", amg_smoother="gs",
                amg_coarse_size=16)
     o = O.Oracle.from_problem(pr, first=first, second="bilu0", coarse_size=16, smoother="gs")
