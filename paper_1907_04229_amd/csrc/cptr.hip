@@ -278,7 +278,7 @@ struct SpOp {
 };
 
 // ---------------------------------------------------------------- AMG on device
-constexpr int kGsOneBlock = 8192;  // Gauss-Seidel levels up to this many rows: one workgroup per sweep
+constexpr int kGsOneBlock = 2048;  // Gauss-Seidel levels up to this many rows: one workgroup per sweep
 
 template <typename T>
 struct AmgDev {
@@ -287,6 +287,7 @@ struct AmgDev {
     DevMem dinv, b, x, y, r;
     DevMem gs_rp, gs_ci, gs_v, gs_rows, gs_cptr;  // Gauss-Seidel: A as CSR, rows grouped by colour
     std::vector<int> gs_ptr;             // colour c holds gs_rows[gs_ptr[c] .. gs_ptr[c+1])
+    bool gs_wide = false;                // rows long enough for a wavefront each
     int n = 0;
   };
   std::vector<std::unique_ptr<Level>> lev;
@@ -346,6 +347,7 @@ struct AmgDev {
           for (int i = 0; i < L->n; i++) rows[fill[col[i]]++] = i;
           upload(L->gs_rows, rows);
           upload(L->gs_cptr, L->gs_ptr);
+          L->gs_wide = H.A.nnz() >= 16 * (long long)L->n;
           upload(L->gs_rp, H.A.rp);
           upload(L->gs_ci, H.A.ci);
           std::vector<T> av(H.A.v.begin(), H.A.v.end());
@@ -386,9 +388,14 @@ struct AmgDev {
       auto sweep = [&](bool reverse) {
         const int ncol = int(L.gs_ptr.size()) - 1;
         if (L.n <= kGsOneBlock) {  // coarse levels: many colours, few rows each
-          hipLaunchKernelGGL((k_gs_level<T>), dim3(1), dim3(kBlock), 0, st, ncol, reverse ? 1 : 0,
-                             devp<int>(L.gs_cptr), devp<int>(L.gs_rows), devp<int>(L.gs_rp), devp<int>(L.gs_ci),
-                             devp<T>(L.gs_v), b, x);
+          if (L.gs_wide)
+            hipLaunchKernelGGL((k_gs_level_wave<T>), dim3(1), dim3(64 * kGsWaves), 0, st, ncol, reverse ? 1 : 0,
+                               devp<int>(L.gs_cptr), devp<int>(L.gs_rows), devp<int>(L.gs_rp),
+                               devp<int>(L.gs_ci), devp<T>(L.gs_v), b, x);
+          else
+            hipLaunchKernelGGL((k_gs_level<T>), dim3(1), dim3(kBlock), 0, st, ncol, reverse ? 1 : 0,
+                               devp<int>(L.gs_cptr), devp<int>(L.gs_rows), devp<int>(L.gs_rp),
+                               devp<int>(L.gs_ci), devp<T>(L.gs_v), b, x);
           LAUNCH_CHECK();
           return;
         }
@@ -396,9 +403,14 @@ struct AmgDev {
           const int c = reverse ? ncol - 1 - cc : cc;
           const int cnt = L.gs_ptr[c + 1] - L.gs_ptr[c];
           if (cnt <= 0) continue;
-          hipLaunchKernelGGL((k_gs_color<T>), dim3(nblk(cnt)), dim3(kBlock), 0, st, cnt,
-                             devp<int>(L.gs_rows) + L.gs_ptr[c], devp<int>(L.gs_rp), devp<int>(L.gs_ci),
-                             devp<T>(L.gs_v), b, x);
+          if (L.gs_wide)
+            hipLaunchKernelGGL((k_gs_color_wave<T>), dim3(nblk((size_t)cnt * 64)), dim3(kBlock), 0, st, cnt,
+                               devp<int>(L.gs_rows) + L.gs_ptr[c], devp<int>(L.gs_rp), devp<int>(L.gs_ci),
+                               devp<T>(L.gs_v), b, x);
+          else
+            hipLaunchKernelGGL((k_gs_color<T>), dim3(nblk(cnt)), dim3(kBlock), 0, st, cnt,
+                               devp<int>(L.gs_rows) + L.gs_ptr[c], devp<int>(L.gs_rp), devp<int>(L.gs_ci),
+                               devp<T>(L.gs_v), b, x);
           LAUNCH_CHECK();
         }
       };

@@ -446,6 +446,54 @@ __global__ void __launch_bounds__(kBlock) k_gs_color(int cnt, const int *__restr
   x[i] = s / d;
 }
 
+// one wavefront per row, for rows with many entries (coarse Galerkin levels):
+// the lanes split the row and sum by shuffles
+template <typename T>
+__device__ __forceinline__ void gs_row_wave(int i, int lane, const int *__restrict__ rp,
+                                            const int *__restrict__ ci, const T *__restrict__ v,
+                                            const T *__restrict__ b, T *x) {
+  T s = T(0), d = T(0);
+  for (int k = rp[i] + lane; k < rp[i + 1]; k += 64) {
+    const int j = ci[k];
+    if (j == i)
+      d = v[k];
+    else
+      s += v[k] * x[j];
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    s += __shfl_xor(s, o);
+    d += __shfl_xor(d, o);
+  }
+  if (lane == 0) x[i] = (b[i] - s) / d;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_gs_color_wave(int cnt, const int *__restrict__ rows,
+                                                          const int *__restrict__ rp, const int *__restrict__ ci,
+                                                          const T *__restrict__ v, const T *__restrict__ b, T *x) {
+  const int w = (blockIdx.x * kBlock + threadIdx.x) >> 6;  // the same for the whole wavefront
+  if (w >= cnt) return;
+  gs_row_wave<T>(rows[w], threadIdx.x & 63, rp, ci, v, b, x);
+}
+
+// a whole sweep of a small level in one workgroup of kGsWaves wavefronts, a
+// wavefront per row, a barrier between colours
+constexpr int kGsWaves = 16;
+template <typename T>
+__global__ void __launch_bounds__(64 * kGsWaves) k_gs_level_wave(int ncol, int reverse, const int *__restrict__ cptr,
+                                                                 const int *__restrict__ rows,
+                                                                 const int *__restrict__ rp,
+                                                                 const int *__restrict__ ci,
+                                                                 const T *__restrict__ v, const T *__restrict__ b,
+                                                                 T *x) {
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int cc = 0; cc < ncol; cc++) {
+    const int c = reverse ? ncol - 1 - cc : cc;
+    for (int t = cptr[c] + wv; t < cptr[c + 1]; t += kGsWaves) gs_row_wave<T>(rows[t], lane, rp, ci, v, b, x);
+    __syncthreads();
+  }
+}
+
 // a whole sweep of a small level in one workgroup: colours in order (reverse:
 // descending), a barrier between colours
 template <typename T>

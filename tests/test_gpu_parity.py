@@ -304,12 +304,14 @@ def test_decoupled_first_stage_fp64(name, kind, first):
 def test_gauss_seidel_smoother_fp64(name, first):
     """amg_smoother = GS, symmetric multicolour Gauss-Seidel on every level:
     V-cycles, first stage, application and FGMRES (FP64) against the oracle
-    with the same smoother.  gs_large: a fine level above 8192 rows, swept one
-    launch per colour (smaller levels: one workgroup per sweep)."""
+    with the same smoother.  Levels above 2048 rows are swept one launch per
+    colour, smaller ones in one workgroup; rows of 16 entries or more on
+    average take a wavefront each.  gs_large has a finest level and a second
+    level (long rows) above 2048 rows."""
     banner(f"gauss-seidel smoother {first} {name}")
     if name == "gs_large":
-        pr = make_problem(shape=(24, 24, 16), kind="gaussian", sigma=1.5, corr_len=4.0, seed=37)
-        assert pr.n > 8192
+        pr = make_problem(shape=(40, 40, 24), kind="gaussian", sigma=1.5, corr_len=4.0, seed=37)
+        assert pr.n > 2048
     else:
         pr = prob(name)
     s = solver(pr, precision="fp64", first_stage=first, second_stage="bilu0", amg_smoother="gs",
