@@ -128,6 +128,47 @@ int cptrh_ilu_get(void *h, int *order, int *lev_lower, int *lev_upper, int *colo
   return I.ncolor;
 }
 
+// The factor pattern kept for the GPU refactorisation: sizes (entries, forward
+// and backward sweep blocks, forward levels) with null arrays, else the arrays
+// frp [n+1], fci / src / dst [nnzf], dpos / fwd [n], f_lev_ptr [levels+1].
+int cptrh_ilu_pattern(void *h, int *sizes, int *frp, int *fci, int *src, int *dpos, int *dst, int *fwd,
+                      int *f_lev_ptr) {
+  auto &I = static_cast<IluBox *>(h)->h;
+  if (sizes) {
+    sizes[0] = int(I.fci.size());
+    sizes[1] = int(I.f_col.size());
+    sizes[2] = int(I.b_col.size());
+    sizes[3] = int(I.f_lev_ptr.size()) - 1;
+  }
+  auto cp = [](int *dst_, const std::vector<int> &v) {
+    if (dst_) std::memcpy(dst_, v.data(), sizeof(int) * v.size());
+  };
+  cp(frp, I.frp);
+  cp(fci, I.fci);
+  cp(src, I.src);
+  cp(dpos, I.dpos);
+  cp(dst, I.dst);
+  cp(fwd, I.fwd);
+  cp(f_lev_ptr, I.f_lev_ptr);
+  return 0;
+}
+
+// Algebraic S~_T of a BSR matrix (schur_algebraic): nnz with null arrays,
+// else rp [n+1], ci / v [nnz].  Negative status code on failure.
+int cptrh_schur(int n, int nv, int ip, int iT, const int *rp, const int *ci, const double *v, int diag,
+                int *srp, int *sci, double *sv) {
+  try {
+    HostCSR s = schur_algebraic(n, nv, ip, iT, rp, ci, v, diag != 0);
+    if (srp) std::memcpy(srp, s.rp.data(), sizeof(int) * s.rp.size());
+    if (sci) std::memcpy(sci, s.ci.data(), sizeof(int) * s.ci.size());
+    if (sv) std::memcpy(sv, s.v.data(), sizeof(double) * s.v.size());
+    return s.nnz();
+  } catch (const Error &e) {
+    g_err = e.msg;
+    return e.code;
+  }
+}
+
 void cptrh_ilu_free(void *h) { delete static_cast<IluBox *>(h); }
 
 }  // extern "C"

@@ -23,6 +23,8 @@ def load():
         L.cptrh_uamg_build.restype = vp
         L.cptrh_uamg_build.argtypes = [C.c_int, C.c_int, ip, ip, dp, C.c_double, C.c_int, C.c_int,
                                        C.c_uint, C.c_int, C.c_int, ip]
+        L.cptrh_ilu_pattern.argtypes = [vp] + [ip] * 8
+        L.cptrh_schur.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, ip, ip, dp, C.c_int, ip, ip, dp]
         L.cptrh_amg_nlevels.argtypes = [vp]
         L.cptrh_amg_level_info.argtypes = [vp, C.c_int, ip, ip, ip]
         L.cptrh_amg_get.argtypes = [vp, C.c_int, ip, ip, ip, dp, ip, ip, dp, dp]
@@ -112,6 +114,31 @@ def ilu_schedule(row_ptr, col, vals, nv, multicolor, level=0):
         order, ll, lu, color = (np.zeros(n, np.int32) for _ in range(4))
         dinv = np.zeros(n * nv * nv)
         nc = L.cptrh_ilu_get(h, _i(order), _i(ll), _i(lu), _i(color), _d(dinv))
-        return dict(order=order, lev_lower=ll, lev_upper=lu, color=color, dinv=dinv, ncolor=nc)
+        sz = np.zeros(4, np.int32)
+        L.cptrh_ilu_pattern(h, _i(sz), None, None, None, None, None, None, None)
+        nnzf, nfb, nbb, nlev = (int(x) for x in sz)
+        frp, dpos, fwd = np.zeros(n + 1, np.int32), np.zeros(n, np.int32), np.zeros(n, np.int32)
+        fci, src, dst = (np.zeros(max(nnzf, 1), np.int32) for _ in range(3))
+        flp = np.zeros(nlev + 1, np.int32)
+        L.cptrh_ilu_pattern(h, None, _i(frp), _i(fci), _i(src), _i(dpos), _i(dst), _i(fwd), _i(flp))
+        return dict(order=order, lev_lower=ll, lev_upper=lu, color=color, dinv=dinv, ncolor=nc,
+                    frp=frp, fci=fci[:nnzf], src=src[:nnzf], dpos=dpos, dst=dst[:nnzf], fwd=fwd,
+                    f_lev_ptr=flp, n_fwd_blocks=nfb, n_bwd_blocks=nbb)
     finally:
         L.cptrh_ilu_free(h)
+
+
+def schur_algebraic(row_ptr, col, vals, nv, ip=0, iT=None, diag=True):
+    """The library's algebraic S~_T (A_TT, or A_TT - A_Tp diag(A_pp)^-1 A_pT)."""
+    rp = np.ascontiguousarray(row_ptr, np.int32)
+    ci = np.ascontiguousarray(col, np.int32)
+    v = np.ascontiguousarray(vals, np.float64)
+    n = rp.size - 1
+    iT = nv - 1 if iT is None else iT
+    L = load()
+    nnz = L.cptrh_schur(n, nv, ip, iT, _i(rp), _i(ci), _d(v), int(bool(diag)), None, None, None)
+    if nnz < 0:
+        raise RuntimeError(f"S~_T failed ({nnz}): {L.cptrh_last_error().decode()}")
+    srp, sci, sv = np.zeros(n + 1, np.int32), np.zeros(max(nnz, 1), np.int32), np.zeros(max(nnz, 1))
+    L.cptrh_schur(n, nv, ip, iT, _i(rp), _i(ci), _d(v), int(bool(diag)), _i(srp), _i(sci), _d(sv))
+    return srp, sci[:nnz], sv[:nnz]

@@ -98,3 +98,53 @@ def test_ilu_schedule_matches_oracle(mc, level, oracle_lib):
     d_ref = ref["dinv"].reshape(-1, nv, nv)
     d_got = got["dinv"].reshape(-1, nv, nv)[cells]
     assert np.abs(d_ref - d_got).max() <= 1e-12 * np.abs(d_ref).max()
+
+
+@pytest.mark.parametrize("mc", [False, True])
+@pytest.mark.parametrize("level", [0, 1])
+def test_ilu_refactorisation_pattern_is_consistent(mc, level):
+    # what the GPU refactorisation indexes: the forward levels order every row
+    # after the rows it reads, each factor block lands in exactly one block of
+    # the two sweeps, and each starts from its own block of A (or from zero)
+    pr = make_problem(shape=(7, 6, 5), kind="iid", seed=9, three_phase=True)
+    f = H.ilu_schedule(pr.row_ptr, pr.col_idx, pr.vals, pr.nv, mc, level)
+    n, order = pr.n, f["order"]
+    frp, fci, src, dpos, dst, fwd, flp = (f[k] for k in ("frp", "fci", "src", "dpos", "dst", "fwd", "f_lev_ptr"))
+    assert sorted(fwd) == list(range(n)) and flp[0] == 0 and flp[-1] == n
+    lev = np.empty(n, int)
+    for l in range(flp.size - 1):
+        lev[fwd[flp[l]:flp[l + 1]]] = l
+    nf = nb = 0
+    seen_f, seen_b, seen_a = set(), set(), set()
+    for p in range(n):
+        row = fci[frp[p]:frp[p + 1]]
+        assert (np.diff(row) > 0).all() and fci[dpos[p]] == p
+        for k in range(frp[p], frp[p + 1]):
+            if k < dpos[p]:
+                assert lev[fci[k]] < lev[p]
+                assert dst[k] >= 0 and dst[k] not in seen_f
+                seen_f.add(dst[k])
+            elif k > dpos[p]:
+                assert dst[k] <= -2 and -dst[k] - 2 not in seen_b
+                seen_b.add(-dst[k] - 2)
+            else:
+                assert dst[k] == -1
+            if src[k] >= 0:
+                i = order[p]
+                assert pr.row_ptr[i] <= src[k] < pr.row_ptr[i + 1] and pr.col_idx[src[k]] == order[fci[k]]
+                seen_a.add(src[k])
+    assert seen_f == set(range(f["n_fwd_blocks"])) and seen_b == set(range(f["n_bwd_blocks"]))
+    assert seen_a == set(range(pr.row_ptr[-1]))           # every block of A is used once
+    assert ((src < 0).sum() > 0) == (level == 1)          # fill blocks only with ILU(1)
+
+
+@pytest.mark.parametrize("case", range(len(CASES)))
+@pytest.mark.parametrize("schur", ["att", "diag"])
+def test_algebraic_schur_bit_exact(case, schur, oracle_lib):
+    # the library's S~_T from A (Section 3.3.1) against the oracle's, bit for bit
+    pr = make_problem(**CASES[case])
+    o = O.Oracle.from_problem(pr, first="cptr", second="none", coarse_size=10_000, schur=schur)
+    ref = o.amg_levels(1)[0]["A"]
+    got = H.schur_algebraic(pr.row_ptr, pr.col_idx, pr.vals, pr.nv, diag=schur == "diag")
+    for x, y in zip(got, ref):
+        assert np.array_equal(x, y)
