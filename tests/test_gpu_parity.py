@@ -268,7 +268,10 @@ def test_decoupled_first_stage_fp64(name, kind, first):
     hierarchy aggregates bit-exact, V-cycle on S_p (S_0), first stage and
     application (FP64) and FGMRES against the oracle."""
     banner(f"decoupled {first} {name} {kind}")
-    pr = prob(name)
+    _decoupled_check(prob(name), kind, first)
+
+
+def _decoupled_check(pr, kind, first):
     s = solver(pr, precision="fp64", first_stage=first, second_stage="bilu0", decoupling=kind,
                amg_coarse_size=16)
     o = O.Oracle.from_problem(pr, first=first, second="bilu0", decoupling=kind, coarse_size=16)
@@ -643,3 +646,20 @@ def test_deterministic_solution():
     x2, _ = s.solve(dev(pr.b))
     assert torch.equal(x1, x2)
     s.close()
+
+
+@pytest.mark.parametrize("name", ["three", "small"])
+@pytest.mark.parametrize("kind", ["qi", "ti"])
+def test_pT_decoupling_with_distinct_energy_rows(name, kind):
+    """CPTR-uAMG decoupling with the energy rows scaled by 3.  At the uniform
+    initial temperature the generated pressure and energy rows have equal
+    saturation derivatives, so the two rows of D_i coincide; scaled, they
+    differ, and a mix-up between them would show."""
+    banner(f"decoupled cptr_uamg, distinct energy rows, {name} {kind}")
+    import copy
+    pr = prob(name)
+    pr2 = copy.copy(pr)
+    v = pr.vals.reshape(-1, pr.nv, pr.nv).copy()
+    v[:, pr.nv - 1, :] *= 3.0
+    pr2.vals = np.ascontiguousarray(v.reshape(-1))
+    _decoupled_check(pr2, kind, "cptr_uamg")

@@ -563,9 +563,13 @@ def test_single_level_unknown_based_stage_is_A00_inverse(tiny, oracle_lib):
 def _local_saturation(pr, zero):
     """Values of pr with the saturation (every slot but pressure 0 and
     temperature nv-1) columns (zero = "cols") or rows (zero = "rows") of every
-    off-diagonal block set to zero."""
+    off-diagonal block set to zero, and the energy rows scaled by 3: at the
+    uniform initial temperature the generator's pressure and energy rows have
+    the same saturation derivatives, which would make the two rows of D_i
+    equal and hide a mix-up between them."""
     nv = pr.nv
     vals = pr.vals.reshape(-1, nv, nv).copy()
+    vals[:, nv - 1, :] *= 3.0
     rows = np.repeat(np.arange(pr.n), np.diff(pr.row_ptr))
     off = pr.col_idx != rows
     if zero == "cols":
