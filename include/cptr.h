@@ -10,10 +10,14 @@
  *                submatrix (eq:A00), A00~^{-1} the block preconditioner of
  *                eq:Aschur with its Schur-complement approximation S~_T (eq:Se),
  *                each inverse one algebraic-multigrid V-cycle;
- *   second stage block ILU(0) of the full matrix;
+ *   second stage block ILU(0) of the full matrix (or ILU(1), or the learned
+ *                stage of cptr_learn.h);
  *   combination  x1 = M1^{-1} v, b1 = v - A x1, z = M2^{-1} b1 + x1
  *                ("Two-stage preconditioners", Section 3).
- * CPR (Section 3.1: pressure-only first stage) is available for comparison.
+ * Other first stages: CPR (Section 3.1, pressure only, optionally with a
+ * Quasi-/True-IMPES decoupling operator), the block lower-triangular and
+ * block-diagonal (Section 4.4) variants of the block preconditioner, and the
+ * unknown-based AMG of the pressure-temperature block (Section 3.4).
  *
  * Conventions shared by every entry point
  *   - All matrix and vector pointers are DEVICE pointers (HIP memory on the
@@ -28,6 +32,8 @@
  *     is the energy equation and temperature unknown.
  *   - S~_T is a scalar CSR matrix on the cell graph (int32/int32/double),
  *     assembled by the caller from eq:Se; it cannot be recovered from A alone.
+ *     The options also offer two algebraic approximations formed from A
+ *     (cptr_options.schur), for which no S~_T is passed.
  *   - `stream` is a hipStream_t passed as void*; NULL is the null stream.
  *   - Return values: 0 = CPTR_OK, > 0 informational, < 0 error.  No C++
  *     exception crosses this interface.  cptr_last_error() gives the message
@@ -128,7 +134,8 @@ typedef struct {
   int amg_max_levels;    /* <= 16 (10) */
   int amg_coarse_size;   /* coarsest level solved directly once n <= this (512) */
   unsigned amg_seed;     /* aggregation priority seed (0) */
-  int amg_sweeps;        /* l1-Jacobi sweeps before and after the coarse correction (2) */
+  int amg_sweeps;        /* smoother sweeps (amg_smoother) before and after the coarse
+                            correction (2) */
   int amg_smooth_p;      /* 1 smoothed aggregation, 0 plain aggregation (1) */
   int amg_smooth_p_T;    /* the same for the second hierarchy alone (S~_T; A_TT for
                             CPTR_FIRST_BD; the temperature block of the CPTR_FIRST_UAMG
@@ -184,7 +191,8 @@ typedef struct {
 } cptr_solve_info;
 
 typedef struct {
-  int nlevels[2];        /* AMG levels of A_pp [0] and S~_T [1] */
+  int nlevels[2];        /* AMG levels of A_pp [0] and S~_T [1] (A_TT for CPTR_FIRST_BD;
+                            [0] the coupled A_00 and [1] none for CPTR_FIRST_UAMG) */
   int level_rows[2][16];
   int level_nnz[2][16];
   int ilu_levels_lower;  /* dependent steps of the forward sweep */
