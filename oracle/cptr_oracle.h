@@ -10,9 +10,14 @@
  *   - BSR / CSR products;
  *   - smoothed-aggregation AMG (strength, distance-2 maximal independent set,
  *     aggregation, Jacobi-smoothed prolongation, Galerkin product, dense LU
- *     on the coarsest level) and its V-cycle with l1-Jacobi smoothing;
- *   - block ILU(0) in natural and in multicolour order, its level sets;
- *   - the two-stage CPR / CPTR preconditioners of Section 3;
+ *     on the coarsest level) and its V-cycle with l1-Jacobi or symmetric
+ *     multicolour Gauss-Seidel smoothing; the same built per unknown on the
+ *     coupled pressure-temperature block (unknown-based AMG, Section 3.4);
+ *   - block ILU(0) and ILU(1) in natural and in multicolour order, level sets;
+ *   - the two-stage CPR / CPTR preconditioners of Section 3 with the first
+ *     stages CPTR-Block, its lower-triangular and block-diagonal variants,
+ *     CPR and CPTR-uAMG, the Quasi-/True-IMPES decoupling operators (Sections
+ *     3.1, 3.2) and the algebraic S~_T approximations of Section 3.3.1;
  *   - right-preconditioned flexible GMRES(m) with modified Gram-Schmidt.
  */
 #ifndef CPTR_ORACLE_H
