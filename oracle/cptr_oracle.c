@@ -612,9 +612,6 @@ static int uamg_setup(amg *m, csr fine, int np, double theta, int max_levels, in
   return amg_finish(m);
 }
 
-/* One V-cycle from a zero initial guess: l1-Jacobi pre-smoothing (one sweep),
- * residual, restriction, recursion, prolongation, l1-Jacobi post-smoothing;
- * the coarsest level is solved exactly. */
 /* one multicolour Gauss-Seidel sweep: colours in ascending (or descending)
  * order; rows of one colour are not coupled, so each colour is one Jacobi
  * update with the latest values of the other colours */
@@ -634,6 +631,12 @@ static void gs_sweep(const amg *m, int l, const double *b, double *x, int revers
   }
 }
 
+/* One V-cycle from a zero initial guess on level l: `sweeps` pre-smoothing
+ * sweeps (l1-Jacobi, x += D_l1^{-1}(b - A x), or forward multicolour
+ * Gauss-Seidel), the residual, restriction by R = P^T, the cycle on the next
+ * level, prolongation, then `sweeps` post-smoothing sweeps (l1-Jacobi, or
+ * Gauss-Seidel with the colours in descending order); the coarsest level is
+ * solved exactly by its LU factors. */
 static void vcycle(const amg *m, int l, const double *b, double *x) {
   const csr *a = &m->A[l];
   int n = a->nr;
@@ -1192,8 +1195,8 @@ void *orc_create(int n, int nv, const int *rp, const int *ci, const double *vals
       csr_free(&fine);
     }
     h->have_p = 1;
-    if (st == 0 && (o->first_stage == ORC_FIRST_CPTR_BLOCK ||
-                    o->first_stage == ORC_FIRST_CPTR_LOWER || o->first_stage == ORC_FIRST_CPTR_BD)) {
+    if (st == 0 && (o->first_stage == ORC_FIRST_CPTR_BLOCK || o->first_stage == ORC_FIRST_CPTR_LOWER ||
+                    o->first_stage == ORC_FIRST_CPTR_UPPER || o->first_stage == ORC_FIRST_CPTR_BD)) {
       /* the second hierarchy: S~_T (eq:Se, or one of the algebraic
        * approximations of Section 3.3.1), or A_TT for the block-diagonal stage */
       csr s;
@@ -1252,7 +1255,11 @@ void orc_destroy(void *hv) {
  *  CPTR block (eq:Aschur, its five steps):
  *    x_p = A_pp^{-1} b_p;  b~_T = b_T - A_Tp x_p;  d_T = S~_T^{-1} b~_T;
  *    b~_p = b_p - A_pT d_T;  d_p = A_pp^{-1} b~_p
- *  CPTR lower (right factor of eq:Aschur dropped): d_p = x_p.
+ *  CPTR lower (left factor of eq:Aschur dropped, the inverse of the block
+ *    lower-triangular [A_pp 0; A_Tp S~_T]): d_p = x_p.
+ *  CPTR upper (right factor of eq:Aschur dropped, the inverse of the block
+ *    upper-triangular [A_pp A_pT; 0 S~_T]): d_T = S~_T^{-1} b_T,
+ *    d_p = A_pp^{-1} (b_p - A_pT d_T).
  *  CPR (Section 3.1): d_p = A_pp^{-1} b_p, d_T = 0; with a decoupling
  *    operator G: d_p = S_p^{-1} (G v)_p, S_p = A_pp - D A_sp, (G v)_p = v_p - D v_s.
  *  CPTR-BD(AMG) (Section 4.4, block-diagonal first stage): d_p = A_pp^{-1} b_p,
@@ -1294,6 +1301,17 @@ int orc_first_stage(void *hv, const double *v, double *x1) {
     for (int i = 0; i < n; i++) {
       x1[(size_t)i * nv + ip] = h->xp[i];
       x1[(size_t)i * nv + iT] = h->xp[n + i];
+    }
+    return 0;
+  }
+  if (h->o.first_stage == ORC_FIRST_CPTR_UPPER) {
+    vcycle(&h->amg_s, 0, h->bt, h->dt);
+    csr_mv(&h->ApT, h->dt, h->tmp);
+    for (int i = 0; i < n; i++) h->tmp[i] = h->bp[i] - h->tmp[i];
+    vcycle(&h->amg_p, 0, h->tmp, h->dp);
+    for (int i = 0; i < n; i++) {
+      x1[(size_t)i * nv + ip] = h->dp[i];
+      x1[(size_t)i * nv + iT] = h->dt[i];
     }
     return 0;
   }

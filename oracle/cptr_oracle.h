@@ -28,7 +28,7 @@ extern "C" {
 #endif
 
 enum { ORC_FIRST_NONE = 0, ORC_FIRST_CPTR_BLOCK = 1, ORC_FIRST_CPTR_LOWER = 2,
-       ORC_FIRST_CPR = 3, ORC_FIRST_CPTR_BD = 4, ORC_FIRST_CPTR_UAMG = 5 };
+       ORC_FIRST_CPR = 3, ORC_FIRST_CPTR_BD = 4, ORC_FIRST_CPTR_UAMG = 5, ORC_FIRST_CPTR_UPPER = 6 };
 enum { ORC_SECOND_NONE = 0, ORC_SECOND_BILU0 = 1, ORC_SECOND_BILU0_MC = 2,
        ORC_SECOND_IDENTITY = 3, ORC_SECOND_EXACT = 4 };
 

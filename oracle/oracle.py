@@ -14,7 +14,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "liborc.so")
 _SRC = os.path.join(_HERE, "cptr_oracle.c")
 
-FIRST = {"none": 0, "cptr": 1, "cptr_lower": 2, "cpr": 3, "cptr_bd": 4, "cptr_uamg": 5}
+FIRST = {"none": 0, "cptr": 1, "cptr_lower": 2, "cpr": 3, "cptr_bd": 4, "cptr_uamg": 5, "cptr_upper": 6}
 DECOUPLING = {"none": 0, "qi": 1, "ti": 2}
 SCHUR = {"assembled": 0, "att": 1, "diag": 2}
 SECOND = {"none": 0, "bilu0": 1, "bilu0_mc": 2, "identity": 3, "exact": 4}

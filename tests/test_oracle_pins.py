@@ -192,6 +192,63 @@ def test_prolongator_galerkin_and_omega(mid, oracle_lib):
         assert np.abs(Ac - ref).max() <= 1e-12 * np.abs(ref).max()
 
 
+def test_plain_aggregation_prolongator_is_the_aggregate_indicator(oracle_lib):
+    # plain (tentative) aggregation, the S~_T hierarchy of the block first
+    # stages (smooth_p_T = False): P is the 0/1 indicator of the aggregates
+    # (one unit entry per aggregated row in the column of its aggregate, an
+    # empty row for a node without strong neighbours), and every coarse
+    # operator is the Galerkin product T^T A T formed densely.  A strongly
+    # heterogeneous field so that isolated nodes occur.
+    pr = make_problem(shape=(10, 9, 6), kind="gaussian", sigma=3.0, corr_len=2.0, seed=13)
+    o = O.Oracle.from_problem(pr, first="cptr", coarse_size=8, smooth_p_T=False)
+    lv = o.amg_levels(1)
+    assert len(lv) >= 3
+    S = dense_csr(pr.st_row_ptr, pr.st_col_idx, pr.st_vals)
+    assert np.array_equal(dense_csr(*lv[0]["A"]), S)             # the fine level is S~_T itself
+    isolated_seen = False
+    for l in range(len(lv) - 1):
+        n, nc = lv[l]["n"], lv[l + 1]["n"]
+        agg = lv[l]["agg"]
+        prp, pci, pv = lv[l]["P"]
+        isolated_seen |= bool((agg < 0).any())
+        # row by row: exactly the indicator entry, nothing else
+        for i in range(n):
+            cols, vals = pci[prp[i]:prp[i + 1]], pv[prp[i]:prp[i + 1]]
+            if agg[i] < 0:
+                assert vals.size == 0 or not vals.any()
+            else:
+                assert cols.tolist() == [agg[i]] and vals.tolist() == [1.0]
+        T = np.zeros((n, nc))
+        T[np.arange(n)[agg >= 0], agg[agg >= 0]] = 1.0
+        assert np.array_equal(dense_csr(prp, pci, pv, ncol=nc), T)
+        A = dense_csr(*lv[l]["A"])
+        ref = T.T @ A @ T                                          # sums of aggregate blocks
+        Ac = dense_csr(*lv[l + 1]["A"])
+        assert np.abs(Ac - ref).max() <= 1e-13 * np.abs(ref).max()
+    assert isolated_seen
+
+
+def test_plain_aggregation_two_grid_cycle_is_textbook(mid, oracle_lib):
+    # the two-grid cycle of the plain-aggregation S~_T hierarchy against the
+    # textbook formula with the indicator prolongator formed from the aggregates
+    o = O.Oracle.from_problem(mid, first="cptr", coarse_size=8, max_levels=2, sweeps=2, smooth_p_T=False)
+    lv = o.amg_levels(1)
+    assert len(lv) == 2
+    A = dense_csr(mid.st_row_ptr, mid.st_col_idx, mid.st_vals)
+    agg = lv[0]["agg"]
+    T = np.zeros((A.shape[0], lv[1]["n"]))
+    T[np.arange(A.shape[0])[agg >= 0], agg[agg >= 0]] = 1.0
+    d = np.abs(A).sum(axis=1)
+    b = np.random.default_rng(33).standard_normal(A.shape[0])
+    x = np.zeros_like(b)
+    for _ in range(2):
+        x = x + (b - A @ x) / d
+    x = x + T @ np.linalg.solve(T.T @ A @ T, T.T @ (b - A @ x))
+    for _ in range(2):
+        x = x + (b - A @ x) / d
+    assert np.allclose(o.vcycle(1, b), x, rtol=1e-9, atol=1e-12 * np.abs(x).max())
+
+
 @pytest.mark.parametrize("first", ["cptr", "cptr_uamg"])
 @pytest.mark.parametrize("sweeps", [1, 2])
 def test_two_grid_cycle_is_textbook(mid, sweeps, first, oracle_lib):
@@ -399,6 +456,71 @@ def test_bilu0_is_exact_on_a_chain(oracle_lib):
     assert np.allclose(A @ z, b, rtol=1e-10, atol=1e-10 * np.abs(b).max())
 
 
+def test_bilu0_in_a_given_order_is_ilu0_of_the_permuted_matrix(tiny, oracle_lib):
+    # a caller-given factor order pi: the factor is ILU(0) of P A P^T (rows and
+    # columns renumbered by pi) -- (LU)_ij = (P A P^T)_ij on the pattern -- and
+    # the second stage applies P^T (LU)^{-1} P; the identity order gives the
+    # natural-order factor bit for bit
+    n, nv = tiny.n, tiny.nv
+    v = np.random.default_rng(7).standard_normal(n * nv)
+    nat = O.Oracle.from_problem(tiny, first="none", second="bilu0")
+    ident = O.Oracle.from_problem(tiny, first="none", second="bilu0", ilu_order=np.arange(n))
+    assert np.array_equal(ident.apply(v), nat.apply(v))
+    perm = np.random.default_rng(8).permutation(n).astype(np.int32)
+    o = O.Oracle.from_problem(tiny, first="none", second="bilu0", ilu_order=perm)
+    f = o.ilu()
+    assert np.array_equal(f["perm"], perm)
+    rp, ci, bl = _permuted(tiny, perm)
+    A = dense_bsr(rp, ci, bl.reshape(-1), nv)
+    L, U = _lu_dense(f, rp, ci, nv, n)
+    mask = np.zeros((n, n), bool)
+    for i in range(n):
+        mask[i, ci[rp[i]:rp[i + 1]]] = True
+    M = np.kron(mask, np.ones((nv, nv), bool))
+    assert np.abs((L @ U - A)[M]).max() <= 1e-12 * np.abs(A).max()
+    idx = (perm[:, None] * nv + np.arange(nv)[None, :]).reshape(-1)   # factor row -> unknown
+    want = np.empty(n * nv)
+    want[idx] = np.linalg.solve(L @ U, v[idx])
+    assert np.allclose(o.apply(v), want, rtol=1e-10, atol=1e-12 * np.abs(want).max())
+
+
+def test_bilu0_over_a_partition_is_block_jacobi(oracle_lib):
+    # a partition of the cells: couplings between parts are dropped, so the
+    # factor is the ILU(0) of A with its cross-part blocks removed (block
+    # Jacobi over the parts).  On a chain every part is itself a chain, whose
+    # ILU(0) is its exact LU: the stage is the exact inverse of the
+    # block-diagonal truncation of A.
+    pr = make_problem(shape=(12, 1, 1), kind="iid", seed=4)
+    n, nv = pr.n, pr.nv
+    part = (np.arange(n) // 4).astype(np.int32)
+    o = O.Oracle.from_problem(pr, first="none", second="bilu0", ilu_part=part)
+    A = dense_bsr(pr.row_ptr, pr.col_idx, pr.vals, nv)
+    same = np.kron(part[:, None] == part[None, :], np.ones((nv, nv), bool))
+    Ab = np.where(same, A, 0.0)
+    assert (Ab != A).any()
+    v = np.random.default_rng(9).standard_normal(n * nv)
+    want = np.linalg.solve(Ab, v)
+    assert np.allclose(o.apply(v), want, rtol=1e-10, atol=1e-10 * np.abs(want).max())
+    # on a 3D grid: (LU)_ij = A_ij on the pattern of the truncated matrix and
+    # the factor holds no cross-part block
+    pr3 = make_problem(shape=(4, 3, 3), kind="iid", seed=11)
+    n3 = pr3.n
+    part3 = (np.arange(n3) % 2).astype(np.int32)            # two interleaved parts
+    o3 = O.Oracle.from_problem(pr3, first="none", second="bilu0", ilu_part=part3)
+    f = o3.ilu()
+    rp, ci = f["rp"], f["ci"]
+    for i in range(n3):
+        assert (part3[ci[rp[i]:rp[i + 1]]] == part3[i]).all()
+    L, U = _lu_dense(f, rp, ci, nv, n3)
+    A3 = dense_bsr(pr3.row_ptr, pr3.col_idx, pr3.vals, nv)
+    same3 = np.kron(part3[:, None] == part3[None, :], np.ones((nv, nv), bool))
+    mask = np.zeros((n3, n3), bool)
+    for i in range(n3):
+        mask[i, ci[rp[i]:rp[i + 1]]] = True
+    M = np.kron(mask, np.ones((nv, nv), bool))
+    assert np.abs((L @ U - np.where(same3, A3, 0.0))[M]).max() <= 1e-12 * np.abs(A3).max()
+
+
 # ---------------------------------------------------------------- two-stage
 def _columns(fn, N):
     return np.stack([fn(e) for e in np.eye(N)], axis=1)
@@ -440,6 +562,29 @@ def test_block_preconditioner_with_exact_solves_is_A00_inverse(tiny, oracle_lib)
     r0 = np.concatenate([b1[0::nv], b1[nv - 1::nv]])
     assert np.abs(r0).max() <= 1e-9 * np.abs(v).max()
     del full
+
+
+@pytest.mark.parametrize("first", ["cptr_lower", "cptr_upper"])
+def test_block_triangular_stages_with_exact_solves(tiny, first, oracle_lib):
+    # with exact A_pp^{-1} and the exact Schur complement S, dropping one
+    # factor of eq:Aschur leaves the inverse of a block triangular matrix:
+    # lower [A_pp 0; A_Tp S], upper [A_pp A_pT; 0 S] (independent of eq:Aschur:
+    # the triangular matrices are formed and inverted densely)
+    A, App, ApT, ATp, ATT, S = _dense_Ainv00(tiny, True)
+    n, nv = tiny.n, tiny.nv
+    srp = np.arange(0, n * n + 1, n, dtype=np.int32)
+    sci = np.tile(np.arange(n, dtype=np.int32), n)
+    o = O.Oracle(n, nv, tiny.row_ptr, tiny.col_idx, tiny.vals, srp, sci, S.reshape(-1),
+                 first=first, second="none", coarse_size=10_000)
+    Z = np.zeros((n, n))
+    T = np.block([[App, Z], [ATp, S]]) if first == "cptr_lower" else np.block([[App, ApT], [Z, S]])
+    v = np.random.default_rng(21).standard_normal(n * nv)
+    x1 = o.first_stage(v)
+    want = np.linalg.solve(T, np.concatenate([v[0::nv], v[nv - 1::nv]]))
+    got = np.concatenate([x1[0::nv], x1[nv - 1::nv]])
+    assert np.allclose(got, want, rtol=1e-10, atol=1e-10 * np.abs(want).max())
+    for u in range(1, nv - 1):
+        assert (x1[u::nv] == 0).all()
 
 
 def test_block_diagonal_stage_with_exact_solves(tiny, oracle_lib):
@@ -786,7 +931,7 @@ def _vcycle_matrix(o, which, n):
     return _columns(lambda e: o.vcycle(which, e), n)
 
 
-@pytest.mark.parametrize("first", ["cptr", "cptr_lower", "cpr", "cptr_bd", "cptr_uamg"])
+@pytest.mark.parametrize("first", ["cptr", "cptr_lower", "cptr_upper", "cpr", "cptr_bd", "cptr_uamg"])
 def test_first_stage_product_form(mid, first, oracle_lib):
     # eq:Aschur as a product of its three factors, each inverse replaced by the
     # (linear) V-cycle operator; CPR: R_p^T V(A_pp) R_p (Section 3.1).
@@ -806,9 +951,12 @@ def test_first_stage_product_form(mid, first, oracle_lib):
         # unknown-based stage (Section 3.4): one V-cycle on the coupled A_00
         M1 = _vcycle_matrix(o, 0, 2 * n)
     else:
+        # eq:Aschur = left . diag . right; the lower variant drops the left
+        # factor, the upper variant the right one
         Vs = _vcycle_matrix(o, 1, n)
-        left = np.block([[I, -Vp @ ApT], [Z, I]]) if first == "cptr" else np.eye(2 * n)
-        M1 = left @ np.block([[Vp, Z], [Z, Vs]]) @ np.block([[I, Z], [-ATp @ Vp, I]])
+        left = np.block([[I, -Vp @ ApT], [Z, I]]) if first != "cptr_lower" else np.eye(2 * n)
+        right = np.block([[I, Z], [-ATp @ Vp, I]]) if first != "cptr_upper" else np.eye(2 * n)
+        M1 = left @ np.block([[Vp, Z], [Z, Vs]]) @ right
     v = np.random.default_rng(5).standard_normal(n * nv)
     x1 = o.first_stage(v)
     want = M1 @ np.concatenate([v[0::nv], v[nv - 1::nv]])
