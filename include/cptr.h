@@ -63,7 +63,9 @@ extern "C" {
 /* first stage */
 #define CPTR_FIRST_NONE 0        /* x1 = 0 */
 #define CPTR_FIRST_BLOCK 1       /* CPTR-Block: the five steps of eq:Aschur */
-#define CPTR_FIRST_BLOCK_LOWER 2 /* right factor of eq:Aschur dropped (block lower triangular) */
+#define CPTR_FIRST_BLOCK_LOWER 2 /* left factor of eq:Aschur dropped: the inverse of the block
+                                    lower-triangular [A_pp 0; A_Tp S~_T] (steps 1-3 of the five,
+                                    d_p = x_p) */
 #define CPTR_FIRST_CPR 3         /* CPR: x1 = R_p^T V(A_pp) R_p v */
 #define CPTR_FIRST_BD 4          /* CPTR-BD(AMG) (Section 4.4): block-diagonal first stage,
                                     d_p = V(A_pp) b_p, d_T = V(A_TT) b_T (couplings left out) */
@@ -72,6 +74,9 @@ extern "C" {
                                     pressure-temperature block in unknown-wise order (each unknown
                                     coarsened on its own diagonal block, couplings kept in the
                                     Galerkin coarse operators) */
+#define CPTR_FIRST_BLOCK_UPPER 6 /* right factor of eq:Aschur dropped: the inverse of the block
+                                    upper-triangular [A_pp A_pT; 0 S~_T]: d_T = V(S~_T) b_T,
+                                    d_p = V(A_pp) (b_p - A_pT d_T) */
 
 /* Decoupling operators G = [I, -D; 0, I] (Section 3.1).  CPR: p = pressure,
  * s = every other unknown in slot order, D one 1 x (nv-1) block per cell; the
@@ -165,7 +170,7 @@ typedef struct {
   int ilu_level;         /* level of fill of the BILU second stages: 0 (BILU(0)) or 1 (BILU(1):
                             the blocks of A and the level-1 fill, Section 4's ILU(1)) (0);
                             the learned stage's fallback stays BILU(0) */
-  int schur;             /* S~_T of CPTR_FIRST_BLOCK(_LOWER): CPTR_SCHUR_* (ASSEMBLED) */
+  int schur;             /* S~_T of CPTR_FIRST_BLOCK(_LOWER, _UPPER): CPTR_SCHUR_* (ASSEMBLED) */
   int lrn_fallback;      /* CPTR_SECOND_LEARNED in fgmres_solve: 1 switch to the BILU(0)
                             fallback on a non-finite Arnoldi step or a restart cycle whose true
                             residual did not halve; 0 never (a non-finite step is then
@@ -216,7 +221,7 @@ void cptr_default_options(cptr_options *opt);
  *   out   receives the handle (NULL on failure).
  *   A     must stay alive and unchanged until cptr_destroy: A->vals (FP64) is
  *         BORROWED for the FP64 Arnoldi products; everything derived is owned.
- *   S_T   the assembled S~_T of eq:Se; required for CPTR_FIRST_BLOCK(_LOWER)
+ *   S_T   the assembled S~_T of eq:Se; required for CPTR_FIRST_BLOCK(_LOWER, _UPPER)
  *         with CPTR_SCHUR_ASSEMBLED, ignored (may be NULL) otherwise; with
  *         CPTR_SCHUR_ATT / _DIAG the library forms S~_T from A (a zero A_pp
  *         diagonal entry gives CPTR_ERR_SINGULAR_BLOCK).
@@ -237,6 +242,13 @@ int cptr_apply(cptr_handle *h, const double *v, double *z, void *stream);
 /* Only the first stage: x1 = M1^{-1} v prolonged to the full vector (zeros in
  * the saturation slots).  Device FP64 [n*nv].  Asynchronous. */
 int cptr_first_stage(cptr_handle *h, const double *v, double *x1, void *stream);
+
+/* The input of the second stage for v: b1 = v - A x1 with x1 = M1^{-1} v the
+ * first-stage result ("Two-stage preconditioners", Section 3), formed by the
+ * same kernels and in the handle's precision as inside cptr_apply (x1 = 0
+ * without a first stage), then widened to FP64.  v, b1: device FP64 [n*nv],
+ * must not alias.  Training inputs of a learned second stage.  Asynchronous. */
+int cptr_stage_residual(cptr_handle *h, const double *v, double *b1, void *stream);
 
 /* One AMG V-cycle from a zero initial guess on A_pp (which = 0) or the
  * second hierarchy (which = 1: S~_T, or A_TT with CPTR_FIRST_BD), in the
@@ -276,7 +288,7 @@ int cptr_krylov_vector(const cptr_handle *h, int j, double *out, void *stream);
  * system per nonlinear iteration).  A_vals: device FP64 BSR values in the
  * layout of cptr_bsr.vals (the handle borrows this pointer from now on, as it
  * did the original); S_vals: device FP64 values of S~_T in the pattern given
- * to cptr_setup (required for CPTR_FIRST_BLOCK / _BLOCK_LOWER with
+ * to cptr_setup (required for CPTR_FIRST_BLOCK / _BLOCK_LOWER / _BLOCK_UPPER with
  * CPTR_SCHUR_ASSEMBLED, else ignored: the algebraic S~_T is formed anew from
  * A_vals).
  * The aggregates of both AMG hierarchies and the block ILU's order, pattern

@@ -20,9 +20,9 @@
  * Adam; every step runs on the device (forward, A^T product, backward,
  * deterministic gradient reductions, Adam).
  * A handle set up with CPTR_SECOND_LEARNED applies the attached model and
- * falls back to BILU(0) (multicolour) if the stage produces a non-finite
- * value or if a whole FGMRES cycle fails to halve the true residual
- * (cptr_solve_info.fell_back).  Pointers are device pointers unless named
+ * falls back to BILU(0) in natural order (plain ILU(0)-CPTR) if the stage
+ * produces a non-finite value or if a whole FGMRES cycle fails to halve the
+ * true residual (cptr_solve_info.fell_back).  Pointers are device pointers unless named
  * *_host; status codes as in cptr.h.
  */
 #ifndef CPTR_LEARN_H

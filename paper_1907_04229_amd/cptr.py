@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(_HERE, "libcptr.so")
 
 CPTR_OK = 0
 CPTR_NOT_CONVERGED = 1
-FIRST = {"none": 0, "cptr": 1, "cptr_lower": 2, "cpr": 3, "cptr_bd": 4, "cptr_uamg": 5}
+FIRST = {"none": 0, "cptr": 1, "cptr_lower": 2, "cpr": 3, "cptr_bd": 4, "cptr_uamg": 5, "cptr_upper": 6}
 SECOND = {"none": 0, "bilu0": 1, "bilu0_mc": 2, "identity": 3, "learned": 4}
 PRECISION = {"fp64": 0, "fp32": 1}
 DECOUPLING = {"none": 0, "qi": 1, "ti": 2}
@@ -85,6 +85,7 @@ def load():
         L.cptr_setup.argtypes = [C.POINTER(vp), C.POINTER(Bsr), C.POINTER(Csr), C.POINTER(Options), vp]
         L.cptr_apply.argtypes = [vp, vp, vp, vp]
         L.cptr_first_stage.argtypes = [vp, vp, vp, vp]
+        L.cptr_stage_residual.argtypes = [vp, vp, vp, vp]
         L.cptr_vcycle.argtypes = [vp, ip, vp, vp, vp]
         L.fgmres_solve.argtypes = [vp, vp, vp, C.POINTER(SolveOpts), C.POINTER(SolveInfo), vp]
         L.cptr_krylov_vector.argtypes = [vp, ip, vp, vp]
@@ -183,6 +184,12 @@ def cptr_first_stage(h, v, x1, stream=None):
     import torch
     _check(load().cptr_first_stage(h, _ptr(v, torch.float64), _ptr(x1, torch.float64),
                                    _stream(stream)))
+
+
+def cptr_stage_residual(h, v, b1, stream=None):
+    import torch
+    _check(load().cptr_stage_residual(h, _ptr(v, torch.float64), _ptr(b1, torch.float64),
+                                      _stream(stream)))
 
 
 def cptr_vcycle(h, which, b, x, stream=None):

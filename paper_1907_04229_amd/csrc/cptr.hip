@@ -326,6 +326,15 @@ struct AmgDev {
         }
         upload(L->dinv, d);
         if (smoother == CPTR_SMOOTHER_GS) {
+          // every row needs a nonzero diagonal entry (the sweeps divide by it)
+          for (int i = 0; i < L->n; i++) {
+            double dii = 0.0;
+            for (int k = H.A.rp[i]; k < H.A.rp[i + 1]; k++)
+              if (H.A.ci[k] == i) dii = H.A.v[k];
+            if (dii == 0.0)
+              throw Error{CPTR_ERR_SINGULAR_BLOCK, "Gauss-Seidel smoother: zero diagonal entry in row " +
+                                                       std::to_string(i) + " of AMG level " + std::to_string(l)};
+          }
           // greedy colouring in natural order: the smallest colour not taken
           // by a lower-numbered neighbour (a proper colouring: the pattern is
           // symmetric); rows grouped by colour, ascending inside a colour
@@ -353,12 +362,24 @@ struct AmgDev {
           std::vector<T> av(H.A.v.begin(), H.A.v.end());
           upload(L->gs_v, av);
         }
-        // pre: sweeps passes over A, each leaving the residual of its iterate;
-        // post: sweeps Jacobi passes; restriction and prolongation once each
         double n = L->n;
-        bytes_per_cycle += (2.0 * sweeps) * (L->A.bytes() + 3 * n * s)  // A x, b, dinv, x
-                           + L->R.bytes() + n * s + H.R.nr * s          // R r
-                           + L->P.bytes() + 2 * n * s + H.P.nc * s;     // x += P x_c
+        if (smoother == CPTR_SMOOTHER_GS) {
+          // x = 0; sweeps forward and sweeps backward Gauss-Seidel sweeps, each
+          // reading the CSR values and indices, the row list, b_i and x_i and
+          // writing x_i (the x_j of the neighbours from cache); the residual
+          // b - A x; restriction; prolongation; the final copy to the output
+          const double sweep = double(H.A.nnz()) * (s + 4) + 4.0 * (n + 1) + 4.0 * n + 3 * n * s;
+          bytes_per_cycle += n * s + (2.0 * sweeps) * sweep + (L->A.bytes() + 3 * n * s)  // b - A x
+                             + L->R.bytes() + n * s + H.R.nr * s                          // R r
+                             + L->P.bytes() + 2 * n * s + H.P.nc * s                      // x += P x_c
+                             + 2 * n * s;                                                 // out = x
+        } else {
+          // pre: sweeps passes over A, each leaving the residual of its iterate;
+          // post: sweeps Jacobi passes; restriction and prolongation once each
+          bytes_per_cycle += (2.0 * sweeps) * (L->A.bytes() + 3 * n * s)  // A x, b, dinv, x
+                             + L->R.bytes() + n * s + H.R.nr * s          // R r
+                             + L->P.bytes() + 2 * n * s + H.P.nc * s;     // x += P x_c
+        }
       }
       lev.push_back(std::move(L));
     }
@@ -835,6 +856,7 @@ struct PrecondBase {
   virtual ~PrecondBase() = default;
   virtual void apply(hipStream_t st, const ApplySlots *slots, bool z_double) = 0;
   virtual void first_stage(hipStream_t st, const ApplySlots *slots) = 0;
+  virtual void stage_residual(hipStream_t st, const ApplySlots *slots, double *out) = 0;
   virtual void vcycle(hipStream_t st, int which, const double *b, double *x) = 0;
   virtual void set_learned(LearnedDev *l, const LearnModelDev *m) = 0;
   virtual bool &fallback_flag() = 0;
@@ -890,6 +912,12 @@ struct Precond : PrecondBase {
       amg_s.cycle(st, btt, dTT);
       return;
     }
+    if (fs == CPTR_FIRST_BLOCK_UPPER) {  // d_T = V(S~_T) b_T, d_p = V(A_pp) (b_p - A_pT d_T)
+      amg_s.cycle(st, btt, dTT);
+      ApT.template spmv<2>(st, dTT, bpp, t);
+      amg_p.cycle(st, t, dpp);
+      return;
+    }
     amg_p.cycle(st, bpp, xpp);
     ATp.template spmv<2>(st, xpp, btt, t);
     amg_s.cycle(st, t, dTT);
@@ -909,6 +937,31 @@ struct Precond : PrecondBase {
     return (fs == CPTR_FIRST_NONE || fs == CPTR_FIRST_CPR) ? nullptr : devp<T>(dT);
   }
 
+  // a9: the two-stage residual b1 = v - A x1 into b1 (x1 = 0 without a first stage)
+  template <int NV>
+  void form_b1(hipStream_t st, const ApplySlots *slots) {
+    const int n = op.n;
+    T *b1p = devp<T>(b1);
+    if (sl_vals64)
+      hipLaunchKernelGGL((k_resid_pT_sliced64<NV, T>), dim3((n + 63) / 64), dim3(64 * NV), 0, st, n, sl_kptr,
+                         sl_cols, sl_vals64, op.o.ip, op.o.iT, slots, x1p() ? x1p() : (const T *)zero_vec(), x1T(),
+                         b1p);
+    else
+      hipLaunchKernelGGL((k_resid_pT_sliced<NV, T>), dim3((n + 63) / 64), dim3(64 * NV), 0, st, n, sl_kptr,
+                         sl_cols, devp<T>(acol), slots, x1p() ? x1p() : (const T *)zero_vec(), x1T(), b1p);
+    LAUNCH_CHECK();
+  }
+
+  // the second stage's input b1 of v (first stage, a9), widened to FP64 into out
+  void stage_residual(hipStream_t st, const ApplySlots *slots, double *out) override {
+    apply_first(st, slots);
+    if (op.nv == 3) form_b1<3>(st, slots);
+    else form_b1<4>(st, slots);
+    hipLaunchKernelGGL((k_convert<T, double>), dim3(sgrid((size_t)op.n * op.nv)), dim3(kBlock), 0, st,
+                       (const T *)devp<T>(b1), out, (size_t)op.n * op.nv);
+    LAUNCH_CHECK();
+  }
+
   template <int NV, typename ZT>
   void apply_nv(hipStream_t st, const ApplySlots *slots) {
     const int n = op.n, ss = op.o.second_stage;
@@ -921,14 +974,7 @@ struct Precond : PrecondBase {
       LAUNCH_CHECK();
       return;
     }
-    if (sl_vals64)
-      hipLaunchKernelGGL((k_resid_pT_sliced64<NV, T>), dim3((n + 63) / 64), dim3(64 * NV), 0, st, n, sl_kptr,
-                         sl_cols, sl_vals64, op.o.ip, op.o.iT, slots, x1p() ? x1p() : (const T *)zero_vec(), x1T(),
-                         b1p);
-    else
-      hipLaunchKernelGGL((k_resid_pT_sliced<NV, T>), dim3((n + 63) / 64), dim3(64 * NV), 0, st, n, sl_kptr,
-                         sl_cols, devp<T>(acol), slots, x1p() ? x1p() : (const T *)zero_vec(), x1T(), b1p);
-    LAUNCH_CHECK();
+    form_b1<NV>(st, slots);
     if (ss == CPTR_SECOND_LEARNED && !fell_back) {
       if (!model || !lrn) throw Error{CPTR_ERR_INVALID_ARG, "no learned model attached to this handle"};
       lrn->forward<NV, T, ZT, T>(st, *model, b1p, false,
@@ -1207,8 +1253,10 @@ static void build_precond(cptr_handle *h, const std::vector<int> &rp, const std:
     bytes += ncyc * P.amg_p.bytes_per_cycle;
     if (P.have_s) {
       bytes += P.amg_s.bytes_per_cycle;
-      if (o.first_stage != CPTR_FIRST_BD) bytes += P.ATp.bytes() + 3.0 * n * s;  // b~_T
-      if (o.first_stage == CPTR_FIRST_BLOCK) bytes += P.ApT.bytes() + 3.0 * n * s;
+      if (o.first_stage == CPTR_FIRST_BLOCK || o.first_stage == CPTR_FIRST_BLOCK_LOWER)
+        bytes += P.ATp.bytes() + 3.0 * n * s;  // b~_T
+      if (o.first_stage == CPTR_FIRST_BLOCK || o.first_stage == CPTR_FIRST_BLOCK_UPPER)
+        bytes += P.ApT.bytes() + 3.0 * n * s;  // b~_p
     }
   }
   if (o.second_stage == CPTR_SECOND_LEARNED) {
@@ -1322,7 +1370,7 @@ static void validate_and_fetch(const cptr_bsr *A, const cptr_csr *S, const cptr_
     throw Error{CPTR_ERR_INVALID_ARG, "invalid p/T slots"};
   if (o.amg_max_levels < 1 || o.amg_coarse_size < 1 || o.amg_sweeps < 1 || !(o.amg_theta >= 0.0))
     throw Error{CPTR_ERR_INVALID_ARG, "invalid AMG options"};
-  if (o.first_stage < 0 || o.first_stage > 5) throw Error{CPTR_ERR_INVALID_ARG, "invalid first stage"};
+  if (o.first_stage < 0 || o.first_stage > 6) throw Error{CPTR_ERR_INVALID_ARG, "invalid first stage"};
   if (o.decoupling < 0 || o.decoupling > 2) throw Error{CPTR_ERR_INVALID_ARG, "invalid decoupling"};
   if (o.ilu_level != 0 && o.ilu_level != 1) throw Error{CPTR_ERR_UNSUPPORTED, "ilu_level must be 0 or 1"};
   if (o.schur < CPTR_SCHUR_ASSEMBLED || o.schur > CPTR_SCHUR_DIAG) throw Error{CPTR_ERR_INVALID_ARG, "invalid schur"};
@@ -1362,7 +1410,8 @@ static void validate_and_fetch(const cptr_bsr *A, const cptr_csr *S, const cptr_
     }
   for (double v : vals)
     if (!std::isfinite(v)) throw Error{CPTR_ERR_NONFINITE, "non-finite value in A"};
-  const bool need_s = o.first_stage == CPTR_FIRST_BLOCK || o.first_stage == CPTR_FIRST_BLOCK_LOWER;
+  const bool need_s = o.first_stage == CPTR_FIRST_BLOCK || o.first_stage == CPTR_FIRST_BLOCK_LOWER ||
+                      o.first_stage == CPTR_FIRST_BLOCK_UPPER;
   if (need_s && o.schur != CPTR_SCHUR_ASSEMBLED) {
     // Section 3.3.1's algebraic approximations, formed from A
     sh = schur_algebraic(n, nv, o.ip, o.iT, rp.data(), ci.data(), vals.data(), o.schur == CPTR_SCHUR_DIAG);
@@ -1833,6 +1882,8 @@ static int apply_common(cptr_handle *h, const double *v, void *z, void *stream, 
     if (what == 0) {
       h->pc->apply(st, sl, true);
       h->stats.applies++;
+    } else if (what == 3) {
+      h->pc->stage_residual(st, sl, (double *)z);
     } else {
       h->pc->first_stage(st, sl);
     }
@@ -1860,6 +1911,10 @@ int cptr_first_stage(cptr_handle *h, const double *v, double *x1, void *stream) 
     }
   }
   return apply_common(h, v, x1, stream, 1, 0);
+}
+
+int cptr_stage_residual(cptr_handle *h, const double *v, double *b1, void *stream) {
+  return apply_common(h, v, b1, stream, 3, 0);
 }
 
 int cptr_vcycle(cptr_handle *h, int which, const double *b, double *x, void *stream) {
@@ -1917,7 +1972,7 @@ int cptr_krylov_vector(const cptr_handle *h, int j, double *out, void *stream) {
 int cptr_update_values(cptr_handle *h, const double *A_vals, const double *S_vals, void *stream) {
   if (!h || !A_vals) return fail(Error{CPTR_ERR_INVALID_ARG, "null argument"});
   const int fs = h->op.o.first_stage;
-  const bool need_s = fs == CPTR_FIRST_BLOCK || fs == CPTR_FIRST_BLOCK_LOWER;
+  const bool need_s = fs == CPTR_FIRST_BLOCK || fs == CPTR_FIRST_BLOCK_LOWER || fs == CPTR_FIRST_BLOCK_UPPER;
   const bool two_hier = need_s || fs == CPTR_FIRST_BD;  // a second AMG hierarchy to keep
   const bool caller_s = need_s && h->op.o.schur == CPTR_SCHUR_ASSEMBLED;
   if (caller_s && !S_vals) return fail(Error{CPTR_ERR_INVALID_ARG, "S~_T values required by this first stage"});
@@ -1970,17 +2025,22 @@ int cptr_update_values(cptr_handle *h, const double *A_vals, const double *S_val
     }
     h->vals = A_vals;
     build_sliced(h, rp, ci, vals);
-    LearnedDev *lrn = h->lrn.get();
     if (h->op.o.precision == CPTR_FP32)
       build_precond<float>(h, rp, ci, vals, need_s ? &sh : nullptr, &agg_p, two_hier ? &agg_s : nullptr,
                            ilu_f.get());
     else
       build_precond<double>(h, rp, ci, vals, need_s ? &sh : nullptr, &agg_p, two_hier ? &agg_s : nullptr,
                             ilu_d.get());
-    if (lrn) {
-      lrn->build(n, nv, rp, ci, vals);  // edge features of the new values
-      if (h->model) h->pc->set_learned(lrn, &h->model->dev);
+    // the learned stage's matrix data: build_precond made it anew for a
+    // learned second stage; a handle of another second stage that was
+    // attached for training keeps its own, rebuilt here from the new values
+    if (h->lrn && h->op.o.second_stage != CPTR_SECOND_LEARNED) {
+      const bool col = h->lrn->use_col;
+      h->lrn->build(n, nv, rp, ci, vals);
+      h->lrn->use_col = col;
+      h->lrn->have_pass = false;
     }
+    if (h->lrn && h->model) h->pc->set_learned(h->lrn.get(), &h->model->dev);
     if (h->graph_exec) {
       (void)hipGraphExecDestroy(h->graph_exec);
       (void)hipGraphDestroy(h->graph);

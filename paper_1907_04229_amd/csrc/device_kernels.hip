@@ -435,7 +435,7 @@ __global__ void __launch_bounds__(kBlock) k_gs_color(int cnt, const int *__restr
   const int t = blockIdx.x * kBlock + threadIdx.x;
   if (t >= cnt) return;
   const int i = rows[t];
-  T s = b[i], d = T(1);
+  T s = b[i], d = T(1);  // the diagonal entry is present and nonzero on every row (checked at setup)
   for (int k = rp[i]; k < rp[i + 1]; k++) {
     const int j = ci[k];
     if (j == i)
@@ -452,6 +452,8 @@ template <typename T>
 __device__ __forceinline__ void gs_row_wave(int i, int lane, const int *__restrict__ rp,
                                             const int *__restrict__ ci, const T *__restrict__ v,
                                             const T *__restrict__ b, T *x) {
+  // the diagonal entry is present and nonzero on every row (checked at setup);
+  // lanes that do not hold it add zero
   T s = T(0), d = T(0);
   for (int k = rp[i] + lane; k < rp[i + 1]; k += 64) {
     const int j = ci[k];

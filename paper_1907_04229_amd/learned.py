@@ -18,7 +18,8 @@ def training_pairs(solver, count, seed, restart=30, rtol=1e-6):
     """(count, n*nv) FP64 device tensor of second-stage inputs for one system.
 
     The vectors the preconditioner sees inside FGMRES are the Arnoldi basis
-    vectors v_j; each gives the pair input b1 = v_j - A M1^{-1} v_j.  They are
+    vectors v_j; each gives the pair input b1 = v_j - A M1^{-1} v_j, formed by
+    the library's two-stage residual (cptr_stage_residual).  They are
     collected from FGMRES solves (with the solver's own second stage) of the
     Newton right-hand side and of products A x of random increments."""
     import torch
@@ -29,8 +30,6 @@ def training_pairs(solver, count, seed, restart=30, rtol=1e-6):
     rng = np.random.Generator(np.random.PCG64(seed))
     scale = np.array([_SCALE["p"]] + [_SCALE["s"]] * (nv - 2) + [_SCALE["T"]])
     out = torch.empty((count, N), dtype=torch.float64, device=dev)
-    x1 = torch.empty(N, dtype=torch.float64, device=dev)
-    ax = torch.empty(N, dtype=torch.float64, device=dev)
     v = torch.empty(N, dtype=torch.float64, device=dev)
     k, solves = 0, 0
     while k < count:
@@ -47,9 +46,9 @@ def training_pairs(solver, count, seed, restart=30, rtol=1e-6):
             if k == count:
                 break
             cptr.cptr_krylov_vector(solver.h, j, v)
-            cptr.cptr_first_stage(solver.h, v, x1)
-            cptr.cptr_bsr_spmv(n, nv, solver.rp, solver.ci, solver.vals, x1, ax)
-            out[k] = v - ax
+            # b1 = v - A M1^{-1} v as the second stage receives it (the
+            # library's two-stage residual, in the solver's precision)
+            cptr.cptr_stage_residual(solver.h, v, out[k])
             k += 1
         if solves > 4 * count:
             raise RuntimeError("FGMRES produced too few basis vectors for the training set")

@@ -78,7 +78,7 @@ def test_binding_stage_codes_match_the_header():
     text = open(os.path.join(ROOT, "include", "cptr.h")).read()
     defs = {m.group(1): int(m.group(2)) for m in re.finditer(r"#define\s+(CPTR_\w+)\s+(-?\d+)", text)}
     first = {"none": "NONE", "cptr": "BLOCK", "cptr_lower": "BLOCK_LOWER", "cpr": "CPR",
-             "cptr_bd": "BD", "cptr_uamg": "UAMG"}
+             "cptr_bd": "BD", "cptr_uamg": "UAMG", "cptr_upper": "BLOCK_UPPER"}
     assert set(first) == set(cptr.FIRST)
     for k, v in first.items():
         assert cptr.FIRST[k] == defs["CPTR_FIRST_" + v], k

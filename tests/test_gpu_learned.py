@@ -131,6 +131,40 @@ def test_column_schedule_is_bit_exact(k):
     assert torch.equal(res[0][2], res[1][2])
 
 
+def test_update_values_of_a_learned_handle_equals_fresh_setup():
+    """cptr_update_values on a handle whose second stage is the learned one,
+    with a model attached: the stage's matrix data follow the new values 2A,
+    and the application and the forward pass equal those of a fresh setup of
+    2A with the same model, bit for bit.  A BILU(0) handle attached for
+    training rebuilds its edge features from the new values as well."""
+    banner("update_values, learned stage")
+    import copy
+    pr = case("nv3c")[0]
+    pr2 = copy.copy(pr)
+    pr2.vals = pr.vals * 2.0
+    pr2.st_vals = pr.st_vals * 2.0
+    theta = init_params(pr.nv, seed=9, out_scale=0.3)
+    s, m = solver_with(pr, theta, precision="fp32", second_stage="learned")
+    s.update_values(pr2)
+    f, mf = solver_with(pr2, theta, precision="fp32", second_stage="learned")
+    t, mt = solver_with(pr, theta, precision="fp32", second_stage="bilu0")
+    t.update_values(pr2)
+    rng = np.random.default_rng(10)
+    v = torch.as_tensor(rng.standard_normal(pr.n * pr.nv), device=DEV)
+    assert torch.equal(s.apply(v), f.apply(v))
+    b1 = torch.as_tensor(rng.standard_normal(pr.n * pr.nv), device=DEV)
+    zf = cptr.cptr_learn_forward(f, b1)
+    assert torch.equal(cptr.cptr_learn_forward(s, b1), zf)
+    assert torch.equal(cptr.cptr_learn_forward(t, b1), zf)
+    x, info = s.solve(torch.as_tensor(pr2.b, device=DEV), restart=30, rtol=1e-6)
+    xf, infof = f.solve(torch.as_tensor(pr2.b, device=DEV), restart=30, rtol=1e-6)
+    assert info["iters"] == infof["iters"] and torch.equal(x, xf)
+    for h in (s, f, t):
+        h.close()
+    for mm in (m, mf, mt):
+        mm.close()
+
+
 @pytest.mark.parametrize("name", ["nv3", "nv4"])
 def test_gradient_matches_oracle(name):
     banner(f"gradient {name}")

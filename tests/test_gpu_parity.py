@@ -133,7 +133,7 @@ def test_aggregates_and_schedule_bit_exact(name, first):
 
 # ---------------------------------------------------------------- one application
 @pytest.mark.parametrize("name", ["ragged", "three", "small", "chain", "single"])
-@pytest.mark.parametrize("first", ["cptr", "cptr_lower", "cpr", "cptr_bd", "cptr_uamg"])
+@pytest.mark.parametrize("first", ["cptr", "cptr_lower", "cptr_upper", "cpr", "cptr_bd", "cptr_uamg"])
 def test_vcycle_and_first_stage_fp64(name, first):
     banner(f"first stage fp64 {name} {first}")
     pr = prob(name)
@@ -219,7 +219,8 @@ def test_diagonal_storage(name):
 @pytest.mark.parametrize("first,second", [("cptr", "bilu0"), ("cptr", "bilu0_mc"),
                                           ("cpr", "bilu0"), ("none", "bilu0"),
                                           ("cptr", "identity"), ("cptr_lower", "bilu0_mc"),
-                                          ("cptr_bd", "bilu0_mc"), ("cptr_uamg", "bilu0")])
+                                          ("cptr_upper", "bilu0"), ("cptr_bd", "bilu0_mc"),
+                                          ("cptr_uamg", "bilu0")])
 def test_apply_fp64(name, first, second):
     banner(f"apply fp64 {name} {first}+{second}")
     pr = prob(name)
@@ -256,6 +257,42 @@ def test_apply_fp32(name, second):
     print(f"fp32 first stage max rel err {e1:.2e}, application 2-norm rel err {e2:.2e}")
     assert e1 <= 1e-5
     assert e2 <= (1e-2 if second == "bilu0_mc" else 0.2)
+    s.close()
+
+
+@pytest.mark.parametrize("name", ["ragged", "three", "small", "single"])
+@pytest.mark.parametrize("precision,r64", [("fp64", 0), ("fp32", 0), ("fp32", 1)])
+def test_stage_residual(name, precision, r64):
+    """cptr_stage_residual: the second stage's input b1 = v - A x1 (a9) for the
+    handle's own first-stage result x1, against v - A x1 formed by the oracle's
+    FP64 BSR product from that x1.  FP64: rounding of a sum of 7 nv products,
+    <= 1e-13 of sum_j |a_ij x_j| + |v_i|.  FP32 (FP32 copies of the p and T
+    columns, FP32 accumulation): a dot product of K = 2 x 7 terms with FP32
+    operands and accumulation errs by at most (K + 2) u sum |a x| + u |v_i|,
+    u = 2^-24; checked at 32 u.  FP32 with FP64 accumulation (resid_fp64):
+    only the final rounding of b1 to FP32, <= u |b1_i| + 1e-13 of the sum."""
+    banner(f"stage residual {name} {precision} resid_fp64={r64}")
+    pr = prob(name)
+    s = solver(pr, precision=precision, resid_fp64=r64, second_stage="bilu0", amg_coarse_size=16)
+    v = np.random.default_rng(41).standard_normal(pr.n * pr.nv)
+    x1 = torch.empty_like(dev(v))
+    b1 = torch.empty_like(x1)
+    cptr.cptr_first_stage(s.h, dev(v), x1)
+    cptr.cptr_stage_residual(s.h, dev(v), b1)
+    torch.cuda.synchronize()
+    x1, b1 = x1.cpu().numpy(), b1.cpu().numpy()
+    ref = v - O.bsr_spmv(pr.row_ptr, pr.col_idx, pr.vals, pr.nv, x1)
+    mag = O.bsr_spmv(pr.row_ptr, pr.col_idx, np.abs(pr.vals), pr.nv, np.abs(x1)) + np.abs(v)
+    u = 2.0 ** -24
+    if precision == "fp64":
+        bound = 1e-13 * mag
+    elif r64:
+        bound = u * np.abs(ref) + 1e-13 * mag
+    else:
+        bound = 32 * u * mag
+    worst = float(np.max(np.abs(b1 - ref) / np.maximum(bound, 1e-300)))
+    print(f"worst error / bound {worst:.3f}")
+    assert worst <= 1.0
     s.close()
 
 
@@ -442,7 +479,7 @@ def test_bilu1_fp64(name, second):
 @pytest.mark.parametrize("name", ["ragged", "three", "small", "chain"])
 @pytest.mark.parametrize("first,second", [("cptr", "bilu0"), ("cptr", "bilu0_mc"),
                                           ("cpr", "bilu0_mc"), ("cptr_bd", "bilu0"),
-                                          ("cptr_uamg", "bilu0_mc")])
+                                          ("cptr_uamg", "bilu0_mc"), ("cptr_upper", "bilu0")])
 @pytest.mark.parametrize("graph", [1, 0])
 def test_fgmres_fp64_matches_oracle(name, first, second, graph):
     banner(f"fgmres fp64 {name} {first}+{second} graph={graph}")
@@ -527,14 +564,14 @@ def test_invalid_inputs_are_rejected():
         cptr.Solver(replace(pr, vals=sing.reshape(-1)), device=DEV, first_stage="cpr")
     assert e.value.code in (-4, -7)
     # decoupling operators belong to the CPR and CPTR-uAMG first stages
-    for first in ("cptr", "cptr_lower", "cptr_bd"):
+    for first in ("cptr", "cptr_lower", "cptr_upper", "cptr_bd"):
         with pytest.raises(cptr.CptrError) as e:
             cptr.Solver(pr, device=DEV, first_stage=first, decoupling="ti")
         assert e.value.code == -2
 
 
 @pytest.mark.parametrize("name", ["three", "small"])
-@pytest.mark.parametrize("first", ["cptr", "cptr_bd", "cptr_uamg"])
+@pytest.mark.parametrize("first", ["cptr", "cptr_upper", "cptr_bd", "cptr_uamg"])
 def test_update_values_equals_fresh_setup(name, first):
     """cptr_update_values with 2A (and 2 S~_T): the strength test, the
     prolongator weights and the Galerkin products scale exactly, so the kept
