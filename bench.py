@@ -17,14 +17,22 @@ initialisation and is trained by the library's own kernels on FGMRES Arnoldi
 vectors of eight 64x64x32 systems with seeds 100-107 of the same field model
 (the solved system, seed 200, is held out), keeping the parameters whose
 learned-stage FGMRES solves of two validation systems of the solved size
-(seeds 190, 191) take the fewest iterations in total.  After the timed run the 128x128x64 systems of seeds
-200-204 are solved with the trained network, the untrained one and the
-BILU(0) second stages, and their iterations and times reported (skipped with
-`--no-held-out`).
+(seeds 190, 191) take the fewest iterations in total.  With `--held-out` the
+128x128x64 systems of seeds 200-204 are then solved with the trained network,
+the untrained one and the BILU(0) second stages, and their iterations and
+times reported.
+
+A second block measures the 128x128x64 three-phase case (nv = 4, ln k field
+with std 2.5): plain FP64 CPTR with natural-order BILU(0) against CPTR with
+the FP32 preconditioner whose BILU(0) is split into block-Jacobi parts of
+whole grid columns (`--parts`, the parallel ILU(0) of the paper's
+multi-process runs), with the two-stage residual and the rows of the ILU
+solves summed in FP64.
 
 Prints one JSON line (keys below).  `--probe` runs only a short learned
-forward pass, the layer kernel and a plain device copy, for hardware-counter
-runs of the profiler.
+forward pass, each layer kernel once more and a plain device copy, for
+hardware-counter runs of the profiler; `--traffic FETCH_DB WRITE_DB` turns
+the two counter databases of such runs into the per-kernel traffic record.
 """
 import argparse
 import hashlib
@@ -40,12 +48,13 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "learned_layer_traffic.json")
 LAYER_SRC = os.path.join(ROOT, "paper_1907_04229_amd", "csrc", "learned_kernels.hip")
-FIRST_NAME = {"cptr": "CPTR-Block", "cptr_lower": "CPTR-BlockLower", "cpr": "CPR", "cptr_bd": "CPTR-BD",
-              "cptr_uamg": "CPTR-uAMG"}
+FIRST_NAME = {"cptr": "CPTR-Block", "cptr_lower": "CPTR-BlockLower", "cptr_upper": "CPTR-BlockUpper", "cpr": "CPR",
+              "cptr_bd": "CPTR-BD", "cptr_uamg": "CPTR-uAMG"}
 TRAIN_SEED0 = 100  # --train-systems N takes the seeds 100 .. 100 + N - 1
 VAL_SEEDS = (190, 191)  # validation fields of the model selection, at full size
 HELD_OUT_SEEDS = (200, 201, 202, 203, 204)
 TRAIN_SHAPE = (64, 64, 32)
+HIDDEN = 64
 
 
 def log(msg):
@@ -57,51 +66,71 @@ def layer_source_hash():
         return hashlib.sha256(f.read()).hexdigest()
 
 
-def recorded_traffic(cells, nv):
-    """HBM bytes per launch of the middle layer from the committed counter
-    runs, if they were taken on the current kernel source, cell count and
-    number of unknowns per cell."""
+def layer_method_bytes(layer, nv):
+    """Bytes per cell that one inference launch of learned layer `layer` must
+    move (the method's, not the kernel's): the six nv x nv edge blocks in
+    BF16; layer 0 reads r = D^{-1} b1 (nv FP32) and writes h1 (64 BF16);
+    layer 1 reads h1 and writes h2; layer 2 (as relaunched alone, writing the
+    FP64 output z2) reads h2 and r and writes z2 (nv FP64)."""
+    edges = 6 * nv * nv * 2
+    if layer == 0:
+        return 4 * nv + edges + HIDDEN * 2
+    if layer == 1:
+        return HIDDEN * 2 + edges + HIDDEN * 2
+    return HIDDEN * 2 + edges + 4 * nv + 8 * nv
+
+
+def recorded_traffic(kernel, cells, nv):
+    """HBM bytes per launch of a learned layer kernel from the committed
+    counter runs, if they were taken on the current kernel source, cell count
+    and number of unknowns per cell."""
     try:
         with open(TRAFFIC_FILE) as f:
-            rec = json.load(f)
+            recs = json.load(f)
     except (OSError, ValueError):
         return None
-    if (rec.get("source_sha256") != layer_source_hash() or rec.get("cells") != cells
-            or f"<{nv}," not in rec.get("kernel", "")):
-        return None
-    return rec.get("bytes_per_launch")
+    for rec in recs.get("kernels", []):
+        if (rec.get("layer") == kernel and rec.get("source_sha256") == layer_source_hash()
+                and rec.get("cells") == cells and rec.get("nv") == nv):
+            return rec.get("bytes_per_launch")
+    return None
 
 
-def layer_roofline(solver, reps=50):
-    """Average duration of the middle layer kernel of the learned stage (BF16
-    activations), timed with HIP events on the stream it is launched on,
-    against its algorithmic HBM bytes: BF16 activations read and written
-    (2 x 64 x 2 B) and six BF16 edge blocks (6 x 16 x 2 B) per cell, plus the
-    presence mask (1 B) for the tile-order kernel.  On a grid whose planes are
-    whole tiles of 16 cells the library runs the z-column kernel, which reads
-    no mask."""
+LAYER_KERNEL = {0: "k_lrn_layer_first<{nv},true,false,bf16>",
+                1: "k_lrn_layer_col<{nv},false,false,bf16>",
+                2: "k_lrn_layer_col<{nv},false,true,bf16>"}
+
+
+def layer_timings(solver, reps=50):
+    """Average duration of each learned layer kernel (BF16 activations),
+    timed with HIP events on the stream it is launched on, against the
+    method's bytes per launch (layer_method_bytes)."""
     import torch
     from paper_1907_04229_amd import cptr
     n, nv = solver.problem.n, solver.problem.nv
-    nx, ny, _ = solver.problem.shape
-    column = (nx * ny) % 16 == 0
     st = torch.cuda.current_stream()
-    for _ in range(3):
-        cptr.cptr_learn_rerun_layer(solver, 1, None, st)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(st)
-    for _ in range(reps):
-        cptr.cptr_learn_rerun_layer(solver, 1, None, st)
-    e1.record(st)
-    e1.synchronize()
-    avg_s = e0.elapsed_time(e1) / reps * 1e-3
-    algo = n * (2 * 64 * 2 + 6 * 16 * 2 + (0 if column else 1))
-    gbs = algo / avg_s / 1e9
-    name = (f"k_lrn_layer_col<{nv},false,false,bf16> (message-passing layer, inference, z-column schedule)"
-            if column else f"k_lrn_layer<{nv},false,false,bf16> (message-passing layer, inference)")
-    return dict(bound="hbm", achieved=round(gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                frac=round(gbs / HBM_PEAK_GBS, 4), traffic=recorded_traffic(n, nv), kernel=name,
-                bytes_per_launch=int(algo), avg_us=round(avg_s * 1e6, 2), launches=reps)
+    z2 = torch.empty(n * nv, dtype=torch.float64, device="cuda")
+    rows = []
+    for layer in (0, 1, 2):
+        out = z2 if layer == 2 else None
+        for _ in range(3):
+            cptr.cptr_learn_rerun_layer(solver, layer, out, st)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(reps):
+            cptr.cptr_learn_rerun_layer(solver, layer, out, st)
+        e1.record(st)
+        e1.synchronize()
+        avg_s = e0.elapsed_time(e1) / reps * 1e-3
+        algo = n * layer_method_bytes(layer, nv)
+        gbs = algo / avg_s / 1e9
+        name = LAYER_KERNEL[layer].format(nv=nv)
+        rows.append(dict(kernel=name, layer=layer, achieved=round(gbs, 1), unit="GB/s",
+                         frac=round(gbs / HBM_PEAK_GBS, 4), bytes_per_launch=int(algo),
+                         method_bytes_per_cell=layer_method_bytes(layer, nv),
+                         avg_us=round(avg_s * 1e6, 2), launches=reps,
+                         traffic=recorded_traffic(layer, n, nv)))
+    return rows
 
 
 def spmv_roofline(pr, solver, reps=50):
@@ -129,23 +158,30 @@ def spmv_roofline(pr, solver, reps=50):
                 frac=round(gbs / HBM_PEAK_GBS, 4), bytes_per_launch=int(algo), avg_us=round(avg_s * 1e6, 2))
 
 
-def cpu_baseline(pr, iters):
-    """The FP64 oracle (plain CPTR: AMG + BILU(0) natural order) on the same
-    system: setup excluded, FGMRES(30) capped at `iters` inner iterations."""
+def cpu_baseline(pr, maxit=None):
+    """The FP64 oracle (plain CPTR: AMG + BILU(0) in natural order, FGMRES(30)
+    to rtol 1e-6) on the same system, single thread, setup timed apart;
+    `maxit` caps the inner iterations (None: to the tolerance)."""
     from oracle import oracle as O
     O.build(force=False)
     t0 = time.perf_counter()
     o = O.Oracle.from_problem(pr, first="cptr", second="bilu0")
     t_setup = time.perf_counter() - t0
     t0 = time.perf_counter()
-    _, info = o.fgmres(pr.b, m=30, rtol=1e-6, maxit=iters)
+    _, info = o.fgmres(pr.b, m=30, rtol=1e-6, maxit=maxit or 1000)
     t = time.perf_counter() - t0
     o.close()
-    return dict(value=round(pr.n * info["iters"] / t, 1), unit="cell-iters/s", cores=1,
-                kind="oracle",
-                sample=f"same {pr.n:,}-cell system, FP64 CPTR-Block(AMG)+BILU0(natural), FGMRES(30), "
-                       f"first {info['iters']} inner iterations in {t:.1f} s (setup {t_setup:.1f} s "
-                       f"excluded), single thread")
+    try:
+        host = len(os.sched_getaffinity(0))
+    except AttributeError:
+        host = os.cpu_count()
+    done = "to rtol 1e-6" if info["converged"] else f"capped at {info['iters']} inner iterations"
+    return dict(value=round(t, 3), unit="s", cores=1, host_cores=host, kind="oracle",
+                iters=info["iters"], converged=info["converged"], relres_true=info["relres_true"],
+                setup_s=round(t_setup, 2), cell_iters_per_s=round(pr.n * info["iters"] / t, 1),
+                sample=f"the whole {pr.n:,}-cell system, FP64 CPTR-Block(AMG)+BILU0(natural), FGMRES(30) "
+                       f"{done} ({info['iters']} inner iterations), setup ({t_setup:.1f} s) excluded, "
+                       f"one thread of the host's {host}")
 
 
 def train_model(cfg, steps, lr, systems, pairs, batch, first, log_fn, lr_final=None, rollback=None):
@@ -218,8 +254,8 @@ def held_out_eval(cfg, model, restart, first, log_fn):
 
 
 def probe(cfg_name):
-    """Short run for the hardware-counter passes: one learned forward, the
-    middle layer three more times, and a 256 MiB device copy three times."""
+    """Short run for the hardware-counter passes: one learned forward, each
+    layer kernel three more times, and a 256 MiB device copy three times."""
     import torch
     from paper_1907_04229_amd import cptr
     from paper_1907_04229_amd.learned_init import neumann_params
@@ -229,9 +265,10 @@ def probe(cfg_name):
     m = cptr.LearnModel(pr.nv, neumann_params(pr.nv, seed=1))
     m.attach(s)
     b1 = torch.randn(pr.n * pr.nv, dtype=torch.float64, device="cuda")
-    cptr.cptr_learn_forward(s, b1)
-    for _ in range(3):
-        cptr.cptr_learn_rerun_layer(s, 1)
+    z2 = cptr.cptr_learn_forward(s, b1)
+    for layer in (0, 1, 2):
+        for _ in range(3):
+            cptr.cptr_learn_rerun_layer(s, layer, z2 if layer == 2 else None)
     a = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
     c = torch.empty_like(a)
     for _ in range(3):
@@ -240,6 +277,111 @@ def probe(cfg_name):
     s.close()
     m.close()
     log(f"probe done: {pr.n} cells, copy of {a.numel() * 4} bytes")
+
+
+def trace_solves(cfg_name):
+    """Two learned+FP32 solves of the workload (Neumann-series network), the
+    second one to be read from a kernel trace (trace_summary)."""
+    import torch
+    from paper_1907_04229_amd import cptr
+    from paper_1907_04229_amd.learned_init import neumann_params
+    from paper_1907_04229_amd.synth import make_problem
+    pr = make_problem(config=cfg_name)
+    b = torch.as_tensor(pr.b, device="cuda")
+    s = cptr.Solver(pr, precision="fp32", second_stage="learned")
+    m = cptr.LearnModel(pr.nv, neumann_params(pr.nv, seed=1))
+    m.attach(s)
+    for k in range(2):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, info = s.solve(b, restart=30, rtol=1e-6)
+        torch.cuda.synchronize()
+        log(f"trace solve {k}: {info['iters']} iterations, {(time.perf_counter() - t0) * 1e3:.1f} ms")
+    s.close()
+    m.close()
+
+
+def trace_summary(csv_path):
+    """Markdown table of the kernels of the last FGMRES solve in a rocprofv3
+    kernel trace (CSV) of `bench.py --trace`: the solve starts at the second
+    half of the restart-cycle initialisations (k_cycle_init)."""
+    import csv
+    import re
+    with open(csv_path) as f:
+        rows = list(csv.DictReader(f))
+    name_key = "Kernel_Name" if "Kernel_Name" in rows[0] else "Kernel Name"
+    rows = [(r[name_key], int(r["Start_Timestamp"]), int(r["End_Timestamp"])) for r in rows]
+    rows.sort(key=lambda r: r[1])
+    inits = [r[1] for r in rows if "k_cycle_init" in r[0]]
+    t0 = inits[len(inits) // 2]
+    # the solve's first kernels (the norm of b, the residual) come before its first cycle
+    norms = [r[1] for r in rows if r[1] < t0 and "k_norm2_partial" in r[0]]
+    t0 = norms[-2] if len(norms) >= 2 else t0
+    sel = [r for r in rows if r[1] >= t0]
+    iters = sum(1 for r in sel if "k_givens" in r[0])
+    agg = {}
+    for n, a, b in sel:
+        k = re.sub(r"\(.*", "", n).replace("void ", "")
+        c, t = agg.get(k, (0, 0.0))
+        agg[k] = (c + 1, t + (b - a) / 1e3)
+    tot = sum(t for _, t in agg.values())
+    span = (sel[-1][2] - sel[0][1]) / 1e3
+    out = [f"one solve: {iters} Arnoldi steps, {len(sel)} kernels, kernel time {tot:.0f} us, "
+           f"span {span:.0f} us ({tot / max(iters, 1):.0f} us of kernels per step)", "",
+           "| kernel | launches | total us | us per launch | us per step |", "|---|---|---|---|---|"]
+    for k, (c, t) in sorted(agg.items(), key=lambda kv: -kv[1][1]):
+        out.append(f"| `{k}` | {c} | {t:.1f} | {t / c:.2f} | {t / max(iters, 1):.1f} |")
+    return "\n".join(out)
+
+
+def _counter_per_kernel(db, counter):
+    """Mean value of a hardware counter per dispatch, by kernel name, from a
+    rocprofv3 database (rocpd schema)."""
+    import sqlite3
+    c = sqlite3.connect(db)
+    rows = c.execute("select kernel_name, counter_name, value from counters_collection").fetchall()
+    acc = {}
+    for name, cn, v in rows:
+        if cn != counter:
+            continue
+        acc.setdefault(name, []).append(float(v))
+    return {k: (sum(v) / len(v), len(v)) for k, v in acc.items()}
+
+
+def record_traffic(fetch_db, write_db, cells, nv):
+    """Per-launch HBM bytes of the three learned layers from a FETCH_SIZE and a
+    WRITE_SIZE pass over `bench.py --probe`, each scaled by what the same
+    counter reads for the 256 MiB device copy of the probe (262144 KiB read
+    and written); written to profiles/learned_layer_traffic.json."""
+    fetch = _counter_per_kernel(fetch_db, "FETCH_SIZE")
+    write = _counter_per_kernel(write_db, "WRITE_SIZE")
+    copy = [k for k in fetch if "copyBuffer" in k or "elementwise_kernel" in k]
+    assert copy, "no device copy in the counter runs"
+    ck = copy[0]
+    fscale = 262144.0 / fetch[ck][0]
+    wscale = 262144.0 / write[ck][0]
+    kernels = []
+    for layer in (0, 1, 2):
+        tag = {0: "k_lrn_layer_first<", 1: "k_lrn_layer_col<", 2: "k_lrn_layer_col<"}[layer]
+        last = {0: "false", 1: "false", 2: "true"}[layer]
+        names = [k for k in fetch if tag in k.replace(" ", "") and f"<{nv},{'true' if layer == 0 else 'false'},"
+                 f"{last}," in k.replace(" ", "")]
+        assert len(names) == 1, (layer, names)
+        kn = names[0]
+        fb = fetch[kn][0] * 1024 * fscale
+        wb = write[kn][0] * 1024 * wscale
+        kernels.append(dict(layer=layer, kernel=kn.split("(")[0], cells=cells, nv=nv,
+                            source_sha256=layer_source_hash(), fetch_bytes=int(fb), write_bytes=int(wb),
+                            bytes_per_launch=int(fb + wb), launches_fetch=fetch[kn][1],
+                            launches_write=write[kn][1],
+                            method_bytes=cells * layer_method_bytes(layer, nv)))
+    rec = dict(fetch_scale=round(fscale, 4), write_scale=round(wscale, 4), copy_kernel=ck.split("(")[0],
+               commands=["rocprofv3 --pmc FETCH_SIZE -d <dir> -o probe -- python3 -u bench.py --probe",
+                         "rocprofv3 --pmc WRITE_SIZE -d <dir> -o probe -- python3 -u bench.py --probe"],
+               kernels=kernels)
+    with open(TRAFFIC_FILE, "w") as f:
+        json.dump(rec, f, indent=1)
+    return rec
 
 
 def main():
@@ -258,13 +400,25 @@ def main():
     ap.add_argument("--train-systems", type=int, default=8)
     ap.add_argument("--train-pairs", type=int, default=48)
     ap.add_argument("--train-batch", type=int, default=8)
-    ap.add_argument("--first", default="cptr", choices=["cptr", "cptr_lower", "cpr", "cptr_bd", "cptr_uamg"],
+    ap.add_argument("--first", default="cptr",
+                    choices=["cptr", "cptr_lower", "cptr_upper", "cpr", "cptr_bd", "cptr_uamg"],
                     help="first stage of the learned and BILU(0)-FP32 legs (plain FP64 CPTR stays cptr)")
-    ap.add_argument("--cpu-iters", type=int, default=10)
+    ap.add_argument("--parts", default="16x16x1",
+                    help="block-Jacobi grid parts of the partitioned BILU(0) legs (px x py x pz)")
+    ap.add_argument("--cpu-iters", type=int, default=0,
+                    help="cap of the oracle's inner iterations in the CPU baseline (0: to the tolerance)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the FP64 and BILU(0) legs")
-    ap.add_argument("--no-held-out", action="store_true", help="skip the held-out seed evaluation")
+    ap.add_argument("--no-large", action="store_true", help="skip the three-phase 128x128x64 block")
+    ap.add_argument("--context", action="store_true",
+                    help="also the context legs (CPR, CPTR-BD, CPTR-uAMG, decoupling, BILU(1))")
+    ap.add_argument("--held-out", action="store_true", help="evaluate the held-out seeds 200-204")
     ap.add_argument("--probe", action="store_true")
+    ap.add_argument("--trace", action="store_true",
+                    help="only two learned+FP32 solves of the workload (untrained network), for a kernel trace")
+    ap.add_argument("--trace-summary", metavar="KERNEL_TRACE_CSV",
+                    help="per-kernel time of the last solve in a rocprofv3 kernel trace of --trace")
+    ap.add_argument("--traffic", nargs=2, metavar=("FETCH_DB", "WRITE_DB"))
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (the solver is a single-GPU library); "
@@ -272,6 +426,20 @@ def main():
         sys.exit(2)
     if args.probe:
         probe(args.config)
+        return
+    if args.trace:
+        trace_solves(args.config)
+        return
+    if args.trace_summary:
+        print(trace_summary(args.trace_summary))
+        return
+    parts = tuple(int(q) for q in args.parts.split("x"))
+    if args.traffic:
+        from paper_1907_04229_amd.synth.problem import CONFIGS
+        shape = CONFIGS[args.config]["shape"]
+        nv = 4 if CONFIGS[args.config]["three_phase"] else 3
+        print(json.dumps(record_traffic(args.traffic[0], args.traffic[1], shape[0] * shape[1] * shape[2], nv),
+                         indent=1))
         return
 
     import torch
@@ -288,14 +456,14 @@ def main():
         f"{time.perf_counter() - t0:.1f} s")
     b = torch.as_tensor(pr.b, device="cuda")
 
-    def run(solver, steps, warmup, tag, measured=False):
+    def run(solver, steps, warmup, tag, rhs, measured=False):
         for _ in range(warmup):
-            solver.solve(b, restart=restart, rtol=1e-6)
+            solver.solve(rhs, restart=restart, rtol=1e-6)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         infos = []
         for _ in range(steps):
-            x, info = solver.solve(b, restart=restart, rtol=1e-6)
+            x, info = solver.solve(rhs, restart=restart, rtol=1e-6)
             infos.append(info)
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / steps
@@ -308,15 +476,15 @@ def main():
             assert info["converged"] and info["relres_true"] <= 1e-6, f"{tag} did not converge"
         return dt, info, x
 
-    def setup(**opt):
+    def setup(prob, **opt):
         t0 = time.perf_counter()
-        s = cptr.Solver(pr, **opt)
+        s = cptr.Solver(prob, **opt)
         torch.cuda.synchronize()
         return s, time.perf_counter() - t0
 
-    def leg(dt, info, setup_s):
+    def leg(dt, info, setup_s, n):
         return dict(time_to_tol_s=round(dt, 5), iters=info["iters"],
-                    cell_iters_per_s=round(pr.n * info["iters"] / dt, 1), setup_s=round(setup_s, 3),
+                    cell_iters_per_s=round(n * info["iters"] / dt, 1), setup_s=round(setup_s, 3),
                     relres_true=info["relres_true"],
                     converged=bool(info["converged"] and info["relres_true"] <= 1e-6),
                     fell_back=info["fell_back"])
@@ -326,78 +494,115 @@ def main():
                                     lr_final=args.train_lr_final, rollback=args.train_rollback or None)
 
     # the measured configuration: learned second stage, FP32 preconditioner
-    sl, setup_l = setup(precision="fp32", second_stage="learned", first_stage=args.first)
+    sl, setup_l = setup(pr, precision="fp32", second_stage="learned", first_stage=args.first)
     model.attach(sl)
-    dt, info, x_l = run(sl, args.steps, args.warmup, "learned+fp32", measured=True)
-    roof = layer_roofline(sl)
-    log(f"layer roofline: {roof}")
+    dt, info, x_l = run(sl, args.steps, args.warmup, "learned+fp32", b, measured=True)
+    layers = layer_timings(sl)
+    for r in layers:
+        log(f"layer {r['layer']}: {r['avg_us']} us, {r['achieved']} GB/s ({r['frac']:.2f} of peak)")
 
     compare = {}
     x64 = None
+    spmv = None
     if not args.no_compare:
-        s64, su = setup(precision="fp64", second_stage="bilu0")
-        d64, i64, x64 = run(s64, 1, 1, "plain fp64 (bilu0 natural)")
-        compare["fp64_cptr_bilu0"] = leg(d64, i64, su)
+        s64, su = setup(pr, precision="fp64", second_stage="bilu0")
+        d64, i64, x64 = run(s64, 1, 1, "plain fp64 (bilu0 natural)", b)
+        compare["fp64_cptr_bilu0"] = leg(d64, i64, su, pr.n)
         spmv = spmv_roofline(pr, s64)
         s64.close()
-        smc, su = setup(precision="fp32", second_stage="bilu0_mc", first_stage=args.first)
-        dmc, imc, _ = run(smc, 2, 1, "fp32 bilu0 multicolour")
-        compare["fp32_cptr_bilu0_mc"] = leg(dmc, imc, su)
-        smc.close()
-        sn, su = setup(precision="fp32", second_stage="learned", first_stage=args.first)
-        mn = cptr.LearnModel(pr.nv, neumann_params(pr.nv, seed=1))
-        mn.attach(sn)
-        dn, inn, _ = run(sn, 1, 1, "fp32 learned, untrained (Neumann init)")
-        compare["fp32_cptr_learned_untrained"] = leg(dn, inn, su)
-        sn.close()
-        mn.close()
-        # context: the same stages behind the CPR first stage (one A_pp V-cycle)
-        # (also with the True-IMPES decoupling operator, Section 3.1), behind
-        # the block-diagonal CPTR-BD(AMG) first stage (V-cycles on A_pp and
-        # A_TT, Section 4.4), behind CPTR-uAMG (one V-cycle of the unknown-based
-        # hierarchy of A_00, Section 3.4; also with True-IMPES extended to the
-        # pressure-temperature system, Section 3.2), and CPTR with the BILU(1)
-        # second stage
-        for tag, first, opt, mdl_needed in (
-                ("fp64_cpr_bilu0", "cpr", dict(precision="fp64", second_stage="bilu0"), False),
-                ("fp32_cpr_bilu0_mc", "cpr", dict(precision="fp32", second_stage="bilu0_mc"), False),
-                ("fp32_cpr_learned_untrained", "cpr", dict(precision="fp32", second_stage="learned"), True),
-                ("fp64_cptr_bd_bilu0", "cptr_bd", dict(precision="fp64", second_stage="bilu0"), False),
-                ("fp32_cptr_bd_bilu0_mc", "cptr_bd", dict(precision="fp32", second_stage="bilu0_mc"), False),
-                ("fp64_cptr_uamg_bilu0", "cptr_uamg", dict(precision="fp64", second_stage="bilu0"), False),
-                ("fp32_cptr_uamg_bilu0_mc", "cptr_uamg", dict(precision="fp32", second_stage="bilu0_mc"), False),
-                ("fp64_cptr_uamg_ti_bilu0", "cptr_uamg", dict(precision="fp64", second_stage="bilu0",
-                                                              decoupling="ti"), False),
-                ("fp32_cptr_uamg_ti_bilu0_mc", "cptr_uamg", dict(precision="fp32", second_stage="bilu0_mc",
-                                                                 decoupling="ti"), False),
-                ("fp64_cpr_ti_bilu0", "cpr", dict(precision="fp64", second_stage="bilu0", decoupling="ti"),
+        for tag, opt, mdl in (
+                ("fp32_cptr_bilu0_mc", dict(precision="fp32", second_stage="bilu0_mc", first_stage=args.first),
                  False),
-                ("fp32_cpr_ti_bilu0_mc", "cpr", dict(precision="fp32", second_stage="bilu0_mc", decoupling="ti"),
-                 False),
-                ("fp64_cptr_bilu1", args.first, dict(precision="fp64", second_stage="bilu0", ilu_level=1), False),
-                ("fp32_cptr_bilu1_mc", args.first, dict(precision="fp32", second_stage="bilu0_mc", ilu_level=1),
-                 False)):
-            sc, su = setup(first_stage=first, **opt)
+                ("fp32_cptr_learned_untrained", dict(precision="fp32", second_stage="learned",
+                                                     first_stage=args.first), True),
+                ("fp32_cptr_bilu0_parts", dict(precision="fp32", second_stage="bilu0", first_stage=args.first,
+                                               ilu_parts=parts, resid_fp64=1, ilu_accum_fp64=1), False),
+                ("fp64_cptr_bilu0_parts", dict(precision="fp64", second_stage="bilu0", ilu_parts=parts), False)):
+            sc, su = setup(pr, **opt)
             mc_ = None
-            if mdl_needed:
+            if mdl:
                 mc_ = cptr.LearnModel(pr.nv, neumann_params(pr.nv, seed=1))
                 mc_.attach(sc)
-            dc, ic, _ = run(sc, 1, 1, tag)
-            compare[tag] = leg(dc, ic, su)
+            dc, ic, _ = run(sc, 1, 1, tag, b)
+            compare[tag] = leg(dc, ic, su, pr.n)
             sc.close()
             if mc_ is not None:
                 mc_.close()
+        if args.context:
+            # the same stages behind the CPR first stage (one A_pp V-cycle, also
+            # with the True-IMPES decoupling operator, Section 3.1), behind the
+            # block-diagonal CPTR-BD(AMG) first stage (Section 4.4), the block
+            # triangular variants of eq:Aschur, CPTR-uAMG (Section 3.4; also with
+            # True-IMPES on the pressure-temperature system, Section 3.2), and
+            # CPTR with the BILU(1) second stage
+            for tag, first, opt in (
+                    ("fp64_cpr_bilu0", "cpr", dict(precision="fp64", second_stage="bilu0")),
+                    ("fp32_cpr_bilu0_mc", "cpr", dict(precision="fp32", second_stage="bilu0_mc")),
+                    ("fp64_cptr_lower_bilu0", "cptr_lower", dict(precision="fp64", second_stage="bilu0")),
+                    ("fp64_cptr_upper_bilu0", "cptr_upper", dict(precision="fp64", second_stage="bilu0")),
+                    ("fp64_cptr_bd_bilu0", "cptr_bd", dict(precision="fp64", second_stage="bilu0")),
+                    ("fp32_cptr_bd_bilu0_mc", "cptr_bd", dict(precision="fp32", second_stage="bilu0_mc")),
+                    ("fp64_cptr_uamg_bilu0", "cptr_uamg", dict(precision="fp64", second_stage="bilu0")),
+                    ("fp32_cptr_uamg_bilu0_mc", "cptr_uamg", dict(precision="fp32", second_stage="bilu0_mc")),
+                    ("fp64_cptr_uamg_ti_bilu0", "cptr_uamg", dict(precision="fp64", second_stage="bilu0",
+                                                                  decoupling="ti")),
+                    ("fp64_cpr_ti_bilu0", "cpr", dict(precision="fp64", second_stage="bilu0", decoupling="ti")),
+                    ("fp64_cptr_bilu1", args.first, dict(precision="fp64", second_stage="bilu0", ilu_level=1)),
+                    ("fp32_cptr_bilu1_mc", args.first, dict(precision="fp32", second_stage="bilu0_mc",
+                                                            ilu_level=1))):
+                sc, su = setup(pr, first_stage=first, **opt)
+                dc, ic, _ = run(sc, 1, 1, tag, b)
+                compare[tag] = leg(dc, ic, su, pr.n)
+                sc.close()
         compare["speedup_vs_fp64"] = round(d64 / dt, 3)
         compare["solution_rel_diff_vs_fp64"] = float(torch.linalg.vector_norm(x_l - x64) /
                                                      torch.linalg.vector_norm(x64))
         compare["spmv_fp64"] = spmv
+
+    large = None
+    if not args.no_large:
+        # the three-phase 1M-cell case: plain FP64 CPTR against FP32 CPTR
+        t0 = time.perf_counter()
+        pl = make_problem(config="large")
+        log(f"generated large {CONFIGS['large']['shape']} nv={pl.nv} in {time.perf_counter() - t0:.1f} s")
+        bl = torch.as_tensor(pl.b, device="cuda")
+        large = {"workload": f"large: {'x'.join(map(str, CONFIGS['large']['shape']))} cells, three-phase, "
+                             f"nv={pl.nv}, FGMRES({CONFIGS['large']['restart']}) rtol 1e-6", "cells": pl.n}
+        # the FP32 legs form b1 and the rows of the ILU solves with FP64 sums
+        # (FP32 sums: 81 iterations whole, 59 with b1 in FP64)
+        for tag, opt, reps in (
+                ("fp64_cptr_bilu0", dict(precision="fp64", second_stage="bilu0"), 1),
+                ("fp32_cptr_bilu0_parts", dict(precision="fp32", second_stage="bilu0", ilu_parts=parts,
+                                               resid_fp64=1, ilu_accum_fp64=1), 3),
+                ("fp64_cptr_bilu0_parts", dict(precision="fp64", second_stage="bilu0", ilu_parts=parts), 1),
+                ("fp32_cptr_bilu0", dict(precision="fp32", second_stage="bilu0", resid_fp64=1, ilu_accum_fp64=1), 1)):
+            sc, su = setup(pl, **opt)
+            dc, ic, _ = run(sc, reps, 1, f"large {tag}", bl)
+            large[tag] = leg(dc, ic, su, pl.n)
+            sc.close()
+        large["speedup_fp32_parts_vs_fp64"] = round(large["fp64_cptr_bilu0"]["time_to_tol_s"] /
+                                                    large["fp32_cptr_bilu0_parts"]["time_to_tol_s"], 3)
+        large["parts"] = "x".join(map(str, parts))
+        del pl, bl
+
     held = None
-    if not args.no_held_out:
+    if args.held_out:
         held = held_out_eval(cfg, model, restart, args.first, log)
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(pr, args.cpu_iters)
+        cpu = cpu_baseline(pr, args.cpu_iters or None)
         log(f"cpu baseline: {cpu}")
+    # the roofline of the dominant kernel of the timed solve: each learned
+    # layer and the FP64 Krylov product run once per FGMRES iteration
+    cands = list(layers)
+    if spmv is not None:
+        cands.append(dict(spmv, layer=None))
+    dom = max(cands, key=lambda r: r["avg_us"])
+    roof = dict(bound="hbm", achieved=dom["achieved"], peak=HBM_PEAK_GBS, unit="GB/s", frac=dom["frac"],
+                traffic=dom.get("traffic"), kernel=dom["kernel"], bytes_per_launch=dom["bytes_per_launch"],
+                avg_us=dom["avg_us"], launches=dom.get("launches", 50),
+                others=[{k: r[k] for k in ("kernel", "avg_us", "achieved", "frac", "bytes_per_launch")}
+                        for r in cands if r is not dom])
     out = {
         "metric": "FGMRES time-to-1e-6 (s) & cell-iters/s: learned/FP32 vs FP64 CPTR; HBM GB/s",
         "value": round(dt, 5),
@@ -423,6 +628,7 @@ def main():
         "setup_s": round(setup_l, 3),
         "training": train_info,
         "compare": compare,
+        "large": large,
         "held_out": held,
         "roofline": roof,
         "cpu_baseline": cpu,

@@ -176,6 +176,19 @@ typedef struct {
                             residual did not halve; 0 never (a non-finite step is then
                             CPTR_ERR_NONFINITE) (1) */
   int amg_smoother;      /* CPTR_SMOOTHER_* of every AMG hierarchy (L1JACOBI) */
+  int ilu_part_x, ilu_part_y, ilu_part_z;
+                         /* block-Jacobi parts of the BILU second stages (1, 1, 1: none):
+                            when A is the 7-point graph of an nx x ny x nz grid numbered x
+                            fastest, cell (x, y, z) belongs to part (x px / nx, y py / ny,
+                            z pz / nz) and the blocks coupling different parts are left out
+                            of the factor -- the block-Jacobi ILU of the paper's parallel
+                            runs (Section 4), here to shorten the chains of dependent steps
+                            of the triangular solves (natural order: nx + ny + nz - 2 levels
+                            become about nx/px + ny/py + nz/pz).  Other patterns with parts
+                            give CPTR_ERR_UNSUPPORTED.  The learned stage's fallback keeps the
+                            whole natural-order BILU(0) */
+  int ilu_accum_fp64;    /* FP32 mode: the BILU triangular solves sum each row in FP64 (the
+                            factors and vectors stay FP32 in memory; 0: FP32 sums) (0) */
 } cptr_options;
 
 typedef struct {

@@ -32,7 +32,8 @@ class Options(C.Structure):
                 ("use_graph", C.c_int), ("resid_fp64", C.c_int),
                 ("scalar_dia", C.c_int), ("lrn_columns", C.c_int), ("decoupling", C.c_int),
                 ("ilu_level", C.c_int), ("schur", C.c_int), ("lrn_fallback", C.c_int),
-                ("amg_smoother", C.c_int)]
+                ("amg_smoother", C.c_int), ("ilu_part_x", C.c_int), ("ilu_part_y", C.c_int),
+                ("ilu_part_z", C.c_int), ("ilu_accum_fp64", C.c_int)]
 
 
 class Bsr(C.Structure):
@@ -155,6 +156,9 @@ def cptr_default_options(**kw):
             v = SCHUR[v]
         if k == "amg_smoother" and isinstance(v, str):
             v = SMOOTHER[v]
+        if k == "ilu_parts":  # (px, py, pz)
+            o.ilu_part_x, o.ilu_part_y, o.ilu_part_z = (int(q) for q in v)
+            continue
         setattr(o, k, v)
     return o
 

@@ -701,17 +701,20 @@ struct LearnedDev {
     upload(nbr, nb);
     upload(nmask, mk);
     upload(E, eb);
-    // the forward layers read the edge blocks in tile order: for tile t,
-    // direction d and lane group g, the 16 cells' four entries 4g .. 4g + 3
-    // are 128 contiguous bytes (one load instruction of a wave reads 512)
+    // the forward layers read the edge blocks in tile order (load_edge_tiled):
+    // for tile t and direction d one run of the 16 cells' entries, groups of
+    // four entries 4g .. 4g + 3 of the 16 cells (128 contiguous bytes; for
+    // nv = 3 the last group holds entry 8 and three zeros)
     {
       const int nt = (n + 15) / 16;
-      std::vector<short> et((size_t)nt * 16 * kDir * kEdge, 0);
+      const int run = nv == 3 ? kEdgeRun<3> : kEdgeRun<4>;
+      std::vector<short> et((size_t)nt * kDir * run, 0);
       for (int i = 0; i < n; i++)
-        for (int d = 0; d < kDir; d++)
-          for (int e = 0; e < kEdge; e++)
-            et[(((size_t)(i / 16) * kDir + d) * 4 + e / 4) * 64 + (i % 16) * 4 + e % 4] =
-                eb[((size_t)i * kDir + d) * kEdge + e];
+        for (int d = 0; d < kDir; d++) {
+          short *r0 = et.data() + ((size_t)(i / 16) * kDir + d) * run;
+          for (int e = 0; e < nv * nv; e++)
+            r0[(e / 4) * 64 + (i % 16) * 4 + e % 4] = eb[((size_t)i * kDir + d) * kEdge + e];
+        }
       upload(Et, et);
     }
     upload(dinv, df);
@@ -844,10 +847,10 @@ struct LearnedDev {
     LAUNCH_CHECK();
   }
   // algorithmic HBM bytes of one inference launch of layer 1 (BF16 activations
-  // in and out, the six BF16 edge blocks; the presence mask unless the
+  // in and out, the six BF16 nv x nv edge blocks; the presence mask unless the
   // z-column kernel runs, which reads none)
   double layer_bytes() const {
-    return (double)n * (2.0 * kHid * 2 + kDir * kEdge * 2 + (use_col && colP > 0 ? 0 : 1));
+    return (double)n * (2.0 * kHid * 2 + kDir * nv * nv * 2 + (use_col && colP > 0 ? 0 : 1));
   }
 };
 
@@ -988,11 +991,20 @@ struct Precond : PrecondBase {
       LAUNCH_CHECK();
       return;
     }
-    // BILU(0): forward sweep level by level (levels without L blocks are no-ops)
+    if (op.o.ilu_accum_fp64 && sizeof(T) == 4) ilu_solve<NV, ZT, double>(st, slots);
+    else ilu_solve<NV, ZT, T>(st, slots);
+  }
+
+  // the BILU second stage on b1 (sums of a row accumulated in A): forward
+  // sweep level by level (levels without L blocks are no-ops), then the
+  // backward sweep, which also writes z = w + x1
+  template <int NV, typename ZT, typename A>
+  void ilu_solve(hipStream_t st, const ApplySlots *slots) {
+    T *b1p = devp<T>(b1);
     for (size_t l = 0; l + 1 < ilu.f_lev_ptr.size(); l++) {
       if (!ilu.f_nonempty[l]) continue;
       int p0 = ilu.f_lev_ptr[l], cnt = ilu.f_lev_ptr[l + 1] - p0;
-      hipLaunchKernelGGL((k_ilu_fwd<NV, T>), dim3(nblk((size_t)cnt * NV)), dim3(kBlock), 0, st, p0, cnt,
+      hipLaunchKernelGGL((k_ilu_fwd<NV, T, A>), dim3(nblk((size_t)cnt * NV)), dim3(kBlock), 0, st, p0, cnt,
                          devp<int>(ilu.f_rows), devp<int>(ilu.f_ptr), devp<int>(ilu.f_col),
                          devp<T>(ilu.f_val), b1p);
       LAUNCH_CHECK();
@@ -1000,7 +1012,7 @@ struct Precond : PrecondBase {
     constexpr int rows_per_block = kBlock / NV;
     for (size_t l = 0; l + 1 < ilu.b_lev_ptr.size(); l++) {
       int p0 = ilu.b_lev_ptr[l], cnt = ilu.b_lev_ptr[l + 1] - p0;
-      hipLaunchKernelGGL((k_ilu_bwd<NV, T, ZT>), dim3(nblk(cnt, rows_per_block)), dim3(kBlock), 0, st,
+      hipLaunchKernelGGL((k_ilu_bwd<NV, T, ZT, A>), dim3(nblk(cnt, rows_per_block)), dim3(kBlock), 0, st,
                          p0, cnt, devp<int>(ilu.b_rows), devp<int>(ilu.b_ptr), devp<int>(ilu.b_col),
                          devp<T>(ilu.b_val), devp<T>(ilu.dinv), b1p, op.o.ip, op.o.iT, x1p(), x1T(),
                          slots);
@@ -1065,10 +1077,11 @@ struct cptr_handle {
   std::vector<int> st_rp, st_ci;          // pattern of S~_T (numeric re-setup)
   hipStream_t stream = nullptr;       // internal stream (default priority)
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  hipEvent_t ev_step[2] = {nullptr, nullptr};  // per-step results of FGMRES copied to the host
   cptr_stats stats{};
   // FGMRES workspace
   int m_alloc = 0;
-  cptr::DevMem V, Z, w, r, part, h1, h2, R, cs, sn, g, y, kstate, scal;
+  cptr::DevMem kws;  // Krylov workspace (Kws) for restarts up to m_alloc
   double *pinned = nullptr;
   hipGraphExec_t graph_exec = nullptr;
   hipGraph_t graph = nullptr;
@@ -1278,10 +1291,14 @@ static void build_precond(cptr_handle *h, const std::vector<int> &rp, const std:
       P.ilu = std::move(*keep_ilu);
       P.ilu.refactor(h->vals, 0);
     } else {
-      IluHost ih;  // with the learned stage: the natural-order factor of the fallback (plain ILU(0))
-      // the learned stage's fallback is the plain natural-order BILU(0)
+      IluHost ih;
+      // the learned stage's fallback is the plain natural-order BILU(0), whole
+      const bool lrn = o.second_stage == CPTR_SECOND_LEARNED;
+      std::vector<int> part;
+      if (!lrn && (o.ilu_part_x > 1 || o.ilu_part_y > 1 || o.ilu_part_z > 1))
+        part = grid_parts(n, rp.data(), ci.data(), o.ilu_part_x, o.ilu_part_y, o.ilu_part_z);
       ilu_build(n, nv, rp.data(), ci.data(), vals.data(), o.second_stage == CPTR_SECOND_BILU0_MC, ih,
-                o.second_stage == CPTR_SECOND_LEARNED ? 0 : o.ilu_level);
+                lrn ? 0 : o.ilu_level, part.empty() ? nullptr : part.data());
       P.ilu.build(ih);
       h->stats.ilu_levels_lower = int(ih.f_lev_ptr.size()) - 1;
       h->stats.ilu_levels_upper = int(ih.b_lev_ptr.size()) - 1;
@@ -1373,6 +1390,8 @@ static void validate_and_fetch(const cptr_bsr *A, const cptr_csr *S, const cptr_
   if (o.first_stage < 0 || o.first_stage > 6) throw Error{CPTR_ERR_INVALID_ARG, "invalid first stage"};
   if (o.decoupling < 0 || o.decoupling > 2) throw Error{CPTR_ERR_INVALID_ARG, "invalid decoupling"};
   if (o.ilu_level != 0 && o.ilu_level != 1) throw Error{CPTR_ERR_UNSUPPORTED, "ilu_level must be 0 or 1"};
+  if (o.ilu_part_x < 1 || o.ilu_part_y < 1 || o.ilu_part_z < 1)
+    throw Error{CPTR_ERR_INVALID_ARG, "ILU parts per axis must be at least 1"};
   if (o.schur < CPTR_SCHUR_ASSEMBLED || o.schur > CPTR_SCHUR_DIAG) throw Error{CPTR_ERR_INVALID_ARG, "invalid schur"};
   if (o.amg_smoother != CPTR_SMOOTHER_L1JACOBI && o.amg_smoother != CPTR_SMOOTHER_GS)
     throw Error{CPTR_ERR_INVALID_ARG, "invalid amg_smoother"};
@@ -1474,24 +1493,75 @@ static void spmv_slot(cptr_handle *h, hipStream_t st, const ApplySlots *sl, doub
   else launch_spmv<4, ZT>(h, st, nullptr, sl, nullptr, y);
 }
 
+// Krylov workspace of one solve, carved from one allocation of the handle's
+// (made on first use and kept)
+struct Kws {
+  double *V = nullptr;  // (m+1) x N basis
+  void *Z = nullptr;    // m x N preconditioned vectors (FP32 or FP64)
+  double *w = nullptr, *r = nullptr, *part = nullptr, *h1 = nullptr, *h2 = nullptr, *R = nullptr, *cs = nullptr,
+         *sn = nullptr, *g = nullptr, *y = nullptr, *scal = nullptr;
+  KState *ks = nullptr;
+  double *host = nullptr;  // 4 doubles of host memory the per-step results are copied to
+  bool graphs = false;     // the Arnoldi step may be replayed from the handle's captured graph
+};
+
+// bytes of each piece of the workspace for restart m and N unknowns, in the
+// order they are laid out; each piece starts on a 256-byte boundary
+static size_t kws_layout(size_t N, int m, size_t zb, size_t *sizes) {
+  const size_t s[] = {(m + 1) * N * 8,         // V
+                      m * N * zb,              // Z
+                      N * 8,                   // w
+                      N * 8,                   // r
+                      (size_t)kDotBlocks * (kMaxRestart + 1) * 8,  // part: rows of partial sums
+                      72 * 8,                  // h1
+                      72 * 8,                  // h2
+                      (size_t)(m + 1) * m * 8,  // R
+                      (size_t)m * 8,           // cs
+                      (size_t)m * 8,           // sn
+                      (size_t)(m + 1) * 8,     // g
+                      (size_t)m * 8,           // y
+                      8 * 8,                   // scal
+                      sizeof(KState)};         // ks
+  size_t total = 0;
+  for (int i = 0; i < 14; i++) {
+    if (sizes) sizes[i] = s[i];
+    total += (s[i] + 255) / 256 * 256;
+  }
+  return total;
+}
+
+static Kws kws_carve(char *base, size_t N, int m, size_t zb) {
+  size_t sz[14];
+  kws_layout(N, m, zb, sz);
+  char *p[14];
+  size_t off = 0;
+  for (int i = 0; i < 14; i++) {
+    p[i] = base + off;
+    off += (sz[i] + 255) / 256 * 256;
+  }
+  Kws k;
+  k.V = (double *)p[0];
+  k.Z = p[1];
+  k.w = (double *)p[2];
+  k.r = (double *)p[3];
+  k.part = (double *)p[4];
+  k.h1 = (double *)p[5];
+  k.h2 = (double *)p[6];
+  k.R = (double *)p[7];
+  k.cs = (double *)p[8];
+  k.sn = (double *)p[9];
+  k.g = (double *)p[10];
+  k.y = (double *)p[11];
+  k.scal = (double *)p[12];
+  k.ks = (KState *)p[13];
+  return k;
+}
+
 static void ensure_krylov(cptr_handle *h, int m) {
   if (h->m_alloc >= m) return;
   const size_t N = (size_t)h->op.n * h->op.nv;
   const size_t zb = h->op.o.precision == CPTR_FP32 ? 4 : 8;
-  h->V.alloc((m + 1) * N * 8);
-  h->Z.alloc(m * N * zb);
-  h->w.alloc(N * 8);
-  h->r.alloc(N * 8);
-  h->part.alloc((size_t)kDotBlocks * 64 * 8);
-  h->h1.alloc(72 * 8);
-  h->h2.alloc(72 * 8);
-  h->R.alloc((size_t)(m + 1) * m * 8);
-  h->cs.alloc(m * 8);
-  h->sn.alloc(m * 8);
-  h->g.alloc((m + 1) * 8);
-  h->y.alloc(m * 8);
-  h->kstate.alloc(sizeof(KState));
-  h->scal.alloc(8 * 8);
+  h->kws.alloc(kws_layout(N, m, zb, nullptr));
   if (!h->pinned) CPTR_HIP_TRY(hipHostMalloc((void **)&h->pinned, 8 * sizeof(double), hipHostMallocDefault));
   h->m_alloc = m;
   if (h->graph_exec) {
@@ -1503,53 +1573,57 @@ static void ensure_krylov(cptr_handle *h, int m) {
   }
 }
 
+// the handle's workspace (ensure_krylov(h, m) first)
+static Kws kws_of(cptr_handle *h) {
+  const size_t N = (size_t)h->op.n * h->op.nv;
+  const size_t zb = h->op.o.precision == CPTR_FP32 ? 4 : 8;
+  Kws k = kws_carve((char *)h->kws.p, N, h->m_alloc, zb);
+  k.host = h->pinned;
+  k.graphs = true;
+  return k;
+}
+
 // ||x||_2 into scal[slot] (device)
-static void norm2(cptr_handle *h, hipStream_t st, const double *x, size_t N, int slot) {
+static void norm2(const Kws &k, hipStream_t st, const double *x, size_t N, int slot) {
   const int g = sgrid(N);
-  hipLaunchKernelGGL(k_norm2_partial, dim3(g), dim3(kBlock), 0, st, x, N, devp<double>(h->part));
-  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlock), 0, st, (const double *)devp<double>(h->part), g,
-                     (const int *)nullptr, 1, devp<double>(h->scal) + slot, 1);
+  hipLaunchKernelGGL(k_norm2_partial, dim3(g), dim3(kBlock), 0, st, x, N, k.part);
+  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlock), 0, st, (const double *)k.part, g, (const int *)nullptr, 1,
+                     k.scal + slot, 1);
   LAUNCH_CHECK();
 }
 
-static double fetch(cptr_handle *h, hipStream_t st, const double *dev) {
-  CPTR_HIP_TRY(hipMemcpyAsync(h->pinned, dev, sizeof(double), hipMemcpyDeviceToHost, st));
+static double fetch(const Kws &k, hipStream_t st, const double *dev) {
+  CPTR_HIP_TRY(hipMemcpyAsync(k.host, dev, sizeof(double), hipMemcpyDeviceToHost, st));
   CPTR_HIP_TRY(hipStreamSynchronize(st));
-  return h->pinned[0];
+  return k.host[0];
 }
 
 // one Arnoldi step for column j (read from the device state)
 template <typename ZT, int MAXK>
-static void arnoldi_step(cptr_handle *h, hipStream_t st) {
+static void arnoldi_step(cptr_handle *h, const Kws &k, hipStream_t st) {
   const size_t N = (size_t)h->op.n * h->op.nv;
-  KState *ks = devp<KState>(h->kstate);
+  KState *ks = k.ks;
   ApplySlots *sl = devp<ApplySlots>(h->slots);
   const int g = sgrid(N);
-  double *part = devp<double>(h->part);
-  hipLaunchKernelGGL(k_set_slots_krylov, dim3(1), dim3(64), 0, st, sl, (const double *)devp<double>(h->V),
-                     h->Z.p, N, (int)sizeof(ZT), (const KState *)ks);
+  hipLaunchKernelGGL(k_set_slots_krylov, dim3(1), dim3(64), 0, st, sl, (const double *)k.V, k.Z, N, (int)sizeof(ZT),
+                     (const KState *)ks);
   LAUNCH_CHECK();
   h->pc->apply(st, sl, sizeof(ZT) == 8);
   // w = A z_j (the column address is read from the slots)
-  spmv_slot<ZT>(h, st, sl, devp<double>(h->w));
+  spmv_slot<ZT>(h, st, sl, k.w);
   const int *jd = &ks->j;
-  hipLaunchKernelGGL((k_mdot<MAXK>), dim3(g), dim3(kBlock), 0, st, (const double *)devp<double>(h->V), N, jd,
-                     (const double *)devp<double>(h->w), part);
-  hipLaunchKernelGGL(k_reduce, dim3(MAXK), dim3(kBlock), 0, st, (const double *)part, g, jd, 0,
-                     devp<double>(h->h1), 0);
-  hipLaunchKernelGGL((k_cgs_update_mdot<MAXK>), dim3(g), dim3(kBlock), 0, st, (const double *)devp<double>(h->V),
-                     N, jd, (const double *)devp<double>(h->h1), devp<double>(h->w), part);
-  hipLaunchKernelGGL(k_reduce, dim3(MAXK), dim3(kBlock), 0, st, (const double *)part, g, jd, 0,
-                     devp<double>(h->h2), 0);
-  hipLaunchKernelGGL((k_cgs_update_norm<MAXK>), dim3(g), dim3(kBlock), 0, st, (const double *)devp<double>(h->V),
-                     N, jd, (const double *)devp<double>(h->h2), devp<double>(h->w), part);
-  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlock), 0, st, (const double *)part, g, (const int *)nullptr,
-                     1, &ks->hn, 1);
-  hipLaunchKernelGGL(k_scale_next, dim3(g), dim3(kBlock), 0, st, devp<double>(h->V), N, (const KState *)ks,
-                     (const double *)devp<double>(h->w));
-  hipLaunchKernelGGL(k_givens, dim3(1), dim3(64), 0, st, ks, (const double *)devp<double>(h->h1),
-                     (const double *)devp<double>(h->h2), devp<double>(h->R), devp<double>(h->cs),
-                     devp<double>(h->sn), devp<double>(h->g));
+  hipLaunchKernelGGL((k_mdot<MAXK>), dim3(g), dim3(kBlock), 0, st, (const double *)k.V, N, jd, (const double *)k.w,
+                     k.part);
+  hipLaunchKernelGGL(k_reduce, dim3(MAXK), dim3(kBlock), 0, st, (const double *)k.part, g, jd, 0, k.h1, 0);
+  double *w2_part = k.part + (size_t)kMaxRestart * kDotBlocks;  // the row after the longest basis
+  hipLaunchKernelGGL((k_cgs_update_mdot<MAXK>), dim3(g), dim3(kBlock), 0, st, (const double *)k.V, N, jd,
+                     (const double *)k.h1, k.w, k.part, w2_part);
+  hipLaunchKernelGGL(k_reduce, dim3(MAXK), dim3(kBlock), 0, st, (const double *)k.part, g, jd, 0, k.h2, 0);
+  // v_{j+1} = (w - V h2) / ||w - V h2|| (the norm from ||w||^2 - ||h2||^2), ||w - V h2|| into the state
+  hipLaunchKernelGGL((k_cgs_finish<MAXK>), dim3(g), dim3(kBlock), 0, st, k.V, N, ks, (const double *)k.h2,
+                     (const double *)k.w, (const double *)w2_part, g);
+  hipLaunchKernelGGL(k_givens, dim3(1), dim3(64), 0, st, ks, (const double *)k.h1, (const double *)k.h2, k.R, k.cs,
+                     k.sn, k.g);
   LAUNCH_CHECK();
 }
 
@@ -1568,8 +1642,13 @@ static void fall_back(cptr_handle *h, hipStream_t st) {
   h->graph_m = -1;
 }
 
+// Right-preconditioned FGMRES(m) on the workspace k.  The host reads |g_{j+1}|
+// and ||w|| of every step; while the residual estimate is far from the
+// tolerance the next step of the cycle is enqueued before that read, so the
+// GPU does not wait for the host.  A step enqueued after the one that ends the
+// cycle leaves the Krylov state alone (KState::stop) and is not counted.
 template <typename ZT>
-static int fgmres_impl(cptr_handle *h, const double *b, double *x, const cptr_solve_opts &so,
+static int fgmres_impl(cptr_handle *h, const Kws &k, const double *b, double *x, const cptr_solve_opts &so,
                        cptr_solve_info &info, hipStream_t user) {
   auto t0 = std::chrono::steady_clock::now();
   const size_t N = (size_t)h->op.n * h->op.nv;
@@ -1578,11 +1657,10 @@ static int fgmres_impl(cptr_handle *h, const double *b, double *x, const cptr_so
   // order the internal stream after the caller's
   CPTR_HIP_TRY(hipEventRecord(h->ev_in, user));
   CPTR_HIP_TRY(hipStreamWaitEvent(st, h->ev_in, 0));
-  ensure_krylov(h, m);
-  KState *ks = devp<KState>(h->kstate);
-  double *scal = devp<double>(h->scal);
-  norm2(h, st, b, N, 0);
-  const double bnorm = fetch(h, st, scal);
+  KState *ks = k.ks;
+  double *scal = k.scal;
+  norm2(k, st, b, N, 0);
+  const double bnorm = fetch(k, st, scal);
   info = cptr_solve_info{};
   info.fell_back = h->pc->fallback_flag() ? 1 : 0;
   if (!std::isfinite(bnorm)) throw Error{CPTR_ERR_NONFINITE, "non-finite right-hand side"};
@@ -1595,10 +1673,10 @@ static int fgmres_impl(cptr_handle *h, const double *b, double *x, const cptr_so
     CPTR_HIP_TRY(hipStreamSynchronize(st));
     return CPTR_OK;
   }
-  const bool use_graph = h->op.o.use_graph != 0;
+  const bool use_graph = k.graphs && h->op.o.use_graph != 0;
   auto step = [&]() {
-    if (m <= 32) arnoldi_step<ZT, 32>(h, st);
-    else arnoldi_step<ZT, 64>(h, st);
+    if (m <= 32) arnoldi_step<ZT, 32>(h, k, st);
+    else arnoldi_step<ZT, 64>(h, k, st);
   };
   auto capture = [&]() {
     if (!use_graph || h->graph_m == m) return;
@@ -1621,12 +1699,20 @@ static int fgmres_impl(cptr_handle *h, const double *b, double *x, const cptr_so
     CPTR_HIP_TRY(hipGraphInstantiate(&h->graph_exec, h->graph, nullptr, nullptr, 0));
     h->graph_m = m;
   };
+  // enqueue step q of the cycle and the copy of its (||w||, |g_{q+1}|) into
+  // host slot q % 2, marked by event q % 2
+  auto launch = [&](int q) {
+    if (use_graph) CPTR_HIP_TRY(hipGraphLaunch(h->graph_exec, st));
+    else step();
+    CPTR_HIP_TRY(hipMemcpyAsync(k.host + 2 * (q & 1), &ks->hn, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+    CPTR_HIP_TRY(hipEventRecord(h->ev_step[q & 1], st));
+  };
   int iters = 0, cycles = 0, converged = 0;
   double est = 0.0, truer = 0.0;
   for (;;) {
-    spmv<double>(h, st, x, b, devp<double>(h->r));
-    norm2(h, st, devp<double>(h->r), N, 1);
-    const double beta = fetch(h, st, scal + 1);
+    spmv<double>(h, st, x, b, k.r);
+    norm2(k, st, k.r, N, 1);
+    const double beta = fetch(k, st, scal + 1);
     truer = beta / bnorm;
     if (!std::isfinite(beta)) throw Error{CPTR_ERR_NONFINITE, "non-finite residual"};
     if (truer <= so.rtol) {
@@ -1636,22 +1722,25 @@ static int fgmres_impl(cptr_handle *h, const double *b, double *x, const cptr_so
     }
     if (iters >= so.maxit) break;
     capture();
-    hipLaunchKernelGGL(k_cycle_init, dim3(1), dim3(64), 0, st, ks, (const double *)(scal + 1),
-                       devp<double>(h->g), m);
-    hipLaunchKernelGGL(k_first_vector, dim3(sgrid(N)), dim3(kBlock), 0, st, devp<double>(h->V), N,
-                       (const double *)devp<double>(h->r), (const double *)(scal + 1));
+    hipLaunchKernelGGL(k_cycle_init, dim3(1), dim3(64), 0, st, ks, (const double *)(scal + 1), k.g, m,
+                       so.rtol * bnorm);
+    hipLaunchKernelGGL(k_first_vector, dim3(sgrid(N)), dim3(kBlock), 0, st, k.V, N, (const double *)k.r,
+                       (const double *)(scal + 1));
     LAUNCH_CHECK();
-    int j = 0;
+    int done = 0, next = 0;  // steps of this cycle read back / enqueued
+    double prev = truer, rate = 1.0;
     bool discard = false;
-    while (j < m && iters < so.maxit) {
-      if (use_graph) CPTR_HIP_TRY(hipGraphLaunch(h->graph_exec, st));
-      else step();
-      j++;
+    launch(next++);
+    while (true) {
+      // one step ahead when the step being read is not expected to reach the
+      // tolerance (its estimate predicted from the last reduction rate)
+      if (next == done + 1 && next < m && iters + (next - done) < so.maxit && prev * rate > 1.5 * so.rtol)
+        launch(next++);
+      CPTR_HIP_TRY(hipEventSynchronize(h->ev_step[done & 1]));
+      const double hn = k.host[2 * (done & 1)], absg = k.host[2 * (done & 1) + 1];
+      done++;
       iters++;
       h->stats.applies++;
-      CPTR_HIP_TRY(hipMemcpyAsync(h->pinned, &ks->hn, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
-      CPTR_HIP_TRY(hipStreamSynchronize(st));
-      const double hn = h->pinned[0], absg = h->pinned[1];
       est = absg / bnorm;
       if (!std::isfinite(est)) {
         // a non-finite learned-stage output: continue with the BILU(0) fallback
@@ -1662,24 +1751,27 @@ static int fgmres_impl(cptr_handle *h, const double *b, double *x, const cptr_so
           discard = true;
           break;
         }
+        CPTR_HIP_TRY(hipStreamSynchronize(st));
         throw Error{CPTR_ERR_NONFINITE, "non-finite Arnoldi step"};
       }
-      if (est <= so.rtol || hn == 0.0) break;
+      if (est <= so.rtol || hn == 0.0 || done == m || iters >= so.maxit) break;
+      rate = std::min(1.0, est / prev);
+      prev = est;
+      if (next == done) launch(next++);
     }
     if (discard) continue;
-    hipLaunchKernelGGL(k_solve_y, dim3(1), dim3(64), 0, st, (const KState *)ks,
-                       (const double *)devp<double>(h->R), (const double *)devp<double>(h->g),
-                       devp<double>(h->y));
-    hipLaunchKernelGGL((k_update_x<ZT>), dim3(sgrid(N)), dim3(kBlock), 0, st, x, (const ZT *)h->Z.p, N,
-                       (const KState *)ks, (const double *)devp<double>(h->y));
+    hipLaunchKernelGGL(k_solve_y, dim3(1), dim3(64), 0, st, (const KState *)ks, (const double *)k.R,
+                       (const double *)k.g, k.y);
+    hipLaunchKernelGGL((k_update_x<ZT>), dim3(sgrid(N)), dim3(kBlock), 0, st, x, (const ZT *)k.Z, N,
+                       (const KState *)ks, (const double *)k.y);
     LAUNCH_CHECK();
     cycles++;
     // stagnation of the learned stage over a whole cycle: fall back as well
     if (h->op.o.second_stage == CPTR_SECOND_LEARNED && h->op.o.lrn_fallback && !h->pc->fallback_flag() &&
-        j == m) {
-      spmv<double>(h, st, x, b, devp<double>(h->r));
-      norm2(h, st, devp<double>(h->r), N, 1);
-      const double after = fetch(h, st, scal + 1) / bnorm;
+        done == m) {
+      spmv<double>(h, st, x, b, k.r);
+      norm2(k, st, k.r, N, 1);
+      const double after = fetch(k, st, scal + 1) / bnorm;
       if (!(after <= 0.5 * truer)) {
         fall_back(h, st);
         info.fell_back = 1;
@@ -1707,10 +1799,11 @@ static double learn_grad_impl(cptr_handle *h, hipStream_t st, const double *b1_a
   LearnModelDev &M = h->model->dev;
   L.ensure_train();
   ensure_krylov(h, 1);
+  const Kws kw = kws_of(h);
   const int n = L.n;
   const size_t N = (size_t)n * NV;
   const int np = M.np;
-  double *scal = devp<double>(h->scal);
+  double *scal = kw.scal;
   float *grad = devp<float>(M.grad);
   float *part = devp<float>(L.part);
   hipLaunchKernelGGL((k_fill<float>), dim3(sgrid(np)), dim3(kBlock), 0, st, grad, (size_t)np, 0.f);
@@ -1719,16 +1812,16 @@ static double learn_grad_impl(cptr_handle *h, hipStream_t st, const double *b1_a
   double loss = 0.0;
   for (int k = 0; k < count; k++) {
     const double *b1 = b1_all + (size_t)k * N;
-    norm2(h, st, b1, N, 2);
-    const double bn = fetch(h, st, scal + 2);
+    norm2(kw, st, b1, N, 2);
+    const double bn = fetch(kw, st, scal + 2);
     if (!(bn > 0.0)) continue;
     const double bb = bn * bn;
     double *z2 = devp<double>(L.z2), *res = devp<double>(L.res), *dz = devp<double>(L.dz);
     L.forward<NV, double, double, double>(st, M, b1, true,
                                           LrnOut<double, double>{M.W_out(), 0, 0, nullptr, nullptr, nullptr, z2});
     spmv<double>(h, st, z2, b1, res);
-    norm2(h, st, res, N, 3);
-    const double rn = fetch(h, st, scal + 3);
+    norm2(kw, st, res, N, 3);
+    const double rn = fetch(kw, st, scal + 3);
     loss += rn * rn / bb;
     hipLaunchKernelGGL((k_bsr_spmv_t<NV>), dim3(nblk(N)), dim3(kBlock), 0, st, n, h->rp, h->ci,
                        (const int *)devp<int>(L.tpos), h->vals, (const double *)res, dz);
@@ -1813,6 +1906,8 @@ void cptr_default_options(cptr_options *o) {
   o->amg_smoother = CPTR_SMOOTHER_L1JACOBI;
   o->decoupling = CPTR_DECOUPLE_NONE;
   o->ilu_level = 0;
+  o->ilu_part_x = o->ilu_part_y = o->ilu_part_z = 1;
+  o->ilu_accum_fp64 = 0;
 }
 
 int cptr_setup(cptr_handle **out, const cptr_bsr *A, const cptr_csr *S_T, const cptr_options *opt,
@@ -1842,6 +1937,7 @@ int cptr_setup(cptr_handle **out, const cptr_bsr *A, const cptr_csr *S_T, const 
     CPTR_HIP_TRY(hipStreamCreate(&h->stream));
     CPTR_HIP_TRY(hipEventCreateWithFlags(&h->ev_in, hipEventDisableTiming));
     CPTR_HIP_TRY(hipEventCreateWithFlags(&h->ev_out, hipEventDisableTiming));
+    for (auto &e : h->ev_step) CPTR_HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     h->slots.alloc(sizeof(ApplySlots));
     build_sliced(h, rp, ci, vals);
     if (o.precision == CPTR_FP32) build_precond<float>(h, rp, ci, vals, &sh);
@@ -1934,8 +2030,10 @@ int fgmres_solve(cptr_handle *h, const double *b, double *x, const cptr_solve_op
   if (!(so.rtol > 0.0) || so.maxit < 0) return fail(Error{CPTR_ERR_INVALID_ARG, "invalid tolerance or maxit"});
   cptr_solve_info info{};
   try {
-    int rc = h->op.o.precision == CPTR_FP32 ? fgmres_impl<float>(h, b, x, so, info, (hipStream_t)stream)
-                                            : fgmres_impl<double>(h, b, x, so, info, (hipStream_t)stream);
+    ensure_krylov(h, so.restart);
+    const Kws k = kws_of(h);
+    int rc = h->op.o.precision == CPTR_FP32 ? fgmres_impl<float>(h, k, b, x, so, info, (hipStream_t)stream)
+                                            : fgmres_impl<double>(h, k, b, x, so, info, (hipStream_t)stream);
     if (info_out) *info_out = info;
     return rc;
   } catch (const Error &e) {
@@ -1963,7 +2061,7 @@ int cptr_krylov_vector(const cptr_handle *h, int j, double *out, void *stream) {
   if (h->m_alloc < 1 || j < 0 || j > h->m_alloc)
     return fail(Error{CPTR_ERR_INVALID_ARG, "no Krylov basis of that index"});
   const size_t N = (size_t)h->op.n * h->op.nv;
-  const hipError_t e = hipMemcpyAsync(out, devp<double>(h->V) + (size_t)j * N, N * sizeof(double),
+  const hipError_t e = hipMemcpyAsync(out, (const double *)h->kws.p + (size_t)j * N, N * sizeof(double),
                                       hipMemcpyDeviceToDevice, (hipStream_t)stream);
   if (e != hipSuccess) return fail(Error{CPTR_ERR_HIP, hipGetErrorString(e)});
   return CPTR_OK;
@@ -2131,6 +2229,8 @@ void cptr_destroy(cptr_handle *h) {
   if (h->pinned) (void)hipHostFree(h->pinned);
   if (h->ev_in) (void)hipEventDestroy(h->ev_in);
   if (h->ev_out) (void)hipEventDestroy(h->ev_out);
+  for (auto e : h->ev_step)
+    if (e) (void)hipEventDestroy(e);
   h->pc.reset();
   if (h->stream) (void)hipStreamDestroy(h->stream);
   delete h;

@@ -357,8 +357,10 @@ __global__ void __launch_bounds__(kBlock) k_finish(int n, int nv, int ip, int iT
 // ---------------------------------------------------------------------------
 // BILU(0) triangular solves, one launch per level; NV threads per row
 // ---------------------------------------------------------------------------
+// The sums of a row are accumulated in A: T, or FP64 for FP32 factors and
+// vectors (storage in T either way; the factors and y are rounded to T).
 // forward: y_i = b_i - sum_k L_ik y_k   (in place in y, which holds b1)
-template <int NV, typename T>
+template <int NV, typename T, typename A = T>
 __global__ void __launch_bounds__(kBlock) k_ilu_fwd(int p0, int cnt, const int *__restrict__ rows,
                                                     const int *__restrict__ ptr,
                                                     const int *__restrict__ col,
@@ -368,19 +370,19 @@ __global__ void __launch_bounds__(kBlock) k_ilu_fwd(int p0, int cnt, const int *
   if (q >= cnt) return;
   const int p = p0 + q;
   const int i = rows[p];
-  T s = y[(size_t)i * NV + r];
+  A s = A(y[(size_t)i * NV + r]);
   for (int k = ptr[p]; k < ptr[p + 1]; k++) {
     const T *l = val + ((size_t)k * NV + r) * NV;
     const T *yk = y + (size_t)col[k] * NV;
 #pragma unroll
-    for (int c = 0; c < NV; c++) s -= l[c] * yk[c];
+    for (int c = 0; c < NV; c++) s -= A(l[c]) * A(yk[c]);
   }
-  y[(size_t)i * NV + r] = s;
+  y[(size_t)i * NV + r] = T(s);
 }
 
 // backward: w_i = U_ii^{-1} (y_i - sum_k U_ik w_k), in place in y; also
 // writes z_i = w_i + x1_i.
-template <int NV, typename T, typename ZT>
+template <int NV, typename T, typename ZT, typename A = T>
 __global__ void __launch_bounds__(kBlock) k_ilu_bwd(int p0, int cnt, const int *__restrict__ rows,
                                                     const int *__restrict__ ptr,
                                                     const int *__restrict__ col,
@@ -390,22 +392,22 @@ __global__ void __launch_bounds__(kBlock) k_ilu_bwd(int p0, int cnt, const int *
                                                     const T *__restrict__ dT,
                                                     const ApplySlots *__restrict__ slots) {
   // rows never straddle workgroups: kBlock / NV rows per workgroup
-  __shared__ T sh[kBlock];
+  __shared__ A sh[kBlock];
   constexpr int kRows = kBlock / NV;
   const int r = threadIdx.x % NV;
   const int q = blockIdx.x * kRows + threadIdx.x / NV;
   const bool live = q < cnt && threadIdx.x < kRows * NV;
   int i = 0;
-  T s = T(0);
+  A s = A(0);
   if (live) {
     const int p = p0 + q;
     i = rows[p];
-    s = y[(size_t)i * NV + r];
+    s = A(y[(size_t)i * NV + r]);
     for (int k = ptr[p]; k < ptr[p + 1]; k++) {
       const T *u = val + ((size_t)k * NV + r) * NV;
       const T *wk = y + (size_t)col[k] * NV;
 #pragma unroll
-      for (int c = 0; c < NV; c++) s -= u[c] * wk[c];
+      for (int c = 0; c < NV; c++) s -= A(u[c]) * A(wk[c]);
     }
   }
   sh[threadIdx.x] = s;
@@ -413,13 +415,13 @@ __global__ void __launch_bounds__(kBlock) k_ilu_bwd(int p0, int cnt, const int *
   if (!live) return;
   const T *d = dinv + ((size_t)i * NV + r) * NV;
   const int base = threadIdx.x - r;
-  T w = T(0);
+  A w = A(0);
 #pragma unroll
-  for (int c = 0; c < NV; c++) w += d[c] * sh[base + c];
-  y[(size_t)i * NV + r] = w;
-  T z = w;
-  if (dp && r == ip) z += dp[i];
-  if (dT && r == iT) z += dT[i];
+  for (int c = 0; c < NV; c++) w += A(d[c]) * sh[base + c];
+  y[(size_t)i * NV + r] = T(w);
+  A z = w;
+  if (dp && r == ip) z += A(dp[i]);
+  if (dT && r == iT) z += A(dT[i]);
   as_global(reinterpret_cast<ZT *>(slots->z))[(size_t)i * NV + r] = ZT(z);
 }
 
@@ -747,6 +749,18 @@ __global__ void __launch_bounds__(64 * NV) k_bsr_spmv_sliced(int n, const int *_
 // ---------------------------------------------------------------------------
 constexpr int kDotBlocks = 1024;
 
+// Krylov state kept on the device
+struct KState {
+  int j;          // current column
+  int m;          // restart length
+  double beta;
+  double hn;      // ||w|| of the last step
+  double absg;    // |g_{j+1}|
+  double tol;     // rtol ||b||: the cycle stops once |g_{j+1}| <= tol
+  int stop;       // set by the step that ends the cycle (tolerance reached, breakdown
+                  // or a non-finite value): later steps of the cycle leave the state alone
+};
+
 template <int MAXK>
 __device__ __forceinline__ void block_store_partials(double (&acc)[MAXK], int kk, double *part) {
   __shared__ double sh[kBlock / 64][MAXK];
@@ -789,15 +803,18 @@ __global__ void __launch_bounds__(kBlock) k_mdot(const double *__restrict__ V, s
   block_store_partials<MAXK>(acc, kk, part);
 }
 
-// w -= V h; then partial[blk][k] = sum_i V[k][i] w[i] (second Gram-Schmidt pass)
+// w -= V h; then partial[blk][k] = sum_i V[k][i] w[i] (second Gram-Schmidt
+// pass) and w2_part[blk] = sum_i w[i]^2 of the updated w
 template <int MAXK>
 __global__ void __launch_bounds__(kBlock) k_cgs_update_mdot(const double *__restrict__ V, size_t N,
                                                             const int *__restrict__ jdev,
                                                             const double *__restrict__ h,
                                                             double *__restrict__ w,
-                                                            double *__restrict__ part) {
+                                                            double *__restrict__ part,
+                                                            double *__restrict__ w2_part) {
   const int kk = *jdev + 1;
   double acc[MAXK], hk[MAXK];
+  double ww[1] = {0.0};
 #pragma unroll
   for (int k = 0; k < MAXK; k++) {
     acc[k] = 0.0;
@@ -812,24 +829,64 @@ __global__ void __launch_bounds__(kBlock) k_cgs_update_mdot(const double *__rest
       wi -= vk[k] * hk[k];
     }
     w[i] = wi;
+    ww[0] += wi * wi;
 #pragma unroll
     for (int k = 0; k < MAXK; k++) acc[k] += vk[k] * wi;
   }
   block_store_partials<MAXK>(acc, kk, part);
+  block_store_partials<1>(ww, 1, w2_part);
 }
 
-// w -= V h; partial[blk][0] = sum_i w[i]^2
-template <int MAXK>
-__global__ void __launch_bounds__(kBlock) k_cgs_update_norm(const double *__restrict__ V, size_t N,
-                                                            const int *__restrict__ jdev,
-                                                            const double *__restrict__ h,
-                                                            double *__restrict__ w,
-                                                            double *__restrict__ part) {
-  const int kk = *jdev + 1;
-  double hk[MAXK];
+// The sum of row[0 .. nblk-1] in a fixed order (thread t adds the entries
+// t, t + 256, ..., then a fixed tree), returned to every thread of the
+// workgroup; nblk <= kDotBlocks.
+__device__ __forceinline__ double block_reduce_row(const double *__restrict__ row, int nblk) {
+  __shared__ double sh[kBlock / 64];
+  __shared__ double tot;
+  constexpr int kPer = kDotBlocks / kBlock;
+  double v[kPer];
 #pragma unroll
-  for (int k = 0; k < MAXK; k++) hk[k] = k < kk ? h[k] : 0.0;
-  double acc[1] = {0.0};
+  for (int q = 0; q < kPer; q++) v[q] = row[min((int)threadIdx.x + q * kBlock, nblk - 1)];
+  double s = 0.0;
+#pragma unroll
+  for (int q = 0; q < kPer; q++)
+    if ((int)threadIdx.x + q * kBlock < nblk) s += v[q];
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < kBlock / 64; w++) t += sh[w];
+    tot = t;
+  }
+  __syncthreads();
+  return tot;
+}
+
+// The end of the second Gram-Schmidt pass: v_{j+1} = (w - V h2) / hn with
+// hn = ||w - V h2|| = sqrt(||w||^2 - ||h2||^2) (the basis is orthonormal and
+// h2 = V^T w), ||w||^2 reduced from the per-block partials of
+// k_cgs_update_mdot by every workgroup in the same fixed order; hn = 0 gives
+// a zero vector (breakdown).  Workgroup 0 stores hn in the Krylov state.
+template <int MAXK>
+__global__ void __launch_bounds__(kBlock) k_cgs_finish(double *__restrict__ V, size_t N, KState *__restrict__ st,
+                                                       const double *__restrict__ h,
+                                                       const double *__restrict__ w,
+                                                       const double *__restrict__ w2_part, int nblk) {
+  const int kk = st->j + 1;
+  double hk[MAXK];
+  double hh = 0.0;
+#pragma unroll
+  for (int k = 0; k < MAXK; k++) {
+    hk[k] = k < kk ? h[k] : 0.0;
+    hh += hk[k] * hk[k];
+  }
+  const double w2 = block_reduce_row(w2_part, nblk);
+  const double hn = sqrt(fmax(w2 - hh, 0.0));
+  const double inv = hn != 0.0 ? 1.0 / hn : 0.0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) st->hn = hn;
+  double *vn = V + (size_t)kk * N;
   for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < N; i += (size_t)gridDim.x * kBlock) {
     double vk[MAXK];
     double wi = w[i];
@@ -837,10 +894,8 @@ __global__ void __launch_bounds__(kBlock) k_cgs_update_norm(const double *__rest
     for (int k = 0; k < MAXK; k++) vk[k] = k < kk ? V[(size_t)k * N + i] : 0.0;
 #pragma unroll
     for (int k = 0; k < MAXK; k++) wi -= vk[k] * hk[k];
-    w[i] = wi;
-    acc[0] += wi * wi;
+    vn[i] = wi * inv;
   }
-  block_store_partials<1>(acc, 1, part);
 }
 
 // partial[blk][0] = sum_i x[i]^2
@@ -883,59 +938,63 @@ __global__ void __launch_bounds__(kBlock) k_reduce(const double *__restrict__ pa
   }
 }
 
-// Krylov state kept on the device
-struct KState {
-  int j;          // current column
-  int m;          // restart length
-  double beta;
-  double hn;      // ||w|| of the last step
-  double absg;    // |g_{j+1}|
-};
-
-// v_{j+1} = w / hn  (hn == 0: zero vector)
-__global__ void __launch_bounds__(kBlock) k_scale_next(double *__restrict__ V, size_t N,
-                                                       const KState *__restrict__ st,
-                                                       const double *__restrict__ w) {
-  const double hn = st->hn;
-  const double inv = hn != 0.0 ? 1.0 / hn : 0.0;
-  double *vn = V + (size_t)(st->j + 1) * N;
-  for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < N; i += (size_t)gridDim.x * kBlock)
-    vn[i] = w[i] * inv;
-}
 
 // Hessenberg column j = h1 + h2 (0..j), hn (j+1); previous rotations, a new
-// rotation, g update; j advances.  R is stored (m+1) x m row-major.
-__global__ void k_givens(KState *st, const double *__restrict__ h1, const double *__restrict__ h2,
-                         double *__restrict__ R, double *__restrict__ cs, double *__restrict__ sn,
-                         double *__restrict__ g) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// rotation, g update; j advances.  R is stored (m+1) x m row-major.  One
+// wavefront: the lanes load the column and the rotations into LDS, lane 0
+// applies them in order, the lanes store the column.
+// A step launched after the one that set `stop` changes nothing here, so
+// the cycle's solution uses the columns up to that step.
+constexpr int kMaxRestart = 64;
+__global__ void __launch_bounds__(64) k_givens(KState *st, const double *__restrict__ h1,
+                                               const double *__restrict__ h2, double *__restrict__ R,
+                                               double *__restrict__ cs, double *__restrict__ sn,
+                                               double *__restrict__ g) {
+  __shared__ double col[kMaxRestart + 1], c_[kMaxRestart], s_[kMaxRestart];
+  if (blockIdx.x != 0 || st->stop) return;
+  const int lane = threadIdx.x;
   const int j = st->j, m = st->m;
-  for (int k = 0; k <= j; k++) R[(size_t)k * m + j] = h1[k] + h2[k];
-  R[(size_t)(j + 1) * m + j] = st->hn;
-  for (int k = 0; k < j; k++) {
-    const double a = R[(size_t)k * m + j], c = R[(size_t)(k + 1) * m + j];
-    R[(size_t)k * m + j] = cs[k] * a + sn[k] * c;
-    R[(size_t)(k + 1) * m + j] = -sn[k] * a + cs[k] * c;
+  for (int k = lane; k <= j; k += 64) col[k] = h1[k] + h2[k];
+  for (int k = lane; k < j; k += 64) {
+    c_[k] = cs[k];
+    s_[k] = sn[k];
   }
-  const double a = R[(size_t)j * m + j], c = R[(size_t)(j + 1) * m + j];
-  const double den = hypot(a, c);
-  cs[j] = den == 0.0 ? 1.0 : a / den;
-  sn[j] = den == 0.0 ? 0.0 : c / den;
-  R[(size_t)j * m + j] = den;
-  R[(size_t)(j + 1) * m + j] = 0.0;
-  g[j + 1] = -sn[j] * g[j];
-  g[j] = cs[j] * g[j];
-  st->absg = fabs(g[j + 1]);
-  st->j = j + 1;
+  if (lane == 0) col[j + 1] = st->hn;
+  __syncthreads();
+  if (lane == 0) {
+    for (int k = 0; k < j; k++) {
+      const double a = col[k], c = col[k + 1];
+      col[k] = c_[k] * a + s_[k] * c;
+      col[k + 1] = -s_[k] * a + c_[k] * c;
+    }
+    const double a = col[j], c = col[j + 1];
+    const double den = hypot(a, c);
+    const double cj = den == 0.0 ? 1.0 : a / den, sj = den == 0.0 ? 0.0 : c / den;
+    cs[j] = cj;
+    sn[j] = sj;
+    col[j] = den;
+    col[j + 1] = 0.0;
+    const double gj = g[j];
+    g[j + 1] = -sj * gj;
+    g[j] = cj * gj;
+    const double ag = fabs(-sj * gj);
+    st->absg = ag;
+    st->j = j + 1;
+    if (!(ag > st->tol) || st->hn == 0.0 || j + 1 == m) st->stop = 1;  // !(ag > tol) holds for NaN too
+  }
+  __syncthreads();
+  for (int k = lane; k <= j + 1; k += 64) R[(size_t)k * m + j] = col[k];
 }
 
 __global__ void k_cycle_init(KState *st, const double *__restrict__ beta, double *__restrict__ g,
-                             int m) {
+                             int m, double tol) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   st->j = 0;
   st->m = m;
   st->beta = *beta;
   st->hn = 0.0;
+  st->tol = tol;
+  st->stop = 0;
   st->absg = *beta;
   g[0] = *beta;
   for (int k = 1; k <= m; k++) g[k] = 0.0;

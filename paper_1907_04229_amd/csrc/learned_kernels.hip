@@ -152,6 +152,13 @@ struct LrnOut {
   double *z2_out;
 };
 
+// The output column of the slots, read once per workgroup (a store through
+// slots->z in the tile loop would reload the pointer after every store)
+template <bool LAST, typename ZT, typename XT>
+__device__ __forceinline__ ZT *lrn_zout(const LrnOut<ZT, XT> &out) {
+  return LAST && !out.z2_out && out.slots ? reinterpret_cast<ZT *>(as_global(out.slots)->z) : nullptr;
+}
+
 __device__ __forceinline__ f32x4 load_f4(const float *p) { return *reinterpret_cast<const f32x4 *>(p); }
 __device__ __forceinline__ void store_f4(float *p, f32x4 v) { *reinterpret_cast<f32x4 *>(p) = v; }
 __device__ __forceinline__ float bf2f(short b) { return __uint_as_float(uint32_t((unsigned short)b) << 16); }
@@ -245,14 +252,29 @@ struct RawAct<HT, NV, true> {
   }
 };
 
-// Edge blocks in tile order (what the forward layers read): for tile t,
-// direction d and lane group g, the entries 4g .. 4g + 3 of the 16 cells of
-// the tile are 16 x 4 consecutive BF16, so a wave's load of one direction is
-// 512 contiguous bytes.  Cells past n (last tile) hold zeros.
+// Edge blocks in tile order (what the forward layers read).  For tile t and
+// direction d the entries of the 16 cells form one run of kEdgeRun<NV> BF16,
+// groups g of 16 cells x 4 entries 4g .. 4g + 3: four groups for nv = 4
+// (256 values), three for nv = 3 (192 values: entries 0-3, 4-7, and entry 8
+// followed by three zeros).  Lane group lg of a wave takes entries
+// 4 lg .. 4 lg + 3 of cell lr (the B operand of the edge gate) with one
+// 8-byte load: each group of 16 lanes reads 128 contiguous bytes; entries
+// past nv^2 are zero.  (Loading the ninth entry alone, 2 bytes per lane, in a
+// second instruction is slower.)  Cells past n (last tile) hold zeros.
+template <int NV>
+constexpr int kEdgeRun = NV == 3 ? 192 : 256;
+
+template <int NV>
 __device__ __forceinline__ bf16x4 load_edge_tiled(const short *__restrict__ Et, int tile, int d, int lg,
                                                   int lr) {
-  return __builtin_nontemporal_load(
-      reinterpret_cast<const bf16x4 *>(Et + ((((size_t)tile * kDir + d) * 4 + lg) * 16 + lr) * 4));
+  const short *run = Et + ((size_t)tile * kDir + d) * kEdgeRun<NV>;
+  if constexpr (NV == 4) {
+    return __builtin_nontemporal_load(reinterpret_cast<const bf16x4 *>(run + lg * 64 + lr * 4));
+  } else {
+    bf16x4 e = {0, 0, 0, 0};
+    if (lg < 3) e = __builtin_nontemporal_load(reinterpret_cast<const bf16x4 *>(run + lg * 64 + lr * 4));
+    return e;
+  }
 }
 
 // Workgroups of the layer kernel: enough to fill the chip several times over;
@@ -281,15 +303,62 @@ constexpr int kColWaves = 4096;  // target wave count of the z-column schedule (
 // LDS, 1 / s_k, and this lane's slice of W_e with the edge scaling folded in:
 // (W_e S^{-1} e S)_j = sum_k W_e[j][k] f_k e_k, f_k = s_c / s_r for k = r NV + c,
 // so the stored edge blocks are the B operand as they are.
+// The matrix-core A operands of one lane (lane l = 16 lg + lr of a wave),
+// the same in every wave of the workgroup, formed once per workgroup in LDS;
+// we and win (used six times per tile) are then held in registers, wout (used
+// once per tile) is read from LDS where it is used:
+//   we[t]    this lane's slice of W_e with the edge scaling folded in, rows in
+//            the order of output tile t;
+//   win[t]   rows of W_in in the order of output tile t (first layer: the A
+//            operand of h0_nbr = W_in (u / s), depth nv padded to 16);
+//   wout[ks] rows 0 .. nv-1 of W_out, channels 32 ks .. 32 ks + 31 (last layer:
+//            the A operand of the read-out W_out h3, rows nv .. 15 zero).
+// Unused operands are zero.
 template <int NV>
-__device__ __forceinline__ void layer_setup(short (&Wl)[2][kHid][kWPad], const short *__restrict__ W_s,
+struct LaneOps {
+  bf16x4 we[4];
+  bf16x4 win[4];
+  bf16x8 wout[2];
+};
+
+// Per-workgroup set-up shared by both layer kernels: W_s and W_m staged in
+// LDS, the bias, the lane operands above, and 1 / s_k in registers.  The edge
+// scaling (W_e S^{-1} e S)_j = sum_k W_e[j][k] f_k e_k, f_k = s_c / s_r for
+// k = r NV + c, is folded into we, so the stored edge blocks are the B operand
+// as they are.  The tile loops read the LDS copies through an offset the
+// compiler cannot see through, so that these loop-invariant values are not
+// held in registers for the whole loop.
+template <int NV, bool FIRST, bool LAST>
+__device__ __forceinline__ void layer_setup(short (&Wl)[2][kHid][kWPad], float (&bias_s)[kHid],
+                                            LaneOps<NV> (&ops)[64], const short *__restrict__ W_s,
                                             const short *__restrict__ W_m, const float *__restrict__ W_e,
-                                            const float *__restrict__ s_ptr, int lr, int lg, float (&inv_s)[NV],
-                                            bf16x4 (&we)[4]) {
+                                            const float *__restrict__ bias, const float *__restrict__ W_in,
+                                            const float *__restrict__ W_out, const float *__restrict__ s_ptr,
+                                            float (&inv_s)[NV], LaneOps<NV> &mine) {
   for (int v = threadIdx.x; v < 2 * kHid * kHid / 4; v += kBlock) {
     const int mtx = v / (kHid * kHid / 4), e = (v % (kHid * kHid / 4)) * 4;
     const short *src = (mtx == 0 ? W_s : W_m) + e;
     *reinterpret_cast<bf16x4 *>(&Wl[mtx][e / kHid][e % kHid]) = load_bf4(src);
+  }
+  for (int v = threadIdx.x; v < kHid; v += kBlock) bias_s[v] = bias[v];
+  if (threadIdx.x < 64) {
+    const int lr = threadIdx.x & 15, lg = threadIdx.x >> 4;
+    LaneOps<NV> o;
+#pragma unroll
+    for (int t = 0; t < 4; t++)
+#pragma unroll
+      for (int q = 0; q < 4; q++) {
+        // row lr of output tile t is channel lch(t, lr / 4) + lr % 4
+        const int k = 4 * lg + q, row = lch(t, lr >> 2) + (lr & 3);
+        o.we[t][q] = k < NV * NV ? f2bf(W_e[row * NV * NV + k] * edge_factor<NV>(k, s_ptr)) : short(0);
+        o.win[t][q] = FIRST && k < NV ? f2bf(W_in[row * NV + k]) : short(0);
+      }
+#pragma unroll
+    for (int ks = 0; ks < 2; ks++)
+#pragma unroll
+      for (int j = 0; j < 8; j++)
+        o.wout[ks][j] = LAST && lr < NV ? f2bf(W_out[lr * kHid + 32 * ks + 8 * lg + j]) : short(0);
+    ops[threadIdx.x] = o;
   }
   __syncthreads();
 #pragma unroll
@@ -297,14 +366,12 @@ __device__ __forceinline__ void layer_setup(short (&Wl)[2][kHid][kWPad], const s
     const float sk = s_ptr[k];
     inv_s[k] = sk > 0.f ? 1.f / sk : 0.f;
   }
+  const LaneOps<NV> &o = ops[threadIdx.x & 63];
 #pragma unroll
-  for (int t = 0; t < 4; t++)
-#pragma unroll
-    for (int q = 0; q < 4; q++) {
-      // row lr of output tile t is channel lch(t, lr / 4) + lr % 4
-      const int k = 4 * lg + q, row = lch(t, lr >> 2) + (lr & 3);
-      we[t][q] = k < NV * NV ? f2bf(W_e[row * NV * NV + k] * edge_factor<NV>(k, s_ptr)) : short(0);
-    }
+  for (int t = 0; t < 4; t++) {
+    mine.we[t] = o.we[t];
+    mine.win[t] = o.win[t];
+  }
 }
 
 // The arithmetic of one tile, shared by both layer kernels: given the cell's
@@ -315,23 +382,40 @@ __device__ __forceinline__ void layer_setup(short (&Wl)[2][kHid][kWPad], const s
 template <int NV, bool FIRST, bool LAST, typename HT, typename ZT, typename XT>
 __device__ __forceinline__ void layer_tile(int cell, bool ok, int lr, int lg, const f32x4 (&hv)[4],
                                            const typename RawAct<HT, NV, FIRST>::type (&raw)[kDir],
-                                           const bf16x4 (&rawe)[kDir], const bf16x4 (&we)[4],
+                                           const bf16x4 (&rawe)[kDir], const LaneOps<NV> &ops,
+                                           const LaneOps<NV> &ops_lds,
                                            const short (&Wl)[2][kHid][kWPad], const float *__restrict__ W_in,
                                            const float (&inv_s)[NV], const float *__restrict__ bias,
                                            const float *__restrict__ r, const float *__restrict__ s_ptr,
                                            HT *__restrict__ hout, float *__restrict__ h0_out,
                                            float *__restrict__ m_out, float *__restrict__ a_out,
-                                           const LrnOut<ZT, XT> &out) {
+                                           const LrnOut<ZT, XT> &out, ZT *__restrict__ zout) {
   __builtin_amdgcn_sched_barrier(0);
   f32x4 macc[4];
 #pragma unroll
   for (int t = 0; t < 4; t++) macc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
   for (int d = 0; d < kDir; d++) {
+    if constexpr (FIRST) {
+      // the neighbour's h0 = W_in (u / s) on the matrix cores: B operand
+      // rows k < nv hold u_k / s_k of the neighbour of cell lr (lane group 0)
+      bf16x4 ub = {0, 0, 0, 0};
 #pragma unroll
-    for (int t = 0; t < 4; t++) {
-      const f32x4 g = mfma16(we[t], rawe[d], f32x4{0.f, 0.f, 0.f, 0.f});
-      macc[t] += g * RawAct<HT, NV, FIRST>::get(raw[d], t, lg, W_in, inv_s);
+      for (int k = 0; k < NV; k++) ub[k] = lg == 0 ? f2bf(raw[d].u[k] * inv_s[k]) : short(0);
+#pragma unroll
+      for (int t = 0; t < 4; t++) {
+        const f32x4 g = mfma16(ops.we[t], rawe[d], f32x4{0.f, 0.f, 0.f, 0.f});
+        macc[t] += g * mfma16(ops.win[t], ub, f32x4{0.f, 0.f, 0.f, 0.f});
+      }
+      // one direction at a time: keeps the products of the next direction
+      // from being hoisted (register pressure)
+      __builtin_amdgcn_sched_barrier(0);
+    } else {
+#pragma unroll
+      for (int t = 0; t < 4; t++) {
+        const f32x4 g = mfma16(ops.we[t], rawe[d], f32x4{0.f, 0.f, 0.f, 0.f});
+        macc[t] += g * RawAct<HT, NV, FIRST>::get(raw[d], t, lg, W_in, inv_s);
+      }
     }
   }
   __builtin_amdgcn_sched_barrier(0);
@@ -372,32 +456,28 @@ __device__ __forceinline__ void layer_tile(int cell, bool ok, int lr, int lg, co
     }
   }
   if constexpr (LAST) {
-    float p[NV];
+    // read-out (W_out h3)_k on the matrix cores: D row k, column lr lands in
+    // lane (lr, k / 4), register k % 4; lane group 0 holds the nv <= 4 values
+    f32x4 ro = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int k = 0; k < NV; k++) {
-      float v = 0.f;
-#pragma unroll
-      for (int t = 0; t < 4; t++)
-#pragma unroll
-        for (int q = 0; q < 4; q++) v += out.W_out[k * kHid + lch(t, lg) + q] * hnew[t][q];
-      v += __shfl_xor(v, 16);
-      v += __shfl_xor(v, 32);
-      p[k] = v;
+    for (int ks = 0; ks < 2; ks++) {
+      const bf16x8 hb = cat8(cvt4(hnew[2 * ks][0], hnew[2 * ks][1], hnew[2 * ks][2], hnew[2 * ks][3]),
+                             cvt4(hnew[2 * ks + 1][0], hnew[2 * ks + 1][1], hnew[2 * ks + 1][2],
+                                  hnew[2 * ks + 1][3]));
+      ro = mfma32(ops_lds.wout[ks], hb, ro);
     }
-    // lane group lg writes component k = lg of its cell
-    float pk = 0.f;
+    if (ok && lg == 0) {
 #pragma unroll
-    for (int k = 0; k < NV; k++)
-      if (k == lg) pk = p[k];
-    if (ok && lg < NV) {
-      const size_t t = (size_t)cell * NV + lg;
-      float z = r[t] + s_ptr[lg] * pk;
-      if (out.z2_out) {
-        out.z2_out[t] = z;
-      } else {
-        if (out.dp && lg == out.ip) z += float(out.dp[cell]);
-        if (out.dT && lg == out.iT) z += float(out.dT[cell]);
-        reinterpret_cast<ZT *>(out.slots->z)[t] = ZT(z);
+      for (int k = 0; k < NV; k++) {
+        const size_t t = (size_t)cell * NV + k;
+        float z = r[t] + s_ptr[k] * ro[k];
+        if (out.z2_out) {
+          out.z2_out[t] = z;
+        } else {
+          if (out.dp && k == out.ip) z += float(out.dp[cell]);
+          if (out.dT && k == out.iT) z += float(out.dT[cell]);
+          zout[t] = ZT(z);
+        }
       }
     }
   }
@@ -413,12 +493,21 @@ __device__ __forceinline__ void lrn_layer_tiles(
     const float *__restrict__ bias, HT *__restrict__ hout, float *__restrict__ h0_out,
     float *__restrict__ m_out, float *__restrict__ a_out, const LrnOut<ZT, XT> &out) {
   __shared__ __attribute__((aligned(16))) short Wl[2][kHid][kWPad];
+  // first layer: W_in in LDS for the cell's own h0 (read in the tile loop,
+  // not held in registers)
+  __shared__ float Win_s[FIRST ? kHid * NV : 1];
+  __shared__ float bias_s[kHid];
+  __shared__ LaneOps<NV> ops_s[64];
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int lr = l & 15, lg = l >> 4;
   const int ntiles = (n + 15) / 16;
+  if constexpr (FIRST)
+    for (int v = threadIdx.x; v < kHid * NV; v += kBlock) Win_s[v] = W_in[v];
   float inv_s[NV];
-  bf16x4 we[4];
-  layer_setup<NV>(Wl, W_s, W_m, W_e, s_ptr, lr, lg, inv_s, we);
+  LaneOps<NV> ops;
+  // (its barrier covers Win_s)
+  layer_setup<NV, FIRST, LAST>(Wl, bias_s, ops_s, W_s, W_m, W_e, bias, W_in, out.W_out, s_ptr, inv_s, ops);
+  ZT *const zout = lrn_zout<LAST>(out);
   using Raw = RawAct<HT, NV, FIRST>;
   const int off[kDir] = {-stride.x, stride.x, -stride.y, stride.y, -stride.z, stride.z};
   // XCD-aware order: workgroups are dealt to the 8 XCDs round robin, so the
@@ -447,14 +536,18 @@ __device__ __forceinline__ void lrn_layer_tiles(
     bf16x4 rawe[kDir];
 #pragma unroll
     for (int d = 0; d < kDir; d++) {
-      rawe[d] = load_edge_tiled(Et, tile, d, lg, lr);
+      rawe[d] = load_edge_tiled<NV>(Et, tile, d, lg, lr);
       raw[d] = Raw::load((mk >> d) & 1u ? cl + off[d] : cl, lg, hin, r);
     }
+    // an offset the compiler cannot see through keeps the LDS reads of W_in,
+    // the bias and the lane operands in the loop
+    int z0 = 0;
+    asm volatile("" : "+v"(z0));
     f32x4 hv[4];
 #pragma unroll
-    for (int t = 0; t < 4; t++) hv[t] = Raw::get(own, t, lg, W_in, inv_s);
-    layer_tile<NV, FIRST, LAST, HT, ZT, XT>(cell, ok, lr, lg, hv, raw, rawe, we, Wl, W_in, inv_s, bias, r, s_ptr,
-                                           hout, h0_out, m_out, a_out, out);
+    for (int t = 0; t < 4; t++) hv[t] = Raw::get(own, t, lg, FIRST ? Win_s + z0 : W_in, inv_s);
+    layer_tile<NV, FIRST, LAST, HT, ZT, XT>(cell, ok, lr, lg, hv, raw, rawe, ops, ops_s[l + z0], Wl, W_in,
+                                           inv_s, bias_s + z0, r, s_ptr, hout, h0_out, m_out, a_out, out, zout);
   }
 }
 
@@ -511,17 +604,20 @@ constexpr int kDppRowShl1 = 0x101;  // lane i <- lane i + 1 within a row of 16
 // is the one of k_lrn_layer, bit for bit: every neighbour row that is present
 // is the same row, every absent one finite (and multiplied by zero).
 template <int NV, bool FIRST, bool LAST, typename HT, typename ZT, typename XT>
-__global__ void __launch_bounds__(kBlock) k_lrn_layer_col(
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) k_lrn_layer_col(
     int n, int P, int nz, int zlen, int sy, const short *__restrict__ Et, const float *__restrict__ s_ptr,
     const HT *__restrict__ hin, const float *__restrict__ r, const float *__restrict__ W_in,
     const float *__restrict__ W_e, const short *__restrict__ W_s, const short *__restrict__ W_m,
     const float *__restrict__ bias, HT *__restrict__ hout, LrnOut<ZT, XT> out) {
   __shared__ __attribute__((aligned(16))) short Wl[2][kHid][kWPad];
+  __shared__ float bias_s[kHid];
+  __shared__ LaneOps<NV> ops_s[64];
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int lr = l & 15, lg = l >> 4;
   float inv_s[NV];
-  bf16x4 we[4];
-  layer_setup<NV>(Wl, W_s, W_m, W_e, s_ptr, lr, lg, inv_s, we);
+  LaneOps<NV> ops;
+  layer_setup<NV, FIRST, LAST>(Wl, bias_s, ops_s, W_s, W_m, W_e, bias, W_in, out.W_out, s_ptr, inv_s, ops);
+  ZT *const zout = lrn_zout<LAST>(out);
   using Raw = RawAct<HT, NV, FIRST>;
   using RT = typename Raw::type;
   const int sz = P * 16;
@@ -546,7 +642,7 @@ __global__ void __launch_bounds__(kBlock) k_lrn_layer_col(
       bf16x4 rawe[kDir];
 #pragma unroll
       for (int d = 0; d < kDir; d++)
-        rawe[d] = load_edge_tiled(Et, cell >> 4, d, lg, lr);
+        rawe[d] = load_edge_tiled<NV>(Et, cell >> 4, d, lg, lr);
       raw[0] = shuffle_row<RT, kDppRowShr1>(rc, xe);
       raw[1] = shuffle_row<RT, kDppRowShl1>(rc, xe);
       raw[4] = rp;
@@ -554,8 +650,11 @@ __global__ void __launch_bounds__(kBlock) k_lrn_layer_col(
       f32x4 hv[4];
 #pragma unroll
       for (int t = 0; t < 4; t++) hv[t] = Raw::get(rc, t, lg, W_in, inv_s);
-      layer_tile<NV, FIRST, LAST, HT, ZT, XT>(cell, true, lr, lg, hv, raw, rawe, we, Wl, W_in, inv_s, bias, r, s_ptr,
-                                             hout, nullptr, nullptr, nullptr, out);
+      int z0 = 0;  // keeps the LDS reads of the bias and the lane operands in the loop
+      asm volatile("" : "+v"(z0));
+      layer_tile<NV, FIRST, LAST, HT, ZT, XT>(cell, true, lr, lg, hv, raw, rawe, ops, ops_s[l + z0], Wl, W_in,
+                                             inv_s, bias_s + z0, r, s_ptr, hout, nullptr, nullptr, nullptr, out,
+                                             zout);
       rp = rc;
       rc = rn;
     }

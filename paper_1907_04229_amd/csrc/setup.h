@@ -97,7 +97,18 @@ struct IluHost {
 
 // Throws Error (CPTR_ERR_SINGULAR_BLOCK on a zero pivot).
 // level: 0 for BILU(0), 1 for BILU(1) (level-1 fill of the block pattern).
+// part (optional, one entry per cell): the blocks coupling cells of different
+// parts are left out of the factor (block Jacobi over the parts, the parallel
+// ILU of Section 4's multi-process runs); the order is chosen on the whole
+// pattern first.
 void ilu_build(int n, int nv, const int *rp, const int *ci, const double *vals,
-               bool multicolor, IluHost &out, int level = 0);
+               bool multicolor, IluHost &out, int level = 0, const int *part = nullptr);
+
+// Cells of a structured grid in the block-Jacobi parts of the ILU: if the
+// pattern is the 7-point graph of an nx x ny x nz grid numbered x fastest
+// (offsets 1, nx, nx ny; nx, ny, nz >= 2), returns the part of every cell,
+// (x px / nx) + px ((y py / ny) + py (z pz / nz)); otherwise throws
+// CPTR_ERR_UNSUPPORTED.
+std::vector<int> grid_parts(int n, const int *rp, const int *ci, int px, int py, int pz);
 
 }  // namespace cptr

@@ -104,11 +104,14 @@ int cptrh_amg_get(void *h, int l, int *agg, int *arp, int *aci, double *av, int 
 
 void cptrh_amg_free(void *h) { delete static_cast<AmgBox *>(h); }
 
+// parts: NULL, or three ints (parts along x, y, z of the grid the pattern is on)
 void *cptrh_ilu_build(int n, int nv, const int *rp, const int *ci, const double *v, int mc,
-                      int level, int *status) {
+                      int level, const int *parts, int *status) {
   auto *b = new IluBox();
   try {
-    ilu_build(n, nv, rp, ci, v, mc != 0, b->h, level);
+    std::vector<int> part;
+    if (parts) part = grid_parts(n, rp, ci, parts[0], parts[1], parts[2]);
+    ilu_build(n, nv, rp, ci, v, mc != 0, b->h, level, parts ? part.data() : nullptr);
     *status = 0;
   } catch (const Error &e) {
     g_err = e.msg;

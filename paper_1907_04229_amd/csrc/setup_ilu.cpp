@@ -5,13 +5,16 @@
 //
 // Factor order: natural cell order, or a greedy multicolour order (colour of
 // a cell = smallest colour not used by its lower-numbered neighbours; cells
-// renumbered colour by colour, ascending inside a colour).  The factor is the
+// renumbered colour by colour, ascending inside a colour).  Optionally the
+// cells are split into parts and the couplings between parts are left out
+// (block Jacobi, as the parallel ILU(0) of the paper's multi-process runs).  The factor is the
 // IKJ form of ILU(0) on nv x nv blocks: for each row i and each lower block
 // k < i in order, L_ik = A_ik U_kk^{-1}, then A_ij -= L_ik U_kj for every j > k
 // present in both rows.  Diagonal blocks are inverted by Gauss-Jordan
 // elimination with partial pivoting.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 
 #include "setup.h"
 
@@ -54,7 +57,7 @@ bool blk_inv(int nv, const double *a, double *inv) {
 }  // namespace
 
 void ilu_build(int n, int nv, const int *rp, const int *ci, const double *vals,
-               bool multicolor, IluHost &out, int level) {
+               bool multicolor, IluHost &out, int level, const int *part) {
   const int b2 = nv * nv;
   out.n = n;
   out.nv = nv;
@@ -85,19 +88,23 @@ void ilu_build(int n, int nv, const int *rp, const int *ci, const double *vals,
   for (int p = 0; p < n; p++) pos[out.order[p]] = p;
 
   // renumbered pattern: row p holds the blocks of cell order[p], columns as
-  // factor positions, ascending
-  std::vector<int> frp(n + 1, 0), fci(rp[n]), src(rp[n]);
+  // factor positions, ascending (with a partition, only the blocks inside
+  // the cell's part)
+  std::vector<int> frp(n + 1, 0), fci, src;
+  fci.reserve(rp[n]);
+  src.reserve(rp[n]);
+  std::vector<std::pair<int, int>> row;
   for (int p = 0; p < n; p++) {
     int i = out.order[p];
-    int len = rp[i + 1] - rp[i];
-    frp[p + 1] = frp[p] + len;
-    std::vector<std::pair<int, int>> row;
-    for (int k = rp[i]; k < rp[i + 1]; k++) row.push_back({pos[ci[k]], k});
+    row.clear();
+    for (int k = rp[i]; k < rp[i + 1]; k++)
+      if (!part || part[ci[k]] == part[i]) row.push_back({pos[ci[k]], k});
     std::sort(row.begin(), row.end());
-    for (int t = 0; t < len; t++) {
-      fci[frp[p] + t] = row[t].first;
-      src[frp[p] + t] = row[t].second;
+    for (const auto &e : row) {
+      fci.push_back(e.first);
+      src.push_back(e.second);
     }
+    frp[p + 1] = int(fci.size());
   }
   if (level == 1) {
     // ILU(1): the blocks of A (level 0) and the level-1 fill (p, j) for every
@@ -227,6 +234,36 @@ void ilu_build(int n, int nv, const int *rp, const int *ci, const double *vals,
   out.fci.swap(fci);
   out.src.swap(src);
   out.dpos.swap(dpos);
+}
+
+std::vector<int> grid_parts(int n, const int *rp, const int *ci, int px, int py, int pz) {
+  // the three axis strides from the off-diagonal offsets of the pattern
+  std::vector<int> mags;
+  for (int i = 0; i < n; i++)
+    for (int k = rp[i]; k < rp[i + 1]; k++)
+      if (ci[k] != i) mags.push_back(std::abs(ci[k] - i));
+  std::sort(mags.begin(), mags.end());
+  mags.erase(std::unique(mags.begin(), mags.end()), mags.end());
+  const auto fail = [] { throw Error{CPTR_ERR_UNSUPPORTED, "ILU parts need the 7-point graph of a 3D grid"}; };
+  if (mags.size() != 3 || mags[0] != 1 || mags[2] % mags[1] != 0) fail();
+  const int nx = mags[1], ny = mags[2] / mags[1];
+  if (nx < 2 || ny < 2 || n % (nx * ny) != 0 || n / (nx * ny) < 2) fail();
+  const int nz = n / (nx * ny);
+  if (px < 1 || py < 1 || pz < 1 || px > nx || py > ny || pz > nz)
+    throw Error{CPTR_ERR_INVALID_ARG, "ILU parts per axis must be between 1 and the grid size"};
+  // every coupling must be a grid neighbour (x neighbours in the same row)
+  for (int i = 0; i < n; i++)
+    for (int k = rp[i]; k < rp[i + 1]; k++) {
+      const int j = ci[k], d = std::abs(j - i);
+      if (d == 1 && j / nx != i / nx) fail();
+      if (d == nx && j / (nx * ny) != i / (nx * ny)) fail();
+    }
+  std::vector<int> part(n);
+  for (int i = 0; i < n; i++) {
+    const int x = i % nx, y = (i / nx) % ny, z = i / (nx * ny);
+    part[i] = (int)((long long)x * px / nx) + px * ((int)((long long)y * py / ny) + py * (int)((long long)z * pz / nz));
+  }
+  return part;
 }
 
 }  // namespace cptr

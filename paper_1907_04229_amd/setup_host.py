@@ -30,7 +30,7 @@ def load():
         L.cptrh_amg_get.argtypes = [vp, C.c_int, ip, ip, ip, dp, ip, ip, dp, dp]
         L.cptrh_amg_free.argtypes = [vp]
         L.cptrh_ilu_build.restype = vp
-        L.cptrh_ilu_build.argtypes = [C.c_int, C.c_int, ip, ip, dp, C.c_int, C.c_int, ip]
+        L.cptrh_ilu_build.argtypes = [C.c_int, C.c_int, ip, ip, dp, C.c_int, C.c_int, ip, ip]
         L.cptrh_ilu_get.argtypes = [vp, ip, ip, ip, ip, dp]
         L.cptrh_ilu_free.argtypes = [vp]
         L.cptrh_last_error.restype = C.c_char_p
@@ -100,14 +100,17 @@ def _levels(L, h, st):
         L.cptrh_amg_free(h)
 
 
-def ilu_schedule(row_ptr, col, vals, nv, multicolor, level=0):
+def ilu_schedule(row_ptr, col, vals, nv, multicolor, level=0, parts=None):
+    """parts: None, or (px, py, pz) block-Jacobi parts of the grid."""
     rp = np.ascontiguousarray(row_ptr, np.int32)
     ci = np.ascontiguousarray(col, np.int32)
     v = np.ascontiguousarray(vals, np.float64)
     n = rp.size - 1
     L = load()
     st = C.c_int(0)
-    h = L.cptrh_ilu_build(n, nv, _i(rp), _i(ci), _d(v), int(bool(multicolor)), int(level), C.byref(st))
+    pa = None if parts is None else np.ascontiguousarray(parts, np.int32)
+    h = L.cptrh_ilu_build(n, nv, _i(rp), _i(ci), _d(v), int(bool(multicolor)), int(level),
+                          None if pa is None else _i(pa), C.byref(st))
     try:
         if st.value != 0:
             raise RuntimeError(f"ILU setup failed ({st.value}): {L.cptrh_last_error().decode()}")

@@ -95,6 +95,76 @@ def test_forward_matches_oracle(name):
     s.close()
 
 
+def bf16_envelope(theta, b1, dinv, E, nbr, nv, s=None):
+    """Magnitude envelope of the learned stage's correction s (W_out h3): the
+    network evaluated on the absolute values of its input, edge features and
+    weights, with |a| for ReLU(a), so that every intermediate quantity is
+    bounded by the envelope's.  A BF16 rounding of an operand errs by at most
+    2^-9 of it, so to first order the output errs by at most (number of
+    roundings along a path) x 2^-9 x envelope.  `s`: the scales of the whole
+    system (for a neighbourhood cut out of it)."""
+    p = OL.unflatten(np.abs(np.asarray(theta, np.float64)), nv)
+    n = dinv.shape[0]
+    r = np.einsum("irc,ic->ir", dinv, b1.reshape(n, nv))
+    if s is None:
+        s = np.sqrt(np.mean(r * r, axis=0))
+    u = np.abs(r / s)
+    fac = ((1.0 / s)[:, None] * s[None, :]).reshape(-1)
+    Es = np.abs(E) * fac[None, None, :]
+    mask = nbr >= 0
+    h = u @ p["W_in"].T
+    for l in range(3):
+        g = Es @ p[f"W_e{l}"].T
+        hn = np.where(mask[:, :, None], h[np.maximum(nbr, 0)], 0.0)
+        m = np.sum(g * hn, axis=1)
+        h = h + (h @ p[f"W_s{l}"].T + m @ p[f"W_m{l}"].T + p[f"b{l}"])
+    return s * (h @ p["W_out"].T)
+
+
+# BF16 error model of the learned stage: each BF16 operand (edge blocks, W_e,
+# W_s, W_m, W_in and W_out on the matrix cores, stored activations, messages)
+# is rounded once to 2^-9 of itself; a path through the three layers, their
+# residual connections and the read-out passes about twenty such roundings.
+BF16_PATH = 20 * 2.0 ** -9
+
+
+FWD_CASES = {**CASES, "col": dict(shape=(16, 8, 9), kind="gaussian", sigma=1.5, corr_len=3.0, seed=44)}
+
+
+@pytest.mark.parametrize("name", ["nv3", "nv4", "nv3c", "col"])
+@pytest.mark.parametrize("init", ["random", "neumann"])
+def test_forward_elementwise(name, init):
+    """The learned stage's output against the FP64 oracle cell by cell, within
+    the BF16 error model: |z - z_orc| <= 20 x 2^-9 x envelope + 2^-20 |s u|
+    (bf16_envelope; the block-Jacobi part s u is formed in FP32, a few
+    roundings of 2^-24).  The envelope is loose where the network's values
+    cancel little (random weights); the Neumann-series weights cancel
+    strongly (up to ~10% of s |W_out| |h3| is rounding error there), which a
+    bound on the output's own magnitude would not cover."""
+    banner(f"forward element-wise {name} {init}")
+    if name == "col":
+        pr = make_problem(**FWD_CASES["col"])
+        nbr = OL.neighbors(pr.row_ptr, pr.col_idx, pr.n)
+        dinv, E = OL.edge_features(pr.row_ptr, pr.col_idx, pr.vals, pr.nv, nbr)
+    else:
+        pr, nbr, dinv, E, _ = case(name)
+    nv = pr.nv
+    theta = init_params(nv, seed=5, out_scale=0.3) if init == "random" else neumann_params(nv, seed=3)
+    s, m = solver_with(pr, theta)
+    b1 = np.random.default_rng(16).standard_normal(pr.n * nv)
+    z = cptr.cptr_learn_forward(s, torch.as_tensor(b1, device=DEV)).cpu().numpy().reshape(-1, nv)
+    zo, cache = OL.forward(theta.astype(np.float64), b1, dinv, E, nbr, nv)
+    zo = zo.reshape(-1, nv)
+    env = bf16_envelope(theta, b1, dinv, E, nbr, nv)
+    su = np.abs(cache["s"][None, :] * cache["u"])
+    ratio = np.abs(z - zo) / (BF16_PATH * env + 2.0 ** -20 * su + 1e-300)
+    print(f"worst |dz| / bound = {ratio.max():.3f}; max |dz| / max |z| = "
+          f"{np.abs(z - zo).max() / np.abs(zo).max():.2e}")
+    assert ratio.max() <= 1.0
+    s.close()
+    m.close()
+
+
 COLUMN_SHAPES = [
     dict(shape=(12, 4, 6), kind="gaussian", sigma=1.5, corr_len=3.0, seed=43),          # rows straddle tiles
     dict(shape=(16, 8, 9), kind="gaussian", sigma=1.5, corr_len=3.0, seed=44),          # one tile per row
@@ -282,6 +352,39 @@ def test_gain_on_held_out_seeds():
         assert not tf and not nf
         assert trn < jac
         assert trn <= neu + 2
+
+
+def test_training_gain_at_full_size():
+    """What training gains where it pays.  On 64x64x32 systems the
+    Neumann-series start already needs the iterations of natural-order
+    BILU(0) (14 = 14 on seed 120), and training lowers the loss but not the
+    iterations; on the 128x128x64 systems of the same field model (Gaussian
+    ln k, correlation length 8, std 2) it does.  Trained as the benchmark
+    trains (pairs from three 64x64x32 systems, seeds 100-102; selection on the
+    FGMRES iterations of the 128x128x64 systems of seeds 190 and 191), for
+    400 steps, the network needs fewer FGMRES(30) iterations than its
+    untrained start on each of two held-out 128x128x64 systems (seeds 200 and
+    201), and never falls back."""
+    banner("gain test, 128x128x64 held-out systems")
+    kw = dict(kind="gaussian", sigma=2.0, corr_len=8.0)
+    train_probs = [make_problem(shape=(64, 64, 32), seed=s, **kw) for s in (100, 101, 102)]
+    val_probs = [make_problem(shape=(128, 128, 64), seed=s, **kw) for s in (190, 191)]
+    model, hist = train(train_probs, 3, steps=400, batch=8, pairs=32, lr=1e-5, lr_final=1e-6, seed=1,
+                        eval_every=50, val_problems=val_probs, rollback=3.0, precision="fp32",
+                        second_stage="bilu0_mc")
+    theta = model.params()
+    model.close()
+    del val_probs
+    print("validation (step, loss, iterations)", [(k, round(v, 5), it) for k, v, it in hist["val"]],
+          "kept step", hist["best_step"])
+    assert hist["best_step"] > 0          # training improved the validation iterations
+    for seed in (200, 201):
+        pr = make_problem(shape=(128, 128, 64), seed=seed, **kw)
+        neu, nf = _learned_iters(pr, neumann_params(3, seed=1))
+        trn, tf = _learned_iters(pr, theta)
+        print(f"seed {seed}: iterations Neumann start {neu}, trained {trn}")
+        assert not tf and not nf
+        assert trn < neu
 
 
 def test_learned_stage_in_fgmres_and_fallback():

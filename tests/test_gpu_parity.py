@@ -8,13 +8,18 @@ Tolerances (relative, max-norm over the vector unless stated):
       that amplification at up to ~1e6 on the three-phase case, i.e. ~2e-10 in FP64)
   FP32 first stage                         <= 1e-5   (V-cycles and scalar products
       in FP32, coarsest level FP64; observed ~2.5e-7)
-  FP32 full application (2-norm)           <= 1e-2 multicolour, <= 0.2 natural
-      order (b1 = v - A x1 cancels in FP32 and the ILU solves amplify it;
-      observed 1.4e-4 and 4.3e-2 on the three-phase case)
+  FP32 full application (2-norm)           <= 1e-2 multicolour (b1 = v - A x1
+      cancels in FP32 and the ILU solves amplify it)
+  FP32 second stage alone                  element by element within a first-
+      order bound of FP32 rounding in the triangular solves (computed from the
+      oracle's dense factors)
+  FP32 two-stage residual                  element by element within (K + 2) u
+      sum |a x| (FP32 sums) or u |b1| (FP64 sums)
   FGMRES, FP64                             iterations within +-1 and
       ||x_gpu - x_orc|| / ||x_orc|| <= 1e-8 at rtol 1e-6
   FGMRES, FP32 preconditioner              converged with the FP64 true residual
-      <= rtol ||b||; the error against the oracle is reported
+      <= rtol ||b||; the error against the oracle is reported; at rtol 1e-12
+      the solution within 1e-8 of the oracle's
   integer setup results                    bit-identical
 """
 import numpy as np
@@ -256,7 +261,10 @@ def test_apply_fp32(name, second):
     e2 = np.linalg.norm(z.cpu().numpy() - zo) / np.linalg.norm(zo)
     print(f"fp32 first stage max rel err {e1:.2e}, application 2-norm rel err {e2:.2e}")
     assert e1 <= 1e-5
-    assert e2 <= (1e-2 if second == "bilu0_mc" else 0.2)
+    if second == "bilu0_mc":
+        assert e2 <= 1e-2
+    # (the natural-order FP32 second stage is checked element by element
+    # against a rounding bound in test_bilu0_fp32_second_stage_elementwise)
     s.close()
 
 
@@ -475,6 +483,114 @@ def test_bilu1_fp64(name, second):
     s.close()
 
 
+def _grid_part(pr, parts):
+    nx, ny, nz = pr.shape
+    i = np.arange(pr.n)
+    x, y, z = i % nx, (i // nx) % ny, i // (nx * ny)
+    px, py, pz = parts
+    return (x * px // nx + px * (y * py // ny + py * (z * pz // nz))).astype(np.int32)
+
+
+@pytest.mark.parametrize("name", ["ragged", "three", "small"])
+@pytest.mark.parametrize("second", ["bilu0", "bilu0_mc"])
+@pytest.mark.parametrize("parts", [(2, 2, 1), (2, 1, 2)])
+def test_partitioned_bilu0_fp64(name, second, parts):
+    """BILU(0) over block-Jacobi grid parts (ilu_part_*): level schedule
+    bit-exact against the oracle with the same partition, FP64 application
+    within 1e-9 and FGMRES within +-1 iterations and 1e-8."""
+    banner(f"partitioned bilu0 {name} {second} {parts}")
+    pr = prob(name)
+    part = _grid_part(pr, parts)
+    s = solver(pr, precision="fp64", second_stage=second, ilu_parts=parts, amg_coarse_size=16)
+    o = O.Oracle.from_problem(pr, first="cptr", second=second, ilu_part=part, coarse_size=16)
+    ll, lu, col = cptr.cptr_get_ilu_schedule(s.h, pr.n)
+    f = o.ilu()
+    cells = f["perm"]
+    assert np.array_equal(ll[cells], f["lev_lower"]) and np.array_equal(lu[cells], f["lev_upper"])
+    v = np.random.default_rng(51).standard_normal(pr.n * pr.nv)
+    z = s.apply(dev(v))
+    torch.cuda.synchronize()
+    assert relerr(z.cpu().numpy(), o.apply(v)) <= 1e-9
+    s.close()
+    s = solver(pr, precision="fp64", second_stage=second, ilu_parts=parts)
+    o = O.Oracle.from_problem(pr, first="cptr", second=second, ilu_part=part)
+    xg, info = s.solve(dev(pr.b), restart=30, rtol=1e-6)
+    xo, io = o.fgmres(pr.b, m=30, rtol=1e-6)
+    err = np.linalg.norm(xg.cpu().numpy() - xo) / np.linalg.norm(xo)
+    print(f"iters gpu {info['iters']} oracle {io['iters']} err {err:.2e}")
+    assert info["converged"] and abs(info["iters"] - io["iters"]) <= 1 and err <= 1e-8
+    s.close()
+
+
+def test_partitions_need_a_grid():
+    banner("ILU parts on a chain")
+    with pytest.raises(cptr.CptrError) as e:
+        solver(prob("chain"), precision="fp64", second_stage="bilu0", ilu_parts=(2, 1, 1))
+    assert e.value.code == -2
+
+
+def _dense_factors(f, nv, n):
+    """Unit-lower L and upper U (diagonal blocks = inverses of dinv) of the
+    oracle's block factor, in factor order."""
+    rp, ci = f["rp"], f["ci"]
+    L = np.eye(n * nv)
+    U = np.zeros((n * nv, n * nv))
+    bl = f["lu"].reshape(-1, nv, nv)
+    di = f["dinv"].reshape(-1, nv, nv)
+    for i in range(n):
+        for k in range(rp[i], rp[i + 1]):
+            j = ci[k]
+            blk = slice(i * nv, (i + 1) * nv), slice(j * nv, (j + 1) * nv)
+            if j < i:
+                L[blk] = bl[k]
+            elif j > i:
+                U[blk] = bl[k]
+        U[i * nv:(i + 1) * nv, i * nv:(i + 1) * nv] = np.linalg.inv(di[i])
+    return L, U
+
+
+@pytest.mark.parametrize("name", ["ragged", "three", "small"])
+@pytest.mark.parametrize("second", ["bilu0", "bilu0_mc"])
+@pytest.mark.parametrize("accum", [0, 1])
+def test_bilu0_fp32_second_stage_elementwise(name, second, accum):
+    """The FP32 BILU(0) second stage alone (no first stage: z = BILU0^{-1} v)
+    against the oracle's FP64 one, element by element, within a first-order
+    bound of FP32 rounding.  A triangular solve computes the exact solution
+    of (T + dT) x = b with |dT| <= g |T|, g = (k + 2) u (k the terms of the
+    longest row, u = 2^-24), so |dx| <= g |T^{-1}| |T| |x|; rounding the FP64
+    factors and v to FP32 adds u |T| and u |v|.  Bound on z = U^{-1} L^{-1} v:
+    |U^{-1}| (g |U| |z| + |dy|) + u |U^{-1}| |L^{-1}| |v|, |dy| = g |L^{-1}| |L| |y|,
+    with g = (k + 4) u; asserted with a factor 2 for the first-order terms.
+    ilu_accum_fp64 sums the rows in FP64: the same bound holds."""
+    banner(f"fp32 bilu0 second stage {name} {second} accum64={accum}")
+    pr = prob(name)
+    n, nv = pr.n, pr.nv
+    s = solver(pr, precision="fp32", first_stage="none", second_stage=second, ilu_accum_fp64=accum)
+    o = O.Oracle.from_problem(pr, first="none", second=second)
+    v = np.random.default_rng(47).standard_normal(n * nv)
+    z = s.apply(dev(v))
+    torch.cuda.synchronize()
+    z = z.cpu().numpy()
+    zo = o.apply(v)
+    f = o.ilu()
+    L, U = _dense_factors(f, nv, n)
+    idx = (f["perm"][:, None] * nv + np.arange(nv)[None, :]).reshape(-1)   # factor unknown -> unknown
+    vb = v[idx]
+    y = np.linalg.solve(L, vb)
+    zf = np.linalg.solve(U, y)
+    assert np.allclose(zf, zo[idx], rtol=1e-8, atol=1e-10 * np.abs(zf).max())
+    k = int(np.diff(f["rp"]).max()) * nv
+    u = 2.0 ** -24
+    g = (k + 4) * u
+    Li, Ui = np.abs(np.linalg.inv(L)), np.abs(np.linalg.inv(U))
+    dy = g * Li @ (np.abs(L) @ np.abs(y))
+    bound = Ui @ (g * np.abs(U) @ np.abs(zf) + dy) + u * Ui @ (Li @ np.abs(vb))
+    ratio = np.abs(z[idx] - zf) / (2 * bound + 1e-300)
+    print(f"worst |dz| / (2 bound) = {ratio.max():.3f}, max rel err {relerr(z, zo):.2e}")
+    assert ratio.max() <= 1.0
+    s.close()
+
+
 # ---------------------------------------------------------------- FGMRES
 @pytest.mark.parametrize("name", ["ragged", "three", "small", "chain"])
 @pytest.mark.parametrize("first,second", [("cptr", "bilu0"), ("cptr", "bilu0_mc"),
@@ -482,20 +598,37 @@ def test_bilu1_fp64(name, second):
                                           ("cptr_uamg", "bilu0_mc"), ("cptr_upper", "bilu0")])
 @pytest.mark.parametrize("graph", [1, 0])
 def test_fgmres_fp64_matches_oracle(name, first, second, graph):
+    """Iterations within +-1 and solution within 1e-8 of the oracle at rtol
+    1e-6.  That bar presumes the iterate at rtol 1e-6 moves by much less than
+    1e-8 under rounding-level changes.  The upper block-triangular stage
+    converges slowly on these systems (12 iterations on the 10x10x5 case,
+    against 2 for the full block stage), and there the oracle's own iterate
+    moves by up to 5e-8 when b is perturbed by 1e-15 relative (the Jacobians
+    have condition numbers near 1e12; the same holds with the unknowns in
+    scaled units).  For that stage the solution bar is the larger of 1e-8 and
+    ten times the oracle's own movement under three such perturbations (the
+    GPU's differences are larger than a perturbation of b: classical instead
+    of modified Gram-Schmidt, an explicit coarsest inverse)."""
     banner(f"fgmres fp64 {name} {first}+{second} graph={graph}")
     pr = prob(name)
     s = solver(pr, precision="fp64", first_stage=first, second_stage=second, use_graph=graph)
     o = O.Oracle.from_problem(pr, first=first, second=second)
+    rng = np.random.default_rng(43)
     for rhs in (pr.b, pr.b_star):
         x, info = s.solve(dev(rhs), restart=30, rtol=1e-6)
         xo, io = o.fgmres(rhs, m=30, rtol=1e-6)
         xg = x.cpu().numpy()
         err = np.linalg.norm(xg - xo) / np.linalg.norm(xo)
+        bar = 1e-8
+        if first == "cptr_upper":
+            self_move = max(np.linalg.norm(o.fgmres(rhs * (1 + 1e-15 * rng.standard_normal(rhs.size)), m=30,
+                                                    rtol=1e-6)[0] - xo) / np.linalg.norm(xo) for _ in range(3))
+            bar = max(bar, 10 * self_move)
         print(f"iters gpu {info['iters']} oracle {io['iters']} relres {info['relres_true']:.2e} "
-              f"err {err:.2e}")
+              f"err {err:.2e} (bar {bar:.1e})")
         assert info["converged"] and abs(info["iters"] - io["iters"]) <= 1
         assert info["relres_true"] <= 1e-6
-        assert err <= 1e-8
+        assert err <= bar
     s.close()
 
 
@@ -516,6 +649,25 @@ def test_fgmres_fp32_converges(name, second, first):
     print(f"fp32: iters {info['iters']} (oracle fp64 {io['iters']}), true relres {relres:.2e}, "
           f"error vs oracle {err:.2e}")
     assert info["converged"] and relres <= 1.0001e-6
+    s.close()
+
+
+@pytest.mark.parametrize("name", ["ragged", "small"])
+@pytest.mark.parametrize("second", ["bilu0", "bilu0_mc"])
+def test_fgmres_fp32_tight_tolerance_solution_error(name, second):
+    """The solution-error bar with the FP32 preconditioner: at rtol 1e-12
+    FGMRES (FP64 Arnoldi and true residual) reaches the FP64 oracle's
+    rtol-1e-12 solution to <= 1e-8; the FP32 preconditioner changes the
+    iterations, not the solution FGMRES converges to."""
+    banner(f"fgmres fp32 rtol 1e-12 {name} {second}")
+    pr = prob(name)
+    s = solver(pr, precision="fp32", second_stage=second, resid_fp64=1)
+    o = O.Oracle.from_problem(pr, first="cptr", second=second)
+    x, info = s.solve(dev(pr.b), restart=30, rtol=1e-12, maxit=600)
+    xo, io = o.fgmres(pr.b, m=30, rtol=1e-12)
+    err = np.linalg.norm(x.cpu().numpy() - xo) / np.linalg.norm(xo)
+    print(f"iters fp32 {info['iters']} oracle fp64 {io['iters']} err {err:.2e}")
+    assert info["converged"] and io["converged"] and err <= 1e-8
     s.close()
 
 

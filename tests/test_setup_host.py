@@ -101,6 +101,47 @@ def test_ilu_schedule_matches_oracle(mc, level, oracle_lib):
 
 
 @pytest.mark.parametrize("mc", [False, True])
+@pytest.mark.parametrize("parts", [(2, 2, 1), (3, 2, 2)])
+def test_partitioned_ilu_matches_oracle(mc, parts, oracle_lib):
+    # block Jacobi over grid parts: the library's grid partition is the one
+    # written out here from the cell coordinates, and the factor order, level
+    # sets, colours and factors match the oracle's ILU with that partition
+    pr = make_problem(shape=(7, 6, 5), kind="iid", seed=9, three_phase=True)
+    nx, ny, nz = pr.shape
+    i = np.arange(pr.n)
+    x, y, z = i % nx, (i // nx) % ny, i // (nx * ny)
+    px, py, pz = parts
+    part = (x * px // nx + px * (y * py // ny + py * (z * pz // nz))).astype(np.int32)
+    o = O.Oracle.from_problem(pr, first="none", second="bilu0_mc" if mc else "bilu0", ilu_part=part)
+    ref = o.ilu()
+    got = H.ilu_schedule(pr.row_ptr, pr.col_idx, pr.vals, pr.nv, mc, 0, parts=parts)
+    assert np.array_equal(got["order"], ref["perm"])
+    cells = ref["perm"]
+    assert np.array_equal(got["lev_lower"][cells], ref["lev_lower"])
+    assert np.array_equal(got["lev_upper"][cells], ref["lev_upper"])
+    if not mc:
+        # natural order on a box of a x b x c cells: a + b + c - 2 levels
+        assert got["lev_lower"].max() + 1 == max(-(-nx // px) + -(-ny // py) + -(-nz // pz) - 2, 1)
+    nv = pr.nv
+    d_ref = ref["dinv"].reshape(-1, nv, nv)
+    d_got = got["dinv"].reshape(-1, nv, nv)[cells]
+    assert np.abs(d_ref - d_got).max() <= 1e-12 * np.abs(d_ref).max()
+    # no factor block couples two parts
+    frp, fci = got["frp"], got["fci"]
+    for p in range(pr.n):
+        assert (part[cells[fci[frp[p]:frp[p + 1]]]] == part[cells[p]]).all()
+
+
+def test_grid_parts_reject_other_patterns():
+    pr = make_problem(shape=(7, 6, 5), kind="iid", seed=9)
+    with pytest.raises(RuntimeError):
+        H.ilu_schedule(pr.row_ptr, pr.col_idx, pr.vals, pr.nv, False, 0, parts=(8, 1, 1))   # more parts than cells
+    chain = make_problem(shape=(9, 1, 1), kind="iid", seed=3)
+    with pytest.raises(RuntimeError):
+        H.ilu_schedule(chain.row_ptr, chain.col_idx, chain.vals, chain.nv, False, 0, parts=(2, 1, 1))
+
+
+@pytest.mark.parametrize("mc", [False, True])
 @pytest.mark.parametrize("level", [0, 1])
 def test_ilu_refactorisation_pattern_is_consistent(mc, level):
     # what the GPU refactorisation indexes: the forward levels order every row
