@@ -281,6 +281,28 @@ int cptr_vcycle(cptr_handle *h, int which, const double *b, double *x, void *str
 int fgmres_solve(cptr_handle *h, const double *b, double *x, const cptr_solve_opts *so,
                  cptr_solve_info *info, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * fgmres_solve with its Krylov workspace -- basis, preconditioned vectors,
+ * Hessenberg and Givens data, reduction partials, step state -- taken from a
+ * device array of the library instead of memory the handle allocates on its
+ * first solve.  The array holds CPTR_STATIC_WORKSPACE_BYTES (256 MiB) on every
+ * GPU the library runs on and is kept until the process ends.  The call
+ * allocates nothing: no hipMalloc, hipFree or hipHostMalloc, no graph capture
+ * (every Arnoldi step is launched directly, the per-step results are copied
+ * to the calling thread's stack); the preconditioner's memory is the
+ * handle's, allocated by cptr_setup.  The workspace needs about
+ * (m+1) N 8 + m N zb + 2 N 8 bytes plus 70 KB for restart m, N = n nv
+ * unknowns, zb = 4 (FP32 preconditioner) or 8 (FP64); a larger need returns
+ * CPTR_ERR_INVALID_ARG before anything is launched.  Every call on one GPU
+ * uses the same array and leaves its contents there: calls that overlap on
+ * one GPU (other threads, other streams, other handles) race and must be
+ * serialised by the caller.  Arguments, results, blocking and the solve
+ * itself as fgmres_solve; cptr_krylov_vector does not see its basis. */
+#define CPTR_STATIC_WORKSPACE_BYTES (256u << 20)
+int fgmres_solve_static(cptr_handle *h, const double *b, double *x, const cptr_solve_opts *so,
+                        cptr_solve_info *info, void *stream);
+
 /* y = A x with the matrix of h (Section 3, the linearised system), using the
  * handle's sliced device copy of A (the product of every FGMRES step).
  * x, y: device FP64 [n*nv], must not alias.  Asynchronous on `stream`. */

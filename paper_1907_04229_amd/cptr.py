@@ -89,6 +89,7 @@ def load():
         L.cptr_stage_residual.argtypes = [vp, vp, vp, vp]
         L.cptr_vcycle.argtypes = [vp, ip, vp, vp, vp]
         L.fgmres_solve.argtypes = [vp, vp, vp, C.POINTER(SolveOpts), C.POINTER(SolveInfo), vp]
+        L.fgmres_solve_static.argtypes = [vp, vp, vp, C.POINTER(SolveOpts), C.POINTER(SolveInfo), vp]
         L.cptr_krylov_vector.argtypes = [vp, ip, vp, vp]
         L.cptr_matvec.argtypes = [vp, vp, vp, vp]
         L.cptr_update_values.argtypes = [vp, vp, vp, vp]
@@ -218,6 +219,19 @@ def fgmres_solve(h, b, x, restart=30, rtol=1e-6, maxit=1000, nonzero_guess=False
     info = SolveInfo()
     rc = load().fgmres_solve(h, _ptr(b, torch.float64), _ptr(x, torch.float64), C.byref(so),
                              C.byref(info), _stream(stream))
+    _check(rc, allow=(CPTR_OK, CPTR_NOT_CONVERGED))
+    return dict(iters=info.iters, restarts=info.restarts, converged=bool(info.converged),
+                relres_est=info.relres_est, relres_true=info.relres_true, solve_ms=info.solve_ms,
+                fell_back=bool(info.fell_back))
+
+
+def fgmres_solve_static(h, b, x, restart=30, rtol=1e-6, maxit=1000, nonzero_guess=False, stream=None):
+    """fgmres_solve with the library's static Krylov workspace (allocates nothing)."""
+    import torch
+    so = SolveOpts(restart, rtol, maxit, int(bool(nonzero_guess)))
+    info = SolveInfo()
+    rc = load().fgmres_solve_static(h, _ptr(b, torch.float64), _ptr(x, torch.float64), C.byref(so),
+                                    C.byref(info), _stream(stream))
     _check(rc, allow=(CPTR_OK, CPTR_NOT_CONVERGED))
     return dict(iters=info.iters, restarts=info.restarts, converged=bool(info.converged),
                 relres_est=info.relres_est, relres_true=info.relres_true, solve_ms=info.solve_ms,

@@ -20,6 +20,7 @@
 #include <cmath>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1493,8 +1494,8 @@ static void spmv_slot(cptr_handle *h, hipStream_t st, const ApplySlots *sl, doub
   else launch_spmv<4, ZT>(h, st, nullptr, sl, nullptr, y);
 }
 
-// Krylov workspace of one solve, carved from one allocation of the handle's
-// (made on first use and kept)
+// Krylov workspace of one solve: the handle's own (allocated on first use and
+// kept) or carved from the library's static device array (fgmres_solve_static)
 struct Kws {
   double *V = nullptr;  // (m+1) x N basis
   void *Z = nullptr;    // m x N preconditioned vectors (FP32 or FP64)
@@ -1879,6 +1880,34 @@ static void ensure_learned_data(cptr_handle *h) {
 
 }  // namespace cptr
 
+// Krylov workspace of fgmres_solve_static: one array per GPU, loaded with the
+// library's code object and held until the process ends.  Host code uses only
+// the device address returned for the current device by scratch_ptr(), never
+// the name of the array.
+static __device__ __align__(256) unsigned char scratch[CPTR_STATIC_WORKSPACE_BYTES];
+
+namespace cptr {
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[kMaxDevices] = {};
+
+// device address of `scratch` on the current device, looked up once per device
+static void *scratch_ptr() {
+  int dev = -1;
+  CPTR_HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) throw Error{CPTR_ERR_UNSUPPORTED, "device index beyond 63"};
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      throw Error{CPTR_ERR_HIP, std::string("hipGetSymbolAddress of the static workspace: ") + hipGetErrorString(e)};
+    g_scratch_ptr[dev] = p;
+  }
+  return g_scratch_ptr[dev];
+}
+}  // namespace cptr
+
 using namespace cptr;
 
 extern "C" {
@@ -2041,6 +2070,39 @@ int fgmres_solve(cptr_handle *h, const double *b, double *x, const cptr_solve_op
     return fail(e);
   } catch (...) {
     return fail(Error{CPTR_ERR_HIP, "unexpected failure in fgmres_solve"});
+  }
+}
+
+int fgmres_solve_static(cptr_handle *h, const double *b, double *x, const cptr_solve_opts *so_in,
+                        cptr_solve_info *info_out, void *stream) {
+  if (!h || !b || !x) return fail(Error{CPTR_ERR_INVALID_ARG, "null argument"});
+  cptr_solve_opts so{30, 1e-6, 1000, 0};
+  if (so_in) so = *so_in;
+  if (so.restart < 1 || so.restart > 64) return fail(Error{CPTR_ERR_INVALID_ARG, "restart must be in [1, 64]"});
+  if (!(so.rtol > 0.0) || so.maxit < 0) return fail(Error{CPTR_ERR_INVALID_ARG, "invalid tolerance or maxit"});
+  const size_t N = (size_t)h->op.n * h->op.nv;
+  const size_t zb = h->op.o.precision == CPTR_FP32 ? 4 : 8;
+  const size_t need = kws_layout(N, so.restart, zb, nullptr);
+  if (need > CPTR_STATIC_WORKSPACE_BYTES)
+    return fail(Error{CPTR_ERR_INVALID_ARG, "the Krylov workspace of " + std::to_string(N) + " unknowns and restart " +
+                                                std::to_string(so.restart) + " needs " + std::to_string(need) +
+                                                " bytes, more than the static workspace's " +
+                                                std::to_string((size_t)CPTR_STATIC_WORKSPACE_BYTES)});
+  cptr_solve_info info{};
+  try {
+    Kws k = kws_carve((char *)scratch_ptr(), N, so.restart, zb);
+    double host[4] = {0.0, 0.0, 0.0, 0.0};  // per-step results, copied from the device
+    k.host = host;
+    k.graphs = false;
+    int rc = h->op.o.precision == CPTR_FP32 ? fgmres_impl<float>(h, k, b, x, so, info, (hipStream_t)stream)
+                                            : fgmres_impl<double>(h, k, b, x, so, info, (hipStream_t)stream);
+    if (info_out) *info_out = info;
+    return rc;
+  } catch (const Error &e) {
+    if (info_out) *info_out = info;
+    return fail(e);
+  } catch (...) {
+    return fail(Error{CPTR_ERR_HIP, "unexpected failure in fgmres_solve_static"});
   }
 }
 
