@@ -30,8 +30,8 @@ multi-process runs), with the two-stage residual and the rows of the ILU
 solves summed in FP64.
 
 Prints one JSON line (keys below).  `--probe` runs only a short learned
-forward pass, each layer kernel once more and a plain device copy, for
-hardware-counter runs of the profiler; `--traffic FETCH_DB WRITE_DB` turns
+forward pass, each layer kernel three more times, the FP64 BSR product and
+a plain 1 GiB device copy, for hardware-counter runs of the profiler; `--traffic FETCH_DB WRITE_DB` turns
 the two counter databases of such runs into the per-kernel traffic record.
 """
 import argparse
@@ -46,8 +46,10 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "learned_layer_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "kernel_traffic_1M.json")
 LAYER_SRC = os.path.join(ROOT, "paper_1907_04229_amd", "csrc", "learned_kernels.hip")
+SPMV_SRC = os.path.join(ROOT, "paper_1907_04229_amd", "csrc", "device_kernels.hip")
+COPY_BYTES = 1 << 30  # the reference copy of the counter runs (larger than the last-level cache)
 FIRST_NAME = {"cptr": "CPTR-Block", "cptr_lower": "CPTR-BlockLower", "cptr_upper": "CPTR-BlockUpper", "cpr": "CPR",
               "cptr_bd": "CPTR-BD", "cptr_uamg": "CPTR-uAMG"}
 TRAIN_SEED0 = 100  # --train-systems N takes the seeds 100 .. 100 + N - 1
@@ -61,9 +63,17 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def layer_source_hash():
-    with open(LAYER_SRC, "rb") as f:
+def source_hash(path):
+    with open(path, "rb") as f:
         return hashlib.sha256(f.read()).hexdigest()
+
+
+def layer_source_hash():
+    return source_hash(LAYER_SRC)
+
+
+def spmv_source_hash():
+    return source_hash(SPMV_SRC)
 
 
 def layer_method_bytes(layer, nv):
@@ -81,16 +91,17 @@ def layer_method_bytes(layer, nv):
 
 
 def recorded_traffic(kernel, cells, nv):
-    """HBM bytes per launch of a learned layer kernel from the committed
-    counter runs, if they were taken on the current kernel source, cell count
-    and number of unknowns per cell."""
+    """HBM bytes per launch of a kernel (a learned layer 0, 1, 2, or "spmv",
+    the FP64 BSR product) from the committed counter runs, if they were taken
+    on the current kernel source, cell count and number of unknowns per cell."""
     try:
         with open(TRAFFIC_FILE) as f:
             recs = json.load(f)
     except (OSError, ValueError):
         return None
+    src = spmv_source_hash() if kernel == "spmv" else layer_source_hash()
     for rec in recs.get("kernels", []):
-        if (rec.get("layer") == kernel and rec.get("source_sha256") == layer_source_hash()
+        if (rec.get("layer") == kernel and rec.get("source_sha256") == src
                 and rec.get("cells") == cells and rec.get("nv") == nv):
             return rec.get("bytes_per_launch")
     return None
@@ -155,7 +166,8 @@ def spmv_roofline(pr, solver, reps=50):
     algo = pr.nnzb * (nv * nv * 8 + 4) + 4 * (n + 1) + 2 * 8 * n * nv
     gbs = algo / avg_s / 1e9
     return dict(kernel=f"k_bsr_spmv_sliced<{nv},double>", achieved=round(gbs, 1), unit="GB/s",
-                frac=round(gbs / HBM_PEAK_GBS, 4), bytes_per_launch=int(algo), avg_us=round(avg_s * 1e6, 2))
+                frac=round(gbs / HBM_PEAK_GBS, 4), bytes_per_launch=int(algo), avg_us=round(avg_s * 1e6, 2),
+                launches=reps, traffic=recorded_traffic("spmv", n, nv))
 
 
 def cpu_baseline(pr, maxit=None):
@@ -255,7 +267,8 @@ def held_out_eval(cfg, model, restart, first, log_fn):
 
 def probe(cfg_name):
     """Short run for the hardware-counter passes: one learned forward, each
-    layer kernel three more times, and a 256 MiB device copy three times."""
+    layer kernel three more times, the FP64 BSR product four times, and a
+    1 GiB device copy three times."""
     import torch
     from paper_1907_04229_amd import cptr
     from paper_1907_04229_amd.learned_init import neumann_params
@@ -269,7 +282,10 @@ def probe(cfg_name):
     for layer in (0, 1, 2):
         for _ in range(3):
             cptr.cptr_learn_rerun_layer(s, layer, z2 if layer == 2 else None)
-    a = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(b1)
+    for _ in range(4):
+        cptr.cptr_matvec(s.h, b1, y)
+    a = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
     c = torch.empty_like(a)
     for _ in range(3):
         c.copy_(a)
@@ -334,48 +350,66 @@ def trace_summary(csv_path):
     return "\n".join(out)
 
 
-def _counter_per_kernel(db, counter):
-    """Mean value of a hardware counter per dispatch, by kernel name, from a
-    rocprofv3 database (rocpd schema)."""
+def _counter_dispatches(db, counter):
+    """(grid size, value) of every dispatch, by kernel name, for one hardware
+    counter of a rocprofv3 database (rocpd schema)."""
     import sqlite3
     c = sqlite3.connect(db)
-    rows = c.execute("select kernel_name, counter_name, value from counters_collection").fetchall()
+    rows = c.execute("select kernel_name, grid_size, value from counters_collection where counter_name = ?",
+                     (counter,)).fetchall()
     acc = {}
-    for name, cn, v in rows:
-        if cn != counter:
-            continue
-        acc.setdefault(name, []).append(float(v))
-    return {k: (sum(v) / len(v), len(v)) for k, v in acc.items()}
+    for name, grid, v in rows:
+        acc.setdefault(name, []).append((int(grid), float(v)))
+    return acc
+
+
+def _mean_of(disp, name, largest_grid=False):
+    """Mean counter value per dispatch of kernel `name` (only the dispatches
+    of its largest grid with largest_grid) and the number of dispatches."""
+    d = disp[name]
+    if largest_grid:
+        g = max(x[0] for x in d)
+        d = [x for x in d if x[0] == g]
+    return sum(x[1] for x in d) / len(d), len(d)
 
 
 def record_traffic(fetch_db, write_db, cells, nv):
-    """Per-launch HBM bytes of the three learned layers from a FETCH_SIZE and a
-    WRITE_SIZE pass over `bench.py --probe`, each scaled by what the same
-    counter reads for the 256 MiB device copy of the probe (262144 KiB read
-    and written); written to profiles/learned_layer_traffic.json."""
-    fetch = _counter_per_kernel(fetch_db, "FETCH_SIZE")
-    write = _counter_per_kernel(write_db, "WRITE_SIZE")
+    """Per-launch HBM bytes of the three learned layers and the FP64 BSR
+    product from a FETCH_SIZE and a WRITE_SIZE pass over `bench.py --probe`,
+    each scaled by what the same counter reads for the probe's 1 GiB device
+    copy (its largest-grid dispatches: COPY_BYTES read and written); written
+    to TRAFFIC_FILE."""
+    fetch = _counter_dispatches(fetch_db, "FETCH_SIZE")
+    write = _counter_dispatches(write_db, "WRITE_SIZE")
     copy = [k for k in fetch if "copyBuffer" in k or "elementwise_kernel" in k]
     assert copy, "no device copy in the counter runs"
-    ck = copy[0]
-    fscale = 262144.0 / fetch[ck][0]
-    wscale = 262144.0 / write[ck][0]
+    ck = max(copy, key=lambda k: max(x[0] for x in fetch[k]))
+    kib = COPY_BYTES / 1024.0
+    fcopy, nfc = _mean_of(fetch, ck, True)
+    wcopy, nwc = _mean_of(write, ck, True)
+    fscale, wscale = kib / fcopy, kib / wcopy
+    norm = lambda k: k.replace(" ", "")  # noqa: E731
+    want = [(0, f"k_lrn_layer_first<{nv},true,false,", "layer", cells * layer_method_bytes(0, nv)),
+            (1, f"k_lrn_layer_col<{nv},false,false,", "layer", cells * layer_method_bytes(1, nv)),
+            (2, f"k_lrn_layer_col<{nv},false,true,", "layer", cells * layer_method_bytes(2, nv)),
+            ("spmv", f"k_bsr_spmv_sliced<{nv},double,", "spmv", None)]
     kernels = []
-    for layer in (0, 1, 2):
-        tag = {0: "k_lrn_layer_first<", 1: "k_lrn_layer_col<", 2: "k_lrn_layer_col<"}[layer]
-        last = {0: "false", 1: "false", 2: "true"}[layer]
-        names = [k for k in fetch if tag in k.replace(" ", "") and f"<{nv},{'true' if layer == 0 else 'false'},"
-                 f"{last}," in k.replace(" ", "")]
-        assert len(names) == 1, (layer, names)
+    for key, tag, kind, method in want:
+        names = [k for k in fetch if tag in norm(k)]
+        assert len(names) == 1, (key, names)
         kn = names[0]
-        fb = fetch[kn][0] * 1024 * fscale
-        wb = write[kn][0] * 1024 * wscale
-        kernels.append(dict(layer=layer, kernel=kn.split("(")[0], cells=cells, nv=nv,
-                            source_sha256=layer_source_hash(), fetch_bytes=int(fb), write_bytes=int(wb),
-                            bytes_per_launch=int(fb + wb), launches_fetch=fetch[kn][1],
-                            launches_write=write[kn][1],
-                            method_bytes=cells * layer_method_bytes(layer, nv)))
-    rec = dict(fetch_scale=round(fscale, 4), write_scale=round(wscale, 4), copy_kernel=ck.split("(")[0],
+        f_kib, nf = _mean_of(fetch, kn)
+        w_kib, nw = _mean_of(write, kn)
+        fb, wb = f_kib * 1024 * fscale, w_kib * 1024 * wscale
+        kernels.append(dict(layer=key, kernel=kn.split("(")[0], cells=cells, nv=nv,
+                            source_sha256=spmv_source_hash() if kind == "spmv" else layer_source_hash(),
+                            fetch_kib_raw=round(f_kib, 1), write_kib_raw=round(w_kib, 1),
+                            fetch_bytes=int(fb), write_bytes=int(wb), bytes_per_launch=int(fb + wb),
+                            launches_fetch=nf, launches_write=nw,
+                            method_bytes=method))
+    rec = dict(copy_kernel=ck.split("(")[0], copy_bytes=COPY_BYTES, copy_dispatches=[nfc, nwc],
+               copy_fetch_kib_raw=round(fcopy, 1), copy_write_kib_raw=round(wcopy, 1),
+               fetch_scale=round(fscale, 4), write_scale=round(wscale, 4),
                commands=["rocprofv3 --pmc FETCH_SIZE -d <dir> -o probe -- python3 -u bench.py --probe",
                          "rocprofv3 --pmc WRITE_SIZE -d <dir> -o probe -- python3 -u bench.py --probe"],
                kernels=kernels)

@@ -35,6 +35,48 @@ def test_traffic_record_lookup(monkeypatch, tmp_path):
     assert bench.recorded_traffic(1, 1048576, 3) is None         # the kernel changed since
 
 
+def test_spmv_traffic_record_follows_its_own_source(monkeypatch, tmp_path):
+    """The FP64 BSR product's record is keyed to the source file of its
+    kernel, not to that of the learned layers."""
+    rec = {"kernels": [dict(layer="spmv", cells=1048576, nv=3, source_sha256="b" * 64, bytes_per_launch=77)]}
+    path = tmp_path / "traffic.json"
+    path.write_text(json.dumps(rec))
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(path))
+    monkeypatch.setattr(bench, "layer_source_hash", lambda: "a" * 64)
+    monkeypatch.setattr(bench, "spmv_source_hash", lambda: "b" * 64)
+    assert bench.recorded_traffic("spmv", 1048576, 3) == 77
+    monkeypatch.setattr(bench, "spmv_source_hash", lambda: "a" * 64)
+    assert bench.recorded_traffic("spmv", 1048576, 3) is None
+
+
+def test_copy_reference_uses_the_largest_dispatches(tmp_path):
+    """The scale of a counter comes from the large reference copy alone,
+    not from small device copies of the same kernel elsewhere in the run."""
+    import sqlite3
+    for name, counter, big in (("f.db", "FETCH_SIZE", 524288.0), ("w.db", "WRITE_SIZE", 1048576.0)):
+        c = sqlite3.connect(tmp_path / name)
+        c.execute("create table counters_collection (kernel_name text, grid_size int, counter_name text, value real)")
+        rows = [("__amd_rocclr_copyBuffer", 512, counter, 3.0)] * 5 + [("__amd_rocclr_copyBuffer", 131072, counter, big)] * 3
+        for key, k in ((0, "void cptr::k_lrn_layer_first<3, true, false, short, float, float>(int)"),
+                       (1, "void cptr::k_lrn_layer_col<3, false, false, short, float, float>(int)"),
+                       (2, "void cptr::k_lrn_layer_col<3, false, true, short, double, double>(int)"),
+                       (3, "void cptr::k_bsr_spmv_sliced<3, double, true>(int)")):
+            rows.append((k, 4096, counter, 1024.0 * (key + 1)))
+        c.executemany("insert into counters_collection values (?, ?, ?, ?)", rows)
+        c.commit()
+        c.close()
+    old = bench.TRAFFIC_FILE
+    bench.TRAFFIC_FILE = str(tmp_path / "out.json")
+    try:
+        rec = bench.record_traffic(str(tmp_path / "f.db"), str(tmp_path / "w.db"), 1048576, 3)
+    finally:
+        bench.TRAFFIC_FILE = old
+    assert rec["fetch_scale"] == 2.0 and rec["write_scale"] == 1.0
+    by = {k["layer"]: k for k in rec["kernels"]}
+    assert by["spmv"]["fetch_bytes"] == 4096 * 1024 * 2 and by["spmv"]["write_bytes"] == 4096 * 1024
+    assert by[0]["bytes_per_launch"] == 1024 * 1024 * 3
+
+
 def test_layer_method_bytes():
     """The method's bytes per cell of the three learned layers: nv x nv BF16
     edge blocks (no padding), BF16 activations, FP32 r, FP64 z2."""
