@@ -189,6 +189,12 @@ typedef struct {
                             whole natural-order BILU(0) */
   int ilu_accum_fp64;    /* FP32 mode: the BILU triangular solves sum each row in FP64 (the
                             factors and vectors stay FP32 in memory; 0: FP32 sums) (0) */
+  int resetup_device;    /* cptr_update_values recomputes the AMG values on the GPU (1) or on
+                            the host (0); both give the same values bit for bit.  The GPU
+                            form keeps FP64 CSR copies of every level and of its P, R and
+                            A P on the device from cptr_setup on (some hundreds of MB per
+                            hierarchy at 10^6 cells).  CPTR_FIRST_UAMG and the decoupling
+                            operators are re-set up on the host either way (1) */
 } cptr_options;
 
 typedef struct {
@@ -327,10 +333,14 @@ int cptr_krylov_vector(const cptr_handle *h, int j, double *out, void *stream);
  * CPTR_SCHUR_ASSEMBLED, else ignored: the algebraic S~_T is formed anew from
  * A_vals).
  * The aggregates of both AMG hierarchies and the block ILU's order, pattern
- * and level schedules are kept; prolongator values, Galerkin products and the
- * coarsest inverse are recomputed on the host, the block ILU factors on the
- * GPU (the same FP64 factorisation, bit for bit), and the sliced copy of A and
- * the learned stage's edge features are rebuilt.  Blocking.  CPTR_ERR_INVALID_ARG for a missing argument,
+ * and level schedules are kept.  With resetup_device = 1 everything else is
+ * recomputed on the GPU: the prolongator values, the Galerkin products R (A P),
+ * the l1-Jacobi diagonals, the explicit inverse of the coarsest operator, the
+ * algebraic S~_T, the block ILU factors, the sliced copy of A and the learned
+ * stage's diagonal-block inverses and edge features, each entry with the
+ * operations and summation order of the host setup (results equal to the
+ * host re-setup bit for bit); with 0 (and for CPTR_FIRST_UAMG or a decoupling
+ * operator) the AMG values are recomputed on the host.  Blocking.  CPTR_ERR_INVALID_ARG for a missing argument,
  * CPTR_ERR_NONFINITE for a non-finite value, CPTR_ERR_SINGULAR_BLOCK as in
  * cptr_setup; on error the handle must be destroyed. */
 int cptr_update_values(cptr_handle *h, const double *A_vals, const double *S_vals,

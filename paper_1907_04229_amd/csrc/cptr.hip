@@ -28,6 +28,7 @@
 #include "common.h"
 #include "device_kernels.hip"
 #include "learned_kernels.hip"
+#include "setup_kernels.hip"
 
 namespace cptr {
 
@@ -189,6 +190,22 @@ struct SpOp {
     view.col = devp<int>(col);
     view.val = devp<T>(val);
   }
+  // New values on the kept pattern: CSR entry k of the operator (device row
+  // pointers rp and columns ci, as given to build) is src[k stride + off],
+  // stored as build stores it.
+  void refresh(hipStream_t st, const int *rp_d, const int *ci_d, const double *src, int stride, int off) {
+    if (fmt == kCsrv)
+      hipLaunchKernelGGL((k_rs_csr_vals<T>), dim3(nblk(nnz)), dim3(kBlock), 0, st, nnz, src, stride, off,
+                         devp<T>(val));
+    else if (fmt == kSell)
+      hipLaunchKernelGGL((k_rs_sell_vals<T>), dim3(nblk(nrows)), dim3(kBlock), 0, st, nrows, rp_d, src, stride, off,
+                         devp<int>(sptr), devp<T>(val));
+    else
+      hipLaunchKernelGGL((k_rs_dia_vals<T>), dim3(nblk(nrows)), dim3(kBlock), 0, st, nrows, rp_d, ci_d, src, stride,
+                         off, dia, devp<T>(val));
+    LAUNCH_CHECK();
+  }
+
   // algorithmic bytes of one product: stored values, indices, row/slice offsets
   double bytes() const {
     if (fmt == kDia) return double(dia.ndiag) * nrows * sizeof(T);
@@ -279,6 +296,7 @@ struct SpOp {
 };
 
 // ---------------------------------------------------------------- AMG on device
+constexpr int kSpgWaveMin = 32;   // products per row above which a Galerkin product takes a wavefront per row
 constexpr int kGsOneBlock = 2048;  // Gauss-Seidel levels up to this many rows: one workgroup per sweep
 
 template <typename T>
@@ -299,12 +317,167 @@ struct AmgDev {
   std::vector<std::vector<int>> agg;  // host copy of the aggregates (introspection)
   double bytes_per_cycle = 0.0;
 
-  void build(const AmgHost &h, int nsweeps, bool dia, int smoother_kind = CPTR_SMOOTHER_L1JACOBI) {
+  // Numeric re-setup on the device: every level in FP64 CSR with the kept
+  // patterns of its setup products (the prolongator P, R = P^T and A P), so
+  // that new level-0 values give the values of the whole hierarchy (renumeric).
+  struct Num {
+    int n = 0;
+    bool smooth = false;
+    size_t nnz = 0, pnnz = 0, rnnz = 0;
+    DevMem a_rp, a_ci, a_v, diag, ratio;                        // level operator A
+    DevMem agg, p_rp, p_ci, p_v, pslot;                         // P; pslot: P entry of each A entry
+    DevMem r_rp, r_ci, r_src, r_v;                              // R; r_src: P entry of each R entry
+    DevMem t_rp, t_ci, t_v;                                     // A P
+    bool ap_wave = false, rt_wave = false;  // A P, R (A P): many products per row, a wavefront each
+  };
+  std::vector<Num> num;   // empty: the hierarchy is re-set up on the host
+  DevMem gj, gj_f, scal;  // coarsest [A | I] of the Gauss-Jordan inverse, its column factors; omega, block maxima
+
+  void build_plan(const AmgHost &h) {
+    num.clear();
+    num.resize(h.lev.size());
+    for (size_t l = 0; l < h.lev.size(); l++) {
+      const AmgLevelHost &H = h.lev[l];
+      Num &N = num[l];
+      N.n = H.A.nr;
+      N.nnz = H.A.ci.size();
+      upload(N.a_rp, H.A.rp);
+      upload(N.a_ci, H.A.ci);
+      upload(N.a_v, H.A.v);
+      if (l + 1 == h.lev.size()) break;
+      N.smooth = H.smooth;
+      N.diag.alloc((size_t)N.n * 8);
+      if (N.smooth) N.ratio.alloc((size_t)N.n * 8);
+      N.pnnz = H.P.ci.size();
+      N.rnnz = H.R.ci.size();
+      upload(N.agg, H.agg);
+      upload(N.p_rp, H.P.rp);
+      upload(N.p_ci, H.P.ci);
+      upload(N.p_v, H.P.v);
+      upload(N.r_rp, H.R.rp);
+      upload(N.r_ci, H.R.ci);
+      upload(N.r_v, H.R.v);
+      upload(N.t_rp, H.AP.rp);
+      upload(N.t_ci, H.AP.ci);
+      N.t_v.alloc(std::max<size_t>(H.AP.ci.size(), 1) * 8);
+      {  // products per row of A P and of R (A P)
+        double fa = 0.0, fr = 0.0;
+        for (int k = 0; k < (int)N.nnz; k++) fa += H.P.rp[H.A.ci[k] + 1] - H.P.rp[H.A.ci[k]];
+        for (size_t k = 0; k < N.rnnz; k++) fr += H.AP.rp[H.R.ci[k] + 1] - H.AP.rp[H.R.ci[k]];
+        N.ap_wave = fa > kSpgWaveMin * std::max(1, N.n);
+        N.rt_wave = fr > kSpgWaveMin * std::max(1, H.R.nr);
+      }
+      if (N.smooth) {
+        std::vector<int> ps(N.nnz, -1);
+        for (int i = 0; i < N.n; i++)
+          for (int k = H.A.rp[i]; k < H.A.rp[i + 1]; k++) {
+            const int J = H.agg[H.A.ci[k]];
+            if (J < 0) continue;
+            const auto b = H.P.ci.begin() + H.P.rp[i], e = H.P.ci.begin() + H.P.rp[i + 1];
+            const auto it = std::lower_bound(b, e, J);
+            if (it == e || *it != J) throw Error{CPTR_ERR_SETUP, "prolongator pattern misses an aggregate"};
+            ps[k] = int(it - H.P.ci.begin());
+          }
+        upload(N.pslot, ps);
+        // R = P^T entry by entry, in the order of the transpose
+        std::vector<int> fill(H.R.rp.begin(), H.R.rp.end() - 1), src(N.rnnz);
+        for (int i = 0; i < N.n; i++)
+          for (int k = H.P.rp[i]; k < H.P.rp[i + 1]; k++) {
+            const int q = fill[H.P.ci[k]]++;
+            if (H.R.ci[q] != i) throw Error{CPTR_ERR_SETUP, "restriction pattern is not the transpose"};
+            src[q] = k;
+          }
+        upload(N.r_src, src);
+      }
+    }
+    const int nc = h.lev.back().A.nr;
+    gj.alloc((size_t)nc * 2 * nc * 8);
+    gj_f.alloc((size_t)nc * 8);
+    scal.alloc((1 + kDotBlocks) * 8);
+  }
+
+  // C = A B on C's kept pattern (k_rs_spgemm, or k_rs_spgemm_wave for rows of many products)
+  static void spgemm(hipStream_t st, bool wave, int nr, const DevMem &arp, const DevMem &aci, const DevMem &av,
+                     const DevMem &brp, const DevMem &bci, const DevMem &bv, const DevMem &crp, const DevMem &cci,
+                     DevMem &cv) {
+    if (nr <= 0) return;
+    if (wave)
+      hipLaunchKernelGGL(k_rs_spgemm_wave, dim3(nr), dim3(64), 0, st, devp<int>(arp), devp<int>(aci),
+                         devp<double>(av), devp<int>(brp), devp<int>(bci), devp<double>(bv), devp<int>(crp),
+                         devp<int>(cci), devp<double>(cv));
+    else
+      hipLaunchKernelGGL(k_rs_spgemm, dim3(nblk(nr)), dim3(kBlock), 0, st, nr, devp<int>(arp), devp<int>(aci),
+                         devp<double>(av), devp<int>(brp), devp<int>(bci), devp<double>(bv), devp<int>(crp),
+                         devp<int>(cci), devp<double>(cv));
+    LAUNCH_CHECK();
+  }
+
+  // New values of every level from those of level 0 (num[0].a_v), on the
+  // kept aggregates and patterns, as amg_build computes them (see the kernels
+  // of the numeric re-setup); errors are or-ed into *flag.
+  void renumeric(hipStream_t st, int *flag) {
+    const size_t L = lev.size();
+    double *omega = devp<double>(scal), *part = omega + 1;
+    for (size_t l = 0; l + 1 < L; l++) {
+      Num &N = num[l], &C = num[l + 1];
+      Level &Lv = *lev[l];
+      const bool gs = smoother == CPTR_SMOOTHER_GS;
+      hipLaunchKernelGGL((k_rs_rowabs<T>), dim3(nblk(N.n)), dim3(kBlock), 0, st, N.n, devp<int>(N.a_rp),
+                         devp<int>(N.a_ci), devp<double>(N.a_v), devp<double>(N.diag),
+                         N.smooth ? devp<double>(N.ratio) : (double *)nullptr, devp<T>(Lv.dinv),
+                         (N.smooth || gs) ? 1 : 0, flag);
+      LAUNCH_CHECK();
+      if (N.smooth) {
+        const int nb = sgrid(N.n);
+        hipLaunchKernelGGL(k_rs_max_partial, dim3(nb), dim3(kBlock), 0, st, N.n, devp<double>(N.ratio), part);
+        hipLaunchKernelGGL(k_rs_omega, dim3(1), dim3(kBlock), 0, st, nb, (const double *)part, omega);
+        hipLaunchKernelGGL(k_rs_prolong, dim3(nblk(N.n)), dim3(kBlock), 0, st, N.n, devp<int>(N.a_rp),
+                           devp<double>(N.a_v), devp<int>(N.pslot), devp<int>(N.agg), devp<double>(N.diag),
+                           (const double *)omega, devp<int>(N.p_rp), devp<int>(N.p_ci), devp<double>(N.p_v));
+        hipLaunchKernelGGL(k_rs_gather, dim3(nblk(N.rnnz)), dim3(kBlock), 0, st, N.rnnz, devp<int>(N.r_src),
+                           devp<double>(N.p_v), devp<double>(N.r_v));
+        LAUNCH_CHECK();
+      }
+      spgemm(st, N.ap_wave, N.n, N.a_rp, N.a_ci, N.a_v, N.p_rp, N.p_ci, N.p_v, N.t_rp, N.t_ci, N.t_v);
+      spgemm(st, N.rt_wave, C.n, N.r_rp, N.r_ci, N.r_v, N.t_rp, N.t_ci, N.t_v, C.a_rp, C.a_ci, C.a_v);
+      Lv.A.refresh(st, devp<int>(N.a_rp), devp<int>(N.a_ci), devp<double>(N.a_v), 1, 0);
+      if (N.smooth) {
+        Lv.P.refresh(st, devp<int>(N.p_rp), devp<int>(N.p_ci), devp<double>(N.p_v), 1, 0);
+        Lv.R.refresh(st, devp<int>(N.r_rp), devp<int>(N.r_ci), devp<double>(N.r_v), 1, 0);
+      }
+      if (gs) {
+        hipLaunchKernelGGL((k_rs_csr_vals<T>), dim3(nblk(N.nnz)), dim3(kBlock), 0, st, N.nnz,
+                           (const double *)devp<double>(N.a_v), 1, 0, devp<T>(Lv.gs_v));
+        LAUNCH_CHECK();
+      }
+    }
+    // the coarsest operator's explicit inverse
+    const Num &Q = num[L - 1];
+    const int m = Q.n;
+    double *g = devp<double>(gj), *f = devp<double>(gj_f);
+    hipLaunchKernelGGL(k_rs_gj_init, dim3(nblk(m)), dim3(kBlock), 0, st, m, devp<int>(Q.a_rp), devp<int>(Q.a_ci),
+                       devp<double>(Q.a_v), g);
+    LAUNCH_CHECK();
+    for (int c = 0; c < m; c++) {
+      hipLaunchKernelGGL(k_rs_gj_pivot, dim3(1), dim3(kGjBlock), 0, st, m, c, g, f, flag);
+      hipLaunchKernelGGL(k_rs_gj_elim, dim3(nblk((size_t)m * 2 * m)), dim3(kBlock), 0, st, m, c, g,
+                         (const double *)f);
+    }
+    LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_rs_gj_out, dim3(nblk((size_t)m * m)), dim3(kBlock), 0, st, m, (const double *)g,
+                       devp<double>(coarse_inv));
+    LAUNCH_CHECK();
+  }
+
+  void build(const AmgHost &h, int nsweeps, bool dia, int smoother_kind = CPTR_SMOOTHER_L1JACOBI,
+             bool plan = false) {
     sweeps = std::max(1, nsweeps);
     smoother = smoother_kind;
     lev.clear();
     agg.clear();
+    num.clear();
     bytes_per_cycle = 0.0;
+    if (plan) build_plan(h);
     const size_t s = sizeof(T);
     for (size_t l = 0; l < h.lev.size(); l++) {
       auto L = std::make_unique<Level>();
@@ -728,6 +901,20 @@ struct LearnedDev {
     hB.alloc((size_t)((n + 15) / 16) * 16 * kHid * 2);
   }
 
+  // New matrix values on the pattern given to build (device BSR rp, ci,
+  // vals): the diagonal-block inverses and the edge features recomputed on
+  // the GPU as build computes them; errors or-ed into *flag.
+  void refresh(hipStream_t st, const int *rp_d, const int *ci_d, const double *vals, int *flag) {
+    if (nv == 3)
+      hipLaunchKernelGGL((k_rs_learned<3>), dim3(nblk(n)), dim3(kBlock), 0, st, n, rp_d, ci_d, vals,
+                         devp<int>(nbr), devp<float>(dinv), devp<short>(E), devp<short>(Et), kEdgeRun<3>, flag);
+    else
+      hipLaunchKernelGGL((k_rs_learned<4>), dim3(nblk(n)), dim3(kBlock), 0, st, n, rp_d, ci_d, vals,
+                         devp<int>(nbr), devp<float>(dinv), devp<short>(E), devp<short>(Et), kEdgeRun<4>, flag);
+    LAUNCH_CHECK();
+    have_pass = false;
+  }
+
   void ensure_train() {
     if (train_ready) return;
     const size_t hb = (size_t)n * kHid * 4;
@@ -1089,6 +1276,7 @@ struct cptr_handle {
   int graph_m = -1;
   std::unique_ptr<cptr::LearnedDev> lrn;  // learned-stage data of this matrix
   cptr_learn_model *model = nullptr;      // attached model (not owned)
+  cptr::DevMem rs_flag, rs_work;          // numeric re-setup on the device: error bits, diag(A_pp)
 };
 
 struct cptr_learn_model {
@@ -1096,6 +1284,12 @@ struct cptr_learn_model {
 };
 
 namespace cptr {
+
+// The first stages whose numeric re-setup runs on the GPU; CPTR-uAMG and the
+// decoupling operators keep the host re-setup.
+static bool resetup_on_device(const cptr_options &o) {
+  return o.resetup_device != 0 && o.first_stage != CPTR_FIRST_UAMG && o.decoupling == 0;
+}
 
 template <typename T>
 static void build_precond(cptr_handle *h, const std::vector<int> &rp, const std::vector<int> &ci,
@@ -1247,7 +1441,8 @@ static void build_precond(cptr_handle *h, const std::vector<int> &rp, const std:
     } else {
       amg_build(pp, prm, hp, agg_p);
     }
-    P.amg_p.build(hp, o.amg_sweeps, o.scalar_dia != 0, o.amg_smoother);
+    const bool plan = resetup_on_device(o);
+    P.amg_p.build(hp, o.amg_sweeps, o.scalar_dia != 0, o.amg_smoother, plan);
     if (o.first_stage != CPTR_FIRST_CPR && o.first_stage != CPTR_FIRST_UAMG) {
       // the second hierarchy: S~_T, or A_TT for the block-diagonal stage
       AmgHost hs;
@@ -1255,7 +1450,7 @@ static void build_precond(cptr_handle *h, const std::vector<int> &rp, const std:
         amg_build(sub(o.iT, o.iT), prm_s, hs, agg_s);
       else
         amg_build(*S, prm_s, hs, agg_s);
-      P.amg_s.build(hs, o.amg_sweeps, o.scalar_dia != 0, o.amg_smoother);
+      P.amg_s.build(hs, o.amg_sweeps, o.scalar_dia != 0, o.amg_smoother, plan);
       P.have_s = true;
       if (o.first_stage != CPTR_FIRST_BD) {
         P.ApT.build(sub(o.ip, o.iT), o.scalar_dia != 0);
@@ -1910,6 +2105,86 @@ static void *scratch_ptr() {
 
 using namespace cptr;
 
+namespace cptr {
+
+// New values for every part of a preconditioner on its kept patterns, on the
+// GPU (resetup_on_device): the p/T columns, the level-0 operators of the AMG
+// hierarchies and then all their levels, the p-T couplings of the block
+// stages and the block ILU factors.
+template <typename T>
+static void refresh_precond(cptr_handle *h, Precond<T> &P, const double *A, const double *S, hipStream_t st,
+                            int *flag) {
+  const cptr_options &o = h->op.o;
+  const int n = h->op.n, nv = h->op.nv, nnzb = h->op.nnzb, b2 = nv * nv, fs = o.first_stage;
+  if (P.acol.p) {
+    hipLaunchKernelGGL((k_rs_pt_cols<T>), dim3(nblk(n)), dim3(kBlock), 0, st, n, nv, o.ip, o.iT, h->rp,
+                       devp<int>(h->sl_kptr), A, devp<T>(P.acol));
+    LAUNCH_CHECK();
+  }
+  if (fs != CPTR_FIRST_NONE) {
+    auto &N0 = P.amg_p.num.at(0);
+    hipLaunchKernelGGL(k_rs_strided, dim3(nblk(nnzb)), dim3(kBlock), 0, st, (size_t)nnzb, A, b2, o.ip * nv + o.ip,
+                       devp<double>(N0.a_v));
+    LAUNCH_CHECK();
+    if (P.have_s) {
+      auto &S0 = P.amg_s.num.at(0);
+      if (fs == CPTR_FIRST_BD || o.schur == CPTR_SCHUR_ATT) {
+        hipLaunchKernelGGL(k_rs_strided, dim3(nblk(nnzb)), dim3(kBlock), 0, st, (size_t)nnzb, A, b2,
+                           o.iT * nv + o.iT, devp<double>(S0.a_v));
+      } else if (o.schur == CPTR_SCHUR_ASSEMBLED) {
+        CPTR_HIP_TRY(hipMemcpyAsync(S0.a_v.p, S, S0.nnz * sizeof(double), hipMemcpyDeviceToDevice, st));
+      } else {
+        if (h->rs_work.bytes < (size_t)n * 8) h->rs_work.alloc((size_t)n * 8);
+        hipLaunchKernelGGL(k_rs_app, dim3(nblk(n)), dim3(kBlock), 0, st, n, nv, o.ip, h->rp, h->ci, A,
+                           devp<double>(h->rs_work), flag);
+        hipLaunchKernelGGL(k_rs_schur, dim3(nblk(n)), dim3(kBlock), 0, st, n, nv, o.ip, o.iT, h->rp, h->ci, A,
+                           (const double *)devp<double>(h->rs_work), devp<int>(S0.a_rp), devp<int>(S0.a_ci),
+                           devp<double>(S0.a_v));
+      }
+      LAUNCH_CHECK();
+    }
+    P.amg_p.renumeric(st, flag);
+    if (P.have_s) P.amg_s.renumeric(st, flag);
+    if (P.ApT.nrows) {
+      P.ApT.refresh(st, h->rp, h->ci, A, b2, o.ip * nv + o.iT);
+      P.ATp.refresh(st, h->rp, h->ci, A, b2, o.iT * nv + o.ip);
+    }
+  }
+  if (P.have_ilu) P.ilu.refactor(A, st);
+}
+
+static void update_on_device(cptr_handle *h, const double *A, const double *S, hipStream_t st) {
+  const int n = h->op.n, nv = h->op.nv;
+  const size_t nval = (size_t)h->op.nnzb * nv * nv;
+  if (!h->rs_flag.p) h->rs_flag.alloc(sizeof(int));
+  int *flag = devp<int>(h->rs_flag);
+  int hf = 0;
+  auto read_flag = [&]() {
+    CPTR_HIP_TRY(hipMemcpyAsync(&hf, flag, sizeof(int), hipMemcpyDeviceToHost, st));
+    CPTR_HIP_TRY(hipStreamSynchronize(st));
+  };
+  hipLaunchKernelGGL((k_fill<int>), dim3(1), dim3(kBlock), 0, st, flag, (size_t)1, 0);
+  hipLaunchKernelGGL(k_rs_finite, dim3(sgrid(nval)), dim3(kBlock), 0, st, nval, A, flag);
+  LAUNCH_CHECK();
+  read_flag();
+  if (hf & kRsNonfinite) throw Error{CPTR_ERR_NONFINITE, "non-finite matrix value"};
+  h->vals = A;
+  hipLaunchKernelGGL(k_rs_sliced, dim3(nblk(n)), dim3(kBlock), 0, st, n, nv * nv, h->rp, devp<int>(h->sl_kptr), A,
+                     devp<double>(h->sl_vals));
+  LAUNCH_CHECK();
+  if (auto *Pf = dynamic_cast<Precond<float> *>(h->pc.get()))
+    refresh_precond(h, *Pf, A, S, st, flag);
+  else
+    refresh_precond(h, *dynamic_cast<Precond<double> *>(h->pc.get()), A, S, st, flag);
+  if (h->lrn) h->lrn->refresh(st, h->rp, h->ci, A, flag);
+  read_flag();
+  if (hf & kRsSingular)
+    throw Error{CPTR_ERR_SINGULAR_BLOCK, "zero diagonal entry of an AMG operator or singular diagonal block"};
+  if (hf & kRsCoarse) throw Error{CPTR_ERR_SETUP, "singular coarsest AMG operator"};
+}
+
+}  // namespace cptr
+
 extern "C" {
 
 void cptr_default_options(cptr_options *o) {
@@ -1937,6 +2212,7 @@ void cptr_default_options(cptr_options *o) {
   o->ilu_level = 0;
   o->ilu_part_x = o->ilu_part_y = o->ilu_part_z = 1;
   o->ilu_accum_fp64 = 0;
+  o->resetup_device = 1;
 }
 
 int cptr_setup(cptr_handle **out, const cptr_bsr *A, const cptr_csr *S_T, const cptr_options *opt,
@@ -2140,6 +2416,20 @@ int cptr_update_values(cptr_handle *h, const double *A_vals, const double *S_val
     auto t0 = std::chrono::steady_clock::now();
     CPTR_HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
     CPTR_HIP_TRY(hipDeviceSynchronize());
+    if (resetup_on_device(h->op.o) && h->pc) {
+      update_on_device(h, A_vals, S_vals, (hipStream_t)stream);
+      if (h->graph_exec) {
+        (void)hipGraphExecDestroy(h->graph_exec);
+        (void)hipGraphDestroy(h->graph);
+        h->graph_exec = nullptr;
+        h->graph = nullptr;
+      }
+      h->graph_m = -1;
+      CPTR_HIP_TRY(hipDeviceSynchronize());
+      h->stats.setup_ms =
+          std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+      return CPTR_OK;
+    }
     const int n = h->op.n, nv = h->op.nv, nnzb = h->op.nnzb;
     std::vector<int> rp(n + 1), ci(nnzb);
     std::vector<double> vals((size_t)nnzb * nv * nv);

@@ -37,8 +37,10 @@ struct AmgLevelHost {
   HostCSR A;            // level operator
   HostCSR P;            // prolongation to this level from the next (n_l x n_{l+1})
   HostCSR R;            // restriction = P^T
+  HostCSR AP;           // pattern of the product A P (no values), kept by amg_build
   std::vector<int> agg; // aggregate of each row (empty on the coarsest level)
   double omega = 0.0;
+  bool smooth = false;  // P smoothed (else the tentative prolongator)
 };
 
 struct AmgHost {

@@ -497,6 +497,7 @@ void amg_build(const HostCSR &fine, const AmgParams &prm, AmgHost &out,
       if (na >= n) break;  // no coarsening possible
     }
     L.agg = agg;
+    L.smooth = prm.smooth_p != 0;
     if (prm.smooth_p)
       L.P = prolongator(L.A, agg, na, true, L.omega);
     else
@@ -504,6 +505,9 @@ void amg_build(const HostCSR &fine, const AmgParams &prm, AmgHost &out,
     L.R = transpose(L.P);
     HostCSR t = multiply(L.A, L.P);
     HostCSR ac = multiply(L.R, t);
+    t.v.clear();
+    t.v.shrink_to_fit();
+    L.AP = std::move(t);
     out.lev.emplace_back();
     out.lev.back().A = std::move(ac);
     theta *= 0.5;

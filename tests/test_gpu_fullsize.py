@@ -211,6 +211,45 @@ def test_learned_workload_fgmres_converges():
     print(f"solution difference {d:.2e}")
 
 
+def test_learned_workload_device_re_setup_equals_host():
+    """The numeric re-setup of the benchmark solver (learned second stage,
+    FP32 preconditioner) for new values at 1,048,576 cells: the GPU re-setup
+    equals the host re-setup bit for bit (both AMG hierarchies through their
+    V-cycles, the application with the learned stage, the forward pass), and
+    is timed against it."""
+    banner("learned 128x128x64: re-setup on the GPU and on the host")
+    import copy
+    pr = prob("learned")
+    rng = np.random.default_rng(61)
+    p2 = copy.copy(pr)
+    p2.vals = np.ascontiguousarray(pr.vals * (1.0 + 0.2 * rng.uniform(-1.0, 1.0, pr.vals.size)))
+    p2.st_vals = np.ascontiguousarray(pr.st_vals * (1.0 + 0.2 * rng.uniform(-1.0, 1.0, pr.st_vals.size)))
+    hs, ms, models = [], [], []
+    for device in (1, 0):
+        s = cptr.Solver(pr, device=DEV, precision="fp32", second_stage="learned", resetup_device=device)
+        m = cptr.LearnModel(pr.nv, neumann_params(pr.nv, seed=1))
+        m.attach(s)
+        models.append(m)
+        s.update_values(p2)
+        ms.append(cptr.cptr_get_stats(s.h)["setup_ms"])
+        hs.append(s)
+    print(f"cptr_update_values: GPU {ms[0]:.1f} ms, host {ms[1]:.1f} ms")
+    for which in (0, 1):
+        b = torch.as_tensor(rng.standard_normal(pr.n), device=DEV)
+        x0, x1 = torch.empty_like(b), torch.empty_like(b)
+        cptr.cptr_vcycle(hs[0].h, which, b, x0)
+        cptr.cptr_vcycle(hs[1].h, which, b, x1)
+        torch.cuda.synchronize()
+        assert torch.equal(x0, x1), f"V-cycle of hierarchy {which}"
+    v = dev(rng.standard_normal(pr.n * pr.nv))
+    assert torch.equal(hs[0].apply(v), hs[1].apply(v))
+    assert torch.equal(cptr.cptr_learn_forward(hs[0], v), cptr.cptr_learn_forward(hs[1], v))
+    for s in hs:
+        s.close()
+    for m in models:
+        m.close()
+
+
 # ---------------------------------------------------------------- 128x128x64 three-phase
 # Three-phase systems take plain aggregation for the S~_T hierarchy
 # (amg_smooth_p_T = 0): their S~_T has rows that are not diagonally dominant,

@@ -827,6 +827,98 @@ def test_update_values_rejects_bad_input():
     s.close()
 
 
+def _perturbed(pr, seed):
+    """The same pattern with every value of A and S~_T scaled by its own
+    factor in [0.7, 1.3] (signs kept): new values on which the kept aggregates
+    are no longer those a fresh setup would choose."""
+    import copy
+    rng = np.random.default_rng(seed)
+    p2 = copy.copy(pr)
+    p2.vals = np.ascontiguousarray(pr.vals * (1.0 + 0.3 * rng.uniform(-1.0, 1.0, pr.vals.size)))
+    p2.st_vals = np.ascontiguousarray(pr.st_vals * (1.0 + 0.3 * rng.uniform(-1.0, 1.0, pr.st_vals.size)))
+    return p2
+
+
+RESETUP_CASES = [
+    # name, first stage, S~_T, precision, smoother, extra options
+    ("three", "cptr", "assembled", "fp64", "l1jacobi", dict(amg_coarse_size=16)),
+    ("three", "cptr", "diag", "fp32", "l1jacobi", dict(amg_coarse_size=16)),
+    ("dia2", "cptr", "assembled", "fp32", "l1jacobi", dict()),
+    ("dia2", "cptr", "att", "fp64", "gs", dict(amg_coarse_size=64)),
+    ("ragged", "cptr_lower", "assembled", "fp64", "l1jacobi", dict(amg_coarse_size=8, amg_smooth_p_T=1)),
+    ("three", "cptr_upper", "assembled", "fp32", "gs", dict(amg_coarse_size=16, resid_fp64=1)),
+    ("dia3", "cpr", "assembled", "fp64", "l1jacobi", dict(amg_coarse_size=64)),
+    ("dia2", "cptr_bd", "assembled", "fp32", "l1jacobi", dict(amg_coarse_size=64, second_stage="bilu0_mc")),
+    ("small", "none", "assembled", "fp64", "l1jacobi", dict()),
+]
+
+
+@pytest.mark.parametrize("name,first,schur,precision,smoother,extra", RESETUP_CASES)
+def test_update_values_on_the_device_equals_the_host_re_setup(name, first, schur, precision, smoother, extra):
+    """Numeric re-setup on the GPU (resetup_device = 1: prolongator values,
+    Galerkin products, l1 diagonals, coarsest inverse, algebraic S~_T, the
+    sliced copy of A, the p/T columns and the ILU factors) against the host
+    re-setup (resetup_device = 0) on the same kept aggregates, for values
+    perturbed entry by entry: every V-cycle of both hierarchies, the first
+    stage, the application and an FGMRES solve are equal bit for bit."""
+    banner(f"device re-setup {name} {first} {schur} {precision} {smoother}")
+    pr = prob(name)
+    p2 = _perturbed(pr, 41)
+    opts = dict(precision=precision, first_stage=first, schur=schur, amg_smoother=smoother)
+    opts.setdefault("second_stage", "bilu0")
+    opts.update(extra)
+    sd = solver(pr, resetup_device=1, **opts)
+    sh = solver(pr, resetup_device=0, **opts)
+    sd.update_values(p2)
+    sh.update_values(p2)
+    rng = np.random.default_rng(43)
+    st = cptr.cptr_get_stats(sd.h)
+    for which in (0, 1):
+        if st["nlevels"][which] == 0:
+            continue
+        b = dev(rng.standard_normal(pr.n))
+        xd, xh = torch.empty_like(b), torch.empty_like(b)
+        cptr.cptr_vcycle(sd.h, which, b, xd)
+        cptr.cptr_vcycle(sh.h, which, b, xh)
+        torch.cuda.synchronize()
+        assert torch.equal(xd, xh), f"V-cycle of hierarchy {which}"
+    v = dev(rng.standard_normal(pr.n * pr.nv))
+    a, b = torch.empty_like(v), torch.empty_like(v)
+    cptr.cptr_first_stage(sd.h, v, a)
+    cptr.cptr_first_stage(sh.h, v, b)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    assert torch.equal(sd.apply(v), sh.apply(v))
+    xa, ia = sd.solve(dev(p2.b), restart=30, rtol=1e-6)
+    xb, ib = sh.solve(dev(p2.b), restart=30, rtol=1e-6)
+    print(f"iters {ia['iters']} {ib['iters']}")
+    assert ia["iters"] == ib["iters"] and torch.equal(xa, xb)
+    sd.close()
+    sh.close()
+
+
+@pytest.mark.parametrize("device", [1, 0])
+def test_update_values_reports_a_zero_amg_diagonal(device):
+    """A zero pressure-pressure entry on one diagonal block of the new values
+    (the block itself stays invertible): the smoothed prolongator of A_pp
+    divides by it, and both re-setups report CPTR_ERR_SINGULAR_BLOCK."""
+    banner(f"update_values, zero A_pp diagonal, device {device}")
+    import copy
+    pr = prob("three")
+    s = solver(pr, precision="fp64", first_stage="cptr", second_stage="none", resetup_device=device,
+               amg_coarse_size=16)
+    pb = copy.copy(pr)
+    v = pr.vals.reshape(-1, pr.nv, pr.nv).copy()
+    i = 7
+    d = [k for k in range(pr.row_ptr[i], pr.row_ptr[i + 1]) if pr.col_idx[k] == i][0]
+    v[d, 0, 0] = 0.0
+    pb.vals = np.ascontiguousarray(v.reshape(-1))
+    with pytest.raises(cptr.CptrError) as e:
+        s.update_values(pb)
+    assert e.value.code == -4
+    s.close()
+
+
 def test_deterministic_solution():
     banner("determinism")
     pr = prob("three")
