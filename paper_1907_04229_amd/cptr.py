@@ -65,6 +65,24 @@ class Stats(C.Structure):
                 ("spmv_bytes", C.c_double), ("applies", C.c_longlong)]
 
 
+class ModelDesc(C.Structure):
+    _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int), ("dx", C.c_double),
+                ("three_phase", C.c_int), ("dt", C.c_double), ("perm", C.c_void_p), ("poro", C.c_void_p),
+                ("inj", C.POINTER(C.c_int)), ("n_inj", C.c_int), ("prod", C.POINTER(C.c_int)),
+                ("n_prod", C.c_int), ("heat", C.POINTER(C.c_int)), ("n_heat", C.c_int)]
+
+
+class NewtonOpts(C.Structure):
+    _fields_ = [("max_it", C.c_int), ("rtol", C.c_double), ("stol", C.c_double),
+                ("max_backtrack", C.c_int), ("lin", SolveOpts)]
+
+
+class NewtonInfo(C.Structure):
+    _fields_ = [("iters", C.c_int), ("lin_iters", C.c_int), ("backtracks", C.c_int),
+                ("converged", C.c_int), ("fnorm0", C.c_double), ("fnorm", C.c_double),
+                ("solve_ms", C.c_double)]
+
+
 class CptrError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"{msg} (status {code})")
@@ -114,6 +132,14 @@ def load():
         L.cptr_learn_grad.argtypes = [vp, vp, ip, fp, fp, vp]
         L.cptr_learn_rerun_layer.argtypes = [vp, ip, vp, vp]
         L.cptr_learn_train_step.argtypes = [vp, vp, ip, C.c_float, fp, vp]
+        ipp = C.POINTER(C.c_int)
+        L.cptr_model_create.argtypes = [C.POINTER(vp), C.POINTER(ModelDesc)]
+        L.cptr_model_destroy.argtypes = [vp]
+        L.cptr_model_info.argtypes = [vp, ipp, ipp, ipp, C.POINTER(vp), C.POINTER(vp)]
+        L.cptr_model_pattern.argtypes = [vp, ipp, ipp]
+        L.cptr_model_assemble.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+        L.cptr_newton_default_options.argtypes = [C.POINTER(NewtonOpts)]
+        L.cptr_newton_solve.argtypes = [vp, vp, vp, vp, C.POINTER(NewtonOpts), C.POINTER(NewtonInfo), vp]
         _lib = L
     return _lib
 
@@ -302,6 +328,18 @@ class Solver:
         self.h = cptr_setup(self.n, self.nv, self.rp, self.ci, self.vals, self.srp, self.sci,
                             self.svals, self.options)
 
+    @classmethod
+    def from_tensors(cls, n, nv, rp, ci, vals, srp, sci, svals, **opts):
+        """A solver on device tensors (int32 patterns, float64 values) that
+        the object keeps alive; no host problem attached."""
+        self = cls.__new__(cls)
+        self.problem = None
+        self.rp, self.ci, self.vals, self.srp, self.sci, self.svals = rp, ci, vals, srp, sci, svals
+        self.n, self.nv = n, nv
+        self.options = cptr_default_options(**opts)
+        self.h = cptr_setup(n, nv, rp, ci, vals, srp, sci, svals, self.options)
+        return self
+
     def update_values(self, problem):
         """Numeric re-setup for a system with the same pattern (cptr_update_values)."""
         import torch
@@ -419,3 +457,81 @@ def cptr_learn_train_step(solver, b1_batch, lr, stream=None):
                                         b1_batch.shape[0], float(lr), C.byref(loss),
                                         _stream(stream)))
     return float(loss.value)
+
+
+# ---------------------------------------------------------------- thermal model (cptr_model.h)
+def _host_ints(a):
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.int32).reshape(-1))
+    return a, a.ctypes.data_as(C.POINTER(C.c_int))
+
+
+class Model:
+    """The DG(0)/TPFA thermal model on the device (cptr_model_*): residual,
+    Jacobian and S~_T assembly, and Newton steps with cptr_newton_solve."""
+
+    def __init__(self, shape, perm, poro, three_phase=False, dt=10 * 86400.0, inj=(), prod=(), heat=(),
+                 dx=0.5, device="cuda"):
+        import torch
+        nx, ny, nz = shape
+        self.shape = tuple(shape)
+        dev = torch.device(device)
+        pt = torch.as_tensor(np.ascontiguousarray(perm, dtype=np.float64), device=dev)
+        po = torch.as_tensor(np.ascontiguousarray(poro, dtype=np.float64), device=dev)
+        lists = [_host_ints(c) for c in (inj, prod, heat)]
+        d = ModelDesc(nx, ny, nz, dx, int(bool(three_phase)), dt, _ptr(pt, torch.float64), _ptr(po, torch.float64),
+                      lists[0][1], lists[0][0].size, lists[1][1], lists[1][0].size, lists[2][1], lists[2][0].size)
+        self.m = C.c_void_p()
+        _check(load().cptr_model_create(C.byref(self.m), C.byref(d)))
+        nv, n, nnzb = C.c_int(), C.c_int(), C.c_int()
+        _check(load().cptr_model_info(self.m, C.byref(nv), C.byref(n), C.byref(nnzb), None, None))
+        self.nv, self.n, self.nnzb = nv.value, n.value, nnzb.value
+        rp = np.empty(self.n + 1, np.int32)
+        ci = np.empty(self.nnzb, np.int32)
+        _check(load().cptr_model_pattern(self.m, rp.ctypes.data_as(C.POINTER(C.c_int)),
+                                         ci.ctypes.data_as(C.POINTER(C.c_int))))
+        self.row_ptr, self.col_idx = rp, ci
+        self.rp = torch.as_tensor(rp, device=dev)
+        self.ci = torch.as_tensor(ci, device=dev)
+        self.device = dev
+
+    def assemble(self, x, xn, F=True, A=True, S=True, stream=None):
+        """(F*(x), Jacobian values, S~_T values) as float64 device tensors (None where not asked)."""
+        import torch
+        N = self.n * self.nv
+        Ft = torch.empty(N, dtype=torch.float64, device=self.device) if F else None
+        At = torch.empty(self.nnzb * self.nv * self.nv, dtype=torch.float64, device=self.device) if A else None
+        St = torch.empty(self.nnzb, dtype=torch.float64, device=self.device) if S else None
+        _check(load().cptr_model_assemble(self.m, _ptr(x, torch.float64), _ptr(xn, torch.float64), _ptr(Ft),
+                                          _ptr(At), _ptr(St), _stream(stream)))
+        return Ft, At, St
+
+    def solver(self, x, xn, **opts):
+        """A Solver set up on the Jacobian and S~_T at state x (host setup of the hierarchies)."""
+        _, A, S = self.assemble(x, xn, F=False)
+        return Solver.from_tensors(self.n, self.nv, self.rp, self.ci, A, self.rp, self.ci, S, **opts)
+
+    def newton(self, solver, x, xn, max_it=50, rtol=1e-8, stol=1e-8, max_backtrack=10, restart=30,
+               lin_rtol=1e-6, lin_maxit=1000, stream=None):
+        """One implicit time step (cptr_newton_solve); x is updated in place."""
+        import torch
+        o = NewtonOpts()
+        load().cptr_newton_default_options(C.byref(o))
+        o.max_it, o.rtol, o.stol, o.max_backtrack = max_it, rtol, stol, max_backtrack
+        o.lin = SolveOpts(restart, lin_rtol, lin_maxit, 0)
+        info = NewtonInfo()
+        _check(load().cptr_newton_solve(self.m, solver.h, _ptr(x, torch.float64), _ptr(xn, torch.float64),
+                                        C.byref(o), C.byref(info), _stream(stream)))
+        return dict(iters=info.iters, lin_iters=info.lin_iters, backtracks=info.backtracks,
+                    converged=bool(info.converged), fnorm0=info.fnorm0, fnorm=info.fnorm,
+                    solve_ms=info.solve_ms)
+
+    def close(self):
+        if getattr(self, "m", None):
+            load().cptr_model_destroy(self.m)
+            self.m = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

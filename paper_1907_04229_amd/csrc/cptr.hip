@@ -25,9 +25,11 @@
 #include <vector>
 
 #include "../../include/cptr_learn.h"
+#include "../../include/cptr_model.h"
 #include "common.h"
 #include "device_kernels.hip"
 #include "learned_kernels.hip"
+#include "model_kernels.hip"
 #include "setup_kernels.hip"
 
 namespace cptr {
@@ -2185,6 +2187,43 @@ static void update_on_device(cptr_handle *h, const double *A, const double *S, h
 
 }  // namespace cptr
 
+// ---------------------------------------------------------------- thermal model
+struct cptr_model {
+  cptr::ModelView view{};
+  int nv = 0, nnzb = 0;
+  cptr::DevMem perm, poro, wi, well, rp, ci;     // model data and its 7-point pattern
+  cptr::DevMem F, Ft, A, S, xt, dx, rhs, part;   // Newton work arrays
+  std::vector<double> part_host;
+};
+
+namespace cptr {
+
+static void model_assemble(cptr_model *m, const double *x, const double *xn, double *F, double *A, double *S,
+                           hipStream_t st) {
+  const int n = m->view.n;
+  if (m->nv == 3)
+    hipLaunchKernelGGL((k_model_assemble<3>), dim3(nblk(n, 128)), dim3(128), 0, st, m->view, x, xn,
+                       devp<int>(m->rp), devp<int>(m->ci), F, A, S);
+  else
+    hipLaunchKernelGGL((k_model_assemble<4>), dim3(nblk(n, 128)), dim3(128), 0, st, m->view, x, xn,
+                       devp<int>(m->rp), devp<int>(m->ci), F, A, S);
+  LAUNCH_CHECK();
+}
+
+// ||x||_2 of a device vector: block sums of squares in a fixed order, added on the host in block order
+static double model_norm(cptr_model *m, const double *x, size_t len, hipStream_t st) {
+  hipLaunchKernelGGL(k_model_sumsq, dim3(kModelNormBlocks), dim3(kBlock), 0, st, len, x, devp<double>(m->part));
+  LAUNCH_CHECK();
+  CPTR_HIP_TRY(hipMemcpyAsync(m->part_host.data(), m->part.p, kModelNormBlocks * sizeof(double),
+                              hipMemcpyDeviceToHost, st));
+  CPTR_HIP_TRY(hipStreamSynchronize(st));
+  double s = 0.0;
+  for (double v : m->part_host) s += v;
+  return std::sqrt(s);
+}
+
+}  // namespace cptr
+
 extern "C" {
 
 void cptr_default_options(cptr_options *o) {
@@ -2746,6 +2785,212 @@ int cptr_learn_train_step(cptr_handle *h, const double *b1, int count, float lr,
     return CPTR_OK;
   } catch (const Error &e) {
     return fail(e);
+  }
+}
+
+int cptr_model_create(cptr_model **out, const cptr_model_desc *d) {
+  if (!out || !d || !d->perm || !d->poro) return fail(Error{CPTR_ERR_INVALID_ARG, "null argument"});
+  *out = nullptr;
+  if (d->nx < 1 || d->ny < 1 || d->nz < 1 || !(d->dx > 0.0) || !(d->dt > 0.0) ||
+      (long long)d->nx * d->ny * d->nz > (1LL << 28))
+    return fail(Error{CPTR_ERR_INVALID_ARG, "invalid grid or time step"});
+  try {
+    auto m = std::make_unique<cptr_model>();
+    const int nx = d->nx, ny = d->ny, nz = d->nz, n = nx * ny * nz;
+    ModelView &v = m->view;
+    v.nx = nx;
+    v.ny = ny;
+    v.nz = nz;
+    v.n = n;
+    v.dx = d->dx;
+    v.vol = d->dx * d->dx * d->dx;
+    v.area = d->dx * d->dx;
+    v.dt = d->dt;
+    m->nv = d->three_phase ? 4 : 3;
+    // c_ref: sum_a S_a c_va of the initial saturations (the oil one eliminated)
+    {
+      using namespace phys;
+      const double sw = 0.1, sg = 0.05;
+      v.c_ref = d->three_phase ? 0.0 + sw * CV_WATER + sg * CV_GAS + (1.0 - (sw + sg)) * CV_OIL
+                               : 0.0 + sw * CV_WATER + (1.0 - sw) * CV_OIL;
+    }
+    m->perm.alloc((size_t)n * 8);
+    m->poro.alloc((size_t)n * 8);
+    CPTR_HIP_TRY(hipMemcpy(m->perm.p, d->perm, (size_t)n * 8, hipMemcpyDeviceToDevice));
+    CPTR_HIP_TRY(hipMemcpy(m->poro.p, d->poro, (size_t)n * 8, hipMemcpyDeviceToDevice));
+    // Peaceman well index 2 pi K dx / ln(r_o / r_w), r_o = 0.198 dx, r_w = 0.01 m
+    std::vector<double> perm_h(n);
+    CPTR_HIP_TRY(hipMemcpy(perm_h.data(), d->perm, (size_t)n * 8, hipMemcpyDeviceToHost));
+    std::vector<double> wi(n);
+    const double lr = std::log(0.198 * d->dx / 0.01);
+    for (int i = 0; i < n; i++) wi[i] = 2.0 * M_PI * perm_h[i] * d->dx / lr;
+    upload(m->wi, wi);
+    std::vector<unsigned char> well(n, 0);
+    auto mark = [&](const int *c, int cnt, unsigned bit) {
+      if (cnt > 0 && !c) throw Error{CPTR_ERR_INVALID_ARG, "null cell list"};
+      for (int q = 0; q < cnt; q++) {
+        if (c[q] < 0 || c[q] >= n) throw Error{CPTR_ERR_INVALID_ARG, "well cell out of range"};
+        well[c[q]] |= (unsigned char)bit;
+      }
+    };
+    mark(d->inj, d->n_inj, 1u);
+    mark(d->prod, d->n_prod, 2u);
+    mark(d->heat, d->n_heat, 4u);
+    upload(m->well, well);
+    // the 7-point pattern, ascending columns
+    std::vector<int> rp(n + 1, 0), ci;
+    ci.reserve((size_t)7 * n);
+    const int nxy = nx * ny;
+    for (int i = 0; i < n; i++) {
+      const int ix = i % nx, iy = (i / nx) % ny, iz = i / nxy;
+      if (iz > 0) ci.push_back(i - nxy);
+      if (iy > 0) ci.push_back(i - nx);
+      if (ix > 0) ci.push_back(i - 1);
+      ci.push_back(i);
+      if (ix < nx - 1) ci.push_back(i + 1);
+      if (iy < ny - 1) ci.push_back(i + nx);
+      if (iz < nz - 1) ci.push_back(i + nxy);
+      rp[i + 1] = int(ci.size());
+    }
+    m->nnzb = int(ci.size());
+    upload(m->rp, rp);
+    upload(m->ci, ci);
+    v.perm = devp<double>(m->perm);
+    v.poro = devp<double>(m->poro);
+    v.wi = devp<double>(m->wi);
+    v.well = devp<unsigned char>(m->well);
+    const size_t N = (size_t)n * m->nv;
+    for (DevMem *a : {&m->F, &m->Ft, &m->xt, &m->dx, &m->rhs}) a->alloc(N * 8);
+    m->A.alloc((size_t)m->nnzb * m->nv * m->nv * 8);
+    m->S.alloc((size_t)m->nnzb * 8);
+    m->part.alloc(kModelNormBlocks * 8);
+    m->part_host.assign(kModelNormBlocks, 0.0);
+    *out = m.release();
+    return CPTR_OK;
+  } catch (const Error &e) {
+    return fail(e);
+  } catch (const std::bad_alloc &) {
+    return fail(Error{CPTR_ERR_OOM, "host allocation failed"});
+  }
+}
+
+void cptr_model_destroy(cptr_model *m) { delete m; }
+
+int cptr_model_info(const cptr_model *m, int *nv, int *n, int *nnzb, const int **row_ptr, const int **col_idx) {
+  if (!m) return fail(Error{CPTR_ERR_INVALID_ARG, "null argument"});
+  if (nv) *nv = m->nv;
+  if (n) *n = m->view.n;
+  if (nnzb) *nnzb = m->nnzb;
+  if (row_ptr) *row_ptr = devp<int>(m->rp);
+  if (col_idx) *col_idx = devp<int>(m->ci);
+  return CPTR_OK;
+}
+
+int cptr_model_pattern(const cptr_model *m, int *row_ptr_host, int *col_idx_host) {
+  if (!m) return fail(Error{CPTR_ERR_INVALID_ARG, "null argument"});
+  try {
+    if (row_ptr_host)
+      CPTR_HIP_TRY(hipMemcpy(row_ptr_host, m->rp.p, sizeof(int) * (m->view.n + 1), hipMemcpyDeviceToHost));
+    if (col_idx_host) CPTR_HIP_TRY(hipMemcpy(col_idx_host, m->ci.p, sizeof(int) * m->nnzb, hipMemcpyDeviceToHost));
+    return CPTR_OK;
+  } catch (const Error &e) {
+    return fail(e);
+  }
+}
+
+int cptr_model_assemble(cptr_model *m, const double *x, const double *xn, double *F, double *A_vals,
+                        double *S_vals, void *stream) {
+  if (!m || !x || !xn) return fail(Error{CPTR_ERR_INVALID_ARG, "null argument"});
+  try {
+    model_assemble(m, x, xn, F, A_vals, S_vals, (hipStream_t)stream);
+    return CPTR_OK;
+  } catch (const Error &e) {
+    return fail(e);
+  }
+}
+
+void cptr_newton_default_options(cptr_newton_opts *o) {
+  if (!o) return;
+  o->max_it = 50;
+  o->rtol = 1e-8;
+  o->stol = 1e-8;
+  o->max_backtrack = 10;
+  o->lin.restart = 30;
+  o->lin.rtol = 1e-6;
+  o->lin.maxit = 1000;
+  o->lin.nonzero_guess = 0;
+}
+
+int cptr_newton_solve(cptr_model *m, cptr_handle *h, double *x, const double *xn, const cptr_newton_opts *o_in,
+                      cptr_newton_info *info_out, void *stream) {
+  if (!m || !h || !x || !xn) return fail(Error{CPTR_ERR_INVALID_ARG, "null argument"});
+  if (h->op.n != m->view.n || h->op.nv != m->nv || h->op.nnzb != m->nnzb)
+    return fail(Error{CPTR_ERR_INVALID_ARG, "the handle was not set up on this model's pattern"});
+  cptr_newton_opts o;
+  cptr_newton_default_options(&o);
+  if (o_in) o = *o_in;
+  if (o.max_it < 0 || o.max_backtrack < 0 || !(o.rtol >= 0.0) || !(o.stol >= 0.0))
+    return fail(Error{CPTR_ERR_INVALID_ARG, "invalid Newton options"});
+  o.lin.nonzero_guess = 0;
+  cptr_newton_info info{};
+  const auto t0 = std::chrono::steady_clock::now();
+  try {
+    hipStream_t st = (hipStream_t)stream;
+    const size_t N = (size_t)m->view.n * m->nv;
+    double *F = devp<double>(m->F), *Ft = devp<double>(m->Ft), *xt = devp<double>(m->xt);
+    double *dx = devp<double>(m->dx), *rhs = devp<double>(m->rhs);
+    model_assemble(m, x, xn, F, nullptr, nullptr, st);
+    double f = model_norm(m, F, N, st);
+    info.fnorm0 = f;
+    if (!std::isfinite(f)) throw Error{CPTR_ERR_NONFINITE, "non-finite residual at the initial state"};
+    bool done = f == 0.0;
+    while (!done && info.iters < o.max_it) {
+      model_assemble(m, x, xn, nullptr, devp<double>(m->A), devp<double>(m->S), st);
+      int rc = cptr_update_values(h, devp<double>(m->A), devp<double>(m->S), stream);
+      if (rc != CPTR_OK) return rc;
+      hipLaunchKernelGGL(k_model_neg, dim3(nblk(N)), dim3(kBlock), 0, st, N, (const double *)F, rhs);
+      LAUNCH_CHECK();
+      cptr_solve_info li{};
+      rc = fgmres_solve(h, rhs, dx, &o.lin, &li, stream);
+      if (rc != CPTR_OK) return rc;
+      info.lin_iters += li.iters;
+      // backtracking line search on ||F*||
+      double lambda = 1.0, ft = 0.0;
+      bool ok = false;
+      for (int bt = 0; bt <= o.max_backtrack; bt++) {
+        hipLaunchKernelGGL(k_model_axpy, dim3(nblk(N)), dim3(kBlock), 0, st, N, (const double *)x, lambda,
+                           (const double *)dx, xt);
+        LAUNCH_CHECK();
+        model_assemble(m, xt, xn, Ft, nullptr, nullptr, st);
+        ft = model_norm(m, Ft, N, st);
+        if (std::isfinite(ft) && ft <= (1.0 - 1e-4 * lambda) * f) {
+          ok = true;
+          break;
+        }
+        lambda *= 0.5;
+        info.backtracks++;
+      }
+      info.iters++;
+      if (!ok) break;  // line search failure: x stays at the last accepted iterate
+      const double step = lambda * model_norm(m, dx, N, st);
+      CPTR_HIP_TRY(hipMemcpyAsync(x, xt, N * 8, hipMemcpyDeviceToDevice, st));
+      std::swap(m->F, m->Ft);
+      F = devp<double>(m->F);
+      Ft = devp<double>(m->Ft);
+      f = ft;
+      const double xnorm = model_norm(m, x, N, st);
+      done = f <= o.rtol * info.fnorm0 || step <= o.stol * xnorm;
+    }
+    info.converged = done ? 1 : 0;
+    info.fnorm = f;
+    CPTR_HIP_TRY(hipStreamSynchronize(st));
+    info.solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (info_out) *info_out = info;
+    return CPTR_OK;
+  } catch (const Error &e) {
+    return fail(e);
+  } catch (const std::bad_alloc &) {
+    return fail(Error{CPTR_ERR_OOM, "host allocation failed"});
   }
 }
 

@@ -111,7 +111,10 @@ class Grid:
         slot = {}
         for off, m in offs:
             col[pos[m]] = i[m] + off
-            slot[off] = np.where(m, pos, -1)
+            # offsets of different axes coincide when nx or ny is 1 (-nx = -1,
+            # nx ny = nx); such a pair never has both neighbours, so the
+            # positions are merged
+            slot[off] = np.where(m, pos, slot.get(off, -1))
             pos = pos + m
         return row_ptr, col, slot
 

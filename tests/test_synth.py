@@ -40,9 +40,12 @@ def test_property_spot_values():
         assert P.rho_water(p, T) == pytest.approx(rho, abs=1e-2)
 
 
-@pytest.mark.parametrize("three_phase", [False, True])
-def test_jacobian_matches_finite_differences(three_phase):
-    m = build_model((4, 3, 3), three_phase=three_phase, kind="iid", seed=3, heater=True)
+@pytest.mark.parametrize("three_phase,shape", [(False, (4, 3, 3)), (True, (4, 3, 3)),
+                                               (False, (1, 1, 9)), (False, (1, 4, 3)), (True, (5, 1, 3))])
+def test_jacobian_matches_finite_differences(three_phase, shape):
+    """Also on grids with nx = 1 or ny = 1, where stencil offsets of two axes
+    coincide (-nx = -1, nx ny = nx)."""
+    m = build_model(shape, three_phase=three_phase, kind="iid", seed=3, heater=True)
     x, x0 = _perturbed(m)
     rp, col, vals = m.jacobian(x, x0)
     n, nv = m.g.n, m.nv
