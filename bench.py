@@ -29,6 +29,11 @@ whole grid columns (`--parts`, the parallel ILU(0) of the paper's
 multi-process runs), with the two-stage residual and the rows of the ILU
 solves summed in FP64.
 
+Context of the Newton use (`newton` key): cptr_update_values on the measured
+solver's options, on the GPU and on the host, and one implicit Euler step of
+the thermal model on the workload's grid from its initial state with the
+device Newton loop (assembly, GPU re-setup, CPTR-FGMRES, line search).
+
 Prints one JSON line (keys below).  `--probe` runs only a short learned
 forward pass, each layer kernel three more times, the FP64 BSR product and
 a plain 1 GiB device copy, for hardware-counter runs of the profiler; `--traffic FETCH_DB WRITE_DB` turns
@@ -142,6 +147,60 @@ def layer_timings(solver, reps=50):
                          avg_us=round(avg_s * 1e6, 2), launches=reps,
                          traffic=recorded_traffic(layer, n, nv)))
     return rows
+
+
+def resetup_times(pr, solver_opts):
+    """cptr_update_values on the measured solver's options: the GPU re-setup
+    (three calls, the last timed) and the host re-setup (one call), in ms."""
+    import copy
+    from paper_1907_04229_amd import cptr
+    out = {}
+    for tag, dev in (("gpu_ms", 1), ("host_ms", 0)):
+        s = cptr.Solver(pr, resetup_device=dev, **solver_opts)
+        for _ in range(3 if dev else 1):
+            s.update_values(copy.copy(pr))
+        out[tag] = round(cptr.cptr_get_stats(s.h)["setup_ms"], 1)
+        s.close()
+    return out
+
+
+def newton_leg(cfg_name, log_fn):
+    """One implicit Euler step of the thermal model on the device at the
+    workload's grid (cptr_newton_solve: TPFA assembly, GPU re-setup,
+    CPTR-FGMRES, line search), from the initial state, with two
+    preconditioners; and the assembly kernel's time."""
+    import torch
+    from paper_1907_04229_amd import cptr
+    from paper_1907_04229_amd.synth.problem import CONFIGS, build_model
+    kw = dict(CONFIGS[cfg_name])
+    shape = kw.pop("shape")
+    m = build_model(shape, **kw)
+    g, w = m.g, m.wells
+    d = cptr.Model((g.nx, g.ny, g.nz), m.perm, m.poro, three_phase=m.three_phase, dt=m.dt, inj=w.inj,
+                   prod=w.prod, heat=w.heat, dx=g.dx)
+    x0 = torch.as_tensor(m.initial_state().reshape(-1), device="cuda")
+    out = {"grid": "x".join(map(str, shape)), "cells": g.n, "dt_days": m.dt / 86400.0}
+    st = torch.cuda.current_stream()
+    for _ in range(2):
+        d.assemble(x0, x0)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(10):
+        d.assemble(x0, x0)
+    e1.record(st)
+    e1.synchronize()
+    out["assemble_ms"] = round(e0.elapsed_time(e1) / 10, 3)
+    for tag, opts in (("fp32_cptr_bilu0_mc", dict(precision="fp32", second_stage="bilu0_mc")),
+                      ("fp64_cptr_bilu0", dict(precision="fp64", second_stage="bilu0"))):
+        x = x0.clone()
+        s = d.solver(x, x0, **opts)
+        info = d.newton(s, x, x0, max_it=20)
+        log_fn(f"newton {tag}: {info['iters']} iterations ({info['lin_iters']} linear, {info['backtracks']} "
+               f"halvings), {info['solve_ms']:.0f} ms, |F| {info['fnorm0']:.3e} -> {info['fnorm']:.3e}")
+        out[tag] = dict(info, solve_ms=round(info["solve_ms"], 1))
+        s.close()
+    d.close()
+    return out
 
 
 def spmv_roofline(pr, solver, reps=50):
@@ -444,6 +503,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the FP64 and BILU(0) legs")
     ap.add_argument("--no-large", action="store_true", help="skip the three-phase 128x128x64 block")
+    ap.add_argument("--no-newton", action="store_true",
+                    help="skip the re-setup timings and the implicit step with the device Newton loop")
     ap.add_argument("--context", action="store_true",
                     help="also the context legs (CPR, CPTR-BD, CPTR-uAMG, decoupling, BILU(1))")
     ap.add_argument("--held-out", action="store_true", help="evaluate the held-out seeds 200-204")
@@ -534,6 +595,10 @@ def main():
     layers = layer_timings(sl)
     for r in layers:
         log(f"layer {r['layer']}: {r['avg_us']} us, {r['achieved']} GB/s ({r['frac']:.2f} of peak)")
+    resetup = None
+    if not args.no_newton:
+        resetup = resetup_times(pr, dict(precision="fp32", second_stage="learned", first_stage=args.first))
+        log(f"re-setup (cptr_update_values): GPU {resetup['gpu_ms']} ms, host {resetup['host_ms']} ms")
 
     compare = {}
     x64 = None
@@ -619,6 +684,11 @@ def main():
         large["parts"] = "x".join(map(str, parts))
         del pl, bl
 
+    newton = None
+    if not args.no_newton:
+        newton = newton_leg(args.config, log)
+        newton["resetup"] = resetup
+
     held = None
     if args.held_out:
         held = held_out_eval(cfg, model, restart, args.first, log)
@@ -664,6 +734,7 @@ def main():
         "compare": compare,
         "large": large,
         "held_out": held,
+        "newton": newton,
         "roofline": roof,
         "cpu_baseline": cpu,
     }
