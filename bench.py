@@ -117,9 +117,35 @@ LAYER_KERNEL = {0: "k_lrn_layer_first<{nv},true,false,bf16>",
                 2: "k_lrn_layer_col<{nv},false,true,bf16>"}
 
 
+FLUSH_BYTES = 1 << 30  # written between timed launches: more than the 256 MB last-level cache
+
+
+def cold_launch_time(launch, reps, st):
+    """Average duration (s) of launch() on stream st, each launch timed alone
+    with HIP events after a 1 GiB fill, so that none of its operands is still
+    in the last-level cache (inside a solve the other kernels of the
+    iteration pass far more data through it than it holds)."""
+    import torch
+    junk = torch.empty(FLUSH_BYTES // 4, dtype=torch.float32, device="cuda")
+    for _ in range(2):
+        launch()
+    total = 0.0
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for e0, e1 in evs:
+        junk.fill_(1.0)
+        e0.record(st)
+        launch()
+        e1.record(st)
+    evs[-1][1].synchronize()
+    for e0, e1 in evs:
+        total += e0.elapsed_time(e1)
+    return total / reps * 1e-3
+
+
 def layer_timings(solver, reps=50):
     """Average duration of each learned layer kernel (BF16 activations),
-    timed with HIP events on the stream it is launched on, against the
+    each launch timed alone with HIP events on the stream it is launched on,
+    the last-level cache flushed before it (cold_launch_time), against the
     method's bytes per launch (layer_method_bytes)."""
     import torch
     from paper_1907_04229_amd import cptr
@@ -129,15 +155,7 @@ def layer_timings(solver, reps=50):
     rows = []
     for layer in (0, 1, 2):
         out = z2 if layer == 2 else None
-        for _ in range(3):
-            cptr.cptr_learn_rerun_layer(solver, layer, out, st)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(st)
-        for _ in range(reps):
-            cptr.cptr_learn_rerun_layer(solver, layer, out, st)
-        e1.record(st)
-        e1.synchronize()
-        avg_s = e0.elapsed_time(e1) / reps * 1e-3
+        avg_s = cold_launch_time(lambda: cptr.cptr_learn_rerun_layer(solver, layer, out, st), reps, st)
         algo = n * layer_method_bytes(layer, nv)
         gbs = algo / avg_s / 1e9
         name = LAYER_KERNEL[layer].format(nv=nv)
@@ -205,23 +223,16 @@ def newton_leg(cfg_name, log_fn):
 
 def spmv_roofline(pr, solver, reps=50):
     """FP64 BSR product y = A x (the Arnoldi w = A z of every step, on the
-    solver's sliced copy of A): average duration with HIP events, algorithmic
-    bytes = values + column indices + row pointers + x + y of the BSR matrix."""
+    solver's sliced copy of A): average duration of single launches after a
+    cache flush (cold_launch_time), algorithmic bytes = values + column
+    indices + row pointers + x + y of the BSR matrix."""
     import torch
     from paper_1907_04229_amd import cptr
     n, nv = pr.n, pr.nv
     x = torch.randn(n * nv, dtype=torch.float64, device="cuda")
     y = torch.empty_like(x)
     st = torch.cuda.current_stream()
-    for _ in range(5):
-        cptr.cptr_matvec(solver.h, x, y, st)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(st)
-    for _ in range(reps):
-        cptr.cptr_matvec(solver.h, x, y, st)
-    e1.record(st)
-    e1.synchronize()
-    avg_s = e0.elapsed_time(e1) / reps * 1e-3
+    avg_s = cold_launch_time(lambda: cptr.cptr_matvec(solver.h, x, y, st), reps, st)
     algo = pr.nnzb * (nv * nv * 8 + 4) + 4 * (n + 1) + 2 * 8 * n * nv
     gbs = algo / avg_s / 1e9
     return dict(kernel=f"k_bsr_spmv_sliced<{nv},double>", achieved=round(gbs, 1), unit="GB/s",
