@@ -82,17 +82,23 @@ def spmv_source_hash():
 
 
 def layer_method_bytes(layer, nv):
-    """Bytes per cell that one inference launch of learned layer `layer` must
-    move (the method's, not the kernel's): the six nv x nv edge blocks in
-    BF16; layer 0 reads r = D^{-1} b1 (nv FP32) and writes h1 (64 BF16);
-    layer 1 reads h1 and writes h2; layer 2 (as relaunched alone, writing the
-    FP64 output z2) reads h2 and r and writes z2 (nv FP64)."""
+    """Bytes per cell that one inference launch of learned layer `layer`
+    moves inside a solve (the method's, not the kernel's): the six nv x nv
+    edge blocks in BF16; layer 0 reads r = D^{-1} b1 (nv FP32) and writes h1
+    (64 BF16); layer 1 reads h1 and writes h2; layer 2 reads h2, r and the p
+    and T components of the first stage's x1 (FP32) and writes z (nv FP32)."""
     edges = 6 * nv * nv * 2
     if layer == 0:
         return 4 * nv + edges + HIDDEN * 2
     if layer == 1:
         return HIDDEN * 2 + edges + HIDDEN * 2
-    return HIDDEN * 2 + edges + 4 * nv + 8 * nv
+    return HIDDEN * 2 + edges + 4 * nv + 2 * 4 + 4 * nv
+
+
+def product_method_bytes(n, nnzb, nv, z_bytes=4):
+    """The Arnoldi product w = A z inside the FP32-preconditioner solve: FP64
+    blocks and block column indices, row pointers, z (FP32), w (FP64)."""
+    return nnzb * (nv * nv * 8 + 4) + 4 * (n + 1) + n * nv * (z_bytes + 8)
 
 
 def recorded_traffic(kernel, cells, nv):
@@ -112,58 +118,38 @@ def recorded_traffic(kernel, cells, nv):
     return None
 
 
-LAYER_KERNEL = {0: "k_lrn_layer_first<{nv},true,false,bf16>",
-                1: "k_lrn_layer_col<{nv},false,false,bf16>",
-                2: "k_lrn_layer_col<{nv},false,true,bf16>"}
+LAYER_KERNEL = {0: "k_lrn_layer_first<{nv},true,false,short,float,float>",
+                1: "k_lrn_layer_col<{nv},false,false,short,float,float>",
+                2: "k_lrn_layer_col<{nv},false,true,short,float,float>"}
+PRODUCT_KERNEL = "k_bsr_spmv_sliced<{nv},float,false>"
 
 
-FLUSH_BYTES = 1 << 30  # written between timed launches: more than the 256 MB last-level cache
-
-
-def cold_launch_time(launch, reps, st):
-    """Average duration (s) of launch() on stream st, each launch timed alone
-    with HIP events after a 1 GiB fill, so that none of its operands is still
-    in the last-level cache (inside a solve the other kernels of the
-    iteration pass far more data through it than it holds)."""
-    import torch
-    junk = torch.empty(FLUSH_BYTES // 4, dtype=torch.float32, device="cuda")
-    for _ in range(2):
-        launch()
-    total = 0.0
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
-    for e0, e1 in evs:
-        junk.fill_(1.0)
-        e0.record(st)
-        launch()
-        e1.record(st)
-    evs[-1][1].synchronize()
-    for e0, e1 in evs:
-        total += e0.elapsed_time(e1)
-    return total / reps * 1e-3
-
-
-def layer_timings(solver, reps=50):
-    """Average duration of each learned layer kernel (BF16 activations),
-    each launch timed alone with HIP events on the stream it is launched on,
-    the last-level cache flushed before it (cold_launch_time), against the
-    method's bytes per launch (layer_method_bytes)."""
-    import torch
+def in_solve_rooflines(solver, rhs, restart, solves=2):
+    """Average duration of the Krylov product and of each learned layer as
+    they run inside solves of the workload (cptr_kernel_timing: HIP events
+    recorded by the library around every launch on the solve's stream; the
+    timed solves run without graph replay), against the method's bytes per
+    launch.  Returns one row per kernel."""
     from paper_1907_04229_amd import cptr
-    n, nv = solver.problem.n, solver.problem.nv
-    st = torch.cuda.current_stream()
-    z2 = torch.empty(n * nv, dtype=torch.float64, device="cuda")
+    n, nv, nnzb = solver.problem.n, solver.problem.nv, solver.problem.nnzb
+    cptr.cptr_kernel_timing(solver.h, True)
+    for _ in range(solves):
+        solver.solve(rhs, restart=restart, rtol=1e-6)
+    us, cnt = cptr.cptr_get_kernel_times(solver.h)
+    cptr.cptr_kernel_timing(solver.h, False)
     rows = []
-    for layer in (0, 1, 2):
-        out = z2 if layer == 2 else None
-        avg_s = cold_launch_time(lambda: cptr.cptr_learn_rerun_layer(solver, layer, out, st), reps, st)
-        algo = n * layer_method_bytes(layer, nv)
-        gbs = algo / avg_s / 1e9
-        name = LAYER_KERNEL[layer].format(nv=nv)
-        rows.append(dict(kernel=name, layer=layer, achieved=round(gbs, 1), unit="GB/s",
+    for kid in range(4):
+        if kid == 0:
+            algo = product_method_bytes(n, nnzb, nv)
+            name, per_cell, key = PRODUCT_KERNEL.format(nv=nv), None, "spmv"
+        else:
+            algo = n * layer_method_bytes(kid - 1, nv)
+            name, per_cell, key = LAYER_KERNEL[kid - 1].format(nv=nv), layer_method_bytes(kid - 1, nv), kid - 1
+        gbs = algo / (us[kid] * 1e-6) / 1e9
+        rows.append(dict(kernel=name, layer=None if kid == 0 else kid - 1, achieved=round(gbs, 1), unit="GB/s",
                          frac=round(gbs / HBM_PEAK_GBS, 4), bytes_per_launch=int(algo),
-                         method_bytes_per_cell=layer_method_bytes(layer, nv),
-                         avg_us=round(avg_s * 1e6, 2), launches=reps,
-                         traffic=recorded_traffic(layer, n, nv)))
+                         method_bytes_per_cell=per_cell, avg_us=round(us[kid], 2), launches=int(cnt[kid]),
+                         traffic=recorded_traffic(key, n, nv)))
     return rows
 
 
@@ -219,25 +205,6 @@ def newton_leg(cfg_name, log_fn):
         s.close()
     d.close()
     return out
-
-
-def spmv_roofline(pr, solver, reps=50):
-    """FP64 BSR product y = A x (the Arnoldi w = A z of every step, on the
-    solver's sliced copy of A): average duration of single launches after a
-    cache flush (cold_launch_time), algorithmic bytes = values + column
-    indices + row pointers + x + y of the BSR matrix."""
-    import torch
-    from paper_1907_04229_amd import cptr
-    n, nv = pr.n, pr.nv
-    x = torch.randn(n * nv, dtype=torch.float64, device="cuda")
-    y = torch.empty_like(x)
-    st = torch.cuda.current_stream()
-    avg_s = cold_launch_time(lambda: cptr.cptr_matvec(solver.h, x, y, st), reps, st)
-    algo = pr.nnzb * (nv * nv * 8 + 4) + 4 * (n + 1) + 2 * 8 * n * nv
-    gbs = algo / avg_s / 1e9
-    return dict(kernel=f"k_bsr_spmv_sliced<{nv},double>", achieved=round(gbs, 1), unit="GB/s",
-                frac=round(gbs / HBM_PEAK_GBS, 4), bytes_per_launch=int(algo), avg_us=round(avg_s * 1e6, 2),
-                launches=reps, traffic=recorded_traffic("spmv", n, nv))
 
 
 def cpu_baseline(pr, maxit=None):
@@ -336,9 +303,10 @@ def held_out_eval(cfg, model, restart, first, log_fn):
 
 
 def probe(cfg_name):
-    """Short run for the hardware-counter passes: one learned forward, each
-    layer kernel three more times, the FP64 BSR product four times, and a
-    1 GiB device copy three times."""
+    """Short run for the hardware-counter passes: a learned+FP32 solve of the
+    workload cut at four FGMRES iterations (the Krylov product and the three
+    layers as they run in the timed solve), and a 1 GiB device copy three
+    times."""
     import torch
     from paper_1907_04229_amd import cptr
     from paper_1907_04229_amd.learned_init import neumann_params
@@ -347,14 +315,7 @@ def probe(cfg_name):
     s = cptr.Solver(pr, precision="fp32", second_stage="learned")
     m = cptr.LearnModel(pr.nv, neumann_params(pr.nv, seed=1))
     m.attach(s)
-    b1 = torch.randn(pr.n * pr.nv, dtype=torch.float64, device="cuda")
-    z2 = cptr.cptr_learn_forward(s, b1)
-    for layer in (0, 1, 2):
-        for _ in range(3):
-            cptr.cptr_learn_rerun_layer(s, layer, z2 if layer == 2 else None)
-    y = torch.empty_like(b1)
-    for _ in range(4):
-        cptr.cptr_matvec(s.h, b1, y)
+    s.solve(torch.as_tensor(pr.b, device="cuda"), restart=30, rtol=1e-6, maxit=4)
     a = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
     c = torch.empty_like(a)
     for _ in range(3):
@@ -444,8 +405,9 @@ def _mean_of(disp, name, largest_grid=False):
 
 
 def record_traffic(fetch_db, write_db, cells, nv):
-    """Per-launch HBM bytes of the three learned layers and the FP64 BSR
-    product from a FETCH_SIZE and a WRITE_SIZE pass over `bench.py --probe`,
+    """Per-launch HBM bytes of the three learned layers and the Krylov
+    product, as they run in the timed solve, from a FETCH_SIZE and a
+    WRITE_SIZE pass over `bench.py --probe`,
     each scaled by what the same counter reads for the probe's 1 GiB device
     copy (its largest-grid dispatches: COPY_BYTES read and written); written
     to TRAFFIC_FILE."""
@@ -459,10 +421,8 @@ def record_traffic(fetch_db, write_db, cells, nv):
     wcopy, nwc = _mean_of(write, ck, True)
     fscale, wscale = kib / fcopy, kib / wcopy
     norm = lambda k: k.replace(" ", "")  # noqa: E731
-    want = [(0, f"k_lrn_layer_first<{nv},true,false,", "layer", cells * layer_method_bytes(0, nv)),
-            (1, f"k_lrn_layer_col<{nv},false,false,", "layer", cells * layer_method_bytes(1, nv)),
-            (2, f"k_lrn_layer_col<{nv},false,true,", "layer", cells * layer_method_bytes(2, nv)),
-            ("spmv", f"k_bsr_spmv_sliced<{nv},double,", "spmv", None)]
+    want = [(q, LAYER_KERNEL[q].format(nv=nv), "layer", cells * layer_method_bytes(q, nv)) for q in (0, 1, 2)]
+    want.append(("spmv", PRODUCT_KERNEL.format(nv=nv), "spmv", None))
     kernels = []
     for key, tag, kind, method in want:
         names = [k for k in fetch if tag in norm(k)]
@@ -603,9 +563,9 @@ def main():
     sl, setup_l = setup(pr, precision="fp32", second_stage="learned", first_stage=args.first)
     model.attach(sl)
     dt, info, x_l = run(sl, args.steps, args.warmup, "learned+fp32", b, measured=True)
-    layers = layer_timings(sl)
-    for r in layers:
-        log(f"layer {r['layer']}: {r['avg_us']} us, {r['achieved']} GB/s ({r['frac']:.2f} of peak)")
+    kernels = in_solve_rooflines(sl, b, restart)
+    for r in kernels:
+        log(f"{r['kernel']}: {r['avg_us']} us in the solve, {r['achieved']} GB/s ({r['frac']:.2f} of peak)")
     resetup = None
     if not args.no_newton:
         resetup = resetup_times(pr, dict(precision="fp32", second_stage="learned", first_stage=args.first))
@@ -613,12 +573,10 @@ def main():
 
     compare = {}
     x64 = None
-    spmv = None
     if not args.no_compare:
         s64, su = setup(pr, precision="fp64", second_stage="bilu0")
         d64, i64, x64 = run(s64, 1, 1, "plain fp64 (bilu0 natural)", b)
         compare["fp64_cptr_bilu0"] = leg(d64, i64, su, pr.n)
-        spmv = spmv_roofline(pr, s64)
         s64.close()
         for tag, opt, mdl in (
                 ("fp32_cptr_bilu0_mc", dict(precision="fp32", second_stage="bilu0_mc", first_stage=args.first),
@@ -667,7 +625,6 @@ def main():
         compare["speedup_vs_fp64"] = round(d64 / dt, 3)
         compare["solution_rel_diff_vs_fp64"] = float(torch.linalg.vector_norm(x_l - x64) /
                                                      torch.linalg.vector_norm(x64))
-        compare["spmv_fp64"] = spmv
 
     large = None
     if not args.no_large:
@@ -708,15 +665,14 @@ def main():
         cpu = cpu_baseline(pr, args.cpu_iters or None)
         log(f"cpu baseline: {cpu}")
     # the roofline of the dominant kernel of the timed solve: each learned
-    # layer and the FP64 Krylov product run once per FGMRES iteration
-    cands = list(layers)
-    if spmv is not None:
-        cands.append(dict(spmv, layer=None))
+    # layer and the Krylov product run once per FGMRES iteration
+    cands = list(kernels)
     dom = max(cands, key=lambda r: r["avg_us"])
     roof = dict(bound="hbm", achieved=dom["achieved"], peak=HBM_PEAK_GBS, unit="GB/s", frac=dom["frac"],
                 traffic=dom.get("traffic"), kernel=dom["kernel"], bytes_per_launch=dom["bytes_per_launch"],
                 avg_us=dom["avg_us"], launches=dom.get("launches", 50),
-                others=[{k: r[k] for k in ("kernel", "avg_us", "achieved", "frac", "bytes_per_launch")}
+                measured="inside two solves of the workload, HIP events around every launch (cptr_kernel_timing)",
+                others=[{k: r[k] for k in ("kernel", "avg_us", "achieved", "frac", "bytes_per_launch", "traffic")}
                         for r in cands if r is not dom])
     out = {
         "metric": "FGMRES time-to-1e-6 (s) & cell-iters/s: learned/FP32 vs FP64 CPTR; HBM GB/s",

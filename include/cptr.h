@@ -346,6 +346,18 @@ int cptr_krylov_vector(const cptr_handle *h, int j, double *out, void *stream);
 int cptr_update_values(cptr_handle *h, const double *A_vals, const double *S_vals,
                        void *stream);
 
+/* Kernel timing for roofline figures.  With enable = 1 (totals reset) the
+ * handle's later solves skip graph replay and record HIP events on the
+ * solve's stream around every launch of the Krylov product w = A z (id 0)
+ * and of the learned stage's three inference layers (ids 1, 2, 3; also in
+ * cptr_apply); enable = 0 stops and keeps the totals.  The events add no
+ * work to the kernels; the launch gaps of a solve without graphs are a few
+ * microseconds longer.  cptr_get_kernel_times: average microseconds per
+ * launch and launch counts of the four ids (host arrays of 4, NULL to skip;
+ * blocks until the timed launches have finished). */
+int cptr_kernel_timing(cptr_handle *h, int enable);
+int cptr_get_kernel_times(cptr_handle *h, double *avg_us, long long *launches);
+
 /* Introspection.  Integer setup results, copied to host arrays (NULL to skip):
  * the aggregate of every row of AMG level `level` (size = rows of that level),
  * and the level / colour of every cell in the BILU(0) solves (size n). */

@@ -132,6 +132,8 @@ def load():
         L.cptr_learn_grad.argtypes = [vp, vp, ip, fp, fp, vp]
         L.cptr_learn_rerun_layer.argtypes = [vp, ip, vp, vp]
         L.cptr_learn_train_step.argtypes = [vp, vp, ip, C.c_float, fp, vp]
+        L.cptr_kernel_timing.argtypes = [vp, ip]
+        L.cptr_get_kernel_times.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_longlong)]
         ipp = C.POINTER(C.c_int)
         L.cptr_model_create.argtypes = [C.POINTER(vp), C.POINTER(ModelDesc)]
         L.cptr_model_destroy.argtypes = [vp]
@@ -302,6 +304,18 @@ def cptr_bsr_spmv(n, nv, row_ptr, col_idx, vals, x, y, stream=None):
     _check(load().cptr_bsr_spmv(n, nv, _ptr(row_ptr, torch.int32), _ptr(col_idx, torch.int32),
                                 _ptr(vals, torch.float64), _ptr(x, torch.float64),
                                 _ptr(y, torch.float64), _stream(stream)))
+
+
+def cptr_kernel_timing(h, enable):
+    _check(load().cptr_kernel_timing(h, int(bool(enable))))
+
+
+def cptr_get_kernel_times(h):
+    """(average us per launch, launches) of ids 0 (Krylov product), 1-3 (learned layers)."""
+    us = (C.c_double * 4)()
+    cnt = (C.c_longlong * 4)()
+    _check(load().cptr_get_kernel_times(h, us, cnt))
+    return list(us), list(cnt)
 
 
 def cptr_destroy(h):

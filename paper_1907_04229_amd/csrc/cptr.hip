@@ -778,6 +778,62 @@ static inline short host_bf16(float f) {
   return (short)(u >> 16);
 }
 
+// Per-launch timing of chosen kernels inside solves (roofline figures): HIP
+// events recorded around each launch on its stream, their elapsed times
+// summed when the solve has finished.  Ids: 0 the Krylov product w = A z,
+// 1..3 the learned stage's inference layers.
+struct KTimer {
+  static constexpr int kIds = 4;
+  bool on = false;
+  std::vector<hipEvent_t> pool;                   // reused event pairs
+  std::vector<std::pair<int, int>> pending;       // (id, pair index) not yet summed
+  double ms[kIds] = {0, 0, 0, 0};
+  long long count[kIds] = {0, 0, 0, 0};
+  ~KTimer() {
+    for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+  }
+  void reset() {
+    pending.clear();
+    for (int i = 0; i < kIds; i++) ms[i] = 0.0, count[i] = 0;
+  }
+  int begin(int id, hipStream_t st) {
+    const int pair = int(pending.size());
+    if (2 * pair + 2 > (int)pool.size())
+      for (int q = 0; q < 2; q++) {
+        hipEvent_t e;
+        CPTR_HIP_TRY(hipEventCreate(&e));
+        pool.push_back(e);
+      }
+    pending.push_back({id, pair});
+    CPTR_HIP_TRY(hipEventRecord(pool[2 * pair], st));
+    return pair;
+  }
+  void end(int pair, hipStream_t st) { CPTR_HIP_TRY(hipEventRecord(pool[2 * pair + 1], st)); }
+  void collect() {  // after the stream has finished the recorded work
+    for (const auto &q : pending) {
+      float t = 0.f;
+      CPTR_HIP_TRY(hipEventSynchronize(pool[2 * q.second + 1]));
+      CPTR_HIP_TRY(hipEventElapsedTime(&t, pool[2 * q.second], pool[2 * q.second + 1]));
+      ms[q.first] += t;
+      count[q.first]++;
+    }
+    pending.clear();
+  }
+};
+
+// times the launches made during its lifetime when the timer is on
+struct KTimeScope {
+  KTimer *t;
+  hipStream_t st;
+  int pair = -1;
+  KTimeScope(KTimer *t_, int id, hipStream_t st_) : t(t_), st(st_) {
+    if (t && t->on) pair = t->begin(id, st);
+  }
+  ~KTimeScope() {
+    if (pair >= 0) (void)hipEventRecord(t->pool[2 * pair + 1], st);
+  }
+};
+
 // Matrix-dependent data of the learned stage: neighbour table, BF16 edge
 // features D_i^{-1} A_{i,nbr(i,d)}, FP32 diagonal-block inverses, transpose
 // positions (for A^T in training), and work buffers.
@@ -790,6 +846,7 @@ struct LearnedDev {
   int colP = 0, colNZ = 0;
   bool use_col = true;
   bool have_pass = false;     // an inference pass has filled r, s, hA, hB
+  KTimer *timer = nullptr;    // the handle's kernel timer
   DevMem H[4], M[3], Aa[3], dh0, dh1, dm, dhown, z2, res, dz, part, mid;
   bool train_ready = false;
 
@@ -1000,6 +1057,7 @@ struct LearnedDev {
       // the layers after the first (whose input rows are nv floats, not 64
       // BF16 channels); about four waves per SIMD, each walking zlen planes
       // of one column
+      KTimeScope ts(timer, 1 + l, st);
       const int nchunk = std::max(1, std::min(colNZ, kColWaves / colP));
       const int zlen = (colNZ + nchunk - 1) / nchunk;
       const int items = colP * ((colNZ + zlen - 1) / zlen);
@@ -1015,6 +1073,7 @@ struct LearnedDev {
                            colP, colNZ, zlen, sy, Ep, sp, (const short *)hb, rp_, mdl.W_in(), We, Ws, Wm, bs,
                            (short *)nullptr, out);
     } else {
+      KTimeScope ts(timer, 1 + l, st);
       short *ha = devp<short>(hA), *hb = devp<short>(hB);
       if (l == 0) {
         if constexpr (NV == 3)  // held to three waves per SIMD (it would spill at NV = 4)
@@ -1279,6 +1338,7 @@ struct cptr_handle {
   std::unique_ptr<cptr::LearnedDev> lrn;  // learned-stage data of this matrix
   cptr_learn_model *model = nullptr;      // attached model (not owned)
   cptr::DevMem rs_flag, rs_work;          // numeric re-setup on the device: error bits, diag(A_pp)
+  cptr::KTimer ktime;                     // cptr_kernel_timing
 };
 
 struct cptr_learn_model {
@@ -1472,6 +1532,7 @@ static void build_precond(cptr_handle *h, const std::vector<int> &rp, const std:
   }
   if (o.second_stage == CPTR_SECOND_LEARNED) {
     h->lrn = std::make_unique<LearnedDev>();
+    h->lrn->timer = &h->ktime;
     h->lrn->build(n, nv, rp, ci, vals);
     h->lrn->use_col = o.lrn_columns != 0;
     P.lrn = h->lrn.get();
@@ -1808,7 +1869,10 @@ static void arnoldi_step(cptr_handle *h, const Kws &k, hipStream_t st) {
   LAUNCH_CHECK();
   h->pc->apply(st, sl, sizeof(ZT) == 8);
   // w = A z_j (the column address is read from the slots)
-  spmv_slot<ZT>(h, st, sl, k.w);
+  {
+    KTimeScope ts(&h->ktime, 0, st);
+    spmv_slot<ZT>(h, st, sl, k.w);
+  }
   const int *jd = &ks->j;
   hipLaunchKernelGGL((k_mdot<MAXK>), dim3(g), dim3(kBlock), 0, st, (const double *)k.V, N, jd, (const double *)k.w,
                      k.part);
@@ -1871,7 +1935,7 @@ static int fgmres_impl(cptr_handle *h, const Kws &k, const double *b, double *x,
     CPTR_HIP_TRY(hipStreamSynchronize(st));
     return CPTR_OK;
   }
-  const bool use_graph = k.graphs && h->op.o.use_graph != 0;
+  const bool use_graph = k.graphs && h->op.o.use_graph != 0 && !h->ktime.on;  // events are not captured
   auto step = [&]() {
     if (m <= 32) arnoldi_step<ZT, 32>(h, k, st);
     else arnoldi_step<ZT, 64>(h, k, st);
@@ -2071,6 +2135,7 @@ static void ensure_learned_data(cptr_handle *h) {
   CPTR_HIP_TRY(hipMemcpy(ci.data(), h->ci, sizeof(int) * nnzb, hipMemcpyDeviceToHost));
   CPTR_HIP_TRY(hipMemcpy(vals.data(), h->vals, sizeof(double) * vals.size(), hipMemcpyDeviceToHost));
   h->lrn = std::make_unique<LearnedDev>();
+  h->lrn->timer = &h->ktime;
   h->lrn->build(n, nv, rp, ci, vals);
   h->lrn->use_col = h->op.o.lrn_columns != 0;
 }
@@ -2378,6 +2443,7 @@ int fgmres_solve(cptr_handle *h, const double *b, double *x, const cptr_solve_op
     const Kws k = kws_of(h);
     int rc = h->op.o.precision == CPTR_FP32 ? fgmres_impl<float>(h, k, b, x, so, info, (hipStream_t)stream)
                                             : fgmres_impl<double>(h, k, b, x, so, info, (hipStream_t)stream);
+    if (h->ktime.on) h->ktime.collect();
     if (info_out) *info_out = info;
     return rc;
   } catch (const Error &e) {
@@ -2385,6 +2451,32 @@ int fgmres_solve(cptr_handle *h, const double *b, double *x, const cptr_solve_op
     return fail(e);
   } catch (...) {
     return fail(Error{CPTR_ERR_HIP, "unexpected failure in fgmres_solve"});
+  }
+}
+
+int cptr_kernel_timing(cptr_handle *h, int enable) {
+  if (!h) return fail(Error{CPTR_ERR_INVALID_ARG, "null argument"});
+  try {
+    if (enable) h->ktime.reset();
+    else h->ktime.collect();
+    h->ktime.on = enable != 0;
+    return CPTR_OK;
+  } catch (const Error &e) {
+    return fail(e);
+  }
+}
+
+int cptr_get_kernel_times(cptr_handle *h, double *avg_us, long long *launches) {
+  if (!h) return fail(Error{CPTR_ERR_INVALID_ARG, "null argument"});
+  try {
+    h->ktime.collect();
+    for (int i = 0; i < KTimer::kIds; i++) {
+      if (avg_us) avg_us[i] = h->ktime.count[i] ? 1e3 * h->ktime.ms[i] / double(h->ktime.count[i]) : 0.0;
+      if (launches) launches[i] = h->ktime.count[i];
+    }
+    return CPTR_OK;
+  } catch (const Error &e) {
+    return fail(e);
   }
 }
 

@@ -59,8 +59,8 @@ def test_copy_reference_uses_the_largest_dispatches(tmp_path):
         rows = [("__amd_rocclr_copyBuffer", 512, counter, 3.0)] * 5 + [("__amd_rocclr_copyBuffer", 131072, counter, big)] * 3
         for key, k in ((0, "void cptr::k_lrn_layer_first<3, true, false, short, float, float>(int)"),
                        (1, "void cptr::k_lrn_layer_col<3, false, false, short, float, float>(int)"),
-                       (2, "void cptr::k_lrn_layer_col<3, false, true, short, double, double>(int)"),
-                       (3, "void cptr::k_bsr_spmv_sliced<3, double, true>(int)")):
+                       (2, "void cptr::k_lrn_layer_col<3, false, true, short, float, float>(int)"),
+                       (3, "void cptr::k_bsr_spmv_sliced<3, float, false>(int)")):
             rows.append((k, 4096, counter, 1024.0 * (key + 1)))
         c.executemany("insert into counters_collection values (?, ?, ?, ?)", rows)
         c.commit()
@@ -78,9 +78,11 @@ def test_copy_reference_uses_the_largest_dispatches(tmp_path):
 
 
 def test_layer_method_bytes():
-    """The method's bytes per cell of the three learned layers: nv x nv BF16
-    edge blocks (no padding), BF16 activations, FP32 r, FP64 z2."""
+    """The method's bytes per cell of the three learned layers inside a solve:
+    nv x nv BF16 edge blocks (no padding), BF16 activations, FP32 r, the FP32
+    p and T components of x1 and the FP32 output z; and of the Krylov product."""
     assert bench.layer_method_bytes(1, 3) == 128 + 6 * 9 * 2 + 128
     assert bench.layer_method_bytes(0, 3) == 12 + 108 + 128
-    assert bench.layer_method_bytes(2, 3) == 128 + 108 + 12 + 24
+    assert bench.layer_method_bytes(2, 3) == 128 + 108 + 12 + 8 + 12
     assert bench.layer_method_bytes(1, 4) == 128 + 6 * 16 * 2 + 128
+    assert bench.product_method_bytes(10, 40, 3) == 40 * 76 + 44 + 10 * 3 * 12

@@ -419,3 +419,29 @@ def test_learned_stage_in_fgmres_and_fallback():
         s.solve(torch.as_tensor(pr.b, device=DEV), restart=30, rtol=1e-6)
     assert e.value.code == -3
     s.close()
+
+
+def test_kernel_timing_counts_and_leaves_results_unchanged():
+    """cptr_kernel_timing: one timed launch of the Krylov product per Arnoldi
+    step run and of each learned layer per application, positive durations,
+    and the same solution bit for bit as the solve with graph replay."""
+    banner("kernel timing")
+    pr = case("nv3c")[0]
+    s, m = solver_with(pr, neumann_params(pr.nv, seed=1), precision="fp32", second_stage="learned")
+    b = torch.as_tensor(pr.b, device=DEV)
+    x0, i0 = s.solve(b, restart=30, rtol=1e-6)
+    assert not i0["fell_back"]
+    cptr.cptr_kernel_timing(s.h, True)
+    x1, i1 = s.solve(b, restart=30, rtol=1e-6)
+    us, cnt = cptr.cptr_get_kernel_times(s.h)
+    cptr.cptr_kernel_timing(s.h, False)
+    print(f"iterations {i1['iters']}, launches {cnt}, us {us}")
+    assert torch.equal(x0, x1) and i0["iters"] == i1["iters"]
+    # a step enqueued ahead of the host's convergence test may run and be discarded at a cycle's end
+    assert i1["iters"] <= cnt[0] <= i1["iters"] + i1["restarts"] + 1
+    assert cnt[1] == cnt[2] == cnt[3] == cnt[0]
+    assert all(u > 0 for u in us)
+    x2, _ = s.solve(b, restart=30, rtol=1e-6)   # timing off: the totals stay
+    assert cptr.cptr_get_kernel_times(s.h)[1] == cnt
+    s.close()
+    m.close()
