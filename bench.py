@@ -463,7 +463,7 @@ def main():
                          "multiple of its lowest value (0: off)")
     ap.add_argument("--train-systems", type=int, default=8)
     ap.add_argument("--train-pairs", type=int, default=48)
-    ap.add_argument("--train-batch", type=int, default=8)
+    ap.add_argument("--train-batch", type=int, default=16)
     ap.add_argument("--first", default="cptr",
                     choices=["cptr", "cptr_lower", "cptr_upper", "cpr", "cptr_bd", "cptr_uamg"],
                     help="first stage of the learned and BILU(0)-FP32 legs (plain FP64 CPTR stays cptr)")
