@@ -404,7 +404,7 @@ def _mean_of(disp, name, largest_grid=False):
     return sum(x[1] for x in d) / len(d), len(d)
 
 
-def record_traffic(fetch_db, write_db, cells, nv):
+def record_traffic(fetch_db, write_db, cells, nv, nnzb=None):
     """Per-launch HBM bytes of the three learned layers and the Krylov
     product, as they run in the timed solve, from a FETCH_SIZE and a
     WRITE_SIZE pass over `bench.py --probe`,
@@ -413,7 +413,8 @@ def record_traffic(fetch_db, write_db, cells, nv):
     to TRAFFIC_FILE."""
     fetch = _counter_dispatches(fetch_db, "FETCH_SIZE")
     write = _counter_dispatches(write_db, "WRITE_SIZE")
-    copy = [k for k in fetch if "copyBuffer" in k or "elementwise_kernel" in k]
+    # the runtime's copy kernel (not the fill that made the source tensor)
+    copy = [k for k in fetch if "copyBuffer" in k] or [k for k in fetch if "copy" in k.lower()]
     assert copy, "no device copy in the counter runs"
     ck = max(copy, key=lambda k: max(x[0] for x in fetch[k]))
     kib = COPY_BYTES / 1024.0
@@ -422,7 +423,8 @@ def record_traffic(fetch_db, write_db, cells, nv):
     fscale, wscale = kib / fcopy, kib / wcopy
     norm = lambda k: k.replace(" ", "")  # noqa: E731
     want = [(q, LAYER_KERNEL[q].format(nv=nv), "layer", cells * layer_method_bytes(q, nv)) for q in (0, 1, 2)]
-    want.append(("spmv", PRODUCT_KERNEL.format(nv=nv), "spmv", None))
+    want.append(("spmv", PRODUCT_KERNEL.format(nv=nv), "spmv",
+                 product_method_bytes(cells, nnzb, nv) if nnzb else None))
     kernels = []
     for key, tag, kind, method in want:
         names = [k for k in fetch if tag in norm(k)]
@@ -502,10 +504,11 @@ def main():
     parts = tuple(int(q) for q in args.parts.split("x"))
     if args.traffic:
         from paper_1907_04229_amd.synth.problem import CONFIGS
-        shape = CONFIGS[args.config]["shape"]
+        nx, ny, nz = CONFIGS[args.config]["shape"]
         nv = 4 if CONFIGS[args.config]["three_phase"] else 3
-        print(json.dumps(record_traffic(args.traffic[0], args.traffic[1], shape[0] * shape[1] * shape[2], nv),
-                         indent=1))
+        # blocks of the 7-point pattern: the diagonal and both directions of every face
+        nnzb = nx * ny * nz + 2 * ((nx - 1) * ny * nz + nx * (ny - 1) * nz + nx * ny * (nz - 1))
+        print(json.dumps(record_traffic(args.traffic[0], args.traffic[1], nx * ny * nz, nv, nnzb), indent=1))
         return
 
     import torch
