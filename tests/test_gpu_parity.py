@@ -47,6 +47,8 @@ SHAPES = {
                  heater=True),                                                       # 4480 cells
     "dia3": dict(shape=(17, 16, 16), kind="gaussian", sigma=2.0, corr_len=4.0, seed=26,
                  three_phase=True),                                                  # nv = 4
+    # a finest and a second AMG level above 2048 rows (Gauss-Seidel sweeps by launches)
+    "gs_large": dict(shape=(40, 40, 24), kind="gaussian", sigma=1.5, corr_len=4.0, seed=37),
 }
 
 
@@ -157,6 +159,37 @@ def test_vcycle_and_first_stage_fp64(name, first):
     cptr.cptr_first_stage(s.h, dev(v), x1)
     torch.cuda.synchronize()
     assert relerr(x1.cpu().numpy(), o.first_stage(v)) <= 1e-10
+    s.close()
+
+
+@pytest.mark.parametrize("name", ["ragged", "three", "gs_large"])
+def test_gauss_seidel_smoother_fp32(name):
+    """amg_smoother = GS with the FP32 preconditioner: V-cycles of both
+    hierarchies and the first stage within the FP32 bar of 1e-5 of the FP64
+    oracle with the same smoother, and FGMRES to rtol 1e-12 within 1e-8 of
+    the oracle's solution (the bar of the FP32 Jacobi smoother: the solve
+    corrects the preconditioner's FP32 rounding)."""
+    banner(f"gauss-seidel fp32 {name}")
+    pr = prob(name)
+    s = solver(pr, precision="fp32", second_stage="bilu0", amg_smoother="gs", amg_coarse_size=16)
+    o = O.Oracle.from_problem(pr, first="cptr", second="bilu0", coarse_size=16, smoother="gs")
+    rng = np.random.default_rng(29)
+    for which in (0, 1):
+        b = rng.standard_normal(pr.n)
+        x = torch.empty(pr.n, dtype=torch.float64, device=DEV)
+        cptr.cptr_vcycle(s.h, which, dev(b), x)
+        torch.cuda.synchronize()
+        assert relerr(x.cpu().numpy(), o.vcycle(which, b)) <= 1e-5
+    v = rng.standard_normal(pr.n * pr.nv)
+    x1 = torch.empty_like(dev(v))
+    cptr.cptr_first_stage(s.h, dev(v), x1)
+    torch.cuda.synchronize()
+    assert relerr(x1.cpu().numpy(), o.first_stage(v)) <= 1e-5
+    xg, info = s.solve(dev(pr.b), restart=30, rtol=1e-12, maxit=600)
+    xo, io = o.fgmres(pr.b, m=30, rtol=1e-12, maxit=600)
+    err = np.linalg.norm(xg.cpu().numpy() - xo) / np.linalg.norm(xo)
+    print(f"iters gpu {info['iters']} oracle {io['iters']} err {err:.2e}")
+    assert info["converged"] and err <= 1e-8
     s.close()
 
 
@@ -357,11 +390,7 @@ def test_gauss_seidel_smoother_fp64(name, first):
     average take a wavefront each.  gs_large has a finest level and a second
     level (long rows) above 2048 rows."""
     banner(f"gauss-seidel smoother {first} {name}")
-    if name == "gs_large":
-        pr = make_problem(shape=(40, 40, 24), kind="gaussian", sigma=1.5, corr_len=4.0, seed=37)
-        assert pr.n > 2048
-    else:
-        pr = prob(name)
+    pr = prob(name)
     s = solver(pr, precision="fp64", first_stage=first, second_stage="bilu0", amg_smoother="gs",
                amg_coarse_size=16)
     o = O.Oracle.from_problem(pr, first=first, second="bilu0", coarse_size=16, smoother="gs")
