@@ -102,9 +102,11 @@ void cptr_newton_default_options(cptr_newton_opts *o);
  * on this model's pattern, and from then on borrows the model's value
  * arrays), solve J dx = -F*(x) with fgmres_solve from dx = 0, then try
  * x + lambda dx for lambda = 1, 1/2, ... until ||F*(x + lambda dx)|| <=
- * (1 - 1e-4 lambda) ||F*(x)||.  x (n nv): the initial guess on entry, the
- * last accepted iterate on return; xn: the previous step's state.  Blocking.
- * Errors of the re-setup or of the linear solver are returned as theirs. */
+ * (1 - 1e-4 lambda) ||F*(x)||.  A linear solve that stops at its iteration
+ * limit still gives the step (inexact Newton).  x (n nv): the initial guess
+ * on entry, the last accepted iterate on return; xn: the previous step's
+ * state.  Blocking.  Errors of the re-setup or of the linear solver are
+ * returned as theirs; a non-finite initial residual is CPTR_ERR_NONFINITE. */
 int cptr_newton_solve(cptr_model *m, cptr_handle *h, double *x, const double *xn, const cptr_newton_opts *o,
                       cptr_newton_info *info, void *stream);
 

@@ -2189,12 +2189,14 @@ static void refresh_precond(cptr_handle *h, Precond<T> &P, const double *A, cons
     LAUNCH_CHECK();
   }
   if (fs != CPTR_FIRST_NONE) {
-    auto &N0 = P.amg_p.num.at(0);
+    if (P.amg_p.num.empty() || (P.have_s && P.amg_s.num.empty()))
+      throw Error{CPTR_ERR_SETUP, "no device re-setup plan in this handle"};
+    auto &N0 = P.amg_p.num[0];
     hipLaunchKernelGGL(k_rs_strided, dim3(nblk(nnzb)), dim3(kBlock), 0, st, (size_t)nnzb, A, b2, o.ip * nv + o.ip,
                        devp<double>(N0.a_v));
     LAUNCH_CHECK();
     if (P.have_s) {
-      auto &S0 = P.amg_s.num.at(0);
+      auto &S0 = P.amg_s.num[0];
       if (fs == CPTR_FIRST_BD || o.schur == CPTR_SCHUR_ATT) {
         hipLaunchKernelGGL(k_rs_strided, dim3(nblk(nnzb)), dim3(kBlock), 0, st, (size_t)nnzb, A, b2,
                            o.iT * nv + o.iT, devp<double>(S0.a_v));
