@@ -2639,6 +2639,8 @@ int cptr_update_values(cptr_handle *h, const double *A_vals, const double *S_val
     return fail(e);
   } catch (const std::bad_alloc &) {
     return fail(Error{CPTR_ERR_OOM, "host allocation failed"});
+  } catch (...) {
+    return fail(Error{CPTR_ERR_HIP, "unexpected failure"});
   }
 }
 
@@ -2965,6 +2967,8 @@ int cptr_model_create(cptr_model **out, const cptr_model_desc *d) {
     return fail(e);
   } catch (const std::bad_alloc &) {
     return fail(Error{CPTR_ERR_OOM, "host allocation failed"});
+  } catch (...) {
+    return fail(Error{CPTR_ERR_HIP, "unexpected failure"});
   }
 }
 
@@ -3085,6 +3089,8 @@ int cptr_newton_solve(cptr_model *m, cptr_handle *h, double *x, const double *xn
     return fail(e);
   } catch (const std::bad_alloc &) {
     return fail(Error{CPTR_ERR_OOM, "host allocation failed"});
+  } catch (...) {
+    return fail(Error{CPTR_ERR_HIP, "unexpected failure"});
   }
 }
 
