@@ -19,6 +19,8 @@
 //   D (16 x 16):  lane holds D[4 (l / 16) + q][l % 16]   (q = register)
 #pragma once
 
+#include <type_traits>
+
 namespace cptr {
 
 constexpr int kHid = 64;   // hidden width
@@ -374,13 +376,34 @@ __device__ __forceinline__ void layer_setup(short (&Wl)[2][kHid][kWPad], float (
   }
 }
 
+// A tile's own activations as layer_tile reads them: four FP32 quads (the
+// first layer's h0, FP32 activations), or the BF16 row itself, widened where
+// it is used.  BF16 -> FP32 -> BF16 is exact, so the BF16 operand of W_s is
+// the row as loaded; keeping only the row spares the 16 registers of a
+// widened copy in the inference layers.
+struct OwnF32 {
+  f32x4 v[4];
+  __device__ __forceinline__ f32x4 get(int t) const { return v[t]; }
+  __device__ __forceinline__ bf16x8 pair(int ks) const {
+    return cat8(cvt4(v[2 * ks][0], v[2 * ks][1], v[2 * ks][2], v[2 * ks][3]),
+                cvt4(v[2 * ks + 1][0], v[2 * ks + 1][1], v[2 * ks + 1][2], v[2 * ks + 1][3]));
+  }
+};
+struct OwnBF16 {
+  bf16x4 v[4];
+  __device__ __forceinline__ f32x4 get(int t) const {
+    return f32x4{bf2f(v[t][0]), bf2f(v[t][1]), bf2f(v[t][2]), bf2f(v[t][3])};
+  }
+  __device__ __forceinline__ bf16x8 pair(int ks) const { return cat8(v[2 * ks], v[2 * ks + 1]); }
+};
+
 // The arithmetic of one tile, shared by both layer kernels: given the cell's
 // activations hv, the raw activations of its six neighbours (direction d =
 // -x, +x, -y, +y, -z, +z; for an absent neighbour any finite row, its edge
 // block being zero) and the six edge blocks, form the messages, the K = 32
 // products, the update and the stores.  Lanes with ok == false store nothing.
-template <int NV, bool FIRST, bool LAST, typename HT, typename ZT, typename XT>
-__device__ __forceinline__ void layer_tile(int cell, bool ok, int lr, int lg, const f32x4 (&hv)[4],
+template <int NV, bool FIRST, bool LAST, typename HT, typename ZT, typename XT, typename OWN>
+__device__ __forceinline__ void layer_tile(int cell, bool ok, int lr, int lg, const OWN &hv,
                                            const typename RawAct<HT, NV, FIRST>::type (&raw)[kDir],
                                            const bf16x4 (&rawe)[kDir], const LaneOps<NV> &ops,
                                            const LaneOps<NV> &ops_lds,
@@ -425,8 +448,7 @@ __device__ __forceinline__ void layer_tile(int cell, bool ok, int lr, int lg, co
 #pragma unroll
   for (int ks = 0; ks < 2; ks++) {
     // B operands: channels 32 ks + 8 lg .. + 7 = slots 2 ks, 2 ks + 1
-    const bf16x8 hb = cat8(cvt4(hv[2 * ks][0], hv[2 * ks][1], hv[2 * ks][2], hv[2 * ks][3]),
-                           cvt4(hv[2 * ks + 1][0], hv[2 * ks + 1][1], hv[2 * ks + 1][2], hv[2 * ks + 1][3]));
+    const bf16x8 hb = hv.pair(ks);
     const bf16x8 mb = cat8(cvt4(macc[2 * ks][0], macc[2 * ks][1], macc[2 * ks][2], macc[2 * ks][3]),
                            cvt4(macc[2 * ks + 1][0], macc[2 * ks + 1][1], macc[2 * ks + 1][2], macc[2 * ks + 1][3]));
 #pragma unroll
@@ -445,14 +467,14 @@ __device__ __forceinline__ void layer_tile(int cell, bool ok, int lr, int lg, co
 #pragma unroll
     for (int q = 0; q < 4; q++) {
       a[q] = acc[t][q] + bias[lch(t, lg) + q];
-      hnew[t][q] = hv[t][q] + fmaxf(a[q], 0.f);
+      hnew[t][q] = hv.get(t)[q] + fmaxf(a[q], 0.f);
     }
     if (ok) {
       const size_t o = (size_t)cell * kHid + lch(t, lg);
       if (hout) store_h4(hout + h_off(hout, cell, lch(t, lg)), hnew[t]);
       if (m_out) store_f4(m_out + o, macc[t]);
       if (a_out) store_f4(a_out + o, a);
-      if (FIRST && h0_out) store_f4(h0_out + o, hv[t]);
+      if (FIRST && h0_out) store_f4(h0_out + o, hv.get(t));
     }
   }
   if constexpr (LAST) {
@@ -543,9 +565,9 @@ __device__ __forceinline__ void lrn_layer_tiles(
     // the bias and the lane operands in the loop
     int z0 = 0;
     asm volatile("" : "+v"(z0));
-    f32x4 hv[4];
+    OwnF32 hv;
 #pragma unroll
-    for (int t = 0; t < 4; t++) hv[t] = Raw::get(own, t, lg, FIRST ? Win_s + z0 : W_in, inv_s);
+    for (int t = 0; t < 4; t++) hv.v[t] = Raw::get(own, t, lg, FIRST ? Win_s + z0 : W_in, inv_s);
     layer_tile<NV, FIRST, LAST, HT, ZT, XT>(cell, ok, lr, lg, hv, raw, rawe, ops, ops_s[l + z0], Wl, W_in,
                                            inv_s, bias_s + z0, r, s_ptr, hout, h0_out, m_out, a_out, out, zout);
   }
@@ -647,14 +669,21 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))
       raw[1] = shuffle_row<RT, kDppRowShl1>(rc, xe);
       raw[4] = rp;
       raw[5] = rn;
-      f32x4 hv[4];
-#pragma unroll
-      for (int t = 0; t < 4; t++) hv[t] = Raw::get(rc, t, lg, W_in, inv_s);
       int z0 = 0;  // keeps the LDS reads of the bias and the lane operands in the loop
       asm volatile("" : "+v"(z0));
-      layer_tile<NV, FIRST, LAST, HT, ZT, XT>(cell, true, lr, lg, hv, raw, rawe, ops, ops_s[l + z0], Wl, W_in,
-                                             inv_s, bias_s + z0, r, s_ptr, hout, nullptr, nullptr, nullptr, out,
-                                             zout);
+      if constexpr (!FIRST && std::is_same_v<HT, short>) {
+        const OwnBF16 hv{{rc.v[0], rc.v[1], rc.v[2], rc.v[3]}};
+        layer_tile<NV, FIRST, LAST, HT, ZT, XT>(cell, true, lr, lg, hv, raw, rawe, ops, ops_s[l + z0], Wl, W_in,
+                                               inv_s, bias_s + z0, r, s_ptr, hout, nullptr, nullptr, nullptr, out,
+                                               zout);
+      } else {
+        OwnF32 hv;
+#pragma unroll
+        for (int t = 0; t < 4; t++) hv.v[t] = Raw::get(rc, t, lg, W_in, inv_s);
+        layer_tile<NV, FIRST, LAST, HT, ZT, XT>(cell, true, lr, lg, hv, raw, rawe, ops, ops_s[l + z0], Wl, W_in,
+                                               inv_s, bias_s + z0, r, s_ptr, hout, nullptr, nullptr, nullptr, out,
+                                               zout);
+      }
       rp = rc;
       rc = rn;
     }
