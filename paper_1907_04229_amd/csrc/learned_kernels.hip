@@ -413,6 +413,18 @@ __device__ __forceinline__ void layer_tile(int cell, bool ok, int lr, int lg, co
                                            HT *__restrict__ hout, float *__restrict__ h0_out,
                                            float *__restrict__ m_out, float *__restrict__ a_out,
                                            const LrnOut<ZT, XT> &out, ZT *__restrict__ zout) {
+  // the last layer's output terms of component k = lg of the cell (r_k, s_k
+  // and x1's p or T part), loaded before the matrix work so that their
+  // latency overlaps it
+  float rpre = 0.f, spre = 0.f, xpre = 0.f;
+  if constexpr (LAST) {
+    if (ok && lg < NV) {
+      rpre = r[(size_t)cell * NV + lg];
+      spre = s_ptr[lg];
+      if (!out.z2_out && out.dp && lg == out.ip) xpre = float(out.dp[cell]);
+      if (!out.z2_out && out.dT && lg == out.iT) xpre = float(out.dT[cell]);
+    }
+  }
   __builtin_amdgcn_sched_barrier(0);
   f32x4 macc[4];
 #pragma unroll
@@ -488,18 +500,22 @@ __device__ __forceinline__ void layer_tile(int cell, bool ok, int lr, int lg, co
                                   hnew[2 * ks + 1][3]));
       ro = mfma32(ops_lds.wout[ks], hb, ro);
     }
-    if (ok && lg == 0) {
+    // component k of column lr moves to lane (lr, k): the lanes of a tile
+    // then store nv consecutive values per cell
+    float rk = 0.f;
 #pragma unroll
-      for (int k = 0; k < NV; k++) {
-        const size_t t = (size_t)cell * NV + k;
-        float z = r[t] + s_ptr[k] * ro[k];
-        if (out.z2_out) {
-          out.z2_out[t] = z;
-        } else {
-          if (out.dp && k == out.ip) z += float(out.dp[cell]);
-          if (out.dT && k == out.iT) z += float(out.dT[cell]);
-          zout[t] = ZT(z);
-        }
+    for (int k = 0; k < NV; k++) {
+      const float v = __shfl(ro[k], lr, 64);
+      if (lg == k) rk = v;
+    }
+    if (ok && lg < NV) {
+      const size_t t = (size_t)cell * NV + lg;
+      float z = rpre + spre * rk;
+      if (out.z2_out) {
+        out.z2_out[t] = z;
+      } else {
+        if ((out.dp && lg == out.ip) || (out.dT && lg == out.iT)) z += xpre;
+        zout[t] = ZT(z);
       }
     }
   }
