@@ -262,7 +262,9 @@ struct RawAct<HT, NV, true> {
 // 4 lg .. 4 lg + 3 of cell lr (the B operand of the edge gate) with one
 // 8-byte load: each group of 16 lanes reads 128 contiguous bytes; entries
 // past nv^2 are zero.  (Loading the ninth entry alone, 2 bytes per lane, in a
-// second instruction is slower.)  Cells past n (last tile) hold zeros.
+// second instruction is slower, and so is a run of exactly nv^2 entries per
+// cell with the six ninth entries in one 12-byte load.)  Cells past n (last
+// tile) hold zeros.
 template <int NV>
 constexpr int kEdgeRun = NV == 3 ? 192 : 256;
 
@@ -273,9 +275,10 @@ __device__ __forceinline__ bf16x4 load_edge_tiled(const short *__restrict__ Et, 
   if constexpr (NV == 4) {
     return __builtin_nontemporal_load(reinterpret_cast<const bf16x4 *>(run + lg * 64 + lr * 4));
   } else {
-    bf16x4 e = {0, 0, 0, 0};
-    if (lg < 3) e = __builtin_nontemporal_load(reinterpret_cast<const bf16x4 *>(run + lg * 64 + lr * 4));
-    return e;
+    // lane group 3 reads group 2's values again: they meet the zero columns
+    // (k >= nv^2) of the W_e operand.  No branch or select on the loaded
+    // value, so no wait for it before its use
+    return __builtin_nontemporal_load(reinterpret_cast<const bf16x4 *>(run + min(lg, 2) * 64 + lr * 4));
   }
 }
 
