@@ -247,7 +247,8 @@ def train_model(cfg, steps, lr, systems, pairs, batch, first, log_fn, lr_final=N
     t0 = time.perf_counter()
     model, hist = train(probs, probs[0].nv, steps=steps, batch=batch, pairs=pairs, lr=lr, seed=1,
                         eval_every=50, val_problems=vprobs, val_restart=cfg["restart"], rollback=rollback,
-                        lr_final=lr_final, precision="fp32", second_stage="bilu0_mc", first_stage=first)
+                        lr_final=lr_final, precision="fp32", second_stage="bilu0_mc", first_stage=first,
+                        log=log_fn)
     t_train = time.perf_counter() - t0
     log_fn(f"trained {steps} steps in {t_train:.1f} s (data {t_gen:.1f} s); validation "
            f"{[(k, round(v, 4), it) for k, v, it in hist['val']]}, kept step {hist['best_step']}")
