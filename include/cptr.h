@@ -317,7 +317,9 @@ int cptr_matvec(const cptr_handle *h, const double *x, double *y, void *stream);
 /* Copy the Arnoldi basis vector v_j of the most recent FGMRES cycle (device
  * FP64 [n*nv], orthonormal in the 2-norm; Section 3, right-preconditioned
  * GMRES) into `out` (device FP64 [n*nv], caller-owned), ordered on `stream`.
- * These are the vectors the preconditioner was applied to, e.g. training
+ * The preconditioner of step j was applied to v_j before its second
+ * Gram-Schmidt projection and normalisation (a multiple of v_j up to a
+ * rounding-level correction), so these stand for its inputs, e.g. training
  * inputs for a learned second stage.  Valid for 0 <= j <= restart after a
  * fgmres_solve with that restart length; only j < (iterations of the last
  * cycle) hold basis vectors of that solve.  CPTR_ERR_INVALID_ARG for a

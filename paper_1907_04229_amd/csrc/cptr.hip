@@ -1847,7 +1847,7 @@ static void norm2(const Kws &k, hipStream_t st, const double *x, size_t N, int s
   const int g = sgrid(N);
   hipLaunchKernelGGL(k_norm2_partial, dim3(g), dim3(kBlock), 0, st, x, N, k.part);
   hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlock), 0, st, (const double *)k.part, g, (const int *)nullptr, 1,
-                     k.scal + slot, 1);
+                     k.scal + slot, 1, (const double *)nullptr);
   LAUNCH_CHECK();
 }
 
@@ -1873,19 +1873,23 @@ static void arnoldi_step(cptr_handle *h, const Kws &k, hipStream_t st) {
     KTimeScope ts(&h->ktime, 0, st);
     spmv_slot<ZT>(h, st, sl, k.w);
   }
+  // CGS2 in two passes over the basis (k_mdot_fix): pass 1 finishes column j
+  // (the second projection and normalisation left by step j - 1) and forms
+  // h1 = V^T w and ||w||^2; pass 2 forms w' = w - V h1, h2 = V^T w', ||w'||^2
+  // and leaves w' / ||w|| as column j + 1; the rotation step takes
+  // hn = ||w' - V h2|| from the norms
   const int *jd = &ks->j;
-  hipLaunchKernelGGL((k_mdot<MAXK>), dim3(g), dim3(kBlock), 0, st, (const double *)k.V, N, jd, (const double *)k.w,
-                     k.part);
-  hipLaunchKernelGGL(k_reduce, dim3(MAXK), dim3(kBlock), 0, st, (const double *)k.part, g, jd, 0, k.h1, 0);
   double *w2_part = k.part + (size_t)kMaxRestart * kDotBlocks;  // the row after the longest basis
-  hipLaunchKernelGGL((k_cgs_update_mdot<MAXK>), dim3(g), dim3(kBlock), 0, st, (const double *)k.V, N, jd,
-                     (const double *)k.h1, k.w, k.part, w2_part);
-  hipLaunchKernelGGL(k_reduce, dim3(MAXK), dim3(kBlock), 0, st, (const double *)k.part, g, jd, 0, k.h2, 0);
-  // v_{j+1} = (w - V h2) / ||w - V h2|| (the norm from ||w||^2 - ||h2||^2), ||w - V h2|| into the state
-  hipLaunchKernelGGL((k_cgs_finish<MAXK>), dim3(g), dim3(kBlock), 0, st, k.V, N, ks, (const double *)k.h2,
-                     (const double *)k.w, (const double *)w2_part, g);
+  hipLaunchKernelGGL((k_mdot_fix<MAXK>), dim3(g), dim3(kBlock), 0, st, k.V, N, (const KState *)ks,
+                     (const double *)k.h2, (const double *)k.h1, (const double *)k.w, k.part, w2_part);
+  hipLaunchKernelGGL(k_reduce, dim3(MAXK + 1), dim3(kBlock), 0, st, (const double *)k.part, g, jd, 0, k.h1, 0,
+                     (const double *)w2_part);
+  hipLaunchKernelGGL((k_cgs_update_mdot<MAXK>), dim3(g), dim3(kBlock), 0, st, k.V, N, jd, (const double *)k.h1,
+                     (const double *)k.w, k.part, w2_part);
+  hipLaunchKernelGGL(k_reduce, dim3(MAXK), dim3(kBlock), 0, st, (const double *)k.part, g, jd, 0, k.h2, 0,
+                     (const double *)nullptr);
   hipLaunchKernelGGL(k_givens, dim3(1), dim3(64), 0, st, ks, (const double *)k.h1, (const double *)k.h2, k.R, k.cs,
-                     k.sn, k.g);
+                     k.sn, k.g, (const double *)w2_part, g);
   LAUNCH_CHECK();
 }
 

@@ -781,35 +781,79 @@ __device__ __forceinline__ void block_store_partials(double (&acc)[MAXK], int kk
   }
 }
 
-// partial[blk][k] = sum_i V[k][i] w[i], k <= j
+// Classical Gram-Schmidt with reorthogonalisation (CGS2) in two passes over
+// the basis per Arnoldi step.  Step j leaves the next basis column as
+// u = (w - V h1) / ||w|| (the first projection, scaled by the norm of w so
+// that the preconditioner's next input has norm <= 1), with h2 = V^T (w - V
+// h1) and hn = ||w - V h1 - V h2|| in the state; step j + 1 first applies
+// the second projection and the normalisation to it,
+//   v_{j+1} = (||w|| u - V h2) / hn,
+// in the pass over the basis it makes anyway.  The preconditioner of step
+// j + 1 receives u, not v_{j+1}: flexible GMRES needs only A z_{j+1} = w and
+// an orthonormal V in the Arnoldi relation, whatever the preconditioned
+// vectors are, and u differs from hn / ||w|| v_{j+1} by the second
+// projection alone, a rounding-level correction.
+
+// Pass 1 of step j: for j > 0 the correction of column j in place,
+//   V[j] <- (V[j] omega - sum_{k<j} h2p[k] V[k]) / hn   (omega^2 = h1[j] and
+//   hn = st->hn, both of step j - 1);
+// then partial[blk][k] = sum_i V[k][i] w[i] for k <= j, and w2_part[blk] =
+// sum_i w[i]^2.
 template <int MAXK>
-__global__ void __launch_bounds__(kBlock) k_mdot(const double *__restrict__ V, size_t N,
-                                                 const int *__restrict__ jdev,
-                                                 const double *__restrict__ w,
-                                                 double *__restrict__ part) {
-  const int kk = *jdev + 1;
-  double acc[MAXK];
+__global__ void __launch_bounds__(kBlock) k_mdot_fix(double *__restrict__ V, size_t N,
+                                                     const KState *__restrict__ st,
+                                                     const double *__restrict__ h2p,
+                                                     const double *__restrict__ h1p,
+                                                     const double *__restrict__ w, double *__restrict__ part,
+                                                     double *__restrict__ w2_part) {
+  const int J = st->j, kk = J + 1;
+  double hk[MAXK], acc[MAXK];
+  double accJ = 0.0, ww[1] = {0.0};
+  const bool fix = J > 0;
+  const double omega = fix ? sqrt(h1p[J]) : 1.0;
+  const double hn = st->hn;
+  const double inv = hn != 0.0 ? 1.0 / hn : 0.0;
 #pragma unroll
-  for (int k = 0; k < MAXK; k++) acc[k] = 0.0;
+  for (int k = 0; k < MAXK; k++) {
+    acc[k] = 0.0;
+    hk[k] = fix && k < J ? h2p[k] : 0.0;
+  }
+  double *__restrict__ vJ = V + (size_t)J * N;
   for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < N; i += (size_t)gridDim.x * kBlock) {
     // every load of the row is issued before the first product waits on one
     double vk[MAXK];
     const double wi = w[i];
+    double v = vJ[i];
 #pragma unroll
-    for (int k = 0; k < MAXK; k++) vk[k] = k < kk ? V[(size_t)k * N + i] : 0.0;
+    for (int k = 0; k < MAXK; k++) vk[k] = k < J ? V[(size_t)k * N + i] : 0.0;
+    if (fix) {
+      v = v * omega;
+#pragma unroll
+      for (int k = 0; k < MAXK; k++) v -= vk[k] * hk[k];
+      v = v * inv;
+      vJ[i] = v;
+    }
 #pragma unroll
     for (int k = 0; k < MAXK; k++) acc[k] += vk[k] * wi;
+    accJ += v * wi;
+    ww[0] += wi * wi;
   }
+#pragma unroll
+  for (int k = 0; k < MAXK; k++)
+    if (k == J) acc[k] = accJ;
   block_store_partials<MAXK>(acc, kk, part);
+  block_store_partials<1>(ww, 1, w2_part);
 }
 
-// w -= V h; then partial[blk][k] = sum_i V[k][i] w[i] (second Gram-Schmidt
-// pass) and w2_part[blk] = sum_i w[i]^2 of the updated w
+// Pass 2 of step j: w' = w - V h1 (columns k <= j); partial[blk][k] =
+// sum_i V[k][i] w'[i] (the second projection) and w2_part[blk] = sum_i
+// w'[i]^2; the next column V[j+1] = w' / ||w|| (||w||^2 = h1[j+1], from pass
+// 1; a zero w leaves a zero column).
 template <int MAXK>
-__global__ void __launch_bounds__(kBlock) k_cgs_update_mdot(const double *__restrict__ V, size_t N,
+__global__ void __launch_bounds__(kBlock) k_cgs_update_mdot(double *__restrict__ V, size_t N,
                                                             const int *__restrict__ jdev,
                                                             const double *__restrict__ h,
-                                                            double *__restrict__ w,
+                                                            const double *__restrict__ w,
                                                             double *__restrict__ part,
                                                             double *__restrict__ w2_part) {
   const int kk = *jdev + 1;
@@ -820,6 +864,9 @@ __global__ void __launch_bounds__(kBlock) k_cgs_update_mdot(const double *__rest
     acc[k] = 0.0;
     hk[k] = k < kk ? h[k] : 0.0;
   }
+  const double wn = sqrt(h[kk]);
+  const double inv = wn != 0.0 ? 1.0 / wn : 0.0;
+  double *__restrict__ vn = V + (size_t)kk * N;
   for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < N; i += (size_t)gridDim.x * kBlock) {
     double vk[MAXK];
     double wi = w[i];
@@ -828,74 +875,13 @@ __global__ void __launch_bounds__(kBlock) k_cgs_update_mdot(const double *__rest
       vk[k] = k < kk ? V[(size_t)k * N + i] : 0.0;
       wi -= vk[k] * hk[k];
     }
-    w[i] = wi;
+    vn[i] = wi * inv;
     ww[0] += wi * wi;
 #pragma unroll
     for (int k = 0; k < MAXK; k++) acc[k] += vk[k] * wi;
   }
   block_store_partials<MAXK>(acc, kk, part);
   block_store_partials<1>(ww, 1, w2_part);
-}
-
-// The sum of row[0 .. nblk-1] in a fixed order (thread t adds the entries
-// t, t + 256, ..., then a fixed tree), returned to every thread of the
-// workgroup; nblk <= kDotBlocks.
-__device__ __forceinline__ double block_reduce_row(const double *__restrict__ row, int nblk) {
-  __shared__ double sh[kBlock / 64];
-  __shared__ double tot;
-  constexpr int kPer = kDotBlocks / kBlock;
-  double v[kPer];
-#pragma unroll
-  for (int q = 0; q < kPer; q++) v[q] = row[min((int)threadIdx.x + q * kBlock, nblk - 1)];
-  double s = 0.0;
-#pragma unroll
-  for (int q = 0; q < kPer; q++)
-    if ((int)threadIdx.x + q * kBlock < nblk) s += v[q];
-  s = wave_sum(s);
-  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double t = 0.0;
-#pragma unroll
-    for (int w = 0; w < kBlock / 64; w++) t += sh[w];
-    tot = t;
-  }
-  __syncthreads();
-  return tot;
-}
-
-// The end of the second Gram-Schmidt pass: v_{j+1} = (w - V h2) / hn with
-// hn = ||w - V h2|| = sqrt(||w||^2 - ||h2||^2) (the basis is orthonormal and
-// h2 = V^T w), ||w||^2 reduced from the per-block partials of
-// k_cgs_update_mdot by every workgroup in the same fixed order; hn = 0 gives
-// a zero vector (breakdown).  Workgroup 0 stores hn in the Krylov state.
-template <int MAXK>
-__global__ void __launch_bounds__(kBlock) k_cgs_finish(double *__restrict__ V, size_t N, KState *__restrict__ st,
-                                                       const double *__restrict__ h,
-                                                       const double *__restrict__ w,
-                                                       const double *__restrict__ w2_part, int nblk) {
-  const int kk = st->j + 1;
-  double hk[MAXK];
-  double hh = 0.0;
-#pragma unroll
-  for (int k = 0; k < MAXK; k++) {
-    hk[k] = k < kk ? h[k] : 0.0;
-    hh += hk[k] * hk[k];
-  }
-  const double w2 = block_reduce_row(w2_part, nblk);
-  const double hn = sqrt(fmax(w2 - hh, 0.0));
-  const double inv = hn != 0.0 ? 1.0 / hn : 0.0;
-  if (blockIdx.x == 0 && threadIdx.x == 0) st->hn = hn;
-  double *vn = V + (size_t)kk * N;
-  for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < N; i += (size_t)gridDim.x * kBlock) {
-    double vk[MAXK];
-    double wi = w[i];
-#pragma unroll
-    for (int k = 0; k < MAXK; k++) vk[k] = k < kk ? V[(size_t)k * N + i] : 0.0;
-#pragma unroll
-    for (int k = 0; k < MAXK; k++) wi -= vk[k] * hk[k];
-    vn[i] = wi * inv;
-  }
 }
 
 // partial[blk][0] = sum_i x[i]^2
@@ -908,17 +894,19 @@ __global__ void __launch_bounds__(kBlock) k_norm2_partial(const double *__restri
 }
 
 // out[k] = sum_blk partial[k][blk] for k < kk (kk = *jdev + 1, or kfix when jdev is
-// null); one workgroup per k; fixed order: thread t sums blocks t, t+256, ...,
+// null), and out[kk] = the sum of the row `extra` when given; one workgroup per k; fixed order: thread t sums blocks t, t+256, ...,
 // then a fixed tree, so the result does not depend on scheduling.  The loads of
 // a thread (nblk <= kDotBlocks) are all issued before the first add.
 __global__ void __launch_bounds__(kBlock) k_reduce(const double *__restrict__ part, int nblk,
                                                    const int *__restrict__ jdev, int kfix,
-                                                   double *__restrict__ out, int sqrt_out) {
+                                                   double *__restrict__ out, int sqrt_out,
+                                                   const double *__restrict__ extra) {
   __shared__ double sh[kBlock / 64];
   const int kk = jdev ? *jdev + 1 : kfix;
   const int k = blockIdx.x;
-  if (k >= kk) return;
-  const double *__restrict__ row = part + (size_t)k * nblk;
+  // with `extra`, workgroup kk sums that row into out[kk]
+  if (k > kk || (k == kk && !extra)) return;
+  const double *__restrict__ row = k == kk ? extra : part + (size_t)k * nblk;
   constexpr int kPer = kDotBlocks / kBlock;
   double v[kPer];
 #pragma unroll
@@ -939,7 +927,8 @@ __global__ void __launch_bounds__(kBlock) k_reduce(const double *__restrict__ pa
 }
 
 
-// Hessenberg column j = h1 + h2 (0..j), hn (j+1); previous rotations, a new
+// Hessenberg column j = h1 + h2 (0..j), hn (j+1, computed here and kept in
+// the state for the next step's correction); previous rotations, a new
 // rotation, g update; j advances.  R is stored (m+1) x m row-major.  One
 // wavefront: the lanes load the column and the rotations into LDS, lane 0
 // applies them in order, the lanes store the column.
@@ -949,11 +938,25 @@ constexpr int kMaxRestart = 64;
 __global__ void __launch_bounds__(64) k_givens(KState *st, const double *__restrict__ h1,
                                                const double *__restrict__ h2, double *__restrict__ R,
                                                double *__restrict__ cs, double *__restrict__ sn,
-                                               double *__restrict__ g) {
+                                               double *__restrict__ g, const double *__restrict__ w2_part,
+                                               int nblk) {
   __shared__ double col[kMaxRestart + 1], c_[kMaxRestart], s_[kMaxRestart];
   if (blockIdx.x != 0 || st->stop) return;
   const int lane = threadIdx.x;
   const int j = st->j, m = st->m;
+  // hn = ||w' - V h2|| = sqrt(||w'||^2 - ||h2||^2) (V orthonormal, h2 = V^T w'),
+  // ||w'||^2 summed from the partials of pass 2 in a fixed order
+  {
+    double t = 0.0;
+    for (int b = lane; b < nblk; b += 64) t += w2_part[b];
+    t = wave_sum(t);
+    if (lane == 0) {
+      double hh = 0.0;
+      for (int k = 0; k <= j; k++) hh += h2[k] * h2[k];
+      st->hn = sqrt(fmax(t - hh, 0.0));
+    }
+    __syncthreads();
+  }
   for (int k = lane; k <= j; k += 64) col[k] = h1[k] + h2[k];
   for (int k = lane; k < j; k += 64) {
     c_[k] = cs[k];
