@@ -1875,9 +1875,9 @@ static void arnoldi_step(cptr_handle *h, const Kws &k, hipStream_t st) {
   }
   // CGS2 in two passes over the basis (k_mdot_fix): pass 1 finishes column j
   // (the second projection and normalisation left by step j - 1) and forms
-  // h1 = V^T w and ||w||^2; pass 2 forms w' = w - V h1, h2 = V^T w', ||w'||^2
-  // and leaves w' / ||w|| as column j + 1; the rotation step takes
-  // hn = ||w' - V h2|| from the norms
+  // h1 = V^T w and ||w||^2 (h1[j+1]); pass 2 forms w' = w - V h1, h2 = V^T w',
+  // ||w'||^2 (h2[j+1]) and leaves w' / ||w|| as column j + 1; the rotation
+  // step takes hn = ||w' - V h2|| from the norms
   const int *jd = &ks->j;
   double *w2_part = k.part + (size_t)kMaxRestart * kDotBlocks;  // the row after the longest basis
   hipLaunchKernelGGL((k_mdot_fix<MAXK>), dim3(g), dim3(kBlock), 0, st, k.V, N, (const KState *)ks,
@@ -1886,10 +1886,10 @@ static void arnoldi_step(cptr_handle *h, const Kws &k, hipStream_t st) {
                      (const double *)w2_part);
   hipLaunchKernelGGL((k_cgs_update_mdot<MAXK>), dim3(g), dim3(kBlock), 0, st, k.V, N, jd, (const double *)k.h1,
                      (const double *)k.w, k.part, w2_part);
-  hipLaunchKernelGGL(k_reduce, dim3(MAXK), dim3(kBlock), 0, st, (const double *)k.part, g, jd, 0, k.h2, 0,
-                     (const double *)nullptr);
+  hipLaunchKernelGGL(k_reduce, dim3(MAXK + 1), dim3(kBlock), 0, st, (const double *)k.part, g, jd, 0, k.h2, 0,
+                     (const double *)w2_part);
   hipLaunchKernelGGL(k_givens, dim3(1), dim3(64), 0, st, ks, (const double *)k.h1, (const double *)k.h2, k.R, k.cs,
-                     k.sn, k.g, (const double *)w2_part, g);
+                     k.sn, k.g);
   LAUNCH_CHECK();
 }
 

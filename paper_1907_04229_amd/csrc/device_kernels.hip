@@ -927,8 +927,8 @@ __global__ void __launch_bounds__(kBlock) k_reduce(const double *__restrict__ pa
 }
 
 
-// Hessenberg column j = h1 + h2 (0..j), hn (j+1, computed here and kept in
-// the state for the next step's correction); previous rotations, a new
+// Hessenberg column j = h1 + h2 (0..j), hn (j+1, computed here from h2 and
+// ||w'||^2 = h2[j+1], kept in the state for the next step's correction); previous rotations, a new
 // rotation, g update; j advances.  R is stored (m+1) x m row-major.  One
 // wavefront: the lanes load the column and the rotations into LDS, lane 0
 // applies them in order, the lanes store the column.
@@ -938,25 +938,19 @@ constexpr int kMaxRestart = 64;
 __global__ void __launch_bounds__(64) k_givens(KState *st, const double *__restrict__ h1,
                                                const double *__restrict__ h2, double *__restrict__ R,
                                                double *__restrict__ cs, double *__restrict__ sn,
-                                               double *__restrict__ g, const double *__restrict__ w2_part,
-                                               int nblk) {
+                                               double *__restrict__ g) {
   __shared__ double col[kMaxRestart + 1], c_[kMaxRestart], s_[kMaxRestart];
   if (blockIdx.x != 0 || st->stop) return;
   const int lane = threadIdx.x;
   const int j = st->j, m = st->m;
-  // hn = ||w' - V h2|| = sqrt(||w'||^2 - ||h2||^2) (V orthonormal, h2 = V^T w'),
-  // ||w'||^2 summed from the partials of pass 2 in a fixed order
-  {
-    double t = 0.0;
-    for (int b = lane; b < nblk; b += 64) t += w2_part[b];
-    t = wave_sum(t);
-    if (lane == 0) {
-      double hh = 0.0;
-      for (int k = 0; k <= j; k++) hh += h2[k] * h2[k];
-      st->hn = sqrt(fmax(t - hh, 0.0));
-    }
-    __syncthreads();
+  // hn = ||w' - V h2|| = sqrt(||w'||^2 - ||h2||^2) (V orthonormal, h2 = V^T w';
+  // ||w'||^2 in h2[j + 1], reduced with h2)
+  if (lane == 0) {
+    double hh = 0.0;
+    for (int k = 0; k <= j; k++) hh += h2[k] * h2[k];
+    st->hn = sqrt(fmax(h2[j + 1] - hh, 0.0));
   }
+  __syncthreads();
   for (int k = lane; k <= j; k += 64) col[k] = h1[k] + h2[k];
   for (int k = lane; k < j; k += 64) {
     c_[k] = cs[k];
