@@ -64,6 +64,11 @@ TRAIN_SHAPE = (64, 64, 32)
 HIDDEN = 64
 
 
+# options of every solver the benchmark sets up (and of the oracle's
+# hierarchy), from the command line
+AMG_OPTS = {}
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -160,7 +165,7 @@ def resetup_times(pr, solver_opts):
     from paper_1907_04229_amd import cptr
     out = {}
     for tag, dev in (("gpu_ms", 1), ("host_ms", 0)):
-        s = cptr.Solver(pr, resetup_device=dev, **solver_opts)
+        s = cptr.Solver(pr, resetup_device=dev, **AMG_OPTS, **solver_opts)
         for _ in range(3 if dev else 1):
             s.update_values(copy.copy(pr))
         out[tag] = round(cptr.cptr_get_stats(s.h)["setup_ms"], 1)
@@ -197,7 +202,7 @@ def newton_leg(cfg_name, log_fn):
     for tag, opts in (("fp32_cptr_bilu0_mc", dict(precision="fp32", second_stage="bilu0_mc")),
                       ("fp64_cptr_bilu0", dict(precision="fp64", second_stage="bilu0"))):
         x = x0.clone()
-        s = d.solver(x, x0, **opts)
+        s = d.solver(x, x0, **AMG_OPTS, **opts)
         info = d.newton(s, x, x0, max_it=20)
         log_fn(f"newton {tag}: {info['iters']} iterations ({info['lin_iters']} linear, {info['backtracks']} "
                f"halvings), {info['solve_ms']:.0f} ms, |F| {info['fnorm0']:.3e} -> {info['fnorm']:.3e}")
@@ -214,7 +219,8 @@ def cpu_baseline(pr, maxit=None):
     from oracle import oracle as O
     O.build(force=False)
     t0 = time.perf_counter()
-    o = O.Oracle.from_problem(pr, first="cptr", second="bilu0")
+    cs = AMG_OPTS.get("amg_coarse_size", 512)
+    o = O.Oracle.from_problem(pr, first="cptr", second="bilu0", coarse_size=cs)
     t_setup = time.perf_counter() - t0
     t0 = time.perf_counter()
     _, info = o.fgmres(pr.b, m=30, rtol=1e-6, maxit=maxit or 1000)
@@ -228,7 +234,8 @@ def cpu_baseline(pr, maxit=None):
     return dict(value=round(t, 3), unit="s", cores=1, host_cores=host, kind="oracle",
                 iters=info["iters"], converged=info["converged"], relres_true=info["relres_true"],
                 setup_s=round(t_setup, 2), cell_iters_per_s=round(pr.n * info["iters"] / t, 1),
-                sample=f"the whole {pr.n:,}-cell system, FP64 CPTR-Block(AMG)+BILU0(natural), FGMRES(30) "
+                sample=f"the whole {pr.n:,}-cell system, FP64 CPTR-Block(AMG, coarsest level <= {cs} rows)"
+                       f"+BILU0(natural), FGMRES(30) "
                        f"{done} ({info['iters']} inner iterations), setup ({t_setup:.1f} s) excluded, "
                        f"one thread of the host's {host}")
 
@@ -248,7 +255,7 @@ def train_model(cfg, steps, lr, systems, pairs, batch, first, log_fn, lr_final=N
     model, hist = train(probs, probs[0].nv, steps=steps, batch=batch, pairs=pairs, lr=lr, seed=1,
                         eval_every=50, val_problems=vprobs, val_restart=cfg["restart"], rollback=rollback,
                         lr_final=lr_final, precision="fp32", second_stage="bilu0_mc", first_stage=first,
-                        log=log_fn)
+                        log=log_fn, **AMG_OPTS)
     t_train = time.perf_counter() - t0
     log_fn(f"trained {steps} steps in {t_train:.1f} s (data {t_gen:.1f} s); validation "
            f"{[(k, round(v, 4), it) for k, v, it in hist['val']]}, kept step {hist['best_step']}")
@@ -284,7 +291,7 @@ def held_out_eval(cfg, model, restart, first, log_fn):
                               ("fp64_bilu0", dict(precision="fp64", second_stage="bilu0", first_stage="cptr"), None),
                               ("fp32_bilu0_mc", dict(precision="fp32", second_stage="bilu0_mc", first_stage=first),
                                None)):
-            s = cptr.Solver(pr, **opt)
+            s = cptr.Solver(pr, **AMG_OPTS, **opt)
             if mdl is not None:
                 mdl.attach(s)
             s.solve(b, restart=restart, rtol=1e-6)
@@ -313,7 +320,7 @@ def probe(cfg_name):
     from paper_1907_04229_amd.learned_init import neumann_params
     from paper_1907_04229_amd.synth import make_problem
     pr = make_problem(config=cfg_name)
-    s = cptr.Solver(pr, precision="fp32", second_stage="learned")
+    s = cptr.Solver(pr, precision="fp32", second_stage="learned", **AMG_OPTS)
     m = cptr.LearnModel(pr.nv, neumann_params(pr.nv, seed=1))
     m.attach(s)
     s.solve(torch.as_tensor(pr.b, device="cuda"), restart=30, rtol=1e-6, maxit=4)
@@ -336,7 +343,7 @@ def trace_solves(cfg_name):
     from paper_1907_04229_amd.synth import make_problem
     pr = make_problem(config=cfg_name)
     b = torch.as_tensor(pr.b, device="cuda")
-    s = cptr.Solver(pr, precision="fp32", second_stage="learned")
+    s = cptr.Solver(pr, precision="fp32", second_stage="learned", **AMG_OPTS)
     m = cptr.LearnModel(pr.nv, neumann_params(pr.nv, seed=1))
     m.attach(s)
     for k in range(2):
@@ -470,6 +477,9 @@ def main():
     ap.add_argument("--first", default="cptr",
                     choices=["cptr", "cptr_lower", "cptr_upper", "cpr", "cptr_bd", "cptr_uamg"],
                     help="first stage of the learned and BILU(0)-FP32 legs (plain FP64 CPTR stays cptr)")
+    ap.add_argument("--amg-coarse-size", type=int, default=1024,
+                    help="rows up to which an AMG level is the coarsest, solved with its explicit inverse "
+                         "(every solver of the run and the oracle's hierarchy)")
     ap.add_argument("--parts", default="16x16x1",
                     help="block-Jacobi grid parts of the partitioned BILU(0) legs (px x py x pz)")
     ap.add_argument("--cpu-iters", type=int, default=0,
@@ -489,6 +499,7 @@ def main():
                     help="per-kernel time of the last solve in a rocprofv3 kernel trace of --trace")
     ap.add_argument("--traffic", nargs=2, metavar=("FETCH_DB", "WRITE_DB"))
     args = ap.parse_args()
+    AMG_OPTS["amg_coarse_size"] = args.amg_coarse_size
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (the solver is a single-GPU library); "
               f"--gpus {args.gpus} is not supported", file=sys.stderr)
@@ -548,7 +559,7 @@ def main():
 
     def setup(prob, **opt):
         t0 = time.perf_counter()
-        s = cptr.Solver(prob, **opt)
+        s = cptr.Solver(prob, **AMG_OPTS, **opt)
         torch.cuda.synchronize()
         return s, time.perf_counter() - t0
 
@@ -694,7 +705,7 @@ def main():
         "config": {"workload": f"{args.config}: {'x'.join(map(str, cfg['shape']))} cells, nv={pr.nv}, "
                                f"FGMRES({restart}) rtol 1e-6, {FIRST_NAME[args.first]}(AMG) + learned "
                                f"second stage, FP32 preconditioner",
-                   "first_stage": args.first,
+                   "first_stage": args.first, "amg_coarse_size": args.amg_coarse_size,
                    "cells": pr.n, "nnzb": pr.nnzb, "restart": restart},
         "iters": info["iters"],
         "cell_iters_per_s": round(pr.n * info["iters"] / dt, 1),
