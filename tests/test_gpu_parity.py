@@ -712,6 +712,42 @@ def test_fgmres_tight_tolerance_solution_error():
     s.close()
 
 
+@pytest.mark.parametrize("name,precision,second", [("dia2", "fp64", "bilu0"), ("gs_large", "fp32", "bilu0_mc"),
+                                                    ("dia3", "fp32", "bilu0")])
+def test_krylov_basis_is_orthonormal(name, precision, second):
+    """The Arnoldi basis of a cycle is orthonormal to rounding.  The Gram-Schmidt
+    of an Arnoldi step projects twice (CGS2), the second projection and the
+    normalisation of each new vector applied in the next step's first pass over
+    the basis, so a mistake in that deferred correction (a wrong coefficient,
+    scale or column) leaves the basis non-orthogonal.  CGS2 keeps
+    ||I - V^T V|| at a modest multiple of the unit roundoff u = 1.1e-16 for a
+    numerically nonsingular sequence (Giraud, Langou and Rozloznik, 2005);
+    the bound 1e-12 (about 9000 u) covers up to 30 vectors.  One cycle of 12
+    steps at an unreachable tolerance, on systems of several thousand cells
+    whose preconditioner is not exact (its residual estimate stays far above
+    the tolerance: the estimate keeps falling past the rounding level of the
+    true residual, so a longer cycle, or a system whose hierarchies are a
+    single exactly inverted level, could end the cycle early and restart);
+    vectors j < 12 are that cycle's."""
+    banner(f"basis orthonormality {name} {precision} {second}")
+    pr = prob(name)
+    s = solver(pr, precision=precision, second_stage=second)
+    N = pr.n * pr.nv
+    _, info = s.solve(dev(pr.b), restart=30, rtol=1e-30, maxit=12)
+    k = info["iters"]
+    assert info["restarts"] == 0 and k == 12
+    V = torch.empty((k, N), dtype=torch.float64, device=DEV)
+    for j in range(k):
+        cptr.cptr_krylov_vector(s.h, j, V[j])
+    torch.cuda.synchronize()
+    Vh = V.cpu().numpy()
+    G = Vh @ Vh.T
+    err = float(np.abs(G - np.eye(k)).max())
+    print(f"max |I - V^T V| = {err:.2e} over {k} vectors")
+    assert err <= 1e-12
+    s.close()
+
+
 # ---------------------------------------------------------------- edge cases and errors
 def test_zero_rhs_and_iteration_cap():
     banner("zero rhs / maxit")
