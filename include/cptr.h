@@ -278,7 +278,10 @@ int cptr_vcycle(cptr_handle *h, int which, const double *b, double *x, void *str
 
 /* Right-preconditioned flexible GMRES(m) (Saad 1993) with the handle's
  * preconditioner; Arnoldi by classical Gram-Schmidt with one
- * re-orthogonalisation in FP64; stops when the Givens estimate reaches
+ * re-orthogonalisation in FP64 (two passes over the basis per step: the
+ * second projection and normalisation of each new basis vector are applied
+ * in the next step, after the preconditioner has been applied to the vector
+ * before them, which flexible GMRES permits); stops when the Givens estimate reaches
  * rtol ||b|| and the FP64 true residual confirms it, otherwise restarts.
  * b, x: device FP64 [n*nv]; x is the initial guess if so->nonzero_guess, and
  * is overwritten with the solution.  `so` NULL for defaults; `info` may be
