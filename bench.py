@@ -144,6 +144,10 @@ def in_solve_rooflines(solver, rhs, restart, solves=2):
     cptr.cptr_kernel_timing(solver.h, False)
     rows = []
     for kid in range(4):
+        # a kernel that did not run (the layers, once the learned stage has
+        # fallen back to BILU(0)) has no row
+        if cnt[kid] == 0 or not us[kid] > 0.0:
+            continue
         if kid == 0:
             algo = product_method_bytes(n, nnzb, nv)
             name, per_cell, key = PRODUCT_KERNEL.format(nv=nv), None, "spmv"

@@ -86,3 +86,18 @@ def test_layer_method_bytes():
     assert bench.layer_method_bytes(2, 3) == 128 + 108 + 12 + 8 + 12
     assert bench.layer_method_bytes(1, 4) == 128 + 6 * 16 * 2 + 128
     assert bench.product_method_bytes(10, 40, 3) == 40 * 76 + 44 + 10 * 3 * 12
+
+
+def test_in_solve_rooflines_skip_kernels_that_did_not_run(monkeypatch):
+    """Once the learned stage has fallen back to BILU(0) no layer runs inside
+    the timed solves: only the Krylov product gets a roofline row."""
+    from types import SimpleNamespace
+    from paper_1907_04229_amd import cptr
+    monkeypatch.setattr(cptr, "cptr_kernel_timing", lambda h, on: None)
+    monkeypatch.setattr(cptr, "cptr_get_kernel_times", lambda h: ([116.0, 0.0, 0.0, 0.0], [60, 0, 0, 0]))
+    monkeypatch.setattr(bench, "recorded_traffic", lambda key, n, nv: None)
+    solver = SimpleNamespace(problem=SimpleNamespace(n=1000, nv=4, nnzb=7000), h=None,
+                             solve=lambda *a, **k: None)
+    rows = bench.in_solve_rooflines(solver, None, 30)
+    assert [r["layer"] for r in rows] == [None]
+    assert rows[0]["launches"] == 60 and rows[0]["achieved"] > 0
