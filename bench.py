@@ -246,7 +246,8 @@ def cpu_baseline(pr, maxit=None):
                        f"one thread of the host's {host}")
 
 
-def train_model(cfg, steps, lr, systems, pairs, batch, first, log_fn, lr_final=None, rollback=None):
+def train_model(cfg, steps, lr, systems, pairs, batch, first, log_fn, lr_final=None, rollback=None,
+                init="neumann"):
     from paper_1907_04229_amd.learned import train
     from paper_1907_04229_amd.synth import make_problem
     kw = {k: v for k, v in cfg.items() if k not in ("shape", "seed", "restart")}
@@ -258,14 +259,16 @@ def train_model(cfg, steps, lr, systems, pairs, batch, first, log_fn, lr_final=N
     vprobs = [make_problem(shape=cfg["shape"], seed=s, **kw) for s in vseeds]
     t_gen = time.perf_counter() - t0
     t0 = time.perf_counter()
-    model, hist = train(probs, probs[0].nv, steps=steps, batch=batch, pairs=pairs, lr=lr, seed=1,
+    from paper_1907_04229_amd.learned_init import init_params
+    theta0 = init_params(probs[0].nv, seed=1) if init == "jacobi" else None
+    model, hist = train(probs, probs[0].nv, steps=steps, batch=batch, pairs=pairs, lr=lr, seed=1, theta0=theta0,
                         eval_every=50, val_problems=vprobs, val_restart=cfg["restart"], rollback=rollback,
                         lr_final=lr_final, precision="fp32", second_stage="bilu0_mc", first_stage=first,
                         log=log_fn, **AMG_OPTS)
     t_train = time.perf_counter() - t0
     log_fn(f"trained {steps} steps in {t_train:.1f} s (data {t_gen:.1f} s); validation "
            f"{[(k, round(v, 4), it) for k, v, it in hist['val']]}, kept step {hist['best_step']}")
-    info = dict(train_s=round(t_train, 2), data_s=round(t_gen, 2), steps=steps, lr=lr, lr_final=lr_final,
+    info = dict(train_s=round(t_train, 2), data_s=round(t_gen, 2), steps=steps, init=init, lr=lr, lr_final=lr_final,
                 rollback=rollback, rollbacks=hist["rollbacks"],
                 systems=f"{len(seeds)} x {'x'.join(map(str, TRAIN_SHAPE))}, seeds {seeds}", pairs=pairs,
                 batch=batch,
@@ -480,6 +483,9 @@ def main():
     ap.add_argument("--train-systems", type=int, default=8)
     ap.add_argument("--train-pairs", type=int, default=48)
     ap.add_argument("--train-batch", type=int, default=16)
+    ap.add_argument("--train-init", default="neumann", choices=["neumann", "jacobi"],
+                    help="start of training: the truncated Neumann series of block Jacobi, or block Jacobi "
+                         "itself (random hidden layers, zero read-out)")
     ap.add_argument("--first", default="cptr",
                     choices=["cptr", "cptr_lower", "cptr_upper", "cpr", "cptr_bd", "cptr_uamg"],
                     help="first stage of the learned and BILU(0)-FP32 legs (plain FP64 CPTR stays cptr)")
@@ -582,7 +588,8 @@ def main():
 
     model, train_info = train_model(cfg, args.train_steps, args.train_lr, args.train_systems,
                                     args.train_pairs, args.train_batch, args.first, log,
-                                    lr_final=args.train_lr_final, rollback=args.train_rollback or None)
+                                    lr_final=args.train_lr_final, rollback=args.train_rollback or None,
+                                    init=args.train_init)
 
     # the measured configuration: learned second stage, FP32 preconditioner
     sl, setup_l = setup(pr, precision="fp32", second_stage="learned", first_stage=args.first)
