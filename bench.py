@@ -225,7 +225,8 @@ def cpu_baseline(pr, maxit=None):
     t0 = time.perf_counter()
     cs = AMG_OPTS.get("amg_coarse_size", 512)
     sw = AMG_OPTS.get("amg_sweeps", 2)
-    o = O.Oracle.from_problem(pr, first="cptr", second="bilu0", coarse_size=cs, sweeps=sw)
+    swT = AMG_OPTS.get("amg_sweeps_T", 0) or sw
+    o = O.Oracle.from_problem(pr, first="cptr", second="bilu0", coarse_size=cs, sweeps=sw, sweeps_T=swT)
     t_setup = time.perf_counter() - t0
     t0 = time.perf_counter()
     _, info = o.fgmres(pr.b, m=30, rtol=1e-6, maxit=maxit or 1000)
@@ -240,7 +241,7 @@ def cpu_baseline(pr, maxit=None):
                 iters=info["iters"], converged=info["converged"], relres_true=info["relres_true"],
                 setup_s=round(t_setup, 2), cell_iters_per_s=round(pr.n * info["iters"] / t, 1),
                 sample=f"the whole {pr.n:,}-cell system, FP64 CPTR-Block(AMG, coarsest level <= {cs} rows, "
-                       f"{sw} sweeps)"
+                       f"{sw} sweeps on A_pp, {swT} on S~_T)"
                        f"+BILU0(natural), FGMRES(30) "
                        f"{done} ({info['iters']} inner iterations), setup ({t_setup:.1f} s) excluded, "
                        f"one thread of the host's {host}")
@@ -495,6 +496,9 @@ def main():
     ap.add_argument("--amg-sweeps", type=int, default=3,
                     help="smoother sweeps before and after the coarse correction on every AMG level "
                          "(every solver of the run and the oracle's hierarchy)")
+    ap.add_argument("--amg-sweeps-T", type=int, default=1,
+                    help="smoother sweeps of the second (S~_T) hierarchy; 0: --amg-sweeps "
+                         "(every solver of the run and the oracle's hierarchy)")
     ap.add_argument("--parts", default="16x16x1",
                     help="block-Jacobi grid parts of the partitioned BILU(0) legs (px x py x pz)")
     ap.add_argument("--cpu-iters", type=int, default=0,
@@ -516,6 +520,7 @@ def main():
     args = ap.parse_args()
     AMG_OPTS["amg_coarse_size"] = args.amg_coarse_size
     AMG_OPTS["amg_sweeps"] = args.amg_sweeps
+    AMG_OPTS["amg_sweeps_T"] = args.amg_sweeps_T
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (the solver is a single-GPU library); "
               f"--gpus {args.gpus} is not supported", file=sys.stderr)
@@ -723,7 +728,7 @@ def main():
                                f"FGMRES({restart}) rtol 1e-6, {FIRST_NAME[args.first]}(AMG) + learned "
                                f"second stage, FP32 preconditioner",
                    "first_stage": args.first, "amg_coarse_size": args.amg_coarse_size,
-                   "amg_sweeps": args.amg_sweeps,
+                   "amg_sweeps": args.amg_sweeps, "amg_sweeps_T": args.amg_sweeps_T,
                    "cells": pr.n, "nnzb": pr.nnzb, "restart": restart},
         "iters": info["iters"],
         "cell_iters_per_s": round(pr.n * info["iters"] / dt, 1),

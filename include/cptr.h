@@ -195,6 +195,9 @@ typedef struct {
                             A P on the device from cptr_setup on (some hundreds of MB per
                             hierarchy at 10^6 cells).  CPTR_FIRST_UAMG and the decoupling
                             operators are re-set up on the host either way (1) */
+  int amg_sweeps_T;      /* smoother sweeps of the second hierarchy (S~_T, or A_TT with
+                            CPTR_FIRST_BD) before and after its coarse corrections; 0: amg_sweeps.
+                            Not used by CPR and CPTR-uAMG, which have no second hierarchy (0) */
 } cptr_options;
 
 typedef struct {

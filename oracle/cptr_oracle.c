@@ -1208,7 +1208,8 @@ void *orc_create(int n, int nv, const int *rp, const int *ci, const double *vals
         s = csr_copy(n, srp, sci, svals);
       if (st == 0) {
         st = amg_setup(&h->amg_s, s, o->theta, o->max_levels, o->coarse_size, o->seed,
-                       o->sweeps, o->smooth_p_T < 0 ? o->smooth_p : o->smooth_p_T, o->smoother);
+                       o->sweeps_T > 0 ? o->sweeps_T : o->sweeps,
+                       o->smooth_p_T < 0 ? o->smooth_p : o->smooth_p_T, o->smoother);
         h->have_s = 1;
       }
     }

@@ -52,6 +52,7 @@ typedef struct {
   int ilu_level;       /* level of fill of the block ILU second stage: 0 (BILU(0)) or 1 (BILU(1)) */
   int schur;           /* S~_T of the block first stages: 0 the assembled one passed in (eq:Se),
                           1 A_TT, 2 A_TT - A_Tp diag(A_pp)^{-1} A_pT (Section 3.3.1) */
+  int sweeps_T;        /* sweeps of the second hierarchy (S~_T or A_TT); 0: sweeps */
 } orc_opts;
 
 typedef struct {

@@ -35,7 +35,7 @@ class _Opts(C.Structure):
                 ("coarse_size", C.c_int), ("seed", C.c_uint), ("sweeps", C.c_int),
                 ("smooth_p", C.c_int), ("smoother", C.c_int), ("ilu_order", C.c_void_p),
                 ("ilu_part", C.c_void_p), ("smooth_p_T", C.c_int), ("decoupling", C.c_int),
-                ("ilu_level", C.c_int), ("schur", C.c_int)]
+                ("ilu_level", C.c_int), ("schur", C.c_int), ("sweeps_T", C.c_int)]
 
 
 class _Info(C.Structure):
@@ -133,7 +133,7 @@ class Oracle:
                  st_vals=None, first="cptr", second="bilu0", ip=0, iT=None,
                  theta=0.08, max_levels=10, coarse_size=512, seed=0, sweeps=2,
                  smooth_p=True, smoother="jacobi", ilu_order=None, ilu_part=None, smooth_p_T=False,
-                 decoupling="none", ilu_level=0, schur="assembled"):
+                 decoupling="none", ilu_level=0, schur="assembled", sweeps_T=0):
         self.n, self.nv = n, nv
         self._keep = [_ci(row_ptr), _ci(col), _cd(vals)]
         if st_row_ptr is None:
@@ -152,7 +152,7 @@ class Oracle:
                   theta, max_levels, coarse_size, seed, sweeps, int(bool(smooth_p)),
                   {"jacobi": 0, "gs": 1}[smoother], extra[0], extra[1],
                   -1 if smooth_p_T is None else int(bool(smooth_p_T)),
-                  DECOUPLING[decoupling], int(ilu_level), SCHUR[schur])
+                  DECOUPLING[decoupling], int(ilu_level), SCHUR[schur], int(sweeps_T))
         status = C.c_int(0)
         rp, ci, v, srp, sci, sv = self._keep[:6]
         self.h = lib().orc_create(n, nv, _i(rp), _i(ci), _d(v), _i(srp), _i(sci), _d(sv),

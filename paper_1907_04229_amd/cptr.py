@@ -33,7 +33,8 @@ class Options(C.Structure):
                 ("scalar_dia", C.c_int), ("lrn_columns", C.c_int), ("decoupling", C.c_int),
                 ("ilu_level", C.c_int), ("schur", C.c_int), ("lrn_fallback", C.c_int),
                 ("amg_smoother", C.c_int), ("ilu_part_x", C.c_int), ("ilu_part_y", C.c_int),
-                ("ilu_part_z", C.c_int), ("ilu_accum_fp64", C.c_int), ("resetup_device", C.c_int)]
+                ("ilu_part_z", C.c_int), ("ilu_accum_fp64", C.c_int), ("resetup_device", C.c_int),
+                ("amg_sweeps_T", C.c_int)]
 
 
 class Bsr(C.Structure):

@@ -1512,7 +1512,8 @@ static void build_precond(cptr_handle *h, const std::vector<int> &rp, const std:
         amg_build(sub(o.iT, o.iT), prm_s, hs, agg_s);
       else
         amg_build(*S, prm_s, hs, agg_s);
-      P.amg_s.build(hs, o.amg_sweeps, o.scalar_dia != 0, o.amg_smoother, plan);
+      P.amg_s.build(hs, o.amg_sweeps_T > 0 ? o.amg_sweeps_T : o.amg_sweeps, o.scalar_dia != 0, o.amg_smoother,
+                    plan);
       P.have_s = true;
       if (o.first_stage != CPTR_FIRST_BD) {
         P.ApT.build(sub(o.ip, o.iT), o.scalar_dia != 0);
@@ -1644,7 +1645,8 @@ static void validate_and_fetch(const cptr_bsr *A, const cptr_csr *S, const cptr_
   if (nv != 3 && nv != 4) throw Error{CPTR_ERR_UNSUPPORTED, "nv must be 3 or 4"};
   if (o.ip < 0 || o.ip >= nv || o.iT < 0 || o.iT >= nv || o.ip == o.iT)
     throw Error{CPTR_ERR_INVALID_ARG, "invalid p/T slots"};
-  if (o.amg_max_levels < 1 || o.amg_coarse_size < 1 || o.amg_sweeps < 1 || !(o.amg_theta >= 0.0))
+  if (o.amg_max_levels < 1 || o.amg_coarse_size < 1 || o.amg_sweeps < 1 || o.amg_sweeps_T < 0 ||
+      !(o.amg_theta >= 0.0))
     throw Error{CPTR_ERR_INVALID_ARG, "invalid AMG options"};
   if (o.first_stage < 0 || o.first_stage > 6) throw Error{CPTR_ERR_INVALID_ARG, "invalid first stage"};
   if (o.decoupling < 0 || o.decoupling > 2) throw Error{CPTR_ERR_INVALID_ARG, "invalid decoupling"};
@@ -2323,6 +2325,7 @@ void cptr_default_options(cptr_options *o) {
   o->ilu_part_x = o->ilu_part_y = o->ilu_part_z = 1;
   o->ilu_accum_fp64 = 0;
   o->resetup_device = 1;
+  o->amg_sweeps_T = 0;
 }
 
 int cptr_setup(cptr_handle **out, const cptr_bsr *A, const cptr_csr *S_T, const cptr_options *opt,

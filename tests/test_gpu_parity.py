@@ -162,6 +162,55 @@ def test_vcycle_and_first_stage_fp64(name, first):
     s.close()
 
 
+@pytest.mark.parametrize("name,first,precision", [("small", "cptr", "fp64"), ("three", "cptr_bd", "fp64"),
+                                                   ("dia2", "cptr", "fp64"), ("dia2", "cptr", "fp32")])
+def test_second_hierarchy_sweeps(name, first, precision):
+    """amg_sweeps_T: three sweeps on A_pp and one on S~_T (or A_TT behind
+    CPTR-BD), against the oracle with the same setting: V-cycles of both
+    hierarchies and the first stage within 1e-10 in FP64, 1e-5 (the FP32
+    bar of the V-cycle tests) with the FP32 preconditioner."""
+    banner(f"second-hierarchy sweeps {name} {first} {precision}")
+    pr = prob(name)
+    s = solver(pr, precision=precision, first_stage=first, second_stage="none", amg_coarse_size=16,
+               amg_sweeps=3, amg_sweeps_T=1)
+    o = O.Oracle.from_problem(pr, first=first, second="none", coarse_size=16, sweeps=3, sweeps_T=1)
+    bar = 1e-10 if precision == "fp64" else 1e-5
+    rng = np.random.default_rng(31)
+    for which in (0, 1):
+        b = rng.standard_normal(pr.n)
+        x = torch.empty(pr.n, dtype=torch.float64, device=DEV)
+        cptr.cptr_vcycle(s.h, which, dev(b), x)
+        torch.cuda.synchronize()
+        assert relerr(x.cpu().numpy(), o.vcycle(which, b)) <= bar
+    v = rng.standard_normal(pr.n * pr.nv)
+    x1 = torch.empty_like(dev(v))
+    cptr.cptr_first_stage(s.h, dev(v), x1)
+    torch.cuda.synchronize()
+    assert relerr(x1.cpu().numpy(), o.first_stage(v)) <= bar
+    s.close()
+    o.close()
+
+
+def test_second_hierarchy_sweeps_fgmres():
+    """FGMRES with the benchmark's AMG settings (coarsest levels up to 1024
+    rows, three sweeps on A_pp, one on S~_T) and BILU(0) in natural order,
+    FP64: iterations within one of the oracle's and the solution within 1e-8
+    (the bar of the other FP64 FGMRES parity tests)."""
+    banner("second-hierarchy sweeps fgmres")
+    pr = prob("dia2")
+    kw = dict(amg_coarse_size=1024, amg_sweeps=3, amg_sweeps_T=1)
+    s = solver(pr, precision="fp64", second_stage="bilu0", **kw)
+    o = O.Oracle.from_problem(pr, first="cptr", second="bilu0", coarse_size=1024, sweeps=3, sweeps_T=1)
+    x, info = s.solve(dev(pr.b), restart=30, rtol=1e-6)
+    xo, io = o.fgmres(pr.b, m=30, rtol=1e-6)
+    err = np.linalg.norm(x.cpu().numpy() - xo) / np.linalg.norm(xo)
+    print(f"iters gpu {info['iters']} oracle {io['iters']} err {err:.2e}")
+    assert info["converged"] and io["converged"]
+    assert abs(info["iters"] - io["iters"]) <= 1 and err <= 1e-8
+    s.close()
+    o.close()
+
+
 @pytest.mark.parametrize("name", ["ragged", "three", "gs_large"])
 def test_gauss_seidel_smoother_fp32(name):
     """amg_smoother = GS with the FP32 preconditioner: V-cycles of both

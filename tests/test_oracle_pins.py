@@ -272,6 +272,46 @@ def test_two_grid_cycle_is_textbook(mid, sweeps, first, oracle_lib):
     assert np.allclose(got, x, rtol=1e-9, atol=1e-12 * np.abs(x).max())
 
 
+def _two_grid_l1_jacobi(lv, sweeps, b):
+    """The textbook two-grid cycle of a level pair: l1-Jacobi sweeps from zero,
+    exact Galerkin coarse correction, l1-Jacobi sweeps."""
+    A = dense_csr(*lv[0]["A"])
+    Pm = dense_csr(*lv[0]["P"], ncol=lv[1]["n"])
+    Ac = Pm.T @ A @ Pm
+    d = np.abs(A).sum(axis=1)
+    x = np.zeros_like(b)
+    for _ in range(sweeps):
+        x = x + (b - A @ x) / d
+    x = x + Pm @ np.linalg.solve(Ac, Pm.T @ (b - A @ x))
+    for _ in range(sweeps):
+        x = x + (b - A @ x) / d
+    return x
+
+
+def test_second_hierarchy_sweeps_apply_to_s_t_alone(mid, oracle_lib):
+    """sweeps_T sets the smoothing of the S~_T hierarchy (Section 3.3: the
+    second AMG solver of the block stage) and of it alone: with sweeps = 3 and
+    sweeps_T = 1 the A_pp cycle is the textbook two-grid cycle with three
+    sweeps and the S~_T cycle the one with a single sweep; sweeps_T = 0 is
+    sweeps."""
+    o = O.Oracle.from_problem(mid, first="cptr", coarse_size=8, max_levels=2, sweeps=3, sweeps_T=1)
+    rng = np.random.default_rng(5)
+    for which, sw in ((0, 3), (1, 1)):
+        lv = o.amg_levels(which)
+        assert len(lv) == 2
+        b = rng.standard_normal(lv[0]["n"])
+        x = _two_grid_l1_jacobi(lv, sw, b)
+        got = o.vcycle(which, b)
+        assert np.allclose(got, x, rtol=1e-9, atol=1e-12 * np.abs(x).max())
+    same = O.Oracle.from_problem(mid, first="cptr", coarse_size=8, max_levels=2, sweeps=3, sweeps_T=0)
+    lv = same.amg_levels(1)
+    b = rng.standard_normal(lv[0]["n"])
+    assert np.allclose(same.vcycle(1, b), _two_grid_l1_jacobi(lv, 3, b), rtol=1e-9,
+                       atol=1e-12 * np.abs(b).max())
+    o.close()
+    same.close()
+
+
 def _greedy_colours(A):
     """Smallest colour not taken by a lower-numbered neighbour, natural order."""
     n = A.shape[0]
